@@ -1,0 +1,784 @@
+/*
+ * oracle.c -- plain FP64 CPU reference (TEST INFRASTRUCTURE ONLY; see
+ * oracle.h).  Single-threaded, sequential, natural-order loops, compiled
+ * with -ffp-contract=off.  Every routine cites the passage of the paper it
+ * follows; where the paper only names a method (CG, BiCGSTAB, Jacobi,
+ * iterative refinement) the textbook definition of the method the paper
+ * cites (Saad's book, cited for CSR in Sec. 2.2.4) is written out step by
+ * step in the paper's operator notation.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ CSR */
+
+/* Canonical CSR (Sec. 2.2.4 stores system matrices in CSR): row_ptr starts at
+ * 0, never decreases, ends at nnz; every column index lies in [0, ncols) and
+ * the indices of one row strictly increase (sorted, no duplicates). */
+int orc_csr_check(int64_t nrows, int64_t ncols, int64_t nnz,
+                  const int32_t *row_ptr, const int32_t *col)
+{
+    if (row_ptr[0] != 0) return ORC_CSR_BAD_START;
+    for (int64_t i = 0; i < nrows; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return ORC_CSR_NOT_MONOTONE;
+    if ((int64_t)row_ptr[nrows] != nnz) return ORC_CSR_BAD_END;
+    for (int64_t i = 0; i < nrows; ++i) {
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            if (col[k] < 0 || (int64_t)col[k] >= ncols) return ORC_CSR_COL_RANGE;
+            if (k > row_ptr[i] && col[k] <= col[k - 1]) return ORC_CSR_COL_ORDER;
+        }
+    }
+    return ORC_CSR_OK;
+}
+
+/* Advanced apply y = alpha*A*x + beta*y (Sec. 4.2; the simple apply of
+ * Sec. 2.2.2 is alpha = 1, beta = 0).  beta == 0 means y is not read. */
+void orc_csr_spmv(int64_t nrows, const int32_t *row_ptr, const int32_t *col,
+                  const double *val, double alpha, const double *x,
+                  double beta, double *y)
+{
+    for (int64_t i = 0; i < nrows; ++i) {
+        double s = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            s += val[k] * x[col[k]];
+        y[i] = (beta == 0.0) ? alpha * s : alpha * s + beta * y[i];
+    }
+}
+
+/* ------------------------------------------------------------------ COO */
+
+/* COO (the format of the solver-bandwidth study, Sec. 7.4): triplets in CSR
+ * order, the row of each entry written out explicitly. */
+void orc_csr_to_coo(int64_t nrows, const int32_t *row_ptr, int32_t *row_out)
+{
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            row_out[k] = (int32_t)i;
+}
+
+/* y = alpha*A*x + beta*y from row-sorted triplets; each row's entries are
+ * summed in storage order, rows without entries get alpha*0 + beta*y. */
+void orc_coo_spmv(int64_t nrows, int64_t nnz, const int32_t *row,
+                  const int32_t *col, const double *val, double alpha,
+                  const double *x, double beta, double *y)
+{
+    double *s = (double *)calloc((size_t)(nrows > 0 ? nrows : 1), sizeof(double));
+    for (int64_t k = 0; k < nnz; ++k)
+        s[row[k]] += val[k] * x[col[k]];
+    for (int64_t i = 0; i < nrows; ++i)
+        y[i] = (beta == 0.0) ? alpha * s[i] : alpha * s[i] + beta * y[i];
+    free(s);
+}
+
+/* ------------------------------------------------------------------ ELL */
+
+int32_t orc_max_row_len(int64_t nrows, const int32_t *row_ptr)
+{
+    int32_t w = 0;
+    for (int64_t i = 0; i < nrows; ++i) {
+        int32_t len = row_ptr[i + 1] - row_ptr[i];
+        if (len > w) w = len;
+    }
+    return w;
+}
+
+/* ELL: width w slots per row, stored slot-major: slot s of row i sits at
+ * s*n_pad + i.  Row i's entries fill its first len_i slots in column order;
+ * unused slots hold the sentinel column -1 and value 0 and are skipped by the
+ * product (so a NaN/Inf in x never meets a padding zero). */
+void orc_csr_to_ell(int64_t nrows, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, int32_t width, int64_t n_pad,
+                    int32_t *ell_col, double *ell_val)
+{
+    for (int64_t s = 0; s < width; ++s)
+        for (int64_t i = 0; i < n_pad; ++i) {
+            ell_col[s * n_pad + i] = -1;
+            ell_val[s * n_pad + i] = 0.0;
+        }
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            int64_t s = k - row_ptr[i];
+            ell_col[s * n_pad + i] = col[k];
+            ell_val[s * n_pad + i] = val[k];
+        }
+}
+
+void orc_ell_spmv(int64_t nrows, int64_t n_pad, int32_t width,
+                  const int32_t *ell_col, const double *ell_val, double alpha,
+                  const double *x, double beta, double *y)
+{
+    for (int64_t i = 0; i < nrows; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < width; ++j) {
+            int32_t c = ell_col[j * n_pad + i];
+            if (c >= 0) s += ell_val[j * n_pad + i] * x[c];
+        }
+        y[i] = (beta == 0.0) ? alpha * s : alpha * s + beta * y[i];
+    }
+}
+
+/* ------------------------------------------------------------------ HYB */
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Hybrid split width k = nearest-rank q-quantile of the row lengths:
+ * sorted length at 1-based rank ceil(q*n) (q in (0,1]). */
+int32_t orc_hyb_width(int64_t nrows, const int32_t *row_ptr, double q)
+{
+    if (nrows == 0) return 0;
+    int32_t *len = (int32_t *)malloc((size_t)nrows * sizeof(int32_t));
+    for (int64_t i = 0; i < nrows; ++i) len[i] = row_ptr[i + 1] - row_ptr[i];
+    qsort(len, (size_t)nrows, sizeof(int32_t), cmp_i32);
+    int64_t rank = (int64_t)ceil(q * (double)nrows);
+    if (rank < 1) rank = 1;
+    if (rank > nrows) rank = nrows;
+    int32_t k = len[rank - 1];
+    free(len);
+    return k;
+}
+
+int64_t orc_hyb_tail_count(int64_t nrows, const int32_t *row_ptr, int32_t k)
+{
+    int64_t t = 0;
+    for (int64_t i = 0; i < nrows; ++i) {
+        int64_t len = row_ptr[i + 1] - row_ptr[i];
+        if (len > k) t += len - k;
+    }
+    return t;
+}
+
+/* HYB = ELL part holding each row's first min(len, k) entries + a row-sorted
+ * COO tail holding the rest, in CSR order. */
+void orc_csr_to_hyb(int64_t nrows, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, int32_t k, int64_t n_pad,
+                    int32_t *ell_col, double *ell_val, int32_t *tail_row,
+                    int32_t *tail_col, double *tail_val)
+{
+    for (int64_t s = 0; s < k; ++s)
+        for (int64_t i = 0; i < n_pad; ++i) {
+            ell_col[s * n_pad + i] = -1;
+            ell_val[s * n_pad + i] = 0.0;
+        }
+    int64_t t = 0;
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int64_t s = e - row_ptr[i];
+            if (s < k) {
+                ell_col[s * n_pad + i] = col[e];
+                ell_val[s * n_pad + i] = val[e];
+            } else {
+                tail_row[t] = (int32_t)i;
+                tail_col[t] = col[e];
+                tail_val[t] = val[e];
+                ++t;
+            }
+        }
+}
+
+/* Each row: ELL slots in order, then its tail entries in order. */
+void orc_hyb_spmv(int64_t nrows, int64_t n_pad, int32_t k,
+                  const int32_t *ell_col, const double *ell_val, int64_t ntail,
+                  const int32_t *tail_row, const int32_t *tail_col,
+                  const double *tail_val, double alpha, const double *x,
+                  double beta, double *y)
+{
+    double *s = (double *)calloc((size_t)(nrows > 0 ? nrows : 1), sizeof(double));
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t j = 0; j < k; ++j) {
+            int32_t c = ell_col[j * n_pad + i];
+            if (c >= 0) s[i] += ell_val[j * n_pad + i] * x[c];
+        }
+    for (int64_t t = 0; t < ntail; ++t)
+        s[tail_row[t]] += tail_val[t] * x[tail_col[t]];
+    for (int64_t i = 0; i < nrows; ++i)
+        y[i] = (beta == 0.0) ? alpha * s[i] : alpha * s[i] + beta * y[i];
+    free(s);
+}
+
+/* --------------------------------------------------------------- Jacobi */
+
+/* Point Jacobi (block-Jacobi with block size 1, Sec. 3.2):
+ * dinv_i = 1 / a_ii.  Returns -1 on success, else the first row whose
+ * diagonal entry is missing or zero. */
+int64_t orc_jacobi_dinv(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                        const double *val, double *dinv)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        int found = 0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) { d = val[k]; found = 1; }
+        if (!found || d == 0.0) return i;
+        dinv[i] = 1.0 / d;
+    }
+    return -1;
+}
+
+/* ---------------------------------------------------------- vector ops */
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+static double nrm2(int64_t n, const double *a) { return sqrt(dot(n, a, a)); }
+
+static void prec(int64_t n, const double *dinv, const double *in, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = dinv ? dinv[i] * in[i] : in[i];
+}
+
+static int nonfinite(double v) { return !isfinite(v); }
+
+/* ------------------------------------------------------------------- CG */
+
+/* Jacobi-preconditioned CG (CG of Sec. 3.1 with the Jacobi preconditioner of
+ * Sec. 3.2, as configured in the introductory example of Sec. 2.1).
+ * Criteria (Sec. 2.5): Iteration (max_iters) OR ResidualNormReduction
+ * (||r_k|| <= reduction*||b||, the recurrence residual), first one met wins.
+ *
+ *   r = b - A x ; z = M^{-1} r ; p = z ; rho = r.z
+ *   repeat: q = A p ; eta = p.q ; alpha = rho/eta ; x += alpha p ;
+ *           r -= alpha q ; stop if ||r|| small ; z = M^{-1} r ;
+ *           rho' = r.z ; p = z + (rho'/rho) p ; rho = rho'
+ *
+ * The iteration count is the number of products q = A p.  eta <= 0 (the
+ * operator is not positive definite along p) or rho' == 0 with r != 0 stops
+ * with BREAKDOWN.  history[k] (optional, max_iters+1 entries) receives
+ * ||r_k||/||b||. */
+int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
+            const double *val, const double *dinv, const double *b, double *x,
+            orc_criteria crit, orc_info *info, double *history)
+{
+    double *r = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    double *z = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    double *p = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    double *q = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    memset(info, 0, sizeof(*info));
+    double nb = nrm2(n, b);
+    int stop = ORC_RUNNING;
+    int64_t k = 0;
+    double rel = 0.0;
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        stop = ORC_CONVERGED;
+        if (history) history[0] = 0.0;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+    orc_csr_spmv(n, row_ptr, col, val, -1.0, x, 1.0, r);
+    info->spmv_count = 1;
+    double rr = dot(n, r, r);
+    rel = sqrt(rr) / nb;
+    if (history) history[0] = rel;
+    if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; goto done; }
+    prec(n, dinv, r, z);
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+    double rho = dot(n, r, z);
+    while (k < crit.max_iters) {
+        orc_csr_spmv(n, row_ptr, col, val, 1.0, p, 0.0, q);
+        info->spmv_count++;
+        double eta = dot(n, p, q);
+        if (crit.nonfinite_check && nonfinite(eta)) { stop = ORC_NONFINITE; break; }
+        if (eta <= 0.0) { stop = ORC_BREAKDOWN; break; }
+        double alpha = rho / eta;
+        for (int64_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        for (int64_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+        ++k;
+        rr = dot(n, r, r);
+        rel = sqrt(rr) / nb;
+        if (history) history[k] = rel;
+        if (crit.nonfinite_check && nonfinite(rr)) { stop = ORC_NONFINITE; break; }
+        if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
+        prec(n, dinv, r, z);
+        double rho_new = dot(n, r, z);
+        if (crit.nonfinite_check && nonfinite(rho_new)) { stop = ORC_NONFINITE; break; }
+        if (rho_new == 0.0) { stop = ORC_BREAKDOWN; break; }
+        double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+    if (stop == ORC_RUNNING) stop = ORC_MAX_ITERS;
+done:
+    info->iterations = k;
+    info->rel_residual = rel;
+    info->stop_reason = stop;
+    free(r); free(z); free(p); free(q);
+    return stop;
+}
+
+/* ------------------------------------------------------------- BiCGSTAB */
+
+/* BiCGSTAB (Sec. 3.1; van der Vorst's method) with right Jacobi
+ * preconditioning, same criteria as CG.  One iteration = one pass of the
+ * loop (two products with A); the half step exits early with
+ * x += alpha*p_hat when ||s|| already meets the criterion.
+ *
+ *   r = b - A x ; r_hat = r ; rho_old = alpha = omega = 1 ; v = p = 0
+ *   repeat: rho = r_hat.r ; beta = (rho/rho_old)(alpha/omega)
+ *           p = r + beta (p - omega v) ; p_hat = M^{-1} p ; v = A p_hat
+ *           alpha = rho / (r_hat.v) ; s = r - alpha v
+ *           [||s|| small: x += alpha p_hat, stop]
+ *           s_hat = M^{-1} s ; t = A s_hat ; omega = (t.s)/(t.t)
+ *           x += alpha p_hat + omega s_hat ; r = s - omega t
+ *           [||r|| small: stop] ; rho_old = rho
+ *
+ * rho == 0, r_hat.v == 0, t.t == 0 or omega == 0 stops with BREAKDOWN. */
+int orc_bicgstab(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                 const double *val, const double *dinv, const double *b,
+                 double *x, orc_criteria crit, orc_info *info, double *history)
+{
+    size_t bytes = (size_t)(n + 1) * sizeof(double);
+    double *r = malloc(bytes), *rh = malloc(bytes), *p = calloc(n + 1, sizeof(double));
+    double *v = calloc(n + 1, sizeof(double)), *ph = malloc(bytes), *s = malloc(bytes);
+    double *sh = malloc(bytes), *t = malloc(bytes);
+    memset(info, 0, sizeof(*info));
+    int stop = ORC_RUNNING;
+    int64_t k = 0;
+    double rel = 0.0;
+    double nb = nrm2(n, b);
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        stop = ORC_CONVERGED;
+        if (history) history[0] = 0.0;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+    orc_csr_spmv(n, row_ptr, col, val, -1.0, x, 1.0, r);
+    info->spmv_count = 1;
+    for (int64_t i = 0; i < n; ++i) rh[i] = r[i];
+    double rn = nrm2(n, r);
+    rel = rn / nb;
+    if (history) history[0] = rel;
+    if (rn <= crit.reduction * nb) { stop = ORC_CONVERGED; goto done; }
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    while (k < crit.max_iters) {
+        double rho = dot(n, rh, r);
+        if (crit.nonfinite_check && nonfinite(rho)) { stop = ORC_NONFINITE; break; }
+        if (rho == 0.0) { stop = ORC_BREAKDOWN; break; }
+        double beta = (rho / rho_old) * (alpha / omega);
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        prec(n, dinv, p, ph);
+        orc_csr_spmv(n, row_ptr, col, val, 1.0, ph, 0.0, v);
+        info->spmv_count++;
+        double rv = dot(n, rh, v);
+        if (crit.nonfinite_check && nonfinite(rv)) { stop = ORC_NONFINITE; break; }
+        if (rv == 0.0) { stop = ORC_BREAKDOWN; break; }
+        alpha = rho / rv;
+        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        ++k;
+        double sn = nrm2(n, s);
+        if (sn <= crit.reduction * nb) {
+            for (int64_t i = 0; i < n; ++i) x[i] += alpha * ph[i];
+            rel = sn / nb;
+            if (history) history[k] = rel;
+            stop = ORC_CONVERGED;
+            break;
+        }
+        prec(n, dinv, s, sh);
+        orc_csr_spmv(n, row_ptr, col, val, 1.0, sh, 0.0, t);
+        info->spmv_count++;
+        double tt = dot(n, t, t);
+        double ts = dot(n, t, s);
+        if (crit.nonfinite_check && (nonfinite(tt) || nonfinite(ts))) { stop = ORC_NONFINITE; break; }
+        if (tt == 0.0) { stop = ORC_BREAKDOWN; break; }
+        omega = ts / tt;
+        for (int64_t i = 0; i < n; ++i) x[i] += alpha * ph[i] + omega * sh[i];
+        for (int64_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+        rn = nrm2(n, r);
+        rel = rn / nb;
+        if (history) history[k] = rel;
+        if (crit.nonfinite_check && nonfinite(rn)) { stop = ORC_NONFINITE; break; }
+        if (rn <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
+        if (omega == 0.0) { stop = ORC_BREAKDOWN; break; }
+        rho_old = rho;
+    }
+    if (stop == ORC_RUNNING) stop = ORC_MAX_ITERS;
+done:
+    info->iterations = k;
+    info->rel_residual = rel;
+    info->stop_reason = stop;
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+    return stop;
+}
+
+/* ------------------------------------------------------ FP32 inner CG */
+
+/* Jacobi-CG whose matrix values and vectors are stored in FP32 (memory
+ * precision decoupled from arithmetic precision, Sec. 3.2):
+ *  - SpMV accumulates each row in FP32 in storage order;
+ *  - dot products multiply FP32 entries exactly in FP64 and sum in FP64;
+ *  - scalars alpha, beta, rho are FP64;
+ *  - each vector update is evaluated in FP64 and rounded once to FP32.
+ * Criterion: ||r_k|| <= reduction*||b|| or max_iters. */
+static void spmv_f32(int64_t n, const int32_t *rp, const int32_t *col,
+                     const float *val, const float *x, float *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float s = 0.0f;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            float prod = val[k] * x[col[k]];
+            s = s + prod;
+        }
+        y[i] = s;
+    }
+}
+
+static double dot_f32(int64_t n, const float *a, const float *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (double)a[i] * (double)b[i];
+    return s;
+}
+
+int orc_pcg_f32(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                const float *val, const float *dinv, const float *b, float *x,
+                orc_criteria crit, orc_info *info)
+{
+    size_t bytes = (size_t)(n + 1) * sizeof(float);
+    float *r = malloc(bytes), *p = malloc(bytes), *q = malloc(bytes);
+    memset(info, 0, sizeof(*info));
+    int stop = ORC_RUNNING;
+    int64_t k = 0;
+    double rel = 0.0;
+    double nb = sqrt(dot_f32(n, b, b));
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0f;
+        stop = ORC_CONVERGED;
+        goto done;
+    }
+    spmv_f32(n, row_ptr, col, val, x, q);
+    info->spmv_count = 1;
+    for (int64_t i = 0; i < n; ++i) r[i] = (float)((double)b[i] - (double)q[i]);
+    double rr = dot_f32(n, r, r);
+    rel = sqrt(rr) / nb;
+    if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; goto done; }
+    double rho = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double zi = (double)dinv[i] * (double)r[i];
+        p[i] = (float)zi;
+        rho += (double)r[i] * zi;
+    }
+    while (k < crit.max_iters) {
+        spmv_f32(n, row_ptr, col, val, p, q);
+        info->spmv_count++;
+        double eta = dot_f32(n, p, q);
+        if (crit.nonfinite_check && nonfinite(eta)) { stop = ORC_NONFINITE; break; }
+        if (eta <= 0.0) { stop = ORC_BREAKDOWN; break; }
+        double alpha = rho / eta;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = (float)((double)x[i] + alpha * (double)p[i]);
+            r[i] = (float)((double)r[i] - alpha * (double)q[i]);
+        }
+        ++k;
+        rr = dot_f32(n, r, r);
+        rel = sqrt(rr) / nb;
+        if (crit.nonfinite_check && nonfinite(rr)) { stop = ORC_NONFINITE; break; }
+        if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
+        double rho_new = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            rho_new += (double)r[i] * ((double)dinv[i] * (double)r[i]);
+        if (rho_new == 0.0) { stop = ORC_BREAKDOWN; break; }
+        double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; ++i)
+            p[i] = (float)((double)dinv[i] * (double)r[i] + beta * (double)p[i]);
+        rho = rho_new;
+    }
+    if (stop == ORC_RUNNING) stop = ORC_MAX_ITERS;
+done:
+    info->iterations = k;
+    info->rel_residual = rel;
+    info->stop_reason = stop;
+    free(r); free(p); free(q);
+    return stop;
+}
+
+/* --------------------------------------------- iterative refinement */
+
+/* Iterative refinement with an inner Jacobi-CG (the IR solver with a
+ * configurable inner solver of Sec. 2.2.3 and Sec. 3.1), the inner solve run
+ * in FP32 storage (precision decoupling, Sec. 3.2):
+ *
+ *   x = x0 ; repeat: r = b - A x (FP64) ; stop if ||r||/||b|| <= outer_red
+ *            s = ||r||_inf ; r32 = fp32(r / s)
+ *            solve A32 d = r32 by FP32 Jacobi-CG from d = 0 to
+ *              ||r_in|| <= inner_red*||r32|| or inner_max_iters
+ *            x += s * fp64(d)
+ *
+ * A32 = fp32(values); dinv32 = fp32(1/a_ii) with the reciprocal taken in
+ * FP64.  info->iterations counts outer steps (refinement corrections
+ * applied), info->inner_iterations all inner CG iterations. */
+int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
+           const double *val, const double *b, double *x,
+           int64_t max_outer, double outer_reduction,
+           int64_t inner_max_iters, double inner_reduction,
+           orc_info *info, double *outer_history)
+{
+    int64_t nnz = row_ptr[n];
+    float *v32 = malloc((size_t)(nnz + 1) * sizeof(float));
+    float *dinv32 = malloc((size_t)(n + 1) * sizeof(float));
+    double *dinv = malloc((size_t)(n + 1) * sizeof(double));
+    double *r = malloc((size_t)(n + 1) * sizeof(double));
+    float *r32 = malloc((size_t)(n + 1) * sizeof(float));
+    float *d32 = malloc((size_t)(n + 1) * sizeof(float));
+    memset(info, 0, sizeof(*info));
+    int stop = ORC_RUNNING;
+    for (int64_t k = 0; k < nnz; ++k) v32[k] = (float)val[k];
+    if (orc_jacobi_dinv(n, row_ptr, col, val, dinv) >= 0) { stop = ORC_BREAKDOWN; goto done; }
+    for (int64_t i = 0; i < n; ++i) dinv32[i] = (float)dinv[i];
+    double nb = nrm2(n, b);
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        stop = ORC_CONVERGED;
+        goto done;
+    }
+    int64_t outer = 0;
+    for (;;) {
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+        orc_csr_spmv(n, row_ptr, col, val, -1.0, x, 1.0, r);
+        info->spmv_count++;
+        double rel = nrm2(n, r) / nb;
+        info->rel_residual = rel;
+        if (outer_history) outer_history[outer] = rel;
+        if (rel <= outer_reduction) { stop = ORC_CONVERGED; break; }
+        if (nonfinite(rel)) { stop = ORC_NONFINITE; break; }
+        if (outer >= max_outer) { stop = ORC_MAX_ITERS; break; }
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) if (fabs(r[i]) > s) s = fabs(r[i]);
+        for (int64_t i = 0; i < n; ++i) { r32[i] = (float)(r[i] / s); d32[i] = 0.0f; }
+        orc_criteria ic = { inner_max_iters, inner_reduction, 1 };
+        orc_info ii;
+        orc_pcg_f32(n, row_ptr, col, v32, dinv32, r32, d32, ic, &ii);
+        info->inner_iterations += ii.iterations;
+        info->spmv_count += ii.spmv_count;
+        for (int64_t i = 0; i < n; ++i) x[i] += s * (double)d32[i];
+        ++outer;
+    }
+    info->iterations = outer;
+done:
+    info->stop_reason = stop;
+    free(v32); free(dinv32); free(dinv); free(r); free(r32); free(d32);
+    return stop;
+}
+
+/* ------------------------------------------------------ batched PCG */
+
+/* Independent Jacobi-PCG per system (per-system stopping status,
+ * Sec. 2.5): system s owns rows sys_ptr[s]..sys_ptr[s+1]-1 of the packed CSR,
+ * its column indices are local to the system.  x0 = 0, criterion
+ * ||r|| <= reduction*||b_s|| or iter_factor*n_s iterations. */
+void orc_batch_pcg(int64_t nsys, const int32_t *sys_ptr, const int32_t *row_ptr,
+                   const int32_t *col, const double *val, const double *b,
+                   double *x, double reduction, int64_t iter_factor,
+                   int32_t *iters, double *rel_res, uint8_t *status)
+{
+    for (int64_t s = 0; s < nsys; ++s) {
+        int64_t r0 = sys_ptr[s], r1 = sys_ptr[s + 1], n = r1 - r0;
+        int64_t k0 = row_ptr[r0];
+        int32_t *rp = malloc((size_t)(n + 1) * sizeof(int32_t));
+        for (int64_t i = 0; i <= n; ++i) rp[i] = (int32_t)(row_ptr[r0 + i] - k0);
+        double *dinv = malloc((size_t)(n + 1) * sizeof(double));
+        const int32_t *c = col + k0;
+        const double *v = val + k0;
+        double *xs = x + r0;
+        for (int64_t i = 0; i < n; ++i) xs[i] = 0.0;
+        orc_info info;
+        if (orc_jacobi_dinv(n, rp, c, v, dinv) >= 0) {
+            iters[s] = 0; rel_res[s] = NAN; status[s] = ORC_BREAKDOWN;
+        } else {
+            orc_criteria crit = { iter_factor * n, reduction, 1 };
+            orc_pcg(n, rp, c, v, dinv, b + r0, xs, crit, &info, NULL);
+            iters[s] = (int32_t)info.iterations;
+            rel_res[s] = info.rel_residual;
+            status[s] = (uint8_t)info.stop_reason;
+        }
+        free(rp); free(dinv);
+    }
+}
+
+/* ------------------------------------------------------------ features */
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Sixteen structural statistics of a sparse matrix, the input of the
+ * format/kernel selector (the paper's runtime "kernel variant selection"
+ * fork, Sec. 7.2):
+ *  0 log10 n          1 log10 max(nnz,1)   2 mean row length mu
+ *  3 std sigma        4 sigma/mu            5 max length
+ *  6 min length       7 median (nearest rank 50%)
+ *  8 p90              9 p99 (nearest rank: sorted[ceil(P*n/100)-1])
+ * 10 fraction of rows with len > 2 mu   11 n*max/nnz (ELL fill)
+ * 12 max|i-j|/n      13 mean|i-j|/n over entries
+ * 14 fraction of entries with |i-j| <= 64
+ * 15 skewness m3/m2^1.5 of the row lengths (0 when m2 == 0)
+ * Moments are population moments, computed in two passes in FP64. */
+void orc_features(int64_t nrows, int64_t ncols, const int32_t *row_ptr,
+                  const int32_t *col, double out[16])
+{
+    (void)ncols;
+    for (int j = 0; j < 16; ++j) out[j] = 0.0;
+    if (nrows <= 0) return;
+    int64_t nnz = row_ptr[nrows];
+    int64_t *len = malloc((size_t)nrows * sizeof(int64_t));
+    for (int64_t i = 0; i < nrows; ++i) len[i] = row_ptr[i + 1] - row_ptr[i];
+    double n = (double)nrows;
+    double mu = (double)nnz / n;
+    double m2 = 0.0, m3 = 0.0;
+    for (int64_t i = 0; i < nrows; ++i) {
+        double d = (double)len[i] - mu;
+        m2 += d * d;
+        m3 += d * d * d;
+    }
+    m2 /= n;
+    m3 /= n;
+    int64_t above = 0;
+    for (int64_t i = 0; i < nrows; ++i) if (len[i] * nrows > 2 * nnz) ++above;
+    int64_t maxbw = 0, near = 0;
+    double sumbw = 0.0;
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            int64_t d = (int64_t)col[k] - i;
+            if (d < 0) d = -d;
+            if (d > maxbw) maxbw = d;
+            sumbw += (double)d;
+            if (d <= 64) ++near;
+        }
+    qsort(len, (size_t)nrows, sizeof(int64_t), cmp_i64);
+    int64_t r50 = (50 * nrows + 99) / 100, r90 = (90 * nrows + 99) / 100;
+    int64_t r99 = (99 * nrows + 99) / 100;
+    double sigma = sqrt(m2);
+    out[0] = log10(n);
+    out[1] = log10(nnz > 0 ? (double)nnz : 1.0);
+    out[2] = mu;
+    out[3] = sigma;
+    out[4] = mu > 0.0 ? sigma / mu : 0.0;
+    out[5] = (double)len[nrows - 1];
+    out[6] = (double)len[0];
+    out[7] = (double)len[r50 - 1];
+    out[8] = (double)len[r90 - 1];
+    out[9] = (double)len[r99 - 1];
+    out[10] = (double)above / n;
+    out[11] = nnz > 0 ? n * (double)len[nrows - 1] / (double)nnz : 0.0;
+    out[12] = (double)maxbw / n;
+    out[13] = nnz > 0 ? sumbw / (double)nnz / n : 0.0;
+    out[14] = nnz > 0 ? (double)near / (double)nnz : 0.0;
+    out[15] = m2 > 0.0 ? m3 / pow(m2, 1.5) : 0.0;
+    free(len);
+}
+
+/* ----------------------------------------------------------------- MLP */
+
+/* Fully connected network dims[0] -> dims[1] -> ... -> dims[nlayers], ReLU
+ * after every layer but the last.  theta packs, layer by layer, W_l
+ * (dims[l+1] x dims[l], row-major) followed by b_l (dims[l+1]).
+ *
+ * loss = sum_{i,c} M_ic (yhat_ic - Y_ic)^2 / sum M  +  lambda * sum_l ||W_l||_F^2
+ *
+ * grad (optional) receives d loss / d theta by reverse-mode differentiation
+ * of exactly this expression; pred (optional) receives yhat (N x dims[L]). */
+double orc_mlp_loss_grad(int32_t nlayers, const int32_t *dims,
+                         const double *theta, int64_t nsamples,
+                         const double *X, const double *Y, const double *M,
+                         double lambda, double *grad, double *pred)
+{
+    int64_t off[64], width = 0, nparams = 0, total_act = 0;
+    for (int l = 0; l < nlayers; ++l) {
+        off[l] = nparams;
+        nparams += (int64_t)dims[l + 1] * dims[l] + dims[l + 1];
+    }
+    for (int l = 0; l <= nlayers; ++l) {
+        if (dims[l] > width) width = dims[l];
+        total_act += dims[l];
+    }
+    int32_t C = dims[nlayers];
+    double msum = 0.0;
+    for (int64_t i = 0; i < nsamples * C; ++i) msum += M[i];
+    double *h = malloc((size_t)total_act * sizeof(double));   /* pre-activations */
+    double *a = malloc((size_t)total_act * sizeof(double));   /* activations */
+    double *da = malloc((size_t)width * sizeof(double));
+    double *dh = malloc((size_t)width * sizeof(double));
+    if (grad) for (int64_t j = 0; j < nparams; ++j) grad[j] = 0.0;
+    double data = 0.0;
+    for (int64_t s = 0; s < nsamples; ++s) {
+        int64_t ao = 0;
+        for (int j = 0; j < dims[0]; ++j) a[j] = X[s * dims[0] + j];
+        for (int l = 0; l < nlayers; ++l) {
+            const double *W = theta + off[l];
+            const double *bb = W + (int64_t)dims[l + 1] * dims[l];
+            int64_t no = ao + dims[l];
+            for (int o = 0; o < dims[l + 1]; ++o) {
+                double acc = bb[o];
+                for (int j = 0; j < dims[l]; ++j) acc += W[(int64_t)o * dims[l] + j] * a[ao + j];
+                h[no + o] = acc;
+                a[no + o] = (l < nlayers - 1) ? (acc > 0.0 ? acc : 0.0) : acc;
+            }
+            ao = no;
+        }
+        for (int c = 0; c < C; ++c) {
+            double e = a[ao + c] - Y[s * C + c];
+            double m = M[s * C + c];
+            data += m * e * e;
+            if (pred) pred[s * C + c] = a[ao + c];
+            dh[c] = msum > 0.0 ? 2.0 * m * e / msum : 0.0;
+        }
+        if (!grad) continue;
+        /* backward: dh holds d loss / d h for layer l's outputs */
+        for (int l = nlayers - 1; l >= 0; --l) {
+            const double *W = theta + off[l];
+            double *gW = grad + off[l];
+            double *gb = gW + (int64_t)dims[l + 1] * dims[l];
+            int64_t in_o = ao - dims[l];
+            for (int o = 0; o < dims[l + 1]; ++o) {
+                gb[o] += dh[o];
+                for (int j = 0; j < dims[l]; ++j)
+                    gW[(int64_t)o * dims[l] + j] += dh[o] * a[in_o + j];
+            }
+            if (l == 0) break;
+            for (int j = 0; j < dims[l]; ++j) {
+                double acc = 0.0;
+                for (int o = 0; o < dims[l + 1]; ++o) acc += W[(int64_t)o * dims[l] + j] * dh[o];
+                da[j] = acc;
+            }
+            for (int j = 0; j < dims[l]; ++j) dh[j] = h[in_o + j] > 0.0 ? da[j] : 0.0;
+            ao = in_o;
+        }
+    }
+    double loss = msum > 0.0 ? data / msum : 0.0;
+    for (int l = 0; l < nlayers; ++l) {
+        const double *W = theta + off[l];
+        int64_t nw = (int64_t)dims[l + 1] * dims[l];
+        for (int64_t j = 0; j < nw; ++j) {
+            loss += lambda * W[j] * W[j];
+            if (grad) grad[off[l] + j] += 2.0 * lambda * W[j];
+        }
+    }
+    free(h); free(a); free(da); free(dh);
+    return loss;
+}
+
+/* Adam (Kingma & Ba) with bias correction; t is the 1-based step count. */
+void orc_adam_step(int64_t nparams, double *theta, const double *grad,
+                   double *m, double *v, int64_t t, double lr, double beta1,
+                   double beta2, double eps)
+{
+    double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t j = 0; j < nparams; ++j) {
+        m[j] = beta1 * m[j] + (1.0 - beta1) * grad[j];
+        v[j] = beta2 * v[j] + (1.0 - beta2) * grad[j] * grad[j];
+        double mh = m[j] / c1, vh = v[j] / c2;
+        theta[j] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
