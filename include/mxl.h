@@ -1,0 +1,304 @@
+/*
+ * mxl.h -- C ABI of the MI355X (gfx950) sparse linear-operator library.
+ *
+ * The library follows the operator view of the paper (Sec. 2.2): a sparse
+ * matrix, a preconditioner and a solver are all linear operators with one
+ * application call, x = L(b) (Sec. 2.2.2), and an advanced form
+ * x = alpha*L(b) + beta*x (Sec. 4.2).  Solvers and preconditioners are
+ * produced by binding a system matrix to a factory (Sec. 2.2.3), with the
+ * stopping criteria of Sec. 2.5.
+ *
+ * Conventions for every entry point
+ *  - Every call returns mxl_status; MXL_OK is 0.  No C++ exception crosses
+ *    this boundary.  On a non-OK status, mxl_last_error() returns a
+ *    thread-local, NUL-terminated description valid until the next call on
+ *    the same thread.
+ *  - Vector and matrix-array arguments are DEVICE pointers on the context's
+ *    device unless a parameter says "host".  The library never frees memory
+ *    it did not allocate.
+ *  - Work is enqueued on the context's HIP stream (borrowed from the caller)
+ *    and is stream-ordered: mxl_apply* returns before the result is ready,
+ *    exactly like a kernel launch.  mxl_solve and
+ *    mxl_batch_solve block until the solve has stopped.
+ *  - Index arrays are int32 and must describe canonical CSR: row_ptr[0] = 0,
+ *    non-decreasing, row_ptr[nrows] = nnz, column indices in [0, ncols) and
+ *    strictly increasing within a row.
+ *  - Handles are not thread-safe: do not use one handle from two host
+ *    threads at once.
+ */
+#ifndef MXL_H
+#define MXL_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MXL_OK = 0,
+    MXL_ERR_INVALID_ARG = 1,       /* null/unknown argument, aliasing, bad enum */
+    MXL_ERR_DIM_MISMATCH = 2,      /* operand sizes do not conform */
+    MXL_ERR_DTYPE = 3,             /* operand value type does not match */
+    MXL_ERR_NOT_IMPLEMENTED = 4,   /* combination not provided */
+    MXL_ERR_INVALID_MATRIX = 5,    /* CSR arrays not canonical */
+    MXL_ERR_ZERO_DIAG = 6,         /* missing or zero diagonal entry */
+    MXL_ERR_OUT_OF_MEMORY = 7,
+    MXL_ERR_INFEASIBLE_FORMAT = 8, /* padded format exceeds its memory budget */
+    MXL_ERR_DEVICE = 9             /* HIP runtime error */
+} mxl_status;
+
+typedef enum { MXL_F64 = 0, MXL_F32 = 1 } mxl_dtype;
+
+typedef enum { MXL_FMT_CSR = 0, MXL_FMT_COO = 1, MXL_FMT_ELL = 2, MXL_FMT_HYB = 3 } mxl_format;
+
+/* Kernel variants (the "kernel variant selection" fork of Sec. 7.2). */
+enum {
+    MXL_CSR_SCALAR = 0,  /* one lane per row */
+    MXL_CSR_VECTOR = 1,  /* W lanes per row, W = vector_width in {2..64} */
+    MXL_CSR_MERGE = 2,   /* merge-path split of rows+nonzeros */
+    MXL_COO_SEGRED = 0,  /* segmented reduction over row-sorted triplets */
+    MXL_ELL_PLAIN = 0,   /* one lane per row, gathers x from memory */
+    MXL_ELL_LDS = 1,     /* stages each block's x window in LDS when it fits */
+    MXL_HYB_DEFAULT = 0
+};
+
+typedef struct {
+    int32_t variant;       /* MXL_CSR_* / MXL_ELL_* ... */
+    int32_t vector_width;  /* CSR vector: lanes per row (0 = from mean row length) */
+    double  hyb_quantile;  /* HYB: ELL width = nearest-rank quantile of row lengths (0 = 0.9) */
+} mxl_format_params;
+
+typedef enum { MXL_OP_MATRIX = 0, MXL_OP_JACOBI = 1, MXL_OP_SOLVER = 2, MXL_OP_BATCH = 3 } mxl_op_kind;
+
+typedef enum { MXL_SOLVER_CG = 0, MXL_SOLVER_BICGSTAB = 1, MXL_SOLVER_IR = 2 } mxl_solver_kind;
+
+/* Stop reasons: the stopping_status of Sec. 2.5. */
+typedef enum {
+    MXL_STOP_NONE = 0, MXL_STOP_CONVERGED = 1, MXL_STOP_MAX_ITERS = 2,
+    MXL_STOP_TIME = 3, MXL_STOP_BREAKDOWN = 4, MXL_STOP_NONFINITE = 5
+} mxl_stop;
+
+/* Stopping criteria (Sec. 2.5), combined by logical OR: the first one met
+ * stops the iteration.  Iteration: max_iters.  ResidualNormReduction:
+ * ||r_k||_2 <= reduction * ||b||_2 on the recurrence residual.  Time:
+ * time_limit_s wall seconds, checked on the host every check_every
+ * iterations (<= 0 disables).  check_every >= 1 is how often the host reads
+ * the device-side status; iterations after a device-side stop are no-ops, so
+ * results do not depend on it.  nonfinite_check = 1 stops with
+ * MXL_STOP_NONFINITE when a reduction yields NaN/Inf. */
+typedef struct {
+    int64_t max_iters;
+    double  reduction;
+    double  time_limit_s;
+    int32_t check_every;
+    int32_t nonfinite_check;
+} mxl_criteria;
+
+/* Convergence record (the Convergence logger of Sec. 2.6) plus an optional
+ * residual history (the Record logger): if history is a non-null HOST
+ * pointer with history_cap > 0 entries, history[k] receives ||r_k||/||b||
+ * for k = 0..min(iterations, history_cap-1). */
+typedef struct {
+    int64_t iterations;
+    int64_t spmv_count;
+    double  rel_residual;   /* recurrence residual norm / ||b|| at exit */
+    int32_t stop_reason;    /* mxl_stop */
+    double  seconds;        /* host wall time of the solve */
+    double *history;        /* in: host buffer or NULL */
+    int64_t history_cap;    /* in */
+    int64_t inner_iterations; /* iterative refinement: total inner iterations */
+    int32_t time_spmv;      /* in: nonzero = time every SpMV launch of the
+                               Krylov loop with HIP events (first 4096) */
+    double  spmv_ms;        /* out: summed SpMV time of the timed launches */
+    int64_t spmv_timed;     /* out: number of timed launches */
+} mxl_solve_info;
+
+typedef struct mxl_ctx mxl_ctx;
+typedef struct mxl_op mxl_op;
+
+/* ---------------------------------------------------------------- context */
+
+/* Executor (Sec. 2.3): one gfx950 device plus the caller's HIP stream
+ * (borrowed, not destroyed; NULL = the null stream).  Errors: INVALID_ARG
+ * for out==NULL, DEVICE if the device cannot be selected or is not gfx950. */
+mxl_status mxl_ctx_create(int device, void *hip_stream, mxl_ctx **out);
+mxl_status mxl_ctx_set_stream(mxl_ctx *ctx, void *hip_stream);
+mxl_status mxl_ctx_destroy(mxl_ctx *ctx);
+const char *mxl_last_error(void);
+/* Library version string, static storage. */
+const char *mxl_version(void);
+
+/* ---------------------------------------------------------------- matrices */
+
+enum { MXL_BORROW = 0, MXL_COPY = 1, MXL_VALIDATE = 2 };
+
+/* Wrap a CSR matrix (Sec. 2.2.4) as an operator.  row_ptr (nrows+1), col
+ * (nnz) and val (nnz, dtype) are device arrays.  flags: MXL_BORROW keeps
+ * views of the caller's arrays, which must stay alive and unchanged until
+ * the handle and everything derived from it are destroyed (the Array views
+ * of Sec. 2.4); MXL_COPY makes library-owned copies.  MXL_VALIDATE (or-ed
+ * in) checks canonical form on the device and fails with INVALID_MATRIX.
+ * Errors: INVALID_ARG (null, negative sizes, nnz >= 2^31), DTYPE,
+ * INVALID_MATRIX, OUT_OF_MEMORY. */
+mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows,
+                          int64_t ncols, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col, const void *val, int flags,
+                          mxl_op **A);
+
+/* New operator with the same values in another format or kernel variant
+ * (COO: explicit row of each entry, CSR order; ELL: slot-major [w][n_pad]
+ * with n_pad = nrows rounded up to 64, padding column -1 / value 0; HYB:
+ * ELL part of width k = nearest-rank quantile of row lengths plus a
+ * row-sorted COO tail).  The result shares A's arrays by reference counting
+ * and adds its own.  Errors: INFEASIBLE_FORMAT when ELL storage exceeds
+ * min(4 x CSR bytes, 32 GiB); NOT_IMPLEMENTED; INVALID_ARG. */
+mxl_status mxl_convert(const mxl_op *A, mxl_format fmt,
+                       const mxl_format_params *params, mxl_op **out);
+
+/* New operator with values rounded to another precision (same format and
+ * variant; index arrays shared).  Memory precision decoupled from
+ * arithmetic precision, Sec. 3.2. */
+mxl_status mxl_cast(const mxl_op *A, mxl_dtype dtype, mxl_op **out);
+
+/* x = L(b) (Sec. 2.2.2).  Matrix: SpMV.  Jacobi: x = D^{-1} b.  Solver:
+ * solve with x as the initial guess (blocks; see mxl_solve).
+ * Errors: INVALID_ARG (null, b == x), NOT_IMPLEMENTED. */
+mxl_status mxl_apply(const mxl_op *L, const void *b, void *x);
+
+/* x = alpha*L(b) + beta*x (Sec. 4.2).  beta == 0: x is not read (BLAS
+ * convention, so NaN in x does not propagate).  Matrices and Jacobi only. */
+mxl_status mxl_apply_adv(const mxl_op *L, double alpha, const void *b,
+                         double beta, void *x);
+
+/* Describe an operator. */
+typedef struct {
+    int32_t kind, format, variant, dtype;
+    int64_t nrows, ncols, nnz;
+    int32_t vector_width, ell_width;
+    int64_t n_pad, tail_nnz;
+    int64_t stored_bytes;  /* bytes of the format's own arrays */
+} mxl_op_desc;
+mxl_status mxl_op_describe(const mxl_op *A, mxl_op_desc *out);
+
+/* Copy one of the format's arrays into dst (device memory, dst_bytes
+ * capacity) on the context stream, for inspection.  which: 0 row_ptr, 1 col,
+ * 2 val, 3 coo_row, 4 ell_col, 5 ell_val, 6 tail_row, 7 tail_col,
+ * 8 tail_val, 9 jacobi dinv.  Errors: INVALID_ARG if absent or too small. */
+mxl_status mxl_op_export(const mxl_op *A, int32_t which, void *dst,
+                         int64_t dst_bytes);
+
+/* Decrement the reference count; storage owned by the library is released
+ * when no handle refers to it any more.  NULL is accepted. */
+mxl_status mxl_op_destroy(mxl_op *op);
+
+/* ---------------------------------------------------- preconditioner/solver */
+
+/* Point Jacobi (block-Jacobi with block size 1, Sec. 3.2):
+ * dinv_i = 1/a_ii computed in FP64 and rounded to A's precision.
+ * Errors: ZERO_DIAG (a missing or zero a_ii), NOT_IMPLEMENTED (non-square). */
+mxl_status mxl_jacobi_generate(const mxl_op *A, mxl_op **P);
+
+/* Solver factory .generate(A) (Sec. 2.2.3, Sec. 3.1): Krylov solver bound to
+ * A with optional preconditioner P (NULL = none).  The solver keeps shared
+ * references to A and P and owns its work vectors. */
+mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *A,
+                               const mxl_op *P, const mxl_criteria *crit,
+                               mxl_op **S);
+
+/* Solve A x = b; x holds the initial guess on entry and the solution on exit
+ * (Sec. 2.1).  Blocks until a criterion stops the iteration.  Not reaching
+ * the tolerance is not an error: the status is OK and info->stop_reason
+ * tells which criterion stopped it.  info may be NULL. */
+mxl_status mxl_solve(const mxl_op *S, const void *b, void *x,
+                     mxl_solve_info *info);
+
+/* Mixed-precision iterative refinement (the IR solver with a configurable
+ * inner solver of Sec. 2.2.3 and Sec. 3.1, the inner solve in FP32 storage
+ * per the precision decoupling of Sec. 3.2).  A must be FP64.  The
+ * generated operator holds an FP32 copy of A's values, FP32 Jacobi
+ * (dinv rounded from the FP64 reciprocal) and an FP32 Jacobi-CG.  mxl_solve
+ * on it repeats: r = b - A x (FP64, on the device); stop if
+ * ||r||/||b|| <= outer.reduction (or outer.max_iters corrections applied, or
+ * outer.time_limit_s); s = ||r||_inf; solve A32 d = fp32(r/s) from d = 0 to
+ * inner.reduction / inner.max_iters; x += s*d (FP64).  info->iterations
+ * counts corrections, info->inner_iterations all inner CG iterations,
+ * info->history the outer relative residuals. */
+typedef struct {
+    mxl_criteria outer;
+    mxl_criteria inner;
+} mxl_ir_params;
+mxl_status mxl_ir_generate(const mxl_op *A, const mxl_ir_params *params, mxl_op **S);
+
+/* ----------------------------------------------------------------- batched */
+
+/* nsys independent systems packed in one CSR: system s owns rows
+ * sys_ptr[s]..sys_ptr[s+1]-1; row_ptr holds global nonzero offsets; column
+ * indices are local to the system.  All arrays are device arrays, FP64
+ * values.  flags as in mxl_csr_create. */
+mxl_status mxl_batch_csr_create(mxl_ctx *ctx, int64_t nsys,
+                                const int32_t *sys_ptr_host,
+                                const int32_t *sys_ptr, const int32_t *row_ptr,
+                                const int32_t *col, const double *val,
+                                int flags, mxl_op **B);
+
+/* Schedule of the persistent batched kernel.  wg_size in {64,128,256,512,
+ * 1024}; wgs_per_cu >= 1 resident workgroups per compute unit; order 0 =
+ * systems in input order, 1 = largest first. */
+typedef struct { int32_t wg_size; int32_t wgs_per_cu; int32_t order; } mxl_tuning;
+
+/* Jacobi-PCG on every system independently (per-system stopping status,
+ * Sec. 2.5), all in one persistent launch.  crit->max_iters <= 0 means
+ * 10*n_s per system.  tuning NULL = the autotuned schedule (cached per
+ * handle).  b, x: device FP64 of total rows; iters, rel_res, status: device
+ * arrays of nsys entries. */
+mxl_status mxl_batch_solve(const mxl_op *B, const mxl_criteria *crit,
+                           const mxl_tuning *tuning, const double *b,
+                           double *x, int32_t *iters, double *rel_res,
+                           uint8_t *status);
+
+/* Autotune the batched schedule: times each candidate (reps launches each)
+ * and stores the best on the handle; best may be NULL. */
+mxl_status mxl_batch_autotune(const mxl_op *B, const mxl_criteria *crit,
+                              const double *b, double *x_scratch, int reps,
+                              mxl_tuning *best, double *best_ms);
+
+/* ---------------------------------------------------------------- selector */
+
+/* The 16 structural features of a CSR matrix (host output, FP64):
+ * log10 n, log10 nnz, mean/std/cv/max/min/median/p90/p99 row length,
+ * fraction of rows longer than twice the mean, ELL fill n*max/nnz,
+ * max and mean |i-j|/n, fraction of entries with |i-j| <= 64, skewness. */
+mxl_status mxl_features(const mxl_op *A, double out_host[16]);
+
+/* Median time in milliseconds of reps applications y = A x (HIP events on
+ * the context stream).  flush != 0 writes a 1 GiB buffer before every rep
+ * to evict the 256 MB last-level cache; its time is excluded. */
+mxl_status mxl_time_apply(const mxl_op *A, const void *x, void *y, int reps,
+                          int flush, double *median_ms);
+
+/* Small FP32 multilayer perceptron dims[0] -> ... -> dims[nlayers] with
+ * ReLU between layers (weights live on the device).  theta_host packs
+ * W_l (row-major, dims[l+1] x dims[l]) then b_l for each layer. */
+typedef struct mxl_mlp mxl_mlp;
+mxl_status mxl_mlp_create(mxl_ctx *ctx, int32_t nlayers, const int32_t *dims,
+                          const float *theta_host, mxl_mlp **out);
+mxl_status mxl_mlp_get_params(const mxl_mlp *m, float *theta_host, int64_t n);
+mxl_status mxl_mlp_set_params(mxl_mlp *m, const float *theta_host, int64_t n);
+/* Y = f(X): X device FP32 (nsamples x dims[0]) -> Y device (nsamples x dims[L]). */
+mxl_status mxl_mlp_forward(const mxl_mlp *m, int64_t nsamples, const float *X,
+                           float *Y);
+/* loss = sum M (f(X)-T)^2 / sum M + lambda sum ||W||^2; gradient kept on the
+ * device (mxl_mlp_get_grad copies it out).  loss_host may be NULL. */
+mxl_status mxl_mlp_loss_grad(mxl_mlp *m, int64_t nsamples, const float *X,
+                             const float *T, const float *M, float lambda,
+                             float *loss_host);
+mxl_status mxl_mlp_get_grad(const mxl_mlp *m, float *grad_host, int64_t n);
+/* Adam step on the stored gradient (bias-corrected, step t >= 1). */
+mxl_status mxl_mlp_adam_step(mxl_mlp *m, int64_t t, float lr, float beta1,
+                             float beta2, float eps);
+mxl_status mxl_mlp_destroy(mxl_mlp *m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MXL_H */

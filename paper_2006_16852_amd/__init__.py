@@ -1,0 +1,344 @@
+"""Python binding of libmxl, the MI355X (gfx950) sparse linear-operator library.
+
+Argument marshalling only: every step of SpMV, Jacobi, the Krylov solvers,
+iterative refinement, the batched solver, the features and the MLP runs in
+the HIP kernels of ``libmxl.so`` behind the C ABI of ``include/mxl.h``.
+PyTorch provides device memory and the current HIP stream.  There is no CPU
+fallback: if ``libmxl.so`` is missing, importing this package raises.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmxl.so")
+
+# ----------------------------------------------------------------- constants
+F64, F32 = 0, 1
+CSR, COO, ELL, HYB = 0, 1, 2, 3
+CSR_SCALAR, CSR_VECTOR, CSR_MERGE = 0, 1, 2
+COO_SEGRED = 0
+ELL_PLAIN, ELL_LDS = 0, 1
+OP_MATRIX, OP_JACOBI, OP_SOLVER, OP_BATCH = 0, 1, 2, 3
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_IR = 0, 1, 2
+STOP_NONE, STOP_CONVERGED, STOP_MAX_ITERS, STOP_TIME, STOP_BREAKDOWN, STOP_NONFINITE = range(6)
+OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_DTYPE, ERR_NOT_IMPLEMENTED, ERR_INVALID_MATRIX, \
+    ERR_ZERO_DIAG, ERR_OUT_OF_MEMORY, ERR_INFEASIBLE_FORMAT, ERR_DEVICE = range(10)
+STATUS_NAMES = ["OK", "INVALID_ARG", "DIM_MISMATCH", "DTYPE", "NOT_IMPLEMENTED",
+                "INVALID_MATRIX", "ZERO_DIAG", "OUT_OF_MEMORY", "INFEASIBLE_FORMAT", "DEVICE"]
+STOP_NAMES = ["none", "converged", "max_iters", "time", "breakdown", "nonfinite"]
+FORMATS = {"csr": CSR, "coo": COO, "ell": ELL, "hyb": HYB}
+EXPORT_IDS = {"row_ptr": 0, "col": 1, "val": 2, "coo_row": 3, "ell_col": 4, "ell_val": 5,
+              "tail_row": 6, "tail_col": 7, "tail_val": 8, "dinv": 9}
+
+
+class MxlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"mxl {name}: {msg}")
+
+
+class Criteria(C.Structure):
+    _fields_ = [("max_iters", C.c_int64), ("reduction", C.c_double),
+                ("time_limit_s", C.c_double), ("check_every", C.c_int32),
+                ("nonfinite_check", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("spmv_count", C.c_int64),
+                ("rel_residual", C.c_double), ("stop_reason", C.c_int32),
+                ("seconds", C.c_double), ("history", C.POINTER(C.c_double)),
+                ("history_cap", C.c_int64), ("inner_iterations", C.c_int64),
+                ("time_spmv", C.c_int32), ("spmv_ms", C.c_double), ("spmv_timed", C.c_int64)]
+
+
+class FormatParams(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("vector_width", C.c_int32),
+                ("hyb_quantile", C.c_double)]
+
+
+class OpDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("format", C.c_int32), ("variant", C.c_int32),
+                ("dtype", C.c_int32), ("nrows", C.c_int64), ("ncols", C.c_int64),
+                ("nnz", C.c_int64), ("vector_width", C.c_int32), ("ell_width", C.c_int32),
+                ("n_pad", C.c_int64), ("tail_nnz", C.c_int64), ("stored_bytes", C.c_int64)]
+
+
+class IrParams(C.Structure):
+    _fields_ = [("outer", Criteria), ("inner", Criteria)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("wg_size", C.c_int32), ("wgs_per_cu", C.c_int32), ("order", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+            f"g.build()'` (hipcc, gfx950). There is no CPU fallback.")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, f64, st = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "mxl_ctx_create": [C.c_int, vp, pp],
+        "mxl_ctx_set_stream": [vp, vp],
+        "mxl_ctx_destroy": [vp],
+        "mxl_csr_create": [vp, C.c_int, i64, i64, i64, vp, vp, vp, C.c_int, pp],
+        "mxl_convert": [vp, C.c_int, C.POINTER(FormatParams), pp],
+        "mxl_cast": [vp, C.c_int, pp],
+        "mxl_apply": [vp, vp, vp],
+        "mxl_apply_adv": [vp, f64, vp, f64, vp],
+        "mxl_op_describe": [vp, C.POINTER(OpDesc)],
+        "mxl_op_export": [vp, i32, vp, i64],
+        "mxl_op_destroy": [vp],
+        "mxl_jacobi_generate": [vp, pp],
+        "mxl_solver_generate": [C.c_int, vp, vp, C.POINTER(Criteria), pp],
+        "mxl_solve": [vp, vp, vp, C.POINTER(SolveInfo)],
+        "mxl_ir_generate": [vp, C.POINTER(IrParams), pp],
+        "mxl_batch_csr_create": [vp, i64, vp, vp, vp, vp, vp, C.c_int, pp],
+        "mxl_batch_solve": [vp, C.POINTER(Criteria), C.POINTER(Tuning), vp, vp, vp, vp, vp],
+        "mxl_batch_autotune": [vp, C.POINTER(Criteria), vp, vp, C.c_int, C.POINTER(Tuning),
+                               C.POINTER(C.c_double)],
+        "mxl_features": [vp, vp],
+        "mxl_time_apply": [vp, vp, vp, C.c_int, C.c_int, C.POINTER(C.c_double)],
+        "mxl_mlp_create": [vp, i32, vp, vp, pp],
+        "mxl_mlp_get_params": [vp, vp, i64],
+        "mxl_mlp_set_params": [vp, vp, i64],
+        "mxl_mlp_forward": [vp, i64, vp, vp],
+        "mxl_mlp_loss_grad": [vp, i64, vp, vp, vp, C.c_float, vp],
+        "mxl_mlp_get_grad": [vp, vp, i64],
+        "mxl_mlp_adam_step": [vp, i64, C.c_float, C.c_float, C.c_float, C.c_float],
+        "mxl_mlp_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
+    L.mxl_last_error.restype = C.c_char_p
+    L.mxl_last_error.argtypes = []
+    L.mxl_version.restype = C.c_char_p
+    L.mxl_version.argtypes = []
+    return L
+
+
+lib = _load()
+_alive = [True]
+
+
+@atexit.register
+def _shutdown():
+    # handles still referenced at interpreter exit are reclaimed by the
+    # process teardown; calling into HIP from finalizers then is unsafe
+    _alive[0] = False
+
+
+def _check(status: int):
+    if status != OK:
+        raise MxlError(status, lib.mxl_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise MxlError(ERR_DTYPE, f"unsupported value dtype {t.dtype}")
+
+
+def _torch_dtype(code: int):
+    return torch.float64 if code == F64 else torch.float32
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise MxlError(ERR_INVALID_ARG, "tensors must be contiguous and on the GPU")
+
+
+def version() -> str:
+    return lib.mxl_version().decode()
+
+
+class Context:
+    """Executor: one device plus torch's current HIP stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+        _check(lib.mxl_ctx_create(device, C.c_void_p(stream), C.byref(h)))
+        self.h = h
+
+    def use_current_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib.mxl_ctx_set_stream(self.h, C.c_void_p(s)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _alive[0]:
+            lib.mxl_ctx_destroy(self.h)
+            self.h = None
+
+
+class Op:
+    """Reference-counted operator handle (matrix, Jacobi, solver)."""
+
+    def __init__(self, h, ctx, keep=(), parents=()):
+        self.h = h
+        self.ctx = ctx
+        self._keep = tuple(keep)      # borrowed tensors must outlive the handle
+        self._parents = tuple(parents)
+
+    def describe(self) -> dict:
+        d = OpDesc()
+        _check(lib.mxl_op_describe(self.h, C.byref(d)))
+        return {f: getattr(d, f) for f, _ in OpDesc._fields_}
+
+    @property
+    def nrows(self):
+        return self.describe()["nrows"]
+
+    @property
+    def dtype(self):
+        return _torch_dtype(self.describe()["dtype"])
+
+    def export(self, which: str) -> torch.Tensor:
+        d = self.describe()
+        n, nnz, w, npad, tail = d["nrows"], d["nnz"], d["ell_width"], d["n_pad"], d["tail_nnz"]
+        vt = _torch_dtype(d["dtype"])
+        shape = {"row_ptr": (n + 1, torch.int32), "col": (nnz, torch.int32), "val": (nnz, vt),
+                 "coo_row": (nnz, torch.int32), "ell_col": (w * npad, torch.int32),
+                 "ell_val": (w * npad, vt), "tail_row": (tail, torch.int32),
+                 "tail_col": (tail, torch.int32), "tail_val": (tail, vt), "dinv": (n, vt)}[which]
+        out = torch.empty(max(shape[0], 1), dtype=shape[1], device=f"cuda:{self.ctx.device}")
+        self.ctx.use_current_stream()
+        _check(lib.mxl_op_export(self.h, EXPORT_IDS[which], _ptr(out),
+                                 out.numel() * out.element_size()))
+        return out[:shape[0]]
+
+    def apply(self, b: torch.Tensor, x: torch.Tensor, alpha: float = 1.0, beta: float = 0.0):
+        """x = alpha * L(b) + beta * x (stream-ordered)."""
+        _need_cuda(b, x)
+        self.ctx.use_current_stream()
+        _check(lib.mxl_apply_adv(self.h, alpha, _ptr(b), beta, _ptr(x)))
+        return x
+
+    def convert(self, fmt: str, variant: int = 0, vector_width: int = 0,
+                hyb_quantile: float = 0.0) -> "Op":
+        p = FormatParams(variant, vector_width, hyb_quantile)
+        h = C.c_void_p()
+        self.ctx.use_current_stream()
+        _check(lib.mxl_convert(self.h, FORMATS[fmt], C.byref(p), C.byref(h)))
+        return Op(h, self.ctx, parents=(self,))
+
+    def cast(self, dtype) -> "Op":
+        code = F64 if dtype == torch.float64 else F32
+        h = C.c_void_p()
+        self.ctx.use_current_stream()
+        _check(lib.mxl_cast(self.h, code, C.byref(h)))
+        return Op(h, self.ctx, parents=(self,))
+
+    def time_apply(self, x, y, reps=20, flush=False) -> float:
+        _need_cuda(x, y)
+        ms = C.c_double()
+        self.ctx.use_current_stream()
+        _check(lib.mxl_time_apply(self.h, _ptr(x), _ptr(y), reps, int(flush), C.byref(ms)))
+        return ms.value
+
+    def features(self):
+        import numpy as np
+        out = np.zeros(16)
+        self.ctx.use_current_stream()
+        _check(lib.mxl_features(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _alive[0]:
+            lib.mxl_op_destroy(self.h)
+            self.h = None
+
+
+def csr(ctx: Context, row_ptr, col, val, ncols=None, copy=False, validate=False) -> Op:
+    """Wrap device CSR arrays (int32 row_ptr/col, float64/float32 values)."""
+    _need_cuda(row_ptr, col, val)
+    if row_ptr.dtype != torch.int32 or col.dtype != torch.int32:
+        raise MxlError(ERR_INVALID_ARG, "row_ptr and col must be int32")
+    n = row_ptr.numel() - 1
+    ncols = n if ncols is None else ncols
+    flags = (1 if copy else 0) | (2 if validate else 0)
+    h = C.c_void_p()
+    ctx.use_current_stream()
+    _check(lib.mxl_csr_create(ctx.h, _dtype_code(val), n, ncols, col.numel(), _ptr(row_ptr),
+                              _ptr(col), _ptr(val), flags, C.byref(h)))
+    return Op(h, ctx, keep=() if copy else (row_ptr, col, val))
+
+
+def jacobi(A: Op) -> Op:
+    h = C.c_void_p()
+    A.ctx.use_current_stream()
+    _check(lib.mxl_jacobi_generate(A.h, C.byref(h)))
+    return Op(h, A.ctx, parents=(A,))
+
+
+def criteria(max_iters=10_000, reduction=1e-10, time_limit=0.0, check_every=1,
+             nonfinite_check=1) -> Criteria:
+    return Criteria(max_iters, reduction, time_limit, check_every, nonfinite_check)
+
+
+class Solver(Op):
+    def solve(self, b: torch.Tensor, x: torch.Tensor, history: int = 0,
+              time_spmv: bool = False) -> dict:
+        """Solve A x = b in place (x = initial guess on entry)."""
+        _need_cuda(b, x)
+        info = SolveInfo()
+        info.time_spmv = int(time_spmv)
+        hbuf = None
+        if history:
+            hbuf = (C.c_double * history)()
+            info.history = C.cast(hbuf, C.POINTER(C.c_double))
+            info.history_cap = history
+        self.ctx.use_current_stream()
+        _check(lib.mxl_solve(self.h, _ptr(b), _ptr(x), C.byref(info)))
+        out = dict(iterations=info.iterations, spmv_count=info.spmv_count,
+                   rel_residual=info.rel_residual, stop_reason=info.stop_reason,
+                   stop=STOP_NAMES[info.stop_reason], seconds=info.seconds,
+                   inner_iterations=info.inner_iterations, spmv_ms=info.spmv_ms,
+                   spmv_timed=info.spmv_timed)
+        if history:
+            cnt = min(history, (info.iterations + 1))
+            out["history"] = list(hbuf[:cnt])
+        return out
+
+
+def solver(kind: str, A: Op, P: Op = None, **crit) -> Solver:
+    k = {"cg": SOLVER_CG, "bicgstab": SOLVER_BICGSTAB}[kind]
+    c = criteria(**crit)
+    h = C.c_void_p()
+    A.ctx.use_current_stream()
+    _check(lib.mxl_solver_generate(k, A.h, P.h if P is not None else None, C.byref(c), C.byref(h)))
+    return Solver(h, A.ctx, parents=(A,) + ((P,) if P is not None else ()))
+
+
+def ir(A: Op, outer: dict = None, inner: dict = None) -> Solver:
+    """FP64-outer / FP32-inner-CG iterative refinement operator."""
+    o = criteria(**({"max_iters": 50, "reduction": 1e-12} | (outer or {})))
+    i = criteria(**({"max_iters": 10_000, "reduction": 1e-4} | (inner or {})))
+    prm = IrParams(o, i)
+    h = C.c_void_p()
+    A.ctx.use_current_stream()
+    _check(lib.mxl_ir_generate(A.h, C.byref(prm), C.byref(h)))
+    return Solver(h, A.ctx, parents=(A,))

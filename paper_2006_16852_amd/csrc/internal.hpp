@@ -1,0 +1,179 @@
+// internal.hpp -- host-side objects of the library (context, reference-
+// counted device buffers, operator handles) and the launcher interfaces the
+// runtime uses to reach the kernels.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mxl.h"
+
+namespace mxl {
+
+
+struct SolverState;
+
+// A device allocation, freed when the last shared owner lets go.  Borrowed
+// views (owned = false) are never freed.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    bool owned = false;
+    ~DevBuf() {
+        if (owned && p) (void)hipFree(p);
+    }
+};
+using BufPtr = std::shared_ptr<DevBuf>;
+
+}  // namespace mxl
+
+struct mxl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::string arch;
+    void *pinned = nullptr;     // host-pinned staging for solver state read-back
+    size_t pinned_bytes = 0;
+    mxl::BufPtr flush_buf;      // lazily allocated 1 GiB buffer for cache flushes
+};
+
+namespace mxl {
+
+struct MatrixImpl {
+    mxl_ctx *ctx = nullptr;
+    int dtype = MXL_F64;
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    int format = MXL_FMT_CSR;
+    int variant = MXL_CSR_VECTOR;
+    int vw = 32;                       // CSR vector lanes per row
+    BufPtr row_ptr, col, val;          // canonical CSR (always present)
+    BufPtr coo_row;                    // COO
+    BufPtr ell_col, ell_val, ell_win;  // ELL / HYB ELL part
+    int ell_w = 0;
+    int64_t n_pad = 0;
+    double hyb_q = 0.0;
+    BufPtr tail_row, tail_col, tail_val;  // HYB COO tail
+    int64_t tail_nnz = 0;
+    BufPtr part;                       // merge-path tile boundaries (int2)
+    int64_t ntiles = 0;                // merge / COO / HYB-tail tiles
+    BufPtr carries;                    // per-tile carries
+    int grid_main = 0, grid_tail = 0;  // workgroups of the chain's kernels
+    int64_t stored_bytes = 0;
+};
+
+struct JacobiImpl {
+    std::shared_ptr<MatrixImpl> A;
+    BufPtr dinv;
+};
+
+struct IrImpl;
+
+struct SolverImpl {
+    int kind = MXL_SOLVER_CG;
+    std::shared_ptr<MatrixImpl> A;
+    std::shared_ptr<JacobiImpl> P;  // may be null
+    mxl_criteria crit{};
+    // work vectors (A's value type)
+    BufPtr r, p, q, z, rhat, v, s, t, ones;
+    BufPtr state;     // SolverState
+    BufPtr partials;  // 3 doubles per slot
+    BufPtr hist;      // max_iters + 1 doubles
+    int64_t hist_len = 0;
+    std::shared_ptr<IrImpl> ir;  // iterative refinement only
+};
+
+struct IrImpl {
+    std::shared_ptr<MatrixImpl> A64, A32;
+    std::shared_ptr<SolverImpl> outer;  // FP64 residual vector, state, partials
+    std::shared_ptr<SolverImpl> inner;  // FP32 Jacobi-CG
+    BufPtr r32, d32;
+    mxl_ir_params prm{};
+};
+
+struct BatchImpl;  // batched.hip
+
+struct SpmvArgs {
+    double alpha = 1.0, beta = 0.0;
+    const void *x = nullptr;
+    void *y = nullptr;
+    const int *stop = nullptr;  // skip all work when *stop != 0 (device flag)
+    const void *w = nullptr;    // fused dot w.y (nullable) ...
+    double *partials = nullptr; // ... one partial per workgroup, spmv_slots(A) slots
+};
+
+// ------------------------------------------------------------- spmv.hip
+void spmv_plan(MatrixImpl &A);
+int spmv_slots(const MatrixImpl &A);
+int64_t merge_tiles(int64_t n, int64_t nnz);
+int64_t coo_tiles(int64_t nnz);
+int64_t carry_bytes(int64_t ntiles);
+int ell_lds_cap();
+hipError_t merge_partition(const MatrixImpl &A, hipStream_t s);
+hipError_t spmv_launch(const MatrixImpl &A, const SpmvArgs &a, hipStream_t s);
+hipError_t launch_validate(const MatrixImpl &A, int *flags, hipStream_t s);
+hipError_t launch_csr_to_coo(const MatrixImpl &A, int *row, hipStream_t s);
+hipError_t launch_csr_to_ell(const MatrixImpl &A, int w, int64_t n_pad, int *ecol, void *evals,
+                             hipStream_t s);
+hipError_t launch_hyb_tail(const MatrixImpl &A, int k, const int64_t *toff, int *trow, int *tcol,
+                           void *tval, hipStream_t s);
+hipError_t launch_ell_windows(const MatrixImpl &A, int2 *win, hipStream_t s);
+hipError_t launch_jacobi(const MatrixImpl &A, void *dinv, int *bad, hipStream_t s);
+hipError_t launch_convert_vals(int64_t n, int from, const void *in, void *out, hipStream_t s);
+
+// ------------------------------------------------------------- krylov.hip
+constexpr int kSolverSlots = 4096;  // partial slots per reduction region
+constexpr int kRegions = 4;         // partial regions A..D, 3 doubles per slot
+int vec_grid(const mxl_ctx *ctx, int64_t n);
+hipError_t launch_finalize(int nv, const double *parts, int slots, SolverState *st, int op, int k,
+                           int max_iters, double *hist, hipStream_t s);
+hipError_t launch_jacobi_apply(int dtype, int64_t n, double alpha, const void *dinv, const void *b,
+                               double beta, void *x, hipStream_t s);
+hipError_t launch_copy(int dtype, int64_t n, const void *src, void *dst, hipStream_t s);
+hipError_t launch_fill(int dtype, int64_t n, double v, void *dst, hipStream_t s);
+hipError_t launch_state_init(SolverState *st, double red, int nonfinite_check, hipStream_t s);
+hipError_t cg_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, const void *r, void *p,
+                   const void *dinv, double *parts, hipStream_t s);
+hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *x, void *r, const void *p,
+                     const void *q, const void *dinv, SolverState *st, const double *pq_parts,
+                     int pq_slots, double *parts, int k, hipStream_t s);
+hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, void *p,
+                      const void *dinv, SolverState *st, const double *parts, int slots, int k,
+                      double *hist, hipStream_t s);
+hipError_t bi_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, const void *r,
+                   void *rhat, void *p, void *v, double *parts, hipStream_t s);
+hipError_t bi_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, void *p,
+                      const void *v, void *phat, const void *dinv, SolverState *st,
+                      const double *parts, int slots, int k, double *hist, hipStream_t s);
+hipError_t bi_supdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, const void *v,
+                      void *sv, void *shat, const void *dinv, SolverState *st,
+                      const double *rv_parts, int rv_slots, double *parts, int k, hipStream_t s);
+hipError_t bi_tdots(const mxl_ctx *ctx, int dtype, int64_t n, const void *t, const void *sv,
+                    SolverState *st, const double *ss_parts, int ss_slots, double *parts, int k,
+                    double *hist, hipStream_t s);
+hipError_t bi_xupdate(const mxl_ctx *ctx, int dtype, int64_t n, void *x, void *r, const void *phat,
+                      const void *shat, const void *sv, const void *t, const void *rhat,
+                      SolverState *st, const double *ts_parts, int ts_slots, double *parts, int k,
+                      hipStream_t s);
+hipError_t ir_norms(const mxl_ctx *ctx, int64_t n, const double *r, SolverState *st, double *parts,
+                    hipStream_t s);
+hipError_t ir_scale_to_f32(int64_t n, const double *r, const SolverState *st, float *r32,
+                           hipStream_t s);
+hipError_t ir_correct(int64_t n, double *x, const float *d, const SolverState *st, hipStream_t s);
+hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
+
+// ------------------------------------------------------------- features.hip / mlp.hip
+mxl_status features_compute(const MatrixImpl &A, double out[16]);
+
+}  // namespace mxl
+
+// The opaque handle handed out by the ABI.
+struct mxl_op {
+    int kind = MXL_OP_MATRIX;
+    std::shared_ptr<mxl::MatrixImpl> mat;
+    std::shared_ptr<mxl::JacobiImpl> jac;
+    std::shared_ptr<mxl::SolverImpl> sol;
+    std::shared_ptr<mxl::BatchImpl> bat;
+};

@@ -1,0 +1,565 @@
+// krylov.hip -- fused vector kernels of the Krylov solvers: the CG step
+// (x += alpha p, r -= alpha q, z = D^{-1} r with r.z and r.r in the same
+// pass), the search-direction update, the BiCGSTAB steps, point-Jacobi
+// application, the iterative-refinement scaling/correction and utilities.
+//
+// Every reduction is deterministic: each workgroup reduces a contiguous
+// range in a fixed tree and publishes one partial; the kernel that needs
+// the scalar reduces the partials in its prologue, identically in every
+// workgroup (device_common.hpp).  Dot products of FP32 vectors multiply
+// exactly in FP64 and accumulate in FP64.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace mxl {
+
+// Contiguous [i0, i1) range of logical workgroup L, walked 256 at a time so
+// each wave's accesses are coalesced.
+#define MXL_RANGE(n)                                   \
+    const int L = xcd_logical(blockIdx.x, gridDim.x);  \
+    int64_t i0, i1;                                    \
+    share_range((n), L, gridDim.x, i0, i1);
+
+#define MXL_LEAD (blockIdx.x == 0 && threadIdx.x == 0)
+
+template <typename V>
+__device__ __forceinline__ double prec_z(const V *dinv, int64_t i, V r) {
+    return dinv ? (double)dinv[i] * (double)r : (double)r;
+}
+
+// ------------------------------------------------------- one-shot finalise
+template <int NV>
+__global__ __launch_bounds__(kWG) void k_finalize(const double *__restrict__ partials, int nslots,
+                                                  SolverState *st, int op, int k, int max_iters,
+                                                  double *hist) {
+    double tot[NV];
+    gather_all<NV>(partials, nslots, tot, op == FIN_NORMS ? 0x2u : 0u);
+    if (threadIdx.x == 0) {
+        double s4[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < NV && j < 4; ++j) s4[j] = tot[j];
+        finalize(op, st, s4, k, max_iters, hist);
+    }
+}
+
+// ---------------------------------------------------------------- CG
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict__ b,
+                                                 const V *__restrict__ r, V *__restrict__ p,
+                                                 const V *__restrict__ dinv,
+                                                 double *__restrict__ parts) {
+    MXL_RANGE(n)
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        V ri = r[i];
+        double z = prec_z(dinv, i, ri);
+        p[i] = (V)z;
+        rz += (double)ri * z;
+        rr += (double)ri * (double)ri;
+        bb += (double)b[i] * (double)b[i];
+    }
+    double v[3] = {rz, rr, bb};
+    publish<3>(v, parts, L);
+}
+
+// Consumes p.q (fused into the SpMV): alpha = rho_{k-1} / p.q.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ x, V *__restrict__ r,
+                                                   const V *__restrict__ p, const V *__restrict__ q,
+                                                   const V *__restrict__ dinv, SolverState *st,
+                                                   const double *__restrict__ pq_parts, int pq_slots,
+                                                   double *__restrict__ parts, int k) {
+    if (st->stop) return;
+    double eta[1];
+    gather_all<1>(pq_parts, pq_slots, eta);
+    const bool chk = st->nonfinite_check != 0;
+    const bool nonfin = chk && !finite_d(eta[0]);
+    if (nonfin || eta[0] <= 0.0) {  // not positive definite along p
+        if (MXL_LEAD) {
+            st->stop = nonfin ? ST_NONFINITE : ST_BREAKDOWN;
+            st->iters = k - 1;
+            st->eta = eta[0];
+        }
+        return;
+    }
+    const double alpha = st->rho2[(k - 1) & 1] / eta[0];
+    if (MXL_LEAD) {
+        st->alpha = alpha;
+        st->eta = eta[0];
+    }
+    MXL_RANGE(n)
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        V xi, ri;
+        if constexpr (sizeof(V) == 8) {
+            xi = x[i] + alpha * p[i];
+            ri = r[i] - alpha * q[i];
+        } else {
+            xi = (V)((double)x[i] + alpha * (double)p[i]);
+            ri = (V)((double)r[i] - alpha * (double)q[i]);
+        }
+        x[i] = xi;
+        r[i] = ri;
+        double z = prec_z(dinv, i, ri);
+        rz += (double)ri * z;
+        rr += (double)ri * (double)ri;
+    }
+    double v[2] = {rz, rr};
+    publish<2>(v, parts, L);
+}
+
+// Consumes r.z and r.r: criterion of iteration k, then p = z + beta p.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, const V *__restrict__ r,
+                                                    V *__restrict__ p, const V *__restrict__ dinv,
+                                                    SolverState *st, const double *__restrict__ parts,
+                                                    int slots, int k, double *hist) {
+    if (st->stop) return;
+    double t[2];
+    gather_all<2>(parts, slots, t);
+    const double rz = t[0], rr = t[1];
+    const bool chk = st->nonfinite_check != 0;
+    const double nb = sqrt(st->nb2);
+    int stop = ST_RUN;
+    if (chk && !finite_d(rr)) stop = ST_NONFINITE;
+    else if (sqrt(rr) <= st->red * nb) stop = ST_CONVERGED;
+    else if (chk && !finite_d(rz)) stop = ST_NONFINITE;
+    else if (rz == 0.0) stop = ST_BREAKDOWN;
+    const double beta = rz / st->rho2[(k - 1) & 1];
+    if (MXL_LEAD) {
+        st->rr = rr;
+        st->iters = k;
+        if (hist) hist[k] = sqrt(rr) / nb;
+        if (stop != ST_RUN) st->stop = stop;
+        else {
+            st->rho2[k & 1] = rz;
+            st->beta = beta;
+        }
+    }
+    if (stop != ST_RUN) return;
+    MXL_RANGE(n)
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG)
+        p[i] = (V)(prec_z(dinv, i, r[i]) + beta * (double)p[i]);
+}
+
+// ------------------------------------------------------------ BiCGSTAB
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_bi_init(int64_t n, const V *__restrict__ b,
+                                                 const V *__restrict__ r, V *__restrict__ rhat,
+                                                 V *__restrict__ p, V *__restrict__ v,
+                                                 double *__restrict__ parts) {
+    MXL_RANGE(n)
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        V ri = r[i];
+        rhat[i] = ri;
+        p[i] = (V)0;
+        v[i] = (V)0;
+        rr += (double)ri * (double)ri;
+        bb += (double)b[i] * (double)b[i];
+    }
+    double s[3] = {rr, rr, bb};  // rhat = r, so rhat.r = r.r
+    publish<3>(s, parts, L);
+}
+
+// Consumes [r.r, rhat.r] of iteration k-1: its criterion (k >= 2), then the
+// loop head of iteration k: rho_k, beta, p = r + beta (p - omega v),
+// p_hat = D^{-1} p.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restrict__ r,
+                                                    V *__restrict__ p, const V *__restrict__ v,
+                                                    V *__restrict__ phat, const V *__restrict__ dinv,
+                                                    SolverState *st, const double *__restrict__ parts,
+                                                    int slots, int k, double *hist) {
+    if (st->stop) return;
+    double t[3];
+    gather_all<3>(parts, slots, t);
+    const double rr = t[0], rho = t[1];
+    const bool chk = st->nonfinite_check != 0;
+    const double nb = sqrt(st->nb2);
+    const double omega_prev = st->omega, alpha_prev = st->alpha;
+    int stop = ST_RUN;
+    if (k >= 2) {
+        if (chk && !finite_d(rr)) stop = ST_NONFINITE;
+        else if (sqrt(rr) <= st->red * nb) stop = ST_CONVERGED;
+        else if (omega_prev == 0.0) stop = ST_BREAKDOWN;
+    }
+    if (stop == ST_RUN) {
+        if (chk && !finite_d(rho)) stop = ST_NONFINITE;
+        else if (rho == 0.0) stop = ST_BREAKDOWN;
+    }
+    const double beta = (rho / st->rho2[(k - 1) & 1]) * (alpha_prev / omega_prev);
+    if (MXL_LEAD) {
+        if (k >= 2) {
+            st->rr = rr;
+            if (hist) hist[k - 1] = sqrt(rr) / nb;
+        }
+        if (stop != ST_RUN) {
+            st->stop = stop;
+            st->iters = k - 1;
+        } else {
+            st->rho2[k & 1] = rho;
+            st->beta = beta;
+        }
+    }
+    if (stop != ST_RUN) return;
+    MXL_RANGE(n)
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        V pi = (V)((double)r[i] + beta * ((double)p[i] - omega_prev * (double)v[i]));
+        p[i] = pi;
+        phat[i] = (V)prec_z(dinv, i, pi);
+    }
+}
+
+// Consumes rhat.v (fused into the SpMV): alpha = rho_k / rhat.v; s = r - alpha v.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restrict__ r,
+                                                    const V *__restrict__ v, V *__restrict__ s,
+                                                    V *__restrict__ shat,
+                                                    const V *__restrict__ dinv, SolverState *st,
+                                                    const double *__restrict__ rv_parts, int rv_slots,
+                                                    double *__restrict__ parts, int k) {
+    if (st->stop) return;
+    double rv[1];
+    gather_all<1>(rv_parts, rv_slots, rv);
+    const bool chk = st->nonfinite_check != 0;
+    const bool nonfin = chk && !finite_d(rv[0]);
+    if (nonfin || rv[0] == 0.0) {
+        if (MXL_LEAD) {
+            st->stop = nonfin ? ST_NONFINITE : ST_BREAKDOWN;
+            st->iters = k - 1;
+        }
+        return;
+    }
+    const double alpha = st->rho2[k & 1] / rv[0];
+    if (MXL_LEAD) st->alpha = alpha;
+    MXL_RANGE(n)
+    double ss = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        V si = (V)((double)r[i] - alpha * (double)v[i]);
+        s[i] = si;
+        shat[i] = (V)prec_z(dinv, i, si);
+        ss += (double)si * (double)si;
+    }
+    double a[1] = {ss};
+    publish<1>(a, parts, L);
+}
+
+// Consumes s.s: half-step criterion; otherwise t.s and t.t.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_bi_tdots(int64_t n, const V *__restrict__ t,
+                                                  const V *__restrict__ s, SolverState *st,
+                                                  const double *__restrict__ ss_parts, int ss_slots,
+                                                  double *__restrict__ parts, int k, double *hist) {
+    if (st->stop) return;
+    double ss[1];
+    gather_all<1>(ss_parts, ss_slots, ss);
+    const double nb = sqrt(st->nb2);
+    if (sqrt(ss[0]) <= st->red * nb) {
+        if (MXL_LEAD) {
+            st->stop = ST_HALF;
+            st->half = 1;
+            st->iters = k;
+            st->rr = ss[0];
+            if (hist) hist[k] = sqrt(ss[0]) / nb;
+        }
+        return;
+    }
+    MXL_RANGE(n)
+    double ts = 0.0, tt = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        double ti = (double)t[i];
+        ts += ti * (double)s[i];
+        tt += ti * ti;
+    }
+    double a[2] = {ts, tt};
+    publish<2>(a, parts, L);
+}
+
+// Consumes t.s and t.t: omega; x += alpha p_hat + omega s_hat, r = s - omega t,
+// then [r.r, rhat.r] for the next loop head.  At a half-step stop of this
+// iteration it applies x += alpha p_hat only.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x, V *__restrict__ r,
+                                                    const V *__restrict__ phat,
+                                                    const V *__restrict__ shat,
+                                                    const V *__restrict__ s, const V *__restrict__ t,
+                                                    const V *__restrict__ rhat, SolverState *st,
+                                                    const double *__restrict__ ts_parts, int ts_slots,
+                                                    double *__restrict__ parts, int k) {
+    const int mode = st->stop;
+    const double alpha = st->alpha;
+    if (mode == ST_HALF) {
+        if (st->iters != k) return;
+        MXL_RANGE(n)
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG)
+            x[i] = (V)((double)x[i] + alpha * (double)phat[i]);
+        return;
+    }
+    if (mode != ST_RUN) return;
+    double d[2];
+    gather_all<2>(ts_parts, ts_slots, d);
+    const double ts = d[0], tt = d[1];
+    const bool chk = st->nonfinite_check != 0;
+    const bool nonfin = chk && (!finite_d(tt) || !finite_d(ts));
+    if (nonfin || tt == 0.0) {
+        if (MXL_LEAD) {
+            st->stop = nonfin ? ST_NONFINITE : ST_BREAKDOWN;
+            st->iters = k;
+        }
+        return;
+    }
+    const double omega = ts / tt;
+    if (MXL_LEAD) st->omega = omega;
+    MXL_RANGE(n)
+    double rr = 0.0, rhr = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        x[i] = (V)((double)x[i] + alpha * (double)phat[i] + omega * (double)shat[i]);
+        V ri = (V)((double)s[i] - omega * (double)t[i]);
+        r[i] = ri;
+        rr += (double)ri * (double)ri;
+        rhr += (double)rhat[i] * (double)ri;
+    }
+    double a[3] = {rr, rhr, 0.0};
+    publish<3>(a, parts, L);
+}
+
+// ----------------------------------------------------- small utilities
+template <typename V>
+__global__ void k_jacobi_apply(int64_t n, V alpha, const V *__restrict__ dinv,
+                               const V *__restrict__ b, V beta, V *__restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        V v = alpha * (dinv[i] * b[i]);
+        x[i] = beta == (V)0 ? v : v + beta * x[i];
+    }
+}
+
+template <typename V>
+__global__ void k_copy(int64_t n, const V *__restrict__ a, V *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+template <typename V>
+__global__ void k_fill(int64_t n, V v, V *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = v;
+}
+
+__global__ void k_state_init(SolverState *st, double red, int chk) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->rho2[0] = st->rho2[1] = 0.0;
+    st->alpha = st->omega = st->beta = st->eta = 0.0;
+    st->rr = st->nb2 = 0.0;
+    st->red = red;
+    for (int j = 0; j < 4; ++j) st->sums[j] = 0.0;
+    st->stop = ST_RUN;
+    st->iters = 0;
+    st->nonfinite_check = chk;
+    st->half = 0;
+}
+
+// ||r||_2^2 and ||r||_inf in one pass (iterative refinement outer step).
+__global__ __launch_bounds__(kWG) void k_ir_norms(int64_t n, const double *__restrict__ r,
+                                                  double *__restrict__ parts) {
+    MXL_RANGE(n)
+    double rr = 0.0, mx = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+        double v = r[i];
+        rr += v * v;
+        double a = fabs(v);
+        mx = a > mx ? a : mx;
+    }
+    double a[2] = {rr, mx};
+    publish<2>(a, parts, L, 0x2u);
+}
+
+__global__ void k_ir_scale(int64_t n, const double *__restrict__ r,
+                           const SolverState *__restrict__ st, float *__restrict__ r32) {
+    const double s = st->sums[1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        r32[i] = (float)(r[i] / s);
+}
+
+__global__ void k_ir_correct(int64_t n, double *__restrict__ x, const float *__restrict__ d,
+                             const SolverState *__restrict__ st) {
+    const double s = st->sums[1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += s * (double)d[i];
+}
+
+__global__ void k_flush(int4 *buf, int64_t n, int v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        buf[i] = make_int4(v, v, v, v);
+}
+
+// ============================================================ host side
+int vec_grid(const mxl_ctx *ctx, int64_t n) {
+    int64_t want = (n + kWG * 4 - 1) / (kWG * 4);
+    int cap = ctx->num_cu * 8 < kMaxGrid ? ctx->num_cu * 8 : kMaxGrid;
+    if (want < 1) want = 1;
+    return (int)(want < cap ? want : cap);
+}
+
+static unsigned gs(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+// Launch KERNEL<double> or KERNEL<float>; arguments of type `VP` are cast.
+#define MXL_LAUNCH_V(dtype, KERNEL, GRID, ...)                                                     \
+    do {                                                                                           \
+        if ((dtype) == MXL_F64) {                                                                  \
+            using V = double;                                                                      \
+            hipLaunchKernelGGL(KERNEL<V>, dim3(GRID), dim3(kWG), 0, s, __VA_ARGS__);               \
+        } else {                                                                                   \
+            using V = float;                                                                       \
+            hipLaunchKernelGGL(KERNEL<V>, dim3(GRID), dim3(kWG), 0, s, __VA_ARGS__);               \
+        }                                                                                          \
+    } while (0)
+
+hipError_t launch_finalize(int nv, const double *parts, int slots, SolverState *st, int op, int k,
+                           int max_iters, double *hist, hipStream_t s) {
+    if (nv == 2)
+        hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kWG), 0, s, parts, slots, st, op, k, max_iters, hist);
+    else
+        hipLaunchKernelGGL(k_finalize<3>, dim3(1), dim3(kWG), 0, s, parts, slots, st, op, k, max_iters, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_apply(int dtype, int64_t n, double alpha, const void *dinv, const void *b,
+                               double beta, void *x, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (dtype == MXL_F64)
+        hipLaunchKernelGGL(k_jacobi_apply<double>, dim3(gs(n)), dim3(256), 0, s, n, alpha,
+                           (const double *)dinv, (const double *)b, beta, (double *)x);
+    else
+        hipLaunchKernelGGL(k_jacobi_apply<float>, dim3(gs(n)), dim3(256), 0, s, n, (float)alpha,
+                           (const float *)dinv, (const float *)b, (float)beta, (float *)x);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int dtype, int64_t n, const void *src, void *dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (dtype == MXL_F64)
+        hipLaunchKernelGGL(k_copy<double>, dim3(gs(n)), dim3(256), 0, s, n, (const double *)src, (double *)dst);
+    else
+        hipLaunchKernelGGL(k_copy<float>, dim3(gs(n)), dim3(256), 0, s, n, (const float *)src, (float *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int dtype, int64_t n, double v, void *dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (dtype == MXL_F64)
+        hipLaunchKernelGGL(k_fill<double>, dim3(gs(n)), dim3(256), 0, s, n, v, (double *)dst);
+    else
+        hipLaunchKernelGGL(k_fill<float>, dim3(gs(n)), dim3(256), 0, s, n, (float)v, (float *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_init(SolverState *st, double red, int nonfinite_check, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, red, nonfinite_check);
+    return hipGetLastError();
+}
+
+hipError_t cg_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, const void *r, void *p,
+                   const void *dinv, double *parts, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_cg_init, vec_grid(ctx, n), n, (const V *)b, (const V *)r, (V *)p,
+                 (const V *)dinv, parts);
+    return hipGetLastError();
+}
+
+hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *x, void *r, const void *p,
+                     const void *q, const void *dinv, SolverState *st, const double *pq_parts,
+                     int pq_slots, double *parts, int k, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_cg_update, vec_grid(ctx, n), n, (V *)x, (V *)r, (const V *)p, (const V *)q,
+                 (const V *)dinv, st, pq_parts, pq_slots, parts, k);
+    return hipGetLastError();
+}
+
+hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, void *p,
+                      const void *dinv, SolverState *st, const double *parts, int slots, int k,
+                      double *hist, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_cg_pupdate, vec_grid(ctx, n), n, (const V *)r, (V *)p, (const V *)dinv, st,
+                 parts, slots, k, hist);
+    return hipGetLastError();
+}
+
+hipError_t bi_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, const void *r,
+                   void *rhat, void *p, void *v, double *parts, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_bi_init, vec_grid(ctx, n), n, (const V *)b, (const V *)r, (V *)rhat, (V *)p,
+                 (V *)v, parts);
+    return hipGetLastError();
+}
+
+hipError_t bi_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, void *p,
+                      const void *v, void *phat, const void *dinv, SolverState *st,
+                      const double *parts, int slots, int k, double *hist, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_bi_pupdate, vec_grid(ctx, n), n, (const V *)r, (V *)p, (const V *)v,
+                 (V *)phat, (const V *)dinv, st, parts, slots, k, hist);
+    return hipGetLastError();
+}
+
+hipError_t bi_supdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, const void *v,
+                      void *sv, void *shat, const void *dinv, SolverState *st,
+                      const double *rv_parts, int rv_slots, double *parts, int k, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_bi_supdate, vec_grid(ctx, n), n, (const V *)r, (const V *)v, (V *)sv,
+                 (V *)shat, (const V *)dinv, st, rv_parts, rv_slots, parts, k);
+    return hipGetLastError();
+}
+
+hipError_t bi_tdots(const mxl_ctx *ctx, int dtype, int64_t n, const void *t, const void *sv,
+                    SolverState *st, const double *ss_parts, int ss_slots, double *parts, int k,
+                    double *hist, hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_bi_tdots, vec_grid(ctx, n), n, (const V *)t, (const V *)sv, st, ss_parts,
+                 ss_slots, parts, k, hist);
+    return hipGetLastError();
+}
+
+hipError_t bi_xupdate(const mxl_ctx *ctx, int dtype, int64_t n, void *x, void *r, const void *phat,
+                      const void *shat, const void *sv, const void *t, const void *rhat,
+                      SolverState *st, const double *ts_parts, int ts_slots, double *parts, int k,
+                      hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_bi_xupdate, vec_grid(ctx, n), n, (V *)x, (V *)r, (const V *)phat,
+                 (const V *)shat, (const V *)sv, (const V *)t, (const V *)rhat, st, ts_parts, ts_slots,
+                 parts, k);
+    return hipGetLastError();
+}
+
+hipError_t ir_norms(const mxl_ctx *ctx, int64_t n, const double *r, SolverState *st, double *parts,
+                    hipStream_t s) {
+    int G = vec_grid(ctx, n);
+    hipLaunchKernelGGL(k_ir_norms, dim3(G), dim3(kWG), 0, s, n, r, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(2, parts, G, st, FIN_NORMS, 0, 0, nullptr, s);
+}
+
+hipError_t ir_scale_to_f32(int64_t n, const double *r, const SolverState *st, float *r32,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_ir_scale, dim3(gs(n)), dim3(256), 0, s, n, r, st, r32);
+    return hipGetLastError();
+}
+
+hipError_t ir_correct(int64_t n, double *x, const float *d, const SolverState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_ir_correct, dim3(gs(n)), dim3(256), 0, s, n, x, d, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s) {
+    static int v = 0;
+    ++v;
+    int64_t n = (int64_t)(bytes / sizeof(int4));
+    hipLaunchKernelGGL(k_flush, dim3(8192), dim3(256), 0, s, (int4 *)buf, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace mxl

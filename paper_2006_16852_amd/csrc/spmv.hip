@@ -1,0 +1,755 @@
+// spmv.hip -- sparse matrix-vector product y = alpha*A*x + beta*y for CSR
+// (scalar, vector-W, merge-path), COO (segmented reduction), ELL (plain and
+// LDS-staged x window) and HYB (ELL + COO tail), with an optional fused dot
+// product w.y and the setup kernels (partitioning, format conversion,
+// validation, Jacobi extraction).
+//
+// The apply semantics are the simple and advanced applications of a linear
+// operator (Sec. 2.2.2 and Sec. 4.2 of the paper); the kernel designs are
+// this library's own, written for wave64 CDNA4: every kernel is
+// HBM-bandwidth bound (about 0.17 flop per byte in FP64), so the designs aim
+// at coalesced, wide, streaming loads of the matrix arrays and keep the
+// gathered x in cache.  No MFMA: this is not a dense contraction.
+#include <climits>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace mxl {
+
+template <typename V>
+struct SpmvK {
+    const V *x;
+    V *y;
+    V alpha, beta;
+    int beta_zero;
+    const int *stop;  // nullable: skip all work when *stop != 0
+    const V *w;       // nullable: fused dot w.y, one partial per workgroup
+    double *partials;
+    int slot_base;
+};
+
+template <typename V>
+__device__ __forceinline__ V combine(const SpmvK<V> &p, V acc, int64_t row) {
+    return p.beta_zero ? p.alpha * acc : p.alpha * acc + p.beta * p.y[row];
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// ------------------------------------------------------------ CSR scalar
+// One lane per row.  Good for very short rows; long rows serialise.
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kWG) void k_csr_scalar(int64_t n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const V *__restrict__ val, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int64_t ngroups = (n + kWG - 1) / kWG;
+    int64_t g0, g1;
+    share_range(ngroups, L, gridDim.x, g0, g1);
+    double dacc = 0.0;
+    for (int64_t g = g0; g < g1; ++g) {
+        int64_t row = g * kWG + threadIdx.x;
+        if (row >= n) continue;
+        int k0 = rp[row], k1 = rp[row + 1];
+        V acc = 0;
+        for (int k = k0; k < k1; ++k) acc += ld_stream(val + k) * p.x[ld_stream(col + k)];
+        V out = combine(p, acc, row);
+        p.y[row] = out;
+        if (DOT) dacc += (double)p.w[row] * (double)out;
+    }
+    if (DOT) {
+        double v[1] = {dacc};
+        publish<1>(v, p.partials, p.slot_base + L);
+    }
+}
+
+// ------------------------------------------------------------ CSR vector
+// W lanes per row (W = 2..64), lanes stride through the row so a group's
+// loads are contiguous; the W partial sums are combined by a shuffle tree.
+template <typename V, int W, bool DOT>
+__global__ __launch_bounds__(kWG) void k_csr_vector(int64_t n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const V *__restrict__ val, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    constexpr int RPG = kWG / W;  // rows per workgroup step
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int64_t ngroups = (n + RPG - 1) / RPG;
+    int64_t g0, g1;
+    share_range(ngroups, L, gridDim.x, g0, g1);
+    const int lane = threadIdx.x % W, sub = threadIdx.x / W;
+    double dacc = 0.0;
+    for (int64_t g = g0; g < g1; ++g) {
+        int64_t row = g * RPG + sub;
+        V acc = 0;
+        if (row < n) {
+            int k0 = rp[row], k1 = rp[row + 1];
+            int k = k0 + lane;
+            // two independent loads in flight per lane
+            for (; k + W < k1; k += 2 * W) {
+                V v0 = ld_stream(val + k), v1 = ld_stream(val + k + W);
+                int c0 = ld_stream(col + k), c1 = ld_stream(col + k + W);
+                acc += v0 * p.x[c0];
+                acc += v1 * p.x[c1];
+            }
+            if (k < k1) acc += ld_stream(val + k) * p.x[ld_stream(col + k)];
+        }
+#pragma unroll
+        for (int off = W / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, W);
+        if (row < n && lane == 0) {
+            V out = combine(p, acc, row);
+            p.y[row] = out;
+            if (DOT) dacc += (double)p.w[row] * (double)out;
+        }
+    }
+    if (DOT) {
+        double v[1] = {dacc};
+        publish<1>(v, p.partials, p.slot_base + L);
+    }
+}
+
+// ------------------------------------------------------- merge path CSR
+// The (row ends) x (nonzeros) merge sequence of n + nnz items is cut into
+// tiles of ITEMS = 256*IPT items; coordinates of every tile boundary are
+// precomputed (k_merge_partition).  A tile stages its products and row ends
+// in LDS with coalesced loads, each thread walks IPT consecutive items, and
+// rows crossing thread or tile boundaries are completed by deterministic
+// carry chains (in LDS within a tile, k_carry_fixup across tiles).
+struct Carry {
+    int32_t row;  // -1: none
+    int32_t pad;
+    double val;
+};
+
+constexpr int kMergeIPT = 6;
+constexpr int kMergeItems = kWG * kMergeIPT;
+constexpr int kCooIPT = 6;
+constexpr int kCooItems = kWG * kCooIPT;
+
+__global__ void k_merge_partition(int64_t n, int64_t nnz, const int *__restrict__ rp, int64_t ntiles,
+                                  int2 *__restrict__ part) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > ntiles) return;
+    int64_t d = b * kMergeItems;
+    if (d > n + nnz) d = n + nnz;
+    // i = number of rows m whose end item (position m + rp[m+1]) precedes d
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (mid + rp[mid + 1] < d) lo = mid + 1;
+        else hi = mid;
+    }
+    part[b] = make_int2((int)lo, (int)(d - lo));
+}
+
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kWG) void k_csr_merge(int64_t n, const int *__restrict__ rp,
+                                                   const int *__restrict__ col,
+                                                   const V *__restrict__ val,
+                                                   const int2 *__restrict__ part, int64_t ntiles,
+                                                   Carry *__restrict__ carries, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    __shared__ int s_end[kMergeItems + 1];
+    __shared__ V s_prod[kMergeItems];
+    __shared__ V s_out[kMergeItems];
+    __shared__ int s_crow[kWG];
+    __shared__ V s_cval[kWG];
+    const int tid = threadIdx.x;
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    int64_t t0, t1;
+    share_range(ntiles, L, gridDim.x, t0, t1);
+    double dacc = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int2 c0 = part[tile], c1 = part[tile + 1];
+        const int r0 = c0.x, k0 = c0.y, r1 = c1.x, k1 = c1.y;
+        const int nr = r1 - r0, nk = k1 - k0;
+        for (int i = tid; i <= nr; i += kWG) s_end[i] = (r0 + i < n) ? rp[r0 + i + 1] : INT_MAX;
+#pragma unroll
+        for (int u = 0; u < kMergeIPT; ++u) {
+            int j = u * kWG + tid;
+            if (j < nk) {
+                int k = k0 + j;
+                s_prod[j] = ld_stream(val + k) * p.x[ld_stream(col + k)];
+            }
+        }
+        __syncthreads();
+        const int total = nr + nk;
+        int d = tid * kMergeIPT;
+        if (d > total) d = total;
+        int dend = d + kMergeIPT;
+        if (dend > total) dend = total;
+        int lo = d - nk > 0 ? d - nk : 0, hi = d < nr ? d : nr;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (mid + (s_end[mid] - k0) < d) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, j = d - lo;
+        V acc = 0;
+        int first_row = -1;
+        V first_val = 0;
+        for (int step = d; step < dend; ++step) {
+            if (i < nr && s_end[i] - k0 <= j) {
+                if (first_row < 0) { first_row = i; first_val = acc; }
+                else s_out[i] = acc;
+                acc = 0;
+                ++i;
+            } else {
+                acc += s_prod[j];
+                ++j;
+            }
+        }
+        s_crow[tid] = i;
+        s_cval[tid] = acc;
+        __syncthreads();
+        if (first_row >= 0) {
+            V c = 0;
+            for (int t2 = tid - 1; t2 >= 0 && s_crow[t2] == first_row; --t2) c += s_cval[t2];
+            s_out[first_row] = first_val + c;
+        }
+        if (tid == 0) {
+            V c = 0;
+            for (int t2 = kWG - 1; t2 >= 0 && s_crow[t2] == nr; --t2) c += s_cval[t2];
+            Carry cr;
+            cr.row = (r1 < n) ? r1 : -1;
+            cr.pad = 0;
+            cr.val = (double)c;
+            carries[tile] = cr;
+            if (DOT && r1 < n) dacc += (double)p.w[r1] * (double)(p.alpha * c);
+        }
+        __syncthreads();
+        for (int ii = tid; ii < nr; ii += kWG) {
+            int64_t row = r0 + ii;
+            V out = combine(p, s_out[ii], row);
+            p.y[row] = out;
+            if (DOT) dacc += (double)p.w[row] * (double)out;
+        }
+        __syncthreads();
+    }
+    if (DOT) {
+        double v[1] = {dacc};
+        publish<1>(v, p.partials, p.slot_base + L);
+    }
+}
+
+// ------------------------------------------------------------------ COO
+// Row-sorted triplets in tiles of kCooItems nonzeros.  A row ends at item k
+// iff row[k+1] != row[k]; the tile holding that item writes y[row] (plus
+// the carries of earlier threads in the tile) and earlier tiles hand their
+// partial sums to k_carry_fixup.  Rows without entries are written by the
+// thread that sees the row index jump over them (skipped in ACC mode, which
+// accumulates into y: the HYB tail).
+template <typename V, bool DOT, bool ACC>
+__global__ __launch_bounds__(kWG) void k_coo(int64_t n, int64_t nnz, const int *__restrict__ row,
+                                             const int *__restrict__ col,
+                                             const V *__restrict__ val, int64_t ntiles,
+                                             Carry *__restrict__ carries, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    __shared__ int s_row[kCooItems + 1];
+    __shared__ V s_prod[kCooItems];
+    __shared__ int s_crow[kWG];
+    __shared__ V s_cval[kWG];
+    const int tid = threadIdx.x;
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    int64_t t0, t1;
+    share_range(ntiles, L, gridDim.x, t0, t1);
+    double dacc = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t k0 = tile * kCooItems;
+        int64_t k1 = k0 + kCooItems;
+        if (k1 > nnz) k1 = nnz;
+        const int nk = (int)(k1 - k0);
+#pragma unroll
+        for (int u = 0; u < kCooIPT; ++u) {
+            int j = u * kWG + tid;
+            if (j < nk) {
+                int64_t k = k0 + j;
+                s_row[j] = ld_stream(row + k);
+                s_prod[j] = ld_stream(val + k) * p.x[ld_stream(col + k)];
+            }
+        }
+        if (tid == 0) s_row[nk] = (k1 < nnz) ? row[k1] : (int)n;  // n: "every row ends"
+        __syncthreads();
+        const int j0 = tid * kCooIPT;
+        int j1 = j0 + kCooIPT;
+        if (j1 > nk) j1 = nk;
+        V acc = 0;
+        int first_row = -1;
+        V first_val = 0;
+        int cur = -1;
+        for (int j = j0; j < j1; ++j) {
+            const int r = s_row[j];
+            if (!ACC && k0 + j == 0)  // rows before the first entry
+                for (int g = 0; g < r; ++g) p.y[g] = combine(p, (V)0, g);
+            cur = r;
+            acc += s_prod[j];
+            const int rn = s_row[j + 1];
+            if (rn != r) {
+                if (!ACC) {  // rows skipped between this entry and the next
+                    const int last = rn < (int)n ? rn : (int)n;
+                    for (int g = r + 1; g < last; ++g) p.y[g] = combine(p, (V)0, g);
+                }
+                if (first_row < 0) { first_row = r; first_val = acc; }
+                else {
+                    V out = ACC ? p.y[r] + p.alpha * acc : combine(p, acc, r);
+                    p.y[r] = out;
+                    if (DOT) dacc += (double)p.w[r] * (double)(ACC ? p.alpha * acc : out);
+                }
+                acc = 0;
+                cur = -1;
+            }
+        }
+        s_crow[tid] = cur;  // -1 when the thread's last row ended (or no items)
+        s_cval[tid] = acc;
+        __syncthreads();
+        if (first_row >= 0) {
+            V c = 0;
+            for (int t2 = tid - 1; t2 >= 0 && s_crow[t2] == first_row; --t2) c += s_cval[t2];
+            V tot = first_val + c;
+            V out = ACC ? p.y[first_row] + p.alpha * tot : combine(p, tot, first_row);
+            p.y[first_row] = out;
+            if (DOT) dacc += (double)p.w[first_row] * (double)(ACC ? p.alpha * tot : out);
+        }
+        if (tid == 0) {
+            Carry cr;
+            cr.row = -1;
+            cr.pad = 0;
+            cr.val = 0.0;
+            if (nk > 0 && s_row[nk] == s_row[nk - 1]) {
+                const int lr = s_row[nk - 1];
+                const int owner = (nk - 1) / kCooIPT;
+                V c = 0;
+                for (int t2 = owner; t2 >= 0 && s_crow[t2] == lr; --t2) c += s_cval[t2];
+                cr.row = lr;
+                cr.val = (double)c;
+                if (DOT) dacc += (double)p.w[lr] * (double)(p.alpha * c);
+            }
+            carries[tile] = cr;
+        }
+        __syncthreads();
+    }
+    if (DOT) {
+        double v[1] = {dacc};
+        publish<1>(v, p.partials, p.slot_base + L);
+    }
+}
+
+// Adds the carried partial sums of rows that crossed tile boundaries: one
+// thread per tile; the first tile of each run of equal carry rows sums the
+// run in tile order (deterministic) and updates y once.
+template <typename V>
+__global__ __launch_bounds__(kWG) void k_carry_fixup(const Carry *__restrict__ carries,
+                                                     int64_t ntiles, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntiles) return;
+    const int r = carries[g].row;
+    if (r < 0) return;
+    if (g > 0 && carries[g - 1].row == r) return;
+    double s = 0.0;
+    for (int64_t g2 = g; g2 < ntiles && carries[g2].row == r; ++g2) s += carries[g2].val;
+    p.y[r] = p.y[r] + p.alpha * (V)s;
+}
+
+// ------------------------------------------------------------------ ELL
+// Slot-major [w][n_pad]: lane i reads slot s of row i at s*n_pad + i, so a
+// wave's loads are contiguous.  Padding column -1 is predicated off.  The
+// LDS variant first copies the tile's x window [lo, hi] (precomputed per
+// 256-row tile) into LDS when it fits, then gathers from LDS.
+constexpr int kEllLdsCap = 4096;  // x entries staged per tile (32 KB in FP64)
+
+template <typename V, bool DOT, bool LDS>
+__global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
+                                             const int *__restrict__ ecol,
+                                             const V *__restrict__ evals,
+                                             const int2 *__restrict__ win, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    __shared__ V s_x[LDS ? kEllLdsCap : 1];
+    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int64_t ntiles = (n + kWG - 1) / kWG;
+    int64_t t0, t1;
+    share_range(ntiles, L, gridDim.x, t0, t1);
+    double dacc = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t row = tile * kWG + threadIdx.x;
+        bool staged = false;
+        int lo = 0;
+        if (LDS) {
+            int2 wv = win[tile];
+            lo = wv.x;
+            int span = wv.y - wv.x + 1;
+            staged = span > 0 && span <= kEllLdsCap;
+            if (staged) {
+                for (int j = threadIdx.x; j < span; j += kWG) s_x[j] = p.x[lo + j];
+            }
+            __syncthreads();
+        }
+        V acc = 0;
+        if (row < n) {
+            int s = 0;
+            for (; s + 1 < w; s += 2) {
+                int c0 = ld_stream(ecol + (int64_t)s * n_pad + row);
+                int c1 = ld_stream(ecol + (int64_t)(s + 1) * n_pad + row);
+                V v0 = ld_stream(evals + (int64_t)s * n_pad + row);
+                V v1 = ld_stream(evals + (int64_t)(s + 1) * n_pad + row);
+                if (c0 >= 0) acc += v0 * ((LDS && staged) ? s_x[c0 - lo] : p.x[c0]);
+                if (c1 >= 0) acc += v1 * ((LDS && staged) ? s_x[c1 - lo] : p.x[c1]);
+            }
+            if (s < w) {
+                int c0 = ld_stream(ecol + (int64_t)s * n_pad + row);
+                V v0 = ld_stream(evals + (int64_t)s * n_pad + row);
+                if (c0 >= 0) acc += v0 * ((LDS && staged) ? s_x[c0 - lo] : p.x[c0]);
+            }
+            V out = combine(p, acc, row);
+            p.y[row] = out;
+            if (DOT) dacc += (double)p.w[row] * (double)out;
+        }
+        if (LDS) __syncthreads();
+    }
+    if (DOT) {
+        double v[1] = {dacc};
+        publish<1>(v, p.partials, p.slot_base + L);
+    }
+}
+
+// y = beta*y (alpha*A*x with no stored entries)
+template <typename V>
+__global__ void k_scale_only(int64_t n, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p.y[i] = combine(p, (V)0, i);
+}
+
+// ----------------------------------------------------------- setup kernels
+__global__ void k_csr_to_coo(int64_t n, const int *__restrict__ rp, int *__restrict__ row) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) row[k] = (int)i;
+}
+
+template <typename V>
+__global__ void k_csr_to_ell(int64_t n, int64_t n_pad, int w, const int *__restrict__ rp,
+                             const int *__restrict__ col, const V *__restrict__ val,
+                             int *__restrict__ ecol, V *__restrict__ evals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    int k0 = 0, len = 0;
+    if (i < n) { k0 = rp[i]; len = rp[i + 1] - k0; }
+    for (int s = 0; s < w; ++s) {
+        int64_t o = (int64_t)s * n_pad + i;
+        if (s < len) { ecol[o] = col[k0 + s]; evals[o] = val[k0 + s]; }
+        else { ecol[o] = -1; evals[o] = (V)0; }
+    }
+}
+
+template <typename V>
+__global__ void k_hyb_tail(int64_t n, int k, const int *__restrict__ rp,
+                           const int *__restrict__ col, const V *__restrict__ val,
+                           const int64_t *__restrict__ toff, int *__restrict__ trow,
+                           int *__restrict__ tcol, V *__restrict__ tval) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t t = toff[i];
+    for (int e = rp[i] + k; e < rp[i + 1]; ++e, ++t) {
+        trow[t] = (int)i;
+        tcol[t] = col[e];
+        tval[t] = val[e];
+    }
+}
+
+// Column window of every 256-row tile (columns are sorted within rows, so
+// the first and last entry of each row bound it).  Empty tile: lo > hi.
+__global__ void k_ell_windows(int64_t n, const int *__restrict__ rp, const int *__restrict__ col,
+                              int64_t ntiles, int2 *__restrict__ win) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int lo = INT_MAX, hi = -1;
+    int64_t r1 = (t + 1) * kWG < n ? (t + 1) * kWG : n;
+    for (int64_t r = t * kWG; r < r1; ++r) {
+        int a = rp[r], b = rp[r + 1];
+        if (b > a) {
+            lo = col[a] < lo ? col[a] : lo;
+            hi = col[b - 1] > hi ? col[b - 1] : hi;
+        }
+    }
+    if (hi < 0) lo = 0;
+    win[t] = make_int2(lo, hi);
+}
+
+// Canonical-form check; sets bits of *flags: 1 start, 2 monotone, 4 end,
+// 8 column range, 16 column order.
+__global__ void k_validate(int64_t n, int64_t ncols, int64_t nnz, const int *__restrict__ rp,
+                           const int *__restrict__ col, int *__restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (rp[0] != 0) atomicOr(flags, 1);
+        if ((int64_t)rp[n] != nnz) atomicOr(flags, 4);
+    }
+    if (i >= n) return;
+    int a = rp[i], b = rp[i + 1];
+    if (b < a) { atomicOr(flags, 2); return; }
+    if (a < 0 || (int64_t)b > nnz) { atomicOr(flags, 4); return; }
+    int f = 0;
+    for (int k = a; k < b; ++k) {
+        int c = col[k];
+        if (c < 0 || (int64_t)c >= ncols) f |= 8;
+        if (k > a && c <= col[k - 1]) f |= 16;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// dinv_i = 1/a_ii in FP64, rounded to V.  *bad = smallest row with a missing
+// or zero diagonal (initialised to INT_MAX by the host).
+template <typename V>
+__global__ void k_jacobi(int64_t n, const int *__restrict__ rp, const int *__restrict__ col,
+                         const V *__restrict__ val, V *__restrict__ dinv, int *__restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = rp[i], hi = rp[i + 1];
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (col[mid] < i) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < rp[i + 1] && col[lo] == i && val[lo] != (V)0) {
+        dinv[i] = (V)(1.0 / (double)val[lo]);
+    } else {
+        dinv[i] = (V)0;
+        atomicMin(bad, (int)i);
+    }
+}
+
+template <typename A, typename B>
+__global__ void k_convert_vals(int64_t n, const A *__restrict__ in, B *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (B)in[i];
+}
+
+// ============================================================ host side
+
+static int grid_for(int64_t tiles, int cap) {
+    if (tiles <= 0) return 0;
+    return (int)(tiles < cap ? tiles : cap);
+}
+
+int spmv_grid_cap(const MatrixImpl &A) {
+    return A.ctx->num_cu * 8 < kMaxGrid ? A.ctx->num_cu * 8 : kMaxGrid;
+}
+
+void spmv_plan(MatrixImpl &A) {
+    const int cap = spmv_grid_cap(A);
+    A.grid_main = A.grid_tail = 0;
+    switch (A.format) {
+    case MXL_FMT_CSR:
+        if (A.variant == MXL_CSR_SCALAR) A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
+        else if (A.variant == MXL_CSR_VECTOR)
+            A.grid_main = grid_for((A.nrows + kWG / A.vw - 1) / (kWG / A.vw), cap);
+        else A.grid_main = grid_for(A.ntiles, cap);
+        break;
+    case MXL_FMT_COO:
+        A.grid_main = grid_for(A.ntiles, cap);
+        break;
+    case MXL_FMT_ELL:
+        A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
+        break;
+    case MXL_FMT_HYB:
+        A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
+        A.grid_tail = grid_for(A.ntiles, cap);
+        break;
+    }
+}
+
+int spmv_slots(const MatrixImpl &A) { return A.grid_main + A.grid_tail; }
+
+int64_t merge_tiles(int64_t n, int64_t nnz) { return (n + nnz + kMergeItems - 1) / kMergeItems; }
+int64_t coo_tiles(int64_t nnz) { return (nnz + kCooItems - 1) / kCooItems; }
+int64_t carry_bytes(int64_t ntiles) { return (ntiles > 0 ? ntiles : 1) * (int64_t)sizeof(Carry); }
+int ell_lds_cap() { return kEllLdsCap; }
+
+hipError_t merge_partition(const MatrixImpl &A, hipStream_t s) {
+    int64_t nb = A.ntiles + 1;
+    int g = (int)((nb + 255) / 256);
+    hipLaunchKernelGGL(k_merge_partition, dim3(g), dim3(256), 0, s, A.nrows, A.nnz,
+                       (const int *)A.row_ptr->p, A.ntiles, (int2 *)A.part->p);
+    return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t s) {
+    SpmvK<V> p;
+    p.x = (const V *)a.x;
+    p.y = (V *)a.y;
+    p.alpha = (V)a.alpha;
+    p.beta = (V)a.beta;
+    p.beta_zero = (a.beta == 0.0);
+    p.stop = a.stop;
+    p.w = (const V *)a.w;
+    p.partials = a.partials;
+    p.slot_base = 0;
+    const bool dot = a.w != nullptr;
+    const int64_t n = A.nrows;
+    if (n == 0) return hipSuccess;
+    const int *rp = (const int *)A.row_ptr->p;
+    const int *col = (const int *)A.col->p;
+    const V *val = (const V *)A.val->p;
+    const dim3 blk(kWG);
+    auto fixup = [&](const Carry *cr, int64_t ntiles) {
+        const unsigned g = (unsigned)((ntiles + kWG - 1) / kWG);
+        if (g) hipLaunchKernelGGL(k_carry_fixup<V>, dim3(g), blk, 0, s, cr, ntiles, p);
+    };
+    switch (A.format) {
+    case MXL_FMT_CSR: {
+        if (A.variant == MXL_CSR_SCALAR) {
+            if (dot) hipLaunchKernelGGL((k_csr_scalar<V, true>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, p);
+            else hipLaunchKernelGGL((k_csr_scalar<V, false>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, p);
+        } else if (A.variant == MXL_CSR_VECTOR) {
+#define MXL_VEC_CASE(WW)                                                                                   \
+    case WW:                                                                                               \
+        if (dot) hipLaunchKernelGGL((k_csr_vector<V, WW, true>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, p); \
+        else hipLaunchKernelGGL((k_csr_vector<V, WW, false>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, p); \
+        break;
+            switch (A.vw) {
+                MXL_VEC_CASE(2) MXL_VEC_CASE(4) MXL_VEC_CASE(8) MXL_VEC_CASE(16) MXL_VEC_CASE(32) MXL_VEC_CASE(64)
+            default: return hipErrorInvalidValue;
+            }
+#undef MXL_VEC_CASE
+        } else {
+            Carry *cr = (Carry *)A.carries->p;
+            const int2 *part = (const int2 *)A.part->p;
+            if (dot) hipLaunchKernelGGL((k_csr_merge<V, true>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, part, A.ntiles, cr, p);
+            else hipLaunchKernelGGL((k_csr_merge<V, false>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, part, A.ntiles, cr, p);
+            fixup(cr, A.ntiles);
+        }
+        break;
+    }
+    case MXL_FMT_COO: {
+        if (A.nnz == 0) {
+            if (dot) return hipErrorNotSupported;
+            hipLaunchKernelGGL(k_scale_only<V>, dim3(256), blk, 0, s, n, p);
+            break;
+        }
+        Carry *cr = (Carry *)A.carries->p;
+        const int *row = (const int *)A.coo_row->p;
+        if (dot) hipLaunchKernelGGL((k_coo<V, true, false>), dim3(A.grid_main), blk, 0, s, n, A.nnz, row, col, val, A.ntiles, cr, p);
+        else hipLaunchKernelGGL((k_coo<V, false, false>), dim3(A.grid_main), blk, 0, s, n, A.nnz, row, col, val, A.ntiles, cr, p);
+        fixup(cr, A.ntiles);
+        break;
+    }
+    case MXL_FMT_ELL:
+    case MXL_FMT_HYB: {
+        const int *ec = (const int *)A.ell_col->p;
+        const V *ev = (const V *)A.ell_val->p;
+        const int2 *win = A.ell_win ? (const int2 *)A.ell_win->p : nullptr;
+        const bool lds = A.variant == MXL_ELL_LDS && win;
+        if (lds) {
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, true>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
+            else hipLaunchKernelGGL((k_ell<V, false, true>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
+        } else {
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, false>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
+            else hipLaunchKernelGGL((k_ell<V, false, false>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
+        }
+        if (A.format == MXL_FMT_HYB && A.tail_nnz > 0) {
+            SpmvK<V> t = p;  // tail accumulates into y
+            t.slot_base = A.grid_main;
+            t.beta = (V)1;
+            t.beta_zero = 0;
+            Carry *cr = (Carry *)A.carries->p;
+            const int *tr = (const int *)A.tail_row->p;
+            const int *tc = (const int *)A.tail_col->p;
+            const V *tv = (const V *)A.tail_val->p;
+            if (dot) hipLaunchKernelGGL((k_coo<V, true, true>), dim3(A.grid_tail), blk, 0, s, n, A.tail_nnz, tr, tc, tv, A.ntiles, cr, t);
+            else hipLaunchKernelGGL((k_coo<V, false, true>), dim3(A.grid_tail), blk, 0, s, n, A.tail_nnz, tr, tc, tv, A.ntiles, cr, t);
+            fixup(cr, A.ntiles);
+        }
+        break;
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t spmv_launch(const MatrixImpl &A, const SpmvArgs &a, hipStream_t s) {
+    return A.dtype == MXL_F64 ? spmv_typed<double>(A, a, s) : spmv_typed<float>(A, a, s);
+}
+
+// ---------------------------------------------------- setup launchers
+static dim3 g1(int64_t n) { return dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)); }
+
+hipError_t launch_validate(const MatrixImpl &A, int *flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, g1(A.nrows + 1), dim3(256), 0, s, A.nrows, A.ncols, A.nnz,
+                       (const int *)A.row_ptr->p, (const int *)A.col->p, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_to_coo(const MatrixImpl &A, int *row, hipStream_t s) {
+    if (A.nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_csr_to_coo, g1(A.nrows), dim3(256), 0, s, A.nrows, (const int *)A.row_ptr->p, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_to_ell(const MatrixImpl &A, int w, int64_t n_pad, int *ecol, void *evals,
+                             hipStream_t s) {
+    if (n_pad == 0 || w == 0) return hipSuccess;
+    if (A.dtype == MXL_F64)
+        hipLaunchKernelGGL(k_csr_to_ell<double>, g1(n_pad), dim3(256), 0, s, A.nrows, n_pad, w,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const double *)A.val->p, ecol, (double *)evals);
+    else
+        hipLaunchKernelGGL(k_csr_to_ell<float>, g1(n_pad), dim3(256), 0, s, A.nrows, n_pad, w,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const float *)A.val->p, ecol, (float *)evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_hyb_tail(const MatrixImpl &A, int k, const int64_t *toff, int *trow, int *tcol,
+                           void *tval, hipStream_t s) {
+    if (A.nrows == 0) return hipSuccess;
+    if (A.dtype == MXL_F64)
+        hipLaunchKernelGGL(k_hyb_tail<double>, g1(A.nrows), dim3(256), 0, s, A.nrows, k,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const double *)A.val->p, toff, trow, tcol, (double *)tval);
+    else
+        hipLaunchKernelGGL(k_hyb_tail<float>, g1(A.nrows), dim3(256), 0, s, A.nrows, k,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const float *)A.val->p, toff, trow, tcol, (float *)tval);
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_windows(const MatrixImpl &A, int2 *win, hipStream_t s) {
+    int64_t nt = (A.nrows + kWG - 1) / kWG;
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_windows, g1(nt), dim3(256), 0, s, A.nrows, (const int *)A.row_ptr->p,
+                       (const int *)A.col->p, nt, win);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const MatrixImpl &A, void *dinv, int *bad, hipStream_t s) {
+    if (A.nrows == 0) return hipSuccess;
+    if (A.dtype == MXL_F64)
+        hipLaunchKernelGGL(k_jacobi<double>, g1(A.nrows), dim3(256), 0, s, A.nrows,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const double *)A.val->p, (double *)dinv, bad);
+    else
+        hipLaunchKernelGGL(k_jacobi<float>, g1(A.nrows), dim3(256), 0, s, A.nrows,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const float *)A.val->p, (float *)dinv, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_vals(int64_t n, int from, const void *in, void *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    unsigned g = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    if (from == MXL_F64)
+        hipLaunchKernelGGL((k_convert_vals<double, float>), dim3(g), dim3(256), 0, s, n, (const double *)in, (float *)out);
+    else
+        hipLaunchKernelGGL((k_convert_vals<float, double>), dim3(g), dim3(256), 0, s, n, (const float *)in, (double *)out);
+    return hipGetLastError();
+}
+
+}  // namespace mxl

@@ -1,0 +1,54 @@
+"""Write the oracle's iteration counts at the full workload sizes.
+
+Calls only the CPU oracle and the seeded input generators; the GPU tests
+compare the HIP solvers' counts against these stored values because the
+oracle needs minutes at these sizes.  Run from the repository root:
+    python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)))))
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+def main():
+    O.build(force=False)
+    out = {"note": "oracle (plain FP64 C) counts; inputs from workloads with the seeds below"}
+    t = time.time()
+    A = W.stencil_3d27(128)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 2))
+    d, _ = O.jacobi_dinv(A)
+    r = O.pcg(A, b, dinv=d, reduction=1e-10, max_iters=5000)
+    out["stencil27_128_pcg_1e-10"] = dict(recipe="x* = U[-1,1) seed 2, b = A x*, x0 = 0",
+                                          iterations=r["iterations"], stop=r["stop_reason"],
+                                          rel_residual=r["rel_residual"])
+    print("27pt", r["iterations"], time.time() - t, flush=True)
+    del A, b, d
+    A = W.aniso_3d7(160)
+    b = W.uniform_vec(A.nrows, 4)
+    d, _ = O.jacobi_dinv(A)
+    for red in (1e-10, 1e-12):
+        t = time.time()
+        r = O.pcg(A, b, dinv=d, reduction=red, max_iters=5000)
+        out[f"aniso7_160_pcg_{red:g}"] = dict(recipe="b = U[-1,1) seed 4, x0 = 0",
+                                             iterations=r["iterations"], stop=r["stop_reason"],
+                                             rel_residual=r["rel_residual"])
+        print("aniso", red, r["iterations"], time.time() - t, flush=True)
+    t = time.time()
+    r = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4)
+    out["aniso7_160_ir_1e-12_inner_1e-4"] = dict(recipe="b = U[-1,1) seed 4, x0 = 0",
+                                                 outer=r["outer"], inner_iterations=r["inner_iterations"],
+                                                 stop=r["stop_reason"], history=list(r["history"]))
+    print("ir", r["outer"], r["inner_iterations"], time.time() - t, flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "solver_counts.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

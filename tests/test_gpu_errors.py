@@ -1,0 +1,110 @@
+"""Every error status of the C ABI is reachable and is raised on the host,
+before any kernel runs (the paper's apply checks sizes, checked casts throw,
+and unimplemented combinations throw)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests._gpu import DEV, dev, matrix
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mxl():
+    import paper_2006_16852_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mxl):
+    return mxl.Context(0)
+
+
+def _status(mxl, fn, *a):
+    with pytest.raises(mxl.MxlError) as e:
+        fn(*a)
+    return e.value.status
+
+
+def test_invalid_args(mxl, ctx):
+    A = W.stencil_2d5(8)
+    M = matrix(mxl, ctx, A)
+    x = torch.ones(64, dtype=torch.float64, device=DEV)
+    assert _status(mxl, M.apply, x, x) == mxl.ERR_INVALID_ARG           # aliasing
+    st = mxl.lib.mxl_apply_adv(M.h, 1.0, None, 0.0, C.c_void_p(x.data_ptr()))
+    assert st == mxl.ERR_INVALID_ARG                                    # NULL
+    host = np.ones(64)
+    y = torch.zeros(64, dtype=torch.float64, device=DEV)
+    st = mxl.lib.mxl_apply_adv(M.h, 1.0, host.ctypes.data_as(C.c_void_p), 0.0,
+                               C.c_void_p(y.data_ptr()))
+    assert st == mxl.ERR_INVALID_ARG                                    # host memory
+    assert "device memory" in mxl.lib.mxl_last_error().decode()
+    assert mxl.lib.mxl_apply(None, None, None) == mxl.ERR_INVALID_ARG
+    assert _status(mxl, lambda: mxl.solver("cg", M, None, max_iters=-1)) == mxl.ERR_INVALID_ARG
+    bad = mxl.lib.mxl_convert(M.h, 3, None, C.byref(C.c_void_p()))
+    assert bad == mxl.OK  # NULL params mean defaults
+
+
+def test_dtype_and_dims(mxl, ctx):
+    A = W.stencil_2d5(8)
+    M64 = matrix(mxl, ctx, A)
+    M32 = matrix(mxl, ctx, A, torch.float32)
+    P32 = mxl.jacobi(M32)
+    assert _status(mxl, mxl.solver, "cg", M64, P32) == mxl.ERR_DTYPE
+    assert _status(mxl, mxl.ir, M32) == mxl.ERR_DTYPE
+    B = W.stencil_2d5(9)
+    PB = mxl.jacobi(matrix(mxl, ctx, B))
+    assert _status(mxl, mxl.solver, "cg", M64, PB) == mxl.ERR_DIM_MISMATCH
+    R = W.random_sparse(10, 12, 0.3, 1)
+    assert _status(mxl, mxl.jacobi, matrix(mxl, ctx, R)) == mxl.ERR_NOT_IMPLEMENTED
+    assert _status(mxl, mxl.solver, "cg", matrix(mxl, ctx, R)) == mxl.ERR_DIM_MISMATCH
+
+
+def test_not_implemented(mxl, ctx):
+    M = matrix(mxl, ctx, W.stencil_2d5(8))
+    assert _status(mxl, M.convert, "csr", 7) == mxl.ERR_NOT_IMPLEMENTED
+    assert _status(mxl, M.convert, "ell", 5) == mxl.ERR_NOT_IMPLEMENTED
+    assert _status(mxl, M.convert, "csr", 1, 3) == mxl.ERR_INVALID_ARG  # width 3
+
+
+def test_invalid_matrix_validation(mxl, ctx):
+    A = W.random_sparse(40, 40, 0.2, 3)
+    r = next(i for i in range(40) if A.row_ptr[i + 1] - A.row_ptr[i] >= 2)
+    k = A.row_ptr[r]
+    col = A.col.copy()
+    col[k], col[k + 1] = col[k + 1], col[k]
+    rp, c, v = dev(A.row_ptr), dev(col), dev(A.val)
+    assert _status(mxl, mxl.csr, ctx, rp, c, v, None, False, True) == mxl.ERR_INVALID_MATRIX
+    col2 = A.col.copy()
+    col2[0] = 40
+    assert _status(mxl, mxl.csr, ctx, rp, dev(col2), v, None, False, True) == mxl.ERR_INVALID_MATRIX
+    ok = mxl.csr(ctx, rp, dev(A.col), v, validate=True)
+    assert ok.describe()["nnz"] == A.nnz
+
+
+def test_zero_diagonal(mxl, ctx):
+    A = W.stencil_2d5(6)
+    A.val[A.row_ptr[7] + 2] = 0.0     # row 7's diagonal (interior row: 5 entries, diag 3rd)
+    assert A.col[A.row_ptr[7] + 2] == 7
+    assert _status(mxl, mxl.jacobi, matrix(mxl, ctx, A)) == mxl.ERR_ZERO_DIAG
+    assert "row 7" in mxl.lib.mxl_last_error().decode()
+
+
+def test_infeasible_ell(mxl, ctx):
+    n = 200_000
+    rows = [([i], [1.0]) for i in range(n)]
+    rows[5] = (list(range(10_000)), [1.0] * 10_000)
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(c) for c, _ in rows])
+    col = np.concatenate([np.array(c, np.int32) for c, _ in rows])
+    val = np.concatenate([np.array(v) for _, v in rows])
+    A = W.Csr(n, n, rp.astype(np.int32), col, val)
+    M = matrix(mxl, ctx, A)
+    assert _status(mxl, M.convert, "ell") == mxl.ERR_INFEASIBLE_FORMAT
+    H = M.convert("hyb", hyb_quantile=0.9)        # the tail absorbs the long row
+    d = H.describe()
+    assert d["ell_width"] == 1 and d["tail_nnz"] == 9_999

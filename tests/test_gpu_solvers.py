@@ -1,0 +1,236 @@
+"""Krylov solver parity (Jacobi-PCG, Jacobi-BiCGSTAB, FP32-inner iterative
+refinement) of the HIP library against the CPU oracle, through the C ABI.
+
+The bar: the stop reason equals the oracle's, the iteration count is within
+max(2, 2%) of the oracle's (summation order differs, so the count may move
+by a step near the threshold), and the residual recomputed in FP64 on the
+CPU meets the tolerance.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests._gpu import DEV, dev, matrix
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def mxl():
+    import paper_2006_16852_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mxl):
+    return mxl.Context(0)
+
+
+def _close_iters(a, b):
+    return abs(a - b) <= max(2, int(0.02 * b))
+
+
+def _true_rel(A, b, x):
+    return np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)
+
+
+FORMATS = [("csr", dict(variant=1)), ("csr", dict(variant=2)), ("csr", dict(variant=0)),
+           ("coo", {}), ("ell", {}), ("hyb", dict(hyb_quantile=0.66))]
+
+
+@pytest.mark.parametrize("fmt,kw", FORMATS, ids=["vec", "merge", "scalar", "coo", "ell", "hyb"])
+def test_pcg_cfg1_all_formats(mxl, ctx, fmt, kw):
+    A = W.stencil_2d5(64)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 1))
+    d, _ = O.jacobi_dinv(A)
+    ref = O.pcg(A, b, dinv=d, reduction=1e-10)
+    M = matrix(mxl, ctx, A).convert(fmt, **kw)
+    P = mxl.jacobi(M)
+    S = mxl.solver("cg", M, P, max_iters=10_000, reduction=1e-10)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x, history=400)
+    print(f"[pcg cfg1 {fmt}] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert _close_iters(info["iterations"], ref["iterations"])
+    assert _true_rel(A, b, x.cpu().numpy()) <= 1.01e-10
+    h = np.array(info["history"])
+    assert h[0] == pytest.approx(1.0) and h[-1] <= 1e-10
+    assert np.allclose(h[:50], ref_hist(A, b, d)[:50], rtol=1e-6)
+
+
+def ref_hist(A, b, d):
+    return O.pcg(A, b, dinv=d, reduction=1e-10, history=True)["history"]
+
+
+def test_pcg_check_every_independent(mxl, ctx):
+    A = W.aniso_3d7(20)
+    b = W.uniform_vec(A.nrows, 4)
+    M = matrix(mxl, ctx, A)
+    P = mxl.jacobi(M)
+    xs = []
+    its = []
+    for ce in (1, 7, 64):
+        S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-11, check_every=ce)
+        x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+        info = S.solve(dev(b), x)
+        xs.append(x.cpu().numpy())
+        its.append(info["iterations"])
+    assert its[0] == its[1] == its[2]
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    ref = O.pcg(A, b, dinv=O.jacobi_dinv(A)[0], reduction=1e-11, max_iters=5000)
+    assert _close_iters(its[0], ref["iterations"])
+
+
+def test_pcg_fp32_matches_oracle_definition(mxl, ctx):
+    A = W.aniso_3d7(16)
+    b32 = W.uniform_vec(A.nrows, 6).astype(np.float32)
+    d, _ = O.jacobi_dinv(A)
+    ref = O.pcg_f32(A, b32, d.astype(np.float32), reduction=1e-5, max_iters=2000)
+    M = matrix(mxl, ctx, A, torch.float32)
+    P = mxl.jacobi(M)
+    S = mxl.solver("cg", M, P, max_iters=2000, reduction=1e-5)
+    x = torch.zeros(A.nrows, dtype=torch.float32, device=DEV)
+    info = S.solve(dev(b32), x)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED == ref["stop_reason"]
+    assert _close_iters(info["iterations"], ref["iterations"])
+
+
+def test_listing_protocol(mxl, ctx):
+    g = json.load(open(os.path.join(GOLD, "listing_cg_jacobi.json")))
+    A = W.stencil_2d5(32)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 3))
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("cg", M, mxl.jacobi(M), max_iters=g["max_iters"], reduction=g["reduction_factor"])
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    assert info["iterations"] == g["expected_iterations"]
+    assert info["stop_reason"] == mxl.STOP_MAX_ITERS
+    ref = O.pcg(A, b, dinv=O.jacobi_dinv(A)[0], max_iters=20, reduction=1e-15)
+    assert np.allclose(x.cpu().numpy(), ref["x"], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["cg", "bicgstab"])
+def test_nan_rhs_protocol(mxl, ctx, kind):
+    g = json.load(open(os.path.join(GOLD, "nan_rhs_protocol.json")))
+    A = W.Csr(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]))
+    M = matrix(mxl, ctx, A)
+    b = torch.full((1,), float("nan"), dtype=torch.float64, device=DEV)
+    for chk, want in ((0, mxl.STOP_MAX_ITERS), (1, mxl.STOP_NONFINITE)):
+        S = mxl.solver(kind, M, None, max_iters=g["iterations"], reduction=1e-10,
+                       nonfinite_check=chk, check_every=g["iterations"])
+        x = torch.zeros(1, dtype=torch.float64, device=DEV)
+        info = S.solve(b, x)
+        assert info["stop_reason"] == want
+        if chk == 0:
+            assert info["iterations"] == g["iterations"]
+
+
+def test_breakdown_zero_rhs_and_initial_guess(mxl, ctx):
+    A = W.Csr(2, 2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("cg", M, None, max_iters=10)
+    x = torch.zeros(2, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(np.array([1.0, 1.0])), x)
+    assert info["stop_reason"] == mxl.STOP_BREAKDOWN and info["iterations"] == 0
+    B = W.stencil_2d5(4)
+    MB = matrix(mxl, ctx, B)
+    S = mxl.solver("cg", MB, mxl.jacobi(MB))
+    x = torch.ones(16, dtype=torch.float64, device=DEV)
+    info = S.solve(torch.zeros(16, dtype=torch.float64, device=DEV), x)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED and info["iterations"] == 0
+    assert not x.any()
+    # resume: a second solve from the returned x needs (almost) no work
+    b = O.spmv(B, W.uniform_vec(16, 1))
+    x = torch.zeros(16, dtype=torch.float64, device=DEV)
+    S.solve(dev(b), x)
+    info = S.solve(dev(b), x)
+    assert info["iterations"] <= 1
+
+
+def test_time_criterion(mxl, ctx):
+    A = W.stencil_2d5(64)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("cg", M, mxl.jacobi(M), max_iters=100_000, reduction=0.0, time_limit=1e-9,
+                   check_every=5)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(W.uniform_vec(A.nrows, 1)), x)
+    assert info["stop_reason"] == mxl.STOP_TIME and info["iterations"] == 5
+
+
+@pytest.mark.parametrize("A", [W.convdiff_2d5(40), W.stencil_2d5(40), W.aniso_3d7(14)],
+                         ids=lambda a: a.name)
+def test_bicgstab(mxl, ctx, A):
+    b = O.spmv(A, W.uniform_vec(A.nrows, 5))
+    d, _ = O.jacobi_dinv(A)
+    ref = O.bicgstab(A, b, dinv=d, reduction=1e-10)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("bicgstab", M, mxl.jacobi(M), max_iters=10_000, reduction=1e-10)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[bicgstab {A.name}] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert _close_iters(info["iterations"], ref["iterations"])
+    assert _true_rel(A, b, x.cpu().numpy()) <= 2e-10
+
+
+def test_bicgstab_diagonal_half_step(mxl, ctx):
+    n = 17
+    dvals = np.linspace(1, 5, n)
+    A = W.Csr(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), dvals)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("bicgstab", M, mxl.jacobi(M), reduction=1e-14)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = S.solve(torch.ones(n, dtype=torch.float64, device=DEV), x)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED and info["iterations"] == 1
+    assert np.allclose(x.cpu().numpy(), 1 / dvals, rtol=1e-15)
+
+
+def test_ir_mixed_precision(mxl, ctx):
+    A = W.aniso_3d7(28)
+    b = W.uniform_vec(A.nrows, 4)
+    ref = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4)
+    M = matrix(mxl, ctx, A)
+    S = mxl.ir(M, outer=dict(max_iters=50, reduction=1e-12), inner=dict(reduction=1e-4, max_iters=10_000))
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x, history=60)
+    print(f"[ir] gpu outer {info['iterations']} inner {info['inner_iterations']} | oracle "
+          f"{ref['outer']} {ref['inner_iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["outer"]) <= 1
+    assert abs(info["inner_iterations"] - ref["inner_iterations"]) <= max(4, 0.05 * ref["inner_iterations"])
+    assert _true_rel(A, b, x.cpu().numpy()) <= 1e-12
+
+
+def test_solver_deterministic(mxl, ctx):
+    A = W.stencil_3d27(20)
+    b = dev(W.uniform_vec(A.nrows, 9))
+    M = matrix(mxl, ctx, A).convert("csr", variant=2)
+    S = mxl.solver("cg", M, mxl.jacobi(M), reduction=1e-10)
+    x1 = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    x2 = torch.zeros_like(x1)
+    S.solve(b, x1)
+    S.solve(b, x2)
+    assert torch.equal(x1, x2)
+
+
+def test_full_size_pcg_stencil27(mxl, ctx):
+    """Jacobi-PCG to 1e-10 on the 128^3 27-point system at full size: the
+    iteration count against the oracle's stored count, the residual recomputed
+    in FP64 on the CPU."""
+    g = json.load(open(os.path.join(GOLD, "solver_counts.json")))["stencil27_128_pcg_1e-10"]
+    A = W.stencil_3d27(128)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 2))
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("cg", M, mxl.jacobi(M), max_iters=5000, reduction=1e-10, check_every=8)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[pcg full27] gpu {info['iterations']} oracle {g['iterations']} {info['seconds']:.3f}s", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert _close_iters(info["iterations"], g["iterations"])
+    assert _true_rel(A, b, x.cpu().numpy()) <= 1.01e-10

@@ -1,0 +1,203 @@
+"""SpMV parity: every (format, variant, dtype) of the HIP library against the
+FP64 CPU oracle, through the C ABI.
+
+Tolerance per row (FP64 1e-12, FP32 1e-5) relative to
+|alpha| sum_j |a_ij||x_j| + |beta||y_i|; integer-exact inputs must agree
+bitwise in every variant; format arrays must equal the oracle's bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests._gpu import DEV, assert_rows_close, dev, matrix, spmv_reference
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [
+    ("csr", 0, 0, 0.0, "csr_scalar"),
+    ("csr", 1, 2, 0.0, "csr_vec2"),
+    ("csr", 1, 4, 0.0, "csr_vec4"),
+    ("csr", 1, 16, 0.0, "csr_vec16"),
+    ("csr", 1, 32, 0.0, "csr_vec32"),
+    ("csr", 1, 64, 0.0, "csr_vec64"),
+    ("csr", 2, 0, 0.0, "csr_merge"),
+    ("coo", 0, 0, 0.0, "coo"),
+    ("ell", 0, 0, 0.0, "ell"),
+    ("ell", 1, 0, 0.0, "ell_lds"),
+    ("hyb", 0, 0, 0.66, "hyb66"),
+    ("hyb", 1, 0, 0.9, "hyb90_lds"),
+]
+
+
+def _matrices():
+    ms = [W.stencil_2d5(64), W.stencil_3d27(22), W.aniso_3d7(17), W.convdiff_2d5(31)]
+    for m in (3, 11, 58):
+        A = W.zipf_suite_matrix(m, scale_n=0.01)
+        ms.append(A)
+    ms += W.edge_matrices()
+    return ms
+
+
+MATS = _matrices()
+
+
+@pytest.fixture(scope="module")
+def mxl():
+    import paper_2006_16852_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mxl):
+    return mxl.Context(0)
+
+
+def _convert(base, fmt, var, vw, q):
+    if fmt == "csr":
+        return base.convert("csr", variant=var, vector_width=vw)
+    return base.convert(fmt, variant=var, hyb_quantile=q)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("fmt,var,vw,q,name", VARIANTS, ids=[v[-1] for v in VARIANTS])
+@pytest.mark.parametrize("A", MATS, ids=[a.name for a in MATS])
+def test_spmv_parity(mxl, ctx, A, fmt, var, vw, q, name, dtype):
+    print(f"[spmv] {A.name} {name} {dtype}", flush=True)
+    base = matrix(mxl, ctx, A, dtype)
+    try:
+        op = _convert(base, fmt, var, vw, q)
+    except mxl.MxlError as e:
+        assert e.status == mxl.ERR_INFEASIBLE_FORMAT and fmt == "ell", e
+        return
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, A.ncols)
+    y0 = rng.uniform(-1, 1, A.nrows)
+    fp32 = dtype == torch.float32
+    tau = 1e-5 if fp32 else 1e-12
+    for alpha, beta in [(1.0, 0.0), (-1.0, 1.0), (0.5, -2.0)]:
+        xd = dev(x, dtype)
+        yd = dev(y0, dtype) if beta != 0 else torch.full((A.nrows,), float("nan"), dtype=dtype, device=DEV)
+        op.apply(xd, yd, alpha, beta)
+        torch.cuda.synchronize()
+        want, bound = spmv_reference(A, x, alpha, beta, y0, fp32)
+        if fp32 and fmt == "csr" and var == 0:
+            # one lane sums a whole row sequentially: charge the classical
+            # FP32 bound gamma_k for rows longer than the 1e-5 budget allows
+            k = A.row_lengths().astype(float) + 2
+            u = 2.0 ** -24
+            tau_rows = np.maximum(tau, k * u / (1 - k * u))
+            assert_rows_close(yd.cpu().numpy(), want, bound * tau_rows / tau, tau, f"{name} a={alpha} b={beta}")
+        else:
+            assert_rows_close(yd.cpu().numpy(), want, bound, tau, f"{name} a={alpha} b={beta}")
+
+
+@pytest.mark.parametrize("fmt,var,vw,q,name", VARIANTS, ids=[v[-1] for v in VARIANTS])
+def test_spmv_integer_exact_bitwise(mxl, ctx, fmt, var, vw, q, name):
+    """Integer values with partial sums < 2^24: every summation order is exact,
+    so FP64 and FP32 results must equal the oracle bitwise."""
+    A = W.random_sparse(777, 901, 0.02, 21, integer=True, int_range=9, empty_row_frac=0.1)
+    rng = np.random.default_rng(3)
+    x = rng.integers(-50, 51, A.ncols).astype(np.float64)
+    want = O.spmv(A, x)
+    assert np.abs(want).max() < 2 ** 24
+    for dtype in (torch.float64, torch.float32):
+        op = _convert(matrix(mxl, ctx, A, dtype), fmt, var, vw, q)
+        y = torch.zeros(A.nrows, dtype=dtype, device=DEV)
+        op.apply(dev(x, dtype), y)
+        got = y.cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, want), name
+
+
+@pytest.mark.parametrize("fmt,var,vw,q,name", VARIANTS, ids=[v[-1] for v in VARIANTS])
+def test_spmv_nan_propagation(mxl, ctx, fmt, var, vw, q, name):
+    """x_j = NaN makes exactly the rows that store column j NaN (padding never
+    multiplies x), including rows whose stored value is an explicit zero."""
+    A = W.random_sparse(300, 300, 0.03, 5)
+    j = int(A.col[10])
+    A.val[10] = 0.0
+    x = np.ones(300)
+    x[j] = np.nan
+    op = _convert(matrix(mxl, ctx, A), fmt, var, vw, q)
+    y = torch.zeros(300, dtype=torch.float64, device=DEV)
+    op.apply(dev(x), y)
+    stores = np.zeros(300, bool)
+    rows = np.repeat(np.arange(300), A.row_lengths())
+    stores[rows[A.col == j]] = True
+    assert np.array_equal(np.isnan(y.cpu().numpy()), stores)
+
+
+@pytest.mark.parametrize("A", [MATS[0], MATS[4], MATS[8], MATS[9]], ids=lambda a: a.name)
+def test_format_arrays_bitwise(mxl, ctx, A):
+    base = matrix(mxl, ctx, A)
+    coo = base.convert("coo")
+    assert np.array_equal(coo.export("coo_row").cpu().numpy(), O.csr_to_coo(A))
+    try:
+        ell = base.convert("ell")
+        w, n_pad, ec, ev = O.csr_to_ell(A)
+        d = ell.describe()
+        assert (d["ell_width"], d["n_pad"]) == (w, n_pad)
+        assert np.array_equal(ell.export("ell_col").cpu().numpy(), ec)
+        assert np.array_equal(ell.export("ell_val").cpu().numpy(), ev)
+    except mxl.MxlError as e:
+        assert e.status == mxl.ERR_INFEASIBLE_FORMAT
+    for q in (0.66, 0.9):
+        hyb = base.convert("hyb", hyb_quantile=q)
+        H = O.csr_to_hyb(A, q=q)
+        d = hyb.describe()
+        assert d["ell_width"] == H["k"] and d["tail_nnz"] == H["tail_row"].size
+        for key in ("ell_col", "ell_val", "tail_row", "tail_col", "tail_val"):
+            got = hyb.export(key).cpu().numpy()
+            assert np.array_equal(got, H[key]), key
+
+
+def test_spmv_deterministic(mxl, ctx):
+    A = W.zipf_suite_matrix(17, scale_n=0.02)
+    x = dev(np.random.default_rng(1).standard_normal(A.ncols))
+    for fmt, var, vw, q, name in VARIANTS:
+        try:
+            op = _convert(matrix(mxl, ctx, A), fmt, var, vw, q)
+        except mxl.MxlError as e:
+            assert e.status == mxl.ERR_INFEASIBLE_FORMAT
+            continue
+        y1 = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+        y2 = torch.zeros_like(y1)
+        op.apply(x, y1)
+        op.apply(x, y2)
+        assert torch.equal(y1, y2), name
+
+
+def test_full_size_stencil27_sampled(mxl, ctx):
+    """The 128^3 27-point operator (n = 2,097,152, nnz = 55,742,968) in every
+    format, at the launch configuration the benchmark times; rows sampled and
+    checked one by one against the oracle, plus the exact row-sum identity."""
+    A = W.stencil_3d27(128)
+    assert A.nnz == 55_742_968
+    x = W.uniform_vec(A.nrows, 2)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, A.nrows, 4000), [0, A.nrows - 1]]))
+    sub = W.Csr(rows.size, A.ncols, np.concatenate([[0], np.cumsum(A.row_lengths()[rows])]).astype(np.int32),
+                np.concatenate([A.col[A.row_ptr[r]:A.row_ptr[r + 1]] for r in rows]),
+                np.concatenate([A.val[A.row_ptr[r]:A.row_ptr[r + 1]] for r in rows]))
+    want, bound = spmv_reference(sub, x, 1.0, 0.0, np.zeros(rows.size), False)
+    base = matrix(mxl, ctx, A)
+    xd = dev(x)
+    ones = torch.ones(A.nrows, dtype=torch.float64, device=DEV)
+    idx = np.arange(A.nrows)
+    N = 128
+    c = [np.where((t == 0) | (t == N - 1), 2, 3) for t in (idx % N, (idx // N) % N, idx // N ** 2)]
+    rowsum = (27 - c[0] * c[1] * c[2]).astype(np.float64)
+    for fmt, var, vw, q, name in [v for v in VARIANTS if v[-1] in
+                                  ("csr_vec32", "csr_merge", "csr_scalar", "coo", "ell", "hyb90_lds")]:
+        print(f"[full27] {name}", flush=True)
+        op = _convert(base, fmt, var, vw, q)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
+        op.apply(xd, y)
+        assert_rows_close(y.cpu().numpy()[rows], want, bound, 1e-12, name)
+        op.apply(ones, y)
+        assert np.array_equal(y.cpu().numpy(), rowsum), name
+        del op
+    torch.cuda.empty_cache()
