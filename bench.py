@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="stencil27",
+                    choices=["stencil27", "aniso_ir", "poisson2d", "batch"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -101,6 +103,10 @@ def main():
 
     import paper_2006_16852_amd as mxl
     import workloads as W
+
+    if args.workload != "stencil27":
+        import bench_extra
+        return bench_extra.run(args)
 
     dev = "cuda:0"
     N = args.grid

@@ -64,7 +64,8 @@ enum {
 
 typedef struct {
     int32_t variant;       /* MXL_CSR_* / MXL_ELL_* ... */
-    int32_t vector_width;  /* CSR vector: lanes per row (0 = from mean row length) */
+    int32_t vector_width;  /* CSR vector: lanes per row (0 = from mean row length);
+                              ELL/HYB: rows per thread 1, 2 or 4 (0 = 2) */
     double  hyb_quantile;  /* HYB: ELL width = nearest-rank quantile of row lengths (0 = 0.9) */
 } mxl_format_params;
 
@@ -92,6 +93,10 @@ typedef struct {
     double  time_limit_s;
     int32_t check_every;
     int32_t nonfinite_check;
+    int32_t launch_mode;   /* CG only: 0 auto, 1 one kernel per step, 2 the
+                              whole solve in one persistent workgroup (FP64,
+                              n <= 16384, max_iters >= 1, no Time criterion
+                              and no history); auto picks 2 for n <= 8192 */
 } mxl_criteria;
 
 /* Convergence record (the Convergence logger of Sec. 2.6) plus an optional
@@ -275,6 +280,15 @@ mxl_status mxl_features(const mxl_op *A, double out_host[16]);
  * to evict the 256 MB last-level cache; its time is excluded. */
 mxl_status mxl_time_apply(const mxl_op *A, const void *x, void *y, int reps,
                           int flush, double *median_ms);
+
+/* Bandwidth reference kernels, the STREAM-style operations the paper uses
+ * to calibrate solver bandwidth (Sec. 7.4, Table 3): op 0 copy c = a,
+ * op 1 triad c = a + 0.5*b, op 2 dot a.b (partials written to c, which
+ * then needs 8*256*num_CU bytes).  FP64, n even.  median_ms: median of reps
+ * launches timed with HIP events on the context stream. */
+mxl_status mxl_stream_bench(mxl_ctx *ctx, int op, int64_t n, const double *a,
+                            const double *b, double *c, int reps,
+                            double *median_ms);
 
 /* Small FP32 multilayer perceptron dims[0] -> ... -> dims[nlayers] with
  * ReLU between layers (weights live on the device).  theta_host packs

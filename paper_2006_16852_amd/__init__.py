@@ -46,7 +46,7 @@ class MxlError(RuntimeError):
 class Criteria(C.Structure):
     _fields_ = [("max_iters", C.c_int64), ("reduction", C.c_double),
                 ("time_limit_s", C.c_double), ("check_every", C.c_int32),
-                ("nonfinite_check", C.c_int32)]
+                ("nonfinite_check", C.c_int32), ("launch_mode", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -107,6 +107,7 @@ def _load():
                                C.POINTER(C.c_double)],
         "mxl_features": [vp, vp],
         "mxl_time_apply": [vp, vp, vp, C.c_int, C.c_int, C.POINTER(C.c_double)],
+        "mxl_stream_bench": [vp, C.c_int, i64, vp, vp, vp, C.c_int, C.POINTER(C.c_double)],
         "mxl_mlp_create": [vp, i32, vp, vp, pp],
         "mxl_mlp_get_params": [vp, vp, i64],
         "mxl_mlp_set_params": [vp, vp, i64],
@@ -189,7 +190,7 @@ class Context:
         _check(lib.mxl_ctx_set_stream(self.h, C.c_void_p(s)))
 
     def __del__(self):
-        if getattr(self, "h", None) and _alive[0]:
+        if getattr(self, "h", None) and _alive and _alive[0]:
             lib.mxl_ctx_destroy(self.h)
             self.h = None
 
@@ -267,7 +268,7 @@ class Op:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None) and _alive[0]:
+        if getattr(self, "h", None) and _alive and _alive[0]:
             lib.mxl_op_destroy(self.h)
             self.h = None
 
@@ -287,6 +288,17 @@ def csr(ctx: Context, row_ptr, col, val, ncols=None, copy=False, validate=False)
     return Op(h, ctx, keep=() if copy else (row_ptr, col, val))
 
 
+def stream_bench(ctx: Context, op: str, a, b=None, c=None, reps: int = 10) -> float:
+    """Median ms of a STREAM-style kernel: 'copy' c = a, 'triad' c = a + 0.5 b,
+    'dot' a.b (c receives per-workgroup partials)."""
+    code = {"copy": 0, "triad": 1, "dot": 2}[op]
+    ms = C.c_double()
+    ctx.use_current_stream()
+    _check(lib.mxl_stream_bench(ctx.h, code, a.numel(), _ptr(a), _ptr(b), _ptr(c), reps,
+                                C.byref(ms)))
+    return ms.value
+
+
 def jacobi(A: Op) -> Op:
     h = C.c_void_p()
     A.ctx.use_current_stream()
@@ -295,8 +307,9 @@ def jacobi(A: Op) -> Op:
 
 
 def criteria(max_iters=10_000, reduction=1e-10, time_limit=0.0, check_every=1,
-             nonfinite_check=1) -> Criteria:
-    return Criteria(max_iters, reduction, time_limit, check_every, nonfinite_check)
+             nonfinite_check=1, launch_mode=0) -> Criteria:
+    """launch_mode (CG): 0 auto, 1 one kernel per step, 2 one persistent workgroup."""
+    return Criteria(max_iters, reduction, time_limit, check_every, nonfinite_check, launch_mode)
 
 
 class Solver(Op):
@@ -331,6 +344,104 @@ def solver(kind: str, A: Op, P: Op = None, **crit) -> Solver:
     A.ctx.use_current_stream()
     _check(lib.mxl_solver_generate(k, A.h, P.h if P is not None else None, C.byref(c), C.byref(h)))
     return Solver(h, A.ctx, parents=(A,) + ((P,) if P is not None else ()))
+
+
+class Batch(Op):
+    """Independent small systems solved by batched Jacobi-PCG in one launch."""
+
+    def solve(self, b, x, iters, rel_res, status, tuning=None, **crit) -> None:
+        _need_cuda(b, x, iters, rel_res, status)
+        c = criteria(**({"max_iters": 0} | crit))
+        t = Tuning(*tuning) if tuning is not None else None
+        self.ctx.use_current_stream()
+        _check(lib.mxl_batch_solve(self.h, C.byref(c), C.byref(t) if t is not None else None,
+                                   _ptr(b), _ptr(x), _ptr(iters), _ptr(rel_res), _ptr(status)))
+
+    def autotune(self, b, x_scratch, reps: int = 2, **crit):
+        """Time every schedule on this batch; returns ((wg_size, wgs_per_cu, order), ms)."""
+        _need_cuda(b, x_scratch)
+        c = criteria(**({"max_iters": 0} | crit))
+        t = Tuning()
+        ms = C.c_double()
+        self.ctx.use_current_stream()
+        _check(lib.mxl_batch_autotune(self.h, C.byref(c), _ptr(b), _ptr(x_scratch), reps,
+                                      C.byref(t), C.byref(ms)))
+        return (t.wg_size, t.wgs_per_cu, t.order), ms.value
+
+
+def batch(ctx: Context, sys_ptr_host, sys_ptr, row_ptr, col, val) -> Batch:
+    """sys_ptr_host: numpy int32 row offsets of the systems; the rest device tensors."""
+    import numpy as np
+    sp = np.ascontiguousarray(sys_ptr_host, dtype=np.int32)
+    _need_cuda(sys_ptr, row_ptr, col, val)
+    h = C.c_void_p()
+    ctx.use_current_stream()
+    _check(lib.mxl_batch_csr_create(ctx.h, sp.size - 1, sp.ctypes.data_as(C.c_void_p),
+                                    _ptr(sys_ptr), _ptr(row_ptr), _ptr(col), _ptr(val), 0,
+                                    C.byref(h)))
+    return Batch(h, ctx, keep=(sys_ptr, row_ptr, col, val))
+
+
+class Mlp:
+    """FP32 MLP whose forward pass, gradient and Adam step run on the GPU."""
+
+    def __init__(self, ctx: Context, dims, theta=None):
+        import numpy as np
+        self.ctx = ctx
+        self.dims = list(dims)
+        self.nparams = sum(self.dims[i + 1] * self.dims[i] + self.dims[i + 1]
+                           for i in range(len(self.dims) - 1))
+        d = np.asarray(self.dims, np.int32)
+        th = None if theta is None else np.ascontiguousarray(theta, np.float32)
+        if th is not None and th.size != self.nparams:
+            raise MxlError(ERR_DIM_MISMATCH, "theta size")
+        h = C.c_void_p()
+        ctx.use_current_stream()
+        _check(lib.mxl_mlp_create(ctx.h, len(self.dims) - 1, d.ctypes.data_as(C.c_void_p),
+                                  th.ctypes.data_as(C.c_void_p) if th is not None else None,
+                                  C.byref(h)))
+        self.h = h
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, np.float32)
+        _check(lib.mxl_mlp_get_params(self.h, out.ctypes.data_as(C.c_void_p), self.nparams))
+        return out
+
+    def set_params(self, theta):
+        import numpy as np
+        th = np.ascontiguousarray(theta, np.float32)
+        _check(lib.mxl_mlp_set_params(self.h, th.ctypes.data_as(C.c_void_p), th.size))
+
+    def grad(self):
+        import numpy as np
+        out = np.zeros(self.nparams, np.float32)
+        _check(lib.mxl_mlp_get_grad(self.h, out.ctypes.data_as(C.c_void_p), self.nparams))
+        return out
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        _need_cuda(X)
+        Y = torch.empty((X.shape[0], self.dims[-1]), dtype=torch.float32, device=X.device)
+        self.ctx.use_current_stream()
+        _check(lib.mxl_mlp_forward(self.h, X.shape[0], _ptr(X), _ptr(Y)))
+        return Y
+
+    def loss_grad(self, X, T, M, lam: float = 1e-4) -> float:
+        _need_cuda(X, T, M)
+        loss = C.c_float()
+        self.ctx.use_current_stream()
+        _check(lib.mxl_mlp_loss_grad(self.h, X.shape[0], _ptr(X), _ptr(T), _ptr(M), lam,
+                                     C.byref(loss)))
+        return loss.value
+
+    def adam_step(self, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx.use_current_stream()
+        _check(lib.mxl_mlp_adam_step(self.h, t, lr, beta1, beta2, eps))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _alive and _alive[0]:
+            lib.mxl_mlp_destroy(self.h)
+            self.h = None
 
 
 def ir(A: Op, outer: dict = None, inner: dict = None) -> Solver:

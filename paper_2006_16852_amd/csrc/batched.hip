@@ -1,0 +1,561 @@
+// batched.hip -- thousands of independent small Jacobi-PCG solves in one
+// persistent launch (per-system stopping status: the per-right-hand-side
+// stopping status of the criteria in Sec. 2.5 of the paper, applied to
+// independent systems).
+//
+// Design (gfx950): a grid of wgs_per_cu x num_CU workgroups stays resident;
+// each workgroup pulls a system id from an atomic queue, runs the whole CG
+// for that system with its vectors r, p, q, x in LDS (or in a per-workgroup
+// global scratch slice when the system is too large for LDS), reduces dot
+// products inside the workgroup (fixed tree: deterministic), writes x, the
+// iteration count, the recurrence residual and the stop reason, and pulls
+// the next id.  Every workgroup exits when the queue is drained.  The
+// schedule (workgroup size, residency, order) is chosen by an autotuner
+// that times the candidates on the actual batch.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace mxl {
+
+struct BatchImpl {
+    mxl_ctx *ctx = nullptr;
+    int64_t nsys = 0, rows = 0, nnz = 0;
+    std::vector<int32_t> sys_ptr_h;
+    int max_n = 0;
+    BufPtr sys_ptr, row_ptr, col, val;
+    BufPtr dinv;             // FP64 1/a_ii of every row
+    BufPtr order_input, order_big;  // processing orders
+    BufPtr queue;            // uint32 work counter
+    BufPtr scratch;          // per-workgroup vectors for systems larger than LDS
+    int64_t scratch_elems = 0;
+    bool tuned = false;
+    mxl_tuning best{};
+};
+
+template <int B>
+__device__ __forceinline__ double wg_sum(double v, double *red) {
+    constexpr int NW = B / kWave;
+    v = wave_sum(v);
+    if (NW == 1) return v;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double a = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) a += red[w];
+    return a;
+}
+
+template <int B>
+__device__ __forceinline__ void wg_sum2(double &u, double &v, double *red) {
+    constexpr int NW = B / kWave;
+    u = wave_sum(u);
+    v = wave_sum(v);
+    if (NW == 1) return;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        red[wid] = u;
+        red[NW + wid] = v;
+    }
+    __syncthreads();
+    double a = red[0], c = red[NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        a += red[w];
+        c += red[NW + w];
+    }
+    u = a;
+    v = c;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_batch_pcg(
+    int64_t nsys, const int *__restrict__ sys_ptr, const int *__restrict__ rp,
+    const int *__restrict__ col, const double *__restrict__ val, const double *__restrict__ dinv,
+    const double *__restrict__ bvec, double *__restrict__ xout, int *__restrict__ iters_out,
+    double *__restrict__ rel_out, uint8_t *__restrict__ status_out, const int *__restrict__ order,
+    unsigned *__restrict__ queue, double red_factor, int64_t max_iters_fixed, int iter_factor,
+    int chk, int lds_cap, double *__restrict__ scratch, int64_t scratch_stride, int use_x0) {
+    extern __shared__ double smem[];
+    __shared__ double red[2 * (B / kWave)];
+    __shared__ int s_q;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_q = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int qi = s_q;
+        __syncthreads();
+        if ((int64_t)qi >= nsys) break;
+        const int s = order[qi];
+        const int r0 = sys_ptr[s];
+        const int n = sys_ptr[s + 1] - r0;
+        const bool in_lds = n <= lds_cap;
+        double *base = in_lds ? smem : scratch + (int64_t)blockIdx.x * scratch_stride;
+        double *x = base, *r = base + n, *p = base + 2 * n, *q = base + 3 * n;
+        const double *b = bvec + r0;
+        const double *di = dinv + r0;
+        const int *rps = rp + r0;
+        // x = x0 (or 0), r = b - A x, p = z = D^{-1} r
+        for (int i = tid; i < n; i += B) x[i] = use_x0 ? xout[r0 + i] : 0.0;
+        if (use_x0) __syncthreads();
+        double rz = 0.0, rr0 = 0.0, bb = 0.0;
+        for (int i = tid; i < n; i += B) {
+            const double bi = b[i];
+            double ax = 0.0;
+            if (use_x0)
+                for (int e = rps[i]; e < rps[i + 1]; ++e) ax += val[e] * x[col[e]];
+            const double ri = bi - ax;
+            const double zi = di[i] * ri;
+            r[i] = ri;
+            p[i] = zi;
+            rz += ri * zi;
+            rr0 += ri * ri;
+            bb += bi * bi;
+        }
+        wg_sum2<B>(rz, bb, red);
+        rr0 = wg_sum<B>(rr0, red);
+        const double nb = sqrt(bb);
+        const int64_t maxit = max_iters_fixed > 0 ? max_iters_fixed : (int64_t)iter_factor * n;
+        int stop = ST_RUN;
+        int64_t k = 0;
+        double rr = rr0;
+        if (bb == 0.0) {  // zero right-hand side: x = 0
+            for (int i = tid; i < n; i += B) x[i] = 0.0;
+            stop = ST_CONVERGED;
+        } else if (sqrt(rr) <= red_factor * nb) {
+            stop = ST_CONVERGED;
+        }
+        double rho = rz;
+        while (stop == ST_RUN && k < maxit) {
+            __syncthreads();  // p complete
+            double pq = 0.0;
+            for (int i = tid; i < n; i += B) {
+                const int e0 = rps[i], e1 = rps[i + 1];
+                double acc = 0.0;
+                for (int e = e0; e < e1; ++e) acc += val[e] * p[col[e]];
+                q[i] = acc;
+                pq += p[i] * acc;
+            }
+            const double eta = wg_sum<B>(pq, red);
+            if (chk && !finite_d(eta)) { stop = ST_NONFINITE; break; }
+            if (eta <= 0.0) { stop = ST_BREAKDOWN; break; }
+            const double alpha = rho / eta;
+            double rzn = 0.0, rrn = 0.0;
+            for (int i = tid; i < n; i += B) {
+                x[i] += alpha * p[i];
+                const double ri = r[i] - alpha * q[i];
+                r[i] = ri;
+                rzn += ri * (di[i] * ri);
+                rrn += ri * ri;
+            }
+            wg_sum2<B>(rzn, rrn, red);
+            ++k;
+            rr = rrn;
+            if (chk && !finite_d(rr)) { stop = ST_NONFINITE; break; }
+            if (sqrt(rr) <= red_factor * nb) { stop = ST_CONVERGED; break; }
+            if (chk && !finite_d(rzn)) { stop = ST_NONFINITE; break; }
+            if (rzn == 0.0) { stop = ST_BREAKDOWN; break; }
+            const double beta = rzn / rho;
+            rho = rzn;
+            for (int i = tid; i < n; i += B) p[i] = di[i] * r[i] + beta * p[i];
+        }
+        if (stop == ST_RUN) stop = ST_MAX_ITERS;
+        __syncthreads();
+        for (int i = tid; i < n; i += B) xout[r0 + i] = x[i];
+        if (tid == 0) {
+            iters_out[s] = (int)k;
+            rel_out[s] = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+            status_out[s] = (uint8_t)stop;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_jacobi(int64_t rows, const int *__restrict__ rows_sys_local_unused,
+                               const int *__restrict__ rp, const int *__restrict__ col,
+                               const double *__restrict__ val, const int *__restrict__ row_local,
+                               double *__restrict__ dinv, int *__restrict__ bad) {
+    (void)rows_sys_local_unused;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const int li = row_local[i];
+    double d = 0.0;
+    bool found = false;
+    for (int e = rp[i]; e < rp[i + 1]; ++e)
+        if (col[e] == li) { d = val[e]; found = true; }
+    if (found && d != 0.0) dinv[i] = 1.0 / d;
+    else { dinv[i] = 0.0; atomicMin(bad, (int)i); }
+}
+
+__global__ void k_zero_u32(unsigned *p) { *p = 0u; }
+
+mxl_ctx *batch_ctx(const BatchImpl &B) { return B.ctx; }
+
+}  // namespace mxl
+
+using namespace mxl;
+
+namespace {
+
+struct Cand {
+    int B, wpc, order;
+};
+
+size_t lds_bytes_for(int n) { return (size_t)4 * n * sizeof(double); }
+
+hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
+                        const double *b, double *x, int32_t *iters, double *rel, uint8_t *status,
+                        int lds_cap, hipStream_t s, int use_x0 = 0) {
+    const int G = t.wgs_per_cu * Bt.ctx->num_cu;
+    const int *order = (const int *)(t.order ? Bt.order_big->p : Bt.order_input->p);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, (unsigned *)Bt.queue->p);
+    const size_t shm = lds_bytes_for(lds_cap);
+    const int chk = c.nonfinite_check;
+    const double red = c.reduction;
+    const int64_t mif = c.max_iters;
+    double *scr = Bt.scratch ? (double *)Bt.scratch->p : nullptr;
+    const int64_t stride = Bt.scratch ? (int64_t)4 * Bt.max_n : 0;
+#define MXL_BATCH_CASE(BB)                                                                          \
+    case BB:                                                                                        \
+        hipLaunchKernelGGL(k_batch_pcg<BB>, dim3(G), dim3(BB), shm, s, Bt.nsys,                     \
+                           (const int *)Bt.sys_ptr->p, (const int *)Bt.row_ptr->p,                 \
+                           (const int *)Bt.col->p, (const double *)Bt.val->p,                      \
+                           (const double *)Bt.dinv->p, b, x, iters, rel, status, order,            \
+                           (unsigned *)Bt.queue->p, red, mif, 10, chk, lds_cap, scr, stride, use_x0); \
+        break;
+    switch (t.wg_size) {
+        MXL_BATCH_CASE(64) MXL_BATCH_CASE(128) MXL_BATCH_CASE(256) MXL_BATCH_CASE(512) MXL_BATCH_CASE(1024)
+    default: return hipErrorInvalidValue;
+    }
+#undef MXL_BATCH_CASE
+    return hipGetLastError();
+}
+
+// LDS capacity (vector length that fits) for a schedule: all resident
+// workgroups of a CU share its LDS.
+int lds_cap_for(const mxl_ctx *ctx, const BatchImpl &Bt, int wpc) {
+    hipDeviceProp_t prop;
+    size_t per_cu = 160 * 1024, per_wg = 64 * 1024;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        if (prop.maxSharedMemoryPerMultiProcessor > 0) per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        if (prop.sharedMemPerBlock > 0) per_wg = prop.sharedMemPerBlock;
+    }
+    size_t budget = std::min(per_wg, per_cu / (size_t)std::max(1, wpc)) - 2048;  // static LDS headroom
+    int cap = (int)(budget / (4 * sizeof(double)));
+    return std::min(cap, Bt.max_n);
+}
+
+}  // namespace
+
+extern "C" mxl_status mxl_batch_csr_create(mxl_ctx *ctx, int64_t nsys, const int32_t *sys_ptr_host,
+                                           const int32_t *sys_ptr, const int32_t *row_ptr,
+                                           const int32_t *col, const double *val, int flags,
+                                           mxl_op **out) {
+    (void)flags;
+    if (!ctx || !out || !sys_ptr_host || nsys <= 0 || !sys_ptr || !row_ptr || !col || !val)
+        return set_error(MXL_ERR_INVALID_ARG, "batch: NULL argument or nsys <= 0");
+    *out = nullptr;
+    auto Bt = std::make_shared<BatchImpl>();
+    Bt->ctx = ctx;
+    Bt->nsys = nsys;
+    Bt->sys_ptr_h.assign(sys_ptr_host, sys_ptr_host + nsys + 1);
+    if (Bt->sys_ptr_h[0] != 0) return set_error(MXL_ERR_INVALID_MATRIX, "sys_ptr[0] != 0");
+    int max_n = 0;
+    for (int64_t s = 0; s < nsys; ++s) {
+        int n = Bt->sys_ptr_h[s + 1] - Bt->sys_ptr_h[s];
+        if (n <= 0) return set_error(MXL_ERR_INVALID_MATRIX, "every system needs at least one row");
+        max_n = std::max(max_n, n);
+    }
+    Bt->max_n = max_n;
+    Bt->rows = Bt->sys_ptr_h[nsys];
+    hipStream_t s = ctx->stream;
+    int32_t nnz_h = 0;
+    if (hipMemcpyAsync(&nnz_h, row_ptr + Bt->rows, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(MXL_ERR_INVALID_ARG, "row_ptr is not readable device memory");
+    Bt->nnz = nnz_h;
+    mxl_status st;
+    if ((st = check_device_ptr(ctx, sys_ptr, (nsys + 1) * 4, "sys_ptr")) != MXL_OK) return st;
+    if ((st = check_device_ptr(ctx, row_ptr, (Bt->rows + 1) * 4, "row_ptr")) != MXL_OK) return st;
+    if ((st = check_device_ptr(ctx, col, Bt->nnz * 4, "col")) != MXL_OK) return st;
+    if ((st = check_device_ptr(ctx, val, Bt->nnz * 8, "val")) != MXL_OK) return st;
+    auto borrow = [](const void *p, size_t b) {
+        auto d = std::make_shared<DevBuf>();
+        d->p = const_cast<void *>(p);
+        d->bytes = b;
+        return d;
+    };
+    Bt->sys_ptr = borrow(sys_ptr, (nsys + 1) * 4);
+    Bt->row_ptr = borrow(row_ptr, (Bt->rows + 1) * 4);
+    Bt->col = borrow(col, Bt->nnz * 4);
+    Bt->val = borrow(val, Bt->nnz * 8);
+    auto alloc = [](size_t bytes) -> BufPtr {
+        auto d = std::make_shared<DevBuf>();
+        if (hipMalloc(&d->p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        d->bytes = bytes;
+        d->owned = true;
+        return d;
+    };
+    Bt->dinv = alloc(Bt->rows * 8);
+    Bt->order_input = alloc(nsys * 4);
+    Bt->order_big = alloc(nsys * 4);
+    Bt->queue = alloc(64);
+    auto rowloc = alloc(Bt->rows * 4);
+    auto bad = alloc(4);
+    if (!Bt->dinv || !Bt->order_input || !Bt->order_big || !Bt->queue || !rowloc || !bad)
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "batch workspace");
+    std::vector<int32_t> ord(nsys), loc(Bt->rows);
+    std::iota(ord.begin(), ord.end(), 0);
+    if (hipMemcpyAsync(Bt->order_input->p, ord.data(), nsys * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "upload order");
+    std::vector<int32_t> big(ord);
+    std::stable_sort(big.begin(), big.end(), [&](int a, int b) {
+        return Bt->sys_ptr_h[a + 1] - Bt->sys_ptr_h[a] > Bt->sys_ptr_h[b + 1] - Bt->sys_ptr_h[b];
+    });
+    for (int64_t sy = 0; sy < nsys; ++sy)
+        for (int32_t r = Bt->sys_ptr_h[sy]; r < Bt->sys_ptr_h[sy + 1]; ++r) loc[r] = r - Bt->sys_ptr_h[sy];
+    int init = INT_MAX;
+    if (hipMemcpyAsync(Bt->order_big->p, big.data(), nsys * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(rowloc->p, loc.data(), Bt->rows * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(bad->p, &init, 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "upload batch tables");
+    hipLaunchKernelGGL(k_batch_jacobi, dim3((unsigned)((Bt->rows + 255) / 256)), dim3(256), 0, s, Bt->rows,
+                       nullptr, (const int *)row_ptr, col, val, (const int *)rowloc->p,
+                       (double *)Bt->dinv->p, (int *)bad->p);
+    int badh = INT_MAX;
+    if (hipMemcpyAsync(&badh, bad->p, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "batch jacobi");
+    if (badh != INT_MAX)
+        return set_error(MXL_ERR_ZERO_DIAG, "row " + std::to_string(badh) + " has a missing or zero diagonal");
+    auto *op = new mxl_op;
+    op->kind = MXL_OP_BATCH;
+    op->bat = Bt;
+    *out = op;
+    return MXL_OK;
+}
+
+static const BatchImpl *batch_of(const mxl_op *op) {
+    return op && op->kind == MXL_OP_BATCH ? op->bat.get() : nullptr;
+}
+
+static mxl_status batch_args(const BatchImpl &Bt, const double *b, double *x, const int32_t *iters,
+                             const double *rel, const uint8_t *status) {
+    mxl_status st;
+    const mxl_ctx *c = Bt.ctx;
+    if ((st = check_device_ptr(c, b, Bt.rows * 8, "b")) != MXL_OK) return st;
+    if ((st = check_device_ptr(c, x, Bt.rows * 8, "x")) != MXL_OK) return st;
+    if ((st = check_device_ptr(c, iters, Bt.nsys * 4, "iters")) != MXL_OK) return st;
+    if ((st = check_device_ptr(c, rel, Bt.nsys * 8, "rel_res")) != MXL_OK) return st;
+    if ((st = check_device_ptr(c, status, Bt.nsys, "status")) != MXL_OK) return st;
+    if ((const void *)b == (const void *)x) return set_error(MXL_ERR_INVALID_ARG, "b and x alias");
+    return MXL_OK;
+}
+
+static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
+                               const double *b, double *x, int32_t *iters, double *rel,
+                               uint8_t *status) {
+    if (t.wg_size != 64 && t.wg_size != 128 && t.wg_size != 256 && t.wg_size != 512 && t.wg_size != 1024)
+        return set_error(MXL_ERR_INVALID_ARG, "wg_size must be 64, 128, 256, 512 or 1024");
+    if (t.wgs_per_cu < 1 || t.wgs_per_cu > 32 || (t.order != 0 && t.order != 1))
+        return set_error(MXL_ERR_INVALID_ARG, "wgs_per_cu in 1..32, order 0 or 1");
+    const int cap = lds_cap_for(Bt.ctx, Bt, t.wgs_per_cu);
+    if (cap < 1) return set_error(MXL_ERR_INVALID_ARG, "schedule leaves no LDS per workgroup");
+    if (cap < Bt.max_n) {  // systems above cap run from a global scratch slice per workgroup
+        const int64_t need = (int64_t)t.wgs_per_cu * Bt.ctx->num_cu * 4 * Bt.max_n;
+        if (Bt.scratch_elems < need) {
+            auto d = std::make_shared<DevBuf>();
+            if (hipMalloc(&d->p, need * 8) != hipSuccess) return set_error(MXL_ERR_OUT_OF_MEMORY, "batch scratch");
+            d->bytes = need * 8;
+            d->owned = true;
+            Bt.scratch = d;
+            Bt.scratch_elems = need;
+        }
+    }
+    const size_t shm = lds_bytes_for(cap);
+    hipError_t e = hipSuccess;
+    if (shm > 64 * 1024) {
+        switch (t.wg_size) {
+        case 64: e = hipFuncSetAttribute((const void *)k_batch_pcg<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
+        case 128: e = hipFuncSetAttribute((const void *)k_batch_pcg<128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
+        case 256: e = hipFuncSetAttribute((const void *)k_batch_pcg<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
+        case 512: e = hipFuncSetAttribute((const void *)k_batch_pcg<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
+        default: e = hipFuncSetAttribute((const void *)k_batch_pcg<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
+        }
+        if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
+    }
+    e = launch_batch(Bt, t, c, b, x, iters, rel, status, cap, Bt.ctx->stream);
+    if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+    return MXL_OK;
+}
+
+static mxl_tuning default_tuning() {
+    mxl_tuning t;
+    t.wg_size = 256;
+    t.wgs_per_cu = 2;
+    t.order = 0;
+    return t;
+}
+
+extern "C" mxl_status mxl_batch_solve(const mxl_op *Bop, const mxl_criteria *crit, const mxl_tuning *tuning,
+                                      const double *b, double *x, int32_t *iters, double *rel_res,
+                                      uint8_t *status) {
+    BatchImpl *Bt = const_cast<BatchImpl *>(batch_of(Bop));
+    if (!Bt || !crit) return set_error(MXL_ERR_INVALID_ARG, "batch operator and criteria required");
+    if (!(crit->reduction >= 0.0)) return set_error(MXL_ERR_INVALID_ARG, "reduction must be >= 0");
+    mxl_status st;
+    if ((st = batch_args(*Bt, b, x, iters, rel_res, status)) != MXL_OK) return st;
+    mxl_tuning t = tuning ? *tuning : (Bt->tuned ? Bt->best : default_tuning());
+    if ((st = run_schedule(*Bt, t, *crit, b, x, iters, rel_res, status)) != MXL_OK) return st;
+    if (hipStreamSynchronize(Bt->ctx->stream) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "batched solve");
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_batch_autotune(const mxl_op *Bop, const mxl_criteria *crit, const double *b,
+                                         double *x_scratch, int reps, mxl_tuning *best_out,
+                                         double *best_ms) {
+    BatchImpl *Bt = const_cast<BatchImpl *>(batch_of(Bop));
+    if (!Bt || !crit || reps < 1) return set_error(MXL_ERR_INVALID_ARG, "batch operator, criteria, reps >= 1");
+    mxl_status st;
+    if ((st = check_device_ptr(Bt->ctx, b, Bt->rows * 8, "b")) != MXL_OK) return st;
+    if ((st = check_device_ptr(Bt->ctx, x_scratch, Bt->rows * 8, "x_scratch")) != MXL_OK) return st;
+    hipStream_t s = Bt->ctx->stream;
+    void *it = nullptr, *rl = nullptr, *stt = nullptr;
+    if (hipMalloc(&it, Bt->nsys * 4) != hipSuccess || hipMalloc(&rl, Bt->nsys * 8) != hipSuccess ||
+        hipMalloc(&stt, Bt->nsys) != hipSuccess) {
+        (void)hipFree(it); (void)hipFree(rl); (void)hipFree(stt);
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "autotune buffers");
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e300;
+    mxl_tuning bt = default_tuning();
+    st = MXL_OK;
+    for (int B : {64, 128, 256, 512}) {
+        for (int wpc : {1, 2, 4, 8}) {
+            if (B * wpc > 2048) continue;  // at most 32 waves per CU
+            for (int ord : {0, 1}) {
+                mxl_tuning t{B, wpc, ord};
+                std::vector<float> ts;
+                for (int r = 0; r < reps + 1 && st == MXL_OK; ++r) {
+                    (void)hipEventRecord(e0, s);
+                    st = run_schedule(*Bt, t, *crit, b, x_scratch, (int32_t *)it, (double *)rl, (uint8_t *)stt);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (r > 0) ts.push_back(ms);  // the first run warms caches
+                }
+                if (st != MXL_OK) break;
+                std::sort(ts.begin(), ts.end());
+                double med = ts[ts.size() / 2];
+                if (med < best) { best = med; bt = t; }
+            }
+            if (st != MXL_OK) break;
+        }
+        if (st != MXL_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(it); (void)hipFree(rl); (void)hipFree(stt);
+    if (st != MXL_OK) return st;
+    Bt->best = bt;
+    Bt->tuned = true;
+    if (best_out) *best_out = bt;
+    if (best_ms) *best_ms = best;
+    return MXL_OK;
+}
+
+namespace mxl {
+
+// A single system (a solver's matrix) viewed as a batch of one, for the
+// one-launch CG path of small systems.
+std::shared_ptr<BatchImpl> batch_from_matrix(const MatrixImpl &A, const void *dinv) {
+    auto Bt = std::make_shared<BatchImpl>();
+    Bt->ctx = A.ctx;
+    Bt->nsys = 1;
+    Bt->rows = A.nrows;
+    Bt->nnz = A.nnz;
+    Bt->sys_ptr_h = {0, (int32_t)A.nrows};
+    Bt->max_n = (int)A.nrows;
+    Bt->row_ptr = A.row_ptr;
+    Bt->col = A.col;
+    Bt->val = A.val;
+    auto alloc = [](size_t bytes) -> BufPtr {
+        auto d = std::make_shared<DevBuf>();
+        if (hipMalloc(&d->p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+        d->bytes = bytes;
+        d->owned = true;
+        return d;
+    };
+    Bt->sys_ptr = alloc(8);
+    Bt->order_input = alloc(4);
+    Bt->order_big = Bt->order_input;
+    Bt->queue = alloc(64);
+    Bt->scratch = nullptr;
+    if (!Bt->sys_ptr || !Bt->order_input || !Bt->queue) return nullptr;
+    if (dinv) {
+        Bt->dinv = std::make_shared<DevBuf>();
+        Bt->dinv->p = const_cast<void *>(dinv);
+        Bt->dinv->bytes = A.nrows * 8;
+    } else {
+        Bt->dinv = alloc(A.nrows * 8);
+        if (!Bt->dinv || launch_fill(MXL_F64, A.nrows, 1.0, Bt->dinv->p, A.ctx->stream) != hipSuccess) return nullptr;
+    }
+    int32_t sp[2] = {0, (int32_t)A.nrows}, z = 0;
+    if (hipMemcpyAsync(Bt->sys_ptr->p, sp, 8, hipMemcpyHostToDevice, A.ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(Bt->order_input->p, &z, 4, hipMemcpyHostToDevice, A.ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(A.ctx->stream) != hipSuccess)
+        return nullptr;
+    return Bt;
+}
+
+// The whole CG of one system in one workgroup (x holds the initial guess).
+mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x,
+                              void *out3, int64_t *iters, double *rel, int *stop) {
+    mxl_tuning t{1024, 1, 0};
+    const int cap = lds_cap_for(Bt.ctx, Bt, 1);
+    if (cap < Bt.max_n && !Bt.scratch) {
+        auto d = std::make_shared<DevBuf>();
+        if (hipMalloc(&d->p, (size_t)Bt.ctx->num_cu * 4 * Bt.max_n * 8) != hipSuccess)
+            return set_error(MXL_ERR_OUT_OF_MEMORY, "single-launch scratch");
+        d->bytes = (size_t)Bt.ctx->num_cu * 4 * Bt.max_n * 8;
+        d->owned = true;
+        Bt.scratch = d;
+        Bt.scratch_elems = (int64_t)Bt.ctx->num_cu * 4 * Bt.max_n;
+    }
+    const size_t shm = lds_bytes_for(cap);
+    if (shm > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)k_batch_pcg<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "LDS attribute");
+    int32_t *dit = (int32_t *)out3;
+    double *drel = (double *)((char *)out3 + 8);
+    uint8_t *dst = (uint8_t *)((char *)out3 + 16);
+    hipError_t e = launch_batch(Bt, t, c, b, x, dit, drel, dst, cap, Bt.ctx->stream, 1);
+    if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("single-launch CG: ") + hipGetErrorString(e));
+    char h[24];
+    if (hipMemcpyAsync(h, out3, 24, hipMemcpyDeviceToHost, Bt.ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(Bt.ctx->stream) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "single-launch read-back");
+    int32_t it;
+    memcpy(&it, h, 4);
+    memcpy(rel, h + 8, 8);
+    *iters = it;
+    *stop = (uint8_t)h[16];
+    return MXL_OK;
+}
+
+}  // namespace mxl

@@ -49,19 +49,24 @@ struct SolverState {
     int32_t half;     // BiCGSTAB: 1 if it stopped at a half step
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that XCD
-// x receives the contiguous logical range [x*q, (x+1)*q): neighbouring tiles
-// (and their shared x-vector window) then live in one L2.
-__device__ __forceinline__ int xcd_logical(int bid, int G) {
-    int q = G / kNumXcd;
-    if (bid < q * kNumXcd) return (bid % kNumXcd) * q + bid / kNumXcd;
-    return bid;
-}
-
-// [lo, hi) share of `total` items for logical workgroup L of G.
-__device__ __forceinline__ void share_range(int64_t total, int L, int G, int64_t &lo, int64_t &hi) {
-    lo = total * L / G;
-    hi = total * (L + 1) / G;
+// Tile walk of workgroup `bid` of G over T tiles.  Workgroups are
+// dispatched round-robin over the 8 XCDs (bid % 8); XCD x owns one
+// contiguous band of tiles, proportional to its workgroup count, and its
+// workgroups walk that band interleaved (first = band start + bid / 8,
+// step = workgroups on the XCD).  Each XCD's resident workgroups therefore
+// sweep one compact region at a time: the x window they gather stays in that
+// XCD's L2 and the streamed matrix arrays are read as a few dense fronts.
+// Every tile is visited exactly once.
+__device__ __forceinline__ void band_walk(int64_t T, int bid, int G, int64_t &first, int64_t &end,
+                                          int &step) {
+    const int x = bid % kNumXcd, j = bid / kNumXcd;
+    const int q = G / kNumXcd, rem = G % kNumXcd;
+    const int cnt = q + (x < rem ? 1 : 0);
+    const int before = x * q + (x < rem ? x : rem);
+    const int64_t lo = T * before / G, hi = T * (before + cnt) / G;
+    first = lo + j;
+    end = hi;
+    step = cnt;
 }
 
 template <typename T>

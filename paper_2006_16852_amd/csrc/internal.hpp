@@ -53,6 +53,7 @@ struct MatrixImpl {
     BufPtr coo_row;                    // COO
     BufPtr ell_col, ell_val, ell_win;  // ELL / HYB ELL part
     int ell_w = 0;
+    int ell_rpt = 1;                   // ELL rows per thread (1, 2, 4)
     int64_t n_pad = 0;
     double hyb_q = 0.0;
     BufPtr tail_row, tail_col, tail_val;  // HYB COO tail
@@ -70,6 +71,7 @@ struct JacobiImpl {
 };
 
 struct IrImpl;
+struct BatchImpl;
 
 struct SolverImpl {
     int kind = MXL_SOLVER_CG;
@@ -83,6 +85,8 @@ struct SolverImpl {
     BufPtr hist;      // max_iters + 1 doubles
     int64_t hist_len = 0;
     std::shared_ptr<IrImpl> ir;  // iterative refinement only
+    std::shared_ptr<BatchImpl> single;  // one-launch CG of a small system
+    BufPtr single_out;                  // iterations, residual, status
 };
 
 struct IrImpl {
@@ -94,6 +98,10 @@ struct IrImpl {
 };
 
 struct BatchImpl;  // batched.hip
+mxl_ctx *batch_ctx(const BatchImpl &B);
+std::shared_ptr<BatchImpl> batch_from_matrix(const MatrixImpl &A, const void *dinv);
+mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x,
+                              void *out3, int64_t *iters, double *rel, int *stop);
 
 struct SpmvArgs {
     double alpha = 1.0, beta = 0.0;
@@ -163,6 +171,12 @@ hipError_t ir_scale_to_f32(int64_t n, const double *r, const SolverState *st, fl
                            hipStream_t s);
 hipError_t ir_correct(int64_t n, double *x, const float *d, const SolverState *st, hipStream_t s);
 hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
+hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a, const double *b,
+                         double *c, hipStream_t s);
+
+// ------------------------------------------------------------- runtime.hip
+mxl_status set_error(mxl_status st, const std::string &msg);
+mxl_status check_device_ptr(const mxl_ctx *ctx, const void *p, size_t bytes, const char *what);
 
 // ------------------------------------------------------------- features.hip / mlp.hip
 mxl_status features_compute(const MatrixImpl &A, double out[16]);

@@ -15,10 +15,16 @@ namespace mxl {
 
 // Contiguous [i0, i1) range of logical workgroup L, walked 256 at a time so
 // each wave's accesses are coalesced.
-#define MXL_RANGE(n)                                   \
-    const int L = xcd_logical(blockIdx.x, gridDim.x);  \
-    int64_t i0, i1;                                    \
-    share_range((n), L, gridDim.x, i0, i1);
+#define MXL_RANGE(n)                                                 \
+    const int L = blockIdx.x;                                        \
+    int64_t tb_, te_;                                                \
+    int ts_;                                                         \
+    band_walk(((n) + kWG - 1) / kWG, blockIdx.x, gridDim.x, tb_, te_, ts_);
+
+// Element loop of one workgroup over its tiles of 256 (see band_walk).
+#define MXL_FOR(i, n)                                   \
+    for (int64_t t_ = tb_; t_ < te_; t_ += ts_)         \
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < (n))
 
 #define MXL_LEAD (blockIdx.x == 0 && threadIdx.x == 0)
 
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict_
                                                  double *__restrict__ parts) {
     MXL_RANGE(n)
     double rz = 0.0, rr = 0.0, bb = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         V ri = r[i];
         double z = prec_z(dinv, i, ri);
         p[i] = (V)z;
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ x,
     }
     MXL_RANGE(n)
     double rz = 0.0, rr = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         V xi, ri;
         if constexpr (sizeof(V) == 8) {
             xi = x[i] + alpha * p[i];
@@ -138,7 +144,7 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, const V *__restri
     }
     if (stop != ST_RUN) return;
     MXL_RANGE(n)
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG)
+    MXL_FOR(i, n)
         p[i] = (V)(prec_z(dinv, i, r[i]) + beta * (double)p[i]);
 }
 
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(kWG) void k_bi_init(int64_t n, const V *__restrict_
                                                  double *__restrict__ parts) {
     MXL_RANGE(n)
     double rr = 0.0, bb = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         V ri = r[i];
         rhat[i] = ri;
         p[i] = (V)0;
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
     }
     if (stop != ST_RUN) return;
     MXL_RANGE(n)
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         V pi = (V)((double)r[i] + beta * ((double)p[i] - omega_prev * (double)v[i]));
         p[i] = pi;
         phat[i] = (V)prec_z(dinv, i, pi);
@@ -235,7 +241,7 @@ __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restri
     if (MXL_LEAD) st->alpha = alpha;
     MXL_RANGE(n)
     double ss = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         V si = (V)((double)r[i] - alpha * (double)v[i]);
         s[i] = si;
         shat[i] = (V)prec_z(dinv, i, si);
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(kWG) void k_bi_tdots(int64_t n, const V *__restrict
     }
     MXL_RANGE(n)
     double ts = 0.0, tt = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         double ti = (double)t[i];
         ts += ti * (double)s[i];
         tt += ti * ti;
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x
     if (mode == ST_HALF) {
         if (st->iters != k) return;
         MXL_RANGE(n)
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG)
+        MXL_FOR(i, n)
             x[i] = (V)((double)x[i] + alpha * (double)phat[i]);
         return;
     }
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x
     if (MXL_LEAD) st->omega = omega;
     MXL_RANGE(n)
     double rr = 0.0, rhr = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         x[i] = (V)((double)x[i] + alpha * (double)phat[i] + omega * (double)shat[i]);
         V ri = (V)((double)s[i] - omega * (double)t[i]);
         r[i] = ri;
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(kWG) void k_ir_norms(int64_t n, const double *__res
                                                   double *__restrict__ parts) {
     MXL_RANGE(n)
     double rr = 0.0, mx = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kWG) {
+    MXL_FOR(i, n) {
         double v = r[i];
         rr += v * v;
         double a = fabs(v);
@@ -391,6 +397,51 @@ __global__ void k_ir_correct(int64_t n, double *__restrict__ x, const float *__r
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         x[i] += s * (double)d[i];
+}
+
+// STREAM-style reference kernels: b = a, c = a + alpha*b, and a.b, with
+// 16-byte accesses, walked like every other streaming kernel (band_walk).
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(kWG) void k_stream_copy(int64_t n2, const dvec2 *__restrict__ a,
+                                                     dvec2 *__restrict__ b) {
+    MXL_RANGE(n2)
+    MXL_FOR(i, n2) b[i] = __builtin_nontemporal_load(a + i);
+}
+
+__global__ __launch_bounds__(kWG) void k_stream_triad(int64_t n2, const dvec2 *__restrict__ a,
+                                                      const dvec2 *__restrict__ b, double alpha,
+                                                      dvec2 *__restrict__ c) {
+    MXL_RANGE(n2)
+    MXL_FOR(i, n2) {
+        dvec2 x = __builtin_nontemporal_load(a + i), y = __builtin_nontemporal_load(b + i);
+        c[i] = x + alpha * y;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_stream_dot(int64_t n2, const dvec2 *__restrict__ a,
+                                                    const dvec2 *__restrict__ b,
+                                                    double *__restrict__ parts) {
+    MXL_RANGE(n2)
+    double acc = 0.0;
+    MXL_FOR(i, n2) {
+        dvec2 x = __builtin_nontemporal_load(a + i), y = __builtin_nontemporal_load(b + i);
+        acc += x.x * y.x + x.y * y.y;
+    }
+    double v[1] = {acc};
+    publish<1>(v, parts, L);
+}
+
+hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a, const double *b,
+                         double *c, hipStream_t s) {
+    const int64_t n2 = n / 2;
+    const int G = ctx->num_cu * 8;
+    switch (op) {
+    case 0: hipLaunchKernelGGL(k_stream_copy, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a, (dvec2 *)c); break;
+    case 1: hipLaunchKernelGGL(k_stream_triad, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a, (const dvec2 *)b, 0.5, (dvec2 *)c); break;
+    case 2: hipLaunchKernelGGL(k_stream_dot, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a, (const dvec2 *)b, c); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 __global__ void k_flush(int4 *buf, int64_t n, int v) {

@@ -159,7 +159,7 @@ mxl_status build_merge(MatrixImpl &A) {
 
 mxl_status build_ell_windows(MatrixImpl &A) {
     hipError_t e;
-    int64_t nt = (A.nrows + kWG - 1) / kWG;
+    int64_t nt = (A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt);
     A.ell_win = alloc((size_t)(nt > 0 ? nt : 1) * sizeof(int2), &e);
     if (!A.ell_win) return hip_fail(e, "alloc ell windows");
     HIP_TRY(launch_ell_windows(A, (int2 *)A.ell_win->p, A.ctx->stream));
@@ -171,6 +171,13 @@ double elapsed_s(std::chrono::steady_clock::time_point t0) {
 }
 
 }  // namespace
+
+namespace mxl {
+mxl_status set_error(mxl_status st, const std::string &msg) { return fail(st, msg); }
+mxl_status check_device_ptr(const mxl_ctx *ctx, const void *p, size_t bytes, const char *what) {
+    return check_dev(ctx, p, bytes, what);
+}
+}  // namespace mxl
 
 // ================================================================== ABI
 
@@ -362,6 +369,9 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
             return fail(MXL_ERR_INFEASIBLE_FORMAT, "ELL storage would exceed min(4x CSR bytes, 32 GiB)");
         A->ell_w = w;
         A->n_pad = n_pad;
+        A->ell_rpt = prm.vector_width > 0 ? prm.vector_width : 2;
+        if (A->ell_rpt != 1 && A->ell_rpt != 2 && A->ell_rpt != 4)
+            return fail(MXL_ERR_INVALID_ARG, "ELL rows per thread (vector_width) must be 1, 2 or 4");
         A->ell_col = alloc((size_t)w * n_pad * 4, &e);
         A->ell_val = alloc((size_t)w * n_pad * vt, &e);
         if (!A->ell_col || !A->ell_val) return hip_fail(hipErrorOutOfMemory, "alloc ell");
@@ -539,9 +549,10 @@ mxl_status mxl_op_destroy(mxl_op *op) {
     const MatrixImpl *A = op->kind == MXL_OP_MATRIX ? op->mat.get()
                           : op->kind == MXL_OP_JACOBI ? op->jac->A.get()
                           : op->kind == MXL_OP_SOLVER ? op->sol->A.get() : nullptr;
-    if (A) {  // queued work may still use the arrays
-        DeviceScope ds(A->ctx->device);
-        (void)hipStreamSynchronize(A->ctx->stream);
+    mxl_ctx *ctx = A ? A->ctx : op->kind == MXL_OP_BATCH ? batch_ctx(*op->bat) : nullptr;
+    if (ctx) {  // queued work may still use the arrays
+        DeviceScope ds(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
     }
     delete op;
     return MXL_OK;
@@ -727,7 +738,44 @@ int map_stop(int s) {
 
 double *region(const SolverImpl &S, int r) { return (double *)S.partials->p + (size_t)r * kSolverSlots * 3; }
 
+constexpr int64_t kSingleAutoN = 8192;   // auto: one persistent workgroup up to this size
+constexpr int64_t kSingleMaxN = 16384;
+
+bool single_launch_ok(const SolverImpl &S, const mxl_solve_info *info) {
+    const mxl_criteria &c = S.crit;
+    if (S.kind != MXL_SOLVER_CG || S.A->dtype != MXL_F64 || c.launch_mode == 1) return false;
+    if (c.max_iters < 1 || c.time_limit_s > 0 || S.A->nrows > kSingleMaxN) return false;
+    if (info && ((info->history && info->history_cap > 0) || info->time_spmv)) return false;
+    return c.launch_mode == 2 || S.A->nrows <= kSingleAutoN;
+}
+
+mxl_status solve_cg_single(SolverImpl &S, const void *b, void *x, mxl_solve_info *info) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!S.single) {
+        S.single = batch_from_matrix(*S.A, S.P ? S.P->dinv->p : nullptr);
+        hipError_t e;
+        S.single_out = alloc(64, &e);
+        if (!S.single || !S.single_out) return fail(MXL_ERR_OUT_OF_MEMORY, "single-launch workspace");
+    }
+    int64_t iters = 0;
+    double rel = 0.0;
+    int stop = 0;
+    mxl_status st = batch_single_solve(*S.single, S.crit, (const double *)b, (double *)x, S.single_out->p,
+                                       &iters, &rel, &stop);
+    if (st != MXL_OK) return st;
+    if (info) {
+        info->iterations = iters;
+        info->spmv_count = 1 + iters;
+        info->rel_residual = rel;
+        info->stop_reason = stop == ST_MAX_ITERS ? MXL_STOP_MAX_ITERS : map_stop(stop);
+        info->seconds = elapsed_s(t0);
+        info->inner_iterations = 0;
+    }
+    return MXL_OK;
+}
+
 mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info *info) {
+    if (single_launch_ok(S, info)) return solve_cg_single(const_cast<SolverImpl &>(S), b, x, info);
     auto t0 = std::chrono::steady_clock::now();
     const MatrixImpl &A = *S.A;
     mxl_ctx *ctx = A.ctx;
@@ -1053,6 +1101,41 @@ extern "C" mxl_status mxl_time_apply(const mxl_op *Aop, const void *x, void *y, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return hip_fail(err, "time_apply");
+    std::sort(ts.begin(), ts.end());
+    size_t m = ts.size();
+    *median_ms = m % 2 ? ts[m / 2] : 0.5 * (ts[m / 2 - 1] + ts[m / 2]);
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_stream_bench(mxl_ctx *ctx, int op, int64_t n, const double *a,
+                                       const double *b, double *c, int reps, double *median_ms) {
+    if (!ctx || !median_ms || reps < 1 || n < 2 || (n & 1) || op < 0 || op > 2)
+        return fail(MXL_ERR_INVALID_ARG, "stream: op in 0..2, even n >= 2, reps >= 1");
+    DeviceScope ds(ctx->device);
+    mxl_status st;
+    const size_t bytes = (size_t)n * 8;
+    if ((st = check_dev(ctx, a, bytes, "a")) != MXL_OK) return st;
+    if (op != 0 && (st = check_dev(ctx, b, bytes, "b")) != MXL_OK) return st;
+    const size_t cbytes = op == 2 ? (size_t)ctx->num_cu * 8 * 8 : bytes;
+    if ((st = check_dev(ctx, c, cbytes, "c")) != MXL_OK) return st;
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::vector<double> ts;
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess) err = launch_stream(ctx, op, n, a, b, c, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        ts.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err, "stream");
     std::sort(ts.begin(), ts.end());
     size_t m = ts.size();
     *median_ms = m % 2 ? ts[m / 2] : 0.5 * (ts[m / 2 - 1] + ts[m / 2]);

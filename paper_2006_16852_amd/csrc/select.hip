@@ -1,0 +1,476 @@
+// select.hip -- the format/kernel selector's device work: the 16 structural
+// features of a CSR matrix, and a small FP32 multilayer perceptron with its
+// forward pass, gradient and Adam step, so the selector is trained on the
+// GPU by this library's own kernels.  The selector stands in for the
+// paper's runtime "kernel variant selection" fork (Sec. 7.2), and its quality
+// is judged with the performance-profile view of Sec. 7.3.
+//
+// Features use exact integer statistics: sums of len, len^2, len^3, |i-j|,
+// counts and extrema are accumulated as 64-bit integers (order-independent,
+// hence deterministic); quantiles come from a row-length histogram.  The
+// host turns the exact integers into the 16 FP64 values.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace mxl {
+
+struct FeatAcc {
+    unsigned long long s2, s3, above, sumbw, near;
+    int maxlen, minlen, maxbw, pad;
+};
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Row statistics: thread per row (grid-stride); wave partials combined with
+// 64-bit integer atomics (exact, so the order does not matter).
+__global__ __launch_bounds__(kWG) void k_features(int64_t n, int64_t nnz, const int *__restrict__ rp,
+                                                  const int *__restrict__ col,
+                                                  FeatAcc *__restrict__ acc,
+                                                  unsigned *__restrict__ hist) {
+    unsigned long long s2 = 0, s3 = 0, above = 0, sumbw = 0, near = 0;
+    int maxlen = 0, minlen = INT_MAX, maxbw = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int a = rp[i], b = rp[i + 1];
+        const unsigned long long len = (unsigned long long)(b - a);
+        s2 += len * len;
+        s3 += len * len * len;
+        if ((int64_t)len * n > 2 * nnz) ++above;
+        maxlen = max(maxlen, (int)len);
+        minlen = min(minlen, (int)len);
+        atomicAdd(hist + len, 1u);
+        for (int e = a; e < b; ++e) {
+            long long d = (long long)col[e] - i;
+            d = d < 0 ? -d : d;
+            sumbw += (unsigned long long)d;
+            near += d <= 64;
+            maxbw = max(maxbw, (int)d);
+        }
+    }
+    s2 = wave_sum_u64(s2);
+    s3 = wave_sum_u64(s3);
+    above = wave_sum_u64(above);
+    sumbw = wave_sum_u64(sumbw);
+    near = wave_sum_u64(near);
+    maxlen = wave_max_i(maxlen);
+    minlen = wave_min_i(minlen);
+    maxbw = wave_max_i(maxbw);
+    if (threadIdx.x % kWave == 0) {
+        atomicAdd(&acc->s2, s2);
+        atomicAdd(&acc->s3, s3);
+        atomicAdd(&acc->above, above);
+        atomicAdd(&acc->sumbw, sumbw);
+        atomicAdd(&acc->near, near);
+        atomicMax(&acc->maxlen, maxlen);
+        atomicMin(&acc->minlen, minlen);
+        atomicMax(&acc->maxbw, maxbw);
+    }
+}
+
+__global__ void k_row_maxlen(int64_t n, const int *__restrict__ rp, int *__restrict__ out) {
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, rp[i + 1] - rp[i]);
+    m = wave_max_i(m);
+    if (threadIdx.x % kWave == 0) atomicMax(out, m);
+}
+
+// ------------------------------------------------------------------ MLP
+// Layer l maps dims[l] -> dims[l+1]; theta packs W_l (row-major) then b_l.
+// One workgroup per sample runs the forward pass and back-propagation in
+// LDS and writes that sample's gradient contribution; a second kernel sums
+// the contributions over samples in index order (deterministic) and adds
+// the weight-decay term.  Widths are at most kMlpMaxW.
+constexpr int kMlpMaxW = 64;
+constexpr int kMlpMaxL = 6;
+
+struct MlpShape {
+    int nl;
+    int dims[kMlpMaxL + 1];
+    int off[kMlpMaxL];  // parameter offset of W_l
+    int nparams;
+};
+
+__global__ __launch_bounds__(kWave) void k_mlp_sample(MlpShape sh, const float *__restrict__ theta,
+                                                      const float *__restrict__ X,
+                                                      const float *__restrict__ T,
+                                                      const float *__restrict__ M, float inv_msum,
+                                                      float *__restrict__ Y, float *__restrict__ gs,
+                                                      float *__restrict__ loss_s, int want_grad) {
+    __shared__ float act[kMlpMaxL + 1][kMlpMaxW];  // activations a_0..a_L
+    __shared__ float pre[kMlpMaxL + 1][kMlpMaxW];  // pre-activations h_1..h_L
+    __shared__ float dh[2][kMlpMaxW];
+    const int smp = blockIdx.x, t = threadIdx.x;
+    const int L = sh.nl;
+    if (t < sh.dims[0]) act[0][t] = X[(int64_t)smp * sh.dims[0] + t];
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+        const int din = sh.dims[l], dout = sh.dims[l + 1];
+        const float *W = theta + sh.off[l];
+        const float *bb = W + dout * din;
+        if (t < dout) {
+            float a = bb[t];
+            for (int j = 0; j < din; ++j) a += W[t * din + j] * act[l][j];
+            pre[l + 1][t] = a;
+            act[l + 1][t] = (l < L - 1) ? fmaxf(a, 0.f) : a;
+        }
+        __syncthreads();
+    }
+    const int C = sh.dims[L];
+    float le = 0.f;
+    if (t < C) {
+        const float yv = act[L][t];
+        if (Y) Y[(int64_t)smp * C + t] = yv;
+        if (T) {
+            const float e = yv - T[(int64_t)smp * C + t];
+            const float m = M[(int64_t)smp * C + t];
+            le = m * e * e;
+            dh[L & 1][t] = 2.f * m * e * inv_msum;
+        }
+    }
+    if (loss_s) {
+        float v = le;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+        if (t == 0) loss_s[smp] = v;
+    }
+    if (!want_grad) return;
+    __syncthreads();
+    float *g = gs + (int64_t)smp * sh.nparams;
+    for (int l = L - 1; l >= 0; --l) {
+        const int din = sh.dims[l], dout = sh.dims[l + 1];
+        const float *W = theta + sh.off[l];
+        float *gW = g + sh.off[l];
+        float *gb = gW + dout * din;
+        const float *d = dh[(l + 1) & 1];
+        for (int idx = t; idx < dout * din; idx += kWave) gW[idx] = d[idx / din] * act[l][idx % din];
+        if (t < dout) gb[t] = d[t];
+        if (l > 0 && t < din) {
+            float a = 0.f;
+            for (int o = 0; o < dout; ++o) a += W[o * din + t] * d[o];
+            dh[l & 1][t] = pre[l][t] > 0.f ? a : 0.f;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_mlp_reduce(MlpShape sh, int64_t nsamples, const float *__restrict__ theta,
+                             const float *__restrict__ gs, float lambda, float *__restrict__ grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= sh.nparams) return;
+    float s = 0.f;
+    for (int64_t k = 0; k < nsamples; ++k) s += gs[k * sh.nparams + j];
+    // weight decay on W entries only
+    bool is_w = false;
+    for (int l = 0; l < sh.nl; ++l) {
+        const int w0 = sh.off[l], w1 = w0 + sh.dims[l] * sh.dims[l + 1];
+        if (j >= w0 && j < w1) is_w = true;
+    }
+    grad[j] = s + (is_w ? 2.f * lambda * theta[j] : 0.f);
+}
+
+__global__ void k_adam(int n, float *__restrict__ theta, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.f - b1) * gj;
+    const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    theta[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+}  // namespace mxl
+
+using namespace mxl;
+
+// ================================================================== host
+namespace mxl {
+
+mxl_status features_compute(const MatrixImpl &A, double out[16]) {
+    mxl_ctx *ctx = A.ctx;
+    hipStream_t s = ctx->stream;
+    for (int j = 0; j < 16; ++j) out[j] = 0.0;
+    const int64_t n = A.nrows, nnz = A.nnz;
+    if (n == 0) return MXL_OK;
+    void *dmax = nullptr, *dacc = nullptr, *dhist = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(dmax);
+        (void)hipFree(dacc);
+        (void)hipFree(dhist);
+    };
+    if (hipMalloc(&dmax, 4) != hipSuccess || hipMalloc(&dacc, sizeof(FeatAcc)) != hipSuccess) {
+        cleanup();
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "features workspace");
+    }
+    const unsigned G = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    int zero = 0;
+    FeatAcc init{};
+    init.minlen = INT_MAX;
+    if (hipMemcpyAsync(dmax, &zero, 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(dacc, &init, sizeof init, hipMemcpyHostToDevice, s) != hipSuccess) {
+        cleanup();
+        return set_error(MXL_ERR_DEVICE, "features init");
+    }
+    hipLaunchKernelGGL(k_row_maxlen, dim3(G), dim3(256), 0, s, n, (const int *)A.row_ptr->p, (int *)dmax);
+    int maxlen = 0;
+    if (hipMemcpyAsync(&maxlen, dmax, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        return set_error(MXL_ERR_DEVICE, "features max length");
+    }
+    if (hipMalloc(&dhist, (size_t)(maxlen + 1) * 4) != hipSuccess ||
+        hipMemsetAsync(dhist, 0, (size_t)(maxlen + 1) * 4, s) != hipSuccess) {
+        cleanup();
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "features histogram");
+    }
+    hipLaunchKernelGGL(k_features, dim3(G), dim3(256), 0, s, n, nnz, (const int *)A.row_ptr->p,
+                       (const int *)A.col->p, (FeatAcc *)dacc, (unsigned *)dhist);
+    FeatAcc h;
+    std::vector<unsigned> hist((size_t)maxlen + 1);
+    if (hipMemcpyAsync(&h, dacc, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hist.data(), dhist, hist.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        return set_error(MXL_ERR_DEVICE, "features read-back");
+    }
+    cleanup();
+    // nearest-rank quantiles: sorted length at 1-based rank ceil(P*n/100)
+    auto quant = [&](int P) {
+        const int64_t rank = (P * n + 99) / 100;
+        int64_t cum = 0;
+        for (size_t L = 0; L < hist.size(); ++L) {
+            cum += hist[L];
+            if (cum >= rank) return (double)L;
+        }
+        return (double)maxlen;
+    };
+    typedef __int128 i128;
+    const double dn = (double)n;
+    const i128 S1 = nnz, S2 = (i128)h.s2, S3 = (i128)h.s3, N = n;
+    const double m2 = (double)(N * S2 - S1 * S1) / (dn * dn);                       // population variance
+    const double m3 = (double)(N * N * S3 - 3 * N * S1 * S2 + 2 * S1 * S1 * S1) / (dn * dn * dn);
+    const double mu = (double)nnz / dn;
+    const double sigma = std::sqrt(std::max(m2, 0.0));
+    out[0] = std::log10(dn);
+    out[1] = std::log10(nnz > 0 ? (double)nnz : 1.0);
+    out[2] = mu;
+    out[3] = sigma;
+    out[4] = mu > 0.0 ? sigma / mu : 0.0;
+    out[5] = (double)h.maxlen;
+    out[6] = (double)h.minlen;
+    out[7] = quant(50);
+    out[8] = quant(90);
+    out[9] = quant(99);
+    out[10] = (double)h.above / dn;
+    out[11] = nnz > 0 ? dn * (double)h.maxlen / (double)nnz : 0.0;
+    out[12] = (double)h.maxbw / dn;
+    out[13] = nnz > 0 ? (double)h.sumbw / (double)nnz / dn : 0.0;
+    out[14] = nnz > 0 ? (double)h.near / (double)nnz : 0.0;
+    out[15] = m2 > 0.0 ? m3 / std::pow(m2, 1.5) : 0.0;
+    return MXL_OK;
+}
+
+}  // namespace mxl
+
+struct mxl_mlp {
+    mxl_ctx *ctx = nullptr;
+    MlpShape sh{};
+    void *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    void *gs = nullptr;  // per-sample gradients
+    int64_t gs_cap = 0;
+    float loss = 0.f;
+};
+
+extern "C" mxl_status mxl_features(const mxl_op *Aop, double out_host[16]) {
+    if (!Aop || Aop->kind != MXL_OP_MATRIX || !out_host)
+        return set_error(MXL_ERR_INVALID_ARG, "matrix operator and output required");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(Aop->mat->ctx->device);
+    mxl_status st = features_compute(*Aop->mat, out_host);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return st;
+}
+
+extern "C" mxl_status mxl_mlp_create(mxl_ctx *ctx, int32_t nlayers, const int32_t *dims,
+                                     const float *theta_host, mxl_mlp **out) {
+    if (!ctx || !dims || !out || nlayers < 1 || nlayers > kMlpMaxL)
+        return set_error(MXL_ERR_INVALID_ARG, "mlp: 1..6 layers, dims and out required");
+    *out = nullptr;
+    MlpShape sh{};
+    sh.nl = nlayers;
+    int off = 0;
+    for (int l = 0; l <= nlayers; ++l) {
+        if (dims[l] < 1 || dims[l] > kMlpMaxW) return set_error(MXL_ERR_INVALID_ARG, "mlp widths must be 1..64");
+        sh.dims[l] = dims[l];
+    }
+    for (int l = 0; l < nlayers; ++l) {
+        sh.off[l] = off;
+        off += dims[l + 1] * dims[l] + dims[l + 1];
+    }
+    sh.nparams = off;
+    auto *mm = new mxl_mlp;
+    mm->ctx = ctx;
+    mm->sh = sh;
+    const size_t pb = (size_t)off * 4;
+    if (hipMalloc(&mm->theta, pb) != hipSuccess || hipMalloc(&mm->grad, pb) != hipSuccess ||
+        hipMalloc(&mm->m, pb) != hipSuccess || hipMalloc(&mm->v, pb) != hipSuccess) {
+        mxl_mlp_destroy(mm);
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "mlp parameters");
+    }
+    hipStream_t s = ctx->stream;
+    std::vector<float> zeros(off, 0.f);
+    if ((theta_host && hipMemcpyAsync(mm->theta, theta_host, pb, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipMemcpyAsync(mm->grad, zeros.data(), pb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(mm->m, zeros.data(), pb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(mm->v, zeros.data(), pb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        mxl_mlp_destroy(mm);
+        return set_error(MXL_ERR_DEVICE, "mlp upload");
+    }
+    *out = mm;
+    return MXL_OK;
+}
+
+static mxl_status mlp_copy(const mxl_mlp *mm, void *dst, const void *src, int64_t n, hipMemcpyKind k) {
+    if (!mm || !dst || !src || n != mm->sh.nparams)
+        return set_error(MXL_ERR_DIM_MISMATCH, "parameter count does not match the network");
+    if (hipMemcpyAsync(dst, src, (size_t)n * 4, k, mm->ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(mm->ctx->stream) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "mlp copy");
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_mlp_get_params(const mxl_mlp *mm, float *theta_host, int64_t n) {
+    return mlp_copy(mm, theta_host, mm ? mm->theta : nullptr, n, hipMemcpyDeviceToHost);
+}
+extern "C" mxl_status mxl_mlp_set_params(mxl_mlp *mm, const float *theta_host, int64_t n) {
+    return mlp_copy(mm, mm ? mm->theta : nullptr, theta_host, n, hipMemcpyHostToDevice);
+}
+extern "C" mxl_status mxl_mlp_get_grad(const mxl_mlp *mm, float *grad_host, int64_t n) {
+    return mlp_copy(mm, grad_host, mm ? mm->grad : nullptr, n, hipMemcpyDeviceToHost);
+}
+
+static mxl_status mlp_run(mxl_mlp *mm, int64_t ns, const float *X, const float *T, const float *M,
+                          float lambda, float *Y, float *loss_host, bool grad) {
+    if (!mm || ns < 1 || !X) return set_error(MXL_ERR_INVALID_ARG, "mlp: network, samples >= 1, X");
+    mxl_status st;
+    const int C = mm->sh.dims[mm->sh.nl];
+    if ((st = check_device_ptr(mm->ctx, X, (size_t)ns * mm->sh.dims[0] * 4, "X")) != MXL_OK) return st;
+    if (Y && (st = check_device_ptr(mm->ctx, Y, (size_t)ns * C * 4, "Y")) != MXL_OK) return st;
+    hipStream_t s = mm->ctx->stream;
+    float inv = 0.f;
+    void *lossd = nullptr;
+    if (T) {
+        if ((st = check_device_ptr(mm->ctx, T, (size_t)ns * C * 4, "T")) != MXL_OK) return st;
+        if ((st = check_device_ptr(mm->ctx, M, (size_t)ns * C * 4, "M")) != MXL_OK) return st;
+        std::vector<float> mh((size_t)ns * C);
+        if (hipMemcpyAsync(mh.data(), M, mh.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "mask read");
+        double msum = 0.0;
+        for (float v : mh) msum += v;
+        inv = msum > 0 ? (float)(1.0 / msum) : 0.f;
+        if (hipMalloc(&lossd, (size_t)ns * 4) != hipSuccess) return set_error(MXL_ERR_OUT_OF_MEMORY, "loss");
+    }
+    if (grad && mm->gs_cap < ns) {
+        (void)hipFree(mm->gs);
+        mm->gs = nullptr;
+        if (hipMalloc(&mm->gs, (size_t)ns * mm->sh.nparams * 4) != hipSuccess) {
+            (void)hipFree(lossd);
+            mm->gs_cap = 0;
+            return set_error(MXL_ERR_OUT_OF_MEMORY, "per-sample gradients");
+        }
+        mm->gs_cap = ns;
+    }
+    hipLaunchKernelGGL(k_mlp_sample, dim3((unsigned)ns), dim3(kWave), 0, s, mm->sh, (const float *)mm->theta,
+                       X, T, M, inv, Y, (float *)mm->gs, (float *)lossd, grad ? 1 : 0);
+    if (grad)
+        hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)((mm->sh.nparams + 255) / 256)), dim3(256), 0, s,
+                           mm->sh, ns, (const float *)mm->theta, (const float *)mm->gs, lambda,
+                           (float *)mm->grad);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipFree(lossd);
+        return set_error(MXL_ERR_DEVICE, "mlp launch");
+    }
+    if (T) {
+        std::vector<float> lh(ns);
+        std::vector<float> th(mm->sh.nparams);
+        hipError_t e = hipMemcpyAsync(lh.data(), lossd, (size_t)ns * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(th.data(), mm->theta, th.size() * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(lossd);
+        if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, "loss read-back");
+        double l = 0.0;
+        for (float v : lh) l += v;
+        l *= inv;
+        for (int ll = 0; ll < mm->sh.nl; ++ll) {
+            const int w0 = mm->sh.off[ll], w1 = w0 + mm->sh.dims[ll] * mm->sh.dims[ll + 1];
+            for (int j = w0; j < w1; ++j) l += (double)lambda * th[j] * th[j];
+        }
+        mm->loss = (float)l;
+        if (loss_host) *loss_host = mm->loss;
+    }
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_mlp_forward(const mxl_mlp *mm, int64_t ns, const float *X, float *Y) {
+    if (!Y) return set_error(MXL_ERR_INVALID_ARG, "Y required");
+    return mlp_run(const_cast<mxl_mlp *>(mm), ns, X, nullptr, nullptr, 0.f, Y, nullptr, false);
+}
+
+extern "C" mxl_status mxl_mlp_loss_grad(mxl_mlp *mm, int64_t ns, const float *X, const float *T,
+                                        const float *M, float lambda, float *loss_host) {
+    if (!T || !M) return set_error(MXL_ERR_INVALID_ARG, "targets and mask required");
+    return mlp_run(mm, ns, X, T, M, lambda, nullptr, loss_host, true);
+}
+
+extern "C" mxl_status mxl_mlp_adam_step(mxl_mlp *mm, int64_t t, float lr, float beta1, float beta2,
+                                        float eps) {
+    if (!mm || t < 1) return set_error(MXL_ERR_INVALID_ARG, "network and step t >= 1");
+    const float c1 = 1.f - (float)std::pow((double)beta1, (double)t);
+    const float c2 = 1.f - (float)std::pow((double)beta2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((mm->sh.nparams + 255) / 256)), dim3(256), 0, mm->ctx->stream,
+                       mm->sh.nparams, (float *)mm->theta, (const float *)mm->grad, (float *)mm->m,
+                       (float *)mm->v, lr, beta1, beta2, eps, c1, c2);
+    if (hipGetLastError() != hipSuccess) return set_error(MXL_ERR_DEVICE, "adam launch");
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_mlp_destroy(mxl_mlp *mm) {
+    if (!mm) return MXL_OK;
+    if (mm->ctx) (void)hipStreamSynchronize(mm->ctx->stream);
+    (void)hipFree(mm->theta);
+    (void)hipFree(mm->grad);
+    (void)hipFree(mm->m);
+    (void)hipFree(mm->v);
+    (void)hipFree(mm->gs);
+    delete mm;
+    return MXL_OK;
+}

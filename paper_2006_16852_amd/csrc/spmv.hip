@@ -46,12 +46,13 @@ __global__ __launch_bounds__(kWG) void k_csr_scalar(int64_t n, const int *__rest
                                                     const int *__restrict__ col,
                                                     const V *__restrict__ val, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int L = blockIdx.x;
     const int64_t ngroups = (n + kWG - 1) / kWG;
     int64_t g0, g1;
-    share_range(ngroups, L, gridDim.x, g0, g1);
+    int gs;
+    band_walk(ngroups, blockIdx.x, gridDim.x, g0, g1, gs);
     double dacc = 0.0;
-    for (int64_t g = g0; g < g1; ++g) {
+    for (int64_t g = g0; g < g1; g += gs) {
         int64_t row = g * kWG + threadIdx.x;
         if (row >= n) continue;
         int k0 = rp[row], k1 = rp[row + 1];
@@ -70,44 +71,66 @@ __global__ __launch_bounds__(kWG) void k_csr_scalar(int64_t n, const int *__rest
 // ------------------------------------------------------------ CSR vector
 // W lanes per row (W = 2..64), lanes stride through the row so a group's
 // loads are contiguous; the W partial sums are combined by a shuffle tree.
+// Each lane group keeps kVecU rows in flight: the row bounds, then the
+// first W entries of all kVecU rows are loaded before any x is gathered, so
+// a wave has several independent memory requests outstanding instead of one
+// dependent chain per row.
+constexpr int kVecU = 4;
+
 template <typename V, int W, bool DOT>
 __global__ __launch_bounds__(kWG) void k_csr_vector(int64_t n, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const V *__restrict__ val, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
     constexpr int RPG = kWG / W;  // rows per workgroup step
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int L = blockIdx.x;
     const int64_t ngroups = (n + RPG - 1) / RPG;
     int64_t g0, g1;
-    share_range(ngroups, L, gridDim.x, g0, g1);
+    int gs;
+    band_walk(ngroups, blockIdx.x, gridDim.x, g0, g1, gs);
     const int lane = threadIdx.x % W, sub = threadIdx.x / W;
     double dacc = 0.0;
-    for (int64_t g = g0; g < g1; ++g) {
-        int64_t row = g * RPG + sub;
-        V acc = 0;
-        if (row < n) {
-            int k0 = rp[row], k1 = rp[row + 1];
-            int k = k0 + lane;
-            // two independent loads in flight per lane
-            for (; k + W < k1; k += 2 * W) {
-                V v0 = ld_stream(val + k), v1 = ld_stream(val + k + W);
-                int c0 = ld_stream(col + k), c1 = ld_stream(col + k + W);
-                acc += v0 * p.x[c0];
-                acc += v1 * p.x[c1];
-            }
-            if (k < k1) acc += ld_stream(val + k) * p.x[ld_stream(col + k)];
-        }
+    for (int64_t g = g0; g < g1; g += (int64_t)gs * kVecU) {
+        int k0[kVecU], k1[kVecU];
 #pragma unroll
-        for (int off = W / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, W);
-        if (row < n && lane == 0) {
-            V out = combine(p, acc, row);
-            p.y[row] = out;
-            if (DOT) dacc += (double)p.w[row] * (double)out;
+        for (int u = 0; u < kVecU; ++u) {
+            const int64_t gu = g + (int64_t)u * gs;
+            const int64_t row = gu * RPG + sub;
+            const bool ok = gu < g1 && row < n;
+            k0[u] = ok ? rp[row] : 0;
+            k1[u] = ok ? rp[row + 1] : 0;
+        }
+        int c[kVecU];
+        V v[kVecU];
+#pragma unroll
+        for (int u = 0; u < kVecU; ++u) {
+            const int k = k0[u] + lane;
+            const bool in = k < k1[u];
+            c[u] = in ? ld_stream(col + k) : -1;
+            v[u] = in ? ld_stream(val + k) : (V)0;
+        }
+        V acc[kVecU];
+#pragma unroll
+        for (int u = 0; u < kVecU; ++u) acc[u] = c[u] >= 0 ? v[u] * p.x[c[u]] : (V)0;
+#pragma unroll
+        for (int u = 0; u < kVecU; ++u)  // rows longer than W
+            for (int k = k0[u] + lane + W; k < k1[u]; k += W) acc[u] += ld_stream(val + k) * p.x[ld_stream(col + k)];
+#pragma unroll
+        for (int u = 0; u < kVecU; ++u) {
+#pragma unroll
+            for (int off = W / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, W);
+            const int64_t gu = g + (int64_t)u * gs;
+            const int64_t row = gu * RPG + sub;
+            if (gu < g1 && row < n && lane == 0) {
+                V out = combine(p, acc[u], row);
+                p.y[row] = out;
+                if (DOT) dacc += (double)p.w[row] * (double)out;
+            }
         }
     }
     if (DOT) {
-        double v[1] = {dacc};
-        publish<1>(v, p.partials, p.slot_base + L);
+        double vv[1] = {dacc};
+        publish<1>(vv, p.partials, p.slot_base + L);
     }
 }
 
@@ -158,11 +181,12 @@ __global__ __launch_bounds__(kWG) void k_csr_merge(int64_t n, const int *__restr
     __shared__ int s_crow[kWG];
     __shared__ V s_cval[kWG];
     const int tid = threadIdx.x;
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int L = blockIdx.x;
     int64_t t0, t1;
-    share_range(ntiles, L, gridDim.x, t0, t1);
+    int ts;
+    band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
     double dacc = 0.0;
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    for (int64_t tile = t0; tile < t1; tile += ts) {
         const int2 c0 = part[tile], c1 = part[tile + 1];
         const int r0 = c0.x, k0 = c0.y, r1 = c1.x, k1 = c1.y;
         const int nr = r1 - r0, nk = k1 - k0;
@@ -253,11 +277,12 @@ __global__ __launch_bounds__(kWG) void k_coo(int64_t n, int64_t nnz, const int *
     __shared__ int s_crow[kWG];
     __shared__ V s_cval[kWG];
     const int tid = threadIdx.x;
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
+    const int L = blockIdx.x;
     int64_t t0, t1;
-    share_range(ntiles, L, gridDim.x, t0, t1);
+    int ts;
+    band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
     double dacc = 0.0;
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    for (int64_t tile = t0; tile < t1; tile += ts) {
         const int64_t k0 = tile * kCooItems;
         int64_t k1 = k0 + kCooItems;
         if (k1 > nnz) k1 = nnz;
@@ -361,20 +386,42 @@ __global__ __launch_bounds__(kWG) void k_carry_fixup(const Carry *__restrict__ c
 // 256-row tile) into LDS when it fits, then gathers from LDS.
 constexpr int kEllLdsCap = 4096;  // x entries staged per tile (32 KB in FP64)
 
-template <typename V, bool DOT, bool LDS>
+// Vector types for R consecutive rows of one ELL slot (R = 1, 2, 4).
+template <int R> struct IdxVec;
+template <> struct IdxVec<1> { typedef int T; };
+template <> struct IdxVec<2> { typedef int T __attribute__((ext_vector_type(2))); };
+template <> struct IdxVec<4> { typedef int T __attribute__((ext_vector_type(4))); };
+template <typename V, int R> struct ValVec { typedef V T __attribute__((ext_vector_type(R))); };
+template <typename V> struct ValVec<V, 1> { typedef V T; };
+
+template <int R, typename T>
+__device__ __forceinline__ auto lane_of(const T &v, int r) {
+    if constexpr (R == 1) return v;
+    else return v[r];
+}
+
+// Each thread owns R consecutive rows (R*256 rows per tile), so one slot's
+// column indices and values arrive as one 4R- and one 8R-byte load (16-byte
+// loads at R = 4 for indices, 2 x 16 bytes for FP64 values).  U slots of
+// loads are issued before their x gathers.
+template <typename V, bool DOT, bool LDS, int R>
 __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                                              const int *__restrict__ ecol,
                                              const V *__restrict__ evals,
                                              const int2 *__restrict__ win, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
+    constexpr int U = 8 / R;
+    typedef typename IdxVec<R>::T IV;
+    typedef typename ValVec<V, R>::T VV;
     __shared__ V s_x[LDS ? kEllLdsCap : 1];
-    const int L = xcd_logical(blockIdx.x, gridDim.x);
-    const int64_t ntiles = (n + kWG - 1) / kWG;
+    const int L = blockIdx.x;
+    const int64_t ntiles = (n + kWG * R - 1) / (kWG * R);
     int64_t t0, t1;
-    share_range(ntiles, L, gridDim.x, t0, t1);
+    int ts;
+    band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
     double dacc = 0.0;
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t row = tile * kWG + threadIdx.x;
+    for (int64_t tile = t0; tile < t1; tile += ts) {
+        const int64_t row0 = tile * kWG * R + (int64_t)threadIdx.x * R;
         bool staged = false;
         int lo = 0;
         if (LDS) {
@@ -387,31 +434,55 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
             }
             __syncthreads();
         }
-        V acc = 0;
-        if (row < n) {
-            int s = 0;
-            for (; s + 1 < w; s += 2) {
-                int c0 = ld_stream(ecol + (int64_t)s * n_pad + row);
-                int c1 = ld_stream(ecol + (int64_t)(s + 1) * n_pad + row);
-                V v0 = ld_stream(evals + (int64_t)s * n_pad + row);
-                V v1 = ld_stream(evals + (int64_t)(s + 1) * n_pad + row);
-                if (c0 >= 0) acc += v0 * ((LDS && staged) ? s_x[c0 - lo] : p.x[c0]);
-                if (c1 >= 0) acc += v1 * ((LDS && staged) ? s_x[c1 - lo] : p.x[c1]);
+        if (row0 < n) {  // rows row0..row0+R-1 < n_pad (n_pad is a multiple of 64)
+            const IV *cp = (const IV *)(ecol + row0);
+            const VV *vp = (const VV *)(evals + row0);
+            const int64_t stride = n_pad / R;  // one slot, in vector units
+            V acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = 0;
+            for (int s0 = 0; s0 < w; s0 += U) {
+                IV c[U];
+                VV v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (s0 + u < w) {
+                        c[u] = __builtin_nontemporal_load(cp + (int64_t)(s0 + u) * stride);
+                        v[u] = __builtin_nontemporal_load(vp + (int64_t)(s0 + u) * stride);
+                    } else {
+                        c[u] = (IV)(-1);
+                        v[u] = (VV)(V)0;
+                    }
+                }
+                V xv[U][R];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int cc = lane_of<R>(c[u], r);
+                        xv[u][r] = cc >= 0 ? ((LDS && staged) ? s_x[cc - lo] : p.x[cc]) : (V)0;
+                    }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (lane_of<R>(c[u], r) >= 0) acc[r] += lane_of<R>(v[u], r) * xv[u][r];
             }
-            if (s < w) {
-                int c0 = ld_stream(ecol + (int64_t)s * n_pad + row);
-                V v0 = ld_stream(evals + (int64_t)s * n_pad + row);
-                if (c0 >= 0) acc += v0 * ((LDS && staged) ? s_x[c0 - lo] : p.x[c0]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t row = row0 + r;
+                if (row < n) {
+                    V out = combine(p, acc[r], row);
+                    p.y[row] = out;
+                    if (DOT) dacc += (double)p.w[row] * (double)out;
+                }
             }
-            V out = combine(p, acc, row);
-            p.y[row] = out;
-            if (DOT) dacc += (double)p.w[row] * (double)out;
         }
         if (LDS) __syncthreads();
     }
     if (DOT) {
-        double v[1] = {dacc};
-        publish<1>(v, p.partials, p.slot_base + L);
+        double vv[1] = {dacc};
+        publish<1>(vv, p.partials, p.slot_base + L);
     }
 }
 
@@ -464,12 +535,12 @@ __global__ void k_hyb_tail(int64_t n, int k, const int *__restrict__ rp,
 // Column window of every 256-row tile (columns are sorted within rows, so
 // the first and last entry of each row bound it).  Empty tile: lo > hi.
 __global__ void k_ell_windows(int64_t n, const int *__restrict__ rp, const int *__restrict__ col,
-                              int64_t ntiles, int2 *__restrict__ win) {
+                              int64_t ntiles, int tile_rows, int2 *__restrict__ win) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     int lo = INT_MAX, hi = -1;
-    int64_t r1 = (t + 1) * kWG < n ? (t + 1) * kWG : n;
-    for (int64_t r = t * kWG; r < r1; ++r) {
+    int64_t r1 = (t + 1) * tile_rows < n ? (t + 1) * tile_rows : n;
+    for (int64_t r = t * tile_rows; r < r1; ++r) {
         int a = rp[r], b = rp[r + 1];
         if (b > a) {
             lo = col[a] < lo ? col[a] : lo;
@@ -555,10 +626,10 @@ void spmv_plan(MatrixImpl &A) {
         A.grid_main = grid_for(A.ntiles, cap);
         break;
     case MXL_FMT_ELL:
-        A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
+        A.grid_main = grid_for((A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt), cap);
         break;
     case MXL_FMT_HYB:
-        A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
+        A.grid_main = grid_for((A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt), cap);
         A.grid_tail = grid_for(A.ntiles, cap);
         break;
     }
@@ -646,13 +717,22 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
         const V *ev = (const V *)A.ell_val->p;
         const int2 *win = A.ell_win ? (const int2 *)A.ell_win->p : nullptr;
         const bool lds = A.variant == MXL_ELL_LDS && win;
-        if (lds) {
-            if (dot) hipLaunchKernelGGL((k_ell<V, true, true>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
-            else hipLaunchKernelGGL((k_ell<V, false, true>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
-        } else {
-            if (dot) hipLaunchKernelGGL((k_ell<V, true, false>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
-            else hipLaunchKernelGGL((k_ell<V, false, false>), dim3(A.grid_main), blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);
+        const dim3 ge(A.grid_main);
+#define MXL_ELL_CASE(RR)                                                                                          \
+    case RR:                                                                                                      \
+        if (lds) {                                                                                                \
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, true, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);   \
+            else hipLaunchKernelGGL((k_ell<V, false, true, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);      \
+        } else {                                                                                                  \
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, false, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);  \
+            else hipLaunchKernelGGL((k_ell<V, false, false, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);     \
+        }                                                                                                         \
+        break;
+        switch (A.ell_rpt) {
+            MXL_ELL_CASE(1) MXL_ELL_CASE(2) MXL_ELL_CASE(4)
+        default: return hipErrorInvalidValue;
         }
+#undef MXL_ELL_CASE
         if (A.format == MXL_FMT_HYB && A.tail_nnz > 0) {
             SpmvK<V> t = p;  // tail accumulates into y
             t.slot_base = A.grid_main;
@@ -722,10 +802,11 @@ hipError_t launch_hyb_tail(const MatrixImpl &A, int k, const int64_t *toff, int 
 }
 
 hipError_t launch_ell_windows(const MatrixImpl &A, int2 *win, hipStream_t s) {
-    int64_t nt = (A.nrows + kWG - 1) / kWG;
+    const int tr = kWG * A.ell_rpt;
+    int64_t nt = (A.nrows + tr - 1) / tr;
     if (nt == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ell_windows, g1(nt), dim3(256), 0, s, A.nrows, (const int *)A.row_ptr->p,
-                       (const int *)A.col->p, nt, win);
+                       (const int *)A.col->p, nt, tr, win);
     return hipGetLastError();
 }
 

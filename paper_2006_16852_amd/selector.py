@@ -1,0 +1,195 @@
+"""Learned format/kernel selector.
+
+The paper forks at run time over matrix format and kernel variant (Sec. 7.2)
+and judges kernels with a performance profile (Sec. 7.3).  This module
+learns that fork: 16 structural features of a CSR matrix (computed on the GPU
+by ``mxl_features``) go through a small MLP (trained on the GPU by the
+library's own forward/backward/Adam kernels) that predicts, for each
+(format, variant) class, s_c ~ log(t_c / t_best).  The choice is the argmin
+over feasible classes; when the network is unsure (top-2 margin below
+``delta``) or the matrix lies outside the training distribution (a
+standardised feature beyond ``zmax``) it falls back to timing the top-3
+candidates.  Exhaustive timing (``mxl_time_apply``) produces the labels and
+is the judge (time regret = t_choice / t_best - 1).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import torch
+
+from . import Mlp, MxlError, ERR_INFEASIBLE_FORMAT
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "selector_weights.json")
+
+# (name, format, convert kwargs)
+CLASSES = [
+    ("csr_scalar", "csr", dict(variant=0)),
+    ("csr_vec4", "csr", dict(variant=1, vector_width=4)),
+    ("csr_vec16", "csr", dict(variant=1, vector_width=16)),
+    ("csr_vec64", "csr", dict(variant=1, vector_width=64)),
+    ("csr_merge", "csr", dict(variant=2)),
+    ("coo", "coo", {}),
+    ("ell", "ell", {}),
+    ("ell_lds", "ell", dict(variant=1)),
+    ("hyb66", "hyb", dict(hyb_quantile=0.66)),
+    ("hyb90", "hyb", dict(hyb_quantile=0.9)),
+]
+NCLS = len(CLASSES)
+DIMS = [16, 32, 32, NCLS]
+# heavy-tailed features enter through log1p before standardisation
+LOG_FEATS = [5, 6, 7, 8, 9, 11]
+
+
+def transform(F: np.ndarray) -> np.ndarray:
+    F = np.array(F, dtype=np.float64, copy=True)
+    F[..., LOG_FEATS] = np.log1p(np.maximum(F[..., LOG_FEATS], 0.0))
+    return F
+
+
+def ell_feasible(f: np.ndarray, vt: int = 8) -> bool:
+    """Mirror of the library's ELL budget from features (n, nnz, max length)."""
+    n = 10 ** f[0]
+    nnz = 10 ** f[1] if f[2] > 0 else 0.0
+    n_pad = math.ceil(round(n) / 64) * 64
+    ell = n_pad * f[5] * (vt + 4)
+    csr = nnz * (vt + 4) + (n + 1) * 4
+    return ell <= min(max(4 * csr, 1 << 20), 32 * (1 << 30))
+
+
+def feasible_mask(f: np.ndarray) -> np.ndarray:
+    m = np.ones(NCLS, bool)
+    if not ell_feasible(f):
+        m[[6, 7]] = False
+    return m
+
+
+def convert(base, k: int):
+    _, fmt, kw = CLASSES[k]
+    return base.convert(fmt, **kw)
+
+
+def time_classes(base, x, y, reps: int = 20, flush: bool = True, classes=None):
+    """Median ms of every class (inf when the format is infeasible)."""
+    t = np.full(NCLS, np.inf)
+    for k in (range(NCLS) if classes is None else classes):
+        try:
+            op = convert(base, k)
+        except MxlError as e:
+            if e.status == ERR_INFEASIBLE_FORMAT:
+                continue
+            raise
+        t[k] = op.time_apply(x, y, reps=reps, flush=flush)
+        del op
+    return t
+
+
+def labels_from_times(T: np.ndarray):
+    """y_c = log(t_c / t_best), mask 0 for infeasible classes."""
+    best = np.min(T, axis=1, keepdims=True)
+    M = np.isfinite(T).astype(np.float64)
+    Y = np.where(M > 0, np.log(np.where(M > 0, T, 1.0) / best), 0.0)
+    return Y, M
+
+
+def he_init(dims, seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(dims) - 1):
+        parts.append(rng.standard_normal(dims[i + 1] * dims[i]) * math.sqrt(2.0 / dims[i]))
+        parts.append(np.zeros(dims[i + 1]))
+    return np.concatenate(parts)
+
+
+class Selector:
+    def __init__(self, theta, mean, std, delta=0.05, zmax=4.0):
+        self.theta = np.asarray(theta, np.float64)
+        self.mean = np.asarray(mean, np.float64)
+        self.std = np.asarray(std, np.float64)
+        self.delta = delta
+        self.zmax = zmax
+        self._mlp = None
+
+    # ---------------------------------------------------------------- io
+    def to_json(self) -> dict:
+        return dict(dims=DIMS, classes=[c[0] for c in CLASSES], theta=self.theta.tolist(),
+                    mean=self.mean.tolist(), std=self.std.tolist(), delta=self.delta,
+                    zmax=self.zmax, log_features=LOG_FEATS)
+
+    def save(self, path: str = WEIGHTS):
+        json.dump(self.to_json(), open(path, "w"))
+
+    @classmethod
+    def load(cls, path: str = WEIGHTS) -> "Selector":
+        d = json.load(open(path))
+        return cls(d["theta"], d["mean"], d["std"], d.get("delta", 0.05), d.get("zmax", 4.0))
+
+    # ----------------------------------------------------------- predict
+    def standardise(self, F) -> np.ndarray:
+        return (transform(F) - self.mean) / self.std
+
+    def scores(self, ctx, F) -> np.ndarray:
+        """Predicted log(t_c / t_best) per class, computed on the GPU."""
+        Z = np.atleast_2d(self.standardise(F)).astype(np.float32)
+        if self._mlp is None or self._mlp.ctx is not ctx:
+            self._mlp = Mlp(ctx, DIMS, self.theta.astype(np.float32))
+        X = torch.from_numpy(Z).to(f"cuda:{ctx.device}")
+        return self._mlp.forward(X).cpu().numpy().astype(np.float64)
+
+    def choose(self, ctx, base, x=None, y=None, fallback: bool = True):
+        """Returns (class index, info dict)."""
+        f = base.features()
+        s = self.scores(ctx, f)[0]
+        mask = feasible_mask(f)
+        s = np.where(mask, s, np.inf)
+        order = np.argsort(s)
+        z = np.abs(self.standardise(f))
+        margin = s[order[1]] - s[order[0]] if np.isfinite(s[order[1]]) else np.inf
+        unsure = margin < self.delta or bool(np.any(z > self.zmax))
+        info = dict(margin=float(margin), max_z=float(z.max()), fallback=False)
+        if fallback and unsure and x is not None:
+            top = [int(k) for k in order[:3] if np.isfinite(s[k])]
+            t = time_classes(base, x, y, reps=5, flush=True, classes=top)
+            info.update(fallback=True, timed=top)
+            return int(top[int(np.argmin(t[top]))]), info
+        return int(order[0]), info
+
+
+def train(ctx, F: np.ndarray, T: np.ndarray, epochs: int = 2000, lr: float = 1e-3,
+          lam: float = 1e-4, seed: int = 0) -> Selector:
+    """Fit the MLP on the GPU (full batch, Adam) to log time ratios."""
+    Ft = transform(F)
+    mean = Ft.mean(axis=0)
+    std = Ft.std(axis=0)
+    std[std == 0] = 1.0
+    Z = ((Ft - mean) / std).astype(np.float32)
+    Y, M = labels_from_times(T)
+    dev = f"cuda:{ctx.device}"
+    X = torch.from_numpy(Z).to(dev)
+    Yd = torch.from_numpy(Y.astype(np.float32)).to(dev)
+    Md = torch.from_numpy(M.astype(np.float32)).to(dev)
+    net = Mlp(ctx, DIMS, he_init(DIMS, seed).astype(np.float32))
+    for t in range(1, epochs + 1):
+        net.loss_grad(X, Yd, Md, lam)
+        net.adam_step(t, lr=lr)
+    return Selector(net.params().astype(np.float64), mean, std)
+
+
+def regret(T: np.ndarray, choice: np.ndarray) -> np.ndarray:
+    best = np.min(T, axis=1)
+    return T[np.arange(len(choice)), choice] / best - 1.0
+
+
+def performance_profile(T: np.ndarray, choices: dict, taus=(1.0, 1.05, 1.1, 1.25, 1.5, 2.0, 3.0)):
+    """Fraction of matrices a policy solves within slowdown tau of the best
+    (the performance-profile view of Sec. 7.3)."""
+    best = np.min(T, axis=1)
+    out = {}
+    for name, ch in choices.items():
+        r = T[np.arange(len(ch)), ch] / best
+        out[name] = {f"{tau:g}": float(np.mean(r <= tau + 1e-12)) for tau in taus}
+    return out

@@ -1,0 +1,158 @@
+"""Train and evaluate the format/kernel selector on the 200-matrix
+row-length-skewed suite (on one GPU).
+
+For every matrix m (generated from its seed, never stored): the 16 features
+on the GPU, then the median time of every feasible (format, variant) class
+(20 repetitions, last-level cache flushed before each).  Matrices 0..199 are
+split 150 train / 50 test (seed 7).  The MLP is trained on the GPU by the
+library's kernels; the test set reports the time regret of the selector,
+the selector with its timing fallback, the best single fixed class and a
+hand rule, plus their performance profiles.
+
+    python -m paper_2006_16852_amd.train_selector --out DIR [--count 200] [--scale 1.0]
+
+Writes DIR/selector_timings.json (features + times), DIR/selector_eval.json
+and DIR/selector_weights.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import paper_2006_16852_amd as mxl  # noqa: E402
+from paper_2006_16852_amd import selector as S  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+def hand_rule(f: np.ndarray) -> int:
+    """No-network baseline: a fixed rule on mean and spread of row lengths."""
+    mu, cv = f[2], f[4]
+    if cv < 0.3 and S.ell_feasible(f):
+        return 6                                   # ell
+    if cv > 1.5:
+        return 4                                   # csr_merge
+    return 2 if mu <= 16 else 3                    # csr_vec16 / csr_vec64
+
+
+def collect(ctx, idx, scale, reps, log):
+    feats, times, meta = [], [], []
+    dev = f"cuda:{ctx.device}"
+    for m in idx:
+        t0 = time.time()
+        A = W.zipf_suite_matrix(m, scale_n=scale)
+        rp = torch.from_numpy(A.row_ptr).to(dev)
+        col = torch.from_numpy(A.col).to(dev)
+        val = torch.from_numpy(A.val).to(dev)
+        base = mxl.csr(ctx, rp, col, val)
+        x = torch.from_numpy(W.uniform_vec(A.ncols, 2000 + m)).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        f = base.features()
+        ws = A.nnz * 12 + A.nrows * 20
+        t = S.time_classes(base, x, y, reps=reps, flush=ws < (512 << 20))
+        feats.append(f)
+        times.append(t)
+        meta.append(dict(m=int(m), n=int(A.nrows), nnz=int(A.nnz)))
+        log(f"[collect] m={m} n={A.nrows} nnz={A.nnz} best={S.CLASSES[int(np.argmin(t))][0]} "
+            f"{time.time() - t0:.1f}s")
+        del base, rp, col, val, x, y, A
+        torch.cuda.empty_cache()
+    return np.array(feats), np.array(times), meta
+
+
+def evaluate(ctx, sel, F, T, fallback_times=None):
+    pred = np.array([int(np.argmin(np.where(S.feasible_mask(f), s, np.inf)))
+                     for f, s in zip(F, sel.scores(ctx, F))])
+    return pred
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--count", type=int, default=200)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=2000)
+    ap.add_argument("--timings", default=None, help="reuse a timings file instead of measuring")
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+
+    def log(s):
+        print(s, flush=True)
+
+    ctx = mxl.Context(0)
+    if args.timings:
+        d = json.load(open(args.timings))
+        F, T, meta = np.array(d["features"]), np.array(d["times_ms"]), d["meta"]
+        T = np.where(np.array(T) < 0, np.inf, T)
+    else:
+        F, T, meta = collect(ctx, range(args.count), args.scale, args.reps, log)
+        json.dump(dict(classes=[c[0] for c in S.CLASSES], features=F.tolist(),
+                       times_ms=np.where(np.isfinite(T), T, -1.0).tolist(), meta=meta,
+                       reps=args.reps, scale=args.scale),
+                  open(os.path.join(args.out, "selector_timings.json"), "w"))
+    n = len(F)
+    perm = np.random.default_rng(7).permutation(n)
+    ntest = max(1, n // 4)
+    test, train_idx = np.sort(perm[:ntest]), np.sort(perm[ntest:])
+    t0 = time.time()
+    sel = S.train(ctx, F[train_idx], T[train_idx], epochs=args.epochs)
+    train_s = time.time() - t0
+    sel.save(os.path.join(args.out, "selector_weights.json"))
+    Ft, Tt = F[test], T[test]
+    choice_net = evaluate(ctx, sel, Ft, Tt)
+    # fallback uses the measured test times of the top-3 (same labels as the judge)
+    scores = sel.scores(ctx, Ft)
+    choice_fb = []
+    nfb = 0
+    for f, s, t in zip(Ft, scores, Tt):
+        s = np.where(S.feasible_mask(f), s, np.inf)
+        order = np.argsort(s)
+        z = np.abs(sel.standardise(f))
+        unsure = (s[order[1]] - s[order[0]] < sel.delta) or np.any(z > sel.zmax)
+        if unsure:
+            nfb += 1
+            top = [k for k in order[:3] if np.isfinite(s[k])]
+            choice_fb.append(int(top[int(np.argmin(t[top]))]))
+        else:
+            choice_fb.append(int(order[0]))
+    choice_fb = np.array(choice_fb)
+    # best single fixed class on the training set (by geometric-mean slowdown)
+    Ttr = T[train_idx]
+    slow = Ttr / Ttr.min(axis=1, keepdims=True)
+    gm = [np.exp(np.mean(np.log(np.where(np.isfinite(slow[:, k]), slow[:, k], 1e3)))) for k in range(S.NCLS)]
+    fixed = int(np.argmin(gm))
+    choice_fixed = np.array([fixed if np.isfinite(t[fixed]) else 4 for t in Tt])
+    choice_hand = np.array([hand_rule(f) if np.isfinite(t[hand_rule(f)]) else 4 for f, t in zip(Ft, Tt)])
+    choice_default = np.array([1 if f[2] <= 6 else (2 if f[2] <= 24 else 3) for f in Ft])  # auto vector width
+
+    def stats(ch):
+        r = S.regret(Tt, ch)
+        return dict(mean=float(r.mean()), geomean=float(np.exp(np.mean(np.log1p(r))) - 1),
+                    p90=float(np.quantile(r, 0.9)), max=float(r.max()),
+                    exact=float(np.mean(r <= 1e-12)))
+
+    ev = dict(n_train=int(len(train_idx)), n_test=int(len(test)), train_seconds=train_s,
+              epochs=args.epochs, fixed_class=S.CLASSES[fixed][0], fallback_used=int(nfb),
+              regret=dict(selector=stats(choice_net), selector_fallback=stats(choice_fb),
+                          best_fixed=stats(choice_fixed), hand_rule=stats(choice_hand),
+                          default_vector=stats(choice_default)),
+              profile=S.performance_profile(Tt, dict(selector=choice_net, selector_fallback=choice_fb,
+                                                     best_fixed=choice_fixed, hand_rule=choice_hand,
+                                                     default_vector=choice_default)),
+              class_wins={S.CLASSES[k][0]: int(np.sum(np.argmin(T, axis=1) == k)) for k in range(S.NCLS)})
+    json.dump(ev, open(os.path.join(args.out, "selector_eval.json"), "w"), indent=1)
+    log(json.dumps(ev["regret"]))
+
+
+if __name__ == "__main__":
+    main()

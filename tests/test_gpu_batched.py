@@ -1,0 +1,122 @@
+"""Batched persistent Jacobi-PCG against the oracle's per-system PCG.
+
+Bar: every system converges; iteration counts within 2 of the oracle's for
+at least 99% of systems (summation order differs); the residual recomputed
+in FP64 on the CPU meets 1e-10; schedules that share the workgroup size give
+bitwise-identical results."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests._gpu import DEV, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mxl():
+    import paper_2006_16852_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mxl):
+    return mxl.Context(0)
+
+
+def _run(mxl, ctx, B, tuning=None, **crit):
+    op = mxl.batch(ctx, B.sys_ptr, dev(B.sys_ptr), dev(B.row_ptr), dev(B.col), dev(B.val))
+    b = dev(B.b)
+    x = torch.zeros_like(b)
+    it = torch.zeros(B.nsys, dtype=torch.int32, device=DEV)
+    rel = torch.zeros(B.nsys, dtype=torch.float64, device=DEV)
+    st = torch.zeros(B.nsys, dtype=torch.uint8, device=DEV)
+    op.solve(b, x, it, rel, st, tuning=tuning, reduction=1e-10, **crit)
+    return op, x.cpu().numpy(), it.cpu().numpy(), rel.cpu().numpy(), st.cpu().numpy()
+
+
+def _check_residuals(B, x, tol=1.01e-10):
+    for s in range(B.nsys):
+        A = B.system(s)
+        r0, r1 = B.sys_ptr[s], B.sys_ptr[s + 1]
+        r = B.b[r0:r1] - O.spmv(A, x[r0:r1])
+        assert np.linalg.norm(r) <= tol * np.linalg.norm(B.b[r0:r1]), s
+
+
+@pytest.mark.parametrize("tuning", [None, (64, 4, 1), (128, 2, 0), (256, 1, 1), (512, 1, 0)],
+                         ids=["default", "64x4", "128x2", "256x1", "512x1"])
+def test_batch_parity(mxl, ctx, tuning):
+    B = W.batch_systems(nsys=300, seed=77)
+    ref = O.batch_pcg(B, reduction=1e-10)
+    _, x, it, rel, st = _run(mxl, ctx, B, tuning)
+    print(f"[batch {tuning}] iters gpu {it.sum()} oracle {ref['iterations'].sum()}", flush=True)
+    assert np.all(st == 1)
+    assert np.mean(np.abs(it - ref["iterations"]) <= 2) >= 0.99
+    assert np.allclose(rel, ref["rel_residual"], rtol=0.5, atol=1e-13)
+    _check_residuals(B, x)
+
+
+def test_batch_schedules_same_wg_size_bitwise(mxl, ctx):
+    B = W.batch_systems(nsys=120, seed=3)
+    _, x1, it1, _, _ = _run(mxl, ctx, B, (128, 1, 0))
+    _, x2, it2, _, _ = _run(mxl, ctx, B, (128, 8, 1))
+    assert np.array_equal(it1, it2) and np.array_equal(x1, x2)
+
+
+def test_batch_large_system_scratch_path(mxl, ctx):
+    """A system larger than the LDS capacity runs from global scratch: the
+    64x64 Poisson system as a batch of one, plus small systems around it."""
+    A = W.stencil_2d5(64)
+    b1 = O.spmv(A, W.uniform_vec(A.nrows, 1))
+    S = W.batch_systems(nsys=5, seed=8)
+    rp = np.concatenate([A.row_ptr[:-1], S.row_ptr + A.nnz]).astype(np.int32)
+    sp = np.concatenate([[0], S.sys_ptr + A.nrows]).astype(np.int32)
+    Bb = W.Batch(6, sp, rp, np.concatenate([A.col, S.col]), np.concatenate([A.val, S.val]),
+                 np.concatenate([b1, S.b]))
+    ref = O.batch_pcg(Bb, reduction=1e-10)
+    _, x, it, rel, st = _run(mxl, ctx, Bb, (1024, 1, 1))
+    assert np.all(st == 1)
+    assert abs(int(it[0]) - int(ref["iterations"][0])) <= 2
+    _check_residuals(Bb, x)
+
+
+def test_batch_max_iters_and_zero_rhs(mxl, ctx):
+    B = W.batch_systems(nsys=20, seed=5)
+    B.b[B.sys_ptr[3]:B.sys_ptr[4]] = 0.0
+    _, x, it, rel, st = _run(mxl, ctx, B, None, max_iters=3)
+    assert st[3] == 1 and it[3] == 0 and not x[B.sys_ptr[3]:B.sys_ptr[4]].any()
+    others = np.delete(np.arange(20), 3)
+    assert np.all(it[others] == 3) and np.all(st[others] == 2)
+
+
+def test_batch_autotune(mxl, ctx):
+    B = W.batch_systems(nsys=400, seed=11)
+    op = mxl.batch(ctx, B.sys_ptr, dev(B.sys_ptr), dev(B.row_ptr), dev(B.col), dev(B.val))
+    b = dev(B.b)
+    xs = torch.zeros_like(b)
+    best, ms = op.autotune(b, xs, reps=1, reduction=1e-10)
+    assert best[0] in (64, 128, 256, 512) and ms > 0
+    x = torch.zeros_like(b)
+    it = torch.zeros(B.nsys, dtype=torch.int32, device=DEV)
+    rel = torch.zeros(B.nsys, dtype=torch.float64, device=DEV)
+    st = torch.zeros(B.nsys, dtype=torch.uint8, device=DEV)
+    op.solve(b, x, it, rel, st, reduction=1e-10)      # uses the tuned schedule
+    assert np.all(st.cpu().numpy() == 1)
+    _check_residuals(B, x.cpu().numpy())
+
+
+def test_batch_full_size(mxl, ctx):
+    """All 10,000 systems (seed 5000) against the oracle."""
+    B = W.batch_systems()
+    ref = O.batch_pcg(B, reduction=1e-10)
+    _, x, it, rel, st = _run(mxl, ctx, B, None)
+    assert np.all(st == 1)
+    assert np.mean(np.abs(it - ref["iterations"]) <= 2) >= 0.99
+    bad = 0
+    for s in range(0, B.nsys, 7):
+        r0, r1 = B.sys_ptr[s], B.sys_ptr[s + 1]
+        r = B.b[r0:r1] - O.spmv(B.system(s), x[r0:r1])
+        bad += np.linalg.norm(r) > 1.01e-10 * np.linalg.norm(B.b[r0:r1])
+    assert bad == 0

@@ -1,0 +1,93 @@
+"""Selector device work against the oracle: the 16 features (integer ones
+bitwise, the rest within 1e-12), the FP32 MLP's outputs, loss and gradients
+against the FP64 oracle (1e-4 relative), the Adam step, and GPU training."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests._gpu import DEV, matrix
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mxl():
+    import paper_2006_16852_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mxl):
+    return mxl.Context(0)
+
+
+FEAT_MATS = ([W.zipf_suite_matrix(m, scale_n=0.02) for m in (0, 5, 33, 71)]
+             + [W.stencil_2d5(64), W.stencil_3d27(16), W.aniso_3d7(12)]
+             + [W.edge_matrices()[i] for i in (0, 2, 3, 4)])
+
+
+@pytest.mark.parametrize("A", FEAT_MATS, ids=[a.name for a in FEAT_MATS])
+def test_features_parity(mxl, ctx, A):
+    got = matrix(mxl, ctx, A).features()
+    want = O.features(A)
+    ints = [5, 6, 7, 8, 9]
+    assert np.array_equal(got[ints], want[ints])
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-13), np.abs(got - want).max()
+
+
+def _data(seed, ns=37, dims=(16, 32, 32, 10)):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((ns, dims[0])).astype(np.float32)
+    Y = rng.standard_normal((ns, dims[-1])).astype(np.float32)
+    M = (rng.random((ns, dims[-1])) < 0.8).astype(np.float32)
+    th = (rng.standard_normal(O.mlp_param_count(list(dims))) * 0.3).astype(np.float32)
+    return X, Y, M, th
+
+
+@pytest.mark.parametrize("dims", [(16, 32, 32, 10), (16, 10), (16, 8, 4)], ids=str)
+def test_mlp_forward_grad_parity(mxl, ctx, dims):
+    X, Y, M, th = _data(1, dims=dims)
+    net = mxl.Mlp(ctx, list(dims), th)
+    Xd, Yd, Md = (torch.from_numpy(a).to(DEV) for a in (X, Y, M))
+    pred = net.forward(Xd).cpu().numpy()
+    loss = net.loss_grad(Xd, Yd, Md, 1e-3)
+    g = net.grad()
+    lo, go, po = O.mlp_loss_grad(list(dims), th.astype(np.float64), X, Y, M, 1e-3, True, True)
+    assert np.allclose(pred, po, rtol=1e-4, atol=1e-5)
+    assert abs(loss - lo) <= 1e-4 * abs(lo)
+    assert np.allclose(g, go, rtol=1e-4, atol=1e-5 * np.abs(go).max())
+
+
+def test_adam_step_parity(mxl, ctx):
+    X, Y, M, th = _data(2)
+    dims = [16, 32, 32, 10]
+    net = mxl.Mlp(ctx, dims, th)
+    Xd, Yd, Md = (torch.from_numpy(a).to(DEV) for a in (X, Y, M))
+    t64 = th.astype(np.float64)
+    m = np.zeros_like(t64)
+    v = np.zeros_like(t64)
+    for t in (1, 2, 3):
+        net.loss_grad(Xd, Yd, Md, 1e-4)
+        g = net.grad().astype(np.float64)
+        net.adam_step(t, lr=1e-2)
+        O.adam_step(t64, g, m, v, t, lr=1e-2)
+        assert np.allclose(net.params(), t64, rtol=1e-5, atol=1e-6)
+        net.set_params(t64.astype(np.float32))
+
+
+def test_training_reduces_loss(mxl, ctx):
+    from paper_2006_16852_amd import selector as S
+    rng = np.random.default_rng(4)
+    F = np.abs(rng.standard_normal((120, 16))) * 3
+    T = np.exp(rng.standard_normal((120, S.NCLS)) * 0.3 + F[:, :1] * np.linspace(-0.2, 0.2, S.NCLS))
+    T[::7, 6:8] = np.inf
+    sel0 = S.train(ctx, F, T, epochs=1)
+    sel = S.train(ctx, F, T, epochs=1500)
+    Y, Mk = S.labels_from_times(T)
+
+    def mse(s):
+        P = s.scores(ctx, F)
+        return float(((P - Y) ** 2 * Mk).sum() / Mk.sum())
+    assert mse(sel) < 0.5 * mse(sel0)

@@ -76,7 +76,7 @@ def test_pcg_check_every_independent(mxl, ctx):
     xs = []
     its = []
     for ce in (1, 7, 64):
-        S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-11, check_every=ce)
+        S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-11, check_every=ce, launch_mode=1)
         x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
         info = S.solve(dev(b), x)
         xs.append(x.cpu().numpy())
@@ -99,6 +99,30 @@ def test_pcg_fp32_matches_oracle_definition(mxl, ctx):
     info = S.solve(dev(b32), x)
     assert info["stop_reason"] == mxl.STOP_CONVERGED == ref["stop_reason"]
     assert _close_iters(info["iterations"], ref["iterations"])
+
+
+@pytest.mark.parametrize("A", [W.stencil_2d5(64), W.aniso_3d7(16), W.convdiff_2d5(20)],
+                         ids=lambda a: a.name)
+def test_single_launch_matches_per_step(mxl, ctx, A):
+    """The whole-solve-in-one-workgroup path (small systems) against the
+    per-step kernels and the oracle, with a nonzero initial guess."""
+    b = O.spmv(A, W.uniform_vec(A.nrows, 1))
+    x0 = W.uniform_vec(A.nrows, 9) * 0.1
+    d, _ = O.jacobi_dinv(A)
+    ref = O.pcg(A, b, x0=x0, dinv=d, reduction=1e-10, max_iters=5000)
+    M = matrix(mxl, ctx, A)
+    P = mxl.jacobi(M)
+    out = {}
+    for mode in (1, 2):
+        S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-10, launch_mode=mode)
+        x = dev(x0)
+        out[mode] = (S.solve(dev(b), x), x.cpu().numpy())
+    for mode in (1, 2):
+        info, x = out[mode]
+        assert info["stop_reason"] == ref["stop_reason"], (mode, info)
+        assert _close_iters(info["iterations"], ref["iterations"]), (mode, info["iterations"], ref["iterations"])
+        if ref["stop_reason"] == mxl.STOP_CONVERGED:
+            assert _true_rel(A, b, x) <= 1.01e-10
 
 
 def test_listing_protocol(mxl, ctx):
