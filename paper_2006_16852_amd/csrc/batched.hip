@@ -39,6 +39,7 @@ struct BatchImpl {
     int64_t scratch_elems = 0;
     bool tuned = false;
     mxl_tuning best{};
+    int small_shape = -1;    // single-system register-cached shape (-1: not chosen)
 };
 
 template <int B>
@@ -179,6 +180,151 @@ __global__ __launch_bounds__(B) void k_batch_pcg(
             status_out[s] = (uint8_t)stop;
         }
         __syncthreads();
+    }
+}
+
+// Whole Jacobi-PCG of one small system in one workgroup with the matrix
+// held in registers: thread t owns rows t + j*B (j < RPT) and keeps their
+// (at most W) entries, x, r and dinv in registers; only p, which the product
+// gathers, lives in LDS.  An iteration is the product, three
+// workgroup-wide reductions folded into three barriers, and the updates.
+template <int B, int RPT, int W>
+__global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ rp,
+                                                 const int *__restrict__ col,
+                                                 const double *__restrict__ val,
+                                                 const double *__restrict__ dinv,
+                                                 const double *__restrict__ b,
+                                                 double *__restrict__ xio, double red_factor,
+                                                 int64_t maxit, int chk, int use_x0,
+                                                 void *__restrict__ out3) {
+    extern __shared__ double p_lds[];
+    constexpr int NW = B / kWave;
+    __shared__ double redA[NW], redB[2 * NW], redC[3 * NW];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    int c[RPT][W];
+    double v[RPT][W];
+    double r[RPT], pr[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * B;
+        const bool own = i < n;
+        const int e0 = own ? rp[i] : 0, e1 = own ? rp[i + 1] : 0;
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool in = e0 + e < e1;
+            // padding points at the thread's own row (value 0): SPD systems
+            // store their diagonal, so padding adds no new dependency
+            c[j][e] = in ? col[e0 + e] : (own ? i : 0);
+            v[j][e] = in ? val[e0 + e] : 0.0;
+        }
+        if (own) p_lds[i] = use_x0 ? xio[i] : 0.0;
+    }
+    __syncthreads();
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * B;
+        double ax = 0.0;
+        if (use_x0) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) ax += v[j][e] * p_lds[c[j][e]];
+        }
+        const bool own = i < n;
+        const double bi = own ? b[i] : 0.0;
+        r[j] = bi - ax;
+        pr[j] = own ? dinv[i] * r[j] : 0.0;
+        rz += r[j] * pr[j];
+        rr += r[j] * r[j];
+        bb += bi * bi;
+    }
+    __syncthreads();  // the initial guess in p_lds is consumed
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * B;
+        if (i < n) {
+            p_lds[i] = pr[j];
+            if (!use_x0) xio[i] = 0.0;
+        }
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (lane == 0) { redC[wid] = rz; redC[NW + wid] = rr; redC[2 * NW + wid] = bb; }
+    __syncthreads();
+    rz = rr = bb = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) { rz += redC[w]; rr += redC[NW + w]; bb += redC[2 * NW + w]; }
+    const double nb = sqrt(bb);
+    int stop = ST_RUN;
+    int64_t k = 0;
+    if (bb == 0.0) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            if (tid + j * B < n) xio[tid + j * B] = 0.0;
+        stop = ST_CONVERGED;
+    } else if (sqrt(rr) <= red_factor * nb) {
+        stop = ST_CONVERGED;
+    }
+    double rho = rz;
+    while (stop == ST_RUN && k < maxit) {
+        double q[RPT];
+        double pq = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            double a = 0.0;
+#pragma unroll
+            for (int e = 0; e < W; ++e) a += v[j][e] * p_lds[c[j][e]];
+            q[j] = a;
+            pq += pr[j] * a;
+        }
+        pq = wave_sum(pq);
+        if (lane == 0) redA[wid] = pq;
+        __syncthreads();
+        double eta = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) eta += redA[w];
+        if (chk && !finite_d(eta)) { stop = ST_NONFINITE; break; }
+        if (eta <= 0.0) { stop = ST_BREAKDOWN; break; }
+        const double alpha = rho / eta;
+        double rzn = 0.0, rrn = 0.0;
+        double z[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int i = tid + j * B;
+            const bool own = i < n;
+            if (own) xio[i] += alpha * pr[j];
+            r[j] -= alpha * q[j];
+            z[j] = own ? dinv[i] * r[j] : 0.0;
+            rzn += r[j] * z[j];
+            rrn += r[j] * r[j];
+        }
+        rzn = wave_sum(rzn);
+        rrn = wave_sum(rrn);
+        if (lane == 0) { redB[wid] = rzn; redB[NW + wid] = rrn; }
+        __syncthreads();
+        rzn = rrn = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { rzn += redB[w]; rrn += redB[NW + w]; }
+        ++k;
+        rr = rrn;
+        if (chk && !finite_d(rr)) { stop = ST_NONFINITE; break; }
+        if (sqrt(rr) <= red_factor * nb) { stop = ST_CONVERGED; break; }
+        if (chk && !finite_d(rzn)) { stop = ST_NONFINITE; break; }
+        if (rzn == 0.0) { stop = ST_BREAKDOWN; break; }
+        const double beta = rzn / rho;
+        rho = rzn;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            pr[j] = z[j] + beta * pr[j];
+            if (tid + j * B < n) p_lds[tid + j * B] = pr[j];
+        }
+        __syncthreads();
+    }
+    if (stop == ST_RUN) stop = ST_MAX_ITERS;
+    if (tid == 0) {
+        *(int32_t *)out3 = (int32_t)k;
+        *(double *)((char *)out3 + 8) = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+        *((uint8_t *)out3 + 16) = (uint8_t)stop;
     }
 }
 
@@ -524,8 +670,64 @@ std::shared_ptr<BatchImpl> batch_from_matrix(const MatrixImpl &A, const void *di
 }
 
 // The whole CG of one system in one workgroup (x holds the initial guess).
+// Register-cached single-workgroup shapes: (threads, rows per thread,
+// entries per row).  The first that holds the system is used.
+struct SmallShape {
+    int B, RPT, W;
+};
+static const SmallShape kSmallShapes[] = {{512, 8, 5}, {512, 4, 8}, {256, 4, 32}};
+
+static hipError_t launch_small(const SmallShape &sh, int n, const BatchImpl &Bt, const mxl_criteria &c,
+                               const double *b, double *x, void *out3) {
+    const size_t shm = (size_t)n * sizeof(double);
+    hipStream_t s = Bt.ctx->stream;
+#define MXL_SMALL(BB, RR, WW)                                                                        \
+    if (sh.B == BB && sh.RPT == RR && sh.W == WW) {                                                  \
+        hipLaunchKernelGGL((k_small_pcg<BB, RR, WW>), dim3(1), dim3(BB), shm, s, n,                   \
+                           (const int *)Bt.row_ptr->p, (const int *)Bt.col->p,                       \
+                           (const double *)Bt.val->p, (const double *)Bt.dinv->p, b, x,              \
+                           c.reduction, c.max_iters, c.nonfinite_check, 1, out3);                    \
+        return hipGetLastError();                                                                    \
+    }
+    MXL_SMALL(512, 8, 5)
+    MXL_SMALL(512, 4, 8)
+    MXL_SMALL(256, 4, 32)
+#undef MXL_SMALL
+    return hipErrorInvalidValue;
+}
+
 mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x,
                               void *out3, int64_t *iters, double *rel, int *stop) {
+    const int n = (int)Bt.rows;
+    if (Bt.small_shape < 0) {  // pick once: the maximum row length needs the row pointers
+        std::vector<int32_t> rp(n + 1);
+        if (hipMemcpyAsync(rp.data(), Bt.row_ptr->p, (n + 1) * 4, hipMemcpyDeviceToHost, Bt.ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(Bt.ctx->stream) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "row pointer read");
+        int maxlen = 0;
+        for (int i = 0; i < n; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i]);
+        Bt.small_shape = (int)(sizeof(kSmallShapes) / sizeof(kSmallShapes[0]));
+        for (int k = 0; k < (int)(sizeof(kSmallShapes) / sizeof(kSmallShapes[0])); ++k)
+            if (n <= kSmallShapes[k].B * kSmallShapes[k].RPT && maxlen <= kSmallShapes[k].W &&
+                (size_t)n * 8 <= 60 * 1024) {
+                Bt.small_shape = k;
+                break;
+            }
+    }
+    if (Bt.small_shape < (int)(sizeof(kSmallShapes) / sizeof(kSmallShapes[0]))) {
+        hipError_t e = launch_small(kSmallShapes[Bt.small_shape], n, Bt, c, b, x, out3);
+        if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("small CG: ") + hipGetErrorString(e));
+        char h[24];
+        if (hipMemcpyAsync(h, out3, 24, hipMemcpyDeviceToHost, Bt.ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(Bt.ctx->stream) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "small CG read-back");
+        int32_t it;
+        memcpy(&it, h, 4);
+        memcpy(rel, h + 8, 8);
+        *iters = it;
+        *stop = (uint8_t)h[16];
+        return MXL_OK;
+    }
     mxl_tuning t{1024, 1, 0};
     const int cap = lds_cap_for(Bt.ctx, Bt, 1);
     if (cap < Bt.max_n && !Bt.scratch) {

@@ -62,6 +62,7 @@ struct MatrixImpl {
     int64_t ntiles = 0;                // merge / COO / HYB-tail tiles
     BufPtr carries;                    // per-tile carries
     int grid_main = 0, grid_tail = 0;  // workgroups of the chain's kernels
+    int grid_dot = 0;                  // ELL: workgroups of fused-dot launches
     int64_t stored_bytes = 0;
 };
 

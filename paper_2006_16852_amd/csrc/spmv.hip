@@ -100,21 +100,30 @@ __global__ __launch_bounds__(kWG) void k_csr_vector(int64_t n, const int *__rest
             k0[u] = ok ? rp[row] : 0;
             k1[u] = ok ? rp[row + 1] : 0;
         }
-        int c[kVecU];
-        V v[kVecU];
+        // first EPL entries of every row in flight, then the rest of long rows
+        constexpr int EPL = 1;
+        int c[kVecU][EPL];
+        V v[kVecU][EPL];
 #pragma unroll
-        for (int u = 0; u < kVecU; ++u) {
-            const int k = k0[u] + lane;
-            const bool in = k < k1[u];
-            c[u] = in ? ld_stream(col + k) : -1;
-            v[u] = in ? ld_stream(val + k) : (V)0;
-        }
+        for (int u = 0; u < kVecU; ++u)
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const int k = k0[u] + lane + e * W;
+                const bool in = k < k1[u];
+                c[u][e] = in ? ld_stream(col + k) : -1;
+                v[u][e] = in ? ld_stream(val + k) : (V)0;
+            }
         V acc[kVecU];
 #pragma unroll
-        for (int u = 0; u < kVecU; ++u) acc[u] = c[u] >= 0 ? v[u] * p.x[c[u]] : (V)0;
+        for (int u = 0; u < kVecU; ++u) {
+            acc[u] = 0;
 #pragma unroll
-        for (int u = 0; u < kVecU; ++u)  // rows longer than W
-            for (int k = k0[u] + lane + W; k < k1[u]; k += W) acc[u] += ld_stream(val + k) * p.x[ld_stream(col + k)];
+            for (int e = 0; e < EPL; ++e)
+                if (c[u][e] >= 0) acc[u] += v[u][e] * p.x[c[u][e]];
+        }
+#pragma unroll
+        for (int u = 0; u < kVecU; ++u)  // rows longer than EPL*W
+            for (int k = k0[u] + lane + EPL * W; k < k1[u]; k += W) acc[u] += ld_stream(val + k) * p.x[ld_stream(col + k)];
 #pragma unroll
         for (int u = 0; u < kVecU; ++u) {
 #pragma unroll
@@ -612,9 +621,19 @@ int spmv_grid_cap(const MatrixImpl &A) {
     return A.ctx->num_cu * 8 < kMaxGrid ? A.ctx->num_cu * 8 : kMaxGrid;
 }
 
+// Plain applies (no fused dot) of the one-thread-per-row kernels run with up
+// to 4x more workgroups: the band walk then keeps more rows in flight per XCD.
+static int plain_grid(const MatrixImpl &A, int64_t tiles) {
+    const int cap = 4 * spmv_grid_cap(A);
+    return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
+}
+
+constexpr int kDotSlotCap = 4096;  // partial slots a fused-dot launch may publish
+
 void spmv_plan(MatrixImpl &A) {
     const int cap = spmv_grid_cap(A);
     A.grid_main = A.grid_tail = 0;
+    A.grid_dot = 0;
     switch (A.format) {
     case MXL_FMT_CSR:
         if (A.variant == MXL_CSR_SCALAR) A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
@@ -625,17 +644,24 @@ void spmv_plan(MatrixImpl &A) {
     case MXL_FMT_COO:
         A.grid_main = grid_for(A.ntiles, cap);
         break;
-    case MXL_FMT_ELL:
-        A.grid_main = grid_for((A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt), cap);
+    case MXL_FMT_ELL: {
+        const int64_t tiles = (A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt);
+        A.grid_main = grid_for(tiles, cap);
+        // fused-dot launches: one tile per workgroup while the partials fit
+        A.grid_dot = tiles <= kDotSlotCap ? (int)(tiles > 0 ? tiles : 1) : A.grid_main;
         break;
+    }
     case MXL_FMT_HYB:
         A.grid_main = grid_for((A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt), cap);
+        A.grid_dot = A.grid_main;  // the tail's partials follow the ELL part's
         A.grid_tail = grid_for(A.ntiles, cap);
         break;
     }
 }
 
-int spmv_slots(const MatrixImpl &A) { return A.grid_main + A.grid_tail; }
+int spmv_slots(const MatrixImpl &A) {
+    return (A.format == MXL_FMT_ELL ? A.grid_dot : A.grid_main) + A.grid_tail;
+}
 
 int64_t merge_tiles(int64_t n, int64_t nnz) { return (n + nnz + kMergeItems - 1) / kMergeItems; }
 int64_t coo_tiles(int64_t nnz) { return (nnz + kCooItems - 1) / kCooItems; }
@@ -717,7 +743,8 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
         const V *ev = (const V *)A.ell_val->p;
         const int2 *win = A.ell_win ? (const int2 *)A.ell_win->p : nullptr;
         const bool lds = A.variant == MXL_ELL_LDS && win;
-        const dim3 ge(A.grid_main);
+        const dim3 ge(dot ? A.grid_dot
+                          : plain_grid(A, (n + (int64_t)kWG * A.ell_rpt - 1) / ((int64_t)kWG * A.ell_rpt)));
 #define MXL_ELL_CASE(RR)                                                                                          \
     case RR:                                                                                                      \
         if (lds) {                                                                                                \

@@ -159,9 +159,13 @@ class Selector:
         return int(order[0]), info
 
 
-def train(ctx, F: np.ndarray, T: np.ndarray, epochs: int = 2000, lr: float = 1e-3,
-          lam: float = 1e-4, seed: int = 0) -> Selector:
-    """Fit the MLP on the GPU (full batch, Adam) to log time ratios."""
+def train(ctx, F: np.ndarray, T: np.ndarray, epochs: int = 4000, lr: float = 3e-3,
+          lam: float = 1e-3, seed: int = 0) -> Selector:
+    """Fit the MLP on the GPU (full batch, Adam) to log time ratios.
+
+    Defaults chosen by 5-fold cross-validation of the mean time regret on the
+    training split of the skewed suite (epochs in {2000, 4000}, lr in
+    {1e-3, 3e-3}, weight decay in {1e-4, 1e-3, 1e-2}, widths 32 and 64)."""
     Ft = transform(F)
     mean = Ft.mean(axis=0)
     std = Ft.std(axis=0)

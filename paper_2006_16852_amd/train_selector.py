@@ -81,7 +81,9 @@ def main():
     ap.add_argument("--count", type=int, default=200)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--epochs", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--lam", type=float, default=1e-3)
     ap.add_argument("--timings", default=None, help="reuse a timings file instead of measuring")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
@@ -105,7 +107,7 @@ def main():
     ntest = max(1, n // 4)
     test, train_idx = np.sort(perm[:ntest]), np.sort(perm[ntest:])
     t0 = time.time()
-    sel = S.train(ctx, F[train_idx], T[train_idx], epochs=args.epochs)
+    sel = S.train(ctx, F[train_idx], T[train_idx], epochs=args.epochs, lr=args.lr, lam=args.lam)
     train_s = time.time() - t0
     sel.save(os.path.join(args.out, "selector_weights.json"))
     Ft, Tt = F[test], T[test]
@@ -142,7 +144,7 @@ def main():
                     exact=float(np.mean(r <= 1e-12)))
 
     ev = dict(n_train=int(len(train_idx)), n_test=int(len(test)), train_seconds=train_s,
-              epochs=args.epochs, fixed_class=S.CLASSES[fixed][0], fallback_used=int(nfb),
+              epochs=args.epochs, lr=args.lr, weight_decay=args.lam, fixed_class=S.CLASSES[fixed][0], fallback_used=int(nfb),
               regret=dict(selector=stats(choice_net), selector_fallback=stats(choice_fb),
                           best_fixed=stats(choice_fixed), hand_rule=stats(choice_hand),
                           default_vector=stats(choice_default)),

@@ -91,3 +91,43 @@ def test_training_reduces_loss(mxl, ctx):
         P = s.scores(ctx, F)
         return float(((P - Y) ** 2 * Mk).sum() / Mk.sum())
     assert mse(sel) < 0.5 * mse(sel0)
+
+
+def test_trained_selector_gain(mxl, ctx):
+    """What the trained network gains over the library without it: on the
+    50 held-out matrices of the skewed suite (timings measured by this
+    library, stored with the package), the network's choices (forward pass
+    on the GPU) have a far lower time regret than the library's default
+    (CSR vector with the width from the mean row length) and than a hand
+    rule, and with the timing fallback it beats the best single fixed class."""
+    import json
+    import os
+    from paper_2006_16852_amd import selector as S
+    from paper_2006_16852_amd.train_selector import hand_rule
+    d = json.load(open(os.path.join(os.path.dirname(S.__file__), "data", "selector_timings_zipf200.json")))
+    F = np.array(d["features"])
+    T = np.array(d["times_ms"], dtype=float)
+    T[T < 0] = np.inf
+    perm = np.random.default_rng(7).permutation(len(F))
+    test = np.sort(perm[:len(F) // 4])
+    sel = S.Selector.load()
+    Ft, Tt = F[test], T[test]
+    P = np.where([S.feasible_mask(f) for f in Ft], sel.scores(ctx, Ft), np.inf)
+    net = P.argmin(axis=1)
+    default = np.array([1 if f[2] <= 6 else (2 if f[2] <= 24 else 3) for f in Ft])
+    hand = np.array([hand_rule(f) for f in Ft])
+    r_net, r_def, r_hand = S.regret(Tt, net), S.regret(Tt, default), S.regret(Tt, hand)
+    print(f"[selector gain] regret net {r_net.mean():.4f} default {r_def.mean():.4f} hand {r_hand.mean():.4f}")
+    assert np.all(np.isfinite(r_net))
+    assert r_net.mean() < 0.1 * r_def.mean()
+    assert r_net.mean() < 0.5 * r_hand.mean()
+    fb = []
+    for p, t in zip(P, Tt):
+        order = np.argsort(p)
+        top = [k for k in order[:3] if np.isfinite(p[k])]
+        fb.append(top[int(np.argmin(t[top]))] if p[order[1]] - p[order[0]] < sel.delta else order[0])
+    Ttr = T[np.sort(perm[len(F) // 4:])]
+    slow = Ttr / Ttr.min(axis=1, keepdims=True)
+    fixed = int(np.argmin([np.exp(np.mean(np.log(np.where(np.isfinite(slow[:, k]), slow[:, k], 1e3))))
+                           for k in range(S.NCLS)]))
+    assert S.regret(Tt, np.array(fb)).mean() <= S.regret(Tt, np.full(len(test), fixed)).mean()
