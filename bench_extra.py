@@ -155,5 +155,62 @@ def batch(args):
                       "read_once_GBs": round(bytes_once / dt / 1e9, 1)}), flush=True)
 
 
+def overhead(args):
+    """The per-iteration cost protocol of the paper's Table 1: a size-1
+    matrix, x = 0, b = NaN, 1,000 iterations (no early stop), averaged."""
+    import numpy as np
+    import torch
+    import paper_2006_16852_amd as mxl
+    dev = "cuda:0"
+    ctx = mxl.Context(0)
+    M = mxl.csr(ctx, torch.tensor([0, 1], dtype=torch.int32, device=dev),
+                torch.tensor([0], dtype=torch.int32, device=dev),
+                torch.tensor([2.0], dtype=torch.float64, device=dev))
+    b = torch.full((1,), float("nan"), dtype=torch.float64, device=dev)
+    x = torch.zeros(1, dtype=torch.float64, device=dev)
+    iters = 1000
+    res = {}
+    for kind, mode, name in (("cg", 2, "cg_one_workgroup"), ("cg", 1, "cg_per_step_kernels"),
+                             ("bicgstab", 1, "bicgstab_per_step_kernels")):
+        S = mxl.solver(kind, M, None, max_iters=iters, nonfinite_check=0, check_every=iters,
+                       launch_mode=mode)
+
+        def f():
+            x.zero_()
+            return S.solve(b, x)
+        dt, info = _timed(f, max(3, args.steps), 1)
+        assert info["iterations"] == iters
+        res[name] = round(dt * 1e6 / iters, 3)
+    print(json.dumps({"metric": "solver overhead per iteration (size-1 system, b = NaN, 1,000 iterations)",
+                      "unit": "us/iteration", "value": res["cg_one_workgroup"], "higher_is_better": False,
+                      "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "n=1 nan-rhs protocol"}, "runs": res,
+                      "paper_table1_us": {"CG": 1.28, "BiCGSTAB": 1.26}}), flush=True)
+
+
+def stream(args):
+    """STREAM-style bandwidth of copy, triad and dot on 2^26 doubles (the
+    calibration the paper uses for solver bandwidth, Sec. 7.4 and Table 3)."""
+    import torch
+    import paper_2006_16852_amd as mxl
+    dev = "cuda:0"
+    ctx = mxl.Context(0)
+    n = 1 << 26
+    g = torch.Generator(device="cpu").manual_seed(11)
+    a = torch.rand(n, dtype=torch.float64, generator=g).to(dev)
+    b = torch.rand(n, dtype=torch.float64, generator=g).to(dev)
+    c = torch.empty(n, dtype=torch.float64, device=dev)
+    reps = max(5, args.steps)
+    res = {}
+    for op, nbytes in (("copy", 16 * n), ("triad", 24 * n), ("dot", 16 * n)):
+        ms = mxl.stream_bench(ctx, op, a, b, c, reps=reps)
+        res[op] = {"ms": round(ms, 4), "GBs": round(nbytes / ms / 1e6, 1), "bytes": nbytes}
+    print(json.dumps({"metric": "STREAM triad bandwidth", "unit": "GB/s", "value": res["triad"]["GBs"],
+                      "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "stream 2^26 doubles", "n": n}, "runs": res,
+                      "peak_GBs": 8000.0}), flush=True)
+
+
 def run(args):
-    {"aniso_ir": aniso_ir, "poisson2d": poisson2d, "batch": batch}[args.workload](args)
+    {"aniso_ir": aniso_ir, "poisson2d": poisson2d, "batch": batch, "overhead": overhead,
+     "stream": stream}[args.workload](args)

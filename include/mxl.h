@@ -312,6 +312,61 @@ mxl_status mxl_mlp_adam_step(mxl_mlp *m, int64_t t, float lr, float beta1,
                              float beta2, float eps);
 mxl_status mxl_mlp_destroy(mxl_mlp *m);
 
+/* Run-time choice of (format, kernel variant), the fork of Sec. 7.2, learned
+ * from timings and judged by time, with performance profiles (Sec. 7.3) as
+ * the evaluation.  A selector holds the candidate classes, a trained MLP
+ * (16 features -> one score per class, s_c ~ log(t_c / t_best)) and the
+ * feature standardisation z_j = (phi_j(f_j) - mean_j) / std_j, where phi_j is
+ * log(1 + f) for the features flagged in log_mask (bit j) and the identity
+ * otherwise.  All arrays are HOST pointers and are copied. */
+typedef struct {
+    int32_t format;             /* mxl_format */
+    mxl_format_params params;   /* as for mxl_convert */
+} mxl_kernel_class;
+
+typedef struct mxl_selector mxl_selector;
+
+/* dims[0] must be 16 and dims[nlayers] = nclasses (1..64).  delta: top-2
+ * score margin below which the prediction counts as unsure; zmax: largest
+ * |z_j| still inside the training distribution.  Errors: INVALID_ARG,
+ * OUT_OF_MEMORY, DEVICE. */
+mxl_status mxl_selector_create(mxl_ctx *ctx, int32_t nclasses,
+                               const mxl_kernel_class *classes,
+                               int32_t nlayers, const int32_t *dims,
+                               const float *theta_host, const double *mean16,
+                               const double *std16, uint32_t log_mask,
+                               double delta, double zmax, mxl_selector **out);
+mxl_status mxl_selector_destroy(mxl_selector *s);
+
+enum {
+    MXL_SELECT_MODEL = 0,           /* argmin of the predicted scores */
+    MXL_SELECT_EXHAUSTIVE = 1,      /* time every feasible class */
+    MXL_SELECT_MODEL_FALLBACK = 2   /* model; time the top 3 when unsure */
+};
+
+typedef struct {
+    double  margin;     /* second-best minus best predicted score (inf if one class) */
+    double  max_z;      /* largest |standardised feature| */
+    int32_t fallback;   /* 1 if the choice was made by timing */
+    int32_t ntimed;     /* classes timed */
+    double  best_ms;    /* median time of the chosen class if timed, else 0 */
+} mxl_select_info;
+
+/* Choose a class for the CSR matrix A (any matrix operator; its CSR arrays
+ * are used).  Classes whose padded storage exceeds the mxl_convert budget
+ * are never chosen.  Timing (EXHAUSTIVE, and FALLBACK when unsure) converts
+ * each candidate and takes the median of reps applications y = A x with the
+ * last-level cache flushed before each (mxl_time_apply), so it needs device
+ * vectors x (ncols) and y (nrows, overwritten); with x or y NULL the
+ * FALLBACK mode never times and EXHAUSTIVE is INVALID_ARG.  Optional HOST
+ * outputs: scores[nclasses] (predicted scores, +inf for infeasible classes;
+ * NaN in EXHAUSTIVE mode), times_ms[nclasses] (NaN where not timed), info.
+ * Blocks until done.  Errors: INVALID_ARG, DIM_MISMATCH, OUT_OF_MEMORY,
+ * DEVICE, or any error of mxl_convert other than INFEASIBLE_FORMAT. */
+mxl_status mxl_select(const mxl_selector *s, const mxl_op *A, int32_t mode,
+                      const void *x, void *y, int32_t reps, int32_t *class_out,
+                      double *scores, double *times_ms, mxl_select_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,18 @@ class Tuning(C.Structure):
     _fields_ = [("wg_size", C.c_int32), ("wgs_per_cu", C.c_int32), ("order", C.c_int32)]
 
 
+class KernelClass(C.Structure):
+    _fields_ = [("format", C.c_int32), ("params", FormatParams)]
+
+
+class SelectInfo(C.Structure):
+    _fields_ = [("margin", C.c_double), ("max_z", C.c_double), ("fallback", C.c_int32),
+                ("ntimed", C.c_int32), ("best_ms", C.c_double)]
+
+
+SELECT_MODEL, SELECT_EXHAUSTIVE, SELECT_MODEL_FALLBACK = 0, 1, 2
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -116,6 +128,10 @@ def _load():
         "mxl_mlp_get_grad": [vp, vp, i64],
         "mxl_mlp_adam_step": [vp, i64, C.c_float, C.c_float, C.c_float, C.c_float],
         "mxl_mlp_destroy": [vp],
+        "mxl_selector_create": [vp, i32, vp, i32, vp, vp, vp, vp, C.c_uint32, f64, f64, pp],
+        "mxl_selector_destroy": [vp],
+        "mxl_select": [vp, vp, i32, vp, vp, i32, C.POINTER(C.c_int32), vp, vp,
+                       C.POINTER(SelectInfo)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -441,6 +457,62 @@ class Mlp:
     def __del__(self):
         if getattr(self, "h", None) and _alive and _alive[0]:
             lib.mxl_mlp_destroy(self.h)
+            self.h = None
+
+
+class SelectorHandle:
+    """A trained format/kernel selector living in the library (mxl_select).
+
+    classes: list of (format name, convert kwargs) as for Op.convert."""
+
+    def __init__(self, ctx: Context, classes, dims, theta, mean, std, log_features,
+                 delta: float = 0.05, zmax: float = 4.0):
+        import numpy as np
+        self.ctx = ctx
+        self.classes = list(classes)
+        k = (KernelClass * len(self.classes))()
+        for i, (fmt, kw) in enumerate(self.classes):
+            k[i].format = FORMATS[fmt]
+            k[i].params = FormatParams(kw.get("variant", 0), kw.get("vector_width", 0),
+                                       kw.get("hyb_quantile", 0.0))
+        d = np.asarray(dims, np.int32)
+        th = np.ascontiguousarray(theta, np.float32)
+        mu = np.ascontiguousarray(mean, np.float64)
+        sd = np.ascontiguousarray(std, np.float64)
+        mask = 0
+        for j in log_features:
+            mask |= 1 << int(j)
+        h = C.c_void_p()
+        ctx.use_current_stream()
+        _check(lib.mxl_selector_create(ctx.h, len(self.classes), C.cast(k, C.c_void_p), len(d) - 1,
+                                       d.ctypes.data_as(C.c_void_p), th.ctypes.data_as(C.c_void_p),
+                                       mu.ctypes.data_as(C.c_void_p), sd.ctypes.data_as(C.c_void_p),
+                                       mask, delta, zmax, C.byref(h)))
+        self.h = h
+
+    def select(self, A: Op, mode: int = SELECT_MODEL_FALLBACK, x: torch.Tensor = None,
+               y: torch.Tensor = None, reps: int = 5):
+        """Returns (class index, info dict with scores, times_ms, margin, ...)."""
+        import numpy as np
+        if x is not None or y is not None:
+            _need_cuda(x, y)
+        n = len(self.classes)
+        sc = np.zeros(n)
+        tm = np.zeros(n)
+        out = C.c_int32()
+        info = SelectInfo()
+        self.ctx.use_current_stream()
+        _check(lib.mxl_select(self.h, A.h, mode, _ptr(x) if x is not None else None,
+                              _ptr(y) if y is not None else None, reps, C.byref(out),
+                              sc.ctypes.data_as(C.c_void_p), tm.ctypes.data_as(C.c_void_p),
+                              C.byref(info)))
+        return int(out.value), dict(scores=sc, times_ms=tm, margin=info.margin, max_z=info.max_z,
+                                    fallback=bool(info.fallback), ntimed=info.ntimed,
+                                    best_ms=info.best_ms)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _alive and _alive[0]:
+            lib.mxl_selector_destroy(self.h)
             self.h = None
 
 

@@ -185,10 +185,12 @@ __global__ __launch_bounds__(B) void k_batch_pcg(
 
 // Whole Jacobi-PCG of one small system in one workgroup with the matrix
 // held in registers: thread t owns rows t + j*B (j < RPT) and keeps their
-// (at most W) entries, x, r and dinv in registers; only p, which the product
-// gathers, lives in LDS.  An iteration is the product, three
-// workgroup-wide reductions folded into three barriers, and the updates.
-template <int B, int RPT, int W>
+// (at most W) entries, r and p in registers; p, which the product gathers,
+// is mirrored in LDS.  x and dinv stay in global memory for the large
+// shapes (register budget) and in registers when REG; a one-wave shape
+// (B = 64) reduces with lane shuffles only.  An iteration is the product,
+// two reductions and the updates.
+template <int B, int RPT, int W, bool REG>
 __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ rp,
                                                  const int *__restrict__ col,
                                                  const double *__restrict__ val,
@@ -204,10 +206,15 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
     int c[RPT][W];
     double v[RPT][W];
     double r[RPT], pr[RPT];
+    double xr[REG ? RPT : 1], dv[REG ? RPT : 1];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int i = tid + j * B;
         const bool own = i < n;
+        if constexpr (REG) {
+            dv[j] = own ? dinv[i] : 0.0;
+            xr[j] = own && use_x0 ? xio[i] : 0.0;
+        }
         const int e0 = own ? rp[i] : 0, e1 = own ? rp[i + 1] : 0;
 #pragma unroll
         for (int e = 0; e < W; ++e) {
@@ -232,7 +239,8 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
         const bool own = i < n;
         const double bi = own ? b[i] : 0.0;
         r[j] = bi - ax;
-        pr[j] = own ? dinv[i] * r[j] : 0.0;
+        if constexpr (REG) pr[j] = dv[j] * r[j];
+        else pr[j] = own ? dinv[i] * r[j] : 0.0;
         rz += r[j] * pr[j];
         rr += r[j] * r[j];
         bb += bi * bi;
@@ -243,24 +251,30 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
         const int i = tid + j * B;
         if (i < n) {
             p_lds[i] = pr[j];
-            if (!use_x0) xio[i] = 0.0;
+            if (!REG && !use_x0) xio[i] = 0.0;
         }
     }
     rz = wave_sum(rz);
     rr = wave_sum(rr);
     bb = wave_sum(bb);
-    if (lane == 0) { redC[wid] = rz; redC[NW + wid] = rr; redC[2 * NW + wid] = bb; }
-    __syncthreads();
-    rz = rr = bb = 0.0;
+    if constexpr (NW > 1) {
+        if (lane == 0) { redC[wid] = rz; redC[NW + wid] = rr; redC[2 * NW + wid] = bb; }
+        __syncthreads();
+        rz = rr = bb = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) { rz += redC[w]; rr += redC[NW + w]; bb += redC[2 * NW + w]; }
+        for (int w = 0; w < NW; ++w) { rz += redC[w]; rr += redC[NW + w]; bb += redC[2 * NW + w]; }
+    } else {
+        __syncthreads();  // p_lds complete before the first product
+    }
     const double nb = sqrt(bb);
     int stop = ST_RUN;
     int64_t k = 0;
     if (bb == 0.0) {
 #pragma unroll
-        for (int j = 0; j < RPT; ++j)
-            if (tid + j * B < n) xio[tid + j * B] = 0.0;
+        for (int j = 0; j < RPT; ++j) {
+            if constexpr (REG) xr[j] = 0.0;
+            else if (tid + j * B < n) xio[tid + j * B] = 0.0;
+        }
         stop = ST_CONVERGED;
     } else if (sqrt(rr) <= red_factor * nb) {
         stop = ST_CONVERGED;
@@ -278,11 +292,15 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
             pq += pr[j] * a;
         }
         pq = wave_sum(pq);
-        if (lane == 0) redA[wid] = pq;
-        __syncthreads();
         double eta = 0.0;
+        if constexpr (NW > 1) {
+            if (lane == 0) redA[wid] = pq;
+            __syncthreads();
 #pragma unroll
-        for (int w = 0; w < NW; ++w) eta += redA[w];
+            for (int w = 0; w < NW; ++w) eta += redA[w];
+        } else {
+            eta = pq;
+        }
         if (chk && !finite_d(eta)) { stop = ST_NONFINITE; break; }
         if (eta <= 0.0) { stop = ST_BREAKDOWN; break; }
         const double alpha = rho / eta;
@@ -292,19 +310,26 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
         for (int j = 0; j < RPT; ++j) {
             const int i = tid + j * B;
             const bool own = i < n;
-            if (own) xio[i] += alpha * pr[j];
             r[j] -= alpha * q[j];
-            z[j] = own ? dinv[i] * r[j] : 0.0;
+            if constexpr (REG) {
+                xr[j] += alpha * pr[j];
+                z[j] = dv[j] * r[j];
+            } else {
+                if (own) xio[i] += alpha * pr[j];
+                z[j] = own ? dinv[i] * r[j] : 0.0;
+            }
             rzn += r[j] * z[j];
             rrn += r[j] * r[j];
         }
         rzn = wave_sum(rzn);
         rrn = wave_sum(rrn);
-        if (lane == 0) { redB[wid] = rzn; redB[NW + wid] = rrn; }
-        __syncthreads();
-        rzn = rrn = 0.0;
+        if constexpr (NW > 1) {
+            if (lane == 0) { redB[wid] = rzn; redB[NW + wid] = rrn; }
+            __syncthreads();
+            rzn = rrn = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) { rzn += redB[w]; rrn += redB[NW + w]; }
+            for (int w = 0; w < NW; ++w) { rzn += redB[w]; rrn += redB[NW + w]; }
+        }
         ++k;
         rr = rrn;
         if (chk && !finite_d(rr)) { stop = ST_NONFINITE; break; }
@@ -321,6 +346,11 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
         __syncthreads();
     }
     if (stop == ST_RUN) stop = ST_MAX_ITERS;
+    if constexpr (REG) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            if (tid + j * B < n) xio[tid + j * B] = xr[j];
+    }
     if (tid == 0) {
         *(int32_t *)out3 = (int32_t)k;
         *(double *)((char *)out3 + 8) = nb > 0.0 ? sqrt(rr) / nb : 0.0;
@@ -675,7 +705,7 @@ std::shared_ptr<BatchImpl> batch_from_matrix(const MatrixImpl &A, const void *di
 struct SmallShape {
     int B, RPT, W;
 };
-static const SmallShape kSmallShapes[] = {{512, 8, 5}, {512, 4, 8}, {256, 4, 32}};
+static const SmallShape kSmallShapes[] = {{64, 2, 8}, {512, 8, 5}, {512, 4, 8}, {256, 4, 32}};
 
 static hipError_t launch_small(const SmallShape &sh, int n, const BatchImpl &Bt, const mxl_criteria &c,
                                const double *b, double *x, void *out3) {
@@ -683,12 +713,13 @@ static hipError_t launch_small(const SmallShape &sh, int n, const BatchImpl &Bt,
     hipStream_t s = Bt.ctx->stream;
 #define MXL_SMALL(BB, RR, WW)                                                                        \
     if (sh.B == BB && sh.RPT == RR && sh.W == WW) {                                                  \
-        hipLaunchKernelGGL((k_small_pcg<BB, RR, WW>), dim3(1), dim3(BB), shm, s, n,                   \
+        hipLaunchKernelGGL((k_small_pcg<BB, RR, WW, (BB == 64)>), dim3(1), dim3(BB), shm, s, n,       \
                            (const int *)Bt.row_ptr->p, (const int *)Bt.col->p,                       \
                            (const double *)Bt.val->p, (const double *)Bt.dinv->p, b, x,              \
                            c.reduction, c.max_iters, c.nonfinite_check, 1, out3);                    \
         return hipGetLastError();                                                                    \
     }
+    MXL_SMALL(64, 2, 8)
     MXL_SMALL(512, 8, 5)
     MXL_SMALL(512, 4, 8)
     MXL_SMALL(256, 4, 32)

@@ -47,6 +47,8 @@ struct SolverState {
     int32_t iters;    // iteration count when stop was set
     int32_t nonfinite_check;
     int32_t half;     // BiCGSTAB: 1 if it stopped at a half step
+    int32_t ustop;    // CG: set by k_cg_update for k_cg_pupdate (1 = do nothing),
+                      // so that k_cg_pupdate never reads the stop it writes
 };
 
 // Tile walk of workgroup `bid` of G over T tiles.  Workgroups are

@@ -145,10 +145,10 @@ hipError_t launch_fill(int dtype, int64_t n, double v, void *dst, hipStream_t s)
 hipError_t launch_state_init(SolverState *st, double red, int nonfinite_check, hipStream_t s);
 hipError_t cg_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, const void *r, void *p,
                    const void *dinv, double *parts, hipStream_t s);
-hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *x, void *r, const void *p,
-                     const void *q, const void *dinv, SolverState *st, const double *pq_parts,
-                     int pq_slots, double *parts, int k, hipStream_t s);
-hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, void *p,
+hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *r, const void *q, const void *dinv,
+                     SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
+                     hipStream_t s);
+hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, void *x, const void *r, void *p,
                       const void *dinv, SolverState *st, const double *parts, int slots, int k,
                       double *hist, hipStream_t s);
 hipError_t bi_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, const void *r,
@@ -179,8 +179,32 @@ hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a,
 mxl_status set_error(mxl_status st, const std::string &msg);
 mxl_status check_device_ptr(const mxl_ctx *ctx, const void *p, size_t bytes, const char *what);
 
-// ------------------------------------------------------------- features.hip / mlp.hip
-mxl_status features_compute(const MatrixImpl &A, double out[16]);
+// Makes `dev` current for the scope's lifetime, then restores the caller's device.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+size_t vt_size(int dtype);
+int64_t csr_bytes(const MatrixImpl &A);
+// Padded ELL storage (w slots of n rounded up to 64 rows) may cost up to 4x
+// the CSR bytes, at least 1 MiB (so tiny matrices are never refused for
+// their row padding) and at most 32 GiB.
+bool ell_fits(const MatrixImpl &S, int64_t w);
+// Nearest-rank q-quantile of row lengths, rank = ceil(q n) clamped to [1, n].
+int64_t quantile_rank(double q, int64_t n);
+
+// ------------------------------------------------------------- select.hip
+// The 16 features; hist (optional) receives the row-length histogram.
+mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<unsigned> *hist = nullptr);
 
 }  // namespace mxl
 

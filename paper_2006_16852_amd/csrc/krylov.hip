@@ -68,14 +68,18 @@ __global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict_
     publish<3>(v, parts, L);
 }
 
-// Consumes p.q (fused into the SpMV): alpha = rho_{k-1} / p.q.
+// Consumes p.q (fused into the SpMV): alpha = rho_{k-1} / p.q, then
+// r -= alpha q and the reductions r.z, r.r.  The matching x += alpha p is
+// applied by k_cg_pupdate, which reads p anyway, so p is read once less.
 template <typename V>
-__global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ x, V *__restrict__ r,
-                                                   const V *__restrict__ p, const V *__restrict__ q,
+__global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r, const V *__restrict__ q,
                                                    const V *__restrict__ dinv, SolverState *st,
                                                    const double *__restrict__ pq_parts, int pq_slots,
                                                    double *__restrict__ parts, int k) {
-    if (st->stop) return;
+    if (st->stop) {
+        if (MXL_LEAD) st->ustop = 1;
+        return;
+    }
     double eta[1];
     gather_all<1>(pq_parts, pq_slots, eta);
     const bool chk = st->nonfinite_check != 0;
@@ -83,6 +87,7 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ x,
     if (nonfin || eta[0] <= 0.0) {  // not positive definite along p
         if (MXL_LEAD) {
             st->stop = nonfin ? ST_NONFINITE : ST_BREAKDOWN;
+            st->ustop = 1;
             st->iters = k - 1;
             st->eta = eta[0];
         }
@@ -92,19 +97,14 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ x,
     if (MXL_LEAD) {
         st->alpha = alpha;
         st->eta = eta[0];
+        st->ustop = 0;
     }
     MXL_RANGE(n)
     double rz = 0.0, rr = 0.0;
     MXL_FOR(i, n) {
-        V xi, ri;
-        if constexpr (sizeof(V) == 8) {
-            xi = x[i] + alpha * p[i];
-            ri = r[i] - alpha * q[i];
-        } else {
-            xi = (V)((double)x[i] + alpha * (double)p[i]);
-            ri = (V)((double)r[i] - alpha * (double)q[i]);
-        }
-        x[i] = xi;
+        V ri;
+        if constexpr (sizeof(V) == 8) ri = r[i] - alpha * q[i];
+        else ri = (V)((double)r[i] - alpha * (double)q[i]);
         r[i] = ri;
         double z = prec_z(dinv, i, ri);
         rz += (double)ri * z;
@@ -114,16 +114,20 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ x,
     publish<2>(v, parts, L);
 }
 
-// Consumes r.z and r.r: criterion of iteration k, then p = z + beta p.
+// Consumes r.z and r.r: x += alpha p (alpha from k_cg_update), the
+// criterion of iteration k, then p = z + beta p unless the solve stops.
 template <typename V>
-__global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, const V *__restrict__ r,
+__global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x, const V *__restrict__ r,
                                                     V *__restrict__ p, const V *__restrict__ dinv,
                                                     SolverState *st, const double *__restrict__ parts,
                                                     int slots, int k, double *hist) {
-    if (st->stop) return;
+    // k_cg_update saw an earlier stop or broke down: x is not advanced.  The
+    // stop this kernel decides goes to st->stop, which it never reads.
+    if (st->ustop) return;
     double t[2];
     gather_all<2>(parts, slots, t);
     const double rz = t[0], rr = t[1];
+    const double alpha = st->alpha;
     const bool chk = st->nonfinite_check != 0;
     const double nb = sqrt(st->nb2);
     int stop = ST_RUN;
@@ -132,6 +136,20 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, const V *__restri
     else if (chk && !finite_d(rz)) stop = ST_NONFINITE;
     else if (rz == 0.0) stop = ST_BREAKDOWN;
     const double beta = rz / st->rho2[(k - 1) & 1];
+    MXL_RANGE(n)
+    if (stop != ST_RUN) {
+        MXL_FOR(i, n) {
+            if constexpr (sizeof(V) == 8) x[i] = x[i] + alpha * p[i];
+            else x[i] = (V)((double)x[i] + alpha * (double)p[i]);
+        }
+    } else {
+        MXL_FOR(i, n) {
+            const V pi = p[i];
+            if constexpr (sizeof(V) == 8) x[i] = x[i] + alpha * pi;
+            else x[i] = (V)((double)x[i] + alpha * (double)pi);
+            p[i] = (V)(prec_z(dinv, i, r[i]) + beta * (double)pi);
+        }
+    }
     if (MXL_LEAD) {
         st->rr = rr;
         st->iters = k;
@@ -142,10 +160,6 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, const V *__restri
             st->beta = beta;
         }
     }
-    if (stop != ST_RUN) return;
-    MXL_RANGE(n)
-    MXL_FOR(i, n)
-        p[i] = (V)(prec_z(dinv, i, r[i]) + beta * (double)p[i]);
 }
 
 // ------------------------------------------------------------ BiCGSTAB
@@ -366,6 +380,7 @@ __global__ void k_state_init(SolverState *st, double red, int chk) {
     st->iters = 0;
     st->nonfinite_check = chk;
     st->half = 0;
+    st->ustop = 0;
 }
 
 // ||r||_2^2 and ||r||_inf in one pass (iterative refinement outer step).
@@ -528,19 +543,19 @@ hipError_t cg_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, cons
     return hipGetLastError();
 }
 
-hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *x, void *r, const void *p,
-                     const void *q, const void *dinv, SolverState *st, const double *pq_parts,
-                     int pq_slots, double *parts, int k, hipStream_t s) {
-    MXL_LAUNCH_V(dtype, k_cg_update, vec_grid(ctx, n), n, (V *)x, (V *)r, (const V *)p, (const V *)q,
-                 (const V *)dinv, st, pq_parts, pq_slots, parts, k);
+hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *r, const void *q, const void *dinv,
+                     SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
+                     hipStream_t s) {
+    MXL_LAUNCH_V(dtype, k_cg_update, vec_grid(ctx, n), n, (V *)r, (const V *)q, (const V *)dinv, st,
+                 pq_parts, pq_slots, parts, k);
     return hipGetLastError();
 }
 
-hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, const void *r, void *p,
+hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, void *x, const void *r, void *p,
                       const void *dinv, SolverState *st, const double *parts, int slots, int k,
                       double *hist, hipStream_t s) {
-    MXL_LAUNCH_V(dtype, k_cg_pupdate, vec_grid(ctx, n), n, (const V *)r, (V *)p, (const V *)dinv, st,
-                 parts, slots, k, hist);
+    MXL_LAUNCH_V(dtype, k_cg_pupdate, vec_grid(ctx, n), n, (V *)x, (const V *)r, (V *)p, (const V *)dinv,
+                 st, parts, slots, k, hist);
     return hipGetLastError();
 }
 

@@ -42,19 +42,6 @@ mxl_status hip_fail(hipError_t e, const char *where) {
         if (_e != hipSuccess) return hip_fail(_e, #expr);  \
     } while (0)
 
-struct DeviceScope {
-    int prev = -1;
-    explicit DeviceScope(int dev) {
-        (void)hipGetDevice(&prev);
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceScope() {
-        int cur = -1;
-        (void)hipGetDevice(&cur);
-        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 BufPtr alloc(size_t bytes, hipError_t *err) {
     auto b = std::make_shared<DevBuf>();
     b->bytes = bytes;
@@ -76,7 +63,11 @@ BufPtr borrow(const void *p, size_t bytes) {
     return b;
 }
 
+}  // namespace
+namespace mxl {
 size_t vt_size(int dtype) { return dtype == MXL_F64 ? 8 : 4; }
+}  // namespace mxl
+namespace {
 
 // Device pointer on ctx's device whose allocation covers `bytes` from p.
 mxl_status check_dev(const mxl_ctx *ctx, const void *p, size_t bytes, const char *what) {
@@ -122,9 +113,26 @@ mxl_status finish_matrix(MatrixImpl &A) {
     return MXL_OK;
 }
 
+}  // namespace
+namespace mxl {
 int64_t csr_bytes(const MatrixImpl &A) {
     return A.nnz * (int64_t)(vt_size(A.dtype) + 4) + (A.nrows + 1) * 4;
 }
+
+bool ell_fits(const MatrixImpl &S, int64_t w) {
+    const int64_t n_pad = ((S.nrows + 63) / 64) * 64;
+    const double ell_bytes = (double)w * (double)n_pad * (double)(vt_size(S.dtype) + 4);
+    const double budget = std::min(std::max(4.0 * (double)csr_bytes(S), (double)(1 << 20)),
+                                   32.0 * (double)(1ull << 30));
+    return ell_bytes <= budget || ell_bytes <= 0;
+}
+
+int64_t quantile_rank(double q, int64_t n) {
+    const int64_t rank = (int64_t)std::ceil(q * (double)n);
+    return std::min<int64_t>(std::max<int64_t>(rank, 1), n);
+}
+}  // namespace mxl
+namespace {
 
 void compute_stored_bytes(MatrixImpl &A) {
     const int64_t vt = (int64_t)vt_size(A.dtype);
@@ -353,19 +361,13 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
             A->hyb_q = q;
             if (S.nrows > 0) {
                 std::vector<int32_t> srt(len);
-                int64_t rank = (int64_t)std::ceil(q * (double)S.nrows);
-                rank = std::min<int64_t>(std::max<int64_t>(rank, 1), S.nrows);
+                const int64_t rank = quantile_rank(q, S.nrows);
                 std::nth_element(srt.begin(), srt.begin() + (rank - 1), srt.end());
                 w = srt[rank - 1];
             }
         }
         const int64_t n_pad = ((S.nrows + 63) / 64) * 64;
-        const double ell_bytes = (double)w * (double)n_pad * (double)(vt + 4);
-        // padded storage may cost up to 4x the CSR bytes (at least 1 MiB, so
-        // tiny matrices are never refused for their row padding), at most 32 GiB
-        const double budget = std::min(std::max(4.0 * (double)csr_bytes(S), (double)(1 << 20)),
-                                       32.0 * (double)(1ull << 30));
-        if (ell_bytes > budget && ell_bytes > 0)
+        if (!ell_fits(S, w))
             return fail(MXL_ERR_INFEASIBLE_FORMAT, "ELL storage would exceed min(4x CSR bytes, 32 GiB)");
         A->ell_w = w;
         A->n_pad = n_pad;
@@ -816,8 +818,8 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
         a.partials = pA;
         HIP_TRY(spmv_launch(A, a, s));
         timer.end(k);
-        HIP_TRY(cg_update(ctx, dt, n, x, S.r->p, S.p->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
-        HIP_TRY(cg_pupdate(ctx, dt, n, S.r->p, S.p->p, dinv, st, pB, gv, (int)k, hist, s));
+        HIP_TRY(cg_update(ctx, dt, n, S.r->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
+        HIP_TRY(cg_pupdate(ctx, dt, n, x, S.r->p, S.p->p, dinv, st, pB, gv, (int)k, hist, s));
         if (k % c.check_every == 0 || k == c.max_iters) {
             if ((rs = read_state(S, h)) != MXL_OK) return rs;
             if (h.stop) {

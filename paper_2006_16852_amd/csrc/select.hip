@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -212,7 +213,7 @@ using namespace mxl;
 // ================================================================== host
 namespace mxl {
 
-mxl_status features_compute(const MatrixImpl &A, double out[16]) {
+mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<unsigned> *hist_out) {
     mxl_ctx *ctx = A.ctx;
     hipStream_t s = ctx->stream;
     for (int j = 0; j < 16; ++j) out[j] = 0.0;
@@ -260,6 +261,7 @@ mxl_status features_compute(const MatrixImpl &A, double out[16]) {
         return set_error(MXL_ERR_DEVICE, "features read-back");
     }
     cleanup();
+    if (hist_out) *hist_out = hist;
     // nearest-rank quantiles: sorted length at 1-based rank ceil(P*n/100)
     auto quant = [&](int P) {
         const int64_t rank = (P * n + 99) / 100;
@@ -472,5 +474,191 @@ extern "C" mxl_status mxl_mlp_destroy(mxl_mlp *mm) {
     (void)hipFree(mm->v);
     (void)hipFree(mm->gs);
     delete mm;
+    return MXL_OK;
+}
+
+// ================================================================ selector
+struct mxl_selector {
+    mxl_ctx *ctx = nullptr;
+    std::vector<mxl_kernel_class> classes;
+    mxl_mlp *net = nullptr;
+    double mean[16], sd[16];
+    uint32_t log_mask = 0;
+    double delta = 0.05, zmax = 4.0;
+    void *dz = nullptr, *ds = nullptr;  // one standardised feature row, one score row
+};
+
+extern "C" mxl_status mxl_selector_create(mxl_ctx *ctx, int32_t nclasses, const mxl_kernel_class *classes,
+                                          int32_t nlayers, const int32_t *dims, const float *theta_host,
+                                          const double *mean16, const double *std16, uint32_t log_mask,
+                                          double delta, double zmax, mxl_selector **out) {
+    if (!ctx || !classes || !dims || !theta_host || !mean16 || !std16 || !out || nclasses < 1 ||
+        nclasses > kMlpMaxW || nlayers < 1 || nlayers > kMlpMaxL)
+        return set_error(MXL_ERR_INVALID_ARG, "selector: context, 1..64 classes, network and statistics required");
+    *out = nullptr;
+    if (dims[0] != 16 || dims[nlayers] != nclasses)
+        return set_error(MXL_ERR_DIM_MISMATCH, "selector network must map 16 features to one score per class");
+    for (int c = 0; c < nclasses; ++c) {
+        const int f = classes[c].format;
+        if (f < MXL_FMT_CSR || f > MXL_FMT_HYB) return set_error(MXL_ERR_INVALID_ARG, "selector: unknown format");
+    }
+    for (int j = 0; j < 16; ++j)
+        if (!(std16[j] > 0.0) || !std::isfinite(mean16[j]))
+            return set_error(MXL_ERR_INVALID_ARG, "selector: std must be positive, mean finite");
+    DeviceScope dsc(ctx->device);
+    auto *S = new mxl_selector;
+    S->ctx = ctx;
+    S->classes.assign(classes, classes + nclasses);
+    for (int j = 0; j < 16; ++j) {
+        S->mean[j] = mean16[j];
+        S->sd[j] = std16[j];
+    }
+    S->log_mask = log_mask;
+    S->delta = delta;
+    S->zmax = zmax;
+    mxl_status st = mxl_mlp_create(ctx, nlayers, dims, theta_host, &S->net);
+    if (st != MXL_OK) {
+        delete S;
+        return st;
+    }
+    if (hipMalloc(&S->dz, 16 * 4) != hipSuccess || hipMalloc(&S->ds, (size_t)nclasses * 4) != hipSuccess) {
+        mxl_selector_destroy(S);
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "selector buffers");
+    }
+    *out = S;
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_selector_destroy(mxl_selector *S) {
+    if (!S) return MXL_OK;
+    {
+        DeviceScope dsc(S->ctx->device);
+        mxl_mlp_destroy(S->net);
+        (void)hipFree(S->dz);
+        (void)hipFree(S->ds);
+    }
+    delete S;
+    return MXL_OK;
+}
+
+namespace {
+
+// Width of the padded part a class needs (-1: not padded).
+int64_t class_width(const mxl_kernel_class &k, const std::vector<unsigned> &hist, int64_t n) {
+    if (k.format != MXL_FMT_ELL && k.format != MXL_FMT_HYB) return -1;
+    if (n == 0) return 0;
+    if (k.format == MXL_FMT_ELL) return (int64_t)hist.size() - 1;
+    const double q = k.params.hyb_quantile > 0 ? k.params.hyb_quantile : 0.9;
+    const int64_t rank = quantile_rank(std::min(q, 1.0), n);
+    int64_t cum = 0;
+    for (size_t L = 0; L < hist.size(); ++L) {
+        cum += hist[L];
+        if (cum >= rank) return (int64_t)L;
+    }
+    return (int64_t)hist.size() - 1;
+}
+
+}  // namespace
+
+extern "C" mxl_status mxl_select(const mxl_selector *S, const mxl_op *Aop, int32_t mode, const void *x,
+                                 void *y, int32_t reps, int32_t *class_out, double *scores,
+                                 double *times_ms, mxl_select_info *info) {
+    if (!S || !Aop || Aop->kind != MXL_OP_MATRIX || !class_out)
+        return set_error(MXL_ERR_INVALID_ARG, "selector, matrix operator and class output required");
+    if (mode != MXL_SELECT_MODEL && mode != MXL_SELECT_EXHAUSTIVE && mode != MXL_SELECT_MODEL_FALLBACK)
+        return set_error(MXL_ERR_INVALID_ARG, "unknown selection mode");
+    if (mode == MXL_SELECT_EXHAUSTIVE && (!x || !y))
+        return set_error(MXL_ERR_INVALID_ARG, "exhaustive selection needs x and y to time with");
+    if (Aop->mat->ctx->device != S->ctx->device)
+        return set_error(MXL_ERR_INVALID_ARG, "matrix and selector live on different devices");
+    if ((x || y) && reps < 1) return set_error(MXL_ERR_INVALID_ARG, "reps must be >= 1");
+    const MatrixImpl &A = *Aop->mat;
+    DeviceScope dsc(S->ctx->device);
+    const int C = (int)S->classes.size();
+    const double inf = std::numeric_limits<double>::infinity(), nan = std::nan("");
+    mxl_select_info inf_out{};
+    double f[16];
+    std::vector<unsigned> hist;
+    mxl_status st = features_compute(A, f, &hist);
+    if (st != MXL_OK) return st;
+    if (hist.empty()) hist.assign(1, (unsigned)A.nrows);
+    std::vector<bool> feasible(C);
+    for (int c = 0; c < C; ++c) {
+        const int64_t w = class_width(S->classes[c], hist, A.nrows);
+        feasible[c] = w < 0 || ell_fits(A, w);
+    }
+    // standardised features and their largest magnitude
+    float z[16];
+    double maxz = 0.0;
+    for (int j = 0; j < 16; ++j) {
+        const double phi = (S->log_mask >> j) & 1u ? std::log1p(std::max(f[j], 0.0)) : f[j];
+        const double zj = (phi - S->mean[j]) / S->sd[j];
+        z[j] = (float)zj;
+        maxz = std::max(maxz, std::fabs(zj));
+    }
+    inf_out.max_z = maxz;
+    std::vector<double> sc(C, nan), tm(C, nan);
+    std::vector<int> order;
+    if (mode != MXL_SELECT_EXHAUSTIVE) {
+        std::vector<float> out((size_t)C);
+        hipStream_t s = S->ctx->stream;
+        if (hipMemcpyAsync(S->dz, z, sizeof z, hipMemcpyHostToDevice, s) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "selector feature upload");
+        if ((st = mxl_mlp_forward(S->net, 1, (const float *)S->dz, (float *)S->ds)) != MXL_OK) return st;
+        if (hipMemcpyAsync(out.data(), S->ds, (size_t)C * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "selector score read-back");
+        for (int c = 0; c < C; ++c) sc[c] = feasible[c] ? (double)out[c] : inf;
+        for (int c = 0; c < C; ++c)
+            if (feasible[c]) order.push_back(c);
+        // stable order by score, ties to the lower class index
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sc[a] < sc[b]; });
+        if (order.empty()) return set_error(MXL_ERR_INFEASIBLE_FORMAT, "no feasible class");
+        inf_out.margin = order.size() > 1 ? sc[order[1]] - sc[order[0]] : inf;
+    } else {
+        for (int c = 0; c < C; ++c)
+            if (feasible[c]) order.push_back(c);
+        if (order.empty()) return set_error(MXL_ERR_INFEASIBLE_FORMAT, "no feasible class");
+        inf_out.margin = inf;
+    }
+    std::vector<int> timed;
+    if (mode == MXL_SELECT_EXHAUSTIVE) {
+        timed = order;
+    } else if (mode == MXL_SELECT_MODEL_FALLBACK && x && y &&
+               (inf_out.margin < S->delta || maxz > S->zmax || std::isnan(inf_out.margin))) {
+        for (size_t k = 0; k < order.size() && k < 3; ++k) timed.push_back(order[k]);
+    }
+    int choice = order[0];
+    if (!timed.empty()) {
+        double best = inf;
+        int nt = 0;
+        for (int c : timed) {
+            const mxl_kernel_class &k = S->classes[c];
+            mxl_op *op = nullptr;
+            st = mxl_convert(Aop, (mxl_format)k.format, &k.params, &op);
+            if (st == MXL_ERR_INFEASIBLE_FORMAT) continue;
+            if (st != MXL_OK) return st;
+            double ms = 0.0;
+            st = mxl_time_apply(op, x, y, reps, 1, &ms);
+            mxl_op_destroy(op);
+            if (st != MXL_OK) return st;
+            tm[c] = ms;
+            ++nt;
+            if (ms < best) {
+                best = ms;
+                choice = c;
+            }
+        }
+        if (nt == 0) return set_error(MXL_ERR_INFEASIBLE_FORMAT, "no timed class could be built");
+        inf_out.fallback = 1;
+        inf_out.ntimed = nt;
+        inf_out.best_ms = best;
+    }
+    *class_out = choice;
+    if (scores)
+        for (int c = 0; c < C; ++c) scores[c] = sc[c];
+    if (times_ms)
+        for (int c = 0; c < C; ++c) times_ms[c] = tm[c];
+    if (info) *info = inf_out;
     return MXL_OK;
 }

@@ -21,7 +21,8 @@ import os
 import numpy as np
 import torch
 
-from . import Mlp, MxlError, ERR_INFEASIBLE_FORMAT
+from . import Mlp, MxlError, ERR_INFEASIBLE_FORMAT, SelectorHandle, SELECT_MODEL, \
+    SELECT_EXHAUSTIVE, SELECT_MODEL_FALLBACK
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "selector_weights.json")
@@ -113,6 +114,7 @@ class Selector:
         self.delta = delta
         self.zmax = zmax
         self._mlp = None
+        self._handle = None
 
     # ---------------------------------------------------------------- io
     def to_json(self) -> dict:
@@ -140,23 +142,27 @@ class Selector:
         X = torch.from_numpy(Z).to(f"cuda:{ctx.device}")
         return self._mlp.forward(X).cpu().numpy().astype(np.float64)
 
-    def choose(self, ctx, base, x=None, y=None, fallback: bool = True):
-        """Returns (class index, info dict)."""
-        f = base.features()
-        s = self.scores(ctx, f)[0]
-        mask = feasible_mask(f)
-        s = np.where(mask, s, np.inf)
-        order = np.argsort(s)
-        z = np.abs(self.standardise(f))
-        margin = s[order[1]] - s[order[0]] if np.isfinite(s[order[1]]) else np.inf
-        unsure = margin < self.delta or bool(np.any(z > self.zmax))
-        info = dict(margin=float(margin), max_z=float(z.max()), fallback=False)
-        if fallback and unsure and x is not None:
-            top = [int(k) for k in order[:3] if np.isfinite(s[k])]
-            t = time_classes(base, x, y, reps=5, flush=True, classes=top)
-            info.update(fallback=True, timed=top)
-            return int(top[int(np.argmin(t[top]))]), info
-        return int(order[0]), info
+    def handle(self, ctx) -> SelectorHandle:
+        """The selector as a library object (features, standardisation, MLP
+        and fallback timing all run inside mxl_select)."""
+        if self._handle is None or self._handle.ctx is not ctx:
+            self._handle = SelectorHandle(ctx, [(c[1], c[2]) for c in CLASSES], DIMS,
+                                          self.theta.astype(np.float32), self.mean, self.std,
+                                          LOG_FEATS, self.delta, self.zmax)
+        return self._handle
+
+    def choose(self, ctx, base, x=None, y=None, fallback: bool = True, reps: int = 5):
+        """Returns (class index, info dict) from mxl_select."""
+        mode = SELECT_MODEL_FALLBACK if fallback else SELECT_MODEL
+        return self.handle(ctx).select(base, mode, x, y, reps=reps)
+
+
+def exhaustive(ctx, base, x, y, reps: int = 20):
+    """Time every feasible class inside the library; returns (class, times_ms)."""
+    sel = Selector(np.zeros(sum(DIMS[i + 1] * DIMS[i] + DIMS[i + 1] for i in range(len(DIMS) - 1))),
+                   np.zeros(16), np.ones(16))
+    k, info = sel.handle(ctx).select(base, SELECT_EXHAUSTIVE, x, y, reps=reps)
+    return k, np.where(np.isnan(info["times_ms"]), np.inf, info["times_ms"])
 
 
 def train(ctx, F: np.ndarray, T: np.ndarray, epochs: int = 4000, lr: float = 3e-3,

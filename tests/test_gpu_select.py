@@ -131,3 +131,100 @@ def test_trained_selector_gain(mxl, ctx):
     fixed = int(np.argmin([np.exp(np.mean(np.log(np.where(np.isfinite(slow[:, k]), slow[:, k], 1e3))))
                            for k in range(S.NCLS)]))
     assert S.regret(Tt, np.array(fb)).mean() <= S.regret(Tt, np.full(len(test), fixed)).mean()
+
+
+# --------------------------------------------------------------- mxl_select
+SEL_MATS = ([W.zipf_suite_matrix(m, scale_n=0.02) for m in (1, 8, 40, 77, 150)]
+            + [W.stencil_3d27(16), W.aniso_3d7(12), W.edge_matrices()[3], W.edge_matrices()[0]])
+
+
+def _oracle_choice(S, sel, A):
+    """Expected model choice: oracle features, the standardisation written
+    out in numpy, the oracle's FP64 forward pass, argmin over the classes
+    whose padded storage fits the conversion budget (widths from the
+    oracle's own layout routines)."""
+    f = O.features(A)
+    z = (S.transform(f) - sel.mean) / sel.std
+    _, _, pred = O.mlp_loss_grad(S.DIMS, sel.theta, z[None, :], np.zeros((1, S.NCLS)),
+                                 np.ones((1, S.NCLS)), 0.0, want_grad=False, want_pred=True)
+    pred = pred[0]
+    n_pad = O.pad_rows(A.nrows)
+    csr = A.nnz * 12 + (A.nrows + 1) * 4
+    budget = min(max(4 * csr, 1 << 20), 32 << 30)
+    feas = np.ones(S.NCLS, bool)
+    for k, (_, fmt, kw) in enumerate(S.CLASSES):
+        if fmt == "ell":
+            w = int(A.row_lengths().max()) if A.nrows else 0
+        elif fmt == "hyb":
+            w = O.hyb_width(A, kw["hyb_quantile"])
+        else:
+            continue
+        feas[k] = n_pad * w * 12 <= budget
+    return np.where(feas, pred, np.inf), np.abs(z).max()
+
+
+@pytest.mark.parametrize("A", SEL_MATS, ids=[a.name for a in SEL_MATS])
+def test_select_model_parity(mxl, ctx, A):
+    """mxl_select (model mode) takes the oracle's choice: same masked
+    scores within the FP32 network's tolerance, same argmin whenever the
+    oracle's top-2 margin exceeds that tolerance."""
+    from paper_2006_16852_amd import selector as S
+    sel = S.Selector.load()
+    want, maxz = _oracle_choice(S, sel, A)
+    k, info = sel.choose(ctx, matrix(mxl, ctx, A), fallback=False)
+    got = info["scores"]
+    assert np.array_equal(np.isinf(got), np.isinf(want))
+    fin = np.isfinite(want)
+    assert np.allclose(got[fin], want[fin], rtol=1e-4, atol=1e-4)
+    assert abs(info["max_z"] - maxz) <= 1e-7 * max(1.0, maxz)
+    srt = np.sort(want[fin])
+    if len(srt) < 2 or srt[1] - srt[0] > 1e-3:
+        assert k == int(np.argmin(want))
+    assert not info["fallback"] and info["ntimed"] == 0
+
+
+@pytest.mark.parametrize("A", [W.zipf_suite_matrix(12, scale_n=0.05), W.edge_matrices()[3]],
+                         ids=lambda a: a.name)
+def test_select_exhaustive_and_fallback(mxl, ctx, A):
+    """Exhaustive mode times exactly the feasible classes and returns the
+    fastest; a selector that is always unsure times its top 3 and returns
+    the fastest of those; without vectors it never times."""
+    from paper_2006_16852_amd import selector as S
+    base = S.Selector.load()
+    want, _ = _oracle_choice(S, base, A)
+    M = matrix(mxl, ctx, A)
+    x = torch.from_numpy(W.uniform_vec(A.ncols, 3)).to(DEV)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
+    k, t = S.exhaustive(ctx, M, x, y, reps=3)
+    assert np.array_equal(np.isfinite(t), np.isfinite(want))
+    assert k == int(np.argmin(t))
+    unsure = S.Selector(base.theta, base.mean, base.std, delta=1e9, zmax=base.zmax)
+    k2, info = unsure.choose(ctx, M, x, y, reps=3)
+    order = np.argsort(info["scores"], kind="stable")
+    top = [int(c) for c in order[:3] if np.isfinite(info["scores"][c])]
+    timed = np.flatnonzero(~np.isnan(info["times_ms"]))
+    assert info["fallback"] and sorted(timed.tolist()) == sorted(top) and info["ntimed"] == len(top)
+    assert k2 == top[int(np.argmin(info["times_ms"][top]))]
+    assert info["best_ms"] == info["times_ms"][k2]
+    k3, info3 = unsure.choose(ctx, M, None, None)
+    assert not info3["fallback"] and k3 == top[0]
+
+
+def test_select_errors(mxl, ctx):
+    from paper_2006_16852_amd import selector as S
+    sel = S.Selector.load()
+    M = matrix(mxl, ctx, W.stencil_2d5(8))
+    h = sel.handle(ctx)
+    with pytest.raises(mxl.MxlError) as e:
+        h.select(M, mxl.SELECT_EXHAUSTIVE)
+    assert e.value.status == mxl.ERR_INVALID_ARG
+    with pytest.raises(mxl.MxlError) as e:
+        h.select(M, 7)
+    assert e.value.status == mxl.ERR_INVALID_ARG
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.SelectorHandle(ctx, [("csr", {})], S.DIMS, sel.theta, sel.mean, sel.std, S.LOG_FEATS)
+    assert e.value.status == mxl.ERR_DIM_MISMATCH
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.SelectorHandle(ctx, [(c[1], c[2]) for c in S.CLASSES], S.DIMS, sel.theta, sel.mean,
+                           np.zeros(16), S.LOG_FEATS)
+    assert e.value.status == mxl.ERR_INVALID_ARG

@@ -101,11 +101,13 @@ def test_pcg_fp32_matches_oracle_definition(mxl, ctx):
     assert _close_iters(info["iterations"], ref["iterations"])
 
 
-@pytest.mark.parametrize("A", [W.stencil_2d5(64), W.aniso_3d7(16), W.convdiff_2d5(20)],
+@pytest.mark.parametrize("A", [W.stencil_2d5(64), W.aniso_3d7(16), W.convdiff_2d5(20), W.stencil_2d5(8),
+                               W.stencil_2d5(11), W.stencil_3d27(5)],
                          ids=lambda a: a.name)
 def test_single_launch_matches_per_step(mxl, ctx, A):
-    """The whole-solve-in-one-workgroup path (small systems) against the
-    per-step kernels and the oracle, with a nonzero initial guess."""
+    """The whole-solve-in-one-workgroup path (small systems; n <= 128 with
+    at most 8 entries per row takes the one-wave register shape) against
+    the per-step kernels and the oracle, with a nonzero initial guess."""
     b = O.spmv(A, W.uniform_vec(A.nrows, 1))
     x0 = W.uniform_vec(A.nrows, 9) * 0.1
     d, _ = O.jacobi_dinv(A)
