@@ -68,6 +68,17 @@ __global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict_
     publish<3>(v, parts, L);
 }
 
+// The update kernels first load their operands for the workgroup's first
+// kPf tiles, then reduce the partials of the previous kernel (gather_all):
+// the loads do not depend on that scalar, so their latency overlaps the
+// reduction instead of every workgroup paying the two in sequence.
+constexpr int kPf = 4;
+
+#define MXL_PF_INDEX(u)                                        \
+    const int64_t t_##u = tb_ + (int64_t)(u) * ts_;             \
+    const int64_t i_##u = t_##u * kWG + threadIdx.x;            \
+    const bool in_##u = t_##u < te_ && i_##u < n;
+
 // Consumes p.q (fused into the SpMV): alpha = rho_{k-1} / p.q, then
 // r -= alpha q and the reductions r.z, r.r.  The matching x += alpha p is
 // applied by k_cg_pupdate, which reads p anyway, so p is read once less.
@@ -79,6 +90,15 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r,
     if (st->stop) {
         if (MXL_LEAD) st->ustop = 1;
         return;
+    }
+    MXL_RANGE(n)
+    V rv[kPf], qv[kPf], dv[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        rv[u] = in_u ? r[i_u] : (V)0;
+        qv[u] = in_u ? q[i_u] : (V)0;
+        dv[u] = in_u && dinv ? dinv[i_u] : (V)1;
     }
     double eta[1];
     gather_all<1>(pq_parts, pq_slots, eta);
@@ -99,17 +119,23 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r,
         st->eta = eta[0];
         st->ustop = 0;
     }
-    MXL_RANGE(n)
     double rz = 0.0, rr = 0.0;
-    MXL_FOR(i, n) {
+    auto step = [&](int64_t i, V r0, V q0, V d0) {
         V ri;
-        if constexpr (sizeof(V) == 8) ri = r[i] - alpha * q[i];
-        else ri = (V)((double)r[i] - alpha * (double)q[i]);
+        if constexpr (sizeof(V) == 8) ri = r0 - alpha * q0;
+        else ri = (V)((double)r0 - alpha * (double)q0);
         r[i] = ri;
-        double z = prec_z(dinv, i, ri);
+        const double z = dinv ? (double)d0 * (double)ri : (double)ri;
         rz += (double)ri * z;
         rr += (double)ri * (double)ri;
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        if (in_u) step(i_u, rv[u], qv[u], dv[u]);
     }
+    for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(i, r[i], q[i], dinv ? dinv[i] : (V)1);
     double v[2] = {rz, rr};
     publish<2>(v, parts, L);
 }
@@ -124,6 +150,16 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     // k_cg_update saw an earlier stop or broke down: x is not advanced.  The
     // stop this kernel decides goes to st->stop, which it never reads.
     if (st->ustop) return;
+    MXL_RANGE(n)
+    V xv[kPf], rv[kPf], pv[kPf], dv[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        xv[u] = in_u ? x[i_u] : (V)0;
+        rv[u] = in_u ? r[i_u] : (V)0;
+        pv[u] = in_u ? p[i_u] : (V)0;
+        dv[u] = in_u && dinv ? dinv[i_u] : (V)1;
+    }
     double t[2];
     gather_all<2>(parts, slots, t);
     const double rz = t[0], rr = t[1];
@@ -136,20 +172,20 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     else if (chk && !finite_d(rz)) stop = ST_NONFINITE;
     else if (rz == 0.0) stop = ST_BREAKDOWN;
     const double beta = rz / st->rho2[(k - 1) & 1];
-    MXL_RANGE(n)
-    if (stop != ST_RUN) {
-        MXL_FOR(i, n) {
-            if constexpr (sizeof(V) == 8) x[i] = x[i] + alpha * p[i];
-            else x[i] = (V)((double)x[i] + alpha * (double)p[i]);
-        }
-    } else {
-        MXL_FOR(i, n) {
-            const V pi = p[i];
-            if constexpr (sizeof(V) == 8) x[i] = x[i] + alpha * pi;
-            else x[i] = (V)((double)x[i] + alpha * (double)pi);
-            p[i] = (V)(prec_z(dinv, i, r[i]) + beta * (double)pi);
-        }
+    const bool run = stop == ST_RUN;
+    auto step = [&](int64_t i, V x0, V r0, V p0, V d0) {
+        if constexpr (sizeof(V) == 8) x[i] = x0 + alpha * p0;
+        else x[i] = (V)((double)x0 + alpha * (double)p0);
+        if (run) p[i] = (V)((dinv ? (double)d0 * (double)r0 : (double)r0) + beta * (double)p0);
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        if (in_u) step(i_u, xv[u], rv[u], pv[u], dv[u]);
     }
+    for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < n)
+            step(i, x[i], run ? r[i] : (V)0, p[i], run && dinv ? dinv[i] : (V)1);
     if (MXL_LEAD) {
         st->rr = rr;
         st->iters = k;
