@@ -43,6 +43,8 @@ def spmv_bytes(fmt, n, nnz, desc, vt=8, it=4, beta_nonzero=False):
         return nnz * (vt + 2 * it) + 2 * n * vt + extra
     if fmt == "ell":
         return n * desc["ell_width"] * (vt + it) + 2 * n * vt + extra
+    if fmt == "ell16":  # 16-bit column offsets
+        return n * desc["ell_width"] * (vt + 2) + 2 * n * vt + extra
     if fmt == "hyb":
         return n * desc["ell_width"] * (vt + it) + desc["tail_nnz"] * (vt + 2 * it) + 2 * n * vt + extra
     raise ValueError(fmt)
@@ -77,7 +79,7 @@ def cpu_baseline(A, x, b, sel_fmt):
             + spmv_bytes("ell", n, nnz, {"ell_width": w})
             + spmv_bytes("hyb", n, nnz, {"ell_width": H["k"], "tail_nnz": H["tail_row"].size})
             + (spmv_bytes("csr", n, nnz, {}, beta_nonzero=True) + 5 * n * 8)
-            + r["iterations"] * (spmv_bytes("csr", n, nnz, {}) + 11 * n * 8))
+            + r["iterations"] * (spmv_bytes("csr", n, nnz, {}) + 10 * n * 8))
     return {"value": round(byts / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"4 SpMVs (csr, coo, ell, hyb) + {r['iterations']} Jacobi-PCG iterations "
                       f"(CSR) on the 128^3 27-point system, {dt:.2f} s on the host"}
@@ -128,18 +130,30 @@ def main():
     ops = {
         "csr_vec32": base.convert("csr", variant=mxl.CSR_VECTOR, vector_width=32),
         "csr_merge": base.convert("csr", variant=mxl.CSR_MERGE),
+        "csr_stream": base.convert("csr", variant=mxl.CSR_STREAM),
         "coo": base.convert("coo"),
         "ell": base.convert("ell"),
+        "ell16": base.convert("ell", variant=mxl.ELL_DELTA16),
         "hyb": base.convert("hyb", hyb_quantile=0.9),
     }
-    fmt_of = {"csr_vec32": "csr", "csr_merge": "csr", "coo": "coo", "ell": "ell", "hyb": "hyb"}
+    fmt_of = {"csr_vec32": "csr", "csr_merge": "csr", "csr_stream": "csr", "coo": "coo", "ell": "ell",
+              "ell16": "ell16", "hyb": "hyb"}
     descs = {k: v.describe() for k, v in ops.items()}
     # exhaustive timing picks the operator used inside CG
-    t_sel = {k: ops[k].time_apply(xd, yd, reps=20) for k in ("csr_vec32", "csr_merge", "ell")}
+    t_sel = {k: ops[k].time_apply(xd, yd, reps=20)
+             for k in ("csr_vec32", "csr_merge", "csr_stream", "ell", "ell16")}
     sel = min(t_sel, key=t_sel.get)
     log(f"[bench] selection times (ms): {t_sel} -> {sel}")
-    csr_best = min(("csr_vec32", "csr_merge"), key=t_sel.get)
-    spmv_set = [csr_best, "coo", "ell", "hyb"]
+    csr_best = min(("csr_vec32", "csr_merge", "csr_stream"), key=t_sel.get)
+    ell_best = min(("ell", "ell16"), key=t_sel.get)
+    spmv_set = [csr_best, "coo", ell_best, "hyb"]
+    # achievable-bandwidth references on this GPU (STREAM-style, 2^26 doubles)
+    sa = torch.rand(1 << 26, dtype=torch.float64, device=dev)
+    sb = torch.rand(1 << 26, dtype=torch.float64, device=dev)
+    sc = torch.empty(1 << 26, dtype=torch.float64, device=dev)
+    ref_gbs = {op: round(nb / mxl.stream_bench(ctx, op, sa, sb, sc, reps=10) / 1e6, 1)
+               for op, nb in (("triad", 24 << 26), ("dot", 16 << 26))}
+    del sa, sb, sc
     M = ops[sel]
     P = mxl.jacobi(M)
     S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-10, check_every=16)
@@ -188,7 +202,7 @@ def main():
                           "alg_MB": round(byts / 1e6, 2), "stored_MB": round(descs[k]["stored_bytes"] / 1e6, 2)}
     its = [i["iterations"] for i in infos]
     cg_spmv = spmv_bytes(fmt_of[sel], n, nnz, descs[sel])
-    cg_iter_bytes = cg_spmv + 11 * n * 8
+    cg_iter_bytes = cg_spmv + 10 * n * 8
     cg_setup_bytes = spmv_bytes(fmt_of[sel], n, nnz, descs[sel], beta_nonzero=True) + 5 * n * 8
     cg_bytes = float(np.mean(its)) * cg_iter_bytes + cg_setup_bytes
     step_bytes += cg_bytes
@@ -220,6 +234,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": f"{sel} SpMV with fused p.q inside the CG loop",
+                     "stream_GBs": ref_gbs, "frac_of_dot": round(achieved / ref_gbs["dot"], 4),
                      "alg_bytes_per_launch": cg_spmv, "avg_launch_us": round(launch_ms * 1e3, 2)},
         "cg": {"iterations": its[0], "time_to_1e-10_ms": round(cg_ms, 3), "true_rel_residual": true_rel,
                "alg_GBs": round(cg_bytes / (cg_ms * 1e-3) / 1e9, 1),

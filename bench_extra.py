@@ -6,6 +6,11 @@ poisson2d : 64x64 Poisson, Jacobi-PCG to 1e-10: one kernel per step vs the whole
             solve in one persistent workgroup (latency-bound case).
 batch     : 10,000 banded SPD systems, batched Jacobi-PCG in one persistent
             launch: default schedule vs autotuned schedule.
+overhead  : the size-1, b = NaN protocol of the paper's Table 1 (per-iteration cost).
+stream    : copy / triad / dot bandwidth, the achievable-peak calibration.
+
+Each line carries a cpu_baseline: the oracle on a bounded sample of the same
+work (one host core), unless --no-cpu-baseline.
 """
 from __future__ import annotations
 
@@ -29,6 +34,14 @@ def _timed(fn, steps, warmup):
         out = fn()
     _sync()
     return (time.perf_counter() - t0) / steps, out
+
+
+def _oracle():
+    """The oracle as it stands (plain FP64 C, one thread): test
+    infrastructure, used here only for the cpu_baseline leg."""
+    import oracle as O
+    O.build(force=False)
+    return O
 
 
 def aniso_ir(args):
@@ -83,6 +96,18 @@ def aniso_ir(args):
     out["best_ir"] = best_ir[1]
     out["runs"] = res
     out["steps"], out["warmup"] = args.steps, args.warmup
+    if not args.no_cpu_baseline:
+        O = _oracle()
+        d, _ = O.jacobi_dinv(A)
+        bh = W.uniform_vec(n, 4)
+        k = 20
+        t0 = time.perf_counter()
+        O.pcg(A, bh, dinv=d, max_iters=k, reduction=0.0)
+        per_it = (time.perf_counter() - t0) / k
+        its = res["fp64_1e-10"]["iterations"]
+        out["cpu_baseline"] = {"value": round(per_it * its * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} FP64 Jacobi-PCG iterations on the 160^3 system "
+                                         f"({per_it * 1e3:.1f} ms each), scaled to the {its} iterations to 1e-10"}
     print(json.dumps(out), flush=True)
 
 
@@ -111,12 +136,23 @@ def poisson2d(args):
         dt, info = _timed(f, max(args.steps, 20), args.warmup + 2)
         res[name] = dict(ms=round(dt * 1e3, 4), iterations=info["iterations"],
                          us_per_iteration=round(dt * 1e6 / info["iterations"], 3))
-    print(json.dumps({"metric": "CG time-to-1e-10 residual (latency-bound 64x64 Poisson)", "unit": "ms",
-                      "value": res["one_workgroup"]["ms"], "higher_is_better": False, "n_gpus": 1,
-                      "dtype": "f64", "data": "synthetic",
-                      "config": {"workload": "stencil2d5_64^2 jacobi-pcg to 1e-10", "n": A.nrows,
-                                 "nnz": A.nnz},
-                      "runs": res, "paper_table1_us_per_iteration_cg": 1.28}), flush=True)
+    out = {"metric": "CG time-to-1e-10 residual (latency-bound 64x64 Poisson)", "unit": "ms",
+           "value": res["one_workgroup"]["ms"], "higher_is_better": False, "n_gpus": 1,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "stencil2d5_64^2 jacobi-pcg to 1e-10", "n": A.nrows, "nnz": A.nnz},
+           "runs": res, "paper_table1_us_per_iteration_cg": 1.28}
+    if not args.no_cpu_baseline:
+        O = _oracle()
+        d, _ = O.jacobi_dinv(A)
+        bh = b.cpu().numpy()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = O.pcg(A, bh, dinv=d, reduction=1e-10)
+        dt = (time.perf_counter() - t0) / reps
+        out["cpu_baseline"] = {"value": round(dt * 1e3, 3), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole solve ({r['iterations']} iterations), mean of {reps}"}
+    print(json.dumps(out), flush=True)
 
 
 def batch(args):
@@ -152,7 +188,23 @@ def batch(args):
                                  "nnz": int(B.row_ptr[-1])},
                       "ms": res, "autotuned_schedule": best, "autotune_seconds": round(tune_s, 3),
                       "converged": ok, "total_iterations": int(it.sum()),
-                      "read_once_GBs": round(bytes_once / dt / 1e9, 1)}), flush=True)
+                      "read_once_GBs": round(bytes_once / dt / 1e9, 1),
+                      **({} if args.no_cpu_baseline else {"cpu_baseline": _batch_cpu(B)})}), flush=True)
+
+
+def _batch_cpu(B, count=500):
+    """The oracle's batched PCG on the first `count` systems, in systems/s."""
+    import numpy as np
+    import workloads as W
+    O = _oracle()
+    rows = int(B.sys_ptr[count])
+    sub = W.Batch(count, B.sys_ptr[:count + 1].copy(), B.row_ptr[:rows + 1].copy(),
+                  B.col[:B.row_ptr[rows]].copy(), B.val[:B.row_ptr[rows]].copy(), B.b[:rows].copy())
+    t0 = time.perf_counter()
+    O.batch_pcg(sub, reduction=1e-10)
+    dt = time.perf_counter() - t0
+    return {"value": round(count / dt, 1), "unit": "systems/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {count} of the 10,000 systems to 1e-10, {dt:.2f} s"}
 
 
 def overhead(args):
@@ -181,24 +233,37 @@ def overhead(args):
         dt, info = _timed(f, max(3, args.steps), 1)
         assert info["iterations"] == iters
         res[name] = round(dt * 1e6 / iters, 3)
-    print(json.dumps({"metric": "solver overhead per iteration (size-1 system, b = NaN, 1,000 iterations)",
-                      "unit": "us/iteration", "value": res["cg_one_workgroup"], "higher_is_better": False,
-                      "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-                      "config": {"workload": "n=1 nan-rhs protocol"}, "runs": res,
-                      "paper_table1_us": {"CG": 1.28, "BiCGSTAB": 1.26}}), flush=True)
+    out = {"metric": "solver overhead per iteration (size-1 system, b = NaN, 1,000 iterations)",
+           "unit": "us/iteration", "value": res["cg_one_workgroup"], "higher_is_better": False,
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "n=1 nan-rhs protocol"}, "runs": res,
+           "paper_table1_us": {"CG": 1.28, "BiCGSTAB": 1.26}}
+    if not args.no_cpu_baseline:
+        import workloads as W
+        O = _oracle()
+        A1 = W.Csr(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]))
+        reps = 200
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.pcg(A1, np.array([np.nan]), max_iters=iters, nonfinite_check=0)
+        dt = (time.perf_counter() - t0) / reps
+        out["cpu_baseline"] = {"value": round(dt * 1e6 / iters, 4), "unit": "us/iteration", "cores": 1,
+                               "kind": "oracle", "sample": f"{reps} solves of {iters} iterations"}
+    print(json.dumps(out), flush=True)
 
 
 def stream(args):
-    """STREAM-style bandwidth of copy, triad and dot on 2^26 doubles (the
-    calibration the paper uses for solver bandwidth, Sec. 7.4 and Table 3)."""
+    """STREAM-style bandwidth of copy, triad and dot on 2^28 doubles (2 GiB
+    per array; the calibration the paper uses for solver bandwidth, Sec. 7.4
+    and Table 3)."""
     import torch
     import paper_2006_16852_amd as mxl
     dev = "cuda:0"
     ctx = mxl.Context(0)
-    n = 1 << 26
-    g = torch.Generator(device="cpu").manual_seed(11)
-    a = torch.rand(n, dtype=torch.float64, generator=g).to(dev)
-    b = torch.rand(n, dtype=torch.float64, generator=g).to(dev)
+    n = 1 << 28
+    torch.manual_seed(11)
+    a = torch.rand(n, dtype=torch.float64, device=dev)
+    b = torch.rand(n, dtype=torch.float64, device=dev)
     c = torch.empty(n, dtype=torch.float64, device=dev)
     reps = max(5, args.steps)
     res = {}
@@ -207,7 +272,7 @@ def stream(args):
         res[op] = {"ms": round(ms, 4), "GBs": round(nbytes / ms / 1e6, 1), "bytes": nbytes}
     print(json.dumps({"metric": "STREAM triad bandwidth", "unit": "GB/s", "value": res["triad"]["GBs"],
                       "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-                      "config": {"workload": "stream 2^26 doubles", "n": n}, "runs": res,
+                      "config": {"workload": "stream 2^28 doubles", "n": n}, "runs": res,
                       "peak_GBs": 8000.0}), flush=True)
 
 

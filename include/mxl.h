@@ -56,9 +56,14 @@ enum {
     MXL_CSR_SCALAR = 0,  /* one lane per row */
     MXL_CSR_VECTOR = 1,  /* W lanes per row, W = vector_width in {2..64} */
     MXL_CSR_MERGE = 2,   /* merge-path split of rows+nonzeros */
+    MXL_CSR_STREAM = 3,  /* blocks of <= 63 rows / 512 nonzeros per wave,
+                            coalesced loads staged in LDS; long rows alone */
     MXL_COO_SEGRED = 0,  /* segmented reduction over row-sorted triplets */
     MXL_ELL_PLAIN = 0,   /* one lane per row, gathers x from memory */
     MXL_ELL_LDS = 1,     /* stages each block's x window in LDS when it fits */
+    MXL_ELL_DELTA16 = 2, /* ELL only: 16-bit column offsets col - row (padding
+                            -32768), 2 index bytes per slot instead of 4;
+                            INFEASIBLE_FORMAT if some |col - row| > 32767 */
     MXL_HYB_DEFAULT = 0
 };
 
@@ -188,7 +193,9 @@ mxl_status mxl_op_describe(const mxl_op *A, mxl_op_desc *out);
 /* Copy one of the format's arrays into dst (device memory, dst_bytes
  * capacity) on the context stream, for inspection.  which: 0 row_ptr, 1 col,
  * 2 val, 3 coo_row, 4 ell_col, 5 ell_val, 6 tail_row, 7 tail_col,
- * 8 tail_val, 9 jacobi dinv.  Errors: INVALID_ARG if absent or too small. */
+ * 8 tail_val, 9 jacobi dinv.  ell_col is int32 [w][n_pad], or int16
+ * offsets col - row for MXL_ELL_DELTA16.  Errors: INVALID_ARG if absent,
+ * DIM_MISMATCH if dst is too small. */
 mxl_status mxl_op_export(const mxl_op *A, int32_t which, void *dst,
                          int64_t dst_bytes);
 
@@ -276,8 +283,9 @@ mxl_status mxl_batch_autotune(const mxl_op *B, const mxl_criteria *crit,
 mxl_status mxl_features(const mxl_op *A, double out_host[16]);
 
 /* Median time in milliseconds of reps applications y = A x (HIP events on
- * the context stream).  flush != 0 writes a 1 GiB buffer before every rep
- * to evict the 256 MB last-level cache; its time is excluded. */
+ * the context stream).  flush != 0 reads a 1 GiB buffer (allocated on first
+ * use and kept by the context) before every rep to evict the 256 MB
+ * last-level cache without leaving dirty lines; its time is excluded. */
 mxl_status mxl_time_apply(const mxl_op *A, const void *x, void *y, int reps,
                           int flush, double *median_ms);
 

@@ -20,9 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libmxl.so")
 # ----------------------------------------------------------------- constants
 F64, F32 = 0, 1
 CSR, COO, ELL, HYB = 0, 1, 2, 3
-CSR_SCALAR, CSR_VECTOR, CSR_MERGE = 0, 1, 2
+CSR_SCALAR, CSR_VECTOR, CSR_MERGE, CSR_STREAM = 0, 1, 2, 3
 COO_SEGRED = 0
-ELL_PLAIN, ELL_LDS = 0, 1
+ELL_PLAIN, ELL_LDS, ELL_DELTA16 = 0, 1, 2
 OP_MATRIX, OP_JACOBI, OP_SOLVER, OP_BATCH = 0, 1, 2, 3
 SOLVER_CG, SOLVER_BICGSTAB, SOLVER_IR = 0, 1, 2
 STOP_NONE, STOP_CONVERGED, STOP_MAX_ITERS, STOP_TIME, STOP_BREAKDOWN, STOP_NONFINITE = range(6)
@@ -238,7 +238,9 @@ class Op:
         n, nnz, w, npad, tail = d["nrows"], d["nnz"], d["ell_width"], d["n_pad"], d["tail_nnz"]
         vt = _torch_dtype(d["dtype"])
         shape = {"row_ptr": (n + 1, torch.int32), "col": (nnz, torch.int32), "val": (nnz, vt),
-                 "coo_row": (nnz, torch.int32), "ell_col": (w * npad, torch.int32),
+                 "coo_row": (nnz, torch.int32),
+                 "ell_col": (w * npad, torch.int16 if (d["format"] == ELL and d["variant"] == ELL_DELTA16)
+                             else torch.int32),
                  "ell_val": (w * npad, vt), "tail_row": (tail, torch.int32),
                  "tail_col": (tail, torch.int32), "tail_val": (tail, vt), "dinv": (n, vt)}[which]
         out = torch.empty(max(shape[0], 1), dtype=shape[1], device=f"cuda:{self.ctx.device}")

@@ -58,8 +58,8 @@ struct MatrixImpl {
     double hyb_q = 0.0;
     BufPtr tail_row, tail_col, tail_val;  // HYB COO tail
     int64_t tail_nnz = 0;
-    BufPtr part;                       // merge-path tile boundaries (int2)
-    int64_t ntiles = 0;                // merge / COO / HYB-tail tiles
+    BufPtr part;                       // merge-path tile boundaries / row-block descriptors (int2)
+    int64_t ntiles = 0;                // merge / COO / HYB-tail tiles, row blocks
     BufPtr carries;                    // per-tile carries
     int grid_main = 0, grid_tail = 0;  // workgroups of the chain's kernels
     int grid_dot = 0;                  // ELL: workgroups of fused-dot launches
@@ -119,11 +119,16 @@ int spmv_slots(const MatrixImpl &A);
 int64_t merge_tiles(int64_t n, int64_t nnz);
 int64_t coo_tiles(int64_t nnz);
 int64_t carry_bytes(int64_t ntiles);
+// Row blocks of the streaming CSR kernel from host row pointers: (first
+// row, first nonzero) of every block plus the terminator (n, nnz).
+void stream_blocks(const std::vector<int32_t> &rp, std::vector<int32_t> &out);
 int ell_lds_cap();
 hipError_t merge_partition(const MatrixImpl &A, hipStream_t s);
 hipError_t spmv_launch(const MatrixImpl &A, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_validate(const MatrixImpl &A, int *flags, hipStream_t s);
 hipError_t launch_csr_to_coo(const MatrixImpl &A, int *row, hipStream_t s);
+hipError_t launch_csr_to_ell16(const MatrixImpl &A, int w, int64_t n_pad, short *ecol, void *evals,
+                               int *overflow, hipStream_t s);
 hipError_t launch_csr_to_ell(const MatrixImpl &A, int w, int64_t n_pad, int *ecol, void *evals,
                              hipStream_t s);
 hipError_t launch_hyb_tail(const MatrixImpl &A, int k, const int64_t *toff, int *trow, int *tcol,

@@ -139,7 +139,9 @@ void compute_stored_bytes(MatrixImpl &A) {
     switch (A.format) {
     case MXL_FMT_CSR: A.stored_bytes = csr_bytes(A); break;
     case MXL_FMT_COO: A.stored_bytes = A.nnz * (vt + 8); break;
-    case MXL_FMT_ELL: A.stored_bytes = (int64_t)A.ell_w * A.n_pad * (vt + 4); break;
+    case MXL_FMT_ELL:
+        A.stored_bytes = (int64_t)A.ell_w * A.n_pad * (vt + (A.variant == MXL_ELL_DELTA16 ? 2 : 4));
+        break;
     case MXL_FMT_HYB:
         A.stored_bytes = (int64_t)A.ell_w * A.n_pad * (vt + 4) + A.tail_nnz * (vt + 8);
         break;
@@ -331,6 +333,15 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
             A->vw = w;
         } else if (prm.variant == MXL_CSR_MERGE) {
             if ((st = build_merge(*A)) != MXL_OK) return st;
+        } else if (prm.variant == MXL_CSR_STREAM) {
+            std::vector<int32_t> rp, bk;
+            if ((st = to_host(ctx, S.row_ptr, rp, (size_t)S.nrows + 1)) != MXL_OK) return st;
+            stream_blocks(rp, bk);
+            A->ntiles = (int64_t)bk.size() / 2 - 1;
+            A->part = alloc(bk.size() * 4, &e);
+            if (!A->part) return hip_fail(e, "alloc row blocks");
+            HIP_TRY(hipMemcpyAsync(A->part->p, bk.data(), bk.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));  // bk lifetime
         } else {
             return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown CSR variant");
         }
@@ -346,7 +357,8 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
         break;
     case MXL_FMT_ELL:
     case MXL_FMT_HYB: {
-        if (prm.variant != MXL_ELL_PLAIN && prm.variant != MXL_ELL_LDS)
+        if (prm.variant != MXL_ELL_PLAIN && prm.variant != MXL_ELL_LDS &&
+            !(fmt == MXL_FMT_ELL && prm.variant == MXL_ELL_DELTA16))
             return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown ELL variant");
         std::vector<int32_t> rp;
         if ((st = to_host(ctx, S.row_ptr, rp, (size_t)S.nrows + 1)) != MXL_OK) return st;
@@ -367,6 +379,7 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
             }
         }
         const int64_t n_pad = ((S.nrows + 63) / 64) * 64;
+        const bool d16 = fmt == MXL_FMT_ELL && prm.variant == MXL_ELL_DELTA16;
         if (!ell_fits(S, w))
             return fail(MXL_ERR_INFEASIBLE_FORMAT, "ELL storage would exceed min(4x CSR bytes, 32 GiB)");
         A->ell_w = w;
@@ -374,10 +387,23 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
         A->ell_rpt = prm.vector_width > 0 ? prm.vector_width : 2;
         if (A->ell_rpt != 1 && A->ell_rpt != 2 && A->ell_rpt != 4)
             return fail(MXL_ERR_INVALID_ARG, "ELL rows per thread (vector_width) must be 1, 2 or 4");
-        A->ell_col = alloc((size_t)w * n_pad * 4, &e);
+        A->ell_col = alloc((size_t)w * n_pad * (d16 ? 2 : 4), &e);
         A->ell_val = alloc((size_t)w * n_pad * vt, &e);
         if (!A->ell_col || !A->ell_val) return hip_fail(hipErrorOutOfMemory, "alloc ell");
-        HIP_TRY(launch_csr_to_ell(*A, w, n_pad, (int *)A->ell_col->p, A->ell_val->p, ctx->stream));
+        if (d16) {
+            auto flag = alloc(4, &e);
+            if (!flag) return hip_fail(e, "alloc overflow flag");
+            int32_t over = 0;
+            HIP_TRY(hipMemcpyAsync(flag->p, &over, 4, hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(launch_csr_to_ell16(*A, w, n_pad, (short *)A->ell_col->p, A->ell_val->p, (int *)flag->p,
+                                        ctx->stream));
+            HIP_TRY(hipMemcpyAsync(&over, flag->p, 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            if (over)
+                return fail(MXL_ERR_INFEASIBLE_FORMAT, "a column offset |col - row| exceeds 32767 (16-bit ELL)");
+        } else {
+            HIP_TRY(launch_csr_to_ell(*A, w, n_pad, (int *)A->ell_col->p, A->ell_val->p, ctx->stream));
+        }
         if (prm.variant == MXL_ELL_LDS)
             if ((st = build_ell_windows(*A)) != MXL_OK) return st;
         if (fmt == MXL_FMT_HYB) {
@@ -528,7 +554,11 @@ mxl_status mxl_op_export(const mxl_op *op, int32_t which, void *dst, int64_t dst
     case 1: b = A->col; bytes = A->nnz * 4; break;
     case 2: b = A->val; bytes = A->nnz * vt; break;
     case 3: b = A->coo_row; bytes = A->nnz * 4; break;
-    case 4: b = A->ell_col; bytes = (size_t)A->ell_w * A->n_pad * 4; break;
+    case 4:
+        b = A->ell_col;
+        bytes = (size_t)A->ell_w * A->n_pad *
+                (A->format == MXL_FMT_ELL && A->variant == MXL_ELL_DELTA16 ? 2 : 4);
+        break;
     case 5: b = A->ell_val; bytes = (size_t)A->ell_w * A->n_pad * vt; break;
     case 6: b = A->tail_row; bytes = A->tail_nnz * 4; break;
     case 7: b = A->tail_col; bytes = A->tail_nnz * 4; break;

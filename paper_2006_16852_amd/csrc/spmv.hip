@@ -12,6 +12,8 @@
 // gathered x in cache.  No MFMA: this is not a dense contraction.
 #include <climits>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -143,6 +145,100 @@ __global__ __launch_bounds__(kWG) void k_csr_vector(int64_t n, const int *__rest
     }
 }
 
+// ------------------------------------------------------- row-block CSR
+// Rows are cut (once, at conversion) into blocks of at most kStreamRows
+// consecutive rows holding at most kStreamK*64 nonzeros; a row longer than
+// that forms a block of its own.  Block b is described by (first row, first
+// nonzero) in blk[b] (blk[nblk] = (n, nnz)).  One wave takes a block: its
+// lanes load the block's nonzeros as kStreamK fully coalesced, independent
+// loads, gather x, and park the products in the wave's LDS slice; then lane
+// l sums the products of row first+l in order.  A long row is swept by the
+// whole wave and reduced by shuffles.  No workgroup barrier is involved:
+// every wave walks its own blocks.
+constexpr int kStreamK = 8;
+constexpr int kStreamRows = 63;  // a lane reads the next row's start from its neighbour
+
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kWG) void k_csr_stream(int64_t nblk, const int2 *__restrict__ blk,
+                                                    const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const V *__restrict__ val, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    __shared__ V s_prod[kWG / kWave][kStreamK * kWave];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    constexpr int WPG = kWG / kWave;
+    // walkers: 4 waves per workgroup; when the grid is a multiple of 8 the
+    // walker id keeps the workgroup's XCD (blockIdx % 8) in its low bits
+    const int G = (int)gridDim.x, nw = G * WPG;
+    const int vid = (G % kNumXcd == 0)
+                        ? ((int)(blockIdx.x / kNumXcd) * WPG + wid) * kNumXcd + (int)(blockIdx.x % kNumXcd)
+                        : (int)blockIdx.x * WPG + wid;
+    int64_t b0, b1;
+    int bs;
+    band_walk(nblk, vid, nw, b0, b1, bs);
+    V *sp = s_prod[wid];
+    double dacc = 0.0;
+    int2 d0 = make_int2(0, 0), d1 = make_int2(0, 0);
+    if (b0 < b1) {
+        d0 = blk[b0];
+        d1 = blk[b0 + 1];
+    }
+    for (int64_t b = b0; b < b1; b += bs) {
+        // descriptor of the next block, loaded while this one is processed
+        const int64_t bn = b + bs;
+        int2 e0 = make_int2(0, 0), e1 = make_int2(0, 0);
+        if (bn < b1) {
+            e0 = blk[bn];
+            e1 = blk[bn + 1];
+        }
+        const int r0 = d0.x, k0 = d0.y, nr = d1.x - d0.x, k1 = d1.y;
+        if (k1 - k0 > kStreamK * kWave) {  // one long row
+            V acc = 0;
+            for (int k = k0 + lane; k < k1; k += kWave) acc += ld_stream(val + k) * p.x[ld_stream(col + k)];
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+            if (lane == 0) {
+                const V out = combine(p, acc, r0);
+                p.y[r0] = out;
+                if (DOT) dacc += (double)p.w[r0] * (double)out;
+            }
+        } else {
+            const int rs = lane <= nr ? rp[r0 + lane] : 0;
+            int c[kStreamK];
+            V v[kStreamK];
+#pragma unroll
+            for (int j = 0; j < kStreamK; ++j) {
+                const int k = k0 + lane + kWave * j;
+                const bool in = k < k1;
+                c[j] = in ? ld_stream(col + k) : -1;
+                v[j] = in ? ld_stream(val + k) : (V)0;
+            }
+#pragma unroll
+            for (int j = 0; j < kStreamK; ++j) sp[lane + kWave * j] = c[j] >= 0 ? v[j] * p.x[c[j]] : (V)0;
+            const int re = __shfl(rs, lane + 1 < kWave ? lane + 1 : kWave - 1, kWave);
+            // products visible to the other lanes of this wave (LDS is in order per wave)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < nr) {
+                V acc = 0;
+                for (int k = rs - k0; k < re - k0; ++k) acc += sp[k];
+                const int64_t row = (int64_t)r0 + lane;
+                const V out = combine(p, acc, row);
+                p.y[row] = out;
+                if (DOT) dacc += (double)p.w[row] * (double)out;
+            }
+            __builtin_amdgcn_wave_barrier();  // reads done before the next block's writes
+        }
+        d0 = e0;
+        d1 = e1;
+    }
+    if (DOT) {
+        double vv[1] = {dacc};
+        publish<1>(vv, p.partials, p.slot_base + (int)blockIdx.x);
+    }
+}
+
 // ------------------------------------------------------- merge path CSR
 // The (row ends) x (nonzeros) merge sequence of n + nnz items is cut into
 // tiles of ITEMS = 256*IPT items; coordinates of every tile boundary are
@@ -158,8 +254,6 @@ struct Carry {
 
 constexpr int kMergeIPT = 6;
 constexpr int kMergeItems = kWG * kMergeIPT;
-constexpr int kCooIPT = 6;
-constexpr int kCooItems = kWG * kCooIPT;
 
 __global__ void k_merge_partition(int64_t n, int64_t nnz, const int *__restrict__ rp, int64_t ntiles,
                                   int2 *__restrict__ part) {
@@ -269,105 +363,142 @@ __global__ __launch_bounds__(kWG) void k_csr_merge(int64_t n, const int *__restr
 }
 
 // ------------------------------------------------------------------ COO
-// Row-sorted triplets in tiles of kCooItems nonzeros.  A row ends at item k
-// iff row[k+1] != row[k]; the tile holding that item writes y[row] (plus
-// the carries of earlier threads in the tile) and earlier tiles hand their
-// partial sums to k_carry_fixup.  Rows without entries are written by the
-// thread that sees the row index jump over them (skipped in ACC mode, which
-// accumulates into y: the HYB tail).
+// Wave-level COO: tiles of kCooWaveItems consecutive triplets, one wave per
+// tile, no workgroup barrier.  The wave loads its tile with coalesced loads
+// (lane l takes items l, l+64, ...), parks rows and products in its LDS
+// slice, and lane l then walks items 8l..8l+7 in order: rows that end inside
+// the lane are written at once; the partial sum of the lane's last row is
+// combined across lanes by a segmented inclusive scan (keys = rows, which
+// are sorted, so equal keys are contiguous).  The row still open at the end
+// of the tile is handed to k_carry_fixup.  Rows without entries are written
+// by the lane that sees the row index jump over them (not in ACC mode,
+// which accumulates into y: the HYB tail).
+constexpr int kCooWaveIPL = 8;                        // items per lane
+constexpr int kCooWaveItems = kWave * kCooWaveIPL;    // items per wave tile
+
 template <typename V, bool DOT, bool ACC>
-__global__ __launch_bounds__(kWG) void k_coo(int64_t n, int64_t nnz, const int *__restrict__ row,
-                                             const int *__restrict__ col,
-                                             const V *__restrict__ val, int64_t ntiles,
-                                             Carry *__restrict__ carries, SpmvK<V> p) {
+__global__ __launch_bounds__(kWG) void k_coo_wave(int64_t n, int64_t nnz, const int *__restrict__ row,
+                                                  const int *__restrict__ col,
+                                                  const V *__restrict__ val, int64_t ntiles,
+                                                  Carry *__restrict__ carries, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
-    __shared__ int s_row[kCooItems + 1];
-    __shared__ V s_prod[kCooItems];
-    __shared__ int s_crow[kWG];
-    __shared__ V s_cval[kWG];
-    const int tid = threadIdx.x;
-    const int L = blockIdx.x;
+    constexpr int WPG = kWG / kWave;
+    __shared__ int s_row[WPG][kCooWaveItems + 1];
+    __shared__ V s_prod[WPG][kCooWaveItems];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const int G = (int)gridDim.x, nw = G * WPG;
+    const int vid = (G % kNumXcd == 0)
+                        ? ((int)(blockIdx.x / kNumXcd) * WPG + wid) * kNumXcd + (int)(blockIdx.x % kNumXcd)
+                        : (int)blockIdx.x * WPG + wid;
     int64_t t0, t1;
     int ts;
-    band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
+    band_walk(ntiles, vid, nw, t0, t1, ts);
+    int *sr = s_row[wid];
+    V *sv = s_prod[wid];
     double dacc = 0.0;
+    const int nrow = (int)n;
+    auto emit = [&](int r, V acc) {  // y[r] from a complete in-tile sum
+        const V out = ACC ? p.y[r] + p.alpha * acc : combine(p, acc, r);
+        p.y[r] = out;
+        if (DOT) dacc += (double)p.w[r] * (double)(ACC ? p.alpha * acc : out);
+    };
     for (int64_t tile = t0; tile < t1; tile += ts) {
-        const int64_t k0 = tile * kCooItems;
-        int64_t k1 = k0 + kCooItems;
-        if (k1 > nnz) k1 = nnz;
-        const int nk = (int)(k1 - k0);
+        const int64_t e0 = tile * kCooWaveItems;
+        const int ne = (int)((nnz - e0) < kCooWaveItems ? (nnz - e0) : kCooWaveItems);
+        int rr[kCooWaveIPL], cc[kCooWaveIPL];
+        V vv[kCooWaveIPL];
 #pragma unroll
-        for (int u = 0; u < kCooIPT; ++u) {
-            int j = u * kWG + tid;
-            if (j < nk) {
-                int64_t k = k0 + j;
-                s_row[j] = ld_stream(row + k);
-                s_prod[j] = ld_stream(val + k) * p.x[ld_stream(col + k)];
+        for (int j = 0; j < kCooWaveIPL; ++j) {
+            const int i = lane + kWave * j;
+            const bool in = i < ne;
+            rr[j] = in ? ld_stream(row + e0 + i) : 0;
+            cc[j] = in ? ld_stream(col + e0 + i) : -1;
+            vv[j] = in ? ld_stream(val + e0 + i) : (V)0;
+        }
+        const int next = (e0 + ne < nnz) ? row[e0 + ne] : nrow;  // row after the tile ("all end" at nnz)
+#pragma unroll
+        for (int j = 0; j < kCooWaveIPL; ++j) {
+            const int i = lane + kWave * j;
+            if (i < ne) {
+                sr[i] = rr[j];
+                sv[i] = vv[j] * p.x[cc[j]];
             }
         }
-        if (tid == 0) s_row[nk] = (k1 < nnz) ? row[k1] : (int)n;  // n: "every row ends"
-        __syncthreads();
-        const int j0 = tid * kCooIPT;
-        int j1 = j0 + kCooIPT;
-        if (j1 > nk) j1 = nk;
+        if (lane == 0) sr[ne] = next;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int j0 = lane * kCooWaveIPL;
+        const int j1 = j0 + kCooWaveIPL < ne ? j0 + kCooWaveIPL : ne;
+        if (!ACC && e0 == 0 && lane == 0 && ne > 0)  // rows before the first entry
+            for (int g = 0; g < sr[0]; ++g) p.y[g] = combine(p, (V)0, g);
+        // walk: rows that start and end inside the lane are final; the first
+        // row of the lane (which may have started earlier) is held back
         V acc = 0;
-        int first_row = -1;
-        V first_val = 0;
-        int cur = -1;
+        int head_row = -1;
+        V head_val = 0;
+        bool at_start = true;
         for (int j = j0; j < j1; ++j) {
-            const int r = s_row[j];
-            if (!ACC && k0 + j == 0)  // rows before the first entry
-                for (int g = 0; g < r; ++g) p.y[g] = combine(p, (V)0, g);
-            cur = r;
-            acc += s_prod[j];
-            const int rn = s_row[j + 1];
+            const int r = sr[j];
+            acc += sv[j];
+            const int rn = sr[j + 1];
             if (rn != r) {
-                if (!ACC) {  // rows skipped between this entry and the next
-                    const int last = rn < (int)n ? rn : (int)n;
+                if (!ACC) {
+                    const int last = rn < nrow ? rn : nrow;
                     for (int g = r + 1; g < last; ++g) p.y[g] = combine(p, (V)0, g);
                 }
-                if (first_row < 0) { first_row = r; first_val = acc; }
-                else {
-                    V out = ACC ? p.y[r] + p.alpha * acc : combine(p, acc, r);
-                    p.y[r] = out;
-                    if (DOT) dacc += (double)p.w[r] * (double)(ACC ? p.alpha * acc : out);
+                if (at_start) {
+                    head_row = r;
+                    head_val = acc;
+                } else {
+                    emit(r, acc);
                 }
                 acc = 0;
-                cur = -1;
+                at_start = false;
             }
         }
-        s_crow[tid] = cur;  // -1 when the thread's last row ended (or no items)
-        s_cval[tid] = acc;
-        __syncthreads();
-        if (first_row >= 0) {
-            V c = 0;
-            for (int t2 = tid - 1; t2 >= 0 && s_crow[t2] == first_row; --t2) c += s_cval[t2];
-            V tot = first_val + c;
-            V out = ACC ? p.y[first_row] + p.alpha * tot : combine(p, tot, first_row);
-            p.y[first_row] = out;
-            if (DOT) dacc += (double)p.w[first_row] * (double)(ACC ? p.alpha * tot : out);
+        // lane tails: the open row at the lane's end and its partial sum
+        const bool has = j1 > j0;
+        const bool open = has && sr[j1] == sr[j1 - 1];
+        int key = open ? sr[j1 - 1] : -1 - lane;  // closed lanes never chain
+        V tail = open ? acc : (V)0;
+        // segmented inclusive scan of the tails over lanes
+        V scan = tail;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const V up = __shfl_up(scan, d, kWave);
+            const int ku = __shfl_up(key, d, kWave);
+            if (lane >= d && ku == key) scan += up;
         }
-        if (tid == 0) {
+        // carry into this lane's head row: the previous lane's scan if its
+        // open row is the head row
+        const V prev_scan = __shfl_up(scan, 1, kWave);
+        const int prev_key = __shfl_up(key, 1, kWave);
+        if (head_row >= 0) {
+            const V cin = (lane > 0 && prev_key == head_row) ? prev_scan : (V)0;
+            emit(head_row, head_val + cin);
+        }
+        // the row still open at the tile's end continues in the next tile
+        const int last_lane = ne > 0 ? (ne - 1) / kCooWaveIPL : 0;
+        const V tile_tail = __shfl(scan, last_lane, kWave);
+        const int tile_key = __shfl(key, last_lane, kWave);
+        if (lane == 0) {
             Carry cr;
             cr.row = -1;
             cr.pad = 0;
             cr.val = 0.0;
-            if (nk > 0 && s_row[nk] == s_row[nk - 1]) {
-                const int lr = s_row[nk - 1];
-                const int owner = (nk - 1) / kCooIPT;
-                V c = 0;
-                for (int t2 = owner; t2 >= 0 && s_crow[t2] == lr; --t2) c += s_cval[t2];
-                cr.row = lr;
-                cr.val = (double)c;
-                if (DOT) dacc += (double)p.w[lr] * (double)(p.alpha * c);
+            if (ne > 0 && next == sr[ne - 1]) {
+                cr.row = tile_key;
+                cr.val = (double)tile_tail;
+                if (DOT) dacc += (double)p.w[tile_key] * (double)(p.alpha * tile_tail);
             }
             carries[tile] = cr;
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // LDS reads done before the next tile's writes
     }
     if (DOT) {
-        double v[1] = {dacc};
-        publish<1>(v, p.partials, p.slot_base + L);
+        double vv2[1] = {dacc};
+        publish<1>(vv2, p.partials, p.slot_base + (int)blockIdx.x);
     }
 }
 
@@ -395,11 +526,11 @@ __global__ __launch_bounds__(kWG) void k_carry_fixup(const Carry *__restrict__ c
 // 256-row tile) into LDS when it fits, then gathers from LDS.
 constexpr int kEllLdsCap = 4096;  // x entries staged per tile (32 KB in FP64)
 
-// Vector types for R consecutive rows of one ELL slot (R = 1, 2, 4).
-template <int R> struct IdxVec;
-template <> struct IdxVec<1> { typedef int T; };
-template <> struct IdxVec<2> { typedef int T __attribute__((ext_vector_type(2))); };
-template <> struct IdxVec<4> { typedef int T __attribute__((ext_vector_type(4))); };
+// Vector types for R consecutive rows of one ELL slot (R = 1, 2, 4); I is
+// int (column indices) or short (16-bit offsets col - row).
+template <typename I, int R> struct IdxVec { typedef I T __attribute__((ext_vector_type(R))); };
+template <typename I> struct IdxVec<I, 1> { typedef I T; };
+constexpr short kEll16Pad = -32768;  // padding slot of the 16-bit-offset layout
 template <typename V, int R> struct ValVec { typedef V T __attribute__((ext_vector_type(R))); };
 template <typename V> struct ValVec<V, 1> { typedef V T; };
 
@@ -413,14 +544,18 @@ __device__ __forceinline__ auto lane_of(const T &v, int r) {
 // column indices and values arrive as one 4R- and one 8R-byte load (16-byte
 // loads at R = 4 for indices, 2 x 16 bytes for FP64 values).  U slots of
 // loads are issued before their x gathers.
-template <typename V, bool DOT, bool LDS, int R>
+// D16: the slots hold 16-bit offsets d = col - row (kEll16Pad = padding),
+// which cuts the index stream from 4 to 2 bytes per slot.
+template <typename V, bool DOT, bool LDS, int R, bool D16 = false>
 __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
-                                             const int *__restrict__ ecol,
+                                             const void *__restrict__ ecol_,
                                              const V *__restrict__ evals,
                                              const int2 *__restrict__ win, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
     constexpr int U = 8 / R;
-    typedef typename IdxVec<R>::T IV;
+    typedef typename std::conditional<D16, short, int>::type IT;
+    typedef typename IdxVec<IT, R>::T IV;
+    const IT *__restrict__ ecol = (const IT *)ecol_;
     typedef typename ValVec<V, R>::T VV;
     __shared__ V s_x[LDS ? kEllLdsCap : 1];
     const int L = blockIdx.x;
@@ -459,23 +594,32 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                         c[u] = __builtin_nontemporal_load(cp + (int64_t)(s0 + u) * stride);
                         v[u] = __builtin_nontemporal_load(vp + (int64_t)(s0 + u) * stride);
                     } else {
-                        c[u] = (IV)(-1);
+                        c[u] = (IV)(D16 ? kEll16Pad : -1);
                         v[u] = (VV)(V)0;
                     }
                 }
+                int ci[U][R];  // column index, -1 for padding
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int e = (int)lane_of<R>(c[u], r);
+                        if constexpr (D16) ci[u][r] = e == kEll16Pad ? -1 : (int)(row0 + r) + e;
+                        else ci[u][r] = e;
+                    }
                 V xv[U][R];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const int cc = lane_of<R>(c[u], r);
+                        const int cc = ci[u][r];
                         xv[u][r] = cc >= 0 ? ((LDS && staged) ? s_x[cc - lo] : p.x[cc]) : (V)0;
                     }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        if (lane_of<R>(c[u], r) >= 0) acc[r] += lane_of<R>(v[u], r) * xv[u][r];
+                        if (ci[u][r] >= 0) acc[r] += lane_of<R>(v[u], r) * xv[u][r];
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -509,6 +653,32 @@ __global__ void k_csr_to_coo(int64_t n, const int *__restrict__ rp, int *__restr
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int k = rp[i]; k < rp[i + 1]; ++k) row[k] = (int)i;
+}
+
+// 16-bit-offset ELL: slot s of row i holds col - row; *overflow is set
+// when some offset does not fit (the layout then cannot hold the matrix).
+template <typename V>
+__global__ void k_csr_to_ell16(int64_t n, int64_t n_pad, int w, const int *__restrict__ rp,
+                               const int *__restrict__ col, const V *__restrict__ val,
+                               short *__restrict__ ecol, V *__restrict__ evals, int *overflow) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    int k0 = 0, len = 0;
+    if (i < n) { k0 = rp[i]; len = rp[i + 1] - k0; }
+    bool bad = false;
+    for (int s = 0; s < w; ++s) {
+        int64_t o = (int64_t)s * n_pad + i;
+        if (s < len) {
+            const int64_t d = (int64_t)col[k0 + s] - i;
+            bad |= d < -32767 || d > 32767;
+            ecol[o] = (short)d;
+            evals[o] = val[k0 + s];
+        } else {
+            ecol[o] = kEll16Pad;
+            evals[o] = (V)0;
+        }
+    }
+    if (bad) atomicOr(overflow, 1);
 }
 
 template <typename V>
@@ -630,6 +800,15 @@ static int plain_grid(const MatrixImpl &A, int64_t tiles) {
 
 constexpr int kDotSlotCap = 4096;  // partial slots a fused-dot launch may publish
 
+// Grids of the wave-walker kernels (4 walking waves per workgroup): a
+// multiple of 8 workgroups keeps each walker on its XCD's band.
+static int walker_grid(int64_t units, int cap) {
+    int64_t g = (units + kWG / kWave - 1) / (kWG / kWave);
+    g = g < cap ? g : cap;
+    if (g >= kNumXcd) g -= g % kNumXcd;
+    return (int)(g > 0 ? g : 1);
+}
+
 void spmv_plan(MatrixImpl &A) {
     const int cap = spmv_grid_cap(A);
     A.grid_main = A.grid_tail = 0;
@@ -639,10 +818,11 @@ void spmv_plan(MatrixImpl &A) {
         if (A.variant == MXL_CSR_SCALAR) A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
         else if (A.variant == MXL_CSR_VECTOR)
             A.grid_main = grid_for((A.nrows + kWG / A.vw - 1) / (kWG / A.vw), cap);
+        else if (A.variant == MXL_CSR_STREAM) A.grid_main = walker_grid(A.ntiles, cap);
         else A.grid_main = grid_for(A.ntiles, cap);
         break;
     case MXL_FMT_COO:
-        A.grid_main = grid_for(A.ntiles, cap);
+        A.grid_main = walker_grid(A.ntiles, cap);
         break;
     case MXL_FMT_ELL: {
         const int64_t tiles = (A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt);
@@ -654,7 +834,7 @@ void spmv_plan(MatrixImpl &A) {
     case MXL_FMT_HYB:
         A.grid_main = grid_for((A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt), cap);
         A.grid_dot = A.grid_main;  // the tail's partials follow the ELL part's
-        A.grid_tail = grid_for(A.ntiles, cap);
+        A.grid_tail = walker_grid(A.ntiles, cap);
         break;
     }
 }
@@ -663,8 +843,24 @@ int spmv_slots(const MatrixImpl &A) {
     return (A.format == MXL_FMT_ELL ? A.grid_dot : A.grid_main) + A.grid_tail;
 }
 
+void stream_blocks(const std::vector<int32_t> &rp, std::vector<int32_t> &out) {
+    const int64_t n = (int64_t)rp.size() - 1;
+    out.clear();
+    int64_t r = 0;
+    while (r < n) {
+        out.push_back((int32_t)r);
+        out.push_back(rp[r]);
+        int64_t r1 = r + 1;
+        if (rp[r + 1] - rp[r] <= kStreamK * kWave)
+            while (r1 < n && r1 - r < kStreamRows && rp[r1 + 1] - rp[r] <= kStreamK * kWave) ++r1;
+        r = r1;
+    }
+    out.push_back((int32_t)n);
+    out.push_back(n >= 0 ? rp[n] : 0);
+}
+
 int64_t merge_tiles(int64_t n, int64_t nnz) { return (n + nnz + kMergeItems - 1) / kMergeItems; }
-int64_t coo_tiles(int64_t nnz) { return (nnz + kCooItems - 1) / kCooItems; }
+int64_t coo_tiles(int64_t nnz) { return (nnz + kCooWaveItems - 1) / kCooWaveItems; }
 int64_t carry_bytes(int64_t ntiles) { return (ntiles > 0 ? ntiles : 1) * (int64_t)sizeof(Carry); }
 int ell_lds_cap() { return kEllLdsCap; }
 
@@ -715,6 +911,10 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
             default: return hipErrorInvalidValue;
             }
 #undef MXL_VEC_CASE
+        } else if (A.variant == MXL_CSR_STREAM) {
+            const int2 *bk = (const int2 *)A.part->p;
+            if (dot) hipLaunchKernelGGL((k_csr_stream<V, true>), dim3(A.grid_main), blk, 0, s, A.ntiles, bk, rp, col, val, p);
+            else hipLaunchKernelGGL((k_csr_stream<V, false>), dim3(A.grid_main), blk, 0, s, A.ntiles, bk, rp, col, val, p);
         } else {
             Carry *cr = (Carry *)A.carries->p;
             const int2 *part = (const int2 *)A.part->p;
@@ -732,22 +932,26 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
         }
         Carry *cr = (Carry *)A.carries->p;
         const int *row = (const int *)A.coo_row->p;
-        if (dot) hipLaunchKernelGGL((k_coo<V, true, false>), dim3(A.grid_main), blk, 0, s, n, A.nnz, row, col, val, A.ntiles, cr, p);
-        else hipLaunchKernelGGL((k_coo<V, false, false>), dim3(A.grid_main), blk, 0, s, n, A.nnz, row, col, val, A.ntiles, cr, p);
+        if (dot) hipLaunchKernelGGL((k_coo_wave<V, true, false>), dim3(A.grid_main), blk, 0, s, n, A.nnz, row, col, val, A.ntiles, cr, p);
+        else hipLaunchKernelGGL((k_coo_wave<V, false, false>), dim3(A.grid_main), blk, 0, s, n, A.nnz, row, col, val, A.ntiles, cr, p);
         fixup(cr, A.ntiles);
         break;
     }
     case MXL_FMT_ELL:
     case MXL_FMT_HYB: {
-        const int *ec = (const int *)A.ell_col->p;
+        const void *ec = A.ell_col->p;
         const V *ev = (const V *)A.ell_val->p;
         const int2 *win = A.ell_win ? (const int2 *)A.ell_win->p : nullptr;
         const bool lds = A.variant == MXL_ELL_LDS && win;
+        const bool d16 = A.format == MXL_FMT_ELL && A.variant == MXL_ELL_DELTA16;
         const dim3 ge(dot ? A.grid_dot
                           : plain_grid(A, (n + (int64_t)kWG * A.ell_rpt - 1) / ((int64_t)kWG * A.ell_rpt)));
 #define MXL_ELL_CASE(RR)                                                                                          \
     case RR:                                                                                                      \
-        if (lds) {                                                                                                \
+        if (d16) {                                                                                                \
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, false, RR, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p); \
+            else hipLaunchKernelGGL((k_ell<V, false, false, RR, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);    \
+        } else if (lds) {                                                                                         \
             if (dot) hipLaunchKernelGGL((k_ell<V, true, true, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);   \
             else hipLaunchKernelGGL((k_ell<V, false, true, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);      \
         } else {                                                                                                  \
@@ -769,8 +973,8 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
             const int *tr = (const int *)A.tail_row->p;
             const int *tc = (const int *)A.tail_col->p;
             const V *tv = (const V *)A.tail_val->p;
-            if (dot) hipLaunchKernelGGL((k_coo<V, true, true>), dim3(A.grid_tail), blk, 0, s, n, A.tail_nnz, tr, tc, tv, A.ntiles, cr, t);
-            else hipLaunchKernelGGL((k_coo<V, false, true>), dim3(A.grid_tail), blk, 0, s, n, A.tail_nnz, tr, tc, tv, A.ntiles, cr, t);
+            if (dot) hipLaunchKernelGGL((k_coo_wave<V, true, true>), dim3(A.grid_tail), blk, 0, s, n, A.tail_nnz, tr, tc, tv, A.ntiles, cr, t);
+            else hipLaunchKernelGGL((k_coo_wave<V, false, true>), dim3(A.grid_tail), blk, 0, s, n, A.tail_nnz, tr, tc, tv, A.ntiles, cr, t);
             fixup(cr, A.ntiles);
         }
         break;
@@ -811,6 +1015,20 @@ hipError_t launch_csr_to_ell(const MatrixImpl &A, int w, int64_t n_pad, int *eco
         hipLaunchKernelGGL(k_csr_to_ell<float>, g1(n_pad), dim3(256), 0, s, A.nrows, n_pad, w,
                            (const int *)A.row_ptr->p, (const int *)A.col->p,
                            (const float *)A.val->p, ecol, (float *)evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_to_ell16(const MatrixImpl &A, int w, int64_t n_pad, short *ecol, void *evals,
+                               int *overflow, hipStream_t s) {
+    if (n_pad == 0 || w == 0) return hipSuccess;
+    if (A.dtype == MXL_F64)
+        hipLaunchKernelGGL(k_csr_to_ell16<double>, g1(n_pad), dim3(256), 0, s, A.nrows, n_pad, w,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const double *)A.val->p, ecol, (double *)evals, overflow);
+    else
+        hipLaunchKernelGGL(k_csr_to_ell16<float>, g1(n_pad), dim3(256), 0, s, A.nrows, n_pad, w,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p,
+                           (const float *)A.val->p, ecol, (float *)evals, overflow);
     return hipGetLastError();
 }
 

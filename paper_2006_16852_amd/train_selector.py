@@ -75,6 +75,27 @@ def evaluate(ctx, sel, F, T, fallback_times=None):
     return pred
 
 
+def suite_bandwidth(T, meta, test, choice_test):
+    """SpMV bandwidth over the suite in CSR-equivalent GB/s (the bytes a CSR
+    product must move: nnz (8+4) + (n+1) 4 + 2 n 8, divided by the measured
+    time), so that formats compare on the same work: quartiles per class,
+    for the fastest class of every matrix, and for the network's choices on
+    the held-out matrices."""
+    n = np.array([m["n"] for m in meta], float)
+    nnz = np.array([m["nnz"] for m in meta], float)
+    byts = nnz * 12 + (n + 1) * 4 + 16 * n
+    G = np.where(np.isfinite(T), byts[:, None] / (T * 1e-3) / 1e9, np.nan)
+
+    def q(v):
+        v = v[np.isfinite(v)]
+        return dict(p25=round(float(np.quantile(v, 0.25)), 1), median=round(float(np.median(v)), 1),
+                    p75=round(float(np.quantile(v, 0.75)), 1), count=int(v.size)) if v.size else None
+    out = {c[0]: q(G[:, k]) for k, c in enumerate(S.CLASSES)}
+    out["best_class"] = q(np.nanmax(G, axis=1))
+    out["selector_test"] = q(G[test, choice_test] if len(test) else np.array([]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
@@ -152,6 +173,7 @@ def main():
                                                      best_fixed=choice_fixed, hand_rule=choice_hand,
                                                      default_vector=choice_default)),
               class_wins={S.CLASSES[k][0]: int(np.sum(np.argmin(T, axis=1) == k)) for k in range(S.NCLS)})
+    ev["suite_bandwidth"] = suite_bandwidth(T, meta, test, choice_net)
     json.dump(ev, open(os.path.join(args.out, "selector_eval.json"), "w"), indent=1)
     log(json.dumps(ev["regret"]))
 

@@ -41,10 +41,11 @@ def _true_rel(A, b, x):
 
 
 FORMATS = [("csr", dict(variant=1)), ("csr", dict(variant=2)), ("csr", dict(variant=0)),
-           ("coo", {}), ("ell", {}), ("hyb", dict(hyb_quantile=0.66))]
+           ("csr", dict(variant=3)), ("coo", {}), ("ell", {}), ("ell", dict(variant=2)),
+           ("hyb", dict(hyb_quantile=0.66))]
 
 
-@pytest.mark.parametrize("fmt,kw", FORMATS, ids=["vec", "merge", "scalar", "coo", "ell", "hyb"])
+@pytest.mark.parametrize("fmt,kw", FORMATS, ids=["vec", "merge", "scalar", "stream", "coo", "ell", "ell16", "hyb"])
 def test_pcg_cfg1_all_formats(mxl, ctx, fmt, kw):
     A = W.stencil_2d5(64)
     b = O.spmv(A, W.uniform_vec(A.nrows, 1))

@@ -25,9 +25,11 @@ VARIANTS = [
     ("csr", 1, 32, 0.0, "csr_vec32"),
     ("csr", 1, 64, 0.0, "csr_vec64"),
     ("csr", 2, 0, 0.0, "csr_merge"),
+    ("csr", 3, 0, 0.0, "csr_stream"),
     ("coo", 0, 0, 0.0, "coo"),
     ("ell", 0, 0, 0.0, "ell"),
     ("ell", 1, 0, 0.0, "ell_lds"),
+    ("ell", 2, 0, 0.0, "ell16"),
     ("hyb", 0, 0, 0.66, "hyb66"),
     ("hyb", 1, 0, 0.9, "hyb90_lds"),
 ]
@@ -142,6 +144,15 @@ def test_format_arrays_bitwise(mxl, ctx, A):
         assert (d["ell_width"], d["n_pad"]) == (w, n_pad)
         assert np.array_equal(ell.export("ell_col").cpu().numpy(), ec)
         assert np.array_equal(ell.export("ell_val").cpu().numpy(), ev)
+        # 16-bit offsets: slot s of row i holds col - i, padding -32768
+        rows = np.arange(ec.size) % n_pad
+        off = np.where(ec >= 0, ec.astype(np.int64) - rows, -32768)
+        if np.all(np.abs(off[ec >= 0]) <= 32767):
+            e16 = base.convert("ell", variant=mxl.ELL_DELTA16)
+            assert e16.export("ell_col").dtype == torch.int16
+            assert np.array_equal(e16.export("ell_col").cpu().numpy().astype(np.int64), off)
+            assert np.array_equal(e16.export("ell_val").cpu().numpy(), ev)
+            assert e16.describe()["stored_bytes"] == ec.size * (8 + 2)
     except mxl.MxlError as e:
         assert e.status == mxl.ERR_INFEASIBLE_FORMAT
     for q in (0.66, 0.9):
@@ -152,6 +163,34 @@ def test_format_arrays_bitwise(mxl, ctx, A):
         for key in ("ell_col", "ell_val", "tail_row", "tail_col", "tail_val"):
             got = hyb.export(key).cpu().numpy()
             assert np.array_equal(got, H[key]), key
+
+
+def test_ell16_offset_range(mxl, ctx):
+    """16-bit offsets hold |col - row| <= 32767 exactly; one entry further
+    out makes the layout infeasible (the 32-bit layout still converts), and
+    a HYB request for it is not provided."""
+    n = 40000
+    for far, ok in ((32767, True), (32768, False)):
+        rp = np.concatenate([[0], np.cumsum(np.r_[2, np.ones(n - 1, np.int64)])]).astype(np.int32)
+        col = np.concatenate([[0, far], np.arange(1, n)]).astype(np.int32)
+        val = np.arange(1, n + 2, dtype=np.float64)
+        A = W.Csr(n, n, rp, col, val, f"far{far}")
+        base = matrix(mxl, ctx, A)
+        base.convert("ell")
+        if ok:
+            e16 = base.convert("ell", variant=mxl.ELL_DELTA16)
+            x = W.uniform_vec(n, 3)
+            y = torch.zeros(n, dtype=torch.float64, device=DEV)
+            e16.apply(dev(x), y)
+            want, bound = spmv_reference(A, x, 1.0, 0.0, np.zeros(n), False)
+            assert_rows_close(y.cpu().numpy(), want, bound, 1e-12, "ell16")
+        else:
+            with pytest.raises(mxl.MxlError) as e:
+                base.convert("ell", variant=mxl.ELL_DELTA16)
+            assert e.value.status == mxl.ERR_INFEASIBLE_FORMAT
+    with pytest.raises(mxl.MxlError) as e:
+        base.convert("hyb", variant=mxl.ELL_DELTA16)
+    assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
 
 
 def test_spmv_deterministic(mxl, ctx):
@@ -191,7 +230,8 @@ def test_full_size_stencil27_sampled(mxl, ctx):
     c = [np.where((t == 0) | (t == N - 1), 2, 3) for t in (idx % N, (idx // N) % N, idx // N ** 2)]
     rowsum = (27 - c[0] * c[1] * c[2]).astype(np.float64)
     for fmt, var, vw, q, name in [v for v in VARIANTS if v[-1] in
-                                  ("csr_vec32", "csr_merge", "csr_scalar", "coo", "ell", "hyb90_lds")]:
+                                  ("csr_vec32", "csr_merge", "csr_stream", "csr_scalar", "coo", "ell",
+                                   "ell16", "hyb90_lds")]:
         print(f"[full27] {name}", flush=True)
         op = _convert(base, fmt, var, vw, q)
         y = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
