@@ -228,6 +228,16 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
                                                     SolverState *st, const double *__restrict__ parts,
                                                     int slots, int k, double *hist) {
     if (st->stop) return;
+    MXL_RANGE(n)
+    V rv[kPf], pv[kPf], vv[kPf], dv[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        rv[u] = in_u ? r[i_u] : (V)0;
+        pv[u] = in_u ? p[i_u] : (V)0;
+        vv[u] = in_u ? v[i_u] : (V)0;
+        dv[u] = in_u && dinv ? dinv[i_u] : (V)1;
+    }
     double t[3];
     gather_all<3>(parts, slots, t);
     const double rr = t[0], rho = t[1];
@@ -259,12 +269,18 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
         }
     }
     if (stop != ST_RUN) return;
-    MXL_RANGE(n)
-    MXL_FOR(i, n) {
-        V pi = (V)((double)r[i] + beta * ((double)p[i] - omega_prev * (double)v[i]));
+    auto step = [&](int64_t i, V r0, V p0, V v0, V d0) {
+        const V pi = (V)((double)r0 + beta * ((double)p0 - omega_prev * (double)v0));
         p[i] = pi;
-        phat[i] = (V)prec_z(dinv, i, pi);
+        phat[i] = (V)(dinv ? (double)d0 * (double)pi : (double)pi);
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        if (in_u) step(i_u, rv[u], pv[u], vv[u], dv[u]);
     }
+    for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(i, r[i], p[i], v[i], dinv ? dinv[i] : (V)1);
 }
 
 // Consumes rhat.v (fused into the SpMV): alpha = rho_k / rhat.v; s = r - alpha v.
@@ -276,6 +292,15 @@ __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restri
                                                     const double *__restrict__ rv_parts, int rv_slots,
                                                     double *__restrict__ parts, int k) {
     if (st->stop) return;
+    MXL_RANGE(n)
+    V r_[kPf], v_[kPf], d_[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        r_[u] = in_u ? r[i_u] : (V)0;
+        v_[u] = in_u ? v[i_u] : (V)0;
+        d_[u] = in_u && dinv ? dinv[i_u] : (V)1;
+    }
     double rv[1];
     gather_all<1>(rv_parts, rv_slots, rv);
     const bool chk = st->nonfinite_check != 0;
@@ -289,14 +314,20 @@ __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restri
     }
     const double alpha = st->rho2[k & 1] / rv[0];
     if (MXL_LEAD) st->alpha = alpha;
-    MXL_RANGE(n)
     double ss = 0.0;
-    MXL_FOR(i, n) {
-        V si = (V)((double)r[i] - alpha * (double)v[i]);
+    auto step = [&](int64_t i, V r0, V v0, V d0) {
+        const V si = (V)((double)r0 - alpha * (double)v0);
         s[i] = si;
-        shat[i] = (V)prec_z(dinv, i, si);
+        shat[i] = (V)(dinv ? (double)d0 * (double)si : (double)si);
         ss += (double)si * (double)si;
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        if (in_u) step(i_u, r_[u], v_[u], d_[u]);
     }
+    for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(i, r[i], v[i], dinv ? dinv[i] : (V)1);
     double a[1] = {ss};
     publish<1>(a, parts, L);
 }
@@ -308,6 +339,14 @@ __global__ __launch_bounds__(kWG) void k_bi_tdots(int64_t n, const V *__restrict
                                                   const double *__restrict__ ss_parts, int ss_slots,
                                                   double *__restrict__ parts, int k, double *hist) {
     if (st->stop) return;
+    MXL_RANGE(n)
+    V t_v[kPf], s_v[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        t_v[u] = in_u ? t[i_u] : (V)0;
+        s_v[u] = in_u ? s[i_u] : (V)0;
+    }
     double ss[1];
     gather_all<1>(ss_parts, ss_slots, ss);
     const double nb = sqrt(st->nb2);
@@ -321,13 +360,19 @@ __global__ __launch_bounds__(kWG) void k_bi_tdots(int64_t n, const V *__restrict
         }
         return;
     }
-    MXL_RANGE(n)
     double ts = 0.0, tt = 0.0;
-    MXL_FOR(i, n) {
-        double ti = (double)t[i];
-        ts += ti * (double)s[i];
+    auto step = [&](V t0, V s0) {
+        const double ti = (double)t0;
+        ts += ti * (double)s0;
         tt += ti * ti;
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        if (in_u) step(t_v[u], s_v[u]);
     }
+    for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(t[i], s[i]);
     double a[2] = {ts, tt};
     publish<2>(a, parts, L);
 }
@@ -353,6 +398,18 @@ __global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x
         return;
     }
     if (mode != ST_RUN) return;
+    MXL_RANGE(n)
+    V xv[kPf], ph[kPf], sh[kPf], sv[kPf], tv[kPf], rh[kPf];
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        xv[u] = in_u ? x[i_u] : (V)0;
+        ph[u] = in_u ? phat[i_u] : (V)0;
+        sh[u] = in_u ? shat[i_u] : (V)0;
+        sv[u] = in_u ? s[i_u] : (V)0;
+        tv[u] = in_u ? t[i_u] : (V)0;
+        rh[u] = in_u ? rhat[i_u] : (V)0;
+    }
     double d[2];
     gather_all<2>(ts_parts, ts_slots, d);
     const double ts = d[0], tt = d[1];
@@ -367,15 +424,21 @@ __global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x
     }
     const double omega = ts / tt;
     if (MXL_LEAD) st->omega = omega;
-    MXL_RANGE(n)
     double rr = 0.0, rhr = 0.0;
-    MXL_FOR(i, n) {
-        x[i] = (V)((double)x[i] + alpha * (double)phat[i] + omega * (double)shat[i]);
-        V ri = (V)((double)s[i] - omega * (double)t[i]);
+    auto step = [&](int64_t i, V x0, V ph0, V sh0, V s0, V t0, V rh0) {
+        x[i] = (V)((double)x0 + alpha * (double)ph0 + omega * (double)sh0);
+        const V ri = (V)((double)s0 - omega * (double)t0);
         r[i] = ri;
         rr += (double)ri * (double)ri;
-        rhr += (double)rhat[i] * (double)ri;
+        rhr += (double)rh0 * (double)ri;
+    };
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+        MXL_PF_INDEX(u)
+        if (in_u) step(i_u, xv[u], ph[u], sh[u], sv[u], tv[u], rh[u]);
     }
+    for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
+        if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(i, x[i], phat[i], shat[i], s[i], t[i], rhat[i]);
     double a[3] = {rr, rhr, 0.0};
     publish<3>(a, parts, L);
 }
