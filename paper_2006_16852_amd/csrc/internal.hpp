@@ -208,8 +208,10 @@ bool ell_fits(const MatrixImpl &S, int64_t w);
 int64_t quantile_rank(double q, int64_t n);
 
 // ------------------------------------------------------------- select.hip
-// The 16 features; hist (optional) receives the row-length histogram.
-mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<unsigned> *hist = nullptr);
+// The 16 features; hist (optional) receives the row-length histogram and
+// maxbw (optional) the largest |col - row|.
+mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<unsigned> *hist = nullptr,
+                            int64_t *maxbw = nullptr);
 
 }  // namespace mxl
 

@@ -213,7 +213,8 @@ using namespace mxl;
 // ================================================================== host
 namespace mxl {
 
-mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<unsigned> *hist_out) {
+mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<unsigned> *hist_out,
+                            int64_t *maxbw_out) {
     mxl_ctx *ctx = A.ctx;
     hipStream_t s = ctx->stream;
     for (int j = 0; j < 16; ++j) out[j] = 0.0;
@@ -262,6 +263,7 @@ mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<uns
     }
     cleanup();
     if (hist_out) *hist_out = hist;
+    if (maxbw_out) *maxbw_out = (int64_t)h.maxbw;
     // nearest-rank quantiles: sorted length at 1-based rank ceil(P*n/100)
     auto quant = [&](int P) {
         const int64_t rank = (P * n + 99) / 100;
@@ -579,13 +581,16 @@ extern "C" mxl_status mxl_select(const mxl_selector *S, const mxl_op *Aop, int32
     mxl_select_info inf_out{};
     double f[16];
     std::vector<unsigned> hist;
-    mxl_status st = features_compute(A, f, &hist);
+    int64_t maxbw = 0;
+    mxl_status st = features_compute(A, f, &hist, &maxbw);
     if (st != MXL_OK) return st;
     if (hist.empty()) hist.assign(1, (unsigned)A.nrows);
     std::vector<bool> feasible(C);
     for (int c = 0; c < C; ++c) {
-        const int64_t w = class_width(S->classes[c], hist, A.nrows);
+        const mxl_kernel_class &k = S->classes[c];
+        const int64_t w = class_width(k, hist, A.nrows);
         feasible[c] = w < 0 || ell_fits(A, w);
+        if (k.format == MXL_FMT_ELL && k.params.variant == MXL_ELL_DELTA16 && maxbw > 32767) feasible[c] = false;
     }
     // standardised features and their largest magnitude
     float z[16];

@@ -34,17 +34,22 @@ from paper_2006_16852_amd import selector as S  # noqa: E402
 import workloads as W  # noqa: E402
 
 
-def hand_rule(f: np.ndarray) -> int:
+def hand_rule(f: np.ndarray) -> str:
     """No-network baseline: a fixed rule on mean and spread of row lengths."""
     mu, cv = f[2], f[4]
     if cv < 0.3 and S.ell_feasible(f):
-        return 6                                   # ell
+        return "ell"
     if cv > 1.5:
-        return 4                                   # csr_merge
-    return 2 if mu <= 16 else 3                    # csr_vec16 / csr_vec64
+        return "csr_merge"
+    return "csr_vec16" if mu <= 16 else "csr_vec64"
 
 
-def collect(ctx, idx, scale, reps, log):
+def default_vector(f: np.ndarray) -> str:
+    """The library's default CSR kernel: vector width from the mean row length."""
+    return "csr_vec4" if f[2] <= 6 else ("csr_vec16" if f[2] <= 24 else "csr_vec64")
+
+
+def collect(ctx, idx, scale, reps, log, classes=S.CLASSES):
     feats, times, meta = [], [], []
     dev = f"cuda:{ctx.device}"
     for m in idx:
@@ -58,11 +63,11 @@ def collect(ctx, idx, scale, reps, log):
         y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
         f = base.features()
         ws = A.nnz * 12 + A.nrows * 20
-        t = S.time_classes(base, x, y, reps=reps, flush=ws < (512 << 20))
+        t = S.time_classes(base, x, y, reps=reps, flush=ws < (512 << 20), classes=classes)
         feats.append(f)
         times.append(t)
         meta.append(dict(m=int(m), n=int(A.nrows), nnz=int(A.nnz)))
-        log(f"[collect] m={m} n={A.nrows} nnz={A.nnz} best={S.CLASSES[int(np.argmin(t))][0]} "
+        log(f"[collect] m={m} n={A.nrows} nnz={A.nnz} best={classes[int(np.argmin(t))]} "
             f"{time.time() - t0:.1f}s")
         del base, rp, col, val, x, y, A
         torch.cuda.empty_cache()
@@ -70,12 +75,12 @@ def collect(ctx, idx, scale, reps, log):
 
 
 def evaluate(ctx, sel, F, T, fallback_times=None):
-    pred = np.array([int(np.argmin(np.where(S.feasible_mask(f), s, np.inf)))
+    pred = np.array([int(np.argmin(np.where(sel.feasible(f), s, np.inf)))
                      for f, s in zip(F, sel.scores(ctx, F))])
     return pred
 
 
-def suite_bandwidth(T, meta, test, choice_test):
+def suite_bandwidth(T, meta, test, choice_test, classes):
     """SpMV bandwidth over the suite in CSR-equivalent GB/s (the bytes a CSR
     product must move: nnz (8+4) + (n+1) 4 + 2 n 8, divided by the measured
     time), so that formats compare on the same work: quartiles per class,
@@ -90,7 +95,7 @@ def suite_bandwidth(T, meta, test, choice_test):
         v = v[np.isfinite(v)]
         return dict(p25=round(float(np.quantile(v, 0.25)), 1), median=round(float(np.median(v)), 1),
                     p75=round(float(np.quantile(v, 0.75)), 1), count=int(v.size)) if v.size else None
-    out = {c[0]: q(G[:, k]) for k, c in enumerate(S.CLASSES)}
+    out = {c: q(G[:, k]) for k, c in enumerate(classes)}
     out["best_class"] = q(np.nanmax(G, axis=1))
     out["selector_test"] = q(G[test, choice_test] if len(test) else np.array([]))
     return out
@@ -117,9 +122,11 @@ def main():
         d = json.load(open(args.timings))
         F, T, meta = np.array(d["features"]), np.array(d["times_ms"]), d["meta"]
         T = np.where(np.array(T) < 0, np.inf, T)
+        classes = list(d["classes"])
     else:
-        F, T, meta = collect(ctx, range(args.count), args.scale, args.reps, log)
-        json.dump(dict(classes=[c[0] for c in S.CLASSES], features=F.tolist(),
+        classes = list(S.CLASSES)
+        F, T, meta = collect(ctx, range(args.count), args.scale, args.reps, log, classes)
+        json.dump(dict(classes=classes, features=F.tolist(),
                        times_ms=np.where(np.isfinite(T), T, -1.0).tolist(), meta=meta,
                        reps=args.reps, scale=args.scale),
                   open(os.path.join(args.out, "selector_timings.json"), "w"))
@@ -128,7 +135,7 @@ def main():
     ntest = max(1, n // 4)
     test, train_idx = np.sort(perm[:ntest]), np.sort(perm[ntest:])
     t0 = time.time()
-    sel = S.train(ctx, F[train_idx], T[train_idx], epochs=args.epochs, lr=args.lr, lam=args.lam)
+    sel = S.train(ctx, F[train_idx], T[train_idx], classes, epochs=args.epochs, lr=args.lr, lam=args.lam)
     train_s = time.time() - t0
     sel.save(os.path.join(args.out, "selector_weights.json"))
     Ft, Tt = F[test], T[test]
@@ -138,7 +145,7 @@ def main():
     choice_fb = []
     nfb = 0
     for f, s, t in zip(Ft, scores, Tt):
-        s = np.where(S.feasible_mask(f), s, np.inf)
+        s = np.where(sel.feasible(f), s, np.inf)
         order = np.argsort(s)
         z = np.abs(sel.standardise(f))
         unsure = (s[order[1]] - s[order[0]] < sel.delta) or np.any(z > sel.zmax)
@@ -152,11 +159,14 @@ def main():
     # best single fixed class on the training set (by geometric-mean slowdown)
     Ttr = T[train_idx]
     slow = Ttr / Ttr.min(axis=1, keepdims=True)
-    gm = [np.exp(np.mean(np.log(np.where(np.isfinite(slow[:, k]), slow[:, k], 1e3)))) for k in range(S.NCLS)]
+    gm = [np.exp(np.mean(np.log(np.where(np.isfinite(slow[:, k]), slow[:, k], 1e3))))
+          for k in range(len(classes))]
     fixed = int(np.argmin(gm))
-    choice_fixed = np.array([fixed if np.isfinite(t[fixed]) else 4 for t in Tt])
-    choice_hand = np.array([hand_rule(f) if np.isfinite(t[hand_rule(f)]) else 4 for f, t in zip(Ft, Tt)])
-    choice_default = np.array([1 if f[2] <= 6 else (2 if f[2] <= 24 else 3) for f in Ft])  # auto vector width
+    merge = classes.index("csr_merge")  # always feasible
+    choice_fixed = np.array([fixed if np.isfinite(t[fixed]) else merge for t in Tt])
+    choice_hand = np.array([classes.index(hand_rule(f)) if np.isfinite(t[classes.index(hand_rule(f))]) else merge
+                            for f, t in zip(Ft, Tt)])
+    choice_default = np.array([classes.index(default_vector(f)) for f in Ft])
 
     def stats(ch):
         r = S.regret(Tt, ch)
@@ -165,15 +175,16 @@ def main():
                     exact=float(np.mean(r <= 1e-12)))
 
     ev = dict(n_train=int(len(train_idx)), n_test=int(len(test)), train_seconds=train_s,
-              epochs=args.epochs, lr=args.lr, weight_decay=args.lam, fixed_class=S.CLASSES[fixed][0], fallback_used=int(nfb),
+              epochs=args.epochs, lr=args.lr, weight_decay=args.lam, fixed_class=classes[fixed], fallback_used=int(nfb),
               regret=dict(selector=stats(choice_net), selector_fallback=stats(choice_fb),
                           best_fixed=stats(choice_fixed), hand_rule=stats(choice_hand),
                           default_vector=stats(choice_default)),
               profile=S.performance_profile(Tt, dict(selector=choice_net, selector_fallback=choice_fb,
                                                      best_fixed=choice_fixed, hand_rule=choice_hand,
                                                      default_vector=choice_default)),
-              class_wins={S.CLASSES[k][0]: int(np.sum(np.argmin(T, axis=1) == k)) for k in range(S.NCLS)})
-    ev["suite_bandwidth"] = suite_bandwidth(T, meta, test, choice_net)
+              classes=classes,
+              class_wins={c: int(np.sum(np.argmin(T, axis=1) == k)) for k, c in enumerate(classes)})
+    ev["suite_bandwidth"] = suite_bandwidth(T, meta, test, choice_net, classes)
     json.dump(ev, open(os.path.join(args.out, "selector_eval.json"), "w"), indent=1)
     log(json.dumps(ev["regret"]))
 

@@ -81,7 +81,8 @@ def test_training_reduces_loss(mxl, ctx):
     from paper_2006_16852_amd import selector as S
     rng = np.random.default_rng(4)
     F = np.abs(rng.standard_normal((120, 16))) * 3
-    T = np.exp(rng.standard_normal((120, S.NCLS)) * 0.3 + F[:, :1] * np.linspace(-0.2, 0.2, S.NCLS))
+    nc = len(S.CLASSES)
+    T = np.exp(rng.standard_normal((120, nc)) * 0.3 + F[:, :1] * np.linspace(-0.2, 0.2, nc))
     T[::7, 6:8] = np.inf
     sel0 = S.train(ctx, F, T, epochs=1)
     sel = S.train(ctx, F, T, epochs=1500)
@@ -103,19 +104,21 @@ def test_trained_selector_gain(mxl, ctx):
     import json
     import os
     from paper_2006_16852_amd import selector as S
-    from paper_2006_16852_amd.train_selector import hand_rule
+    from paper_2006_16852_amd.train_selector import hand_rule, default_vector
     d = json.load(open(os.path.join(os.path.dirname(S.__file__), "data", "selector_timings_zipf200.json")))
     F = np.array(d["features"])
     T = np.array(d["times_ms"], dtype=float)
     T[T < 0] = np.inf
+    classes = list(d["classes"])
     perm = np.random.default_rng(7).permutation(len(F))
     test = np.sort(perm[:len(F) // 4])
     sel = S.Selector.load()
+    assert sel.classes == classes
     Ft, Tt = F[test], T[test]
-    P = np.where([S.feasible_mask(f) for f in Ft], sel.scores(ctx, Ft), np.inf)
+    P = np.where([sel.feasible(f) for f in Ft], sel.scores(ctx, Ft), np.inf)
     net = P.argmin(axis=1)
-    default = np.array([1 if f[2] <= 6 else (2 if f[2] <= 24 else 3) for f in Ft])
-    hand = np.array([hand_rule(f) for f in Ft])
+    default = np.array([classes.index(default_vector(f)) for f in Ft])
+    hand = np.array([classes.index(hand_rule(f)) for f in Ft])
     r_net, r_def, r_hand = S.regret(Tt, net), S.regret(Tt, default), S.regret(Tt, hand)
     print(f"[selector gain] regret net {r_net.mean():.4f} default {r_def.mean():.4f} hand {r_hand.mean():.4f}")
     assert np.all(np.isfinite(r_net))
@@ -129,7 +132,7 @@ def test_trained_selector_gain(mxl, ctx):
     Ttr = T[np.sort(perm[len(F) // 4:])]
     slow = Ttr / Ttr.min(axis=1, keepdims=True)
     fixed = int(np.argmin([np.exp(np.mean(np.log(np.where(np.isfinite(slow[:, k]), slow[:, k], 1e3))))
-                           for k in range(S.NCLS)]))
+                           for k in range(len(classes))]))
     assert S.regret(Tt, np.array(fb)).mean() <= S.regret(Tt, np.full(len(test), fixed)).mean()
 
 
@@ -145,21 +148,25 @@ def _oracle_choice(S, sel, A):
     oracle's own layout routines)."""
     f = O.features(A)
     z = (S.transform(f) - sel.mean) / sel.std
-    _, _, pred = O.mlp_loss_grad(S.DIMS, sel.theta, z[None, :], np.zeros((1, S.NCLS)),
-                                 np.ones((1, S.NCLS)), 0.0, want_grad=False, want_pred=True)
+    nc = len(sel.classes)
+    _, _, pred = O.mlp_loss_grad(sel.dims, sel.theta, z[None, :], np.zeros((1, nc)),
+                                 np.ones((1, nc)), 0.0, want_grad=False, want_pred=True)
     pred = pred[0]
     n_pad = O.pad_rows(A.nrows)
     csr = A.nnz * 12 + (A.nrows + 1) * 4
     budget = min(max(4 * csr, 1 << 20), 32 << 30)
-    feas = np.ones(S.NCLS, bool)
-    for k, (_, fmt, kw) in enumerate(S.CLASSES):
+    rows = np.repeat(np.arange(A.nrows), A.row_lengths())
+    maxoff = int(np.abs(A.col.astype(np.int64) - rows).max()) if A.nnz else 0
+    feas = np.ones(nc, bool)
+    for k, c in enumerate(sel.classes):
+        fmt, kw = S.CATALOG[c]
         if fmt == "ell":
             w = int(A.row_lengths().max()) if A.nrows else 0
         elif fmt == "hyb":
             w = O.hyb_width(A, kw["hyb_quantile"])
         else:
             continue
-        feas[k] = n_pad * w * 12 <= budget
+        feas[k] = n_pad * w * 12 <= budget and (kw.get("variant", 0) != 2 or maxoff <= 32767)
     return np.where(feas, pred, np.inf), np.abs(z).max()
 
 
@@ -222,9 +229,9 @@ def test_select_errors(mxl, ctx):
         h.select(M, 7)
     assert e.value.status == mxl.ERR_INVALID_ARG
     with pytest.raises(mxl.MxlError) as e:
-        mxl.SelectorHandle(ctx, [("csr", {})], S.DIMS, sel.theta, sel.mean, sel.std, S.LOG_FEATS)
+        mxl.SelectorHandle(ctx, [("csr", {})], sel.dims, sel.theta, sel.mean, sel.std, S.LOG_FEATS)
     assert e.value.status == mxl.ERR_DIM_MISMATCH
     with pytest.raises(mxl.MxlError) as e:
-        mxl.SelectorHandle(ctx, [(c[1], c[2]) for c in S.CLASSES], S.DIMS, sel.theta, sel.mean,
+        mxl.SelectorHandle(ctx, [S.CATALOG[c] for c in sel.classes], sel.dims, sel.theta, sel.mean,
                            np.zeros(16), S.LOG_FEATS)
     assert e.value.status == mxl.ERR_INVALID_ARG

@@ -16,9 +16,9 @@ def S():
 
 
 def test_labels_from_times(S):
-    T = np.array([[2.0, 1.0, np.inf, 4.0] + [8.0] * (S.NCLS - 4)])
+    T = np.array([[2.0, 1.0, np.inf, 4.0] + [8.0] * (len(S.CLASSES) - 4)])
     Y, M = S.labels_from_times(T)
-    assert M[0, 2] == 0 and M.sum() == S.NCLS - 1
+    assert M[0, 2] == 0 and M.sum() == len(S.CLASSES) - 1
     assert Y[0, 1] == 0.0 and math.isclose(Y[0, 0], math.log(2.0)) and Y[0, 2] == 0.0
 
 
@@ -35,9 +35,22 @@ def test_ell_feasibility_mirror(S, A):
     assert S.ell_feasible(f) == want
 
 
+@pytest.mark.parametrize("A", [W.stencil_3d27(12), W.aniso_3d7(40), W.zipf_suite_matrix(3, scale_n=0.01),
+                               W.edge_matrices()[3]], ids=lambda a: a.name)
+def test_ell16_feasibility_mirror(S, A):
+    """16-bit offsets: the feature-based mirror agrees with the exact
+    condition max |col - row| <= 32767 plus the storage budget."""
+    f = O.features(A)
+    rows = np.repeat(np.arange(A.nrows), A.row_lengths())
+    maxoff = int(np.abs(A.col.astype(np.int64) - rows).max())
+    assert S.ell16_feasible(f) == (S.ell_feasible(f) and maxoff <= 32767)
+    k = S.CLASSES.index("ell16")
+    assert S.feasible_mask(f)[k] == S.ell16_feasible(f)
+
+
 def test_regret_and_profile(S):
-    T = np.array([[1.0, 2.0, 3.0] + [9.0] * (S.NCLS - 3),
-                  [4.0, 2.0, 1.0] + [9.0] * (S.NCLS - 3)])
+    T = np.array([[1.0, 2.0, 3.0] + [9.0] * (len(S.CLASSES) - 3),
+                  [4.0, 2.0, 1.0] + [9.0] * (len(S.CLASSES) - 3)])
     r = S.regret(T, np.array([0, 1]))
     assert np.allclose(r, [0.0, 1.0])
     prof = S.performance_profile(T, {"p": np.array([0, 1])}, taus=(1.0, 2.0))
@@ -48,5 +61,5 @@ def test_transform_and_init(S):
     F = np.arange(32, dtype=float).reshape(2, 16)
     G = S.transform(F)
     assert np.allclose(G[:, S.LOG_FEATS], np.log1p(F[:, S.LOG_FEATS]))
-    th = S.he_init(S.DIMS, 0)
-    assert th.size == O.mlp_param_count(S.DIMS)
+    th = S.he_init(S.dims_for(len(S.CLASSES)), 0)
+    assert th.size == O.mlp_param_count(S.dims_for(len(S.CLASSES)))
