@@ -120,22 +120,32 @@ def main():
     rp = torch.from_numpy(A.row_ptr).to(dev)
     col = torch.from_numpy(A.col).to(dev)
     val = torch.from_numpy(A.val).to(dev)
-    base = mxl.csr(ctx, rp, col, val)
+    def setup_ms(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, round((time.perf_counter() - t) * 1e3, 3)
+
+    base, t_validate = setup_ms(lambda: mxl.csr(ctx, rp, col, val, validate=True))
     xd = torch.from_numpy(xs).to(dev)
     bd = torch.empty(n, dtype=torch.float64, device=dev)
     base.apply(xd, bd)                      # b = A x* on the GPU
     yd = torch.empty(n, dtype=torch.float64, device=dev)
 
     log("[bench] building formats")
-    ops = {
-        "csr_vec32": base.convert("csr", variant=mxl.CSR_VECTOR, vector_width=32),
-        "csr_merge": base.convert("csr", variant=mxl.CSR_MERGE),
-        "csr_stream": base.convert("csr", variant=mxl.CSR_STREAM),
-        "coo": base.convert("coo"),
-        "ell": base.convert("ell"),
-        "ell16": base.convert("ell", variant=mxl.ELL_DELTA16),
-        "hyb": base.convert("hyb", hyb_quantile=0.9),
+    builds = {
+        "csr_vec32": lambda: base.convert("csr", variant=mxl.CSR_VECTOR, vector_width=32),
+        "csr_merge": lambda: base.convert("csr", variant=mxl.CSR_MERGE),
+        "csr_stream": lambda: base.convert("csr", variant=mxl.CSR_STREAM),
+        "coo": lambda: base.convert("coo"),
+        "ell": lambda: base.convert("ell"),
+        "ell16": lambda: base.convert("ell", variant=mxl.ELL_DELTA16),
+        "hyb": lambda: base.convert("hyb", hyb_quantile=0.9),
     }
+    ops, t_setup = {}, {"validate_csr": t_validate}
+    for k, fn in builds.items():
+        ops[k], t_setup[k] = setup_ms(fn)
     fmt_of = {"csr_vec32": "csr", "csr_merge": "csr", "csr_stream": "csr", "coo": "coo", "ell": "ell",
               "ell16": "ell16", "hyb": "hyb"}
     descs = {k: v.describe() for k, v in ops.items()}
@@ -155,7 +165,7 @@ def main():
                for op, nb in (("triad", 24 << 26), ("dot", 16 << 26))}
     del sa, sb, sc
     M = ops[sel]
-    P = mxl.jacobi(M)
+    P, t_setup["jacobi"] = setup_ms(lambda: mxl.jacobi(M))
     S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-10, check_every=16)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
 
@@ -241,6 +251,7 @@ def main():
                "us_per_iteration": round(cg_ms * 1e3 / its[0], 2)},
         "spmv": spmv_detail,
         "selection_ms": {k: round(v, 4) for k, v in t_sel.items()},
+        "setup_ms": t_setup,
     }
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline (bounded sample)")

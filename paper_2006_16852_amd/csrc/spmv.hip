@@ -803,10 +803,11 @@ constexpr int kDotSlotCap = 4096;  // partial slots a fused-dot launch may publi
 // Grids of the wave-walker kernels (4 walking waves per workgroup): a
 // multiple of 8 workgroups keeps each walker on its XCD's band.
 static int walker_grid(int64_t units, int cap) {
+    if (units <= 0) return 0;  // nothing to launch (and no partial slots)
     int64_t g = (units + kWG / kWave - 1) / (kWG / kWave);
     g = g < cap ? g : cap;
     if (g >= kNumXcd) g -= g % kNumXcd;
-    return (int)(g > 0 ? g : 1);
+    return (int)g;
 }
 
 void spmv_plan(MatrixImpl &A) {

@@ -202,7 +202,7 @@ def test_select_exhaustive_and_fallback(mxl, ctx, A):
     M = matrix(mxl, ctx, A)
     x = torch.from_numpy(W.uniform_vec(A.ncols, 3)).to(DEV)
     y = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
-    k, t = S.exhaustive(ctx, M, x, y, reps=3)
+    k, t = S.exhaustive(ctx, M, x, y, reps=3, classes=base.classes)
     assert np.array_equal(np.isfinite(t), np.isfinite(want))
     assert k == int(np.argmin(t))
     unsure = S.Selector(base.theta, base.mean, base.std, delta=1e9, zmax=base.zmax)
