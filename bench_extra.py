@@ -9,6 +9,7 @@ batch     : 10,000 banded SPD systems, batched Jacobi-PCG in one persistent
 overhead  : the size-1, b = NaN protocol of the paper's Table 1 (per-iteration cost).
 stream    : copy / triad / dot bandwidth, the achievable-peak calibration.
 bicgstab  : 128^3 27-point system, Jacobi-BiCGSTAB to 1e-10.
+stencil_mf: the same operator matrix-free: SpMV and Jacobi-PCG to 1e-10.
 
 Each line carries a cpu_baseline: the oracle on a bounded sample of the same
 work (one host core), unless --no-cpu-baseline.
@@ -336,6 +337,56 @@ def bicgstab(args):
     print(json.dumps(out), flush=True)
 
 
+def stencil_mf(args):
+    """Matrix-free 27-point operator on the 128^3 grid (the user-defined
+    operator of the paper's Sec. 4): SpMV time and Jacobi-PCG to 1e-10,
+    next to the stored-matrix path (ELL with 16-bit offsets).  A
+    matrix-free product moves x and y only: 2 n 8 bytes."""
+    import numpy as np
+    import torch
+    import paper_2006_16852_amd as mxl
+    import workloads as W
+    dev = "cuda:0"
+    N = 128
+    A = W.stencil_3d27(N)
+    n = A.nrows
+    ctx = mxl.Context(0)
+    pts, cf = W.points_3d27()
+    op = mxl.stencil(ctx, (N, N, N), pts, cf)
+    base = mxl.csr(ctx, torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                   torch.from_numpy(A.val).to(dev))
+    ell = base.convert("ell", variant=mxl.ELL_DELTA16)
+    xs = torch.from_numpy(W.uniform_vec(n, 2)).to(dev)
+    b = torch.empty_like(xs)
+    op.apply(xs, b)
+    y = torch.empty_like(b)
+    t_mf = op.time_apply(xs, y, reps=50)
+    t_ell = ell.time_apply(xs, y, reps=20)
+    res = {}
+    for name, M in (("matrix_free", op), ("ell16", ell)):
+        S = mxl.solver("cg", M, mxl.jacobi(M), max_iters=5000, reduction=1e-10, check_every=16)
+        x = torch.zeros_like(b)
+
+        def f():
+            x.zero_()
+            return S.solve(b, x, time_spmv=True)
+        dt, info = _timed(f, args.steps, args.warmup)
+        r = b.clone()
+        op.apply(x, r, -1.0, 1.0)
+        res[name] = dict(ms=round(dt * 1e3, 3), iterations=info["iterations"],
+                         us_per_iteration=round(dt * 1e6 / info["iterations"], 2),
+                         spmv_us_in_loop=round(info["spmv_ms"] * 1e3 / max(info["spmv_timed"], 1), 2),
+                         true_rel=float(torch.linalg.norm(r) / torch.linalg.norm(b)))
+    mf_bytes = 2 * n * 8
+    out = {"metric": "CG time-to-1e-10 residual, matrix-free stencil", "unit": "ms",
+           "value": res["matrix_free"]["ms"], "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "stencil27_128^3 matrix-free jacobi-pcg to 1e-10", "n": n},
+           "spmv": {"matrix_free_us": round(t_mf * 1e3, 2), "matrix_free_GBs": round(mf_bytes / t_mf / 1e6, 1),
+                    "ell16_us": round(t_ell * 1e3, 2)},
+           "runs": res, "steps": args.steps, "warmup": args.warmup}
+    print(json.dumps(out), flush=True)
+
+
 def run(args):
     {"aniso_ir": aniso_ir, "poisson2d": poisson2d, "batch": batch, "overhead": overhead,
-     "stream": stream, "bicgstab": bicgstab}[args.workload](args)
+     "stream": stream, "bicgstab": bicgstab, "stencil_mf": stencil_mf}[args.workload](args)

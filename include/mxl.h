@@ -49,7 +49,10 @@ typedef enum {
 
 typedef enum { MXL_F64 = 0, MXL_F32 = 1 } mxl_dtype;
 
-typedef enum { MXL_FMT_CSR = 0, MXL_FMT_COO = 1, MXL_FMT_ELL = 2, MXL_FMT_HYB = 3 } mxl_format;
+typedef enum {
+    MXL_FMT_CSR = 0, MXL_FMT_COO = 1, MXL_FMT_ELL = 2, MXL_FMT_HYB = 3,
+    MXL_FMT_STENCIL = 4  /* matrix-free stencil (mxl_stencil_create); no arrays */
+} mxl_format;
 
 /* Kernel variants (the "kernel variant selection" fork of Sec. 7.2). */
 enum {
@@ -154,6 +157,23 @@ mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows,
                           int64_t ncols, int64_t nnz, const int32_t *row_ptr,
                           const int32_t *col, const void *val, int flags,
                           mxl_op **A);
+
+/* Matrix-free constant-coefficient stencil operator on an nx x ny x nz grid:
+ * a user-defined linear operator in the sense of Sec. 4, which stores no
+ * matrix.  Unknown r = i + nx (j + ny k); row r of A x is
+ *     sum_p coef[p] * x[(i + di_p) + nx ((j + dj_p) + ny (k + dk_p))]
+ * over the points p whose neighbour lies inside the grid (Dirichlet
+ * boundary: the others are omitted), summed in the order given.
+ * offsets: HOST int32 [npts][3] = (di, dj, dk), each in {-1, 0, 1}, all
+ * distinct; coef: HOST double [npts]; 1 <= npts <= 27; dtype F64 or F32
+ * (coefficients rounded to it).  The operator supports mxl_apply*,
+ * mxl_cast, mxl_jacobi_generate (the point (0,0,0) is the diagonal;
+ * ZERO_DIAG if it is absent or zero), the solvers and mxl_time_apply;
+ * mxl_convert, mxl_features and mxl_select return NOT_IMPLEMENTED.
+ * Errors: INVALID_ARG, DTYPE. */
+mxl_status mxl_stencil_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nx, int64_t ny,
+                              int64_t nz, int32_t npts, const int32_t *offsets,
+                              const double *coef, mxl_op **A);
 
 /* New operator with the same values in another format or kernel variant
  * (COO: explicit row of each entry, CSR order; ELL: slot-major [w][n_pad]

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmxl.so")
 
 # ----------------------------------------------------------------- constants
 F64, F32 = 0, 1
-CSR, COO, ELL, HYB = 0, 1, 2, 3
+CSR, COO, ELL, HYB, STENCIL = 0, 1, 2, 3, 4
 CSR_SCALAR, CSR_VECTOR, CSR_MERGE, CSR_STREAM = 0, 1, 2, 3
 COO_SEGRED = 0
 ELL_PLAIN, ELL_LDS, ELL_DELTA16 = 0, 1, 2
@@ -129,6 +129,7 @@ def _load():
         "mxl_mlp_adam_step": [vp, i64, C.c_float, C.c_float, C.c_float, C.c_float],
         "mxl_mlp_destroy": [vp],
         "mxl_selector_create": [vp, i32, vp, i32, vp, vp, vp, vp, C.c_uint32, f64, f64, pp],
+        "mxl_stencil_create": [vp, C.c_int, i64, i64, i64, i32, vp, vp, pp],
         "mxl_selector_destroy": [vp],
         "mxl_select": [vp, vp, i32, vp, vp, i32, C.POINTER(C.c_int32), vp, vp,
                        C.POINTER(SelectInfo)],
@@ -304,6 +305,24 @@ def csr(ctx: Context, row_ptr, col, val, ncols=None, copy=False, validate=False)
     _check(lib.mxl_csr_create(ctx.h, _dtype_code(val), n, ncols, col.numel(), _ptr(row_ptr),
                               _ptr(col), _ptr(val), flags, C.byref(h)))
     return Op(h, ctx, keep=() if copy else (row_ptr, col, val))
+
+
+def stencil(ctx: Context, shape, points, coefs, dtype=torch.float64) -> Op:
+    """Matrix-free constant-coefficient stencil on an (nx, ny, nz) grid:
+    points = [(di, dj, dk), ...] with entries in {-1, 0, 1}, coefs the
+    matching coefficients (Dirichlet boundary)."""
+    import numpy as np
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    off = np.ascontiguousarray(np.asarray(points, np.int32).reshape(-1, 3))
+    cf = np.ascontiguousarray(np.asarray(coefs, np.float64))
+    if off.shape[0] != cf.size:
+        raise MxlError(ERR_DIM_MISMATCH, "one coefficient per point")
+    code = F64 if dtype == torch.float64 else F32
+    h = C.c_void_p()
+    ctx.use_current_stream()
+    _check(lib.mxl_stencil_create(ctx.h, code, nx, ny, nz, cf.size, off.ctypes.data_as(C.c_void_p),
+                                  cf.ctypes.data_as(C.c_void_p), C.byref(h)))
+    return Op(h, ctx)
 
 
 def stream_bench(ctx: Context, op: str, a, b=None, c=None, reps: int = 10) -> float:

@@ -27,7 +27,7 @@
 namespace mxl {
 
 struct BatchImpl {
-    mxl_ctx *ctx = nullptr;
+    CtxRef ctx;
     int64_t nsys = 0, rows = 0, nnz = 0;
     std::vector<int32_t> sys_ptr_h;
     int max_n = 0;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <memory>
 #include <string>
 #include <vector>
@@ -38,12 +39,43 @@ struct mxl_ctx {
     void *pinned = nullptr;     // host-pinned staging for solver state read-back
     size_t pinned_bytes = 0;
     mxl::BufPtr flush_buf;      // lazily allocated 1 GiB buffer for cache flushes
+    // The caller's handle plus one count per library object that uses the
+    // context: mxl_ctx_destroy drops the caller's count, and the context is
+    // freed with the last object, whatever order handles are destroyed in.
+    std::atomic<int> refs{1};
 };
 
 namespace mxl {
 
+void ctx_release(mxl_ctx *c);  // frees the context when the count reaches zero
+
+// A counted reference to a context (held by every object that uses one).
+struct CtxRef {
+    mxl_ctx *p = nullptr;
+    CtxRef() = default;
+    explicit CtxRef(mxl_ctx *c) : p(c) { retain(); }
+    CtxRef(const CtxRef &o) : p(o.p) { retain(); }
+    CtxRef &operator=(const CtxRef &o) { return *this = o.p; }
+    CtxRef &operator=(mxl_ctx *c) {
+        if (c) c->refs.fetch_add(1);
+        if (p) ctx_release(p);
+        p = c;
+        return *this;
+    }
+    ~CtxRef() {
+        if (p) ctx_release(p);
+    }
+    mxl_ctx *operator->() const { return p; }
+    operator mxl_ctx *() const { return p; }
+
+private:
+    void retain() {
+        if (p) p->refs.fetch_add(1);
+    }
+};
+
 struct MatrixImpl {
-    mxl_ctx *ctx = nullptr;
+    CtxRef ctx;
     int dtype = MXL_F64;
     int64_t nrows = 0, ncols = 0, nnz = 0;
     int format = MXL_FMT_CSR;
@@ -61,6 +93,11 @@ struct MatrixImpl {
     BufPtr part;                       // merge-path tile boundaries / row-block descriptors (int2)
     int64_t ntiles = 0;                // merge / COO / HYB-tail tiles, row blocks
     BufPtr carries;                    // per-tile carries
+    // matrix-free stencil: grid and points (host copies, passed by value)
+    int64_t nx = 0, ny = 0, nz = 0;
+    int st_npts = 0;
+    int8_t st_off[27][3] = {};
+    double st_coef[27] = {};
     int grid_main = 0, grid_tail = 0;  // workgroups of the chain's kernels
     int grid_dot = 0;                  // ELL: workgroups of fused-dot launches
     int64_t stored_bytes = 0;

@@ -137,6 +137,7 @@ namespace {
 void compute_stored_bytes(MatrixImpl &A) {
     const int64_t vt = (int64_t)vt_size(A.dtype);
     switch (A.format) {
+    case MXL_FMT_STENCIL: A.stored_bytes = 0; break;
     case MXL_FMT_CSR: A.stored_bytes = csr_bytes(A); break;
     case MXL_FMT_COO: A.stored_bytes = A.nnz * (vt + 8); break;
     case MXL_FMT_ELL:
@@ -183,6 +184,14 @@ double elapsed_s(std::chrono::steady_clock::time_point t0) {
 }  // namespace
 
 namespace mxl {
+void ctx_release(mxl_ctx *c) {
+    if (c->refs.fetch_sub(1) != 1) return;
+    DeviceScope ds(c->device);
+    c->flush_buf.reset();
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}
+
 mxl_status set_error(mxl_status st, const std::string &msg) { return fail(st, msg); }
 mxl_status check_device_ptr(const mxl_ctx *ctx, const void *p, size_t bytes, const char *what) {
     return check_dev(ctx, p, bytes, what);
@@ -231,11 +240,11 @@ mxl_status mxl_ctx_set_stream(mxl_ctx *ctx, void *hip_stream) {
 
 mxl_status mxl_ctx_destroy(mxl_ctx *ctx) {
     if (!ctx) return MXL_OK;
-    DeviceScope ds(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    ctx->flush_buf.reset();
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    delete ctx;
+    {
+        DeviceScope ds(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+    }
+    ctx_release(ctx);  // objects still using the context keep it alive
     return MXL_OK;
 }
 
@@ -300,11 +309,54 @@ mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows, int64_t 
     return MXL_OK;
 }
 
+mxl_status mxl_stencil_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nx, int64_t ny, int64_t nz,
+                              int32_t npts, const int32_t *offsets, const double *coef, mxl_op **Aout) {
+    if (!ctx || !offsets || !coef || !Aout) return fail(MXL_ERR_INVALID_ARG, "NULL argument");
+    *Aout = nullptr;
+    if (dtype != MXL_F64 && dtype != MXL_F32) return fail(MXL_ERR_DTYPE, "dtype must be F64 or F32");
+    if (nx < 1 || ny < 1 || nz < 1 || npts < 1 || npts > 27)
+        return fail(MXL_ERR_INVALID_ARG, "grid sizes >= 1 and 1 <= npts <= 27 required");
+    if ((double)nx * (double)ny * (double)nz >= 2147483647.0)
+        return fail(MXL_ERR_INVALID_ARG, "the grid must have fewer than 2^31 points");
+    auto A = std::make_shared<MatrixImpl>();
+    A->ctx = ctx;
+    A->dtype = dtype;
+    A->nx = nx;
+    A->ny = ny;
+    A->nz = nz;
+    A->nrows = A->ncols = nx * ny * nz;
+    A->st_npts = npts;
+    int64_t nnz = 0;
+    for (int q = 0; q < npts; ++q) {
+        for (int d = 0; d < 3; ++d) {
+            const int32_t v = offsets[3 * q + d];
+            if (v < -1 || v > 1) return fail(MXL_ERR_INVALID_ARG, "stencil offsets must be -1, 0 or 1");
+            A->st_off[q][d] = (int8_t)v;
+        }
+        for (int r = 0; r < q; ++r)
+            if (A->st_off[r][0] == A->st_off[q][0] && A->st_off[r][1] == A->st_off[q][1] &&
+                A->st_off[r][2] == A->st_off[q][2])
+                return fail(MXL_ERR_INVALID_ARG, "stencil points must be distinct");
+        if (!std::isfinite(coef[q])) return fail(MXL_ERR_INVALID_ARG, "stencil coefficients must be finite");
+        A->st_coef[q] = coef[q];
+        nnz += (nx - std::abs((int)A->st_off[q][0])) * (ny - std::abs((int)A->st_off[q][1])) *
+               (nz - std::abs((int)A->st_off[q][2]));
+    }
+    A->nnz = nnz;  // entries of the equivalent matrix
+    A->format = MXL_FMT_STENCIL;
+    A->variant = 0;
+    compute_stored_bytes(*A);
+    finish_matrix(*A);
+    *Aout = wrap_matrix(A);
+    return MXL_OK;
+}
+
 mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_params *params,
                        mxl_op **out) {
     if (!Aop || !out || Aop->kind != MXL_OP_MATRIX) return fail(MXL_ERR_INVALID_ARG, "not a matrix operator");
     *out = nullptr;
     const MatrixImpl &S = *Aop->mat;
+    if (S.format == MXL_FMT_STENCIL) return fail(MXL_ERR_NOT_IMPLEMENTED, "a matrix-free stencil has no arrays to convert");
     mxl_ctx *ctx = S.ctx;
     DeviceScope ds(ctx->device);
     mxl_format_params prm{};
@@ -443,7 +495,9 @@ mxl_status mxl_cast(const mxl_op *Aop, mxl_dtype dtype, mxl_op **out) {
     DeviceScope ds(S.ctx->device);
     auto A = std::make_shared<MatrixImpl>(S);  // shares every array
     A->dtype = dtype;
-    if (dtype != S.dtype) {
+    if (S.format == MXL_FMT_STENCIL) {
+        // coefficients are kept in FP64 and rounded to the dtype by the kernel
+    } else if (dtype != S.dtype) {
         hipError_t e;
         const size_t vt = vt_size(dtype);
         auto conv = [&](const BufPtr &src, int64_t count) -> BufPtr {
@@ -600,6 +654,20 @@ mxl_status mxl_jacobi_generate(const mxl_op *Aop, mxl_op **P) {
     auto J = std::make_shared<JacobiImpl>();
     J->A = A;
     J->dinv = alloc((size_t)A->nrows * vt_size(A->dtype), &e);
+    if (!J->dinv) return hip_fail(hipErrorOutOfMemory, "alloc jacobi");
+    if (A->format == MXL_FMT_STENCIL) {  // constant diagonal: the point (0,0,0)
+        double diag = 0.0;
+        for (int q = 0; q < A->st_npts; ++q)
+            if (A->st_off[q][0] == 0 && A->st_off[q][1] == 0 && A->st_off[q][2] == 0) diag = A->st_coef[q];
+        if (A->dtype == MXL_F32) diag = (double)(float)diag;
+        if (diag == 0.0) return fail(MXL_ERR_ZERO_DIAG, "the stencil has no nonzero centre point");
+        HIP_TRY(launch_fill(A->dtype, A->nrows, 1.0 / diag, J->dinv->p, A->ctx->stream));
+        auto *op = new mxl_op;
+        op->kind = MXL_OP_JACOBI;
+        op->jac = J;
+        *P = op;
+        return MXL_OK;
+    }
     auto bad = alloc(sizeof(int), &e);
     if (!J->dinv || !bad) return hip_fail(hipErrorOutOfMemory, "alloc jacobi");
     int init = INT_MAX;
@@ -776,6 +844,7 @@ constexpr int64_t kSingleMaxN = 16384;
 bool single_launch_ok(const SolverImpl &S, const mxl_solve_info *info) {
     const mxl_criteria &c = S.crit;
     if (S.kind != MXL_SOLVER_CG || S.A->dtype != MXL_F64 || c.launch_mode == 1) return false;
+    if (S.A->format == MXL_FMT_STENCIL) return false;  // the one-launch path reads CSR arrays
     if (c.max_iters < 1 || c.time_limit_s > 0 || S.A->nrows > kSingleMaxN) return false;
     if (info && ((info->history && info->history_cap > 0) || info->time_spmv)) return false;
     return c.launch_mode == 2 || S.A->nrows <= kSingleAutoN;

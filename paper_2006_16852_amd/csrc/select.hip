@@ -303,7 +303,7 @@ mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<uns
 }  // namespace mxl
 
 struct mxl_mlp {
-    mxl_ctx *ctx = nullptr;
+    CtxRef ctx;
     MlpShape sh{};
     void *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     void *gs = nullptr;  // per-sample gradients
@@ -314,6 +314,8 @@ struct mxl_mlp {
 extern "C" mxl_status mxl_features(const mxl_op *Aop, double out_host[16]) {
     if (!Aop || Aop->kind != MXL_OP_MATRIX || !out_host)
         return set_error(MXL_ERR_INVALID_ARG, "matrix operator and output required");
+    if (Aop->mat->format == MXL_FMT_STENCIL)
+        return set_error(MXL_ERR_NOT_IMPLEMENTED, "a matrix-free stencil has no rows to describe");
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(Aop->mat->ctx->device);
@@ -481,7 +483,7 @@ extern "C" mxl_status mxl_mlp_destroy(mxl_mlp *mm) {
 
 // ================================================================ selector
 struct mxl_selector {
-    mxl_ctx *ctx = nullptr;
+    CtxRef ctx;
     std::vector<mxl_kernel_class> classes;
     mxl_mlp *net = nullptr;
     double mean[16], sd[16];
@@ -573,6 +575,8 @@ extern "C" mxl_status mxl_select(const mxl_selector *S, const mxl_op *Aop, int32
         return set_error(MXL_ERR_INVALID_ARG, "exhaustive selection needs x and y to time with");
     if (Aop->mat->ctx->device != S->ctx->device)
         return set_error(MXL_ERR_INVALID_ARG, "matrix and selector live on different devices");
+    if (Aop->mat->format == MXL_FMT_STENCIL)
+        return set_error(MXL_ERR_NOT_IMPLEMENTED, "a matrix-free stencil has no formats to choose from");
     if ((x || y) && reps < 1) return set_error(MXL_ERR_INVALID_ARG, "reps must be >= 1");
     const MatrixImpl &A = *Aop->mat;
     DeviceScope dsc(S->ctx->device);

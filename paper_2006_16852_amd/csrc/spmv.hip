@@ -648,6 +648,65 @@ __global__ void k_scale_only(int64_t n, SpmvK<V> p) {
         p.y[i] = combine(p, (V)0, i);
 }
 
+// ------------------------------------------------------- matrix-free stencil
+// Constant-coefficient stencil on an nx x ny x nz grid (x fastest): no
+// matrix is stored, so a product moves only x (once, through the caches)
+// and y.  Each thread computes one point; its NP neighbour loads are issued
+// together (out-of-grid neighbours read the point itself and are then
+// discarded by a select, so padding never multiplies x).
+struct StencilK {
+    int64_t nx, ny, nz;
+    double inv_nx, inv_nxy;  // reciprocals for the index split
+    int npts;
+    int64_t off[27];         // linear offset of each point
+    int8_t d[27][3];
+    double c[27];
+};
+
+// q = floor(a / b) for 0 <= a < 2^31 from a rounded reciprocal, corrected
+// by one step either way.
+__device__ __forceinline__ int64_t div_fix(int64_t a, int64_t b, double inv) {
+    int64_t q = (int64_t)((double)a * inv);
+    if (q * b > a) --q;
+    else if ((q + 1) * b <= a) ++q;
+    return q;
+}
+
+template <typename V, bool DOT, int NP>
+__global__ __launch_bounds__(kWG) void k_stencil(StencilK sk, SpmvK<V> p) {
+    if (p.stop && *p.stop) return;
+    const int64_t nxy = sk.nx * sk.ny, n = nxy * sk.nz;
+    const int64_t ntiles = (n + kWG - 1) / kWG;
+    int64_t t0, t1;
+    int ts;
+    band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
+    double dacc = 0.0;
+    for (int64_t tile = t0; tile < t1; tile += ts) {
+        const int64_t r = tile * kWG + threadIdx.x;
+        if (r >= n) continue;
+        const int64_t k = div_fix(r, nxy, sk.inv_nxy), rem = r - k * nxy;
+        const int64_t j = div_fix(rem, sk.nx, sk.inv_nx), i = rem - j * sk.nx;
+        V xv[NP];
+        bool ok[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int64_t ii = i + sk.d[q][0], jj = j + sk.d[q][1], kk = k + sk.d[q][2];
+            ok[q] = q < sk.npts && ii >= 0 && ii < sk.nx && jj >= 0 && jj < sk.ny && kk >= 0 && kk < sk.nz;
+            xv[q] = p.x[ok[q] ? r + sk.off[q] : r];
+        }
+        V acc = 0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) acc += ok[q] ? (V)sk.c[q] * xv[q] : (V)0;
+        const V out = combine(p, acc, r);
+        p.y[r] = out;
+        if (DOT) dacc += (double)p.w[r] * (double)out;
+    }
+    if (DOT) {
+        double vv[1] = {dacc};
+        publish<1>(vv, p.partials, p.slot_base + (int)blockIdx.x);
+    }
+}
+
 // ----------------------------------------------------------- setup kernels
 __global__ void k_csr_to_coo(int64_t n, const int *__restrict__ rp, int *__restrict__ row) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -825,6 +884,9 @@ void spmv_plan(MatrixImpl &A) {
     case MXL_FMT_COO:
         A.grid_main = walker_grid(A.ntiles, cap);
         break;
+    case MXL_FMT_STENCIL:
+        A.grid_main = grid_for((A.nrows + kWG - 1) / kWG, cap);
+        break;
     case MXL_FMT_ELL: {
         const int64_t tiles = (A.nrows + kWG * A.ell_rpt - 1) / (kWG * A.ell_rpt);
         A.grid_main = grid_for(tiles, cap);
@@ -888,9 +950,10 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
     const bool dot = a.w != nullptr;
     const int64_t n = A.nrows;
     if (n == 0) return hipSuccess;
-    const int *rp = (const int *)A.row_ptr->p;
-    const int *col = (const int *)A.col->p;
-    const V *val = (const V *)A.val->p;
+    // a matrix-free stencil has no arrays
+    const int *rp = A.row_ptr ? (const int *)A.row_ptr->p : nullptr;
+    const int *col = A.col ? (const int *)A.col->p : nullptr;
+    const V *val = A.val ? (const V *)A.val->p : nullptr;
     const dim3 blk(kWG);
     auto fixup = [&](const Carry *cr, int64_t ntiles) {
         const unsigned g = (unsigned)((ntiles + kWG - 1) / kWG);
@@ -922,6 +985,29 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
             if (dot) hipLaunchKernelGGL((k_csr_merge<V, true>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, part, A.ntiles, cr, p);
             else hipLaunchKernelGGL((k_csr_merge<V, false>), dim3(A.grid_main), blk, 0, s, n, rp, col, val, part, A.ntiles, cr, p);
             fixup(cr, A.ntiles);
+        }
+        break;
+    }
+    case MXL_FMT_STENCIL: {
+        StencilK sk{};
+        sk.nx = A.nx;
+        sk.ny = A.ny;
+        sk.nz = A.nz;
+        sk.inv_nx = 1.0 / (double)A.nx;
+        sk.inv_nxy = 1.0 / ((double)A.nx * (double)A.ny);
+        sk.npts = A.st_npts;
+        for (int q = 0; q < 27; ++q) {
+            for (int d = 0; d < 3; ++d) sk.d[q][d] = q < A.st_npts ? A.st_off[q][d] : 0;
+            sk.off[q] = sk.d[q][0] + A.nx * (sk.d[q][1] + A.ny * sk.d[q][2]);
+            sk.c[q] = q < A.st_npts ? A.st_coef[q] : 0.0;
+        }
+        const dim3 g(A.grid_main);
+        if (A.st_npts <= 7) {
+            if (dot) hipLaunchKernelGGL((k_stencil<V, true, 7>), g, blk, 0, s, sk, p);
+            else hipLaunchKernelGGL((k_stencil<V, false, 7>), g, blk, 0, s, sk, p);
+        } else {
+            if (dot) hipLaunchKernelGGL((k_stencil<V, true, 27>), g, blk, 0, s, sk, p);
+            else hipLaunchKernelGGL((k_stencil<V, false, 27>), g, blk, 0, s, sk, p);
         }
         break;
     }

@@ -108,3 +108,29 @@ def test_infeasible_ell(mxl, ctx):
     H = M.convert("hyb", hyb_quantile=0.9)        # the tail absorbs the long row
     d = H.describe()
     assert d["ell_width"] == 1 and d["tail_nnz"] == 9_999
+
+
+def test_handles_freed_in_any_order(mxl):
+    """Handles that die together in a reference cycle are finalized in an
+    arbitrary order (the context may go first); the library keeps a
+    context alive while any object still uses it, so nothing is used after
+    it is freed, and the library keeps working afterwards."""
+    import gc
+
+    class Holder:
+        pass
+
+    ctx = mxl.Context(0)
+    A = matrix(mxl, ctx, W.stencil_2d5(8))
+    h = Holder()
+    h.me, h.ctx, h.A, h.P = h, ctx, A, mxl.jacobi(A)
+    h.S = mxl.solver("cg", A, h.P, max_iters=50)
+    x = torch.zeros(64, dtype=torch.float64, device=DEV)
+    h.S.solve(torch.ones(64, dtype=torch.float64, device=DEV), x)
+    del ctx, A, h
+    gc.collect()
+    ctx2 = mxl.Context(0)
+    B = matrix(mxl, ctx2, W.stencil_2d5(8))
+    y = torch.empty(64, dtype=torch.float64, device=DEV)
+    B.apply(torch.ones(64, dtype=torch.float64, device=DEV), y)
+    assert float(y.sum()) == float(W.stencil_2d5(8).val.sum())

@@ -165,6 +165,44 @@ def convdiff_2d5(N: int, peclet: float = 0.5) -> Csr:
     return _from_offset_stencil(n, offs, masks, vals, f"convdiff2d5_{N}")
 
 
+def stencil_grid(nx: int, ny: int, nz: int, points, coefs, name: str = None) -> Csr:
+    """CSR of a constant-coefficient stencil on an nx x ny x nz grid (i
+    fastest), neighbours outside the grid omitted; points must be given in
+    (dk, dj, di) lexicographic order so the columns come out sorted."""
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64)
+    i, j, k = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    offs, masks = [], []
+    for di, dj, dk in points:
+        offs.append(di + nx * (dj + ny * dk))
+        masks.append((i + di >= 0) & (i + di < nx) & (j + dj >= 0) & (j + dj < ny) & (k + dk >= 0) & (k + dk < nz))
+    # points in (dk, dj, di) lexicographic order give every row's in-grid
+    # neighbours in ascending column order (an in-grid |di| step is < nx)
+    return _from_offset_stencil(n, offs, masks, list(coefs), name or f"grid{nx}x{ny}x{nz}_{len(points)}pt")
+
+
+# Point lists of the same operators for a matrix-free stencil: (di, dj, dk)
+# offsets and coefficients, in the column order the CSR generators use.
+def points_2d5():
+    return [(0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0)], [-1.0, -1.0, 4.0, -1.0, -1.0]
+
+
+def points_3d27(diag: float = 26.0, off: float = -1.0):
+    pts = [(di, dj, dk) for dk in (-1, 0, 1) for dj in (-1, 0, 1) for di in (-1, 0, 1)]
+    return pts, [diag if p == (0, 0, 0) else off for p in pts]
+
+
+def points_aniso7(coef=(1.0, 1e-2, 1e-4), shift: float = 1e-3):
+    ax, ay, az = coef
+    pts = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    return pts, [-az, -ay, -ax, 2.0 * (ax + ay + az) + shift, -ax, -ay, -az]
+
+
+def points_convdiff(peclet: float = 0.5):
+    return ([(0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0)],
+            [-1.0, -1.0 - peclet, 4.0 + peclet, -1.0, -1.0])
+
+
 def uniform_vec(n: int, seed: int, dtype=np.float64) -> np.ndarray:
     """x ~ U[-1, 1) from PCG64(seed)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n).astype(dtype)
