@@ -163,7 +163,8 @@ mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows,
  * matrix.  Unknown r = i + nx (j + ny k); row r of A x is
  *     sum_p coef[p] * x[(i + di_p) + nx ((j + dj_p) + ny (k + dk_p))]
  * over the points p whose neighbour lies inside the grid (Dirichlet
- * boundary: the others are omitted), summed in the order given.
+ * boundary: the others are omitted), summed in (dk, dj, di) lexicographic
+ * order (the column order of the equivalent CSR matrix).
  * offsets: HOST int32 [npts][3] = (di, dj, dk), each in {-1, 0, 1}, all
  * distinct; coef: HOST double [npts]; 1 <= npts <= 27; dtype F64 or F32
  * (coefficients rounded to it).  The operator supports mxl_apply*,

@@ -651,52 +651,68 @@ __global__ void k_scale_only(int64_t n, SpmvK<V> p) {
 // ------------------------------------------------------- matrix-free stencil
 // Constant-coefficient stencil on an nx x ny x nz grid (x fastest): no
 // matrix is stored, so a product moves only x (once, through the caches)
-// and y.  Each thread computes one point; its NP neighbour loads are issued
-// together (out-of-grid neighbours read the point itself and are then
-// discarded by a select, so padding never multiplies x).
+// and y.  The points live on the 3x3x3 cube; point q = 9 (dk+1) + 3 (dj+1) +
+// (di+1) is present when bit q of `mask` is set.  Each thread computes one
+// point with the cube unrolled at compile time (STAR keeps only the 7
+// points with at most one nonzero offset); out-of-grid and absent points
+// load the point itself and are discarded by a select, so they never
+// multiply x, and no branch separates the loads.
 struct StencilK {
-    int64_t nx, ny, nz;
+    int nx, ny, nz;
     double inv_nx, inv_nxy;  // reciprocals for the index split
-    int npts;
-    int64_t off[27];         // linear offset of each point
-    int8_t d[27][3];
+    uint32_t mask;
     double c[27];
 };
 
 // q = floor(a / b) for 0 <= a < 2^31 from a rounded reciprocal, corrected
 // by one step either way.
-__device__ __forceinline__ int64_t div_fix(int64_t a, int64_t b, double inv) {
-    int64_t q = (int64_t)((double)a * inv);
+__device__ __forceinline__ int div_fix(int a, int b, double inv) {
+    int q = (int)((double)a * inv);
     if (q * b > a) --q;
     else if ((q + 1) * b <= a) ++q;
     return q;
 }
 
-template <typename V, bool DOT, int NP>
+template <typename V, bool DOT, bool STAR>
 __global__ __launch_bounds__(kWG) void k_stencil(StencilK sk, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
-    const int64_t nxy = sk.nx * sk.ny, n = nxy * sk.nz;
-    const int64_t ntiles = (n + kWG - 1) / kWG;
+    // the coefficients go through LDS (broadcast reads) rather than 54
+    // scalar registers
+    __shared__ V s_c[27];
+    if (threadIdx.x < 27) s_c[threadIdx.x] = (V)sk.c[threadIdx.x];
+    __syncthreads();
+    const int nxy = sk.nx * sk.ny, n = nxy * sk.nz;
+    const int64_t ntiles = ((int64_t)n + kWG - 1) / kWG;
     int64_t t0, t1;
     int ts;
     band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
     double dacc = 0.0;
     for (int64_t tile = t0; tile < t1; tile += ts) {
-        const int64_t r = tile * kWG + threadIdx.x;
+        const int r = (int)(tile * kWG) + (int)threadIdx.x;
         if (r >= n) continue;
-        const int64_t k = div_fix(r, nxy, sk.inv_nxy), rem = r - k * nxy;
-        const int64_t j = div_fix(rem, sk.nx, sk.inv_nx), i = rem - j * sk.nx;
-        V xv[NP];
-        bool ok[NP];
+        const int k = div_fix(r, nxy, sk.inv_nxy), rem = r - k * nxy;
+        const int j = div_fix(rem, sk.nx, sk.inv_nx), i = rem - j * sk.nx;
+        const bool lo[3] = {i > 0, j > 0, k > 0};
+        const bool hi[3] = {i < sk.nx - 1, j < sk.ny - 1, k < sk.nz - 1};
+        V xv[27];
+        uint32_t okb = 0;  // bit q: point q present and inside the grid (one register, not 27 masks)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const int64_t ii = i + sk.d[q][0], jj = j + sk.d[q][1], kk = k + sk.d[q][2];
-            ok[q] = q < sk.npts && ii >= 0 && ii < sk.nx && jj >= 0 && jj < sk.ny && kk >= 0 && kk < sk.nz;
-            xv[q] = p.x[ok[q] ? r + sk.off[q] : r];
+        for (int q = 0; q < 27; ++q) {
+            const int di = q % 3 - 1, dj = (q / 3) % 3 - 1, dk = q / 9 - 1;
+            if (STAR && (di != 0) + (dj != 0) + (dk != 0) > 1) continue;
+            const bool in = (di < 0 ? lo[0] : di > 0 ? hi[0] : true) && (dj < 0 ? lo[1] : dj > 0 ? hi[1] : true) &&
+                            (dk < 0 ? lo[2] : dk > 0 ? hi[2] : true);
+            okb |= (uint32_t)in << q;
+            xv[q] = p.x[in ? r + di + dj * sk.nx + dk * nxy : r];
         }
+        okb &= sk.mask;  // absent points (their loads were in bounds) drop out here
         V acc = 0;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) acc += ok[q] ? (V)sk.c[q] * xv[q] : (V)0;
+        for (int q = 0; q < 27; ++q) {
+            const int di = q % 3 - 1, dj = (q / 3) % 3 - 1, dk = q / 9 - 1;
+            if (STAR && (di != 0) + (dj != 0) + (dk != 0) > 1) continue;
+            acc += ((okb >> q) & 1u) ? s_c[q] * xv[q] : (V)0;
+        }
         const V out = combine(p, acc, r);
         p.y[r] = out;
         if (DOT) dacc += (double)p.w[r] * (double)out;
@@ -990,24 +1006,26 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
     }
     case MXL_FMT_STENCIL: {
         StencilK sk{};
-        sk.nx = A.nx;
-        sk.ny = A.ny;
-        sk.nz = A.nz;
+        sk.nx = (int)A.nx;
+        sk.ny = (int)A.ny;
+        sk.nz = (int)A.nz;
         sk.inv_nx = 1.0 / (double)A.nx;
         sk.inv_nxy = 1.0 / ((double)A.nx * (double)A.ny);
-        sk.npts = A.st_npts;
-        for (int q = 0; q < 27; ++q) {
-            for (int d = 0; d < 3; ++d) sk.d[q][d] = q < A.st_npts ? A.st_off[q][d] : 0;
-            sk.off[q] = sk.d[q][0] + A.nx * (sk.d[q][1] + A.ny * sk.d[q][2]);
-            sk.c[q] = q < A.st_npts ? A.st_coef[q] : 0.0;
+        bool star = true;
+        for (int q = 0; q < A.st_npts; ++q) {
+            const int di = A.st_off[q][0], dj = A.st_off[q][1], dk = A.st_off[q][2];
+            const int c = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+            sk.mask |= 1u << c;
+            sk.c[c] = A.st_coef[q];
+            star = star && (di != 0) + (dj != 0) + (dk != 0) <= 1;
         }
         const dim3 g(A.grid_main);
-        if (A.st_npts <= 7) {
-            if (dot) hipLaunchKernelGGL((k_stencil<V, true, 7>), g, blk, 0, s, sk, p);
-            else hipLaunchKernelGGL((k_stencil<V, false, 7>), g, blk, 0, s, sk, p);
+        if (star) {
+            if (dot) hipLaunchKernelGGL((k_stencil<V, true, true>), g, blk, 0, s, sk, p);
+            else hipLaunchKernelGGL((k_stencil<V, false, true>), g, blk, 0, s, sk, p);
         } else {
-            if (dot) hipLaunchKernelGGL((k_stencil<V, true, 27>), g, blk, 0, s, sk, p);
-            else hipLaunchKernelGGL((k_stencil<V, false, 27>), g, blk, 0, s, sk, p);
+            if (dot) hipLaunchKernelGGL((k_stencil<V, true, false>), g, blk, 0, s, sk, p);
+            else hipLaunchKernelGGL((k_stencil<V, false, false>), g, blk, 0, s, sk, p);
         }
         break;
     }
