@@ -96,6 +96,15 @@ def _declare(L):
     L.orc_mlp_loss_grad.restype = f64
     L.orc_mlp_loss_grad.argtypes = [i32, vp, vp, i64, vp, vp, vp, f64, vp, vp]
     L.orc_adam_step.argtypes = [i64, vp, vp, vp, vp, i64, f64, f64, f64, f64]
+    L.orc_round_f16.restype = f64
+    L.orc_round_f16.argtypes = [f64]
+    L.orc_bj_choose_precision.restype = C.c_int
+    L.orc_bj_choose_precision.argtypes = [C.c_int, vp, f64, f64]
+    L.orc_bj_generate.restype = i64
+    L.orc_bj_generate.argtypes = [i64, vp, vp, vp, i64, vp, C.c_int, f64, vp, vp, vp]
+    L.orc_bj_apply.argtypes = [i64, vp, vp, vp, vp]
+    L.orc_pcg_block.restype = C.c_int
+    L.orc_pcg_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, _Crit, C.POINTER(_Info), vp]
 
 
 def _c(a, dt):
@@ -296,3 +305,68 @@ def adam_step(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _c(grad, np.float64)
     lib().orc_adam_step(theta.size, _p(theta), _p(g), _p(m), _p(v), t, lr, b1, b2, eps)
+
+
+# ------------------------------------------------------------ block Jacobi
+P64, P32, P16 = 0, 1, 2
+
+
+def round_f16(x: float) -> float:
+    """Nearest-even IEEE binary16 rounding (from the format's definition)."""
+    return lib().orc_round_f16(float(x))
+
+
+def uniform_blocks(n: int, bs: int) -> np.ndarray:
+    """Block row pointers of consecutive blocks of bs rows (last one ragged)."""
+    return np.minimum(np.arange(0, n + bs, bs), n).astype(np.int32)[:(n + bs - 1) // bs + 1]
+
+
+def bj_choose_precision(inv: np.ndarray, cond: float, accuracy: float = 0.1) -> int:
+    m = inv.shape[0]
+    return lib().orc_bj_choose_precision(m, _p(_c(inv, np.float64)), cond, accuracy)
+
+
+def bj_generate(A, bptr, adaptive: bool = True, accuracy: float = 0.1):
+    """Block-Jacobi inverses (Sec. 3.2): returns (inv packed block after
+    block, each m x m row-major and rounded to its storage precision, cond
+    per block, precision per block).  Raises ValueError on a singular
+    diagonal block."""
+    rp, col, val = _csr(A)
+    bptr = _c(bptr, np.int32)
+    nb = bptr.size - 1
+    sizes = np.diff(bptr).astype(np.int64)
+    inv = np.zeros(max(int((sizes ** 2).sum()), 1))
+    cond = np.zeros(max(nb, 1))
+    prec = np.zeros(max(nb, 1), np.int32)
+    bad = lib().orc_bj_generate(A.nrows, _p(rp), _p(col), _p(val), nb, _p(bptr), int(adaptive),
+                                accuracy, _p(inv), _p(cond), _p(prec))
+    if bad >= 0:
+        raise ValueError(f"diagonal block {bad} is singular")
+    return inv, cond[:nb], prec[:nb]
+
+
+def bj_apply(bptr, inv, r):
+    bptr = _c(bptr, np.int32)
+    r = _c(r, np.float64)
+    z = np.zeros_like(r)
+    lib().orc_bj_apply(bptr.size - 1, _p(bptr), _p(_c(inv, np.float64)), _p(r), _p(z))
+    return z
+
+
+def pcg_block(A, b, bptr, inv, x0=None, max_iters=10_000, reduction=1e-10, nonfinite_check=1,
+              history=False):
+    """CG with the block-Jacobi preconditioner z = blockdiag(inv) r."""
+    rp, col, val = _csr(A)
+    b = _c(b, np.float64)
+    bptr = _c(bptr, np.int32)
+    inv = _c(inv, np.float64)
+    x = np.zeros(A.nrows) if x0 is None else _c(x0, np.float64).copy()
+    info = _Info()
+    hist = np.full(max_iters + 1, np.nan) if history else None
+    lib().orc_pcg_block(A.nrows, _p(rp), _p(col), _p(val), bptr.size - 1, _p(bptr), _p(inv), _p(b),
+                        _p(x), _Crit(max_iters, reduction, nonfinite_check), C.byref(info), _p(hist))
+    out = dict(x=x, iterations=info.iterations, spmv_count=info.spmv_count,
+               rel_residual=info.rel_residual, stop_reason=info.stop_reason)
+    if history:
+        out["history"] = hist[:info.iterations + 1]
+    return out

@@ -237,6 +237,24 @@ static void prec(int64_t n, const double *dinv, const double *in, double *out)
     for (int64_t i = 0; i < n; ++i) out[i] = dinv ? dinv[i] * in[i] : in[i];
 }
 
+/* A preconditioner z = M^{-1} r: point Jacobi (dinv, or none) or block
+ * Jacobi (bptr/inv). */
+typedef struct {
+    const double *dinv;
+    int64_t nblocks;
+    const int32_t *bptr;
+    const double *inv;
+} orc_prec;
+
+static void orc_bj_apply_impl(int64_t nb, const int32_t *bptr, const double *inv,
+                              const double *r, double *z);
+
+static void apply_prec(int64_t n, const orc_prec *M, const double *in, double *out)
+{
+    if (M->bptr) orc_bj_apply_impl(M->nblocks, M->bptr, M->inv, in, out);
+    else prec(n, M->dinv, in, out);
+}
+
 static int nonfinite(double v) { return !isfinite(v); }
 
 /* ------------------------------------------------------------------- CG */
@@ -255,9 +273,30 @@ static int nonfinite(double v) { return !isfinite(v); }
  * operator is not positive definite along p) or rho' == 0 with r != 0 stops
  * with BREAKDOWN.  history[k] (optional, max_iters+1 entries) receives
  * ||r_k||/||b||. */
+static int pcg_core(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, const orc_prec *M, const double *b, double *x,
+                    orc_criteria crit, orc_info *info, double *history);
+
 int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
             const double *val, const double *dinv, const double *b, double *x,
             orc_criteria crit, orc_info *info, double *history)
+{
+    orc_prec M = {dinv, 0, NULL, NULL};
+    return pcg_core(n, row_ptr, col, val, &M, b, x, crit, info, history);
+}
+
+int orc_pcg_block(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                  const double *val, int64_t nblocks, const int32_t *bptr,
+                  const double *inv, const double *b, double *x,
+                  orc_criteria crit, orc_info *info, double *history)
+{
+    orc_prec M = {NULL, nblocks, bptr, inv};
+    return pcg_core(n, row_ptr, col, val, &M, b, x, crit, info, history);
+}
+
+static int pcg_core(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, const orc_prec *M, const double *b, double *x,
+                    orc_criteria crit, orc_info *info, double *history)
 {
     double *r = (double *)malloc((size_t)(n + 1) * sizeof(double));
     double *z = (double *)malloc((size_t)(n + 1) * sizeof(double));
@@ -281,7 +320,7 @@ int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
     rel = sqrt(rr) / nb;
     if (history) history[0] = rel;
     if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; goto done; }
-    prec(n, dinv, r, z);
+    apply_prec(n, M, r, z);
     for (int64_t i = 0; i < n; ++i) p[i] = z[i];
     double rho = dot(n, r, z);
     while (k < crit.max_iters) {
@@ -299,7 +338,7 @@ int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
         if (history) history[k] = rel;
         if (crit.nonfinite_check && nonfinite(rr)) { stop = ORC_NONFINITE; break; }
         if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
-        prec(n, dinv, r, z);
+        apply_prec(n, M, r, z);
         double rho_new = dot(n, r, z);
         if (crit.nonfinite_check && nonfinite(rho_new)) { stop = ORC_NONFINITE; break; }
         if (rho_new == 0.0) { stop = ORC_BREAKDOWN; break; }
@@ -781,4 +820,157 @@ void orc_adam_step(int64_t nparams, double *theta, const double *grad,
         double mh = m[j] / c1, vh = v[j] / c2;
         theta[j] -= lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* ------------------------------------------------------ block Jacobi */
+
+/* Block-Jacobi (Sec. 3.2): the diagonal blocks of A over consecutive row
+ * ranges [bptr[b], bptr[b+1]) are inverted (Gauss-Jordan elimination with
+ * partial pivoting, as the paper's generation does) and, in the adaptive
+ * mode, each inverse is stored in the lowest precision its conditioning
+ * and exponent range allow (memory precision decoupled from the FP64
+ * arithmetic).  Readings (the paper names the ingredients, not the rule):
+ *   cond_b = ||D_b||_1 ||D_b^{-1}||_1;
+ *   binary16 if cond_b * 2^-11 <= accuracy and every nonzero |inverse
+ *   entry| lies in [2^-14, 65504]; else binary32 if cond_b * 2^-24 <=
+ *   accuracy and they lie in [2^-126, FLT_MAX]; else binary64.
+ * Stored values are the inverse entries rounded to nearest-even in that
+ * precision; the product z_b = D_b^{-1} r_b sums over ascending columns in
+ * FP64. */
+
+/* Nearest-even rounding to IEEE binary16 written from the format's
+ * definition (11-bit significand, exponents -14..15, subnormal quantum
+ * 2^-24, overflow to infinity at 65520). */
+double orc_round_f16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    double a = fabs(x);
+    if (a >= 65520.0) return copysign(INFINITY, x);
+    int e2;
+    frexp(a, &e2);             /* a = m 2^e2, m in [0.5, 1): exponent e2 - 1 */
+    int e = e2 - 1;
+    if (e < -14) e = -14;      /* subnormal range shares the quantum 2^-24 */
+    double quantum = ldexp(1.0, e - 10);
+    double r = nearbyint(a / quantum) * quantum;  /* exact scaling, RNE */
+    return copysign(r, x);
+}
+
+static double round_to(double x, int prec)
+{
+    if (prec == ORC_P32) return (double)(float)x;
+    if (prec == ORC_P16) return orc_round_f16(x);
+    return x;
+}
+
+/* Gauss-Jordan inversion of the m x m row-major matrix D (overwritten)
+ * into Dinv, with partial pivoting.  Returns 0, or 1 if D is singular. */
+static int gauss_jordan(int m, double *D, double *Dinv)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Dinv[i * m + j] = (i == j) ? 1.0 : 0.0;
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (fabs(D[r * m + c]) > fabs(D[piv * m + c])) piv = r;
+        if (D[piv * m + c] == 0.0) return 1;
+        if (piv != c)
+            for (int j = 0; j < m; ++j) {
+                double t = D[c * m + j]; D[c * m + j] = D[piv * m + j]; D[piv * m + j] = t;
+                t = Dinv[c * m + j]; Dinv[c * m + j] = Dinv[piv * m + j]; Dinv[piv * m + j] = t;
+            }
+        double d = D[c * m + c];
+        for (int j = 0; j < m; ++j) { D[c * m + j] /= d; Dinv[c * m + j] /= d; }
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            double f = D[r * m + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < m; ++j) {
+                D[r * m + j] -= f * D[c * m + j];
+                Dinv[r * m + j] -= f * Dinv[c * m + j];
+            }
+        }
+    }
+    return 0;
+}
+
+static double norm1(int m, const double *M)
+{
+    double best = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += fabs(M[i * m + j]);
+        if (s > best) best = s;
+    }
+    return best;
+}
+
+int orc_bj_choose_precision(int m, const double *inv, double cond, double accuracy)
+{
+    double lo = INFINITY, hi = 0.0;
+    for (int k = 0; k < m * m; ++k) {
+        double a = fabs(inv[k]);
+        if (a == 0.0) continue;
+        if (a < lo) lo = a;
+        if (a > hi) hi = a;
+    }
+    if (hi == 0.0) lo = hi = 1.0;
+    if (cond * ldexp(1.0, -11) <= accuracy && lo >= ldexp(1.0, -14) && hi <= 65504.0) return ORC_P16;
+    if (cond * ldexp(1.0, -24) <= accuracy && lo >= ldexp(1.0, -126) && hi <= 3.4028234663852886e38)
+        return ORC_P32;
+    return ORC_P64;
+}
+
+int64_t orc_bj_generate(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                        int64_t nblocks, const int32_t *bptr, int adaptive, double accuracy,
+                        double *inv, double *cond, int32_t *prec_out)
+{
+    int64_t off = 0;
+    int mmax = 0;
+    for (int64_t b = 0; b < nblocks; ++b)
+        if (bptr[b + 1] - bptr[b] > mmax) mmax = bptr[b + 1] - bptr[b];
+    double *D = (double *)malloc((size_t)mmax * mmax * sizeof(double) + 8);
+    double *Dk = (double *)malloc((size_t)mmax * mmax * sizeof(double) + 8);
+    int64_t bad = -1;
+    (void)n;
+    for (int64_t b = 0; b < nblocks && bad < 0; ++b) {
+        const int r0 = bptr[b], m = bptr[b + 1] - bptr[b];
+        for (int k = 0; k < m * m; ++k) D[k] = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int32_t k = row_ptr[r0 + i]; k < row_ptr[r0 + i + 1]; ++k) {
+                const int j = col[k] - r0;
+                if (j >= 0 && j < m) D[i * m + j] = val[k];
+            }
+        const double nD = norm1(m, D);
+        for (int k = 0; k < m * m; ++k) Dk[k] = D[k];
+        if (gauss_jordan(m, Dk, inv + off)) { bad = b; break; }
+        const double c = nD * norm1(m, inv + off);
+        const int p = adaptive ? orc_bj_choose_precision(m, inv + off, c, accuracy) : ORC_P64;
+        for (int k = 0; k < m * m; ++k) inv[off + k] = round_to(inv[off + k], p);
+        cond[b] = c;
+        prec_out[b] = p;
+        off += (int64_t)m * m;
+    }
+    free(D);
+    free(Dk);
+    return bad;
+}
+
+static void orc_bj_apply_impl(int64_t nb, const int32_t *bptr, const double *inv,
+                              const double *r, double *z)
+{
+    int64_t off = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int r0 = bptr[b], m = bptr[b + 1] - bptr[b];
+        for (int i = 0; i < m; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += inv[off + (int64_t)i * m + j] * r[r0 + j];
+            z[r0 + i] = s;
+        }
+        off += (int64_t)m * m;
+    }
+}
+
+void orc_bj_apply(int64_t nb, const int32_t *bptr, const double *inv, const double *r, double *z)
+{
+    orc_bj_apply_impl(nb, bptr, inv, r, z);
 }

@@ -116,6 +116,19 @@ void orc_adam_step(int64_t nparams, double *theta, const double *grad,
                    double *m, double *v, int64_t t, double lr, double beta1,
                    double beta2, double eps);
 
+/* Block-Jacobi (Sec. 3.2), adaptive storage precision: see oracle.c. */
+enum { ORC_P64 = 0, ORC_P32 = 1, ORC_P16 = 2 };
+double  orc_round_f16(double x);
+int     orc_bj_choose_precision(int m, const double *inv, double cond, double accuracy);
+int64_t orc_bj_generate(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                        int64_t nblocks, const int32_t *bptr, int adaptive, double accuracy,
+                        double *inv, double *cond, int32_t *prec);
+void    orc_bj_apply(int64_t nblocks, const int32_t *bptr, const double *inv, const double *r,
+                     double *z);
+int     orc_pcg_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                      int64_t nblocks, const int32_t *bptr, const double *inv, const double *b,
+                      double *x, orc_criteria crit, orc_info *info, double *history);
+
 #ifdef __cplusplus
 }
 #endif
