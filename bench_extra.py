@@ -1,7 +1,8 @@
 """Secondary benchmark workloads of bench.py (--workload ...), one JSON line each.
 
 aniso_ir  : 160^3 anisotropic 7-point diffusion, FP64 Jacobi-PCG vs FP64-outer /
-            FP32-inner-CG iterative refinement: time to 1e-10 and to 1e-12.
+            FP32-inner-CG iterative refinement vs block-Jacobi CG (32-row
+            blocks, binary64 or adaptive storage): time to 1e-10 and 1e-12.
 poisson2d : 64x64 Poisson, Jacobi-PCG to 1e-10: one kernel per step vs the whole
             solve in one persistent workgroup (latency-bound case).
 batch     : 10,000 banded SPD systems, batched Jacobi-PCG in one persistent
@@ -91,11 +92,30 @@ def aniso_ir(args):
             res[f"ir_{red:g}_in{tin:g}"] = dict(ms=round(dt * 1e3, 3), outer=info["iterations"],
                                                inner=info["inner_iterations"],
                                                true_rel=float(torch.linalg.norm(r) / torch.linalg.norm(b)))
+    # block-Jacobi CG (32-row blocks): binary64 storage and adaptive storage
+    for red in (1e-10, 1e-12):
+        for adaptive in (False, True):
+            Pb = mxl.bjacobi(M, 32, adaptive, 0.1)
+            Sb = mxl.solver("cg", M, Pb, max_iters=5000, reduction=red, check_every=16)
+
+            def fb():
+                x.zero_()
+                return Sb.solve(b, x)
+            dt, info = _timed(fb, args.steps, args.warmup)
+            r = b.clone(); base.apply(x, r, -1.0, 1.0)
+            bi = Pb.info()
+            res[f"bjacobi32_{'adaptive' if adaptive else 'fp64'}_{red:g}"] = dict(
+                ms=round(dt * 1e3, 3), iterations=info["iterations"],
+                true_rel=float(torch.linalg.norm(r) / torch.linalg.norm(b)),
+                storage_MB=round(bi["storage_bytes"] / 1e6, 2),
+                blocks_by_precision=[int((bi["precision"] == k).sum()) for k in (0, 1, 2)])
     best_ir = min((v["ms"], k) for k, v in res.items() if k.startswith("ir_1e-10"))
     out["value"] = best_ir[0]
     out["fp64_ms_1e-10"] = res["fp64_1e-10"]["ms"]
     out["speedup_vs_fp64_1e-10"] = round(res["fp64_1e-10"]["ms"] / best_ir[0], 3)
     out["best_ir"] = best_ir[1]
+    out["bjacobi32_adaptive_ms_1e-10"] = res["bjacobi32_adaptive_1e-10"]["ms"]
+    out["speedup_bjacobi_vs_fp64_point_1e-10"] = round(res["fp64_1e-10"]["ms"] / res["bjacobi32_adaptive_1e-10"]["ms"], 3)
     out["runs"] = res
     out["steps"], out["warmup"] = args.steps, args.warmup
     if not args.no_cpu_baseline:

@@ -231,6 +231,29 @@ mxl_status mxl_op_destroy(mxl_op *op);
  * Errors: ZERO_DIAG (a missing or zero a_ii), NOT_IMPLEMENTED (non-square). */
 mxl_status mxl_jacobi_generate(const mxl_op *A, mxl_op **P);
 
+/* Block-Jacobi preconditioner (Sec. 3.2): the diagonal blocks of A over
+ * consecutive ranges of block_size rows (the last range may be shorter) are
+ * inverted by Gauss-Jordan elimination with partial pivoting in FP64.  With
+ * adaptive != 0 each inverse is stored in the lowest of binary16, binary32,
+ * binary64 for which cond_1(D_b) * u <= accuracy (u = 2^-11, 2^-24) and
+ * every nonzero entry lies in that format's normal range (memory precision
+ * decoupled from the FP64 arithmetic); otherwise binary64.  accuracy 0
+ * means 0.1.  mxl_apply computes z = M r in FP64 from the stored entries.
+ * It preconditions the CG solver (per-kernel path).  block_size in
+ * {1, 2, 4, 8, 16, 32}.  Errors: INVALID_ARG, NOT_IMPLEMENTED (non-square,
+ * FP32 or matrix-free operator), ZERO_DIAG (a singular diagonal block),
+ * OUT_OF_MEMORY, DEVICE. */
+mxl_status mxl_bjacobi_generate(const mxl_op *A, int32_t block_size, int32_t adaptive,
+                                double accuracy, mxl_op **P);
+
+/* Per-block data of a block-Jacobi operator (HOST outputs, each may be
+ * NULL): the number of blocks, cond_1 of every diagonal block, its storage
+ * precision (0 binary64, 1 binary32, 2 binary16), the stored inverses as
+ * FP64 (block after block, each m x m row-major, m the block's rows) and
+ * the bytes the inverses occupy.  Blocks until the copies are done. */
+mxl_status mxl_bjacobi_info(const mxl_op *P, int64_t *nblocks, double *cond,
+                            int32_t *precision, double *inv, int64_t *storage_bytes);
+
 /* Solver factory .generate(A) (Sec. 2.2.3, Sec. 3.1): Krylov solver bound to
  * A with optional preconditioner P (NULL = none).  The solver keeps shared
  * references to A and P and owns its work vectors. */

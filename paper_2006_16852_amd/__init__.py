@@ -130,6 +130,8 @@ def _load():
         "mxl_mlp_destroy": [vp],
         "mxl_selector_create": [vp, i32, vp, i32, vp, vp, vp, vp, C.c_uint32, f64, f64, pp],
         "mxl_stencil_create": [vp, C.c_int, i64, i64, i64, i32, vp, vp, pp],
+        "mxl_bjacobi_generate": [vp, i32, i32, f64, pp],
+        "mxl_bjacobi_info": [vp, C.POINTER(C.c_int64), vp, vp, vp, C.POINTER(C.c_int64)],
         "mxl_selector_destroy": [vp],
         "mxl_select": [vp, vp, i32, vp, vp, i32, C.POINTER(C.c_int32), vp, vp,
                        C.POINTER(SelectInfo)],
@@ -341,6 +343,43 @@ def jacobi(A: Op) -> Op:
     A.ctx.use_current_stream()
     _check(lib.mxl_jacobi_generate(A.h, C.byref(h)))
     return Op(h, A.ctx, parents=(A,))
+
+
+class BlockJacobi(Op):
+    """Block-Jacobi preconditioner (inverted diagonal blocks, adaptive
+    storage precision)."""
+
+    def info(self, inverses: bool = False) -> dict:
+        import numpy as np
+        nb = C.c_int64()
+        nbytes = C.c_int64()
+        _check(lib.mxl_bjacobi_info(self.h, C.byref(nb), None, None, None, C.byref(nbytes)))
+        cond = np.zeros(max(nb.value, 1))
+        prec = np.zeros(max(nb.value, 1), np.int32)
+        inv = None
+        ptr_inv = None
+        if inverses:
+            d = self.describe()
+            n, bs = d["nrows"], self._bs
+            sizes = np.minimum(bs, n - np.arange(nb.value) * bs)
+            inv = np.zeros(max(int((sizes ** 2).sum()), 1))
+            ptr_inv = inv.ctypes.data_as(C.c_void_p)
+        _check(lib.mxl_bjacobi_info(self.h, C.byref(nb), cond.ctypes.data_as(C.c_void_p),
+                                    prec.ctypes.data_as(C.c_void_p), ptr_inv, C.byref(nbytes)))
+        out = dict(nblocks=nb.value, cond=cond[:nb.value], precision=prec[:nb.value],
+                   storage_bytes=nbytes.value)
+        if inverses:
+            out["inv"] = inv
+        return out
+
+
+def bjacobi(A: Op, block_size: int = 8, adaptive: bool = True, accuracy: float = 0.1) -> BlockJacobi:
+    h = C.c_void_p()
+    A.ctx.use_current_stream()
+    _check(lib.mxl_bjacobi_generate(A.h, block_size, int(adaptive), accuracy, C.byref(h)))
+    P = BlockJacobi(h, A.ctx, parents=(A,))
+    P._bs = block_size
+    return P
 
 
 def criteria(max_iters=10_000, reduction=1e-10, time_limit=0.0, check_every=1,

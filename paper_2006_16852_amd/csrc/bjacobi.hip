@@ -1,0 +1,510 @@
+// bjacobi.hip -- block-Jacobi preconditioner (Sec. 3.2): batched
+// Gauss-Jordan inversion of the diagonal blocks (one wave per block),
+// adaptive storage precision of each inverse (binary16/32/64 chosen from
+// the block's condition number and exponent range), the product z = M r,
+// and the CG steps that use it (the r update fused with z = M r and the
+// r.z, r.r reductions).
+//
+// Blocks are consecutive ranges of BS rows (BS in {1,...,32}, the last one
+// may be shorter), so a 256-row tile always holds whole blocks.  Every
+// inverse is stored as a BS x BS row-major array (zeros outside a short last
+// block) at byte offset off[b] in the precision prec[b].
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace mxl {
+
+enum { BJ_P64 = 0, BJ_P32 = 1, BJ_P16 = 2 };
+
+// Nearest-even rounding to binary16 from the format's definition: 11-bit
+// significand, exponents -14..15, subnormal quantum 2^-24, overflow to
+// infinity from 65520 on.  Scaling by the quantum is exact, rint rounds to
+// nearest even.
+__device__ __forceinline__ double round_f16(double x) {
+    if (x == 0.0 || !__builtin_isfinite(x)) return x;
+    const double a = fabs(x);
+    if (a >= 65520.0) return copysign(__builtin_inf(), x);
+    int e2;
+    (void)frexp(a, &e2);
+    int e = e2 - 1;
+    if (e < -14) e = -14;
+    const double quantum = ldexp(1.0, e - 10);
+    return copysign(rint(a / quantum) * quantum, x);
+}
+
+// One wave inverts one diagonal block.  Lane j owns column j of D and of
+// its inverse I (both in LDS); every element sees the same operations in the
+// same order as a sequential Gauss-Jordan elimination with partial
+// pivoting (first row of largest magnitude), with no multiply-add
+// contraction, so the inverse, its condition number and the precision
+// decision are reproducible.
+template <int BS>
+__global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__restrict__ rp,
+                                                     const int *__restrict__ col,
+                                                     const double *__restrict__ val, int adaptive,
+                                                     double accuracy, double *__restrict__ inv,
+                                                     double *__restrict__ cond, int *__restrict__ prec,
+                                                     int *__restrict__ bad) {
+#pragma clang fp contract(off)
+    __shared__ double D[BS][BS], I[BS][BS];
+    const int64_t b = blockIdx.x;
+    const int64_t r0 = b * BS;
+    const int m = (int)(n - r0 < BS ? n - r0 : BS);
+    const int j = threadIdx.x;
+    if (j < BS)
+        for (int i = 0; i < BS; ++i) {
+            D[i][j] = 0.0;
+            I[i][j] = (i == j && j < m) ? 1.0 : 0.0;
+        }
+    __syncthreads();
+    if (j < m)  // lane j loads row j of the block
+        for (int k = rp[r0 + j]; k < rp[r0 + j + 1]; ++k) {
+            const int64_t c = (int64_t)col[k] - r0;
+            if (c >= 0 && c < m) D[j][c] = val[k];
+        }
+    __syncthreads();
+    auto norm1 = [&](double (*M)[BS]) {
+        double s = 0.0;
+        if (j < m)
+            for (int i = 0; i < m; ++i) s += fabs(M[i][j]);
+        return wave_max(s);
+    };
+    const double nD = norm1(D);
+    for (int c = 0; c < m; ++c) {
+        const double v = (j >= c && j < m) ? fabs(D[j][c]) : -1.0;
+        const double mx = wave_max(v);
+        if (!(mx > 0.0)) {  // singular block (zero column below the diagonal)
+            if (j == 0) atomicMin(bad, (int)(b < INT_MAX ? b : INT_MAX));
+            return;
+        }
+        const unsigned long long hit = __ballot(v == mx);
+        const int piv = __ffsll((long long)hit) - 1;
+        if (piv != c && j < m) {
+            double t = D[c][j];
+            D[c][j] = D[piv][j];
+            D[piv][j] = t;
+            t = I[c][j];
+            I[c][j] = I[piv][j];
+            I[piv][j] = t;
+        }
+        __syncthreads();
+        const double d = D[c][c];
+        __syncthreads();
+        if (j < m) {
+            D[c][j] = D[c][j] / d;
+            I[c][j] = I[c][j] / d;
+        }
+        __syncthreads();
+        for (int r = 0; r < m; ++r) {
+            if (r == c) continue;
+            const double f = D[r][c];
+            __syncthreads();
+            if (f == 0.0) continue;
+            if (j < m) {
+                const double pd = f * D[c][j];
+                const double pi = f * I[c][j];
+                D[r][j] = D[r][j] - pd;
+                I[r][j] = I[r][j] - pi;
+            }
+            __syncthreads();
+        }
+    }
+    const double nI = norm1(I);
+    const double kappa = nD * nI;
+    int p = BJ_P64;
+    if (adaptive) {
+        double lo = __builtin_inf(), hi = 0.0;
+        if (j < m)
+            for (int i = 0; i < m; ++i) {
+                const double a = fabs(I[i][j]);
+                if (a == 0.0) continue;
+                lo = a < lo ? a : lo;
+                hi = a > hi ? a : hi;
+            }
+        lo = -wave_max(-lo);
+        hi = wave_max(hi);
+        if (hi == 0.0) lo = hi = 1.0;
+        if (kappa * ldexp(1.0, -11) <= accuracy && lo >= ldexp(1.0, -14) && hi <= 65504.0) p = BJ_P16;
+        else if (kappa * ldexp(1.0, -24) <= accuracy && lo >= ldexp(1.0, -126) && hi <= 3.4028234663852886e38)
+            p = BJ_P32;
+    }
+    if (j < BS)
+        for (int i = 0; i < BS; ++i) {
+            double x = I[i][j];
+            if (p == BJ_P32) x = (double)(float)x;
+            else if (p == BJ_P16) x = round_f16(x);
+            inv[(b * BS + i) * BS + j] = x;
+        }
+    if (j == 0) {
+        cond[b] = kappa;
+        prec[b] = p;
+    }
+}
+
+// Packs the rounded inverses into their storage precision (the values are
+// already representable, so the conversions are exact).
+template <int BS>
+__global__ void k_bj_pack(int64_t nb, const double *__restrict__ inv, const int *__restrict__ prec,
+                          const int64_t *__restrict__ off, unsigned char *__restrict__ store) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nb * BS * BS) return;
+    const int64_t b = e / (BS * BS), k = e % (BS * BS);
+    unsigned char *base = store + off[b];
+    const double x = inv[e];
+    switch (prec[b]) {
+    case BJ_P16: ((_Float16 *)base)[k] = (_Float16)x; break;
+    case BJ_P32: ((float *)base)[k] = (float)x; break;
+    default: ((double *)base)[k] = x; break;
+    }
+}
+
+// Row t of block b's stored inverse times the block's vector part held in
+// LDS (xs[0..BS)), summed over ascending columns in FP64.
+template <int BS>
+__device__ __forceinline__ double bj_row(const unsigned char *__restrict__ store, int64_t off, int pr,
+                                         int t, const double *xs) {
+    double s = 0.0;
+    if (pr == BJ_P16) {
+        const _Float16 *rowp = (const _Float16 *)(store + off) + t * BS;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) s += (double)rowp[j] * xs[j];
+    } else if (pr == BJ_P32) {
+        const float *rowp = (const float *)(store + off) + t * BS;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) s += (double)rowp[j] * xs[j];
+    } else {
+        const double *rowp = (const double *)(store + off) + t * BS;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) s += rowp[j] * xs[j];
+    }
+    return s;
+}
+
+// z = M r on 256-row tiles (whole blocks): each wave parks its 64 values of
+// r in LDS, then lane l forms row (l mod BS) of its block.
+#define MXL_BJ_TILE(n)                                                  \
+    const int L = blockIdx.x;                                           \
+    int64_t tb_, te_;                                                   \
+    int ts_;                                                            \
+    band_walk(((n) + kWG - 1) / kWG, blockIdx.x, gridDim.x, tb_, te_, ts_);
+
+template <int BS>
+__global__ __launch_bounds__(kWG) void k_bj_apply(int64_t n, const unsigned char *__restrict__ store,
+                                                  const int64_t *__restrict__ off,
+                                                  const int *__restrict__ prec, double alpha,
+                                                  const double *__restrict__ r, double beta,
+                                                  double *__restrict__ z) {
+    __shared__ double xs[kWG];
+    MXL_BJ_TILE(n)
+    (void)L;
+    const int lane = threadIdx.x;
+    for (int64_t t_ = tb_; t_ < te_; t_ += ts_) {
+        const int64_t i = t_ * kWG + lane;
+        xs[lane] = i < n ? r[i] : 0.0;
+        __syncthreads();
+        if (i < n) {
+            const int64_t blk = i / BS;
+            const int t = (int)(i % BS);
+            const double v = bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
+            z[i] = beta == 0.0 ? alpha * v : alpha * v + beta * z[i];
+        }
+        __syncthreads();
+    }
+}
+
+// CG with block Jacobi, initial step: z = M r, p = z; publishes [r.z, r.r, b.b].
+template <int BS>
+__global__ __launch_bounds__(kWG) void k_cg_init_bj(int64_t n, const double *__restrict__ b,
+                                                    const double *__restrict__ r, double *__restrict__ p,
+                                                    const unsigned char *__restrict__ store,
+                                                    const int64_t *__restrict__ off,
+                                                    const int *__restrict__ prec,
+                                                    double *__restrict__ parts) {
+    __shared__ double xs[kWG];
+    MXL_BJ_TILE(n)
+    const int lane = threadIdx.x;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int64_t t_ = tb_; t_ < te_; t_ += ts_) {
+        const int64_t i = t_ * kWG + lane;
+        const double ri = i < n ? r[i] : 0.0;
+        xs[lane] = ri;
+        __syncthreads();
+        if (i < n) {
+            const int64_t blk = i / BS;
+            const int t = (int)(i % BS);
+            const double zi = bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
+            p[i] = zi;
+            rz += ri * zi;
+            rr += ri * ri;
+            bb += b[i] * b[i];
+        }
+        __syncthreads();
+    }
+    double v[3] = {rz, rr, bb};
+    publish<3>(v, parts, L);
+}
+
+// CG with block Jacobi, after the fused p.q: alpha = rho_{k-1} / p.q,
+// r -= alpha q, z = M r, and the reductions r.z, r.r.  The stop handshake
+// with k_cg_pupdate (st->ustop) is the one of the point-Jacobi kernels.
+template <int BS>
+__global__ __launch_bounds__(kWG) void k_cg_update_bj(int64_t n, double *__restrict__ r,
+                                                      const double *__restrict__ q, double *__restrict__ z,
+                                                      const unsigned char *__restrict__ store,
+                                                      const int64_t *__restrict__ off,
+                                                      const int *__restrict__ prec, SolverState *st,
+                                                      const double *__restrict__ pq_parts, int pq_slots,
+                                                      double *__restrict__ parts, int k) {
+    __shared__ double xs[kWG];
+    if (st->stop) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->ustop = 1;
+        return;
+    }
+    double eta[1];
+    gather_all<1>(pq_parts, pq_slots, eta);
+    const bool chk = st->nonfinite_check != 0;
+    const bool nonfin = chk && !finite_d(eta[0]);
+    if (nonfin || eta[0] <= 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->stop = nonfin ? ST_NONFINITE : ST_BREAKDOWN;
+            st->ustop = 1;
+            st->iters = k - 1;
+            st->eta = eta[0];
+        }
+        return;
+    }
+    const double alpha = st->rho2[(k - 1) & 1] / eta[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->alpha = alpha;
+        st->eta = eta[0];
+        st->ustop = 0;
+    }
+    MXL_BJ_TILE(n)
+    const int lane = threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t t_ = tb_; t_ < te_; t_ += ts_) {
+        const int64_t i = t_ * kWG + lane;
+        double ri = 0.0;
+        if (i < n) {
+            ri = r[i] - alpha * q[i];
+            r[i] = ri;
+        }
+        xs[lane] = ri;
+        __syncthreads();
+        if (i < n) {
+            const int64_t blk = i / BS;
+            const int t = (int)(i % BS);
+            const double zi = bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
+            z[i] = zi;
+            rz += ri * zi;
+            rr += ri * ri;
+        }
+        __syncthreads();
+    }
+    double v[2] = {rz, rr};
+    publish<2>(v, parts, L);
+}
+
+// ------------------------------------------------------------ host side
+#define MXL_BS_SWITCH(BSV, ...)                      \
+    switch (BSV) {                                   \
+    case 1: { constexpr int BS = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int BS = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int BS = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int BS = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int BS = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int BS = 32; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;            \
+    }
+
+hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, const void *b, const void *r,
+                      void *p, double *parts, hipStream_t s) {
+    const int g = vec_grid(ctx, n);
+    MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL(k_cg_init_bj<BS>, dim3(g), dim3(kWG), 0, s, n, (const double *)b,
+                                           (const double *)r, (double *)p,
+                                           (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
+                                           (const int *)P.bprec->p, parts));
+    return hipGetLastError();
+}
+
+hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, void *r, const void *q, void *z,
+                        SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
+                        hipStream_t s) {
+    const int g = vec_grid(ctx, n);
+    MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL(k_cg_update_bj<BS>, dim3(g), dim3(kWG), 0, s, n, (double *)r,
+                                           (const double *)q, (double *)z,
+                                           (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
+                                           (const int *)P.bprec->p, st, pq_parts, pq_slots, parts, k));
+    return hipGetLastError();
+}
+
+hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
+                    double beta, void *z, hipStream_t s) {
+    const int g = vec_grid(ctx, n);
+    MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL(k_bj_apply<BS>, dim3(g), dim3(kWG), 0, s, n,
+                                           (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
+                                           (const int *)P.bprec->p, alpha, (const double *)r, beta,
+                                           (double *)z));
+    return hipGetLastError();
+}
+
+static hipError_t bj_invert(const MatrixImpl &A, int bs, int adaptive, double accuracy, double *inv,
+                            double *cond, int *prec, int *bad, hipStream_t s) {
+    const int64_t nb = (A.nrows + bs - 1) / bs;
+    MXL_BS_SWITCH(bs, hipLaunchKernelGGL(k_bj_invert<BS>, dim3((unsigned)nb), dim3(kWave), 0, s, A.nrows,
+                                         (const int *)A.row_ptr->p, (const int *)A.col->p,
+                                         (const double *)A.val->p, adaptive, accuracy, inv, cond, prec, bad));
+    return hipGetLastError();
+}
+
+static hipError_t bj_pack(int bs, int64_t nb, const double *inv, const int *prec, const int64_t *off,
+                          unsigned char *store, hipStream_t s) {
+    const int64_t total = nb * bs * bs;
+    const unsigned g = (unsigned)((total + 255) / 256);
+    MXL_BS_SWITCH(bs, hipLaunchKernelGGL(k_bj_pack<BS>, dim3(g), dim3(256), 0, s, nb, inv, prec, off, store));
+    return hipGetLastError();
+}
+
+}  // namespace mxl
+
+using namespace mxl;
+
+extern "C" mxl_status mxl_bjacobi_generate(const mxl_op *Aop, int32_t block_size, int32_t adaptive,
+                                           double accuracy, mxl_op **Pout) {
+    if (!Aop || !Pout || Aop->kind != MXL_OP_MATRIX)
+        return set_error(MXL_ERR_INVALID_ARG, "matrix operator and output required");
+    *Pout = nullptr;
+    const auto &A = Aop->mat;
+    if (block_size != 1 && block_size != 2 && block_size != 4 && block_size != 8 && block_size != 16 &&
+        block_size != 32)
+        return set_error(MXL_ERR_INVALID_ARG, "block_size must be 1, 2, 4, 8, 16 or 32");
+    if (A->nrows != A->ncols) return set_error(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi needs a square matrix");
+    if (A->dtype != MXL_F64) return set_error(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi needs an FP64 matrix");
+    if (A->format == MXL_FMT_STENCIL)
+        return set_error(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi needs stored matrix rows");
+    if (A->nrows == 0) return set_error(MXL_ERR_INVALID_ARG, "empty matrix");
+    if (!(accuracy >= 0.0)) return set_error(MXL_ERR_INVALID_ARG, "accuracy must be >= 0");
+    if (accuracy == 0.0) accuracy = 0.1;
+    DeviceScope ds(A->ctx->device);
+    hipStream_t s = A->ctx->stream;
+    const int bs = block_size;
+    const int64_t nb = (A->nrows + bs - 1) / bs;
+    auto J = std::make_shared<JacobiImpl>();
+    J->A = A;
+    J->block = true;
+    J->bs = bs;
+    J->nblocks = nb;
+    hipError_t e = hipSuccess;
+    BufPtr tmp, bad;
+    auto mk = [&](size_t bytes) {
+        auto d = std::make_shared<DevBuf>();
+        if (hipMalloc(&d->p, bytes ? bytes : 16) != hipSuccess) return BufPtr();
+        d->bytes = bytes;
+        d->owned = true;
+        return d;
+    };
+    tmp = mk((size_t)nb * bs * bs * 8);
+    J->bcond = mk((size_t)nb * 8);
+    J->bprec = mk((size_t)nb * 4);
+    J->boff = mk((size_t)nb * 8);
+    bad = mk(4);
+    if (!tmp || !J->bcond || !J->bprec || !J->boff || !bad)
+        return set_error(MXL_ERR_OUT_OF_MEMORY, "block Jacobi workspace");
+    int none = INT_MAX;
+    if ((e = hipMemcpyAsync(bad->p, &none, 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = bj_invert(*A, bs, adaptive ? 1 : 0, accuracy, (double *)tmp->p, (double *)J->bcond->p,
+                       (int *)J->bprec->p, (int *)bad->p, s)) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, std::string("block inversion: ") + hipGetErrorString(e));
+    int hb = INT_MAX;
+    std::vector<int> hp((size_t)nb);
+    if (hipMemcpyAsync(&hb, bad->p, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hp.data(), J->bprec->p, (size_t)nb * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "block inversion read-back");
+    if (hb != INT_MAX) {
+        char msg[96];
+        snprintf(msg, sizeof msg, "diagonal block %d is singular", hb);
+        return set_error(MXL_ERR_ZERO_DIAG, msg);
+    }
+    // byte offsets: each block padded to a multiple of 8 bytes
+    std::vector<int64_t> ho((size_t)nb);
+    int64_t total = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        ho[b] = total;
+        const int64_t sz = (int64_t)bs * bs * (hp[b] == BJ_P16 ? 2 : hp[b] == BJ_P32 ? 4 : 8);
+        total += (sz + 7) / 8 * 8;
+    }
+    J->bstore = mk((size_t)total);
+    if (!J->bstore) return set_error(MXL_ERR_OUT_OF_MEMORY, "block Jacobi storage");
+    J->bstore_bytes = total;
+    if ((e = hipMemcpyAsync(J->boff->p, ho.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = bj_pack(bs, nb, (const double *)tmp->p, (const int *)J->bprec->p, (const int64_t *)J->boff->p,
+                     (unsigned char *)J->bstore->p, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, std::string("block Jacobi packing: ") + hipGetErrorString(e));
+    auto *op = new mxl_op;
+    op->kind = MXL_OP_JACOBI;
+    op->jac = J;
+    *Pout = op;
+    return MXL_OK;
+}
+
+extern "C" mxl_status mxl_bjacobi_info(const mxl_op *Pop, int64_t *nblocks, double *cond_host,
+                                       int32_t *precision_host, double *inv_host, int64_t *storage_bytes) {
+    if (!Pop || Pop->kind != MXL_OP_JACOBI || !Pop->jac->block)
+        return set_error(MXL_ERR_INVALID_ARG, "not a block-Jacobi operator");
+    const JacobiImpl &J = *Pop->jac;
+    DeviceScope ds(J.A->ctx->device);
+    hipStream_t s = J.A->ctx->stream;
+    const int64_t nb = J.nblocks, bs = J.bs, n = J.A->nrows;
+    if (nblocks) *nblocks = nb;
+    if (storage_bytes) *storage_bytes = J.bstore_bytes;
+    if (cond_host && hipMemcpyAsync(cond_host, J.bcond->p, (size_t)nb * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "copy condition numbers");
+    std::vector<int> hp((size_t)nb);
+    if (hipMemcpyAsync(hp.data(), J.bprec->p, (size_t)nb * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "copy precisions");
+    std::vector<unsigned char> store;
+    std::vector<int64_t> ho;
+    if (inv_host) {
+        store.resize((size_t)J.bstore_bytes);
+        ho.resize((size_t)nb);
+        if (hipMemcpyAsync(store.data(), J.bstore->p, store.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(ho.data(), J.boff->p, (size_t)nb * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "copy inverses");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return set_error(MXL_ERR_DEVICE, "block Jacobi read-back");
+    if (precision_host)
+        for (int64_t b = 0; b < nb; ++b) precision_host[b] = hp[b];
+    if (inv_host) {  // packed m x m per block, as FP64
+        int64_t o = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t m = std::min(bs, n - b * bs);
+            const unsigned char *base = store.data() + ho[b];
+            for (int64_t i = 0; i < m; ++i)
+                for (int64_t jj = 0; jj < m; ++jj) {
+                    const int64_t k = i * bs + jj;
+                    double x;
+                    if (hp[b] == BJ_P16) {
+                        _Float16 h;
+                        std::memcpy(&h, base + 2 * k, 2);
+                        x = (double)h;
+                    } else if (hp[b] == BJ_P32) {
+                        float f;
+                        std::memcpy(&f, base + 4 * k, 4);
+                        x = f;
+                    } else {
+                        std::memcpy(&x, base + 8 * k, 8);
+                    }
+                    inv_host[o++] = x;
+                }
+        }
+    }
+    return MXL_OK;
+}

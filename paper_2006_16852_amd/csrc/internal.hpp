@@ -105,7 +105,14 @@ struct MatrixImpl {
 
 struct JacobiImpl {
     std::shared_ptr<MatrixImpl> A;
-    BufPtr dinv;
+    BufPtr dinv;                 // point Jacobi
+    // block Jacobi: inverses of consecutive bs-row diagonal blocks, each
+    // stored bs x bs at byte offset boff[b] in precision bprec[b]
+    bool block = false;
+    int bs = 1;
+    int64_t nblocks = 0;
+    BufPtr bstore, boff, bprec, bcond;
+    int64_t bstore_bytes = 0;
 };
 
 struct IrImpl;
@@ -216,6 +223,15 @@ hipError_t ir_correct(int64_t n, double *x, const float *d, const SolverState *s
 hipError_t launch_flush(void *buf, size_t bytes, hipStream_t s);
 hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a, const double *b,
                          double *c, hipStream_t s);
+
+// ------------------------------------------------------------- bjacobi.hip
+hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, const void *b, const void *r,
+                      void *p, double *parts, hipStream_t s);
+hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, void *r, const void *q, void *z,
+                        SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
+                        hipStream_t s);
+hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
+                    double beta, void *z, hipStream_t s);
 
 // ------------------------------------------------------------- runtime.hip
 mxl_status set_error(mxl_status st, const std::string &msg);

@@ -558,7 +558,8 @@ mxl_status mxl_apply_adv(const mxl_op *L, double alpha, const void *b, double be
         mxl_status st;
         if ((st = check_dev(A.ctx, b, (size_t)A.nrows * vt, "b")) != MXL_OK) return st;
         if ((st = check_dev(A.ctx, x, (size_t)A.nrows * vt, "x")) != MXL_OK) return st;
-        HIP_TRY(launch_jacobi_apply(A.dtype, A.nrows, alpha, L->jac->dinv->p, b, beta, x, A.ctx->stream));
+        if (L->jac->block) HIP_TRY(bj_apply(A.ctx, *L->jac, A.nrows, alpha, b, beta, x, A.ctx->stream));
+        else HIP_TRY(launch_jacobi_apply(A.dtype, A.nrows, alpha, L->jac->dinv->p, b, beta, x, A.ctx->stream));
         return MXL_OK;
     }
     case MXL_OP_SOLVER:
@@ -715,6 +716,7 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
               need(S->partials, (size_t)kRegions * kSolverSlots * 3 * sizeof(double));
     if (ok && kind == MXL_SOLVER_BICGSTAB)
         ok = need(S->rhat, vb) && need(S->v, vb) && need(S->s, vb) && need(S->t, vb) && need(S->z, vb);
+    if (ok && P && P->block) ok = need(S->z, vb);  // z = M r is kept in memory
     S->hist_len = crit.max_iters + 1;
     if (ok) ok = need(S->hist, (size_t)S->hist_len * sizeof(double));
     if (!ok) return hip_fail(hipErrorOutOfMemory, "solver workspace");
@@ -730,6 +732,8 @@ mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *Aop, const mx
     if (kind != MXL_SOLVER_CG && kind != MXL_SOLVER_BICGSTAB)
         return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown solver kind");
     if (Pop && Pop->kind != MXL_OP_JACOBI) return fail(MXL_ERR_NOT_IMPLEMENTED, "only Jacobi preconditioning");
+    if (Pop && Pop->jac->block && kind != MXL_SOLVER_CG)
+        return fail(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi preconditions CG only");
     *Sout = nullptr;
     DeviceScope ds(Aop->mat->ctx->device);
     std::shared_ptr<SolverImpl> S;
@@ -845,6 +849,7 @@ bool single_launch_ok(const SolverImpl &S, const mxl_solve_info *info) {
     const mxl_criteria &c = S.crit;
     if (S.kind != MXL_SOLVER_CG || S.A->dtype != MXL_F64 || c.launch_mode == 1) return false;
     if (S.A->format == MXL_FMT_STENCIL) return false;  // the one-launch path reads CSR arrays
+    if (S.P && S.P->block) return false;                // and point-Jacobi scaling only
     if (c.max_iters < 1 || c.time_limit_s > 0 || S.A->nrows > kSingleMaxN) return false;
     if (info && ((info->history && info->history_cap > 0) || info->time_spmv)) return false;
     return c.launch_mode == 2 || S.A->nrows <= kSingleAutoN;
@@ -887,12 +892,14 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     double *pA = region(S, 0), *pB = region(S, 1), *pC = region(S, 2);
     const int gv = vec_grid(ctx, n), gs = spmv_slots(A);
     double *hist = (double *)S.hist->p;
-    const void *dinv = S.P ? S.P->dinv->p : nullptr;
+    const void *dinv = S.P && S.P->dinv ? S.P->dinv->p : nullptr;
     const mxl_criteria &c = S.crit;
     mxl_status rs;
     HIP_TRY(launch_state_init(st, c.reduction, c.nonfinite_check, s));
     if ((rs = residual(S, b, x)) != MXL_OK) return rs;
-    HIP_TRY(cg_init(ctx, dt, n, b, S.r->p, S.p->p, dinv, pC, s));
+    const bool blockp = S.P && S.P->block;
+    if (blockp) HIP_TRY(bj_cg_init(ctx, *S.P, n, b, S.r->p, S.p->p, pC, s));
+    else HIP_TRY(cg_init(ctx, dt, n, b, S.r->p, S.p->p, dinv, pC, s));
     HIP_TRY(launch_finalize(3, pC, gv, st, FIN_CG_INIT, 0, 0, hist, s));
     SolverState h;
     if ((rs = read_state(S, h)) != MXL_OK) return rs;
@@ -917,8 +924,13 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
         a.partials = pA;
         HIP_TRY(spmv_launch(A, a, s));
         timer.end(k);
-        HIP_TRY(cg_update(ctx, dt, n, S.r->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
-        HIP_TRY(cg_pupdate(ctx, dt, n, x, S.r->p, S.p->p, dinv, st, pB, gv, (int)k, hist, s));
+        if (blockp) {  // r update fused with z = M r; then p = z + beta p (z passed as "r", no scaling)
+            HIP_TRY(bj_cg_update(ctx, *S.P, n, S.r->p, S.q->p, S.z->p, st, pA, gs, pB, (int)k, s));
+            HIP_TRY(cg_pupdate(ctx, dt, n, x, S.z->p, S.p->p, nullptr, st, pB, gv, (int)k, hist, s));
+        } else {
+            HIP_TRY(cg_update(ctx, dt, n, S.r->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
+            HIP_TRY(cg_pupdate(ctx, dt, n, x, S.r->p, S.p->p, dinv, st, pB, gv, (int)k, hist, s));
+        }
         if (k % c.check_every == 0 || k == c.max_iters) {
             if ((rs = read_state(S, h)) != MXL_OK) return rs;
             if (h.stop) {
@@ -958,7 +970,7 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
     double *pA = region(S, 0), *pB = region(S, 1), *pC = region(S, 2), *pD = region(S, 3);
     const int gv = vec_grid(ctx, n), gs = spmv_slots(A);
     double *hist = (double *)S.hist->p;
-    const void *dinv = S.P ? S.P->dinv->p : nullptr;
+    const void *dinv = S.P && S.P->dinv ? S.P->dinv->p : nullptr;
     const mxl_criteria &c = S.crit;
     const int mi = (int)c.max_iters;
     void *phat = S.z->p;

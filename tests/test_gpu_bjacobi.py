@@ -1,0 +1,126 @@
+"""Block-Jacobi (Sec. 3.2) against the oracle: the GPU's batched
+Gauss-Jordan inverses, condition numbers and storage-precision decisions
+equal the oracle's (the device elimination performs the same operations in
+the same order, without contraction), the product z = M r matches the
+oracle's within FP64 rounding, and block-Jacobi CG reaches the oracle's
+iteration counts, at small sizes and at the full 160^3 anisotropic size."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests._gpu import DEV, dev, matrix
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def mxl():
+    import paper_2006_16852_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mxl):
+    return mxl.Context(0)
+
+
+def _dd(n, density, seed):
+    """A random matrix made diagonally dominant (every block invertible)."""
+    A = W.random_sparse(n, n, density, seed)
+    D = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), A.row_lengths())
+    D[rows, A.col] = A.val
+    D += np.eye(n) * (np.abs(D).sum(axis=1).max() + 1.0)
+    r, c = np.nonzero(D)
+    rp = np.concatenate([[0], np.cumsum(np.bincount(r, minlength=n))]).astype(np.int32)
+    return W.Csr(n, n, rp, c.astype(np.int32), D[r, c], f"dd{n}")
+
+
+MATS = [W.aniso_3d7(10), W.stencil_3d27(7), _dd(100, 0.1, 3), _dd(37, 0.3, 4)]
+
+
+@pytest.mark.parametrize("adaptive", [False, True], ids=["fp64", "adaptive"])
+@pytest.mark.parametrize("bs", [1, 4, 8, 32])
+@pytest.mark.parametrize("A", MATS, ids=[a.name for a in MATS])
+def test_generation_parity(mxl, ctx, A, bs, adaptive):
+    bp = O.uniform_blocks(A.nrows, bs)
+    inv, cond, prec = O.bj_generate(A, bp, adaptive=adaptive, accuracy=0.1)
+    P = mxl.bjacobi(matrix(mxl, ctx, A), block_size=bs, adaptive=adaptive, accuracy=0.1)
+    info = P.info(inverses=True)
+    assert info["nblocks"] == bp.size - 1
+    assert np.array_equal(info["cond"], cond), np.abs(info["cond"] - cond).max()
+    assert np.array_equal(info["precision"], prec)
+    assert np.array_equal(info["inv"], inv), np.abs(info["inv"] - inv).max()
+    sizes = np.diff(bp).astype(np.int64)
+    per = np.where(prec == O.P16, 2, np.where(prec == O.P32, 4, 8))
+    assert info["storage_bytes"] == int(((bs * bs * per + 7) // 8 * 8).sum())
+    # the product z = M r
+    r = W.uniform_vec(A.nrows, 9)
+    want = O.bj_apply(bp, inv, r)
+    absz = O.bj_apply(bp, np.abs(inv), np.abs(r))
+    z = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
+    P.apply(dev(r), z)
+    assert np.all(np.abs(z.cpu().numpy() - want) <= 1e-14 * absz + 1e-300)
+
+
+def test_block_cg_matches_oracle(mxl, ctx):
+    A = W.aniso_3d7(24)
+    b = W.uniform_vec(A.nrows, 4)
+    for bs in (4, 32):
+        bp = O.uniform_blocks(A.nrows, bs)
+        inv, _, _ = O.bj_generate(A, bp, adaptive=True)
+        ref = O.pcg_block(A, b, bp, inv, reduction=1e-10)
+        M = matrix(mxl, ctx, A)
+        S = mxl.solver("cg", M, mxl.bjacobi(M, bs, True), max_iters=2000, reduction=1e-10)
+        x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+        info = S.solve(dev(b), x)
+        assert info["stop_reason"] == mxl.STOP_CONVERGED
+        assert abs(info["iterations"] - ref["iterations"]) <= 2, (bs, info["iterations"], ref["iterations"])
+        res = np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) / np.linalg.norm(b)
+        assert res <= 1.01e-10
+
+
+def test_block_cg_full_size(mxl, ctx):
+    """160^3 anisotropic system, 32-row blocks, adaptive storage: the
+    oracle's stored count and every block in binary16."""
+    g = json.load(open(os.path.join(GOLD, "solver_counts.json")))["aniso7_160_bjacobi32_pcg_1e-10"]
+    A = W.aniso_3d7(160)
+    b = W.uniform_vec(A.nrows, 4)
+    M = matrix(mxl, ctx, A).convert("ell")
+    P = mxl.bjacobi(M, 32, True, 0.1)
+    info = P.info()
+    assert [int((info["precision"] == k).sum()) for k in (0, 1, 2)] == g["precision_counts"]
+    assert abs(info["cond"].max() - g["cond_max"]) <= 1e-12 * g["cond_max"]
+    S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-10, check_every=16)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    out = S.solve(dev(b), x)
+    assert out["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(out["iterations"] - g["iterations"]) <= 2
+    r = dev(b).clone()
+    M.apply(x, r, -1.0, 1.0)
+    assert float(torch.linalg.norm(r)) <= 1.01e-10 * float(np.linalg.norm(b))
+
+
+def test_bjacobi_errors(mxl, ctx):
+    A = matrix(mxl, ctx, W.stencil_2d5(8))
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.bjacobi(A, 3)
+    assert e.value.status == mxl.ERR_INVALID_ARG
+    S2 = W.Csr(2, 2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]), "swap")
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.bjacobi(matrix(mxl, ctx, S2), 1)
+    assert e.value.status == mxl.ERR_ZERO_DIAG
+    mxl.bjacobi(matrix(mxl, ctx, S2), 2)  # the 2x2 block [[0,1],[1,0]] is invertible
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.bjacobi(matrix(mxl, ctx, W.stencil_2d5(8), torch.float32), 4)
+    assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
+    P = mxl.bjacobi(A, 4)
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.solver("bicgstab", A, P)
+    assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
