@@ -105,6 +105,11 @@ def _declare(L):
     L.orc_bj_apply.argtypes = [i64, vp, vp, vp, vp]
     L.orc_pcg_block.restype = C.c_int
     L.orc_pcg_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, _Crit, C.POINTER(_Info), vp]
+    L.orc_gmres.restype = C.c_int
+    L.orc_gmres.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, _Crit, C.POINTER(_Info), vp]
+    L.orc_gmres_block.restype = C.c_int
+    L.orc_gmres_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, i32, _Crit, C.POINTER(_Info),
+                                  vp]
 
 
 def _c(a, dt):
@@ -365,6 +370,35 @@ def pcg_block(A, b, bptr, inv, x0=None, max_iters=10_000, reduction=1e-10, nonfi
     hist = np.full(max_iters + 1, np.nan) if history else None
     lib().orc_pcg_block(A.nrows, _p(rp), _p(col), _p(val), bptr.size - 1, _p(bptr), _p(inv), _p(b),
                         _p(x), _Crit(max_iters, reduction, nonfinite_check), C.byref(info), _p(hist))
+    out = dict(x=x, iterations=info.iterations, spmv_count=info.spmv_count,
+               rel_residual=info.rel_residual, stop_reason=info.stop_reason)
+    if history:
+        out["history"] = hist[:info.iterations + 1]
+    return out
+
+
+def gmres(A, b, x0=None, dinv=None, krylov_dim=100, max_iters=10_000, reduction=1e-10,
+          nonfinite_check=1, history=False, bptr=None, inv=None):
+    """Restarted GMRES(krylov_dim) preconditioned from the right with point
+    Jacobi (``dinv``), block Jacobi (``bptr``/``inv``) or nothing; modified
+    Gram-Schmidt Arnoldi, Givens rotations (Sec. 3.1, Table 2).  The
+    iteration count is the number of Arnoldi steps; ``history`` holds the
+    residual estimates |g| / ||b||."""
+    rp, col, val = _csr(A)
+    b = _c(b, np.float64)
+    x = np.zeros(A.nrows) if x0 is None else _c(x0, np.float64).copy()
+    info = _Info()
+    hist = np.full(max_iters + 1, np.nan) if history else None
+    crit = _Crit(max_iters, reduction, nonfinite_check)
+    if bptr is not None:
+        bptr = _c(bptr, np.int32)
+        inv = _c(inv, np.float64)
+        lib().orc_gmres_block(A.nrows, _p(rp), _p(col), _p(val), bptr.size - 1, _p(bptr), _p(inv),
+                              _p(b), _p(x), int(krylov_dim), crit, C.byref(info), _p(hist))
+    else:
+        d = None if dinv is None else _c(dinv, np.float64)
+        lib().orc_gmres(A.nrows, _p(rp), _p(col), _p(val), _p(d), _p(b), _p(x), int(krylov_dim),
+                        crit, C.byref(info), _p(hist))
     out = dict(x=x, iterations=info.iterations, spmv_count=info.spmv_count,
                rel_residual=info.rel_residual, stop_reason=info.stop_reason)
     if history:

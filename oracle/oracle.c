@@ -450,6 +450,155 @@ done:
     return stop;
 }
 
+/* --------------------------------------------------------------- GMRES */
+
+/* Restarted GMRES(m) (Sec. 3.1 lists GMRES among the Krylov solvers; the
+ * memory-volume model of Table 2 counts one dot and one axpy per basis
+ * vector and step, i.e. modified Gram-Schmidt, and a restart parameter),
+ * preconditioned from the right (x = x0 + M^{-1} V y, so the minimised
+ * residual is the residual of the original system), same criteria as CG.
+ *
+ *   r = b - A x ; beta = ||r||
+ *   cycle: v_0 = r/beta ; g = (beta, 0, ..., 0)
+ *     step j = 0, 1, ...: w = A M^{-1} v_j
+ *       for i = 0..j: h_ij = w.v_i ; w -= h_ij v_i      (modified G-S)
+ *       h_{j+1,j} = ||w||
+ *       apply the rotations G_0..G_{j-1} to column j of H, then the
+ *       rotation G_j that zeroes h_{j+1,j}; g <- G_j g
+ *       |g_{j+1}| is ||b - A x_{j+1}|| ; stop if small (or max_iters)
+ *       v_{j+1} = w / h_{j+1,j}    (before the rotation)
+ *     y = R^{-1} g (back substitution) ; x += M^{-1} (V y)
+ *     restart unless stopped: r = b - A x ; beta = ||r|| ; stop if small.
+ *
+ * The iteration count is the number of Arnoldi steps (products A M^{-1} v).
+ * A zero h_{j+1,j} (happy breakdown) gives g_{j+1} = 0, which meets any
+ * reduction.  history[k] receives the residual estimate |g| / ||b|| after
+ * step k. */
+static int gmres_core(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                      const double *val, const orc_prec *M, const double *b, double *x,
+                      int32_t m, orc_criteria crit, orc_info *info, double *history)
+{
+    memset(info, 0, sizeof(*info));
+    if (m < 1) m = 1;
+    double *V = (double *)malloc((size_t)(m + 1) * (size_t)(n + 1) * sizeof(double));
+    double *H = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double)); /* H[i + (m+1) j] */
+    double *cs = (double *)malloc((size_t)m * sizeof(double));
+    double *sn = (double *)malloc((size_t)m * sizeof(double));
+    double *g = (double *)malloc((size_t)(m + 1) * sizeof(double));
+    double *y = (double *)malloc((size_t)m * sizeof(double));
+    double *r = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    double *z = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    double *w = (double *)malloc((size_t)(n + 1) * sizeof(double));
+#define VV(i) (V + (size_t)(i) * (size_t)(n + 1))
+#define HH(i, j) H[(size_t)(i) + (size_t)(m + 1) * (size_t)(j)]
+    int stop = ORC_RUNNING;
+    int64_t k = 0;
+    double rel = 0.0;
+    const double nb = nrm2(n, b);
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        stop = ORC_CONVERGED;
+        if (history) history[0] = 0.0;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+    orc_csr_spmv(n, row_ptr, col, val, -1.0, x, 1.0, r);
+    info->spmv_count = 1;
+    double beta = nrm2(n, r);
+    rel = beta / nb;
+    if (history) history[0] = rel;
+    if (crit.nonfinite_check && nonfinite(beta)) { stop = ORC_NONFINITE; goto done; }
+    if (beta <= crit.reduction * nb) { stop = ORC_CONVERGED; goto done; }
+    for (;;) {
+        for (int64_t i = 0; i < n; ++i) VV(0)[i] = r[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int j = 0;
+        while (j < m && k < crit.max_iters) {
+            apply_prec(n, M, VV(j), z);
+            orc_csr_spmv(n, row_ptr, col, val, 1.0, z, 0.0, w);
+            info->spmv_count++;
+            for (int i = 0; i <= j; ++i) {
+                const double h = dot(n, w, VV(i));
+                HH(i, j) = h;
+                for (int64_t t = 0; t < n; ++t) w[t] -= h * VV(i)[t];
+            }
+            const double hn = nrm2(n, w);
+            HH(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = HH(i, j), c = HH(i + 1, j);
+                HH(i, j) = cs[i] * a + sn[i] * c;
+                HH(i + 1, j) = -sn[i] * a + cs[i] * c;
+            }
+            const double a = HH(j, j), c = HH(j + 1, j);
+            const double d = hypot(a, c);
+            cs[j] = d == 0.0 ? 1.0 : a / d;
+            sn[j] = d == 0.0 ? 0.0 : c / d;
+            HH(j, j) = d;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++j;
+            ++k;
+            rel = fabs(g[j]) / nb;
+            if (history) history[k] = rel;
+            if (crit.nonfinite_check && (nonfinite(rel) || nonfinite(d))) { stop = ORC_NONFINITE; break; }
+            if (fabs(g[j]) <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
+            if (hn == 0.0 || d == 0.0) { stop = ORC_BREAKDOWN; break; }
+            if (j < m)
+                for (int64_t t = 0; t < n; ++t) VV(j)[t] = w[t] / hn;
+        }
+        if (stop == ORC_NONFINITE) break;
+        /* x += M^{-1} V y with R y = g over the j steps of this cycle */
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < j; ++l) s -= HH(i, l) * y[l];
+            y[i] = s / HH(i, i);
+        }
+        for (int64_t t = 0; t < n; ++t) {
+            double s = 0.0;
+            for (int i = 0; i < j; ++i) s += VV(i)[t] * y[i];
+            w[t] = s;
+        }
+        apply_prec(n, M, w, z);
+        for (int64_t t = 0; t < n; ++t) x[t] += z[t];
+        if (stop != ORC_RUNNING) break;
+        if (k >= crit.max_iters) { stop = ORC_MAX_ITERS; break; }
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+        orc_csr_spmv(n, row_ptr, col, val, -1.0, x, 1.0, r);
+        info->spmv_count++;
+        beta = nrm2(n, r);
+        rel = beta / nb;
+        if (crit.nonfinite_check && nonfinite(beta)) { stop = ORC_NONFINITE; break; }
+        if (beta <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
+    }
+#undef VV
+#undef HH
+done:
+    info->iterations = k;
+    info->rel_residual = rel;
+    info->stop_reason = stop;
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(r); free(z); free(w);
+    return stop;
+}
+
+int orc_gmres(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+              const double *dinv, const double *b, double *x, int32_t krylov_dim,
+              orc_criteria crit, orc_info *info, double *history)
+{
+    orc_prec M = {dinv, 0, NULL, NULL};
+    return gmres_core(n, row_ptr, col, val, &M, b, x, krylov_dim, crit, info, history);
+}
+
+int orc_gmres_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                    int64_t nblocks, const int32_t *bptr, const double *inv, const double *b,
+                    double *x, int32_t krylov_dim, orc_criteria crit, orc_info *info,
+                    double *history)
+{
+    orc_prec M = {NULL, nblocks, bptr, inv};
+    return gmres_core(n, row_ptr, col, val, &M, b, x, krylov_dim, crit, info, history);
+}
+
 /* ------------------------------------------------------ FP32 inner CG */
 
 /* Jacobi-CG whose matrix values and vectors are stored in FP32 (memory

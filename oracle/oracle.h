@@ -1,7 +1,7 @@
 /*
  * oracle.h -- plain, slow, obviously-correct CPU reference for the sparse
  * operator hot path (SpMV in CSR/COO/ELL/HYB, point Jacobi, Jacobi-PCG,
- * Jacobi-BiCGSTAB, FP32-inner iterative refinement, batched Jacobi-PCG,
+ * Jacobi-BiCGSTAB, restarted GMRES, FP32-inner iterative refinement, batched Jacobi-PCG,
  * matrix features and the selector MLP).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
@@ -89,6 +89,16 @@ int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
 int orc_bicgstab(int64_t n, const int32_t *row_ptr, const int32_t *col,
                  const double *val, const double *dinv, const double *b,
                  double *x, orc_criteria crit, orc_info *info, double *history);
+
+/* Restarted right-preconditioned GMRES(krylov_dim), modified Gram-Schmidt
+ * Arnoldi with Givens rotations; dinv == NULL means no preconditioner. */
+int orc_gmres(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+              const double *dinv, const double *b, double *x, int32_t krylov_dim,
+              orc_criteria crit, orc_info *info, double *history);
+int orc_gmres_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                    int64_t nblocks, const int32_t *bptr, const double *inv, const double *b,
+                    double *x, int32_t krylov_dim, orc_criteria crit, orc_info *info,
+                    double *history);
 
 int orc_pcg_f32(int64_t n, const int32_t *row_ptr, const int32_t *col,
                 const float *val, const float *dinv, const float *b, float *x,
