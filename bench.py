@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="stencil27",
-                    choices=["stencil27", "aniso_ir", "poisson2d", "batch", "overhead", "stream", "bicgstab", "stencil_mf"])
+                    choices=["stencil27", "aniso_ir", "poisson2d", "batch", "overhead", "stream", "bicgstab", "stencil_mf",
+                             "gmres"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "

@@ -11,6 +11,9 @@ overhead  : the size-1, b = NaN protocol of the paper's Table 1 (per-iteration c
 stream    : copy / triad / dot bandwidth, the achievable-peak calibration.
 bicgstab  : 128^3 27-point system, Jacobi-BiCGSTAB to 1e-10.
 stencil_mf: the same operator matrix-free: SpMV and Jacobi-PCG to 1e-10.
+gmres     : 128^3 3D convection-diffusion (nonsymmetric), Jacobi-GMRES(100) to
+            1e-10, with the solve's algorithmic GB/s and the GB/s the paper's
+            memory model (Table 2) assigns to the same run.
 
 Each line carries a cpu_baseline: the oracle on a bounded sample of the same
 work (one host core), unless --no-cpu-baseline.
@@ -245,7 +248,8 @@ def overhead(args):
     iters = 1000
     res = {}
     for kind, mode, name in (("cg", 2, "cg_one_workgroup"), ("cg", 1, "cg_per_step_kernels"),
-                             ("bicgstab", 1, "bicgstab_per_step_kernels")):
+                             ("bicgstab", 1, "bicgstab_per_step_kernels"),
+                             ("gmres", 1, "gmres100_per_step_kernels")):
         S = mxl.solver(kind, M, None, max_iters=iters, nonfinite_check=0, check_every=iters,
                        launch_mode=mode)
 
@@ -259,7 +263,7 @@ def overhead(args):
            "unit": "us/iteration", "value": res["cg_one_workgroup"], "higher_is_better": False,
            "n_gpus": 1, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "n=1 nan-rhs protocol"}, "runs": res,
-           "paper_table1_us": {"CG": 1.28, "BiCGSTAB": 1.26}}
+           "paper_table1_us": {"CG": 1.28, "BiCGSTAB": 1.26, "GMRES": 1.51}}
     if not args.no_cpu_baseline:
         import workloads as W
         O = _oracle()
@@ -271,6 +275,99 @@ def overhead(args):
         dt = (time.perf_counter() - t0) / reps
         out["cpu_baseline"] = {"value": round(dt * 1e6 / iters, 4), "unit": "us/iteration", "cores": 1,
                                "kind": "oracle", "sample": f"{reps} solves of {iters} iterations"}
+    print(json.dumps(out), flush=True)
+
+
+def gmres_table2_bytes(n, nnz, iters, k, VT=8, IT=4):
+    """Read + write volume of a GMRES(k) run by the paper's memory model
+    (Table 2), r = iters mod k and the triangular inner-step count
+    iter_r = floor(iters/k) (k-1) k / 2 + (r-1) r / 2."""
+    r = iters % k
+    q = iters // k
+    iter_r = q * (k - 1) * k / 2 + (r - 1) * r / 2
+    rd = ((11 * n + 2 * nnz + 2.5 * r + n * r + r * r / 2 + 1) * VT + 2 * nnz * IT
+          + q * ((1 + 2.5 * k + 10 * n + 2 * nnz + k * k / 2 + k * n) * VT + 2 * nnz * IT)
+          + iters * ((7 * n + 5 + 2 * nnz) * VT + 2 * nnz * IT + 8) + iter_r * ((4 * n + 4) * VT))
+    wr = ((6 * n + r + 2 * k + 3) * VT + 8 + q * ((k + 6 * n + 2) * VT + 8)
+          + iters * ((4 * n + 8) * VT + 8) + iter_r * ((n + 2) * VT))
+    return rd + wr
+
+
+def gmres_alg_bytes(n, spmv, iters, k, restarts):
+    """Algorithmic bytes of this implementation's GMRES(k) run without second
+    Gram-Schmidt passes: step j moves the SpMV plus (2 (j+1) + 6) n values
+    (multi-dot over j+1 basis vectors and u; update over the same, u, dinv,
+    writes of V_{j+1} and z); a cycle of J steps closes with (J + 3) n
+    (combination, x read/write, dinv); the start and every restart move a
+    residual SpMV and 6 n (b copy, norm, z)."""
+    total = 0.0
+    left = iters
+    for _ in range(restarts + 1):
+        J = min(k, left)
+        left -= J
+        total += J * spmv + sum((2 * (j + 1) + 6) * n * 8 for j in range(J))
+        total += (J + 3) * n * 8 + spmv + 6 * n * 8
+    return total
+
+
+def gmres(args):
+    """Jacobi-GMRES(100) on the 128^3 3D convection-diffusion system to 1e-10
+    (ELL with 16-bit column offsets)."""
+    import numpy as np
+    import torch
+    import paper_2006_16852_amd as mxl
+    import workloads as W
+    dev = "cuda:0"
+    N = 128
+    A = W.convdiff_3d7(N)
+    n = A.nrows
+    ctx = mxl.Context(0)
+    base = mxl.csr(ctx, torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                   torch.from_numpy(A.val).to(dev))
+    b = torch.from_numpy(W.uniform_vec(n, 5)).to(dev)
+    M = base.convert("ell", variant=mxl.ELL_DELTA16)
+    d = M.describe()
+    spmv = n * d["ell_width"] * (8 + 2) + 2 * n * 8
+    k = 100
+    S = mxl.solver("gmres", M, mxl.jacobi(M), krylov_dim=k, max_iters=5000, reduction=1e-10, check_every=25)
+    x = torch.zeros_like(b)
+
+    def f():
+        x.zero_()
+        return S.solve(b, x)
+    dt, info = _timed(f, args.steps, args.warmup)
+    r = b.clone()
+    base.apply(x, r, -1.0, 1.0)
+    its = info["iterations"]
+    alg = gmres_alg_bytes(n, spmv, its, k, info["restarts"])
+    t2 = gmres_table2_bytes(n, A.nnz, its, k)
+    out = {"metric": "GMRES(100) time-to-1e-10 residual", "unit": "ms", "value": round(dt * 1e3, 3),
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "convdiff3d7_128^3 jacobi-gmres(100) to 1e-10", "n": n, "nnz": A.nnz,
+                      "operator": "ell16", "krylov_dim": k},
+           "iterations": its, "restarts": info["restarts"], "second_passes": info["reorth"],
+           "stop": info["stop"], "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b)),
+           "alg_GB": round(alg / 1e9, 3), "alg_GBs": round(alg / dt / 1e9, 1),
+           "table2_model_GB": round(t2 / 1e9, 3), "table2_model_GBs": round(t2 / dt / 1e9, 1),
+           "us_per_iteration": round(dt * 1e6 / max(its, 1), 2),
+           "steps": args.steps, "warmup": args.warmup}
+    if not args.no_cpu_baseline:
+        O = _oracle()
+        dh, _ = O.jacobi_dinv(A)
+        kk = 20
+        bh = b.cpu().numpy()
+        t0 = time.perf_counter()
+        O.gmres(A, bh, dinv=dh, krylov_dim=k, max_iters=kk, reduction=0.0)
+        first = time.perf_counter() - t0
+        # step j of a cycle costs about (j + 1) basis passes: scale the first
+        # kk steps' time by the ratio of the full run's basis work
+        def work(m):
+            return sum(j + 2 for j in range(m))
+        full = sum(work(min(k, its - c * k)) for c in range(info["restarts"] + 1))
+        est = first * full / work(kk)
+        out["cpu_baseline"] = {"value": round(est * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {kk} Jacobi-GMRES(100) steps ({first:.2f} s), scaled by "
+                                         f"the basis work of the {its} steps to 1e-10"}
     print(json.dumps(out), flush=True)
 
 
@@ -409,4 +506,4 @@ def stencil_mf(args):
 
 def run(args):
     {"aniso_ir": aniso_ir, "poisson2d": poisson2d, "batch": batch, "overhead": overhead,
-     "stream": stream, "bicgstab": bicgstab, "stencil_mf": stencil_mf}[args.workload](args)
+     "stream": stream, "bicgstab": bicgstab, "stencil_mf": stencil_mf, "gmres": gmres}[args.workload](args)

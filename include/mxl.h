@@ -79,7 +79,8 @@ typedef struct {
 
 typedef enum { MXL_OP_MATRIX = 0, MXL_OP_JACOBI = 1, MXL_OP_SOLVER = 2, MXL_OP_BATCH = 3 } mxl_op_kind;
 
-typedef enum { MXL_SOLVER_CG = 0, MXL_SOLVER_BICGSTAB = 1, MXL_SOLVER_IR = 2 } mxl_solver_kind;
+typedef enum { MXL_SOLVER_CG = 0, MXL_SOLVER_BICGSTAB = 1, MXL_SOLVER_IR = 2,
+               MXL_SOLVER_GMRES = 3 } mxl_solver_kind;
 
 /* Stop reasons: the stopping_status of Sec. 2.5. */
 typedef enum {
@@ -124,6 +125,8 @@ typedef struct {
                                Krylov loop with HIP events (first 4096) */
     double  spmv_ms;        /* out: summed SpMV time of the timed launches */
     int64_t spmv_timed;     /* out: number of timed launches */
+    int64_t restarts;       /* out, GMRES: restarted cycles */
+    int64_t reorth;         /* out, GMRES: steps that took a second Gram-Schmidt pass */
 } mxl_solve_info;
 
 typedef struct mxl_ctx mxl_ctx;
@@ -239,7 +242,7 @@ mxl_status mxl_jacobi_generate(const mxl_op *A, mxl_op **P);
  * every nonzero entry lies in that format's normal range (memory precision
  * decoupled from the FP64 arithmetic); otherwise binary64.  accuracy 0
  * means 0.1.  mxl_apply computes z = M r in FP64 from the stored entries.
- * It preconditions the CG solver (per-kernel path).  block_size in
+ * It preconditions CG (per-kernel path) and GMRES.  block_size in
  * {1, 2, 4, 8, 16, 32}.  Errors: INVALID_ARG, NOT_IMPLEMENTED (non-square,
  * FP32 or matrix-free operator), ZERO_DIAG (a singular diagonal block),
  * OUT_OF_MEMORY, DEVICE. */
@@ -256,10 +259,28 @@ mxl_status mxl_bjacobi_info(const mxl_op *P, int64_t *nblocks, double *cond,
 
 /* Solver factory .generate(A) (Sec. 2.2.3, Sec. 3.1): Krylov solver bound to
  * A with optional preconditioner P (NULL = none).  The solver keeps shared
- * references to A and P and owns its work vectors. */
+ * references to A and P and owns its work vectors.  MXL_SOLVER_GMRES is
+ * GMRES(100), the restart the paper's solver study uses (Sec. 7.4). */
 mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *A,
                                const mxl_op *P, const mxl_criteria *crit,
                                mxl_op **S);
+
+/* Restarted GMRES(krylov_dim) (Sec. 3.1; memory model and restart of
+ * Table 2), preconditioned from the right by P (point or block Jacobi, or
+ * NULL): x = x0 + M^{-1} V y minimises ||b - A x|| over the cycle's Krylov
+ * space, so the criterion is checked on the residual of A x = b itself
+ * (the Givens estimate inside a cycle, the recomputed b - A x at each
+ * restart).  One iteration = one Arnoldi step (one product with A);
+ * info->restarts counts restarted cycles, info->spmv_count = 1 + iterations
+ * + restarts.  The basis is orthogonalised by classical Gram-Schmidt with a
+ * second pass when the first one cancels more than half of ||w||^2
+ * (info->reorth counts those steps).  Memory: (krylov_dim + 1) basis
+ * vectors of n doubles plus O(krylov_dim^2).  A FP64, krylov_dim in
+ * [1, 1024].  Errors: INVALID_ARG, NOT_IMPLEMENTED (FP32 operator, non-Jacobi
+ * P), DTYPE / DIM_MISMATCH (P does not conform), OUT_OF_MEMORY. */
+mxl_status mxl_gmres_generate(const mxl_op *A, const mxl_op *P,
+                              const mxl_criteria *crit, int32_t krylov_dim,
+                              mxl_op **S);
 
 /* Solve A x = b; x holds the initial guess on entry and the solution on exit
  * (Sec. 2.1).  Blocks until a criterion stops the iteration.  Not reaching

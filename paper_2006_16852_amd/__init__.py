@@ -24,7 +24,7 @@ CSR_SCALAR, CSR_VECTOR, CSR_MERGE, CSR_STREAM = 0, 1, 2, 3
 COO_SEGRED = 0
 ELL_PLAIN, ELL_LDS, ELL_DELTA16 = 0, 1, 2
 OP_MATRIX, OP_JACOBI, OP_SOLVER, OP_BATCH = 0, 1, 2, 3
-SOLVER_CG, SOLVER_BICGSTAB, SOLVER_IR = 0, 1, 2
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_IR, SOLVER_GMRES = 0, 1, 2, 3
 STOP_NONE, STOP_CONVERGED, STOP_MAX_ITERS, STOP_TIME, STOP_BREAKDOWN, STOP_NONFINITE = range(6)
 OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_DTYPE, ERR_NOT_IMPLEMENTED, ERR_INVALID_MATRIX, \
     ERR_ZERO_DIAG, ERR_OUT_OF_MEMORY, ERR_INFEASIBLE_FORMAT, ERR_DEVICE = range(10)
@@ -54,7 +54,8 @@ class SolveInfo(C.Structure):
                 ("rel_residual", C.c_double), ("stop_reason", C.c_int32),
                 ("seconds", C.c_double), ("history", C.POINTER(C.c_double)),
                 ("history_cap", C.c_int64), ("inner_iterations", C.c_int64),
-                ("time_spmv", C.c_int32), ("spmv_ms", C.c_double), ("spmv_timed", C.c_int64)]
+                ("time_spmv", C.c_int32), ("spmv_ms", C.c_double), ("spmv_timed", C.c_int64),
+                ("restarts", C.c_int64), ("reorth", C.c_int64)]
 
 
 class FormatParams(C.Structure):
@@ -111,6 +112,7 @@ def _load():
         "mxl_op_destroy": [vp],
         "mxl_jacobi_generate": [vp, pp],
         "mxl_solver_generate": [C.c_int, vp, vp, C.POINTER(Criteria), pp],
+        "mxl_gmres_generate": [vp, vp, C.POINTER(Criteria), C.c_int32, pp],
         "mxl_solve": [vp, vp, vp, C.POINTER(SolveInfo)],
         "mxl_ir_generate": [vp, C.POINTER(IrParams), pp],
         "mxl_batch_csr_create": [vp, i64, vp, vp, vp, vp, vp, C.c_int, pp],
@@ -406,19 +408,24 @@ class Solver(Op):
                    rel_residual=info.rel_residual, stop_reason=info.stop_reason,
                    stop=STOP_NAMES[info.stop_reason], seconds=info.seconds,
                    inner_iterations=info.inner_iterations, spmv_ms=info.spmv_ms,
-                   spmv_timed=info.spmv_timed)
+                   spmv_timed=info.spmv_timed, restarts=info.restarts, reorth=info.reorth)
         if history:
             cnt = min(history, (info.iterations + 1))
             out["history"] = list(hbuf[:cnt])
         return out
 
 
-def solver(kind: str, A: Op, P: Op = None, **crit) -> Solver:
-    k = {"cg": SOLVER_CG, "bicgstab": SOLVER_BICGSTAB}[kind]
+def solver(kind: str, A: Op, P: Op = None, krylov_dim: int = None, **crit) -> Solver:
+    """kind: "cg", "bicgstab" or "gmres" (GMRES(krylov_dim), default 100)."""
+    k = {"cg": SOLVER_CG, "bicgstab": SOLVER_BICGSTAB, "gmres": SOLVER_GMRES}[kind]
     c = criteria(**crit)
     h = C.c_void_p()
     A.ctx.use_current_stream()
-    _check(lib.mxl_solver_generate(k, A.h, P.h if P is not None else None, C.byref(c), C.byref(h)))
+    Ph = P.h if P is not None else None
+    if kind == "gmres" and krylov_dim is not None:
+        _check(lib.mxl_gmres_generate(A.h, Ph, C.byref(c), int(krylov_dim), C.byref(h)))
+    else:
+        _check(lib.mxl_solver_generate(k, A.h, Ph, C.byref(c), C.byref(h)))
     return Solver(h, A.ctx, parents=(A,) + ((P,) if P is not None else ()))
 
 

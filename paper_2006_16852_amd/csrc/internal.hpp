@@ -132,6 +132,11 @@ struct SolverImpl {
     std::shared_ptr<IrImpl> ir;  // iterative refinement only
     std::shared_ptr<BatchImpl> single;  // one-launch CG of a small system
     BufPtr single_out;                  // iterations, residual, status
+    // GMRES(krylov): basis V (krylov+1 vectors of ld doubles), workspace,
+    // multi-dot and norm partials
+    int krylov = 0;
+    int64_t ld = 0;
+    BufPtr V, gmws, gdots, gnorm;
 };
 
 struct IrImpl {
@@ -232,6 +237,21 @@ hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, void
                         hipStream_t s);
 hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
                     double beta, void *z, hipStream_t s);
+
+// ------------------------------------------------------------- gmres.hip
+constexpr int kGmMaxKrylov = 1024;
+size_t gm_ws_bytes(int m);
+int gm_grid(int64_t n);
+hipError_t gm_prep(const mxl_ctx *ctx, int64_t n, const double *v, const double *b, const double *dinv,
+                   double *z, double *parts, int *slots, hipStream_t s);
+hipError_t gm_start(const double *parts, int slots, SolverState *st, void *ws, int m, double *hist, int first,
+                    hipStream_t s);
+hipError_t gm_step(int64_t n, int64_t ld, double *V, int j, const double *u, const double *dinv, double *z,
+                   double *dparts, double *nparts, SolverState *st, void *ws, int m, double *hist,
+                   hipStream_t s);
+hipError_t gm_close(int64_t n, int64_t ld, const double *V, const double *dinv, double *x, double *t,
+                    const SolverState *st, void *ws, int m, hipStream_t s);
+hipError_t gm_read(const void *ws, int64_t *reorth, hipStream_t s);
 
 // ------------------------------------------------------------- runtime.hip
 mxl_status set_error(mxl_status st, const std::string &msg);

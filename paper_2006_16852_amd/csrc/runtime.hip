@@ -691,7 +691,7 @@ mxl_status mxl_jacobi_generate(const mxl_op *Aop, mxl_op **P) {
 
 static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
                               const std::shared_ptr<JacobiImpl> &P, const mxl_criteria &crit,
-                              std::shared_ptr<SolverImpl> &out) {
+                              std::shared_ptr<SolverImpl> &out, int krylov = 0) {
     if (crit.max_iters < 0) return fail(MXL_ERR_INVALID_ARG, "max_iters < 0");
     if (crit.max_iters >= INT_MAX) return fail(MXL_ERR_INVALID_ARG, "max_iters too large");
     if (!(crit.reduction >= 0.0)) return fail(MXL_ERR_INVALID_ARG, "reduction must be >= 0");
@@ -717,6 +717,18 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
     if (ok && kind == MXL_SOLVER_BICGSTAB)
         ok = need(S->rhat, vb) && need(S->v, vb) && need(S->s, vb) && need(S->t, vb) && need(S->z, vb);
     if (ok && P && P->block) ok = need(S->z, vb);  // z = M r is kept in memory
+    if (ok && kind == MXL_SOLVER_GMRES) {
+        // basis of krylov+1 vectors (ld rounded to 64 rows), z = M^{-1} v,
+        // multi-dot partials, norm partials, Hessenberg/rotation workspace
+        S->krylov = krylov;
+        S->ld = (A->nrows + 63) / 64 * 64;
+        const int G = gm_grid(A->nrows);
+        ok = need(S->V, (size_t)(krylov + 1) * (size_t)S->ld * sizeof(double)) &&
+             need(S->gmws, gm_ws_bytes(krylov)) &&
+             need(S->gdots, (size_t)(krylov + 2) * (size_t)G * sizeof(double)) &&
+             need(S->gnorm, (size_t)std::max(G, 2 * kMaxGrid) * sizeof(double)) &&
+             (!P || need(S->z, vb));
+    }
     S->hist_len = crit.max_iters + 1;
     if (ok) ok = need(S->hist, (size_t)S->hist_len * sizeof(double));
     if (!ok) return hip_fail(hipErrorOutOfMemory, "solver workspace");
@@ -729,15 +741,29 @@ mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *Aop, const mx
                                const mxl_criteria *crit, mxl_op **Sout) {
     if (!Aop || !Sout || !crit || Aop->kind != MXL_OP_MATRIX)
         return fail(MXL_ERR_INVALID_ARG, "matrix operator and criteria required");
-    if (kind != MXL_SOLVER_CG && kind != MXL_SOLVER_BICGSTAB)
+    if (kind != MXL_SOLVER_CG && kind != MXL_SOLVER_BICGSTAB && kind != MXL_SOLVER_GMRES)
         return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown solver kind");
+    return mxl_gmres_generate(Aop, Pop, crit, kind == MXL_SOLVER_GMRES ? 100 : -(int)kind - 1, Sout);
+}
+
+// kdim >= 1: GMRES(kdim); kdim = -kind-1 routes the other Krylov kinds here.
+mxl_status mxl_gmres_generate(const mxl_op *Aop, const mxl_op *Pop, const mxl_criteria *crit, int32_t kdim,
+                              mxl_op **Sout) {
+    if (!Aop || !Sout || !crit || Aop->kind != MXL_OP_MATRIX)
+        return fail(MXL_ERR_INVALID_ARG, "matrix operator and criteria required");
+    const int kind = kdim < 0 ? -kdim - 1 : MXL_SOLVER_GMRES;
+    if (kind == MXL_SOLVER_GMRES && (kdim < 1 || kdim > kGmMaxKrylov))
+        return fail(MXL_ERR_INVALID_ARG, "krylov_dim must be in [1, 1024]");
+    if (kind == MXL_SOLVER_GMRES && Aop->mat->dtype != MXL_F64)
+        return fail(MXL_ERR_NOT_IMPLEMENTED, "GMRES needs an FP64 operator");
     if (Pop && Pop->kind != MXL_OP_JACOBI) return fail(MXL_ERR_NOT_IMPLEMENTED, "only Jacobi preconditioning");
-    if (Pop && Pop->jac->block && kind != MXL_SOLVER_CG)
-        return fail(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi preconditions CG only");
+    if (Pop && Pop->jac->block && kind == MXL_SOLVER_BICGSTAB)
+        return fail(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi preconditions CG and GMRES");
     *Sout = nullptr;
     DeviceScope ds(Aop->mat->ctx->device);
     std::shared_ptr<SolverImpl> S;
-    mxl_status st = make_solver(kind, Aop->mat, Pop ? Pop->jac : nullptr, *crit, S);
+    mxl_status st = make_solver(kind, Aop->mat, Pop ? Pop->jac : nullptr, *crit, S,
+                                kind == MXL_SOLVER_GMRES ? kdim : 0);
     if (st != MXL_OK) return st;
     auto *op = new mxl_op;
     op->kind = MXL_OP_SOLVER;
@@ -820,6 +846,8 @@ void fill_info(mxl_solve_info *info, const SolverImpl &S, const SolverState &h, 
     info->stop_reason = stop;
     info->seconds = secs;
     info->inner_iterations = 0;
+    info->restarts = 0;
+    info->reorth = 0;
     if (info->history && info->history_cap > 0) {
         int64_t cnt = std::min<int64_t>(iters + 1, std::min<int64_t>(info->history_cap, S.hist_len));
         if (cnt > 0) {
@@ -1038,6 +1066,109 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
     return MXL_OK;
 }
 
+// Restarted GMRES(m): the cycle's steps are enqueued without reading the
+// state (each kernel returns at once after a device-side stop); the host
+// reads it every check_every steps and at the end of every cycle, where it
+// closes the cycle (x update) and restarts from the recomputed residual.
+mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_info *info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const MatrixImpl &A = *S.A;
+    mxl_ctx *ctx = A.ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t n = A.nrows, ld = S.ld;
+    const int m = S.krylov;
+    auto *st = (SolverState *)S.state->p;
+    double *V = (double *)S.V->p, *dp = (double *)S.gdots->p, *np = (double *)S.gnorm->p;
+    void *ws = S.gmws->p;
+    double *x = (double *)xv, *hist = (double *)S.hist->p;
+    const bool blockp = S.P && S.P->block;
+    const double *dinv = S.P && S.P->dinv ? (const double *)S.P->dinv->p : nullptr;
+    double *z = S.P ? (double *)S.z->p : nullptr;
+    const mxl_criteria &c = S.crit;
+    mxl_status rs;
+    // r = b - A x into V_0, ||r||, z = M^{-1} V_0, g = beta e_1, criteria
+    auto restart = [&](int first) -> mxl_status {
+        HIP_TRY(launch_copy(MXL_F64, n, b, V, s));
+        SpmvArgs a;
+        a.alpha = -1.0;
+        a.beta = 1.0;
+        a.x = x;
+        a.y = V;
+        HIP_TRY(spmv_launch(A, a, s));
+        int slots = 0;
+        HIP_TRY(gm_prep(ctx, n, V, first ? (const double *)b : nullptr, blockp ? nullptr : dinv,
+                        blockp ? nullptr : z, np, &slots, s));
+        HIP_TRY(gm_start(np, slots, st, ws, m, hist, first, s));
+        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, V, 0.0, z, s));
+        return MXL_OK;
+    };
+    HIP_TRY(launch_state_init(st, c.reduction, c.nonfinite_check, s));
+    if ((rs = restart(1)) != MXL_OK) return rs;
+    SolverState h;
+    if ((rs = read_state(S, h)) != MXL_OK) return rs;
+    if (h.nb2 == 0.0) {
+        HIP_TRY(launch_fill(MXL_F64, n, 0.0, x, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        fill_info(info, S, h, 0, MXL_STOP_CONVERGED, 1, elapsed_s(t0));
+        return MXL_OK;
+    }
+    int64_t k = 0, restarts = 0;
+    int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
+    while (stop == MXL_STOP_NONE && k < c.max_iters) {
+        const int steps = (int)std::min<int64_t>(m, c.max_iters - k);
+        for (int j = 0; j < steps; ++j) {
+            SpmvArgs a;
+            a.x = z ? (const void *)z : (const void *)(V + (int64_t)j * ld);
+            a.y = S.q->p;
+            a.stop = &st->stop;
+            HIP_TRY(spmv_launch(A, a, s));
+            HIP_TRY(gm_step(n, ld, V, j, (const double *)S.q->p, blockp ? nullptr : dinv, blockp ? nullptr : z,
+                            dp, np, st, ws, m, hist, s));
+            if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, V + (int64_t)(j + 1) * ld, 0.0, z, s));
+            ++k;
+            if (k % c.check_every == 0) {
+                if ((rs = read_state(S, h)) != MXL_OK) return rs;
+                if (h.stop) break;
+                if (c.time_limit_s > 0 && elapsed_s(t0) >= c.time_limit_s) {
+                    stop = MXL_STOP_TIME;
+                    break;
+                }
+            }
+        }
+        HIP_TRY(gm_close(n, ld, V, blockp ? nullptr : dinv, x, blockp ? (double *)S.r->p : nullptr, st, ws, m, s));
+        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.r->p, 1.0, x, s));
+        if ((rs = read_state(S, h)) != MXL_OK) return rs;
+        if (h.stop) {
+            stop = map_stop(h.stop);
+            break;
+        }
+        if (stop != MXL_STOP_NONE || k >= c.max_iters) break;
+        if ((rs = restart(0)) != MXL_OK) return rs;
+        ++restarts;
+        if ((rs = read_state(S, h)) != MXL_OK) return rs;
+        if (h.stop) stop = map_stop(h.stop);
+    }
+    if ((rs = read_state(S, h)) != MXL_OK) return rs;
+    if (stop == MXL_STOP_NONE && h.stop) stop = map_stop(h.stop);
+    int64_t iters;
+    if (stop == MXL_STOP_NONE) {
+        stop = MXL_STOP_MAX_ITERS;
+        iters = k;
+    } else if (stop == MXL_STOP_TIME) {
+        iters = k;
+    } else {
+        iters = h.iters;
+    }
+    fill_info(info, S, h, iters, stop, 1 + iters + restarts, elapsed_s(t0));
+    if (info) {
+        int64_t re = 0;
+        HIP_TRY(gm_read(ws, &re, s));
+        info->restarts = restarts;
+        info->reorth = re;
+    }
+    return MXL_OK;
+}
+
 }  // namespace
 
 // Mixed-precision iterative refinement: an FP64 operator, its FP32 value
@@ -1172,6 +1303,7 @@ extern "C" mxl_status mxl_solve(const mxl_op *Sop, const void *b, void *x, mxl_s
     if (S.kind == MXL_SOLVER_CG) return solve_cg(S, b, x, info);
     if (S.kind == MXL_SOLVER_BICGSTAB) return solve_bicgstab(S, b, x, info);
     if (S.kind == MXL_SOLVER_IR) return solve_ir(S, b, x, info);
+    if (S.kind == MXL_SOLVER_GMRES) return solve_gmres(S, b, x, info);
     return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown solver kind");
 }
 

@@ -5,6 +5,7 @@ compare the HIP solvers' counts against these stored values because the
 oracle needs minutes at these sizes.  Run from the repository root:
     python tests/golden/make_golden.py            # everything
     python tests/golden/make_golden.py bjacobi    # only the block-Jacobi entry
+    python tests/golden/make_golden.py gmres      # only the GMRES entry
 """
 import json
 import os
@@ -34,12 +35,29 @@ def bjacobi(out):
     print("bjacobi", r["iterations"], time.time() - t, flush=True)
 
 
+def gmres(out):
+    """Jacobi-GMRES(100) on the 128^3 convection-diffusion system."""
+    A = W.convdiff_3d7(128)
+    b = W.uniform_vec(A.nrows, 5)
+    t = time.time()
+    d, _ = O.jacobi_dinv(A)
+    r = O.gmres(A, b, dinv=d, krylov_dim=100, reduction=1e-10, max_iters=5000)
+    out["convdiff3d7_128_gmres100_jacobi_1e-10"] = dict(
+        recipe="peclet (0.5, 0.25, 0.125); b = U[-1,1) seed 5, x0 = 0",
+        iterations=r["iterations"], spmv_count=r["spmv_count"], stop=r["stop_reason"],
+        rel_residual=r["rel_residual"])
+    print("gmres", r["iterations"], time.time() - t, flush=True)
+
+
+ONLY = {"bjacobi": bjacobi, "gmres": gmres}
+
+
 def main():
     O.build(force=False)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "solver_counts.json")
-    if sys.argv[1:] == ["bjacobi"]:
+    if len(sys.argv) == 2 and sys.argv[1] in ONLY:
         out = json.load(open(path))
-        bjacobi(out)
+        ONLY[sys.argv[1]](out)
         json.dump(out, open(path, "w"), indent=1)
         print("wrote", path)
         return
@@ -71,6 +89,7 @@ def main():
                                                  stop=r["stop_reason"], history=list(r["history"]))
     print("ir", r["outer"], r["inner_iterations"], time.time() - t, flush=True)
     bjacobi(out)
+    gmres(out)
     json.dump(out, open(path, "w"), indent=1)
     print("wrote", path)
 

@@ -203,6 +203,22 @@ def points_convdiff(peclet: float = 0.5):
             [-1.0, -1.0 - peclet, 4.0 + peclet, -1.0, -1.0])
 
 
+def points_convdiff3d(peclet=(0.5, 0.25, 0.125)):
+    """3D 7-point convection-diffusion: diffusion 6 / -1 plus first-order
+    upwind convection with cell Peclet numbers (px, py, pz) along +i, +j,
+    +k (adds p_d to the diagonal and -p_d to the upwind neighbour).
+    Nonsymmetric, diagonally dominant."""
+    px, py, pz = peclet
+    pts = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    return pts, [-1.0 - pz, -1.0 - py, -1.0 - px, 6.0 + px + py + pz, -1.0, -1.0, -1.0]
+
+
+def convdiff_3d7(N: int, peclet=(0.5, 0.25, 0.125)) -> Csr:
+    """CSR of points_convdiff3d on an N^3 grid."""
+    pts, cf = points_convdiff3d(peclet)
+    return stencil_grid(N, N, N, pts, cf, f"convdiff3d7_{N}")
+
+
 def uniform_vec(n: int, seed: int, dtype=np.float64) -> np.ndarray:
     """x ~ U[-1, 1) from PCG64(seed)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n).astype(dtype)
