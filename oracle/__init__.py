@@ -108,6 +108,13 @@ def _declare(L):
     L.orc_gmres.restype = C.c_int
     L.orc_gmres.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, _Crit, C.POINTER(_Info), vp]
     L.orc_gmres_block.restype = C.c_int
+    L.orc_ilu0.restype = i64
+    L.orc_ilu0.argtypes = [i64, vp, vp, vp, vp]
+    L.orc_parilu.restype = i64
+    L.orc_parilu.argtypes = [i64, vp, vp, vp, i32, vp]
+    L.orc_ilu_apply.argtypes = [i64, vp, vp, vp, i32, i32, vp, vp]
+    L.orc_gmres_ilu.restype = C.c_int
+    L.orc_gmres_ilu.argtypes = [i64, vp, vp, vp, vp, i32, i32, vp, vp, i32, _Crit, C.POINTER(_Info), vp]
     L.orc_gmres_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, i32, _Crit, C.POINTER(_Info),
                                   vp]
 
@@ -399,6 +406,54 @@ def gmres(A, b, x0=None, dinv=None, krylov_dim=100, max_iters=10_000, reduction=
         d = None if dinv is None else _c(dinv, np.float64)
         lib().orc_gmres(A.nrows, _p(rp), _p(col), _p(val), _p(d), _p(b), _p(x), int(krylov_dim),
                         crit, C.byref(info), _p(hist))
+    out = dict(x=x, iterations=info.iterations, spmv_count=info.spmv_count,
+               rel_residual=info.rel_residual, stop_reason=info.stop_reason)
+    if history:
+        out["history"] = hist[:info.iterations + 1]
+    return out
+
+
+def ilu0(A):
+    """ILU(0) factors on A's pattern (L strictly lower with unit diagonal,
+    U the rest) by row-wise elimination; returns (lu, bad_row), bad_row = -1
+    on success."""
+    rp, col, val = _csr(A)
+    lu = np.zeros(A.nnz)
+    bad = lib().orc_ilu0(A.nrows, _p(rp), _p(col), _p(val), _p(lu))
+    return lu, int(bad)
+
+
+def parilu(A, sweeps):
+    """ParILU factors after `sweeps` synchronous fixed-point sweeps."""
+    rp, col, val = _csr(A)
+    lu = np.zeros(A.nnz)
+    bad = lib().orc_parilu(A.nrows, _p(rp), _p(col), _p(val), int(sweeps), _p(lu))
+    return lu, int(bad)
+
+
+def ilu_apply(A, lu, r, mode=0, sweeps=0):
+    """z = U^{-1} L^{-1} r with the factors on A's pattern; mode 0 exact
+    substitution, 1 `sweeps` Jacobi sweeps per triangular system."""
+    rp, col, _ = _csr(A)
+    lu = _c(lu, np.float64)
+    r = _c(r, np.float64)
+    z = np.zeros(A.nrows)
+    lib().orc_ilu_apply(A.nrows, _p(rp), _p(col), _p(lu), int(mode), int(sweeps), _p(r), _p(z))
+    return z
+
+
+def gmres_ilu(A, b, lu, trs_mode=0, trs_sweeps=0, x0=None, krylov_dim=100, max_iters=10_000,
+              reduction=1e-10, nonfinite_check=1, history=False):
+    """Restarted GMRES right-preconditioned by the incomplete LU factors lu."""
+    rp, col, val = _csr(A)
+    b = _c(b, np.float64)
+    lu = _c(lu, np.float64)
+    x = np.zeros(A.nrows) if x0 is None else _c(x0, np.float64).copy()
+    info = _Info()
+    hist = np.full(max_iters + 1, np.nan) if history else None
+    lib().orc_gmres_ilu(A.nrows, _p(rp), _p(col), _p(val), _p(lu), int(trs_mode), int(trs_sweeps), _p(b),
+                        _p(x), int(krylov_dim), _Crit(max_iters, reduction, nonfinite_check),
+                        C.byref(info), _p(hist))
     out = dict(x=x, iterations=info.iterations, spmv_count=info.spmv_count,
                rel_residual=info.rel_residual, stop_reason=info.stop_reason)
     if history:

@@ -237,21 +237,28 @@ static void prec(int64_t n, const double *dinv, const double *in, double *out)
     for (int64_t i = 0; i < n; ++i) out[i] = dinv ? dinv[i] * in[i] : in[i];
 }
 
-/* A preconditioner z = M^{-1} r: point Jacobi (dinv, or none) or block
- * Jacobi (bptr/inv). */
+/* A preconditioner z = M^{-1} r: point Jacobi (dinv, or none), block
+ * Jacobi (bptr/inv) or incomplete LU (lu on the pattern rp/col, applied by
+ * two triangular solves, exact or trs_sweeps Jacobi sweeps). */
 typedef struct {
     const double *dinv;
     int64_t nblocks;
     const int32_t *bptr;
     const double *inv;
+    const int32_t *rp, *col;
+    const double *lu;
+    int32_t trs_mode, trs_sweeps;
 } orc_prec;
 
 static void orc_bj_apply_impl(int64_t nb, const int32_t *bptr, const double *inv,
                               const double *r, double *z);
+void orc_ilu_apply(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *lu,
+                   int32_t mode, int32_t sweeps, const double *r, double *z);
 
 static void apply_prec(int64_t n, const orc_prec *M, const double *in, double *out)
 {
-    if (M->bptr) orc_bj_apply_impl(M->nblocks, M->bptr, M->inv, in, out);
+    if (M->lu) orc_ilu_apply(n, M->rp, M->col, M->lu, M->trs_mode, M->trs_sweeps, in, out);
+    else if (M->bptr) orc_bj_apply_impl(M->nblocks, M->bptr, M->inv, in, out);
     else prec(n, M->dinv, in, out);
 }
 
@@ -281,7 +288,7 @@ int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
             const double *val, const double *dinv, const double *b, double *x,
             orc_criteria crit, orc_info *info, double *history)
 {
-    orc_prec M = {dinv, 0, NULL, NULL};
+    orc_prec M = {dinv, 0, NULL, NULL, NULL, NULL, NULL, 0, 0};
     return pcg_core(n, row_ptr, col, val, &M, b, x, crit, info, history);
 }
 
@@ -290,7 +297,7 @@ int orc_pcg_block(int64_t n, const int32_t *row_ptr, const int32_t *col,
                   const double *inv, const double *b, double *x,
                   orc_criteria crit, orc_info *info, double *history)
 {
-    orc_prec M = {NULL, nblocks, bptr, inv};
+    orc_prec M = {NULL, nblocks, bptr, inv, NULL, NULL, NULL, 0, 0};
     return pcg_core(n, row_ptr, col, val, &M, b, x, crit, info, history);
 }
 
@@ -586,7 +593,7 @@ int orc_gmres(int64_t n, const int32_t *row_ptr, const int32_t *col, const doubl
               const double *dinv, const double *b, double *x, int32_t krylov_dim,
               orc_criteria crit, orc_info *info, double *history)
 {
-    orc_prec M = {dinv, 0, NULL, NULL};
+    orc_prec M = {dinv, 0, NULL, NULL, NULL, NULL, NULL, 0, 0};
     return gmres_core(n, row_ptr, col, val, &M, b, x, krylov_dim, crit, info, history);
 }
 
@@ -595,7 +602,7 @@ int orc_gmres_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const
                     double *x, int32_t krylov_dim, orc_criteria crit, orc_info *info,
                     double *history)
 {
-    orc_prec M = {NULL, nblocks, bptr, inv};
+    orc_prec M = {NULL, nblocks, bptr, inv, NULL, NULL, NULL, 0, 0};
     return gmres_core(n, row_ptr, col, val, &M, b, x, krylov_dim, crit, info, history);
 }
 
@@ -1122,4 +1129,156 @@ static void orc_bj_apply_impl(int64_t nb, const int32_t *bptr, const double *inv
 void orc_bj_apply(int64_t nb, const int32_t *bptr, const double *inv, const double *r, double *z)
 {
     orc_bj_apply_impl(nb, bptr, inv, r, z);
+}
+
+/* ------------------------------------------------------ incomplete LU */
+
+/* Incomplete LU factors are held in A's CSR pattern: the strictly lower
+ * entries are L (unit diagonal implied), the diagonal and upper entries U
+ * (the ILU-type preconditioners of Sec. 3.2). */
+
+static int64_t find_col(const int32_t *row_ptr, const int32_t *col, int64_t row, int64_t c)
+{
+    int64_t lo = row_ptr[row], hi = row_ptr[row + 1] - 1;
+    while (lo <= hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (col[mid] == c) return mid;
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+static int64_t diag_pos(const int32_t *row_ptr, const int32_t *col, int64_t i)
+{
+    return find_col(row_ptr, col, i, i);
+}
+
+/* ILU(0): the factors with L U = A on A's pattern, by the row-wise
+ * elimination of Saad's book (IKJ order): for each row i and each of its
+ * lower entries k < i in ascending order, a_ik /= u_kk, then
+ * a_ij -= a_ik u_kj for every later entry j of row i that row k also holds.
+ * Returns -1, or the first row whose pivot is missing or zero. */
+int64_t orc_ilu0(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val, double *lu)
+{
+    const int64_t nnz = row_ptr[n];
+    for (int64_t q = 0; q < nnz; ++q) lu[q] = val[q];
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t di = diag_pos(row_ptr, col, i);
+        if (di < 0) return i;
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1] && col[q] < i; ++q) {
+            const int64_t k = col[q];
+            const int64_t dk = diag_pos(row_ptr, col, k);
+            lu[q] = lu[q] / lu[dk];
+            for (int64_t t = q + 1; t < row_ptr[i + 1]; ++t) {
+                const int64_t p = find_col(row_ptr, col, k, col[t]);
+                if (p >= 0) lu[t] = lu[t] - lu[q] * lu[p];
+            }
+        }
+        if (lu[di] == 0.0) return i;
+    }
+    return -1;
+}
+
+/* ParILU (the fine-grained fixed-point ILU the paper cites for its ILU
+ * generation), synchronous form: every entry (i, j) of the pattern is
+ * recomputed from the previous sweep's factors,
+ *   s = a_ij - sum_{k < min(i,j)} l_ik u_kj   (ascending k, pattern entries)
+ *   l_ij = s / u_jj (i > j),  u_ij = s (i <= j),
+ * starting from l_ij = a_ij / a_jj and u_ij = a_ij.  The fixed point is
+ * ILU(0).  Returns -1, or the first row with a missing or zero diagonal. */
+int64_t orc_parilu(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                   int32_t sweeps, double *lu)
+{
+    const int64_t nnz = row_ptr[n];
+    int64_t *dg = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    double *old = (double *)malloc((size_t)(nnz + 1) * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        dg[i] = diag_pos(row_ptr, col, i);
+        if (dg[i] < 0 || val[dg[i]] == 0.0) {
+            free(dg);
+            free(old);
+            return i;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
+            lu[q] = col[q] < i ? val[q] / val[dg[col[q]]] : val[q];
+    for (int32_t sw = 0; sw < sweeps; ++sw) {
+        for (int64_t q = 0; q < nnz; ++q) old[q] = lu[q];
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+                const int64_t j = col[q];
+                const int64_t m = i < j ? i : j;
+                double s = val[q];
+                for (int64_t t = row_ptr[i]; t < row_ptr[i + 1] && col[t] < m; ++t) {
+                    const int64_t p = find_col(row_ptr, col, col[t], j);
+                    if (p >= 0) s = s - old[t] * old[p];
+                }
+                lu[q] = i > j ? s / old[dg[j]] : s;
+            }
+    }
+    free(dg);
+    free(old);
+    return -1;
+}
+
+/* Triangular solves with the factors in lu.  mode 0: exact forward and
+ * backward substitution (ascending column order inside each row sum);
+ * mode 1: `sweeps` Jacobi sweeps on each triangular system from
+ * y = r (unit L) and z = y / u_ii (U):
+ *   y_i <- r_i - sum_{k<i} l_ik y_k,   z_i <- (y_i - sum_{k>i} u_ik z_k) / u_ii
+ * each sweep using only the previous sweep's vector.  z = U^{-1} L^{-1} r. */
+void orc_ilu_apply(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *lu,
+                   int32_t mode, int32_t sweeps, const double *r, double *z)
+{
+    double *y = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    double *t = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    if (mode == 0) {
+        for (int64_t i = 0; i < n; ++i) {
+            double s = r[i];
+            for (int64_t q = row_ptr[i]; q < row_ptr[i + 1] && col[q] < i; ++q) s -= lu[q] * y[col[q]];
+            y[i] = s;
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = y[i], d = 0.0;
+            for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+                if (col[q] > i) s -= lu[q] * z[col[q]];
+                else if (col[q] == i) d = lu[q];
+            }
+            z[i] = s / d;
+        }
+    } else {
+        for (int64_t i = 0; i < n; ++i) y[i] = r[i];
+        for (int32_t sw = 0; sw < sweeps; ++sw) {
+            for (int64_t i = 0; i < n; ++i) {
+                double s = r[i];
+                for (int64_t q = row_ptr[i]; q < row_ptr[i + 1] && col[q] < i; ++q) s -= lu[q] * y[col[q]];
+                t[i] = s;
+            }
+            for (int64_t i = 0; i < n; ++i) y[i] = t[i];
+        }
+        for (int64_t i = 0; i < n; ++i) z[i] = y[i] / lu[diag_pos(row_ptr, col, i)];
+        for (int32_t sw = 0; sw < sweeps; ++sw) {
+            for (int64_t i = 0; i < n; ++i) {
+                double s = y[i], d = 0.0;
+                for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+                    if (col[q] > i) s -= lu[q] * z[col[q]];
+                    else if (col[q] == i) d = lu[q];
+                }
+                t[i] = s / d;
+            }
+            for (int64_t i = 0; i < n; ++i) z[i] = t[i];
+        }
+    }
+    free(y);
+    free(t);
+}
+
+int orc_gmres_ilu(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                  const double *lu, int32_t trs_mode, int32_t trs_sweeps, const double *b,
+                  double *x, int32_t krylov_dim, orc_criteria crit, orc_info *info, double *history)
+{
+    orc_prec M = {NULL, 0, NULL, NULL, row_ptr, col, lu, trs_mode, trs_sweeps};
+    return gmres_core(n, row_ptr, col, val, &M, b, x, krylov_dim, crit, info, history);
 }

@@ -1,7 +1,8 @@
 /*
  * oracle.h -- plain, slow, obviously-correct CPU reference for the sparse
  * operator hot path (SpMV in CSR/COO/ELL/HYB, point Jacobi, Jacobi-PCG,
- * Jacobi-BiCGSTAB, restarted GMRES, FP32-inner iterative refinement, batched Jacobi-PCG,
+ * Jacobi-BiCGSTAB, restarted GMRES, incomplete LU (ILU(0), ParILU,
+ * triangular solves), FP32-inner iterative refinement, batched Jacobi-PCG,
  * matrix features and the selector MLP).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
@@ -138,6 +139,19 @@ void    orc_bj_apply(int64_t nblocks, const int32_t *bptr, const double *inv, co
 int     orc_pcg_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                       int64_t nblocks, const int32_t *bptr, const double *inv, const double *b,
                       double *x, orc_criteria crit, orc_info *info, double *history);
+
+/* Incomplete LU on A's pattern (strict lower = L with unit diagonal, the
+ * rest = U): exact ILU(0), ParILU synchronous sweeps, the two triangular
+ * solves (mode 0 exact, 1 Jacobi sweeps) and right-preconditioned GMRES
+ * with it. */
+int64_t orc_ilu0(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val, double *lu);
+int64_t orc_parilu(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                   int32_t sweeps, double *lu);
+void orc_ilu_apply(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *lu,
+                   int32_t mode, int32_t sweeps, const double *r, double *z);
+int orc_gmres_ilu(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                  const double *lu, int32_t trs_mode, int32_t trs_sweeps, const double *b,
+                  double *x, int32_t krylov_dim, orc_criteria crit, orc_info *info, double *history);
 
 #ifdef __cplusplus
 }
