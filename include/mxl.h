@@ -77,7 +77,8 @@ typedef struct {
     double  hyb_quantile;  /* HYB: ELL width = nearest-rank quantile of row lengths (0 = 0.9) */
 } mxl_format_params;
 
-typedef enum { MXL_OP_MATRIX = 0, MXL_OP_JACOBI = 1, MXL_OP_SOLVER = 2, MXL_OP_BATCH = 3 } mxl_op_kind;
+typedef enum { MXL_OP_MATRIX = 0, MXL_OP_JACOBI = 1, MXL_OP_SOLVER = 2, MXL_OP_BATCH = 3,
+               MXL_OP_ILU = 4 } mxl_op_kind;
 
 typedef enum { MXL_SOLVER_CG = 0, MXL_SOLVER_BICGSTAB = 1, MXL_SOLVER_IR = 2,
                MXL_SOLVER_GMRES = 3 } mxl_solver_kind;
@@ -257,6 +258,26 @@ mxl_status mxl_bjacobi_generate(const mxl_op *A, int32_t block_size, int32_t ada
 mxl_status mxl_bjacobi_info(const mxl_op *P, int64_t *nblocks, double *cond,
                             int32_t *precision, double *inv, int64_t *storage_bytes);
 
+/* ILU-type preconditioner (Sec. 3.2): incomplete LU factors of A on A's
+ * own sparsity pattern (L unit lower, U upper; ILU(0) is their fixed point)
+ * generated by `sweeps` synchronous ParILU fixed-point sweeps from
+ * l_ij = a_ij / a_jj, u_ij = a_ij (each sweep recomputes every entry from
+ * the previous sweep's factors: s = a_ij - sum_{k<min(i,j)} l_ik u_kj,
+ * l_ij = s / u_jj or u_ij = s).  mxl_apply(P, r, z) computes
+ * z = U^{-1} L^{-1} r by two triangular solves: trisolve 0 exact
+ * substitution (level-scheduled: one launch per dependency level of each
+ * triangle), 1 iterative, trs_sweeps Jacobi sweeps per triangle from
+ * y = r and z = y / u_ii.  P preconditions GMRES.  A FP64, square, stored
+ * (not matrix-free); P keeps a reference to A.  Errors: INVALID_ARG
+ * (sweeps or trs_sweeps < 0, trisolve not 0/1, empty A), NOT_IMPLEMENTED,
+ * ZERO_DIAG (a missing or zero diagonal entry), OUT_OF_MEMORY, DEVICE. */
+mxl_status mxl_ilu_generate(const mxl_op *A, int32_t sweeps, int32_t trisolve,
+                            int32_t trs_sweeps, mxl_op **P);
+
+/* HOST copies (each may be NULL): the factors in A's CSR order (nnz
+ * doubles) and the number of dependency levels of L and of U (levels[2]). */
+mxl_status mxl_ilu_info(const mxl_op *P, double *lu, int32_t *levels);
+
 /* Solver factory .generate(A) (Sec. 2.2.3, Sec. 3.1): Krylov solver bound to
  * A with optional preconditioner P (NULL = none).  The solver keeps shared
  * references to A and P and owns its work vectors.  MXL_SOLVER_GMRES is
@@ -270,7 +291,8 @@ mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *A,
  * NULL): x = x0 + M^{-1} V y minimises ||b - A x|| over the cycle's Krylov
  * space, so the criterion is checked on the residual of A x = b itself
  * (the Givens estimate inside a cycle, the recomputed b - A x at each
- * restart).  One iteration = one Arnoldi step (one product with A);
+ * restart).  P may also be an ILU operator.  One iteration = one Arnoldi
+ * step (one product with A);
  * info->restarts counts restarted cycles, info->spmv_count = 1 + iterations
  * + restarts.  The basis is orthogonalised by classical Gram-Schmidt with a
  * second pass when the first one cancels more than half of ||w||^2

@@ -23,7 +23,7 @@ CSR, COO, ELL, HYB, STENCIL = 0, 1, 2, 3, 4
 CSR_SCALAR, CSR_VECTOR, CSR_MERGE, CSR_STREAM = 0, 1, 2, 3
 COO_SEGRED = 0
 ELL_PLAIN, ELL_LDS, ELL_DELTA16 = 0, 1, 2
-OP_MATRIX, OP_JACOBI, OP_SOLVER, OP_BATCH = 0, 1, 2, 3
+OP_MATRIX, OP_JACOBI, OP_SOLVER, OP_BATCH, OP_ILU = 0, 1, 2, 3, 4
 SOLVER_CG, SOLVER_BICGSTAB, SOLVER_IR, SOLVER_GMRES = 0, 1, 2, 3
 STOP_NONE, STOP_CONVERGED, STOP_MAX_ITERS, STOP_TIME, STOP_BREAKDOWN, STOP_NONFINITE = range(6)
 OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_DTYPE, ERR_NOT_IMPLEMENTED, ERR_INVALID_MATRIX, \
@@ -134,6 +134,8 @@ def _load():
         "mxl_stencil_create": [vp, C.c_int, i64, i64, i64, i32, vp, vp, pp],
         "mxl_bjacobi_generate": [vp, i32, i32, f64, pp],
         "mxl_bjacobi_info": [vp, C.POINTER(C.c_int64), vp, vp, vp, C.POINTER(C.c_int64)],
+        "mxl_ilu_generate": [vp, i32, i32, i32, pp],
+        "mxl_ilu_info": [vp, vp, vp],
         "mxl_selector_destroy": [vp],
         "mxl_select": [vp, vp, i32, vp, vp, i32, C.POINTER(C.c_int32), vp, vp,
                        C.POINTER(SelectInfo)],
@@ -373,6 +375,32 @@ class BlockJacobi(Op):
         if inverses:
             out["inv"] = inv
         return out
+
+
+class Ilu(Op):
+    """ILU-type preconditioner: ParILU factors on A's pattern, applied by two
+    triangular solves (exact or Jacobi sweeps)."""
+
+    def info(self, factors: bool = False) -> dict:
+        import numpy as np
+        lev = (C.c_int32 * 2)()
+        lu = np.zeros(max(self.describe()["nnz"], 1)) if factors else None
+        _check(lib.mxl_ilu_info(self.h, lu.ctypes.data_as(C.c_void_p) if factors else None,
+                                C.cast(lev, C.c_void_p)))
+        out = dict(levels_lower=lev[0], levels_upper=lev[1])
+        if factors:
+            out["lu"] = lu[:self.describe()["nnz"]]
+        return out
+
+
+def ilu(A: Op, sweeps: int = 5, trisolve: str = "exact", trs_sweeps: int = 0) -> Ilu:
+    """ParILU(sweeps) factors; trisolve "exact" (level-scheduled
+    substitution) or "jacobi" (trs_sweeps Jacobi sweeps per triangle)."""
+    h = C.c_void_p()
+    A.ctx.use_current_stream()
+    mode = {"exact": 0, "jacobi": 1}[trisolve]
+    _check(lib.mxl_ilu_generate(A.h, int(sweeps), mode, int(trs_sweeps), C.byref(h)))
+    return Ilu(h, A.ctx, parents=(A,))
 
 
 def bjacobi(A: Op, block_size: int = 8, adaptive: bool = True, accuracy: float = 0.1) -> BlockJacobi:

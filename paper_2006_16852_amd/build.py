@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libmxl.so")
-SOURCES = ["spmv.hip", "krylov.hip", "batched.hip", "select.hip", "bjacobi.hip", "gmres.hip", "runtime.hip"]
+SOURCES = ["spmv.hip", "krylov.hip", "batched.hip", "select.hip", "bjacobi.hip", "gmres.hip", "ilu.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -115,6 +115,16 @@ struct JacobiImpl {
     int64_t bstore_bytes = 0;
 };
 
+// ILU-type preconditioner: factors on A's pattern (strict lower = L with
+// unit diagonal, the rest = U), diagonal positions, dependency levels of
+// both triangles (rows listed level by level) and three work vectors.
+struct IluImpl {
+    std::shared_ptr<MatrixImpl> A;
+    int sweeps = 0, trisolve = 0, trs_sweeps = 0;
+    BufPtr lu, dpos, lperm, uperm, y, t, z;
+    std::vector<int64_t> lptr, uptr;
+};
+
 struct IrImpl;
 struct BatchImpl;
 
@@ -122,6 +132,7 @@ struct SolverImpl {
     int kind = MXL_SOLVER_CG;
     std::shared_ptr<MatrixImpl> A;
     std::shared_ptr<JacobiImpl> P;  // may be null
+    std::shared_ptr<IluImpl> ilu;   // ILU preconditioner (GMRES), may be null
     mxl_criteria crit{};
     // work vectors (A's value type)
     BufPtr r, p, q, z, rhat, v, s, t, ones;
@@ -253,6 +264,10 @@ hipError_t gm_close(int64_t n, int64_t ld, const double *V, const double *dinv, 
                     const SolverState *st, void *ws, int m, hipStream_t s);
 hipError_t gm_read(const void *ws, int64_t *reorth, hipStream_t s);
 
+// ------------------------------------------------------------- ilu.hip
+// out = alpha U^{-1} L^{-1} r + beta out (beta == 0 overwrites)
+hipError_t ilu_apply(const IluImpl &P, double alpha, const void *r, double beta, void *out, hipStream_t s);
+
 // ------------------------------------------------------------- runtime.hip
 mxl_status set_error(mxl_status st, const std::string &msg);
 mxl_status check_device_ptr(const mxl_ctx *ctx, const void *p, size_t bytes, const char *what);
@@ -295,4 +310,5 @@ struct mxl_op {
     std::shared_ptr<mxl::JacobiImpl> jac;
     std::shared_ptr<mxl::SolverImpl> sol;
     std::shared_ptr<mxl::BatchImpl> bat;
+    std::shared_ptr<mxl::IluImpl> ilu;
 };

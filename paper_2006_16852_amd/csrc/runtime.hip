@@ -562,6 +562,15 @@ mxl_status mxl_apply_adv(const mxl_op *L, double alpha, const void *b, double be
         else HIP_TRY(launch_jacobi_apply(A.dtype, A.nrows, alpha, L->jac->dinv->p, b, beta, x, A.ctx->stream));
         return MXL_OK;
     }
+    case MXL_OP_ILU: {
+        const MatrixImpl &A = *L->ilu->A;
+        DeviceScope ds(A.ctx->device);
+        mxl_status st;
+        if ((st = check_dev(A.ctx, b, (size_t)A.nrows * 8, "b")) != MXL_OK) return st;
+        if ((st = check_dev(A.ctx, x, (size_t)A.nrows * 8, "x")) != MXL_OK) return st;
+        HIP_TRY(ilu_apply(*L->ilu, alpha, b, beta, x, A.ctx->stream));
+        return MXL_OK;
+    }
     case MXL_OP_SOLVER:
         if (alpha == 1.0 && beta == 0.0) return mxl_solve(L, b, x, nullptr);
         return fail(MXL_ERR_NOT_IMPLEMENTED, "advanced apply of a solver");
@@ -580,6 +589,7 @@ mxl_status mxl_op_describe(const mxl_op *op, mxl_op_desc *out) {
     if (op->kind == MXL_OP_MATRIX) A = op->mat.get();
     else if (op->kind == MXL_OP_JACOBI) A = op->jac->A.get();
     else if (op->kind == MXL_OP_SOLVER) A = op->sol->A.get();
+    else if (op->kind == MXL_OP_ILU) A = op->ilu->A.get();
     if (!A) return MXL_OK;
     out->format = A->format;
     out->variant = A->variant;
@@ -635,7 +645,8 @@ mxl_status mxl_op_destroy(mxl_op *op) {
     if (!op) return MXL_OK;
     const MatrixImpl *A = op->kind == MXL_OP_MATRIX ? op->mat.get()
                           : op->kind == MXL_OP_JACOBI ? op->jac->A.get()
-                          : op->kind == MXL_OP_SOLVER ? op->sol->A.get() : nullptr;
+                          : op->kind == MXL_OP_SOLVER ? op->sol->A.get()
+                          : op->kind == MXL_OP_ILU ? op->ilu->A.get() : nullptr;
     mxl_ctx *ctx = A ? A->ctx : op->kind == MXL_OP_BATCH ? batch_ctx(*op->bat) : nullptr;
     if (ctx) {  // queued work may still use the arrays
         DeviceScope ds(ctx->device);
@@ -691,7 +702,8 @@ mxl_status mxl_jacobi_generate(const mxl_op *Aop, mxl_op **P) {
 
 static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
                               const std::shared_ptr<JacobiImpl> &P, const mxl_criteria &crit,
-                              std::shared_ptr<SolverImpl> &out, int krylov = 0) {
+                              std::shared_ptr<SolverImpl> &out, int krylov = 0,
+                              const std::shared_ptr<IluImpl> &ilu = nullptr) {
     if (crit.max_iters < 0) return fail(MXL_ERR_INVALID_ARG, "max_iters < 0");
     if (crit.max_iters >= INT_MAX) return fail(MXL_ERR_INVALID_ARG, "max_iters too large");
     if (!(crit.reduction >= 0.0)) return fail(MXL_ERR_INVALID_ARG, "reduction must be >= 0");
@@ -727,7 +739,8 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
              need(S->gmws, gm_ws_bytes(krylov)) &&
              need(S->gdots, (size_t)(krylov + 2) * (size_t)G * sizeof(double)) &&
              need(S->gnorm, (size_t)std::max(G, 2 * kMaxGrid) * sizeof(double)) &&
-             (!P || need(S->z, vb));
+             (!(P || ilu) || need(S->z, vb));
+        S->ilu = ilu;
     }
     S->hist_len = crit.max_iters + 1;
     if (ok) ok = need(S->hist, (size_t)S->hist_len * sizeof(double));
@@ -756,14 +769,19 @@ mxl_status mxl_gmres_generate(const mxl_op *Aop, const mxl_op *Pop, const mxl_cr
         return fail(MXL_ERR_INVALID_ARG, "krylov_dim must be in [1, 1024]");
     if (kind == MXL_SOLVER_GMRES && Aop->mat->dtype != MXL_F64)
         return fail(MXL_ERR_NOT_IMPLEMENTED, "GMRES needs an FP64 operator");
-    if (Pop && Pop->kind != MXL_OP_JACOBI) return fail(MXL_ERR_NOT_IMPLEMENTED, "only Jacobi preconditioning");
-    if (Pop && Pop->jac->block && kind == MXL_SOLVER_BICGSTAB)
+    const bool ilu = Pop && Pop->kind == MXL_OP_ILU;
+    if (Pop && Pop->kind != MXL_OP_JACOBI && !ilu)
+        return fail(MXL_ERR_NOT_IMPLEMENTED, "only Jacobi or ILU preconditioning");
+    if (Pop && !ilu && Pop->jac->block && kind == MXL_SOLVER_BICGSTAB)
         return fail(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi preconditions CG and GMRES");
+    if (ilu && kind != MXL_SOLVER_GMRES) return fail(MXL_ERR_NOT_IMPLEMENTED, "ILU preconditions GMRES");
+    if (ilu && Pop->ilu->A->nrows != Aop->mat->nrows)
+        return fail(MXL_ERR_DIM_MISMATCH, "preconditioner does not conform to the matrix");
     *Sout = nullptr;
     DeviceScope ds(Aop->mat->ctx->device);
     std::shared_ptr<SolverImpl> S;
-    mxl_status st = make_solver(kind, Aop->mat, Pop ? Pop->jac : nullptr, *crit, S,
-                                kind == MXL_SOLVER_GMRES ? kdim : 0);
+    mxl_status st = make_solver(kind, Aop->mat, Pop && !ilu ? Pop->jac : nullptr, *crit, S,
+                                kind == MXL_SOLVER_GMRES ? kdim : 0, ilu ? Pop->ilu : nullptr);
     if (st != MXL_OK) return st;
     auto *op = new mxl_op;
     op->kind = MXL_OP_SOLVER;
@@ -1081,9 +1099,15 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
     double *V = (double *)S.V->p, *dp = (double *)S.gdots->p, *np = (double *)S.gnorm->p;
     void *ws = S.gmws->p;
     double *x = (double *)xv, *hist = (double *)S.hist->p;
-    const bool blockp = S.P && S.P->block;
+    // point Jacobi is fused into the basis kernels; block Jacobi and ILU
+    // are applied by their own kernels (z = M^{-1} v, x += M^{-1} t)
+    const bool blockp = (S.P && S.P->block) || S.ilu;
     const double *dinv = S.P && S.P->dinv ? (const double *)S.P->dinv->p : nullptr;
-    double *z = S.P ? (double *)S.z->p : nullptr;
+    double *z = S.P || S.ilu ? (double *)S.z->p : nullptr;
+    auto apply_M = [&](const double *in, double beta, double *out) -> hipError_t {
+        if (S.ilu) return ilu_apply(*S.ilu, 1.0, in, beta, out, s);
+        return bj_apply(ctx, *S.P, n, 1.0, in, beta, out, s);
+    };
     const mxl_criteria &c = S.crit;
     mxl_status rs;
     // r = b - A x into V_0, ||r||, z = M^{-1} V_0, g = beta e_1, criteria
@@ -1099,7 +1123,7 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
         HIP_TRY(gm_prep(ctx, n, V, first ? (const double *)b : nullptr, blockp ? nullptr : dinv,
                         blockp ? nullptr : z, np, &slots, s));
         HIP_TRY(gm_start(np, slots, st, ws, m, hist, first, s));
-        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, V, 0.0, z, s));
+        if (blockp) HIP_TRY(apply_M(V, 0.0, z));
         return MXL_OK;
     };
     HIP_TRY(launch_state_init(st, c.reduction, c.nonfinite_check, s));
@@ -1124,7 +1148,7 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
             HIP_TRY(spmv_launch(A, a, s));
             HIP_TRY(gm_step(n, ld, V, j, (const double *)S.q->p, blockp ? nullptr : dinv, blockp ? nullptr : z,
                             dp, np, st, ws, m, hist, s));
-            if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, V + (int64_t)(j + 1) * ld, 0.0, z, s));
+            if (blockp) HIP_TRY(apply_M(V + (int64_t)(j + 1) * ld, 0.0, z));
             ++k;
             if (k % c.check_every == 0) {
                 if ((rs = read_state(S, h)) != MXL_OK) return rs;
@@ -1136,7 +1160,7 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
             }
         }
         HIP_TRY(gm_close(n, ld, V, blockp ? nullptr : dinv, x, blockp ? (double *)S.r->p : nullptr, st, ws, m, s));
-        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.r->p, 1.0, x, s));
+        if (blockp) HIP_TRY(apply_M((const double *)S.r->p, 1.0, x));
         if ((rs = read_state(S, h)) != MXL_OK) return rs;
         if (h.stop) {
             stop = map_stop(h.stop);

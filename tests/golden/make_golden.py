@@ -6,6 +6,7 @@ oracle needs minutes at these sizes.  Run from the repository root:
     python tests/golden/make_golden.py            # everything
     python tests/golden/make_golden.py bjacobi    # only the block-Jacobi entry
     python tests/golden/make_golden.py gmres      # only the GMRES entry
+    python tests/golden/make_golden.py ilu        # only the ILU-GMRES entry
 """
 import json
 import os
@@ -49,7 +50,22 @@ def gmres(out):
     print("gmres", r["iterations"], time.time() - t, flush=True)
 
 
-ONLY = {"bjacobi": bjacobi, "gmres": gmres}
+def ilu(out):
+    """GMRES(100) with ParILU (3 sweeps) and Jacobi-sweep triangular solves
+    (4 sweeps) on the 128^3 convection-diffusion system."""
+    A = W.convdiff_3d7(128)
+    b = W.uniform_vec(A.nrows, 5)
+    t = time.time()
+    lu, _ = O.parilu(A, 3)
+    r = O.gmres_ilu(A, b, lu, trs_mode=1, trs_sweeps=4, krylov_dim=100, reduction=1e-10, max_iters=5000)
+    out["convdiff3d7_128_gmres100_parilu3_jacobi4_1e-10"] = dict(
+        recipe="peclet (0.5, 0.25, 0.125); b = U[-1,1) seed 5, x0 = 0; ParILU 3 sweeps, 4 Jacobi sweeps per triangle",
+        iterations=r["iterations"], spmv_count=r["spmv_count"], stop=r["stop_reason"],
+        rel_residual=r["rel_residual"])
+    print("ilu", r["iterations"], time.time() - t, flush=True)
+
+
+ONLY = {"bjacobi": bjacobi, "gmres": gmres, "ilu": ilu}
 
 
 def main():
@@ -90,6 +106,7 @@ def main():
     print("ir", r["outer"], r["inner_iterations"], time.time() - t, flush=True)
     bjacobi(out)
     gmres(out)
+    ilu(out)
     json.dump(out, open(path, "w"), indent=1)
     print("wrote", path)
 
