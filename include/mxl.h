@@ -127,7 +127,7 @@ typedef struct {
     double  spmv_ms;        /* out: summed SpMV time of the timed launches */
     int64_t spmv_timed;     /* out: number of timed launches */
     int64_t restarts;       /* out, GMRES: restarted cycles */
-    int64_t reorth;         /* out, GMRES: steps that took a second Gram-Schmidt pass */
+    int64_t reorth;         /* out, GMRES: basis vectors orthogonalised a second time */
 } mxl_solve_info;
 
 typedef struct mxl_ctx mxl_ctx;
@@ -294,9 +294,11 @@ mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *A,
  * restart).  P may also be an ILU operator.  One iteration = one Arnoldi
  * step (one product with A);
  * info->restarts counts restarted cycles, info->spmv_count = 1 + iterations
- * + restarts.  The basis is orthogonalised by classical Gram-Schmidt with a
- * second pass when the first one cancels more than half of ||w||^2
- * (info->reorth counts those steps).  Memory: (krylov_dim + 1) basis
+ * + restarts (+ 1 when the criterion stops a cycle early: the product of
+ * the step that finalises the converged column).  The basis is
+ * orthogonalised twice by classical Gram-Schmidt, the second pass of each
+ * vector delayed into the next step so that every step reads the basis
+ * twice (info->reorth counts the vectors).  Memory: (krylov_dim + 1) basis
  * vectors of n doubles plus O(krylov_dim^2).  A FP64, krylov_dim in
  * [1, 1024].  Errors: INVALID_ARG, NOT_IMPLEMENTED (FP32 operator, non-Jacobi
  * P), DTYPE / DIM_MISMATCH (P does not conform), OUT_OF_MEMORY. */

@@ -2,25 +2,31 @@
 // solvers of Sec. 3.1; the restart parameter and memory model of Table 2).
 //
 // The Arnoldi basis V (m+1 vectors of ld >= n doubles, vector after vector)
-// stays resident.  Basis vectors are stored unnormalised: v_k = scl[k] V_k,
-// so no pass rewrites a vector to normalise it.  One Arnoldi step is
+// stays resident.  Orthogonalisation is classical Gram-Schmidt with the
+// re-orthogonalisation of each vector delayed by one step (the "DCGS2"
+// scheme of Bielich, Langou, Thomas, Swirydowicz, Yamazaki and Boman):
+// step j holds the final v_0..v_{j-1}, the candidate t_j (projected once,
+// not normalised) in slot j, and u = A M^{-1} t_j.  One pass over the basis
+// gives s_k = v_k . t_j, c_k = v_k . u (k < j), sigma = t_j . t_j and
+// tau = t_j . u; then
+//   beta = sqrt(sigma - |s|^2)      v_j = (t_j - sum s_k v_k) / beta
+//   column j-1 of H += s, h_{j,j-1} = beta   (column j-1 is now final)
+//   A M^{-1} v_j = (u - V (H s)) / beta      (Arnoldi relation of columns < j)
+//   h_kj = (c_k - (Hs)_k) / beta,  h_jj = ((tau - s.c) / beta - (Hs)_j) / beta
+//   t_{j+1} = u / beta - sum_{k<j} ((Hs)_k / beta + h_kj) v_k
+//             - ((Hs)_j / beta + h_jj) v_j
+// and one more pass writes v_j over t_j and t_{j+1} into slot j+1.  So every
+// step reads the basis twice (a multi-dot and a multi-axpy) and still
+// orthogonalises every vector twice; a modified Gram-Schmidt step reads it
+// five times.  Column j-1 becomes final during step j, so the Givens
+// rotation, the residual estimate and the criteria of step j-1 run there;
+// a cycle ends with one more multi-dot that finalises its last column.
 //
-//   u = A z_j, z_j = M^{-1} V_j                          (SpMV)
-//   h_kj = scl_k scl_j (V_k . u), ||w||^2 = scl_j^2 u.u  (k_gm_dots + k_gm_h)
-//   w' = scl_j u - sum_k h_kj scl_k V_k -> V_{j+1}, z    (k_gm_update)
-//   second pass only when ||w'|| < ||w|| / sqrt(2)        (k_gm_norm1, then
-//     k_gm_dots/k_gm_h/k_gm_update again on V_{j+1})
-//   Givens rotations, residual estimate, criteria         (k_gm_givens)
-//
-// i.e. classical Gram-Schmidt, whose projections are one skinny multi-dot
-// and one multi-axpy over the basis (two passes over V instead of the five
-// of a modified Gram-Schmidt step), with the Daniel-Gragg-Kaufman-Stewart
-// test deciding the re-orthogonalisation that keeps the basis orthogonal to
-// working precision.  A cycle ends with the back substitution R y = g
-// (k_gm_backsub) and x += M^{-1} V (scl .* y) (k_gm_xupdate).
-//
-// Every step kernel returns at once when the solve has stopped, so the host
-// can enqueue steps without reading the state after each one.
+// Kernels of a step: SpMV, k_gm_dots (partials), k_gm_reduce (one
+// workgroup per value), k_gm_finish (one workgroup: column update, Givens,
+// criteria, coefficients), k_gm_update.  Every step kernel returns at once
+// when the solve has stopped, so the host enqueues steps without reading
+// the state after each one.
 #include <cmath>
 #include <cstring>
 
@@ -31,43 +37,44 @@ namespace mxl {
 
 constexpr int kGmRows = 8;              // rows per thread in the basis kernels
 constexpr int kGmTile = kWG * kGmRows;  // rows per workgroup
-constexpr int kGmKC = 8;                // basis vectors per multi-dot chunk
+constexpr int kGmKC = 4;                // basis vectors per multi-dot chunk (2 dots each)
 
 // Device scalars of a GMRES solve besides SolverState.
 struct GmresState {
-    int32_t j;        // steps completed in the current cycle
-    int32_t k;        // steps completed in the solve
-    int32_t reorth;   // 1: the current step takes the second Gram-Schmidt pass
-    int32_t nreorth;  // second passes taken in the solve
-    int32_t jx;       // basis vectors combined by the cycle's closing update
+    int32_t j;      // final columns in the current cycle
+    int32_t k;      // final columns in the solve (the iteration count)
+    int32_t jx;     // basis vectors combined by the cycle's closing update
     int32_t pad;
-    double wn2;       // ||w||^2 before orthogonalisation
-    double hn2;       // ||w||^2 after the first pass
+    double beta;    // norm of the current candidate after re-orthogonalisation
+    double bcoef;   // coefficient of v_j in t_{j+1}
+    int64_t nspmv;  // products A M^{-1} t_j of the steps (each step's finish counts its own)
 };
 
 struct GmPtrs {
-    double *H;     // (m+1) x m Hessenberg matrix, column j at H + (m+1) j
+    double *H;    // (m+1) x m Hessenberg matrix, column j at H + (m+1) j
+    double *R;    // the same columns after the Givens rotations
     double *cs, *sn;
-    double *g;     // m+1: rotated right-hand side beta e_1
-    double *scl;   // m+1: v_k = scl[k] V_k
-    double *coef;  // m+1: projection coefficients / closing combination
-    double *y;     // m
+    double *g;    // m+1: rotated right-hand side beta e_1
+    double *sv;   // m+1: re-orthogonalisation coefficients s_k
+    double *av;   // m+1: coefficients of v_k in t_{j+1}; closing combination y
+    double *red;  // 2m+2: reduced dots of the current step
     GmresState *gs;
     int m;
 };
 
 size_t gm_ws_bytes(int m) {
-    const size_t d = (size_t)(m + 1) * m + 2 * (size_t)m + 3 * (size_t)(m + 1) + (size_t)m;
+    const size_t d = 2 * (size_t)(m + 1) * m + 2 * (size_t)m + 3 * (size_t)(m + 1) + 2 * (size_t)(m + 1);
     return d * sizeof(double) + 256;
 }
 
 static GmPtrs gm_ptrs(void *ws, int m) {
     GmPtrs P;
-    auto *gs = (GmresState *)ws;
-    double *d = (double *)((char *)ws + 256);
-    P.gs = gs;
+    P.gs = (GmresState *)ws;
     P.m = m;
+    double *d = (double *)((char *)ws + 256);
     P.H = d;
+    d += (size_t)(m + 1) * m;
+    P.R = d;
     d += (size_t)(m + 1) * m;
     P.cs = d;
     d += m;
@@ -75,11 +82,11 @@ static GmPtrs gm_ptrs(void *ws, int m) {
     d += m;
     P.g = d;
     d += m + 1;
-    P.scl = d;
+    P.sv = d;
     d += m + 1;
-    P.coef = d;
+    P.av = d;
     d += m + 1;
-    P.y = d;
+    P.red = d;
     return P;
 }
 
@@ -88,7 +95,30 @@ int gm_grid(int64_t n) {
     return (int)(g < 1 ? 1 : g);
 }
 
-__device__ __forceinline__ double nt_ld(const double *p) { return __builtin_nontemporal_load(p); }
+// Thread t of a workgroup owns the row pairs (p, p+1), p = tile start +
+// 512 q + 2 t, q = 0..3: one 16-byte load per pair and vector (a 1 KB
+// contiguous request per wave; 8-byte loads reach only about 60% of the
+// bandwidth on this access pattern).
+typedef double d2 __attribute__((ext_vector_type(2)));
+constexpr int kGmPairs = kGmRows / 2;
+__device__ __forceinline__ int64_t gm_pair(int g, int t, int q) {
+    return (int64_t)g * kGmTile + (int64_t)q * (2 * kWG) + 2 * t;
+}
+// Pair (i, i+1) of a vector, zeros past n; 16-byte aligned when both exist.
+__device__ __forceinline__ d2 ld2(const double *p, int64_t i, int64_t n) {
+    if (i + 1 < n) return *(const d2 *)(p + i);
+    d2 v = {i < n ? p[i] : 0.0, 0.0};
+    return v;
+}
+__device__ __forceinline__ d2 ld2_nt(const double *p, int64_t i, int64_t n) {
+    if (i + 1 < n) return __builtin_nontemporal_load((const d2 *)(p + i));
+    d2 v = {i < n ? p[i] : 0.0, 0.0};
+    return v;
+}
+__device__ __forceinline__ void st2(double *p, int64_t i, int64_t n, d2 v) {
+    if (i + 1 < n) *(d2 *)(p + i) = v;
+    else if (i < n) p[i] = v[0];
+}
 
 // [v.v, b.b] partials (b optional) and z = dinv .* v (when z is given).
 __global__ __launch_bounds__(kWG) void k_gm_prep(int64_t n, const double *__restrict__ v,
@@ -106,9 +136,9 @@ __global__ __launch_bounds__(kWG) void k_gm_prep(int64_t n, const double *__rest
     publish<2>(t, parts, blockIdx.x);
 }
 
-// Start of a cycle from the residual held in V_0: beta = ||V_0||,
-// scl_0 = 1/beta, g = beta e_1, and the criteria on beta.  first: also
-// ||b||^2 and history[0].
+// Start of a cycle from the residual r held (unnormalised) in slot 0:
+// g = 0, the criteria on ||r||.  first: also ||b||^2 and history[0].  Step 0
+// normalises r with its own norm and sets g_0.
 __global__ void k_gm_start(const double *__restrict__ parts, int slots, SolverState *st, GmPtrs P,
                            double *hist, int first) {
     double t[2];
@@ -120,16 +150,13 @@ __global__ void k_gm_start(const double *__restrict__ parts, int slots, SolverSt
         st->nb2 = nb2;
         st->iters = 0;
         gs->k = 0;
-        gs->nreorth = 0;
+        gs->nspmv = 0;
     }
     const double beta = sqrt(t[0]);
     st->rr = t[0];
     gs->j = 0;
     gs->jx = 0;
-    gs->reorth = 0;
     for (int i = 0; i <= P.m; ++i) P.g[i] = 0.0;
-    P.g[0] = beta;
-    P.scl[0] = 1.0 / beta;
     const double nb = sqrt(nb2);
     if (first && hist) hist[0] = nb > 0.0 ? beta / nb : 0.0;
     const bool chk = st->nonfinite_check != 0;
@@ -138,193 +165,214 @@ __global__ void k_gm_start(const double *__restrict__ parts, int slots, SolverSt
     else if (beta <= st->red * nb) st->stop = ST_CONVERGED;
 }
 
-// Partials of V_k . u for k = 0..nv-1 and of u.u (slot nv), one tile of
-// kGmTile rows per workgroup; partial (k, g) at parts[k * G + g].  u may be
-// V_nv itself (second pass).
-__global__ __launch_bounds__(kWG) void k_gm_dots(int64_t n, int64_t ld, const double *__restrict__ V,
-                                                 int nv, const double *u, double *__restrict__ parts,
-                                                 const SolverState *st, const GmresState *gs, int pass) {
+// Partials (one tile of kGmTile rows per workgroup) of s_k = V_k . t and,
+// with u, c_k = V_k . u for k < j, then t.t and t.u, t = slot j.  Value
+// layout: s_k at 2k, c_k at 2k+1, t.t at 2j, t.u at 2j+1; partial (v, g) at
+// parts[v * G + g].
+__global__ __launch_bounds__(kWG) void k_gm_dots(int64_t n, int64_t ld, const double *__restrict__ V, int j,
+                                                 const double *__restrict__ u, double *__restrict__ parts,
+                                                 const SolverState *st) {
     if (st->stop) return;
-    if (pass == 2 && !gs->reorth) return;
-    __shared__ double red[kGmKC][kWG];
+    __shared__ double red[2 * kGmKC][kWG];
     const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x;
-    const int64_t row0 = (int64_t)g * kGmTile + t;
-    double ur[kGmRows];
-    double uu = 0.0;
+    const double *tj = V + (int64_t)j * ld;
+    d2 tr[kGmPairs], ur[kGmPairs];
+    double tt = 0.0, tu = 0.0;
 #pragma unroll
-    for (int r = 0; r < kGmRows; ++r) {
-        const int64_t i = row0 + (int64_t)r * kWG;
-        ur[r] = i < n ? u[i] : 0.0;
-        uu += ur[r] * ur[r];
+    for (int q = 0; q < kGmPairs; ++q) {
+        const int64_t i = gm_pair(g, t, q);
+        tr[q] = ld2(tj, i, n);
+        ur[q] = u ? ld2(u, i, n) : (d2)0.0;
+        tt += tr[q][0] * tr[q][0] + tr[q][1] * tr[q][1];
+        tu += tr[q][0] * ur[q][0] + tr[q][1] * ur[q][1];
     }
-    for (int k0 = 0; k0 < nv; k0 += kGmKC) {
-        double acc[kGmKC];
+    for (int k0 = 0; k0 < j; k0 += kGmKC) {
+        double acc[2 * kGmKC];
 #pragma unroll
         for (int kk = 0; kk < kGmKC; ++kk) {
-            acc[kk] = 0.0;
-            if (k0 + kk < nv) {
+            acc[2 * kk] = 0.0;
+            acc[2 * kk + 1] = 0.0;
+            if (k0 + kk < j) {
                 const double *vk = V + (int64_t)(k0 + kk) * ld;
 #pragma unroll
-                for (int r = 0; r < kGmRows; ++r) {
-                    const int64_t i = row0 + (int64_t)r * kWG;
-                    if (i < n) acc[kk] += nt_ld(vk + i) * ur[r];
+                for (int q = 0; q < kGmPairs; ++q) {
+                    const d2 v = ld2_nt(vk, gm_pair(g, t, q), n);
+                    acc[2 * kk] += v[0] * tr[q][0] + v[1] * tr[q][1];
+                    acc[2 * kk + 1] += v[0] * ur[q][0] + v[1] * ur[q][1];
                 }
             }
         }
 #pragma unroll
-        for (int kk = 0; kk < kGmKC; ++kk) red[kk][t] = acc[kk];
+        for (int e = 0; e < 2 * kGmKC; ++e) red[e][t] = acc[e];
         __syncthreads();
-        // thread t sums 8 of the 256 values of vector kk = t / 32, then the
+        // thread t sums 8 of the 256 partials of value e = t / 32, then the
         // 32 lanes of that group combine by shuffles (fixed order)
-        const int kk = t / 32, q = t % 32;
+        const int e = t / 32, q = t % 32;
         double s = 0.0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) s += red[kk][q * 8 + e];
+        for (int f = 0; f < 8; ++f) s += red[e][q * 8 + f];
 #pragma unroll
         for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-        if (q == 0 && k0 + kk < nv) parts[(int64_t)(k0 + kk) * G + g] = s;
+        if (q == 0 && k0 + e / 2 < j) parts[(int64_t)(2 * k0 + e) * G + g] = s;
         __syncthreads();
     }
-    double v1[1] = {uu};
-    block_reduce<1>(v1);
-    if (t == 0) parts[(int64_t)nv * G + g] = v1[0];
+    double v2[2] = {tt, tu};
+    block_reduce<2>(v2);
+    if (t == 0) {
+        parts[(int64_t)(2 * j) * G + g] = v2[0];
+        parts[(int64_t)(2 * j + 1) * G + g] = v2[1];
+    }
 }
 
-// One workgroup per value k = 0..j+1 of a multi-dot: the total of its G
-// partials (fixed order), then pass 1: h_kj = scl_k scl_j s and
-// ||w||^2 = scl_j^2 s at k = j+1; pass 2: h_kj += scl_k s.  coef_k = h scl_k
-// is the coefficient of V_k in the following update.
-__global__ __launch_bounds__(kWG) void k_gm_h(const double *__restrict__ parts, int G, int j,
-                                              const SolverState *st, GmPtrs P, int pass) {
+// One workgroup per value v: the total of its G partials in a fixed order.
+__global__ __launch_bounds__(kWG) void k_gm_reduce(const double *__restrict__ parts, int G, const SolverState *st,
+                                                   double *__restrict__ red) {
     if (st->stop) return;
-    if (pass == 2 && !P.gs->reorth) return;
-    const int kk = blockIdx.x;
+    const int v = blockIdx.x;
     double s[1] = {0.0};
-    for (int g = threadIdx.x; g < G; g += kWG) s[0] += parts[(int64_t)kk * G + g];
+    for (int g = threadIdx.x; g < G; g += kWG) s[0] += parts[(int64_t)v * G + g];
     block_reduce<1>(s);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x == 0) red[v] = s[0];
+}
+
+// Step j's scalar work (one workgroup): beta; column j-1 final (+ s,
+// h_{j,j-1} = beta), its Givens rotation, residual estimate and criteria
+// (in the oracle's order); then, unless last (the cycle's closing pass),
+// (Hs), column j and the coefficients of the update.
+__global__ __launch_bounds__(kWG) void k_gm_finish(int j, int last, SolverState *st, GmPtrs P, double *hist) {
+    if (st->stop) return;
+    __shared__ double hs[kGmMaxKrylov + 1];
+    __shared__ double bsh[1];
+    __shared__ int stopped[1];
+    GmresState *gs = P.gs;
     const int64_t ldh = P.m + 1;
-    if (kk <= j) {
-        if (pass == 1) {
-            const double h = P.scl[kk] * P.scl[j] * s[0];
-            P.H[kk + ldh * j] = h;
-            P.coef[kk] = h * P.scl[kk];
+    const int t = threadIdx.x;
+    double part[2] = {0.0, 0.0};  // |s|^2, s.c
+    for (int k = t; k < j; k += kWG) {
+        const double s = P.red[2 * k];
+        part[0] += s * s;
+        if (!last) part[1] += s * P.red[2 * k + 1];
+    }
+    block_reduce<2>(part);
+    if (t == 0) {
+        const double b2 = P.red[2 * j] - part[0];
+        // b2 <= 0: the candidate lies in the span (happy breakdown); NaN stays NaN
+        const double beta = b2 <= 0.0 ? 0.0 : sqrt(b2);
+        bsh[0] = beta;
+        gs->beta = beta;
+        stopped[0] = 0;
+        if (!last) gs->nspmv += 1;  // this step's SpMV ran (the solve had not stopped)
+        if (j == 0) {
+            P.g[0] = beta;
         } else {
-            const double c = P.scl[kk] * s[0];
-            P.H[kk + ldh * j] += c;
-            P.coef[kk] = c * P.scl[kk];
+            // column j-1 final; rotate a copy of it
+            double *h = P.H + ldh * (j - 1), *r = P.R + ldh * (j - 1);
+            for (int k = 0; k < j; ++k) h[k] += P.red[2 * k];
+            h[j] = beta;
+            for (int k = 0; k <= j; ++k) r[k] = h[k];
+            const int c0 = j - 1;
+            for (int i = 0; i < c0; ++i) {
+                const double a = r[i], c = r[i + 1];
+                r[i] = P.cs[i] * a + P.sn[i] * c;
+                r[i + 1] = -P.sn[i] * a + P.cs[i] * c;
+            }
+            const double a = r[c0];
+            const double d = hypot(a, beta);
+            const double cc = d == 0.0 ? 1.0 : a / d, ss = d == 0.0 ? 0.0 : beta / d;
+            P.cs[c0] = cc;
+            P.sn[c0] = ss;
+            r[c0] = d;
+            r[c0 + 1] = 0.0;
+            const double gj = P.g[c0];
+            const double gn = -ss * gj;
+            P.g[c0 + 1] = gn;
+            P.g[c0] = cc * gj;
+            const int k = gs->k + 1;
+            gs->k = k;
+            gs->j = j;
+            st->iters = k;
+            st->rr = gn * gn;
+            const double nb = sqrt(st->nb2);
+            const double rel = fabs(gn) / nb;
+            if (hist) hist[k] = rel;
+            const bool chk = st->nonfinite_check != 0;
+            int stop = ST_RUN;
+            if (chk && (!finite_d(rel) || !finite_d(d))) stop = ST_NONFINITE;
+            else if (fabs(gn) <= st->red * nb) stop = ST_CONVERGED;
+            else if (beta == 0.0 || d == 0.0) stop = ST_BREAKDOWN;
+            if (stop != ST_RUN) {
+                st->stop = stop;
+                stopped[0] = 1;
+            }
         }
-    } else if (pass == 1) {
-        P.gs->wn2 = P.scl[j] * P.scl[j] * s[0];
+    }
+    __syncthreads();
+    if (last || stopped[0]) return;
+    const double beta = bsh[0];
+    // (Hs)_l = sum_{k<j} h_lk s_k over the final columns 0..j-1 (h_lk = 0 for l > k+1)
+    for (int l = t; l <= j; l += kWG) {
+        double a = 0.0;
+        for (int k = l > 0 ? l - 1 : 0; k < j; ++k) a += P.H[l + ldh * k] * P.red[2 * k];
+        hs[l] = a;
+    }
+    __syncthreads();
+    const double ib = 1.0 / beta;
+    double *hc = P.H + ldh * j;
+    for (int k = t; k < j; k += kWG) {
+        const double h = (P.red[2 * k + 1] - hs[k]) * ib;
+        hc[k] = h;
+        P.sv[k] = P.red[2 * k];
+        P.av[k] = hs[k] * ib + h;
+    }
+    if (t == 0) {
+        const double hjj = ((P.red[2 * j + 1] - part[1]) * ib - hs[j]) * ib;
+        hc[j] = hjj;
+        gs->bcoef = hs[j] * ib + hjj;
     }
 }
 
-// w = a u - sum_{k<=j} coef_k V_k into V_{j+1} (a = scl_j in pass 1, 1 in
-// pass 2 where u is V_{j+1} itself), z = dinv .* w when z is given, and
-// partials of w.w (one per workgroup).
-__global__ __launch_bounds__(kWG) void k_gm_update(int64_t n, int64_t ld, double *V, int j, const double *u,
-                                                   const double *__restrict__ dinv, double *__restrict__ z,
-                                                   double *__restrict__ parts, const SolverState *st,
-                                                   GmPtrs P, int pass) {
+// v_j = (t_j - sum_{k<j} s_k v_k) / beta over slot j, and
+// t_{j+1} = u / beta - sum_{k<j} a_k v_k - bcoef v_j into slot j+1, with
+// z = dinv .* t_{j+1} (or t_{j+1}) when z is given.
+__global__ __launch_bounds__(kWG) void k_gm_update(int64_t n, int64_t ld, double *V, int j,
+                                                   const double *__restrict__ u, const double *__restrict__ dinv,
+                                                   double *__restrict__ z, const SolverState *st, GmPtrs P) {
     if (st->stop) return;
-    if (pass == 2 && !P.gs->reorth) return;
     const int g = blockIdx.x, t = threadIdx.x;
-    const int64_t row0 = (int64_t)g * kGmTile + t;
-    const double a = pass == 1 ? P.scl[j] : 1.0;
-    double w[kGmRows];
+    double *tj = V + (int64_t)j * ld, *tn = V + (int64_t)(j + 1) * ld;
+    const double ib = 1.0 / P.gs->beta, bc = P.gs->bcoef;
+    d2 a[kGmPairs], b[kGmPairs];
 #pragma unroll
-    for (int r = 0; r < kGmRows; ++r) {
-        const int64_t i = row0 + (int64_t)r * kWG;
-        w[r] = i < n ? a * u[i] : 0.0;
+    for (int q = 0; q < kGmPairs; ++q) {
+        const int64_t i = gm_pair(g, t, q);
+        a[q] = ld2(tj, i, n);
+        b[q] = ld2(u, i, n) * ib;
     }
-    for (int k = 0; k <= j; ++k) {
-        const double c = P.coef[k];
+    for (int k = 0; k < j; ++k) {
+        const double s = P.sv[k], c = P.av[k];
         const double *vk = V + (int64_t)k * ld;
 #pragma unroll
-        for (int r = 0; r < kGmRows; ++r) {
-            const int64_t i = row0 + (int64_t)r * kWG;
-            if (i < n) w[r] -= c * nt_ld(vk + i);
+        for (int q = 0; q < kGmPairs; ++q) {
+            const d2 v = ld2_nt(vk, gm_pair(g, t, q), n);
+            a[q] -= s * v;
+            b[q] -= c * v;
         }
     }
-    double *vn = V + (int64_t)(j + 1) * ld;
-    double ww = 0.0;
 #pragma unroll
-    for (int r = 0; r < kGmRows; ++r) {
-        const int64_t i = row0 + (int64_t)r * kWG;
-        if (i < n) {
-            vn[i] = w[r];
-            if (z) z[i] = dinv ? dinv[i] * w[r] : w[r];
-            ww += w[r] * w[r];
-        }
+    for (int q = 0; q < kGmPairs; ++q) {
+        const int64_t i = gm_pair(g, t, q);
+        if (i >= n) continue;
+        const d2 vj = a[q] * ib;
+        const d2 tn2 = b[q] - bc * vj;
+        st2(tj, i, n, vj);
+        st2(tn, i, n, tn2);
+        if (z) st2(z, i, n, dinv ? ld2(dinv, i, n) * tn2 : tn2);
     }
-    double v1[1] = {ww};
-    publish<1>(v1, parts, g);
 }
 
-// ||w'||^2 after the first pass and the re-orthogonalisation test.
-__global__ __launch_bounds__(kWG) void k_gm_norm1(const double *__restrict__ parts, int G,
-                                                  const SolverState *st, GmresState *gs) {
-    if (st->stop) return;
-    double t[1];
-    gather_all<1>(parts, G, t);
-    if (threadIdx.x != 0) return;
-    gs->hn2 = t[0];
-    const int re = t[0] < 0.5 * gs->wn2 ? 1 : 0;
-    gs->reorth = re;
-    gs->nreorth += re;
-}
-
-// Closes Arnoldi step j: h_{j+1,j} = ||w||, the earlier rotations and a new
-// one on column j, g, the residual estimate |g_{j+1}| and the criteria (in
-// the oracle's order), scl_{j+1} = 1 / h_{j+1,j}.
-__global__ __launch_bounds__(kWG) void k_gm_givens(const double *__restrict__ parts, int G, int j,
-                                                   SolverState *st, GmPtrs P, double *hist) {
-    if (st->stop) return;
-    GmresState *gs = P.gs;
-    double hn2 = gs->hn2;
-    if (gs->reorth) {
-        double t[1];
-        gather_all<1>(parts, G, t);
-        hn2 = t[0];
-    }
-    if (threadIdx.x != 0) return;
-    const int64_t ldh = P.m + 1;
-    double *h = P.H + ldh * j;
-    const double hn = sqrt(hn2);
-    for (int i = 0; i < j; ++i) {
-        const double a = h[i], c = h[i + 1];
-        h[i] = P.cs[i] * a + P.sn[i] * c;
-        h[i + 1] = -P.sn[i] * a + P.cs[i] * c;
-    }
-    const double a = h[j];
-    const double d = hypot(a, hn);
-    const double c = d == 0.0 ? 1.0 : a / d, s = d == 0.0 ? 0.0 : hn / d;
-    P.cs[j] = c;
-    P.sn[j] = s;
-    h[j] = d;
-    h[j + 1] = 0.0;
-    const double gj = P.g[j];
-    const double gn = -s * gj;
-    P.g[j + 1] = gn;
-    P.g[j] = c * gj;
-    const int k = gs->k + 1;
-    gs->k = k;
-    gs->j = j + 1;
-    st->iters = k;
-    st->rr = gn * gn;
-    const double nb = sqrt(st->nb2);
-    const double rel = fabs(gn) / nb;
-    if (hist) hist[k] = rel;
-    P.scl[j + 1] = 1.0 / hn;
-    const bool chk = st->nonfinite_check != 0;
-    if (chk && (!finite_d(rel) || !finite_d(d))) st->stop = ST_NONFINITE;
-    else if (fabs(gn) <= st->red * nb) st->stop = ST_CONVERGED;
-    else if (hn == 0.0 || d == 0.0) st->stop = ST_BREAKDOWN;
-}
-
-// R y = g over the cycle's steps (one wave; column sweep, g kept in LDS),
-// then coef_k = scl_k y_k for the closing update.  Nothing is combined
-// after a non-finite stop.
+// R y = g over the cycle's final columns (one wave; column sweep, g kept
+// in LDS); y goes to av for the closing update.  Nothing is combined after
+// a non-finite stop.
 __global__ __launch_bounds__(kWave) void k_gm_backsub(const SolverState *st, GmPtrs P) {
     __shared__ double gl[kGmMaxKrylov];
     GmresState *gs = P.gs;
@@ -334,43 +382,41 @@ __global__ __launch_bounds__(kWave) void k_gm_backsub(const SolverState *st, GmP
     for (int l = lane; l < jj; l += kWave) gl[l] = P.g[l];
     __syncthreads();
     for (int i = jj - 1; i >= 0; --i) {
-        const double yi = gl[i] / P.H[i + ldh * i];
+        const double yi = gl[i] / P.R[i + ldh * i];
         __syncthreads();
-        for (int l = lane; l < i; l += kWave) gl[l] -= P.H[l + ldh * i] * yi;
-        if (lane == 0) P.y[i] = yi;
+        for (int l = lane; l < i; l += kWave) gl[l] -= P.R[l + ldh * i] * yi;
+        if (lane == 0) P.av[i] = yi;
         __syncthreads();
     }
-    __syncthreads();
-    for (int l = lane; l < jj; l += kWave) P.coef[l] = P.y[l] * P.scl[l];
     if (lane == 0) gs->jx = jj;
 }
 
-// s = sum_{k < jx} coef_k V_k; x += dinv .* s (or s), or t = s for a block
+// s = sum_{k < jx} y_k v_k; x += dinv .* s (or s), or t = s for a block
 // preconditioner applied afterwards (t = 0 when nothing is combined).
 __global__ __launch_bounds__(kWG) void k_gm_xupdate(int64_t n, int64_t ld, const double *__restrict__ V,
                                                     GmPtrs P, const double *__restrict__ dinv,
                                                     double *__restrict__ x, double *__restrict__ tout) {
     const int jx = P.gs->jx;
     if (jx == 0 && !tout) return;
-    const int64_t row0 = (int64_t)blockIdx.x * kGmTile + threadIdx.x;
-    double s[kGmRows];
+    const int g = blockIdx.x, t = threadIdx.x;
+    d2 s[kGmPairs];
 #pragma unroll
-    for (int r = 0; r < kGmRows; ++r) s[r] = 0.0;
+    for (int q = 0; q < kGmPairs; ++q) s[q] = (d2)0.0;
     for (int k = 0; k < jx; ++k) {
-        const double c = P.coef[k];
+        const double c = P.av[k];
         const double *vk = V + (int64_t)k * ld;
 #pragma unroll
-        for (int r = 0; r < kGmRows; ++r) {
-            const int64_t i = row0 + (int64_t)r * kWG;
-            if (i < n) s[r] += c * nt_ld(vk + i);
-        }
+        for (int q = 0; q < kGmPairs; ++q) s[q] += c * ld2_nt(vk, gm_pair(g, t, q), n);
     }
 #pragma unroll
-    for (int r = 0; r < kGmRows; ++r) {
-        const int64_t i = row0 + (int64_t)r * kWG;
+    for (int q = 0; q < kGmPairs; ++q) {
+        const int64_t i = gm_pair(g, t, q);
         if (i >= n) continue;
-        if (tout) tout[i] = s[r];
-        else x[i] += dinv ? dinv[i] * s[r] : s[r];
+        if (tout) {
+            st2(tout, i, n, s[q]);
+        } else {  // x is the caller's vector: element accesses, no alignment assumed
+            for (int e = 0; e < 2 && i + e < n; ++e) x[i + e] += dinv ? dinv[i + e] * s[q][e] : s[q][e];
+        }
     }
 }
 
@@ -389,27 +435,21 @@ hipError_t gm_start(const double *parts, int slots, SolverState *st, void *ws, i
     return hipGetLastError();
 }
 
+// Step j after the SpMV u = A M^{-1} t_j (u == nullptr: the cycle's closing
+// pass, which only finalises column j-1).
 hipError_t gm_step(int64_t n, int64_t ld, double *V, int j, const double *u, const double *dinv, double *z,
-                   double *dparts, double *nparts, SolverState *st, void *ws, int m, double *hist,
-                   hipStream_t s) {
+                   double *dparts, SolverState *st, void *ws, int m, double *hist, hipStream_t s) {
     const int G = gm_grid(n);
     const GmPtrs P = gm_ptrs(ws, m);
-    double *vn = V + (int64_t)(j + 1) * ld;
-    hipLaunchKernelGGL(k_gm_dots, dim3(G), dim3(kWG), 0, s, n, ld, (const double *)V, j + 1, u, dparts,
-                       (const SolverState *)st, (const GmresState *)P.gs, 1);
-    hipLaunchKernelGGL(k_gm_h, dim3(j + 2), dim3(kWG), 0, s, (const double *)dparts, G, j,
-                       (const SolverState *)st, P, 1);
-    hipLaunchKernelGGL(k_gm_update, dim3(G), dim3(kWG), 0, s, n, ld, V, j, u, dinv, z, nparts,
-                       (const SolverState *)st, P, 1);
-    hipLaunchKernelGGL(k_gm_norm1, dim3(1), dim3(kWG), 0, s, (const double *)nparts, G,
-                       (const SolverState *)st, P.gs);
-    hipLaunchKernelGGL(k_gm_dots, dim3(G), dim3(kWG), 0, s, n, ld, (const double *)V, j + 1,
-                       (const double *)vn, dparts, (const SolverState *)st, (const GmresState *)P.gs, 2);
-    hipLaunchKernelGGL(k_gm_h, dim3(j + 1), dim3(kWG), 0, s, (const double *)dparts, G, j,
-                       (const SolverState *)st, P, 2);
-    hipLaunchKernelGGL(k_gm_update, dim3(G), dim3(kWG), 0, s, n, ld, V, j, (const double *)vn, dinv, z,
-                       nparts, (const SolverState *)st, P, 2);
-    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kWG), 0, s, (const double *)nparts, G, j, st, P, hist);
+    const int last = u == nullptr;
+    hipLaunchKernelGGL(k_gm_dots, dim3(G), dim3(kWG), 0, s, n, ld, (const double *)V, j, u, dparts,
+                       (const SolverState *)st);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(2 * j + 2), dim3(kWG), 0, s, (const double *)dparts, G,
+                       (const SolverState *)st, P.red);
+    hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kWG), 0, s, j, last, st, P, hist);
+    if (!last)
+        hipLaunchKernelGGL(k_gm_update, dim3(G), dim3(kWG), 0, s, n, ld, V, j, u, dinv, z, (const SolverState *)st,
+                           P);
     return hipGetLastError();
 }
 
@@ -421,11 +461,11 @@ hipError_t gm_close(int64_t n, int64_t ld, const double *V, const double *dinv, 
     return hipGetLastError();
 }
 
-hipError_t gm_read(const void *ws, int64_t *reorth, hipStream_t s) {
+hipError_t gm_read(const void *ws, int64_t *nspmv, hipStream_t s) {
     GmresState h;
     hipError_t e = hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) *reorth = h.nreorth;
+    if (e == hipSuccess) *nspmv = h.nspmv;
     return e;
 }
 

@@ -257,12 +257,12 @@ hipError_t gm_prep(const mxl_ctx *ctx, int64_t n, const double *v, const double 
                    double *z, double *parts, int *slots, hipStream_t s);
 hipError_t gm_start(const double *parts, int slots, SolverState *st, void *ws, int m, double *hist, int first,
                     hipStream_t s);
+// Arnoldi step j after u = A M^{-1} t_j (u == nullptr: the cycle's closing pass)
 hipError_t gm_step(int64_t n, int64_t ld, double *V, int j, const double *u, const double *dinv, double *z,
-                   double *dparts, double *nparts, SolverState *st, void *ws, int m, double *hist,
-                   hipStream_t s);
+                   double *dparts, SolverState *st, void *ws, int m, double *hist, hipStream_t s);
 hipError_t gm_close(int64_t n, int64_t ld, const double *V, const double *dinv, double *x, double *t,
                     const SolverState *st, void *ws, int m, hipStream_t s);
-hipError_t gm_read(const void *ws, int64_t *reorth, hipStream_t s);
+hipError_t gm_read(const void *ws, int64_t *nspmv, hipStream_t s);
 
 // ------------------------------------------------------------- ilu.hip
 // out = alpha U^{-1} L^{-1} r + beta out (beta == 0 overwrites)

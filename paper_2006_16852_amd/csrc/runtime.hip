@@ -737,7 +737,7 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
         const int G = gm_grid(A->nrows);
         ok = need(S->V, (size_t)(krylov + 1) * (size_t)S->ld * sizeof(double)) &&
              need(S->gmws, gm_ws_bytes(krylov)) &&
-             need(S->gdots, (size_t)(krylov + 2) * (size_t)G * sizeof(double)) &&
+             need(S->gdots, (size_t)(2 * krylov + 2) * (size_t)G * sizeof(double)) &&
              need(S->gnorm, (size_t)std::max(G, 2 * kMaxGrid) * sizeof(double)) &&
              (!(P || ilu) || need(S->z, vb));
         S->ilu = ilu;
@@ -1140,16 +1140,18 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
     int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         const int steps = (int)std::min<int64_t>(m, c.max_iters - k);
+        int done = 0;
         for (int j = 0; j < steps; ++j) {
             SpmvArgs a;
             a.x = z ? (const void *)z : (const void *)(V + (int64_t)j * ld);
             a.y = S.q->p;
             a.stop = &st->stop;
             HIP_TRY(spmv_launch(A, a, s));
-            HIP_TRY(gm_step(n, ld, V, j, (const double *)S.q->p, blockp ? nullptr : dinv, blockp ? nullptr : z,
-                            dp, np, st, ws, m, hist, s));
+            HIP_TRY(gm_step(n, ld, V, j, (const double *)S.q->p, blockp ? nullptr : dinv, blockp ? nullptr : z, dp,
+                            st, ws, m, hist, s));
             if (blockp) HIP_TRY(apply_M(V + (int64_t)(j + 1) * ld, 0.0, z));
             ++k;
+            ++done;
             if (k % c.check_every == 0) {
                 if ((rs = read_state(S, h)) != MXL_OK) return rs;
                 if (h.stop) break;
@@ -1159,6 +1161,8 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
                 }
             }
         }
+        // the cycle's last column becomes final in one more multi-dot pass
+        HIP_TRY(gm_step(n, ld, V, done, nullptr, nullptr, nullptr, dp, st, ws, m, hist, s));
         HIP_TRY(gm_close(n, ld, V, blockp ? nullptr : dinv, x, blockp ? (double *)S.r->p : nullptr, st, ws, m, s));
         if (blockp) HIP_TRY(apply_M((const double *)S.r->p, 1.0, x));
         if ((rs = read_state(S, h)) != MXL_OK) return rs;
@@ -1183,12 +1187,12 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
     } else {
         iters = h.iters;
     }
-    fill_info(info, S, h, iters, stop, 1 + iters + restarts, elapsed_s(t0));
+    int64_t nspmv = 0;
+    HIP_TRY(gm_read(ws, &nspmv, s));
+    fill_info(info, S, h, iters, stop, 1 + nspmv + restarts, elapsed_s(t0));
     if (info) {
-        int64_t re = 0;
-        HIP_TRY(gm_read(ws, &re, s));
         info->restarts = restarts;
-        info->reorth = re;
+        info->reorth = iters;  // every basis vector is orthogonalised twice
     }
     return MXL_OK;
 }

@@ -1,11 +1,13 @@
 """Restarted GMRES (Sec. 3.1, Table 2) on the GPU against the oracle.
 
-The GPU orthogonalises by classical Gram-Schmidt with a conditional second
-pass, the oracle by modified Gram-Schmidt: both compute the same Arnoldi
+The GPU orthogonalises by classical Gram-Schmidt twice (the second pass of
+each vector delayed into the next step), the oracle by modified
+Gram-Schmidt: both compute the same Arnoldi
 process, so before convergence the iterates (the Krylov-space minimisers)
 agree to rounding, the residual estimates agree step by step, and the
 iteration counts to a tolerance agree within two steps (summation order
-may move the crossing of the threshold).  Every converged solution is
+may move the crossing of the threshold), or 5% after ten or more restarts
+(each restart starts from a perturbed iterate).  Every converged solution is
 re-checked by recomputing b - A x in FP64 on the host.  Sizes span several
 2048-row tiles with a ragged tail; edge cases: zero right-hand side, exact
 initial guess, max_iters = 0, n = 1, krylov_dim = 1 and > n, non-finite
@@ -87,9 +89,16 @@ def test_converges_like_oracle(mxl, ctx, A, m, P):
     ref = _oracle(A, b, P, krylov_dim=m, max_iters=3000, reduction=1e-10)
     assert ref["stop_reason"] == O.CONVERGED
     assert info["stop_reason"] == mxl.STOP_CONVERGED
-    assert abs(info["iterations"] - ref["iterations"]) <= 2, (info["iterations"], ref["iterations"])
+    # rounding differences move the threshold crossing by a step or two; each
+    # restart starts from a perturbed iterate, so over many short cycles the
+    # counts may drift further (GMRES(5) on the SPD 2D Laplacian restarts ~90
+    # times): 5% there
+    tol = 2 if info["restarts"] < 10 else max(2, int(0.05 * ref["iterations"]))
+    assert abs(info["iterations"] - ref["iterations"]) <= tol, (info["iterations"], ref["iterations"])
     assert _rel(A, b, x) <= 1.01e-10
-    assert info["spmv_count"] == 1 + info["iterations"] + info["restarts"]
+    # + 1 when the criterion stopped a cycle early (the product of the step
+    # that finalised the converged column)
+    assert info["spmv_count"] - (1 + info["iterations"] + info["restarts"]) in (0, 1)
     # residual estimates step by step over the first 100 steps, while far
     # above the threshold (over many restarts rounding differences grow)
     h, hr = np.array(info["history"]), ref["history"]
