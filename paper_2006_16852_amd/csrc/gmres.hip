@@ -51,8 +51,9 @@ struct GmresState {
 };
 
 struct GmPtrs {
-    double *H;    // (m+1) x m Hessenberg matrix, column j at H + (m+1) j
-    double *R;    // the same columns after the Givens rotations
+    double *H;    // (m+1) x m Hessenberg matrix, column j at H + (m+1) j (final columns)
+    double *Ht;   // the tentative column j of step j (before its re-orthogonalisation)
+    double *R;    // the final columns after the Givens rotations
     double *cs, *sn;
     double *g;    // m+1: rotated right-hand side beta e_1
     double *sv;   // m+1: re-orthogonalisation coefficients s_k
@@ -63,7 +64,7 @@ struct GmPtrs {
 };
 
 size_t gm_ws_bytes(int m) {
-    const size_t d = 2 * (size_t)(m + 1) * m + 2 * (size_t)m + 3 * (size_t)(m + 1) + 2 * (size_t)(m + 1);
+    const size_t d = 3 * (size_t)(m + 1) * m + 2 * (size_t)m + 3 * (size_t)(m + 1) + 2 * (size_t)(m + 1);
     return d * sizeof(double) + 256;
 }
 
@@ -73,6 +74,8 @@ static GmPtrs gm_ptrs(void *ws, int m) {
     P.m = m;
     double *d = (double *)((char *)ws + 256);
     P.H = d;
+    d += (size_t)(m + 1) * m;
+    P.Ht = d;
     d += (size_t)(m + 1) * m;
     P.R = d;
     d += (size_t)(m + 1) * m;
@@ -235,99 +238,119 @@ __global__ __launch_bounds__(kWG) void k_gm_reduce(const double *__restrict__ pa
     if (threadIdx.x == 0) red[v] = s[0];
 }
 
-// Step j's scalar work (one workgroup): beta; column j-1 final (+ s,
-// h_{j,j-1} = beta), its Givens rotation, residual estimate and criteria
-// (in the oracle's order); then, unless last (the cycle's closing pass),
-// (Hs), column j and the coefficients of the update.
+// Step j's scalar work, one launch of j+2 workgroups (1 for the closing
+// pass).  Workgroups l = 0..j form (Hs)_l = sum_{k<j} h_lk s_k over the
+// final columns (column j-1 = its tentative values + s, h_{j,j-1} = beta)
+// and the tentative column j: h_lj = (c_l - (Hs)_l) / beta (l < j),
+// h_jj = ((tau - s.c) / beta - (Hs)_j) / beta, with the update's
+// coefficients.  The last workgroup writes the final column j-1, rotates it
+// (the earlier rotations and a new one), and applies the residual estimate
+// and the criteria in the oracle's order; for j = 0 it sets g_0 = beta.
+// Every workgroup recomputes beta = sqrt(t.t - |s|^2) itself.  No workgroup
+// reads what another one writes: final columns go to H, tentative ones to
+// Ht, and column j-1 is read from Ht.
 __global__ __launch_bounds__(kWG) void k_gm_finish(int j, int last, SolverState *st, GmPtrs P, double *hist) {
     if (st->stop) return;
-    __shared__ double hs[kGmMaxKrylov + 1];
-    __shared__ double bsh[1];
-    __shared__ int stopped[1];
+    __shared__ double col[kGmMaxKrylov + 1], rc[kGmMaxKrylov], rs[kGmMaxKrylov];
     GmresState *gs = P.gs;
     const int64_t ldh = P.m + 1;
     const int t = threadIdx.x;
+    const bool givens = last || (int)blockIdx.x == j + 1;
     double part[2] = {0.0, 0.0};  // |s|^2, s.c
     for (int k = t; k < j; k += kWG) {
-        const double s = P.red[2 * k];
-        part[0] += s * s;
-        if (!last) part[1] += s * P.red[2 * k + 1];
+        const double sk = P.red[2 * k];
+        part[0] += sk * sk;
+        if (!givens) part[1] += sk * P.red[2 * k + 1];
     }
     block_reduce<2>(part);
+    __shared__ double bsh[2];
     if (t == 0) {
         const double b2 = P.red[2 * j] - part[0];
         // b2 <= 0: the candidate lies in the span (happy breakdown); NaN stays NaN
-        const double beta = b2 <= 0.0 ? 0.0 : sqrt(b2);
-        bsh[0] = beta;
-        gs->beta = beta;
-        stopped[0] = 0;
-        if (!last) gs->nspmv += 1;  // this step's SpMV ran (the solve had not stopped)
+        bsh[0] = b2 <= 0.0 ? 0.0 : sqrt(b2);
+        bsh[1] = part[1];
+    }
+    __syncthreads();
+    const double beta = bsh[0];
+    if (givens) {
         if (j == 0) {
-            P.g[0] = beta;
-        } else {
-            // column j-1 final; rotate a copy of it
-            double *h = P.H + ldh * (j - 1), *r = P.R + ldh * (j - 1);
-            for (int k = 0; k < j; ++k) h[k] += P.red[2 * k];
-            h[j] = beta;
-            for (int k = 0; k <= j; ++k) r[k] = h[k];
-            const int c0 = j - 1;
-            for (int i = 0; i < c0; ++i) {
-                const double a = r[i], c = r[i + 1];
-                r[i] = P.cs[i] * a + P.sn[i] * c;
-                r[i + 1] = -P.sn[i] * a + P.cs[i] * c;
+            if (t == 0) {
+                P.g[0] = beta;
+                if (!last) gs->nspmv += 1;
             }
-            const double a = r[c0];
-            const double d = hypot(a, beta);
-            const double cc = d == 0.0 ? 1.0 : a / d, ss = d == 0.0 ? 0.0 : beta / d;
-            P.cs[c0] = cc;
-            P.sn[c0] = ss;
-            r[c0] = d;
-            r[c0 + 1] = 0.0;
-            const double gj = P.g[c0];
-            const double gn = -ss * gj;
-            P.g[c0 + 1] = gn;
-            P.g[c0] = cc * gj;
-            const int k = gs->k + 1;
-            gs->k = k;
-            gs->j = j;
-            st->iters = k;
-            st->rr = gn * gn;
-            const double nb = sqrt(st->nb2);
-            const double rel = fabs(gn) / nb;
-            if (hist) hist[k] = rel;
-            const bool chk = st->nonfinite_check != 0;
-            int stop = ST_RUN;
-            if (chk && (!finite_d(rel) || !finite_d(d))) stop = ST_NONFINITE;
-            else if (fabs(gn) <= st->red * nb) stop = ST_CONVERGED;
-            else if (beta == 0.0 || d == 0.0) stop = ST_BREAKDOWN;
-            if (stop != ST_RUN) {
-                st->stop = stop;
-                stopped[0] = 1;
+            return;
+        }
+        // final column j-1 and the earlier rotations, staged in LDS
+        const double *ht = P.Ht + ldh * (j - 1);
+        for (int k = t; k < j; k += kWG) {
+            col[k] = ht[k] + P.red[2 * k];
+            if (k < j - 1) {
+                rc[k] = P.cs[k];
+                rs[k] = P.sn[k];
             }
         }
+        if (t == 0) col[j] = beta;
+        __syncthreads();
+        double *h = P.H + ldh * (j - 1), *r = P.R + ldh * (j - 1);
+        for (int k = t; k <= j; k += kWG) h[k] = col[k];
+        if (t != 0) return;
+        if (!last) gs->nspmv += 1;  // this step's SpMV ran (the solve had not stopped)
+        const int c0 = j - 1;
+        for (int i = 0; i < c0; ++i) {
+            const double a = col[i], c = col[i + 1];
+            col[i] = rc[i] * a + rs[i] * c;
+            col[i + 1] = -rs[i] * a + rc[i] * c;
+        }
+        const double a = col[c0];
+        const double d = hypot(a, beta);
+        const double cc = d == 0.0 ? 1.0 : a / d, ss = d == 0.0 ? 0.0 : beta / d;
+        P.cs[c0] = cc;
+        P.sn[c0] = ss;
+        col[c0] = d;
+        col[c0 + 1] = 0.0;
+        for (int k = 0; k <= j; ++k) r[k] = col[k];
+        const double gj = P.g[c0];
+        const double gn = -ss * gj;
+        P.g[c0 + 1] = gn;
+        P.g[c0] = cc * gj;
+        const int k = gs->k + 1;
+        gs->k = k;
+        gs->j = j;
+        st->iters = k;
+        st->rr = gn * gn;
+        const double nb = sqrt(st->nb2);
+        const double rel = fabs(gn) / nb;
+        if (hist) hist[k] = rel;
+        const bool chk = st->nonfinite_check != 0;
+        if (chk && (!finite_d(rel) || !finite_d(d))) st->stop = ST_NONFINITE;
+        else if (fabs(gn) <= st->red * nb) st->stop = ST_CONVERGED;
+        else if (beta == 0.0 || d == 0.0) st->stop = ST_BREAKDOWN;
+        return;
     }
-    __syncthreads();
-    if (last || stopped[0]) return;
-    const double beta = bsh[0];
-    // (Hs)_l = sum_{k<j} h_lk s_k over the final columns 0..j-1 (h_lk = 0 for l > k+1)
-    for (int l = t; l <= j; l += kWG) {
-        double a = 0.0;
-        for (int k = l > 0 ? l - 1 : 0; k < j; ++k) a += P.H[l + ldh * k] * P.red[2 * k];
-        hs[l] = a;
+    // workgroup l: (Hs)_l over columns max(l-1, 0) .. j-1
+    const int l = blockIdx.x;
+    double hsl[1] = {0.0};
+    for (int k = (l > 0 ? l - 1 : 0) + t; k < j; k += kWG) {
+        double hlk;
+        if (k < j - 1) hlk = P.H[l + ldh * k];
+        else hlk = l < j ? P.Ht[l + ldh * k] + P.red[2 * l] : beta;  // column j-1
+        hsl[0] += hlk * P.red[2 * k];
     }
-    __syncthreads();
+    block_reduce<1>(hsl);
+    if (t != 0) return;
+    const double hs = hsl[0];
     const double ib = 1.0 / beta;
-    double *hc = P.H + ldh * j;
-    for (int k = t; k < j; k += kWG) {
-        const double h = (P.red[2 * k + 1] - hs[k]) * ib;
-        hc[k] = h;
-        P.sv[k] = P.red[2 * k];
-        P.av[k] = hs[k] * ib + h;
-    }
-    if (t == 0) {
-        const double hjj = ((P.red[2 * j + 1] - part[1]) * ib - hs[j]) * ib;
+    double *hc = P.Ht + ldh * j;
+    if (l < j) {
+        const double h = (P.red[2 * l + 1] - hs) * ib;
+        hc[l] = h;
+        P.sv[l] = P.red[2 * l];
+        P.av[l] = hs * ib + h;
+    } else {
+        const double hjj = ((P.red[2 * j + 1] - bsh[1]) * ib - hs) * ib;
         hc[j] = hjj;
-        gs->bcoef = hs[j] * ib + hjj;
+        gs->beta = beta;
+        gs->bcoef = hs * ib + hjj;
     }
 }
 
@@ -446,7 +469,7 @@ hipError_t gm_step(int64_t n, int64_t ld, double *V, int j, const double *u, con
                        (const SolverState *)st);
     hipLaunchKernelGGL(k_gm_reduce, dim3(2 * j + 2), dim3(kWG), 0, s, (const double *)dparts, G,
                        (const SolverState *)st, P.red);
-    hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(kWG), 0, s, j, last, st, P, hist);
+    hipLaunchKernelGGL(k_gm_finish, dim3(last ? 1 : j + 2), dim3(kWG), 0, s, j, last, st, P, hist);
     if (!last)
         hipLaunchKernelGGL(k_gm_update, dim3(G), dim3(kWG), 0, s, n, ld, V, j, u, dinv, z, (const SolverState *)st,
                            P);

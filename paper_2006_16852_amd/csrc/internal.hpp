@@ -123,6 +123,10 @@ struct IluImpl {
     int sweeps = 0, trisolve = 0, trs_sweeps = 0;
     BufPtr lu, dpos, lperm, uperm, y, t, z;
     std::vector<int64_t> lptr, uptr;
+    // slot-major strict triangles and diag(U) for the Jacobi sweeps (optional)
+    int wl = 0, wu = 0;
+    int64_t n_pad = 0;
+    BufPtr lcol, lval, ucol, uval, udiag;
 };
 
 struct IrImpl;
