@@ -8,7 +8,7 @@
 // Blocks are consecutive ranges of BS rows (BS in {1,...,32}, the last one
 // may be shorter), so a 256-row tile always holds whole blocks.  Every
 // inverse is stored as a BS x BS row-major array (zeros outside a short last
-// block) at byte offset off[b] in the precision prec[b].
+// block) at byte offset off[b] (a multiple of 16) in the precision prec[b].
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -165,25 +165,38 @@ __global__ void k_bj_pack(int64_t nb, const double *__restrict__ inv, const int 
 }
 
 // Row t of block b's stored inverse times the block's vector part held in
-// LDS (xs[0..BS)), summed over ascending columns in FP64.
+// LDS (xs[0..BS)), summed over ascending columns in FP64.  Blocks start at
+// 16-byte-aligned offsets, so a row whose bytes are a multiple of 16 is
+// read with 16-byte vector loads (8 binary16, 4 binary32 or 2 binary64
+// values each); other rows element by element.
+template <typename T, int BS>
+__device__ __forceinline__ double bj_row_t(const unsigned char *__restrict__ base, int t, const double *xs) {
+    constexpr int E = 16 / (int)sizeof(T);
+    double s = 0.0;
+    if constexpr (BS * sizeof(T) % 16 == 0) {
+        typedef T TV __attribute__((ext_vector_type(E)));
+        const TV *rp = (const TV *)base + t * (BS / E);
+#pragma unroll
+        for (int c = 0; c < BS / E; ++c) {
+            const TV v = rp[c];
+#pragma unroll
+            for (int e = 0; e < E; ++e) s += (double)v[e] * xs[c * E + e];
+        }
+    } else {
+        const T *rp = (const T *)base + t * BS;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) s += (double)rp[j] * xs[j];
+    }
+    return s;
+}
+
 template <int BS>
 __device__ __forceinline__ double bj_row(const unsigned char *__restrict__ store, int64_t off, int pr,
                                          int t, const double *xs) {
-    double s = 0.0;
-    if (pr == BJ_P16) {
-        const _Float16 *rowp = (const _Float16 *)(store + off) + t * BS;
-#pragma unroll
-        for (int j = 0; j < BS; ++j) s += (double)rowp[j] * xs[j];
-    } else if (pr == BJ_P32) {
-        const float *rowp = (const float *)(store + off) + t * BS;
-#pragma unroll
-        for (int j = 0; j < BS; ++j) s += (double)rowp[j] * xs[j];
-    } else {
-        const double *rowp = (const double *)(store + off) + t * BS;
-#pragma unroll
-        for (int j = 0; j < BS; ++j) s += rowp[j] * xs[j];
-    }
-    return s;
+    const unsigned char *base = store + off;
+    if (pr == BJ_P16) return bj_row_t<_Float16, BS>(base, t, xs);
+    if (pr == BJ_P32) return bj_row_t<float, BS>(base, t, xs);
+    return bj_row_t<double, BS>(base, t, xs);
 }
 
 // z = M r on 256-row tiles (whole blocks): each wave parks its 64 values of
@@ -432,13 +445,13 @@ extern "C" mxl_status mxl_bjacobi_generate(const mxl_op *Aop, int32_t block_size
         snprintf(msg, sizeof msg, "diagonal block %d is singular", hb);
         return set_error(MXL_ERR_ZERO_DIAG, msg);
     }
-    // byte offsets: each block padded to a multiple of 8 bytes
+    // byte offsets: each block padded to a multiple of 16 bytes (vector row loads)
     std::vector<int64_t> ho((size_t)nb);
     int64_t total = 0;
     for (int64_t b = 0; b < nb; ++b) {
         ho[b] = total;
         const int64_t sz = (int64_t)bs * bs * (hp[b] == BJ_P16 ? 2 : hp[b] == BJ_P32 ? 4 : 8);
-        total += (sz + 7) / 8 * 8;
+        total += (sz + 15) / 16 * 16;
     }
     J->bstore = mk((size_t)total);
     if (!J->bstore) return set_error(MXL_ERR_OUT_OF_MEMORY, "block Jacobi storage");

@@ -59,7 +59,7 @@ def test_generation_parity(mxl, ctx, A, bs, adaptive):
     assert np.array_equal(info["inv"], inv), np.abs(info["inv"] - inv).max()
     sizes = np.diff(bp).astype(np.int64)
     per = np.where(prec == O.P16, 2, np.where(prec == O.P32, 4, 8))
-    assert info["storage_bytes"] == int(((bs * bs * per + 7) // 8 * 8).sum())
+    assert info["storage_bytes"] == int(((bs * bs * per + 15) // 16 * 16).sum())
     # the product z = M r
     r = W.uniform_vec(A.nrows, 9)
     want = O.bj_apply(bp, inv, r)
