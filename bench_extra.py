@@ -152,8 +152,9 @@ def poisson2d(args):
     P = mxl.jacobi(M)
     x = torch.zeros_like(b)
     res = {}
-    for mode, name in ((1, "per_step_kernels"), (2, "one_workgroup")):
-        S = mxl.solver("cg", M, P, max_iters=5000, reduction=1e-10, check_every=32, launch_mode=mode)
+    for kind, mode, name in (("cg", 1, "per_step_kernels"), ("cg", 2, "one_workgroup"),
+                             ("bicgstab", 1, "bicgstab_per_step_kernels"), ("bicgstab", 2, "bicgstab_one_workgroup")):
+        S = mxl.solver(kind, M, P, max_iters=5000, reduction=1e-10, check_every=32, launch_mode=mode)
 
         def f():
             x.zero_()
@@ -248,6 +249,7 @@ def overhead(args):
     iters = 1000
     res = {}
     for kind, mode, name in (("cg", 2, "cg_one_workgroup"), ("cg", 1, "cg_per_step_kernels"),
+                             ("bicgstab", 2, "bicgstab_one_workgroup"),
                              ("bicgstab", 1, "bicgstab_per_step_kernels"),
                              ("gmres", 1, "gmres100_per_step_kernels")):
         S = mxl.solver(kind, M, None, max_iters=iters, nonfinite_check=0, check_every=iters,

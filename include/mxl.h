@@ -103,10 +103,13 @@ typedef struct {
     double  time_limit_s;
     int32_t check_every;
     int32_t nonfinite_check;
-    int32_t launch_mode;   /* CG only: 0 auto, 1 one kernel per step, 2 the
-                              whole solve in one persistent workgroup (FP64,
-                              n <= 16384, max_iters >= 1, no Time criterion
-                              and no history); auto picks 2 for n <= 8192 */
+    int32_t launch_mode;   /* CG and BiCGSTAB: 0 auto, 1 one kernel per step,
+                              2 the whole solve in one persistent workgroup
+                              (FP64, point Jacobi or none, max_iters >= 1, no
+                              Time criterion and no history; CG n <= 16384,
+                              BiCGSTAB n <= 4096 with <= 5 entries per row
+                              (<= 8 for n <= 1024), else per step); auto
+                              picks 2 for n <= 8192 */
 } mxl_criteria;
 
 /* Convergence record (the Convergence logger of Sec. 2.6) plus an optional

@@ -414,7 +414,7 @@ def bjacobi(A: Op, block_size: int = 8, adaptive: bool = True, accuracy: float =
 
 def criteria(max_iters=10_000, reduction=1e-10, time_limit=0.0, check_every=1,
              nonfinite_check=1, launch_mode=0) -> Criteria:
-    """launch_mode (CG): 0 auto, 1 one kernel per step, 2 one persistent workgroup."""
+    """launch_mode (CG, BiCGSTAB): 0 auto, 1 one kernel per step, 2 one persistent workgroup."""
     return Criteria(max_iters, reduction, time_limit, check_every, nonfinite_check, launch_mode)
 
 

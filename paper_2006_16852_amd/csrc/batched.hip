@@ -40,6 +40,7 @@ struct BatchImpl {
     bool tuned = false;
     mxl_tuning best{};
     int small_shape = -1;    // single-system register-cached shape (-1: not chosen)
+    int small_bi_shape = -1; // the same for the one-workgroup BiCGSTAB
 };
 
 template <int B>
@@ -355,6 +356,160 @@ __global__ __launch_bounds__(B) void k_small_pcg(int n, const int *__restrict__ 
         *(int32_t *)out3 = (int32_t)k;
         *(double *)((char *)out3 + 8) = nb > 0.0 ? sqrt(rr) / nb : 0.0;
         *((uint8_t *)out3 + 16) = (uint8_t)stop;
+    }
+}
+
+// Whole Jacobi-BiCGSTAB of one small system in one workgroup, the steps
+// and checks of the per-step solver in its order (right preconditioning,
+// half-step exit x += alpha p_hat when ||s|| meets the criterion).  Thread t
+// owns rows t + j*B (j < RPT): their entries and r, r_hat, p, v, x and dinv
+// stay in registers; the vector the product gathers (p_hat, then s_hat) is
+// mirrored in LDS.  out3: iterations (int32 at 0), relative residual
+// (double at 8), status (byte 16), half step (byte 17).
+template <int B, int RPT, int W>
+__global__ __launch_bounds__(B) void k_small_bicgstab(int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ col,
+                                                      const double *__restrict__ val,
+                                                      const double *__restrict__ dinv,
+                                                      const double *__restrict__ b,
+                                                      double *__restrict__ xio, double red_factor,
+                                                      int64_t maxit, int chk, void *__restrict__ out3) {
+    extern __shared__ double pl[];
+    __shared__ double red[2 * (B / kWave)];
+    const int tid = threadIdx.x;
+    int c[RPT][W];
+    double a[RPT][W];
+    double r[RPT], rh[RPT], p[RPT], v[RPT], x[RPT], dv[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * B;
+        const bool own = i < n;
+        dv[j] = own ? dinv[i] : 0.0;
+        x[j] = own ? xio[i] : 0.0;
+        const int e0 = own ? rp[i] : 0, e1 = own ? rp[i + 1] : 0;
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool in = e0 + e < e1;
+            c[j][e] = in ? col[e0 + e] : (own ? i : 0);  // padding: own row, value 0
+            a[j][e] = in ? val[e0 + e] : 0.0;
+        }
+        if (own) pl[i] = x[j];
+    }
+    __syncthreads();
+    double rr = 0.0, bb = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * B;
+        double ax = 0.0;
+#pragma unroll
+        for (int e = 0; e < W; ++e) ax += a[j][e] * pl[c[j][e]];
+        const double bi = i < n ? b[i] : 0.0;
+        r[j] = bi - ax;
+        rh[j] = r[j];
+        p[j] = 0.0;
+        v[j] = 0.0;
+        rr += r[j] * r[j];
+        bb += bi * bi;
+    }
+    wg_sum2<B>(rr, bb, red);
+    const double nb = sqrt(bb);
+    const double tol = red_factor * nb;
+    int stop = ST_RUN, half = 0;
+    int64_t k = 0;
+    if (bb == 0.0) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) x[j] = 0.0;
+        stop = ST_CONVERGED;
+    } else if (sqrt(rr) <= tol) {
+        stop = ST_CONVERGED;
+    }
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    while (stop == ST_RUN && k < maxit) {
+        double rho = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) rho += rh[j] * r[j];
+        rho = wg_sum<B>(rho, red);
+        if (chk && !finite_d(rho)) { stop = ST_NONFINITE; break; }
+        if (rho == 0.0) { stop = ST_BREAKDOWN; break; }
+        const double beta = (rho / rho_old) * (alpha / omega);
+        __syncthreads();  // the previous product's reads of pl are done
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            p[j] = r[j] + beta * (p[j] - omega * v[j]);
+            if (tid + j * B < n) pl[tid + j * B] = dv[j] * p[j];
+        }
+        __syncthreads();
+        double rv = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            double q = 0.0;
+#pragma unroll
+            for (int e = 0; e < W; ++e) q += a[j][e] * pl[c[j][e]];
+            v[j] = q;
+            rv += rh[j] * q;
+        }
+        rv = wg_sum<B>(rv, red);
+        if (chk && !finite_d(rv)) { stop = ST_NONFINITE; break; }
+        if (rv == 0.0) { stop = ST_BREAKDOWN; break; }
+        alpha = rho / rv;
+        double ss = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            r[j] = r[j] - alpha * v[j];  // s
+            ss += r[j] * r[j];
+        }
+        ++k;
+        ss = wg_sum<B>(ss, red);
+        if (sqrt(ss) <= tol) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) x[j] += alpha * (dv[j] * p[j]);
+            rr = ss;
+            half = 1;
+            stop = ST_CONVERGED;
+            break;
+        }
+        __syncthreads();  // all reads of p_hat done
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            if (tid + j * B < n) pl[tid + j * B] = dv[j] * r[j];
+        __syncthreads();
+        double tt = 0.0, ts = 0.0, t[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            double q = 0.0;
+#pragma unroll
+            for (int e = 0; e < W; ++e) q += a[j][e] * pl[c[j][e]];
+            t[j] = q;
+            tt += q * q;
+            ts += q * r[j];
+        }
+        wg_sum2<B>(tt, ts, red);
+        if (chk && (!finite_d(tt) || !finite_d(ts))) { stop = ST_NONFINITE; break; }
+        if (tt == 0.0) { stop = ST_BREAKDOWN; break; }
+        omega = ts / tt;
+        double rn = 0.0;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            x[j] += alpha * (dv[j] * p[j]) + omega * (dv[j] * r[j]);
+            r[j] = r[j] - omega * t[j];
+            rn += r[j] * r[j];
+        }
+        rn = wg_sum<B>(rn, red);
+        rr = rn;
+        if (chk && !finite_d(rn)) { stop = ST_NONFINITE; break; }
+        if (sqrt(rn) <= tol) { stop = ST_CONVERGED; break; }
+        if (omega == 0.0) { stop = ST_BREAKDOWN; break; }
+        rho_old = rho;
+    }
+    if (stop == ST_RUN) stop = ST_MAX_ITERS;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+        if (tid + j * B < n) xio[tid + j * B] = x[j];
+    if (tid == 0) {
+        *(int32_t *)out3 = (int32_t)k;
+        *(double *)((char *)out3 + 8) = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+        *((uint8_t *)out3 + 16) = (uint8_t)stop;
+        *((uint8_t *)out3 + 17) = (uint8_t)half;
     }
 }
 
@@ -725,6 +880,64 @@ static hipError_t launch_small(const SmallShape &sh, int n, const BatchImpl &Bt,
     MXL_SMALL(256, 4, 32)
 #undef MXL_SMALL
     return hipErrorInvalidValue;
+}
+
+// The whole BiCGSTAB of one system in one workgroup, when a register shape
+// holds it (returns false otherwise; the caller then runs the per-step
+// solver).  x holds the initial guess.
+static const SmallShape kSmallBiShapes[] = {{64, 2, 8}, {256, 4, 8}, {512, 8, 5}};
+
+bool batch_single_bicgstab(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x, void *out3,
+                           int64_t *iters, double *rel, int *stop, int *half, mxl_status *st) {
+    *st = MXL_OK;
+    const int n = (int)Bt.rows;
+    constexpr int NS = (int)(sizeof(kSmallBiShapes) / sizeof(kSmallBiShapes[0]));
+    if (Bt.small_bi_shape < 0) {
+        std::vector<int32_t> rp(n + 1);
+        if (hipMemcpyAsync(rp.data(), Bt.row_ptr->p, (n + 1) * 4, hipMemcpyDeviceToHost, Bt.ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(Bt.ctx->stream) != hipSuccess) {
+            *st = set_error(MXL_ERR_DEVICE, "row pointer read");
+            return true;
+        }
+        int maxlen = 0;
+        for (int i = 0; i < n; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i]);
+        Bt.small_bi_shape = NS;
+        for (int k = 0; k < NS; ++k)
+            if (n <= kSmallBiShapes[k].B * kSmallBiShapes[k].RPT && maxlen <= kSmallBiShapes[k].W &&
+                (size_t)n * 8 <= 60 * 1024) {
+                Bt.small_bi_shape = k;
+                break;
+            }
+    }
+    if (Bt.small_bi_shape >= NS) return false;
+    const SmallShape &sh = kSmallBiShapes[Bt.small_bi_shape];
+    const size_t shm = (size_t)n * sizeof(double);
+    hipStream_t s = Bt.ctx->stream;
+#define MXL_SMALL_BI(BB, RR, WW)                                                                     \
+    if (sh.B == BB && sh.RPT == RR && sh.W == WW)                                                    \
+        hipLaunchKernelGGL((k_small_bicgstab<BB, RR, WW>), dim3(1), dim3(BB), shm, s, n,              \
+                           (const int *)Bt.row_ptr->p, (const int *)Bt.col->p,                       \
+                           (const double *)Bt.val->p, (const double *)Bt.dinv->p, b, x,              \
+                           c.reduction, c.max_iters, c.nonfinite_check, out3);
+    MXL_SMALL_BI(64, 2, 8)
+    MXL_SMALL_BI(256, 4, 8)
+    MXL_SMALL_BI(512, 8, 5)
+#undef MXL_SMALL_BI
+    hipError_t e = hipGetLastError();
+    char h[24];
+    if (e == hipSuccess) e = hipMemcpyAsync(h, out3, 24, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        *st = set_error(MXL_ERR_DEVICE, std::string("small BiCGSTAB: ") + hipGetErrorString(e));
+        return true;
+    }
+    int32_t it;
+    memcpy(&it, h, 4);
+    memcpy(rel, h + 8, 8);
+    *iters = it;
+    *stop = (uint8_t)h[16];
+    *half = (uint8_t)h[17];
+    return true;
 }
 
 mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x,

@@ -167,6 +167,9 @@ mxl_ctx *batch_ctx(const BatchImpl &B);
 std::shared_ptr<BatchImpl> batch_from_matrix(const MatrixImpl &A, const void *dinv);
 mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x,
                               void *out3, int64_t *iters, double *rel, int *stop);
+// One-workgroup BiCGSTAB; false when no register shape holds the system.
+bool batch_single_bicgstab(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x, void *out3,
+                           int64_t *iters, double *rel, int *stop, int *half, mxl_status *st);
 
 struct SpmvArgs {
     double alpha = 1.0, beta = 0.0;

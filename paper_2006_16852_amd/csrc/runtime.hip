@@ -893,7 +893,8 @@ constexpr int64_t kSingleMaxN = 16384;
 
 bool single_launch_ok(const SolverImpl &S, const mxl_solve_info *info) {
     const mxl_criteria &c = S.crit;
-    if (S.kind != MXL_SOLVER_CG || S.A->dtype != MXL_F64 || c.launch_mode == 1) return false;
+    if ((S.kind != MXL_SOLVER_CG && S.kind != MXL_SOLVER_BICGSTAB) || S.A->dtype != MXL_F64 || c.launch_mode == 1)
+        return false;
     if (S.A->format == MXL_FMT_STENCIL) return false;  // the one-launch path reads CSR arrays
     if (S.P && S.P->block) return false;                // and point-Jacobi scaling only
     if (c.max_iters < 1 || c.time_limit_s > 0 || S.A->nrows > kSingleMaxN) return false;
@@ -1005,7 +1006,45 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     return MXL_OK;
 }
 
+// The whole BiCGSTAB in one workgroup for small systems (false: no register
+// shape holds the system; the caller runs the per-step solver).
+bool solve_bicgstab_single(SolverImpl &S, const void *b, void *x, mxl_solve_info *info, mxl_status *st) {
+    auto t0 = std::chrono::steady_clock::now();
+    *st = MXL_OK;
+    if (!S.single) {
+        S.single = batch_from_matrix(*S.A, S.P ? S.P->dinv->p : nullptr);
+        hipError_t e;
+        S.single_out = alloc(64, &e);
+        if (!S.single || !S.single_out) {
+            *st = fail(MXL_ERR_OUT_OF_MEMORY, "single-launch workspace");
+            return true;
+        }
+    }
+    int64_t iters = 0;
+    double rel = 0.0;
+    int stop = 0, half = 0;
+    if (!batch_single_bicgstab(*S.single, S.crit, (const double *)b, (double *)x, S.single_out->p, &iters, &rel,
+                               &stop, &half, st))
+        return false;
+    if (*st != MXL_OK) return true;
+    if (info) {
+        info->iterations = iters;
+        info->spmv_count = 1 + 2 * iters - half;
+        info->rel_residual = rel;
+        info->stop_reason = stop == ST_MAX_ITERS ? MXL_STOP_MAX_ITERS : map_stop(stop);
+        info->seconds = elapsed_s(t0);
+        info->inner_iterations = 0;
+        info->restarts = 0;
+        info->reorth = 0;
+    }
+    return true;
+}
+
 mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve_info *info) {
+    if (single_launch_ok(S, info)) {
+        mxl_status st;
+        if (solve_bicgstab_single(const_cast<SolverImpl &>(S), b, x, info, &st)) return st;
+    }
     auto t0 = std::chrono::steady_clock::now();
     const MatrixImpl &A = *S.A;
     mxl_ctx *ctx = A.ctx;

@@ -128,6 +128,68 @@ def test_single_launch_matches_per_step(mxl, ctx, A):
             assert _true_rel(A, b, x) <= 1.01e-10
 
 
+@pytest.mark.parametrize("A", [W.convdiff_2d5(64), W.convdiff_2d5(20), W.stencil_2d5(11), W.convdiff_2d5(5),
+                               W.convdiff_3d7(9), W.stencil_3d27(5)],
+                         ids=lambda a: a.name)
+def test_single_launch_bicgstab_matches_per_step(mxl, ctx, A):
+    """BiCGSTAB in one workgroup (n <= 4096, shapes of 64, 256 and 512
+    threads; the 27-point case has no shape and runs per step) against the
+    per-step kernels and the oracle, with a nonzero initial guess.  The
+    matrices are well-conditioned: on the anisotropic 1e-4 couplings
+    BiCGSTAB's irregular residual lets rounding move its count by 10%."""
+    b = W.uniform_vec(A.nrows, 2)
+    x0 = W.uniform_vec(A.nrows, 8) * 0.1
+    d, _ = O.jacobi_dinv(A)
+    ref = O.bicgstab(A, b, x0=x0, dinv=d, reduction=1e-10, max_iters=5000)
+    M = matrix(mxl, ctx, A)
+    P = mxl.jacobi(M)
+    for mode in (1, 2):
+        S = mxl.solver("bicgstab", M, P, max_iters=5000, reduction=1e-10, launch_mode=mode)
+        x = dev(x0)
+        info = S.solve(dev(b), x)
+        assert info["stop_reason"] == ref["stop_reason"] == mxl.STOP_CONVERGED, (mode, info)
+        assert _close_iters(info["iterations"], ref["iterations"]), (mode, info["iterations"], ref["iterations"])
+        assert _true_rel(A, b, x.cpu().numpy()) <= 1.01e-10
+        assert info["spmv_count"] in (2 * info["iterations"], 2 * info["iterations"] + 1)
+
+
+def test_single_launch_bicgstab_special_cases(mxl, ctx):
+    """Half-step exit, zero right-hand side, the size-1 NaN protocol with and
+    without the non-finite check, and the iteration limit, in one workgroup."""
+    # a diagonal system: the half step of the first iteration is exact
+    n = 50
+    A = W.Csr(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), 1.0 + np.arange(n) / n, "diag50")
+    b = W.uniform_vec(n, 3)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("bicgstab", M, mxl.jacobi(M), max_iters=100, reduction=1e-12, launch_mode=2)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    ref = O.bicgstab(A, b, dinv=O.jacobi_dinv(A)[0], max_iters=100, reduction=1e-12)
+    assert info["iterations"] == ref["iterations"] == 1 and info["spmv_count"] == ref["spmv_count"] == 2
+    assert np.allclose(x.cpu().numpy(), b / A.val, rtol=1e-14, atol=0)
+    x = dev(np.ones(n))
+    info = S.solve(dev(np.zeros(n)), x)
+    assert info["iterations"] == 0 and info["stop_reason"] == mxl.STOP_CONVERGED and float(x.abs().max()) == 0.0
+    one = W.Csr(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]), "one")
+    M1 = matrix(mxl, ctx, one)
+    for chk, want in ((1, mxl.STOP_NONFINITE), (0, mxl.STOP_MAX_ITERS)):
+        S1 = mxl.solver("bicgstab", M1, None, max_iters=1000, nonfinite_check=chk, launch_mode=2)
+        x1 = torch.zeros(1, dtype=torch.float64, device=DEV)
+        info = S1.solve(dev(np.array([np.nan])), x1)
+        ref = O.bicgstab(one, np.array([np.nan]), max_iters=1000, nonfinite_check=chk)
+        assert info["stop_reason"] == want == ref["stop_reason"]
+        assert info["iterations"] == ref["iterations"]
+    A = W.convdiff_2d5(16)
+    b = W.uniform_vec(A.nrows, 4)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("bicgstab", M, mxl.jacobi(M), max_iters=7, reduction=0.0, launch_mode=2)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    ref = O.bicgstab(A, b, dinv=O.jacobi_dinv(A)[0], max_iters=7, reduction=0.0)
+    assert info["iterations"] == 7 == ref["iterations"] and info["stop_reason"] == mxl.STOP_MAX_ITERS
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-11 * np.linalg.norm(ref["x"])
+
+
 def test_listing_protocol(mxl, ctx):
     g = json.load(open(os.path.join(GOLD, "listing_cg_jacobi.json")))
     A = W.stencil_2d5(32)
