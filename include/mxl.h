@@ -109,7 +109,11 @@ typedef struct {
                               Time criterion and no history; CG n <= 16384,
                               BiCGSTAB n <= 4096 with <= 5 entries per row
                               (<= 8 for n <= 1024), else per step); auto
-                              picks 2 for n <= 8192 */
+                              picks 2 for n <= 8192.  GMRES: 1 launches every
+                              kernel of every step; otherwise each chunk of
+                              check_every steps is captured once as a HIP
+                              graph and replayed (except with an exact ILU
+                              preconditioner) */
 } mxl_criteria;
 
 /* Convergence record (the Convergence logger of Sec. 2.6) plus an optional

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -39,6 +40,8 @@ struct mxl_ctx {
     void *pinned = nullptr;     // host-pinned staging for solver state read-back
     size_t pinned_bytes = 0;
     mxl::BufPtr flush_buf;      // lazily allocated 1 GiB buffer for cache flushes
+    hipStream_t cap_stream = nullptr;  // lazily created stream that graphs are captured on
+                                       // (the caller's stream may be the null stream)
     // The caller's handle plus one count per library object that uses the
     // context: mxl_ctx_destroy drops the caller's count, and the context is
     // freed with the last object, whatever order handles are destroyed in.
@@ -132,6 +135,19 @@ struct IluImpl {
 struct IrImpl;
 struct BatchImpl;
 
+// An instantiated HIP graph (a captured chunk of a solver's launches).
+struct GraphHold {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    GraphHold() = default;
+    GraphHold(const GraphHold &) = delete;
+    GraphHold &operator=(const GraphHold &) = delete;
+    ~GraphHold() {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
 struct SolverImpl {
     int kind = MXL_SOLVER_CG;
     std::shared_ptr<MatrixImpl> A;
@@ -152,6 +168,9 @@ struct SolverImpl {
     int krylov = 0;
     int64_t ld = 0;
     BufPtr V, gmws, gdots, gnorm;
+    // GMRES step chunks captured as graphs, keyed by (first step, count);
+    // their kernels take only solver-owned pointers and the step index
+    std::map<int64_t, std::shared_ptr<GraphHold>> graphs;
 };
 
 struct IrImpl {

@@ -188,6 +188,7 @@ void ctx_release(mxl_ctx *c) {
     if (c->refs.fetch_sub(1) != 1) return;
     DeviceScope ds(c->device);
     c->flush_buf.reset();
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
 }
@@ -1165,6 +1166,25 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
         if (blockp) HIP_TRY(apply_M(V, 0.0, z));
         return MXL_OK;
     };
+    // steps j0 .. j0+cnt-1 of a cycle: the SpMV u = A z (z = M^{-1} t_j, or
+    // t_j itself), the basis kernels, and z for the next step
+    auto enqueue = [&](int j0, int cnt) -> mxl_status {
+        for (int j = j0; j < j0 + cnt; ++j) {
+            SpmvArgs a;
+            a.x = z ? (const void *)z : (const void *)(V + (int64_t)j * ld);
+            a.y = S.q->p;
+            a.stop = &st->stop;
+            HIP_TRY(spmv_launch(A, a, s));
+            HIP_TRY(gm_step(n, ld, V, j, (const double *)S.q->p, blockp ? nullptr : dinv, blockp ? nullptr : z,
+                            dp, st, ws, m, hist, s));
+            if (blockp) HIP_TRY(apply_M(V + (int64_t)(j + 1) * ld, 0.0, z));
+        }
+        return MXL_OK;
+    };
+    // replay captured chunks unless asked for direct launches, or when the
+    // preconditioner is an exact ILU (hundreds of level launches per step)
+    const bool use_graph = c.launch_mode != 1 && !(S.ilu && S.ilu->trisolve == 0);
+    auto &graphs = const_cast<SolverImpl &>(S).graphs;
     HIP_TRY(launch_state_init(st, c.reduction, c.nonfinite_check, s));
     if ((rs = restart(1)) != MXL_OK) return rs;
     SolverState h;
@@ -1180,24 +1200,37 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         const int steps = (int)std::min<int64_t>(m, c.max_iters - k);
         int done = 0;
-        for (int j = 0; j < steps; ++j) {
-            SpmvArgs a;
-            a.x = z ? (const void *)z : (const void *)(V + (int64_t)j * ld);
-            a.y = S.q->p;
-            a.stop = &st->stop;
-            HIP_TRY(spmv_launch(A, a, s));
-            HIP_TRY(gm_step(n, ld, V, j, (const double *)S.q->p, blockp ? nullptr : dinv, blockp ? nullptr : z, dp,
-                            st, ws, m, hist, s));
-            if (blockp) HIP_TRY(apply_M(V + (int64_t)(j + 1) * ld, 0.0, z));
-            ++k;
-            ++done;
-            if (k % c.check_every == 0) {
-                if ((rs = read_state(S, h)) != MXL_OK) return rs;
-                if (h.stop) break;
-                if (c.time_limit_s > 0 && elapsed_s(t0) >= c.time_limit_s) {
-                    stop = MXL_STOP_TIME;
-                    break;
+        for (int j0 = 0; j0 < steps;) {
+            const int cnt = std::min(c.check_every, steps - j0);
+            if (use_graph) {
+                const int64_t key = (int64_t)j0 * 65536 + cnt;
+                auto &G = graphs[key];
+                if (!G) {  // capture the chunk's launches once (on the context's capture stream)
+                    if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+                    auto hold = std::make_shared<GraphHold>();
+                    hipStream_t cs_ = ctx->cap_stream;
+                    HIP_TRY(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
+                    std::swap(s, cs_);  // enqueue launches on s
+                    const mxl_status cs = enqueue(j0, cnt);
+                    std::swap(s, cs_);
+                    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &hold->g);
+                    if (cs != MXL_OK) return cs;
+                    HIP_TRY(ce);
+                    HIP_TRY(hipGraphInstantiate(&hold->e, hold->g, nullptr, nullptr, 0));
+                    G = hold;
                 }
+                HIP_TRY(hipGraphLaunch(G->e, s));
+            } else if ((rs = enqueue(j0, cnt)) != MXL_OK) {
+                return rs;
+            }
+            j0 += cnt;
+            k += cnt;
+            done += cnt;
+            if ((rs = read_state(S, h)) != MXL_OK) return rs;
+            if (h.stop) break;
+            if (c.time_limit_s > 0 && elapsed_s(t0) >= c.time_limit_s) {
+                stop = MXL_STOP_TIME;
+                break;
             }
         }
         // the cycle's last column becomes final in one more multi-dot pass

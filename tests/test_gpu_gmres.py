@@ -134,6 +134,39 @@ def test_check_every_does_not_change_results(mxl, ctx):
         assert np.array_equal(x, xs[0][0]) and it == xs[0][1] and rr == xs[0][2]
 
 
+@pytest.mark.parametrize("P", [None, "jacobi", 4, "ilu"], ids=["none", "jacobi", "bj4", "ilu_jacobi"])
+def test_graph_replays_match_direct_launches(mxl, ctx, P):
+    """The captured step chunks, replayed over several cycles and several
+    solves with other work and synchronisations in between, give exactly
+    the results of direct launches."""
+    A = W.convdiff_2d5(37)
+    b = W.uniform_vec(A.nrows, 12)
+    M = matrix(mxl, ctx, A)
+    if P == "jacobi":
+        Pop = mxl.jacobi(M)
+    elif P == "ilu":
+        Pop = mxl.ilu(M, sweeps=2, trisolve="jacobi", trs_sweeps=2)
+    elif P is None:
+        Pop = None
+    else:
+        Pop = mxl.bjacobi(M, P, True)
+    outs = []
+    for mode in (1, 0):
+        S = mxl.solver("gmres", M, Pop, krylov_dim=15, max_iters=400, reduction=1e-10, check_every=4,
+                       launch_mode=mode)
+        for rep in range(3):
+            x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+            info = S.solve(dev(b), x)
+            y = torch.empty_like(x)
+            M.apply(x, y)  # eager work between replays
+            torch.cuda.synchronize()
+            outs.append((mode, x.cpu().numpy(), info["iterations"], info["rel_residual"], info["spmv_count"]))
+    ref = outs[0]
+    assert ref[2] > 30  # several cycles of 15 steps
+    for mode, x, it, rr, sp in outs[1:]:
+        assert np.array_equal(x, ref[1]) and it == ref[2] and rr == ref[3] and sp == ref[4], mode
+
+
 def test_edge_cases(mxl, ctx):
     A = W.convdiff_2d5(9)
     n = A.nrows
