@@ -251,6 +251,7 @@ def overhead(args):
     for kind, mode, name in (("cg", 2, "cg_one_workgroup"), ("cg", 1, "cg_per_step_kernels"),
                              ("bicgstab", 2, "bicgstab_one_workgroup"),
                              ("bicgstab", 1, "bicgstab_per_step_kernels"),
+                             ("gmres", 0, "gmres100_one_workgroup"),
                              ("gmres", 1, "gmres100_per_step_kernels")):
         S = mxl.solver(kind, M, None, max_iters=iters, nonfinite_check=0, check_every=iters,
                        launch_mode=mode)

@@ -110,10 +110,12 @@ typedef struct {
                               BiCGSTAB n <= 4096 with <= 5 entries per row
                               (<= 8 for n <= 1024), else per step); auto
                               picks 2 for n <= 8192.  GMRES: 1 launches every
-                              kernel of every step; otherwise each chunk of
-                              check_every steps is captured once as a HIP
-                              graph and replayed (except with an exact ILU
-                              preconditioner) */
+                              kernel of every step; otherwise systems with
+                              n <= 1024 and krylov_dim <= 128 (point Jacobi or
+                              none, no Time criterion) run whole in one
+                              workgroup, and larger ones capture each chunk
+                              of check_every steps once as a HIP graph and
+                              replay it (except with an exact ILU) */
 } mxl_criteria;
 
 /* Convergence record (the Convergence logger of Sec. 2.6) plus an optional

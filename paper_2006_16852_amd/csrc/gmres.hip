@@ -443,6 +443,207 @@ __global__ __launch_bounds__(kWG) void k_gm_xupdate(int64_t n, int64_t ld, const
     }
 }
 
+// The whole restarted GMRES of a small system (n <= 1024 rows, Krylov
+// dimension <= 128, point Jacobi or none) in one workgroup of 1024 threads:
+// thread i owns row i (its CSR entries are read from global memory, the
+// vector a product gathers is staged in LDS), the basis V and H live in the
+// solver's buffers (L2-resident at these sizes).  Each step orthogonalises
+// twice by classical Gram-Schmidt: the j+1 dot products run side by side,
+// T threads per basis vector (a power of two <= 64, so a group stays in one
+// wave) reducing by shuffles.  The criteria, history and stop reasons are
+// those of the per-step solver.  out: iterations, products, restarts
+// (int64 at 0, 8, 16), status (int32 at 24), relative residual (double at 32).
+constexpr int kSmallGmN = 1024, kSmallGmM = 128;
+__global__ __launch_bounds__(kSmallGmN) void k_small_gmres(int n, int m, const int *__restrict__ rp,
+                                                           const int *__restrict__ col,
+                                                           const double *__restrict__ val,
+                                                           const double *__restrict__ dinv,
+                                                           const double *__restrict__ b, double *__restrict__ x,
+                                                           double *__restrict__ V, int64_t ld, GmPtrs P,
+                                                           double red_factor, int64_t maxit, int chk,
+                                                           double *hist, char *out) {
+    __shared__ double zl[kSmallGmN], wl[kSmallGmN], hk[kSmallGmM + 2], yv[kSmallGmM];
+    // rotations and the rotated right-hand side stay in LDS for the solve
+    __shared__ double csl[kSmallGmM], snl[kSmallGmM], gl[kSmallGmM + 1], colj[kSmallGmM + 2];
+    __shared__ double red2[2][kSmallGmN / kWave];
+    __shared__ int flag[1];
+    const int t = threadIdx.x, lane = t % kWave, wid = t / kWave;
+    constexpr int NW = kSmallGmN / kWave;
+    const bool own = t < n;
+    const int64_t ldh = m + 1;
+    // deterministic workgroup sums of two values (result in every thread)
+    auto sum2 = [&](double &u, double &v) {
+        u = wave_sum(u);
+        v = wave_sum(v);
+        __syncthreads();
+        if (lane == 0) {
+            red2[0][wid] = u;
+            red2[1][wid] = v;
+        }
+        __syncthreads();
+        double a = 0.0, c = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            a += red2[0][w];
+            c += red2[1][w];
+        }
+        u = a;
+        v = c;
+    };
+    auto spmv_row = [&]() {  // (A zl)_t for the thread's row
+        double s = 0.0;
+        if (own)
+            for (int q = rp[t]; q < rp[t + 1]; ++q) s += val[q] * zl[col[q]];
+        return s;
+    };
+    const double di = own && dinv ? dinv[t] : 1.0;
+    const double bi = own ? b[t] : 0.0;
+    double xi = own ? x[t] : 0.0;
+    if (own) zl[t] = xi;
+    __syncthreads();
+    double ri = bi - spmv_row();
+    double rr = ri * ri, bb = bi * bi;
+    sum2(rr, bb);
+    int64_t k = 0, nspmv = 1, restarts = 0;
+    int stop = ST_RUN;
+    const double nb = sqrt(bb);
+    double rel = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+    if (t == 0 && hist) hist[0] = rel;
+    if (bb == 0.0) {
+        xi = 0.0;
+        rel = 0.0;
+        stop = ST_CONVERGED;
+    } else if (chk && !finite_d(sqrt(rr))) {
+        stop = ST_NONFINITE;
+    } else if (sqrt(rr) <= red_factor * nb) {
+        stop = ST_CONVERGED;
+    }
+    while (stop == ST_RUN) {
+        const double beta = sqrt(rr);
+        if (own) V[t] = ri / beta;
+        if (t <= m) gl[t] = t == 0 ? beta : 0.0;
+        int j = 0;
+        while (j < m && k < maxit) {
+            __syncthreads();  // V column j and the previous products complete
+            if (own) zl[t] = di * V[(int64_t)j * ld + t];
+            __syncthreads();
+            double wi = spmv_row();
+            ++nspmv;
+            const int nv = j + 1;
+            int T = 64;
+            while (T > 1 && T * nv > kSmallGmN) T >>= 1;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (own) wl[t] = wi;
+                __syncthreads();
+                const int kk = t / T, part = t % T;
+                double sdot = 0.0;
+                if (kk < nv)
+                    for (int i = part; i < n; i += T) sdot += V[(int64_t)kk * ld + i] * wl[i];
+                for (int off = T / 2; off > 0; off >>= 1) sdot += __shfl_xor(sdot, off, kWave);
+                if (kk < nv && part == 0) {
+                    hk[kk] = sdot;
+                    colj[kk] = pass == 0 ? sdot : colj[kk] + sdot;
+                }
+                __syncthreads();
+                if (own) {
+#pragma unroll 8
+                    for (int q = 0; q < nv; ++q) wi -= hk[q] * V[(int64_t)q * ld + t];
+                }
+                __syncthreads();  // hk consumed before the next pass writes it
+            }
+            double ww = own ? wi * wi : 0.0, dummy = 0.0;
+            sum2(ww, dummy);
+            const double hn = sqrt(ww);
+            if (t == 0) {  // column j: earlier rotations, a new one, the criteria (oracle order)
+                double *h = colj;
+                h[j + 1] = hn;
+                for (int i2 = 0; i2 < j; ++i2) {
+                    const double a = h[i2], c = h[i2 + 1];
+                    h[i2] = csl[i2] * a + snl[i2] * c;
+                    h[i2 + 1] = -snl[i2] * a + csl[i2] * c;
+                }
+                const double a = h[j];
+                const double d = hypot(a, hn);
+                const double cc = d == 0.0 ? 1.0 : a / d, ss = d == 0.0 ? 0.0 : hn / d;
+                csl[j] = cc;
+                snl[j] = ss;
+                h[j] = d;
+                h[j + 1] = 0.0;
+                const double gj = gl[j];
+                gl[j + 1] = -ss * gj;
+                gl[j] = cc * gj;
+                const double r2 = fabs(gl[j + 1]) / nb;
+                if (hist) hist[k + 1] = r2;
+                int st2 = ST_RUN;
+                if (chk && (!finite_d(r2) || !finite_d(d))) st2 = ST_NONFINITE;
+                else if (fabs(gl[j + 1]) <= red_factor * nb) st2 = ST_CONVERGED;
+                else if (hn == 0.0 || d == 0.0) st2 = ST_BREAKDOWN;
+                flag[0] = st2;
+                hk[kSmallGmM + 1] = r2;
+            }
+            __syncthreads();
+            if (t <= j) P.H[t + ldh * j] = colj[t];  // rotated column j (R) for the back substitution
+            __syncthreads();
+            stop = flag[0];
+            rel = hk[kSmallGmM + 1];
+            ++j;
+            ++k;
+            if (stop != ST_RUN) break;
+            if (j < m && own) V[(int64_t)j * ld + t] = wi / hn;
+        }
+        __syncthreads();
+        if (stop == ST_NONFINITE) break;
+        // x += M^{-1} V y with R y = g over the j steps of this cycle
+        // (column sweep: y_i = g_i / r_ii, then g_l -= r_li y_i for l < i)
+        for (int i2 = j - 1; i2 >= 0; --i2) {
+            if (t == 0) yv[i2] = gl[i2] / P.H[i2 + ldh * i2];
+            __syncthreads();
+            if (t < i2) gl[t] -= P.H[t + ldh * i2] * yv[i2];
+            __syncthreads();
+        }
+        if (own) {
+            double sacc = 0.0;
+#pragma unroll 8
+            for (int l = 0; l < j; ++l) sacc += V[(int64_t)l * ld + t] * yv[l];
+            xi += di * sacc;
+        }
+        if (stop != ST_RUN) break;
+        if (k >= maxit) {
+            stop = ST_MAX_ITERS;
+            break;
+        }
+        // restart from the recomputed residual
+        __syncthreads();
+        if (own) zl[t] = xi;
+        __syncthreads();
+        ri = bi - spmv_row();
+        ++nspmv;
+        ++restarts;
+        rr = ri * ri;
+        double dummy = 0.0;
+        sum2(rr, dummy);
+        rel = sqrt(rr) / nb;
+        if (chk && !finite_d(sqrt(rr))) stop = ST_NONFINITE;
+        else if (sqrt(rr) <= red_factor * nb) stop = ST_CONVERGED;
+    }
+    if (stop == ST_RUN) stop = ST_MAX_ITERS;
+    if (own) x[t] = xi;
+    if (t == 0) {
+        ((int64_t *)out)[0] = k;
+        ((int64_t *)out)[1] = nspmv;
+        ((int64_t *)out)[2] = restarts;
+        ((int32_t *)out)[6] = stop;
+        ((double *)out)[4] = rel;
+    }
+}
+
+hipError_t gm_small(int n, int m, const int *rp, const int *col, const double *val, const double *dinv,
+                    const double *b, double *x, double *V, int64_t ld, void *ws, double red, int64_t maxit, int chk,
+                    double *hist, void *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_small_gmres, dim3(1), dim3(kSmallGmN), 0, s, n, m, rp, col, val, dinv, b, x, V, ld,
+                       gm_ptrs(ws, m), red, maxit, chk, hist, (char *)out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers
 hipError_t gm_prep(const mxl_ctx *ctx, int64_t n, const double *v, const double *b, const double *dinv,
                    double *z, double *parts, int *slots, hipStream_t s) {

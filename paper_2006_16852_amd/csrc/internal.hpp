@@ -289,6 +289,11 @@ hipError_t gm_step(int64_t n, int64_t ld, double *V, int j, const double *u, con
 hipError_t gm_close(int64_t n, int64_t ld, const double *V, const double *dinv, double *x, double *t,
                     const SolverState *st, void *ws, int m, hipStream_t s);
 hipError_t gm_read(const void *ws, int64_t *nspmv, hipStream_t s);
+// The whole solve of a small system (n <= 1024, m <= 128) in one workgroup;
+// out: iterations, products, restarts (int64), status (int32 at 24), rel (double at 32)
+hipError_t gm_small(int n, int m, const int *rp, const int *col, const double *val, const double *dinv,
+                    const double *b, double *x, double *V, int64_t ld, void *ws, double red, int64_t maxit, int chk,
+                    double *hist, void *out, hipStream_t s);
 
 // ------------------------------------------------------------- ilu.hip
 // out = alpha U^{-1} L^{-1} r + beta out (beta == 0 overwrites)

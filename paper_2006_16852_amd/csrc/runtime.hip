@@ -1181,6 +1181,32 @@ mxl_status solve_gmres(const SolverImpl &S, const void *b, void *xv, mxl_solve_i
         }
         return MXL_OK;
     };
+    // small systems: the whole solve in one workgroup
+    if (c.launch_mode != 1 && n <= 1024 && m <= 128 && !blockp && A.format != MXL_FMT_STENCIL &&
+        c.time_limit_s <= 0) {
+        HIP_TRY(gm_small((int)n, m, (const int *)A.row_ptr->p, (const int *)A.col->p, (const double *)A.val->p, dinv,
+                         (const double *)b, x, V, ld, ws, c.reduction, c.max_iters, c.nonfinite_check, hist,
+                         S.gnorm->p, s));
+        char o[40];
+        HIP_TRY(hipMemcpyAsync(o, S.gnorm->p, 40, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int64_t it, sp, rs_;
+        int32_t stc;
+        double rel;
+        memcpy(&it, o, 8);
+        memcpy(&sp, o + 8, 8);
+        memcpy(&rs_, o + 16, 8);
+        memcpy(&stc, o + 24, 4);
+        memcpy(&rel, o + 32, 8);
+        SolverState h0{};
+        fill_info(info, S, h0, it, stc == ST_MAX_ITERS ? MXL_STOP_MAX_ITERS : map_stop(stc), sp, elapsed_s(t0));
+        if (info) {
+            info->rel_residual = rel;
+            info->restarts = rs_;
+            info->reorth = it;
+        }
+        return MXL_OK;
+    }
     // replay captured chunks unless asked for direct launches, or when the
     // preconditioner is an exact ILU (hundreds of level launches per step)
     const bool use_graph = c.launch_mode != 1 && !(S.ilu && S.ilu->trisolve == 0);

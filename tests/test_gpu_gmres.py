@@ -167,6 +167,42 @@ def test_graph_replays_match_direct_launches(mxl, ctx, P):
         assert np.array_equal(x, ref[1]) and it == ref[2] and rr == ref[3] and sp == ref[4], mode
 
 
+SMALL = [W.convdiff_2d5(31), W.convdiff_3d7(8), _nonsym(1000, 5), W.stencil_2d5(6)]
+
+
+@pytest.mark.parametrize("P", [None, "jacobi"], ids=["none", "jacobi"])
+@pytest.mark.parametrize("m", [1, 10, 128])
+@pytest.mark.parametrize("A", SMALL, ids=[a.name for a in SMALL])
+def test_small_systems_in_one_workgroup(mxl, ctx, A, m, P):
+    """n <= 1024 and m <= 128 run the whole solve in one workgroup (launch
+    mode 0) against the per-step kernels (mode 1) and the oracle: converged
+    counts, residuals, and the iterate after a fixed number of steps."""
+    b = W.uniform_vec(A.nrows, 13)
+    ref = _oracle(A, b, P, krylov_dim=m, max_iters=3000, reduction=1e-10)
+    M = matrix(mxl, ctx, A)
+    Pop = mxl.jacobi(M) if P == "jacobi" else None
+    for mode in (0, 1):
+        S = mxl.solver("gmres", M, Pop, krylov_dim=m, max_iters=3000, reduction=1e-10, launch_mode=mode)
+        x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+        info = S.solve(dev(b), x, history=3001)
+        assert info["stop_reason"] == ref["stop_reason"] == mxl.STOP_CONVERGED, (mode, info)
+        tol = 2 if info["restarts"] < 10 else max(2, int(0.05 * ref["iterations"]))
+        assert abs(info["iterations"] - ref["iterations"]) <= tol, (mode, info["iterations"], ref["iterations"])
+        assert _rel(A, b, x.cpu().numpy()) <= 1.01e-10
+        h, hr = np.array(info["history"]), ref["history"]
+        cnt = min(len(h), len(hr), 31)
+        far = hr[:cnt] > 1e-6
+        assert np.all(np.abs(h[:cnt][far] - hr[:cnt][far]) <= 1e-7 * hr[:cnt][far]), mode
+    x0 = W.uniform_vec(A.nrows, 14) * 0.1
+    k = min(7, A.nrows)
+    ref = _oracle(A, b, P, x0=x0, krylov_dim=m, max_iters=k, reduction=0.0)
+    S = mxl.solver("gmres", M, Pop, krylov_dim=m, max_iters=k, reduction=0.0)
+    x = dev(x0)
+    info = S.solve(dev(b), x)
+    assert info["iterations"] == k and info["spmv_count"] == ref["spmv_count"]
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-11 * np.linalg.norm(ref["x"])
+
+
 def test_edge_cases(mxl, ctx):
     A = W.convdiff_2d5(9)
     n = A.nrows
