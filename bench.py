@@ -246,6 +246,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": f"{sel} SpMV with fused p.q inside the CG loop",
                      "stream_GBs": ref_gbs, "frac_of_dot": round(achieved / ref_gbs["dot"], 4),
+                     # the same product's work in format-independent terms: the
+                     # CSR-minimal bytes of y = A x over this kernel's time
+                     "csr_equiv_GBs": round(spmv_bytes("csr", n, nnz, None) / (launch_ms * 1e-3) / 1e9, 1),
                      "alg_bytes_per_launch": cg_spmv, "avg_launch_us": round(launch_ms * 1e3, 2)},
         "cg": {"iterations": its[0], "time_to_1e-10_ms": round(cg_ms, 3), "true_rel_residual": true_rel,
                "alg_GBs": round(cg_bytes / (cg_ms * 1e-3) / 1e9, 1),
