@@ -64,7 +64,8 @@ def aniso_ir(args):
     b = torch.from_numpy(W.uniform_vec(n, 4)).to(dev)
     x = torch.zeros_like(b)
     y = torch.empty_like(b)
-    cands = {"ell": base.convert("ell"), "csr_vec8": base.convert("csr", variant=1, vector_width=8)}
+    cands = {"ell": base.convert("ell"), "ell16": base.convert("ell", variant=mxl.ELL_DELTA16),
+             "csr_vec8": base.convert("csr", variant=1, vector_width=8)}
     t_sel = {k: v.time_apply(b, y, reps=20) for k, v in cands.items()}
     M = cands[min(t_sel, key=t_sel.get)]
     P = mxl.jacobi(M)
