@@ -91,6 +91,10 @@ def _declare(L):
     L.orc_pcg_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, _Crit, C.POINTER(_Info)]
     L.orc_ir.restype = C.c_int
     L.orc_ir.argtypes = [i64, vp, vp, vp, vp, vp, i64, f64, i64, f64, C.POINTER(_Info), vp]
+    L.orc_pcg_f32_block.restype = C.c_int
+    L.orc_pcg_f32_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, _Crit, C.POINTER(_Info)]
+    L.orc_ir_block.restype = C.c_int
+    L.orc_ir_block.argtypes = [i64, vp, vp, vp, vp, vp, i64, f64, i64, f64, i32, f64, C.POINTER(_Info), vp]
     L.orc_batch_pcg.argtypes = [i64, vp, vp, vp, vp, vp, vp, f64, i64, vp, vp, vp]
     L.orc_features.argtypes = [i64, i64, vp, vp, vp]
     L.orc_mlp_loss_grad.restype = f64
@@ -262,15 +266,39 @@ def pcg_f32(A, b32, dinv32, max_iters=10_000, reduction=1e-4):
                 stop_reason=info.stop_reason)
 
 
+def pcg_f32_block(A, b32, bptr, inv, max_iters=10_000, reduction=1e-4):
+    """FP32 CG (vectors and matrix values FP32, scalars FP64) with block
+    Jacobi: z = blockdiag(inv) r evaluated in FP64 and rounded to FP32."""
+    rp, col, _ = _csr(A)
+    v32 = _c(A.val, np.float32)
+    b32 = _c(b32, np.float32)
+    bptr = _c(bptr, np.int32)
+    inv = _c(inv, np.float64)
+    x = np.zeros(A.nrows, np.float32)
+    info = _Info()
+    lib().orc_pcg_f32_block(A.nrows, _p(rp), _p(col), _p(v32), bptr.size - 1, _p(bptr), _p(inv), _p(b32),
+                            _p(x), _Crit(max_iters, reduction, 1), C.byref(info))
+    return dict(x=x, iterations=info.iterations, rel_residual=info.rel_residual,
+                stop_reason=info.stop_reason)
+
+
 def ir(A, b, x0=None, max_outer=50, outer_reduction=1e-12, inner_max_iters=10_000,
-       inner_reduction=1e-4):
+       inner_reduction=1e-4, block_size=0, block_accuracy=0.1):
+    """Mixed-precision iterative refinement (Sec. 3.2): FP64 residual and
+    update, FP32 Jacobi-CG inner solve; block_size > 0 switches the inner
+    preconditioner to adaptive block Jacobi over uniform blocks of that size."""
     rp, col, val = _csr(A)
     b = _c(b, np.float64)
     x = np.zeros(A.nrows) if x0 is None else _c(x0, np.float64).copy()
     info = _Info()
     hist = np.full(max_outer + 1, np.nan)
-    lib().orc_ir(A.nrows, _p(rp), _p(col), _p(val), _p(b), _p(x), max_outer,
-                 outer_reduction, inner_max_iters, inner_reduction, C.byref(info), _p(hist))
+    if block_size > 0:
+        lib().orc_ir_block(A.nrows, _p(rp), _p(col), _p(val), _p(b), _p(x), max_outer, outer_reduction,
+                           inner_max_iters, inner_reduction, block_size, block_accuracy, C.byref(info),
+                           _p(hist))
+    else:
+        lib().orc_ir(A.nrows, _p(rp), _p(col), _p(val), _p(b), _p(x), max_outer,
+                     outer_reduction, inner_max_iters, inner_reduction, C.byref(info), _p(hist))
     return dict(x=x, outer=info.iterations, inner_iterations=info.inner_iterations,
                 spmv_count=info.spmv_count, rel_residual=info.rel_residual,
                 stop_reason=info.stop_reason, history=hist[:info.iterations + 1])

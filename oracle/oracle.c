@@ -635,9 +635,52 @@ static double dot_f32(int64_t n, const float *a, const float *b)
     return s;
 }
 
+/* z = M r for the FP32 inner solver, evaluated in FP64: point Jacobi
+ * (dinv, FP32 entries) or the stored block inverses (bptr/inv), summed over
+ * ascending columns; zr32 != 0 rounds z to FP32 (the block variant keeps z
+ * as an FP32 vector). */
+static void prec_f32(int64_t n, const float *dinv, int64_t nb, const int32_t *bptr, const double *inv,
+                     int zr32, const float *r, double *z)
+{
+    if (bptr) {
+        int64_t off = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int r0 = bptr[b], m = bptr[b + 1] - bptr[b];
+            for (int i = 0; i < m; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < m; ++j) s += inv[off + (int64_t)i * m + j] * (double)r[r0 + j];
+                z[r0 + i] = zr32 ? (double)(float)s : s;
+            }
+            off += (int64_t)m * m;
+        }
+    } else {
+        for (int64_t i = 0; i < n; ++i) z[i] = (double)dinv[i] * (double)r[i];
+    }
+}
+
+static int pcg_f32_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                        const float *dinv, int64_t nblocks, const int32_t *bptr, const double *inv,
+                        const float *b, float *x, orc_criteria crit, orc_info *info);
+
 int orc_pcg_f32(int64_t n, const int32_t *row_ptr, const int32_t *col,
                 const float *val, const float *dinv, const float *b, float *x,
                 orc_criteria crit, orc_info *info)
+{
+    return pcg_f32_core(n, row_ptr, col, val, dinv, 0, NULL, NULL, b, x, crit, info);
+}
+
+/* The same FP32 CG with the block-Jacobi preconditioner (inverses stored as
+ * decided by the adaptive rule, applied in FP64, z rounded to FP32). */
+int orc_pcg_f32_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                      int64_t nblocks, const int32_t *bptr, const double *inv, const float *b, float *x,
+                      orc_criteria crit, orc_info *info)
+{
+    return pcg_f32_core(n, row_ptr, col, val, NULL, nblocks, bptr, inv, b, x, crit, info);
+}
+
+static int pcg_f32_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                        const float *dinv, int64_t nblocks, const int32_t *bptr, const double *inv,
+                        const float *b, float *x, orc_criteria crit, orc_info *info)
 {
     size_t bytes = (size_t)(n + 1) * sizeof(float);
     float *r = malloc(bytes), *p = malloc(bytes), *q = malloc(bytes);
@@ -657,11 +700,12 @@ int orc_pcg_f32(int64_t n, const int32_t *row_ptr, const int32_t *col,
     double rr = dot_f32(n, r, r);
     rel = sqrt(rr) / nb;
     if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; goto done; }
+    double *z = malloc((size_t)(n + 1) * sizeof(double));
     double rho = 0.0;
+    prec_f32(n, dinv, nblocks, bptr, inv, bptr != NULL, r, z);
     for (int64_t i = 0; i < n; ++i) {
-        double zi = (double)dinv[i] * (double)r[i];
-        p[i] = (float)zi;
-        rho += (double)r[i] * zi;
+        p[i] = (float)z[i];
+        rho += (double)r[i] * z[i];
     }
     while (k < crit.max_iters) {
         spmv_f32(n, row_ptr, col, val, p, q);
@@ -679,16 +723,16 @@ int orc_pcg_f32(int64_t n, const int32_t *row_ptr, const int32_t *col,
         rel = sqrt(rr) / nb;
         if (crit.nonfinite_check && nonfinite(rr)) { stop = ORC_NONFINITE; break; }
         if (sqrt(rr) <= crit.reduction * nb) { stop = ORC_CONVERGED; break; }
+        prec_f32(n, dinv, nblocks, bptr, inv, bptr != NULL, r, z);
         double rho_new = 0.0;
-        for (int64_t i = 0; i < n; ++i)
-            rho_new += (double)r[i] * ((double)dinv[i] * (double)r[i]);
+        for (int64_t i = 0; i < n; ++i) rho_new += (double)r[i] * z[i];
         if (rho_new == 0.0) { stop = ORC_BREAKDOWN; break; }
         double beta = rho_new / rho;
-        for (int64_t i = 0; i < n; ++i)
-            p[i] = (float)((double)dinv[i] * (double)r[i] + beta * (double)p[i]);
+        for (int64_t i = 0; i < n; ++i) p[i] = (float)(z[i] + beta * (double)p[i]);
         rho = rho_new;
     }
     if (stop == ORC_RUNNING) stop = ORC_MAX_ITERS;
+    free(z);
 done:
     info->iterations = k;
     info->rel_residual = rel;
@@ -712,11 +756,39 @@ done:
  * A32 = fp32(values); dinv32 = fp32(1/a_ii) with the reciprocal taken in
  * FP64.  info->iterations counts outer steps (refinement corrections
  * applied), info->inner_iterations all inner CG iterations. */
+static int ir_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                   const double *b, double *x, int64_t max_outer, double outer_reduction,
+                   int64_t inner_max_iters, double inner_reduction, int32_t block_size, double accuracy,
+                   orc_info *info, double *outer_history);
+
 int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
            const double *val, const double *b, double *x,
            int64_t max_outer, double outer_reduction,
            int64_t inner_max_iters, double inner_reduction,
            orc_info *info, double *outer_history)
+{
+    return ir_core(n, row_ptr, col, val, b, x, max_outer, outer_reduction, inner_max_iters, inner_reduction, 0,
+                   0.0, info, outer_history);
+}
+
+/* IR whose FP32 inner CG uses block Jacobi: blocks of block_size rows of the
+ * FP64 matrix, inverted and stored by the adaptive rule (accuracy), applied
+ * in FP64 with z rounded to FP32 (memory precision decoupled from the
+ * arithmetic, Sec. 3.2). */
+int orc_ir_block(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                 const double *val, const double *b, double *x,
+                 int64_t max_outer, double outer_reduction,
+                 int64_t inner_max_iters, double inner_reduction, int32_t block_size, double accuracy,
+                 orc_info *info, double *outer_history)
+{
+    return ir_core(n, row_ptr, col, val, b, x, max_outer, outer_reduction, inner_max_iters, inner_reduction,
+                   block_size, accuracy, info, outer_history);
+}
+
+static int ir_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                   const double *b, double *x, int64_t max_outer, double outer_reduction,
+                   int64_t inner_max_iters, double inner_reduction, int32_t block_size, double accuracy,
+                   orc_info *info, double *outer_history)
 {
     int64_t nnz = row_ptr[n];
     float *v32 = malloc((size_t)(nnz + 1) * sizeof(float));
@@ -727,9 +799,26 @@ int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
     float *d32 = malloc((size_t)(n + 1) * sizeof(float));
     memset(info, 0, sizeof(*info));
     int stop = ORC_RUNNING;
+    int64_t nblocks = 0;
+    int32_t *bptr = NULL;
+    double *inv = NULL;
     for (int64_t k = 0; k < nnz; ++k) v32[k] = (float)val[k];
     if (orc_jacobi_dinv(n, row_ptr, col, val, dinv) >= 0) { stop = ORC_BREAKDOWN; goto done; }
     for (int64_t i = 0; i < n; ++i) dinv32[i] = (float)dinv[i];
+    if (block_size > 0) {
+        nblocks = (n + block_size - 1) / block_size;
+        bptr = malloc((size_t)(nblocks + 1) * sizeof(int32_t));
+        for (int64_t k = 0; k <= nblocks; ++k) bptr[k] = (int32_t)(k * block_size < n ? k * block_size : n);
+        int64_t tot = 0;
+        for (int64_t k = 0; k < nblocks; ++k) tot += (int64_t)(bptr[k + 1] - bptr[k]) * (bptr[k + 1] - bptr[k]);
+        inv = malloc((size_t)(tot + 1) * sizeof(double));
+        double *cond = malloc((size_t)(nblocks + 1) * sizeof(double));
+        int32_t *prc = malloc((size_t)(nblocks + 1) * sizeof(int32_t));
+        int64_t bad = orc_bj_generate(n, row_ptr, col, val, nblocks, bptr, 1, accuracy, inv, cond, prc);
+        free(cond);
+        free(prc);
+        if (bad >= 0) { stop = ORC_BREAKDOWN; goto done; }
+    }
     double nb = nrm2(n, b);
     if (nb == 0.0) {
         for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
@@ -752,7 +841,7 @@ int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
         for (int64_t i = 0; i < n; ++i) { r32[i] = (float)(r[i] / s); d32[i] = 0.0f; }
         orc_criteria ic = { inner_max_iters, inner_reduction, 1 };
         orc_info ii;
-        orc_pcg_f32(n, row_ptr, col, v32, dinv32, r32, d32, ic, &ii);
+        pcg_f32_core(n, row_ptr, col, v32, bptr ? NULL : dinv32, nblocks, bptr, inv, r32, d32, ic, &ii);
         info->inner_iterations += ii.iterations;
         info->spmv_count += ii.spmv_count;
         for (int64_t i = 0; i < n; ++i) x[i] += s * (double)d32[i];
@@ -761,7 +850,7 @@ int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
     info->iterations = outer;
 done:
     info->stop_reason = stop;
-    free(v32); free(dinv32); free(dinv); free(r); free(r32); free(d32);
+    free(v32); free(dinv32); free(dinv); free(r); free(r32); free(d32); free(bptr); free(inv);
     return stop;
 }
 

@@ -140,3 +140,66 @@ def test_singular_block_is_reported():
         O.bj_generate(A, np.array([0, 1, 2], np.int32))
     inv, _, _ = O.bj_generate(A, np.array([0, 2], np.int32), adaptive=False)  # [[0,1],[1,0]] is its own inverse
     assert np.array_equal(inv.reshape(2, 2), np.array([[0.0, 1.0], [1.0, 0.0]]))
+
+
+# ----------------------------------------- FP32 inner CG and IR with blocks
+def _a_norm_min(D, Minv, b, k):
+    """argmin ||x - D^{-1} b||_D over x in Minv K_k(D Minv, b) (x0 = 0), by an
+    explicit normalised power basis and its D-orthogonal projection."""
+    B = np.zeros((len(b), k))
+    v = b / np.linalg.norm(b)
+    for i in range(k):
+        B[:, i] = Minv @ v
+        v = D @ (Minv @ v)
+        v /= np.linalg.norm(v)
+    Q, _ = np.linalg.qr(B)
+    c = np.linalg.solve(Q.T @ D @ Q, Q.T @ b)
+    return Q @ c
+
+
+@pytest.mark.parametrize("bs", [3, 8])
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_f32_block_cg_iterate_is_a_norm_minimiser(k, bs):
+    """Preconditioned CG's k-th iterate minimises the energy-norm error over
+    the preconditioned Krylov space; the FP32 vectors hold it to single
+    precision (a wrong block offset or row of the inverse breaks it)."""
+    A = W.aniso_3d7(5)
+    D = _dense(A)
+    bp = O.uniform_blocks(A.nrows, bs)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=False)
+    M = np.zeros_like(D)
+    off = 0
+    for s in range(bp.size - 1):
+        m = bp[s + 1] - bp[s]
+        M[bp[s]:bp[s + 1], bp[s]:bp[s + 1]] = inv[off:off + m * m].reshape(m, m)
+        off += m * m
+    b = W.uniform_vec(A.nrows, 3).astype(np.float32)
+    out = O.pcg_f32_block(A, b, bp, inv, max_iters=k, reduction=0.0)
+    assert out["iterations"] == k and out["stop_reason"] == O.MAX_ITERS
+    D32 = _dense(W.Csr(A.nrows, A.ncols, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64), "a"))
+    want = _a_norm_min(D32, M, b.astype(np.float64), k)
+    assert np.linalg.norm(out["x"] - want) <= 2e-5 * np.linalg.norm(want)
+
+
+def test_ir_block_whole_matrix_block_takes_one_inner_step():
+    """One block holding the whole matrix is an exact preconditioner: every
+    inner solve stops after one step and the outer loop contracts at the
+    single-precision rate."""
+    A = W.aniso_3d7(4)
+    b = W.uniform_vec(A.nrows, 5)
+    res = O.ir(A, b, outer_reduction=1e-13, inner_reduction=1e-4, block_size=A.nrows)
+    assert res["stop_reason"] == O.CONVERGED
+    assert res["inner_iterations"] == res["outer"] <= 4
+
+
+def test_ir_block_true_residual_and_fewer_inner_steps():
+    A = W.aniso_3d7(16)
+    b = W.uniform_vec(A.nrows, 4)
+    pt = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4)
+    for acc in (1e-1, 1e-8):
+        blk = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4, block_size=8, block_accuracy=acc)
+        assert blk["stop_reason"] == O.CONVERGED
+        r = b - O.spmv(A, blk["x"])
+        assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
+        # the strong coupling runs along consecutive rows, which the blocks absorb
+        assert blk["inner_iterations"] < 0.6 * pt["inner_iterations"]
