@@ -332,10 +332,22 @@ mxl_status mxl_solve(const mxl_op *S, const void *b, void *x,
  * outer.time_limit_s); s = ||r||_inf; solve A32 d = fp32(r/s) from d = 0 to
  * inner.reduction / inner.max_iters; x += s*d (FP64).  info->iterations
  * counts corrections, info->inner_iterations all inner CG iterations,
- * info->history the outer relative residuals. */
+ * info->history the outer relative residuals.  inner_block_size > 0 (1, 2,
+ * 4, 8, 16 or 32) replaces the inner point Jacobi with block Jacobi over
+ * uniform blocks of that many rows, generated from the FP64 matrix with the
+ * adaptive storage rule at inner_block_accuracy (as mxl_bjacobi_generate
+ * with adaptive = 1): the inverses are applied in FP64 and z = M r is
+ * rounded to FP32, so the inner solve decouples three precisions
+ * (binary16/32/64 inverses, FP32 vectors, FP64 arithmetic).  0 keeps point
+ * Jacobi; a zero-initialised tail of this struct is therefore the point
+ * Jacobi solver.  Errors: DTYPE (A not FP64), INVALID_ARG (block size not
+ * supported), ZERO_DIAG (a singular diagonal block, or a zero diagonal
+ * entry for point Jacobi), OUT_OF_MEMORY. */
 typedef struct {
     mxl_criteria outer;
     mxl_criteria inner;
+    int32_t inner_block_size;
+    double inner_block_accuracy;
 } mxl_ir_params;
 mxl_status mxl_ir_generate(const mxl_op *A, const mxl_ir_params *params, mxl_op **S);
 

@@ -71,7 +71,8 @@ class OpDesc(C.Structure):
 
 
 class IrParams(C.Structure):
-    _fields_ = [("outer", Criteria), ("inner", Criteria)]
+    _fields_ = [("outer", Criteria), ("inner", Criteria), ("inner_block_size", C.c_int32),
+                ("inner_block_accuracy", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -611,11 +612,13 @@ class SelectorHandle:
             self.h = None
 
 
-def ir(A: Op, outer: dict = None, inner: dict = None) -> Solver:
-    """FP64-outer / FP32-inner-CG iterative refinement operator."""
+def ir(A: Op, outer: dict = None, inner: dict = None, block_size: int = 0,
+       block_accuracy: float = 0.1) -> Solver:
+    """FP64-outer / FP32-inner-CG iterative refinement operator; block_size > 0
+    preconditions the inner CG with adaptive block Jacobi."""
     o = criteria(**({"max_iters": 50, "reduction": 1e-12} | (outer or {})))
     i = criteria(**({"max_iters": 10_000, "reduction": 1e-4} | (inner or {})))
-    prm = IrParams(o, i)
+    prm = IrParams(o, i, block_size, block_accuracy)
     h = C.c_void_p()
     A.ctx.use_current_stream()
     _check(lib.mxl_ir_generate(A.h, C.byref(prm), C.byref(h)))

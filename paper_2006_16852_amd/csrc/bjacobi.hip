@@ -232,9 +232,11 @@ __global__ __launch_bounds__(kWG) void k_bj_apply(int64_t n, const unsigned char
 }
 
 // CG with block Jacobi, initial step: z = M r, p = z; publishes [r.z, r.r, b.b].
-template <int BS>
-__global__ __launch_bounds__(kWG) void k_cg_init_bj(int64_t n, const double *__restrict__ b,
-                                                    const double *__restrict__ r, double *__restrict__ p,
+// V is the vector type: with binary32 vectors z is rounded to binary32
+// before it enters p and r.z (the inverses are still applied in FP64).
+template <typename V, int BS>
+__global__ __launch_bounds__(kWG) void k_cg_init_bj(int64_t n, const V *__restrict__ b,
+                                                    const V *__restrict__ r, V *__restrict__ p,
                                                     const unsigned char *__restrict__ store,
                                                     const int64_t *__restrict__ off,
                                                     const int *__restrict__ prec,
@@ -245,17 +247,17 @@ __global__ __launch_bounds__(kWG) void k_cg_init_bj(int64_t n, const double *__r
     double rz = 0.0, rr = 0.0, bb = 0.0;
     for (int64_t t_ = tb_; t_ < te_; t_ += ts_) {
         const int64_t i = t_ * kWG + lane;
-        const double ri = i < n ? r[i] : 0.0;
+        const double ri = i < n ? (double)r[i] : 0.0;
         xs[lane] = ri;
         __syncthreads();
         if (i < n) {
             const int64_t blk = i / BS;
             const int t = (int)(i % BS);
-            const double zi = bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
-            p[i] = zi;
-            rz += ri * zi;
+            const V zv = (V)bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
+            p[i] = zv;
+            rz += ri * (double)zv;
             rr += ri * ri;
-            bb += b[i] * b[i];
+            bb += (double)b[i] * (double)b[i];
         }
         __syncthreads();
     }
@@ -264,11 +266,12 @@ __global__ __launch_bounds__(kWG) void k_cg_init_bj(int64_t n, const double *__r
 }
 
 // CG with block Jacobi, after the fused p.q: alpha = rho_{k-1} / p.q,
-// r -= alpha q, z = M r, and the reductions r.z, r.r.  The stop handshake
-// with k_cg_pupdate (st->ustop) is the one of the point-Jacobi kernels.
-template <int BS>
-__global__ __launch_bounds__(kWG) void k_cg_update_bj(int64_t n, double *__restrict__ r,
-                                                      const double *__restrict__ q, double *__restrict__ z,
+// r -= alpha q (in FP64, rounded to V), z = M r (rounded to V), and the
+// reductions r.z, r.r.  The stop handshake with k_cg_pupdate (st->ustop) is
+// the one of the point-Jacobi kernels.
+template <typename V, int BS>
+__global__ __launch_bounds__(kWG) void k_cg_update_bj(int64_t n, V *__restrict__ r,
+                                                      const V *__restrict__ q, V *__restrict__ z,
                                                       const unsigned char *__restrict__ store,
                                                       const int64_t *__restrict__ off,
                                                       const int *__restrict__ prec, SolverState *st,
@@ -305,17 +308,20 @@ __global__ __launch_bounds__(kWG) void k_cg_update_bj(int64_t n, double *__restr
         const int64_t i = t_ * kWG + lane;
         double ri = 0.0;
         if (i < n) {
-            ri = r[i] - alpha * q[i];
-            r[i] = ri;
+            V rv;
+            if constexpr (sizeof(V) == 8) rv = r[i] - alpha * q[i];
+            else rv = (V)((double)r[i] - alpha * (double)q[i]);
+            r[i] = rv;
+            ri = (double)rv;
         }
         xs[lane] = ri;
         __syncthreads();
         if (i < n) {
             const int64_t blk = i / BS;
             const int t = (int)(i % BS);
-            const double zi = bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
-            z[i] = zi;
-            rz += ri * zi;
+            const V zv = (V)bj_row<BS>(store, off[blk], prec[blk], t, xs + (lane - t));
+            z[i] = zv;
+            rz += ri * (double)zv;
             rr += ri * ri;
         }
         __syncthreads();
@@ -336,24 +342,40 @@ __global__ __launch_bounds__(kWG) void k_cg_update_bj(int64_t n, double *__restr
     default: return hipErrorInvalidValue;            \
     }
 
-hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, const void *b, const void *r,
-                      void *p, double *parts, hipStream_t s) {
+hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, const void *b,
+                      const void *r, void *p, double *parts, hipStream_t s) {
     const int g = vec_grid(ctx, n);
-    MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL(k_cg_init_bj<BS>, dim3(g), dim3(kWG), 0, s, n, (const double *)b,
-                                           (const double *)r, (double *)p,
-                                           (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
-                                           (const int *)P.bprec->p, parts));
+    const unsigned char *store = (const unsigned char *)P.bstore->p;
+    const int64_t *off = (const int64_t *)P.boff->p;
+    const int *prec = (const int *)P.bprec->p;
+    if (dtype == MXL_F32) {
+        MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL((k_cg_init_bj<float, BS>), dim3(g), dim3(kWG), 0, s, n,
+                                               (const float *)b, (const float *)r, (float *)p, store, off,
+                                               prec, parts));
+    } else {
+        MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL((k_cg_init_bj<double, BS>), dim3(g), dim3(kWG), 0, s, n,
+                                               (const double *)b, (const double *)r, (double *)p, store, off,
+                                               prec, parts));
+    }
     return hipGetLastError();
 }
 
-hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, void *r, const void *q, void *z,
-                        SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
+hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, void *r, const void *q,
+                        void *z, SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
                         hipStream_t s) {
     const int g = vec_grid(ctx, n);
-    MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL(k_cg_update_bj<BS>, dim3(g), dim3(kWG), 0, s, n, (double *)r,
-                                           (const double *)q, (double *)z,
-                                           (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
-                                           (const int *)P.bprec->p, st, pq_parts, pq_slots, parts, k));
+    const unsigned char *store = (const unsigned char *)P.bstore->p;
+    const int64_t *off = (const int64_t *)P.boff->p;
+    const int *prec = (const int *)P.bprec->p;
+    if (dtype == MXL_F32) {
+        MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL((k_cg_update_bj<float, BS>), dim3(g), dim3(kWG), 0, s, n,
+                                               (float *)r, (const float *)q, (float *)z, store, off, prec, st,
+                                               pq_parts, pq_slots, parts, k));
+    } else {
+        MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL((k_cg_update_bj<double, BS>), dim3(g), dim3(kWG), 0, s, n,
+                                               (double *)r, (const double *)q, (double *)z, store, off, prec,
+                                               st, pq_parts, pq_slots, parts, k));
+    }
     return hipGetLastError();
 }
 

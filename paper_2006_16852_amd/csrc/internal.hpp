@@ -267,10 +267,10 @@ hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a,
                          double *c, hipStream_t s);
 
 // ------------------------------------------------------------- bjacobi.hip
-hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, const void *b, const void *r,
-                      void *p, double *parts, hipStream_t s);
-hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, void *r, const void *q, void *z,
-                        SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
+hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, const void *b,
+                      const void *r, void *p, double *parts, hipStream_t s);
+hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, void *r, const void *q,
+                        void *z, SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
                         hipStream_t s);
 hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
                     double beta, void *z, hipStream_t s);

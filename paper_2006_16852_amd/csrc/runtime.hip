@@ -710,8 +710,11 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
     if (!(crit.reduction >= 0.0)) return fail(MXL_ERR_INVALID_ARG, "reduction must be >= 0");
     if (A->nrows != A->ncols) return fail(MXL_ERR_DIM_MISMATCH, "solver needs a square matrix");
     if (A->nrows == 0) return fail(MXL_ERR_INVALID_ARG, "empty system");
-    if (P && (P->A->nrows != A->nrows || P->A->dtype != A->dtype))
-        return fail(P->A->dtype != A->dtype ? MXL_ERR_DTYPE : MXL_ERR_DIM_MISMATCH,
+    // Block-Jacobi inverses keep their own storage precision and are applied
+    // in FP64, so they conform to vectors of either type; point Jacobi's
+    // dinv has the matrix's value type.
+    if (P && (P->A->nrows != A->nrows || (!P->block && P->A->dtype != A->dtype)))
+        return fail(P->A->nrows != A->nrows ? MXL_ERR_DIM_MISMATCH : MXL_ERR_DTYPE,
                     "preconditioner does not conform to the matrix");
     auto S = std::make_shared<SolverImpl>();
     S->kind = kind;
@@ -946,7 +949,7 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     HIP_TRY(launch_state_init(st, c.reduction, c.nonfinite_check, s));
     if ((rs = residual(S, b, x)) != MXL_OK) return rs;
     const bool blockp = S.P && S.P->block;
-    if (blockp) HIP_TRY(bj_cg_init(ctx, *S.P, n, b, S.r->p, S.p->p, pC, s));
+    if (blockp) HIP_TRY(bj_cg_init(ctx, *S.P, dt, n, b, S.r->p, S.p->p, pC, s));
     else HIP_TRY(cg_init(ctx, dt, n, b, S.r->p, S.p->p, dinv, pC, s));
     HIP_TRY(launch_finalize(3, pC, gv, st, FIN_CG_INIT, 0, 0, hist, s));
     SolverState h;
@@ -973,7 +976,7 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
         HIP_TRY(spmv_launch(A, a, s));
         timer.end(k);
         if (blockp) {  // r update fused with z = M r; then p = z + beta p (z passed as "r", no scaling)
-            HIP_TRY(bj_cg_update(ctx, *S.P, n, S.r->p, S.q->p, S.z->p, st, pA, gs, pB, (int)k, s));
+            HIP_TRY(bj_cg_update(ctx, *S.P, dt, n, S.r->p, S.q->p, S.z->p, st, pA, gs, pB, (int)k, s));
             HIP_TRY(cg_pupdate(ctx, dt, n, x, S.z->p, S.p->p, nullptr, st, pB, gv, (int)k, hist, s));
         } else {
             HIP_TRY(cg_update(ctx, dt, n, S.r->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
@@ -1384,17 +1387,28 @@ extern "C" mxl_status mxl_ir_generate(const mxl_op *Aop, const mxl_ir_params *pr
     if (st != MXL_OK) return st;
     ir->A32 = a32->mat;
     delete a32;
-    mxl_op *j64 = nullptr;
-    if ((st = mxl_jacobi_generate(Aop, &j64)) != MXL_OK) return st;
     hipError_t e;
-    auto J32 = std::make_shared<JacobiImpl>();
-    J32->A = ir->A32;
-    J32->dinv = alloc((size_t)A->nrows * 4, &e);
-    if (!J32->dinv) { delete j64; return hip_fail(e, "alloc dinv32"); }
-    e = launch_convert_vals(A->nrows, MXL_F64, j64->jac->dinv->p, J32->dinv->p, A->ctx->stream);
-    if (e != hipSuccess) { delete j64; return hip_fail(e, "convert dinv"); }
-    HIP_TRY(hipStreamSynchronize(A->ctx->stream));
-    delete j64;
+    std::shared_ptr<JacobiImpl> J32;
+    if (prm->inner_block_size > 0) {
+        // block Jacobi from the FP64 matrix; usable with the FP32 vectors as is
+        mxl_op *bj = nullptr;
+        if ((st = mxl_bjacobi_generate(Aop, prm->inner_block_size, 1, prm->inner_block_accuracy, &bj)) != MXL_OK)
+            return st;
+        J32 = bj->jac;
+        delete bj;
+    } else {
+        if (prm->inner_block_size < 0) return fail(MXL_ERR_INVALID_ARG, "inner_block_size < 0");
+        mxl_op *j64 = nullptr;
+        if ((st = mxl_jacobi_generate(Aop, &j64)) != MXL_OK) return st;
+        J32 = std::make_shared<JacobiImpl>();
+        J32->A = ir->A32;
+        J32->dinv = alloc((size_t)A->nrows * 4, &e);
+        if (!J32->dinv) { delete j64; return hip_fail(e, "alloc dinv32"); }
+        e = launch_convert_vals(A->nrows, MXL_F64, j64->jac->dinv->p, J32->dinv->p, A->ctx->stream);
+        if (e != hipSuccess) { delete j64; return hip_fail(e, "convert dinv"); }
+        HIP_TRY(hipStreamSynchronize(A->ctx->stream));
+        delete j64;
+    }
     mxl_criteria oc = prm->outer;
     if ((st = make_solver(MXL_SOLVER_CG, ir->A32, J32, prm->inner, ir->inner)) != MXL_OK) return st;
     mxl_criteria o2 = oc;

@@ -3,7 +3,10 @@ Gauss-Jordan inverses, condition numbers and storage-precision decisions
 equal the oracle's (the device elimination performs the same operations in
 the same order, without contraction), the product z = M r matches the
 oracle's within FP64 rounding, and block-Jacobi CG reaches the oracle's
-iteration counts, at small sizes and at the full 160^3 anisotropic size."""
+iteration counts, at small sizes and at the full 160^3 anisotropic size.
+The same inverses precondition the FP32 CG inside iterative refinement (z
+rounded to FP32): its iterates follow the oracle's to single precision and
+the refinement reaches the oracle's outer and inner counts."""
 import json
 import os
 
@@ -124,3 +127,76 @@ def test_bjacobi_errors(mxl, ctx):
     with pytest.raises(mxl.MxlError) as e:
         mxl.solver("bicgstab", A, P)
     assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
+
+
+@pytest.mark.parametrize("bs", [4, 8, 32])
+@pytest.mark.parametrize("k", [1, 3, 10])
+def test_f32_block_cg_iterates_match_oracle(mxl, ctx, k, bs):
+    """FP32 CG (FP32 matrix values and vectors) with FP64-generated adaptive
+    block inverses, k steps without a tolerance, against the oracle's FP32
+    block CG: the iterates agree to single precision (the reductions sum in
+    another order)."""
+    A = W.aniso_3d7(11)
+    b32 = W.uniform_vec(A.nrows, 6).astype(np.float32)
+    bp = O.uniform_blocks(A.nrows, bs)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=True)
+    ref = O.pcg_f32_block(A, b32, bp, inv, max_iters=k, reduction=0.0)
+    M64 = matrix(mxl, ctx, A)
+    M32 = matrix(mxl, ctx, A, torch.float32)
+    S = mxl.solver("cg", M32, mxl.bjacobi(M64, bs, True), max_iters=k, reduction=0.0)
+    x = torch.zeros(A.nrows, dtype=torch.float32, device=DEV)
+    info = S.solve(torch.from_numpy(b32).to(DEV), x)
+    assert info["iterations"] == k == ref["iterations"] and info["stop_reason"] == mxl.STOP_MAX_ITERS
+    got = x.cpu().numpy().astype(np.float64)
+    want = ref["x"].astype(np.float64)
+    assert np.linalg.norm(got - want) <= 2e-5 * np.linalg.norm(want), np.linalg.norm(got - want) / np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("bs,acc", [(8, 0.1), (32, 0.1), (8, 1e-8)])
+def test_ir_block_inner_matches_oracle(mxl, ctx, bs, acc):
+    A = W.aniso_3d7(28)
+    b = W.uniform_vec(A.nrows, 4)
+    ref = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4, block_size=bs, block_accuracy=acc)
+    M = matrix(mxl, ctx, A)
+    S = mxl.ir(M, outer=dict(max_iters=50, reduction=1e-12), inner=dict(reduction=1e-4, max_iters=10_000),
+               block_size=bs, block_accuracy=acc)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x, history=60)
+    print(f"[ir block {bs} {acc}] gpu outer {info['iterations']} inner {info['inner_iterations']} | oracle "
+          f"{ref['outer']} {ref['inner_iterations']}", flush=True)
+    assert ref["stop_reason"] == O.CONVERGED and info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["outer"]) <= 1
+    assert abs(info["inner_iterations"] - ref["inner_iterations"]) <= max(4, 0.05 * ref["inner_iterations"])
+    res = np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) / np.linalg.norm(b)
+    assert res <= 1e-12
+
+
+def test_ir_block_full_size(mxl, ctx):
+    """160^3 anisotropic system: refinement to 1e-10 with 32-row adaptive
+    block Jacobi in the FP32 inner CG; the FP64 residual recomputed."""
+    A = W.aniso_3d7(160)
+    b = W.uniform_vec(A.nrows, 4)
+    M = matrix(mxl, ctx, A).convert("ell")
+    S = mxl.ir(M, outer=dict(max_iters=20, reduction=1e-10), inner=dict(reduction=1e-4, max_iters=5000,
+                                                                          check_every=16),
+               block_size=32, block_accuracy=0.1)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[ir block full] outer {info['iterations']} inner {info['inner_iterations']} "
+          f"{info['seconds']:.3f}s", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED and info["iterations"] <= 4
+    r = dev(b).clone()
+    M.apply(x, r, -1.0, 1.0)
+    assert float(torch.linalg.norm(r)) <= 1.01e-10 * float(np.linalg.norm(b))
+
+
+def test_ir_block_errors(mxl, ctx):
+    A = matrix(mxl, ctx, W.stencil_2d5(8))
+    for bs in (3, 64, -1):
+        with pytest.raises(mxl.MxlError) as e:
+            mxl.ir(A, block_size=bs)
+        assert e.value.status == mxl.ERR_INVALID_ARG
+    S2 = W.Csr(2, 2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]), "swap")
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.ir(matrix(mxl, ctx, S2), block_size=1)
+    assert e.value.status == mxl.ERR_ZERO_DIAG
