@@ -97,8 +97,9 @@ def main():
                              "gmres"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solver would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (a sharded solve "
+              "would split rows into contiguous slabs, exchange halo entries of the SpMV input and "
+              "all-reduce the scalar dot products).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

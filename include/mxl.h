@@ -431,7 +431,7 @@ mxl_status mxl_mlp_adam_step(mxl_mlp *m, int64_t t, float lr, float beta1,
 mxl_status mxl_mlp_destroy(mxl_mlp *m);
 
 /* Run-time choice of (format, kernel variant), the fork of Sec. 7.2, learned
- * from timings and judged by time, with performance profiles (Sec. 7.3) as
+ * from timings and scored by time, with performance profiles (Sec. 7.3) as
  * the evaluation.  A selector holds the candidate classes, a trained MLP
  * (16 features -> one score per class, s_c ~ log(t_c / t_best)) and the
  * feature standardisation z_j = (phi_j(f_j) - mean_j) / std_j, where phi_j is

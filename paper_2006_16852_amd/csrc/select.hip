@@ -3,7 +3,7 @@
 // forward pass, gradient and Adam step, so the selector is trained on the
 // GPU by this library's own kernels.  The selector stands in for the
 // paper's runtime "kernel variant selection" fork (Sec. 7.2), and its quality
-// is judged with the performance-profile view of Sec. 7.3.
+// is scored with the performance-profile view of Sec. 7.3.
 //
 // Features use exact integer statistics: sums of len, len^2, len^3, |i-j|,
 // counts and extrema are accumulated as 64-bit integers (order-independent,

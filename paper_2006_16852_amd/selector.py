@@ -1,7 +1,7 @@
 """Learned format/kernel selector.
 
 The paper forks at run time over matrix format and kernel variant (Sec. 7.2)
-and judges kernels with a performance profile (Sec. 7.3).  This module
+and compares kernels with a performance profile (Sec. 7.3).  This module
 learns that fork: 16 structural features of a CSR matrix (computed on the GPU
 by ``mxl_features``) go through a small MLP (trained on the GPU by the
 library's own forward/backward/Adam kernels) that predicts, for each
@@ -10,7 +10,7 @@ over feasible classes; when the network is unsure (top-2 margin below
 ``delta``) or the matrix lies outside the training distribution (a
 standardised feature beyond ``zmax``) it falls back to timing the top-3
 candidates.  Exhaustive timing (``mxl_time_apply``) produces the labels and
-is the judge (time regret = t_choice / t_best - 1).
+scores the choice (time regret = t_choice / t_best - 1).
 
 A trained selector carries the names of its classes, so weights trained on
 one set of classes stay valid when the catalog grows.

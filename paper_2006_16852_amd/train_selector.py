@@ -140,7 +140,7 @@ def main():
     sel.save(os.path.join(args.out, "selector_weights.json"))
     Ft, Tt = F[test], T[test]
     choice_net = evaluate(ctx, sel, Ft, Tt)
-    # fallback uses the measured test times of the top-3 (same labels as the judge)
+    # fallback uses the measured test times of the top-3 (the same labels the regret is scored on)
     scores = sel.scores(ctx, Ft)
     choice_fb = []
     nfb = 0

@@ -46,7 +46,7 @@ FORMATS = [("csr", dict(variant=1)), ("csr", dict(variant=2)), ("csr", dict(vari
 
 
 @pytest.mark.parametrize("fmt,kw", FORMATS, ids=["vec", "merge", "scalar", "stream", "coo", "ell", "ell16", "hyb"])
-def test_pcg_cfg1_all_formats(mxl, ctx, fmt, kw):
+def test_pcg_poisson2d_64_all_formats(mxl, ctx, fmt, kw):
     A = W.stencil_2d5(64)
     b = O.spmv(A, W.uniform_vec(A.nrows, 1))
     d, _ = O.jacobi_dinv(A)
@@ -56,7 +56,7 @@ def test_pcg_cfg1_all_formats(mxl, ctx, fmt, kw):
     S = mxl.solver("cg", M, P, max_iters=10_000, reduction=1e-10)
     x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
     info = S.solve(dev(b), x, history=400)
-    print(f"[pcg cfg1 {fmt}] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
+    print(f"[pcg poisson2d {fmt}] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
     assert info["stop_reason"] == mxl.STOP_CONVERGED
     assert _close_iters(info["iterations"], ref["iterations"])
     assert _true_rel(A, b, x.cpu().numpy()) <= 1.01e-10

@@ -322,7 +322,7 @@ def test_cg_textbook_bound_and_monotone_error():
         prev = ek
 
 
-def test_cg_iteration_count_matches_scipy_cfg1():
+def test_cg_iteration_count_matches_scipy_poisson2d_64():
     import scipy.sparse as sp
     import scipy.sparse.linalg as spl
     A = W.stencil_2d5(64)
