@@ -365,8 +365,14 @@ mxl_status mxl_batch_csr_create(mxl_ctx *ctx, int64_t nsys,
 
 /* Schedule of the persistent batched kernel.  wg_size in {64,128,256,512,
  * 1024}; wgs_per_cu >= 1 resident workgroups per compute unit; order 0 =
- * systems in input order, 1 = largest first. */
-typedef struct { int32_t wg_size; int32_t wgs_per_cu; int32_t order; } mxl_tuning;
+ * systems in input order, 1 = largest first; format 0 = the per-system ELL
+ * copy when the batch has one, else CSR, 1 = CSR, 2 = ELL (NOT_IMPLEMENTED
+ * when the batch has no ELL copy).  mxl_batch_csr_create builds the ELL
+ * copy (slot-major per system, int16 local columns) when every system has
+ * at most 32767 rows and the padded slots total at most 1.5 x the stored
+ * entries (+ 64 per system); the ELL kernel keeps a system's vectors and,
+ * when they fit, its matrix in LDS for all of its iterations. */
+typedef struct { int32_t wg_size; int32_t wgs_per_cu; int32_t order; int32_t format; } mxl_tuning;
 
 /* Jacobi-PCG on every system independently (per-system stopping status,
  * Sec. 2.5), all in one persistent launch.  crit->max_iters <= 0 means

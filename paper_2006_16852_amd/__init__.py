@@ -76,7 +76,7 @@ class IrParams(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("wg_size", C.c_int32), ("wgs_per_cu", C.c_int32), ("order", C.c_int32)]
+    _fields_ = [("wg_size", C.c_int32), ("wgs_per_cu", C.c_int32), ("order", C.c_int32), ("format", C.c_int32)]
 
 
 class KernelClass(C.Structure):
@@ -470,7 +470,7 @@ class Batch(Op):
                                    _ptr(b), _ptr(x), _ptr(iters), _ptr(rel_res), _ptr(status)))
 
     def autotune(self, b, x_scratch, reps: int = 2, **crit):
-        """Time every schedule on this batch; returns ((wg_size, wgs_per_cu, order), ms)."""
+        """Time every schedule on this batch; returns ((wg_size, wgs_per_cu, order, format), ms)."""
         _need_cuda(b, x_scratch)
         c = criteria(**({"max_iters": 0} | crit))
         t = Tuning()
@@ -478,7 +478,7 @@ class Batch(Op):
         self.ctx.use_current_stream()
         _check(lib.mxl_batch_autotune(self.h, C.byref(c), _ptr(b), _ptr(x_scratch), reps,
                                       C.byref(t), C.byref(ms)))
-        return (t.wg_size, t.wgs_per_cu, t.order), ms.value
+        return (t.wg_size, t.wgs_per_cu, t.order, t.format), ms.value
 
 
 def batch(ctx: Context, sys_ptr_host, sys_ptr, row_ptr, col, val) -> Batch:

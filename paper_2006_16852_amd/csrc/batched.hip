@@ -41,6 +41,13 @@ struct BatchImpl {
     mxl_tuning best{};
     int small_shape = -1;    // single-system register-cached shape (-1: not chosen)
     int small_bi_shape = -1; // the same for the one-workgroup BiCGSTAB
+    // Per-system slot-major ELL copy (built when it is compact): system s has
+    // w_s = its longest row; slot e of local row i is at off_s + e*n_s + i,
+    // columns as int16 local indices, -1 for padding.
+    bool ell = false;
+    int w_max = 0;
+    int64_t ell_slots = 0;
+    BufPtr ell_val, ell_col, ell_off, ell_w;
 };
 
 template <int B>
@@ -181,6 +188,167 @@ __global__ __launch_bounds__(B) void k_batch_pcg(
             status_out[s] = (uint8_t)stop;
         }
         __syncthreads();
+    }
+}
+
+// The same persistent Jacobi-PCG on the per-system ELL copy.  A system
+// whose five vectors (x, r, p, q, dinv) fit the workgroup's LDS budget keeps
+// them there, and its matrix too when that also fits, so every iteration
+// after the first reads only LDS; the product walks slot-major entries
+// (consecutive rows at consecutive addresses) in each row's stored order,
+// so q and every scalar equal k_batch_pcg's at the same workgroup size.
+// Larger systems keep their vectors in a global scratch slice and read the
+// matrix from the global ELL copy.
+template <int B>
+__global__ __launch_bounds__(B) void k_batch_pcg_ell(
+    int64_t nsys, const int *__restrict__ sys_ptr, const int64_t *__restrict__ ell_off,
+    const int *__restrict__ ell_w, const double *__restrict__ ell_val, const short *__restrict__ ell_col,
+    const double *__restrict__ dinv, const double *__restrict__ bvec, double *__restrict__ xout,
+    int *__restrict__ iters_out, double *__restrict__ rel_out, uint8_t *__restrict__ status_out,
+    const int *__restrict__ order, unsigned *__restrict__ queue, double red_factor, int64_t max_iters_fixed,
+    int iter_factor, int chk, int64_t lds_budget, double *__restrict__ scratch, int64_t scratch_stride,
+    int use_x0) {
+    extern __shared__ double smem[];
+    __shared__ double red[2 * (B / kWave)];
+    __shared__ int s_q;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) s_q = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int qi = s_q;
+        __syncthreads();
+        if ((int64_t)qi >= nsys) break;
+        const int s = order[qi];
+        const int r0 = sys_ptr[s];
+        const int n = sys_ptr[s + 1] - r0;
+        const int w = ell_w[s];
+        const int64_t off = ell_off[s];
+        const int64_t vec_bytes = (int64_t)40 * n, mat_bytes = (int64_t)10 * w * n;
+        const bool in_lds = vec_bytes <= lds_budget;
+        const bool mat_lds = in_lds && vec_bytes + mat_bytes <= lds_budget;
+        double *base = in_lds ? smem : scratch + (int64_t)blockIdx.x * scratch_stride;
+        double *x = base, *r = base + n, *p = base + 2 * n, *q = base + 3 * n, *di = base + 4 * n;
+        const double *Vm = mat_lds ? base + 5 * n : ell_val + off;
+        const short *Cm = mat_lds ? (const short *)(base + 5 * n + (int64_t)w * n) : ell_col + off;
+        if (mat_lds) {
+            double *vl = base + 5 * n;
+            short *cl = (short *)(base + 5 * n + (int64_t)w * n);
+            for (int64_t j = tid; j < (int64_t)w * n; j += B) {
+                vl[j] = ell_val[off + j];
+                cl[j] = ell_col[off + j];
+            }
+        }
+        const double *b = bvec + r0;
+        for (int i = tid; i < n; i += B) {
+            x[i] = use_x0 ? xout[r0 + i] : 0.0;
+            di[i] = dinv[r0 + i];
+        }
+        __syncthreads();
+        // r = b - A x, p = z = D^{-1} r
+        double rz = 0.0, rr0 = 0.0, bb = 0.0;
+        for (int i = tid; i < n; i += B) {
+            const double bi = b[i];
+            double ax = 0.0;
+            if (use_x0)
+                for (int e = 0; e < w; ++e) {
+                    const int c = Cm[(int64_t)e * n + i];
+                    if (c >= 0) ax += Vm[(int64_t)e * n + i] * x[c];
+                }
+            const double ri = bi - ax;
+            const double zi = di[i] * ri;
+            r[i] = ri;
+            p[i] = zi;
+            rz += ri * zi;
+            rr0 += ri * ri;
+            bb += bi * bi;
+        }
+        wg_sum2<B>(rz, bb, red);
+        rr0 = wg_sum<B>(rr0, red);
+        const double nb = sqrt(bb);
+        const int64_t maxit = max_iters_fixed > 0 ? max_iters_fixed : (int64_t)iter_factor * n;
+        int stop = ST_RUN;
+        int64_t k = 0;
+        double rr = rr0;
+        if (bb == 0.0) {  // zero right-hand side: x = 0
+            for (int i = tid; i < n; i += B) x[i] = 0.0;
+            stop = ST_CONVERGED;
+        } else if (sqrt(rr) <= red_factor * nb) {
+            stop = ST_CONVERGED;
+        }
+        double rho = rz;
+        while (stop == ST_RUN && k < maxit) {
+            __syncthreads();  // p complete
+            double pq = 0.0;
+            for (int i = tid; i < n; i += B) {
+                double acc = 0.0;
+#pragma unroll 4
+                for (int e = 0; e < w; ++e) {
+                    const int c = Cm[(int64_t)e * n + i];
+                    if (c >= 0) acc += Vm[(int64_t)e * n + i] * p[c];
+                }
+                q[i] = acc;
+                pq += p[i] * acc;
+            }
+            const double eta = wg_sum<B>(pq, red);
+            if (chk && !finite_d(eta)) { stop = ST_NONFINITE; break; }
+            if (eta <= 0.0) { stop = ST_BREAKDOWN; break; }
+            const double alpha = rho / eta;
+            double rzn = 0.0, rrn = 0.0;
+            for (int i = tid; i < n; i += B) {
+                x[i] += alpha * p[i];
+                const double ri = r[i] - alpha * q[i];
+                r[i] = ri;
+                rzn += ri * (di[i] * ri);
+                rrn += ri * ri;
+            }
+            wg_sum2<B>(rzn, rrn, red);
+            ++k;
+            rr = rrn;
+            if (chk && !finite_d(rr)) { stop = ST_NONFINITE; break; }
+            if (sqrt(rr) <= red_factor * nb) { stop = ST_CONVERGED; break; }
+            if (chk && !finite_d(rzn)) { stop = ST_NONFINITE; break; }
+            if (rzn == 0.0) { stop = ST_BREAKDOWN; break; }
+            const double beta = rzn / rho;
+            rho = rzn;
+            for (int i = tid; i < n; i += B) p[i] = di[i] * r[i] + beta * p[i];
+        }
+        if (stop == ST_RUN) stop = ST_MAX_ITERS;
+        __syncthreads();
+        for (int i = tid; i < n; i += B) xout[r0 + i] = x[i];
+        if (tid == 0) {
+            iters_out[s] = (int)k;
+            rel_out[s] = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+            status_out[s] = (uint8_t)stop;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per system: checks 0 <= col < n_s for every stored entry
+// (lowest bad row into *bad) and, when ev is not null, writes the system's
+// slot-major ELL copy (padding: value 0, column -1).
+__global__ void k_batch_to_ell(const int *__restrict__ sys_ptr, const int *__restrict__ rp,
+                               const int *__restrict__ col, const double *__restrict__ val,
+                               const int64_t *__restrict__ ell_off, const int *__restrict__ ell_w,
+                               double *__restrict__ ev, short *__restrict__ ec, int *__restrict__ bad) {
+    const int s = blockIdx.x;
+    const int r0 = sys_ptr[s], n = sys_ptr[s + 1] - r0;
+    const int w = ev ? ell_w[s] : 0;
+    const int64_t off = ev ? ell_off[s] : 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int e0 = rp[r0 + i], len = rp[r0 + i + 1] - e0;
+        bool ok = true;
+        for (int e = 0; e < len; ++e) {
+            const int c = col[e0 + e];
+            if (c < 0 || c >= n) ok = false;
+        }
+        if (!ok) atomicMin(bad, r0 + i);
+        if (ev)
+            for (int e = 0; e < w; ++e) {
+                const bool in = e < len;
+                ev[off + (int64_t)e * n + i] = in ? val[e0 + e] : 0.0;
+                ec[off + (int64_t)e * n + i] = in ? (short)col[e0 + e] : (short)-1;
+            }
     }
 }
 
@@ -539,23 +707,61 @@ using namespace mxl;
 
 namespace {
 
-struct Cand {
-    int B, wpc, order;
-};
-
 size_t lds_bytes_for(int n) { return (size_t)4 * n * sizeof(double); }
+
+// LDS bytes one workgroup of a schedule may use: all resident workgroups of
+// a CU share its LDS.
+int64_t lds_budget_for(const mxl_ctx *ctx, int wpc) {
+    hipDeviceProp_t prop;
+    size_t per_cu = 160 * 1024, per_wg = 64 * 1024;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        if (prop.maxSharedMemoryPerMultiProcessor > 0) per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        if (prop.sharedMemPerBlock > 0) per_wg = prop.sharedMemPerBlock;
+    }
+    return (int64_t)std::min(per_wg, per_cu / (size_t)std::max(1, wpc)) - 2048;  // static LDS headroom
+}
+
+// Vector length of the CSR kernel's LDS vectors (x, r, p, q) for a schedule.
+int lds_cap_for(const mxl_ctx *ctx, const BatchImpl &Bt, int wpc) {
+    const int64_t budget = lds_budget_for(ctx, wpc);
+    int cap = (int)(budget / (int64_t)(4 * sizeof(double)));
+    return std::min(cap, Bt.max_n);
+}
+
+// The kernel a schedule runs: its format field, 0 choosing ELL when built.
+bool use_ell(const BatchImpl &Bt, const mxl_tuning &t) { return t.format == 2 || (t.format == 0 && Bt.ell); }
 
 hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
                         const double *b, double *x, int32_t *iters, double *rel, uint8_t *status,
-                        int lds_cap, hipStream_t s, int use_x0 = 0) {
+                        int lds_cap, int64_t ell_budget, hipStream_t s, int use_x0 = 0) {
     const int G = t.wgs_per_cu * Bt.ctx->num_cu;
     const int *order = (const int *)(t.order ? Bt.order_big->p : Bt.order_input->p);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, (unsigned *)Bt.queue->p);
-    const size_t shm = lds_bytes_for(lds_cap);
     const int chk = c.nonfinite_check;
     const double red = c.reduction;
     const int64_t mif = c.max_iters;
     double *scr = Bt.scratch ? (double *)Bt.scratch->p : nullptr;
+    if (use_ell(Bt, t)) {
+        const size_t shm = (size_t)ell_budget;
+        const int64_t stride = Bt.scratch ? (int64_t)5 * Bt.max_n : 0;
+#define MXL_BATCH_ELL_CASE(BB)                                                                       \
+    case BB:                                                                                         \
+        hipLaunchKernelGGL(k_batch_pcg_ell<BB>, dim3(G), dim3(BB), shm, s, Bt.nsys,                  \
+                           (const int *)Bt.sys_ptr->p, (const int64_t *)Bt.ell_off->p,              \
+                           (const int *)Bt.ell_w->p, (const double *)Bt.ell_val->p,                 \
+                           (const short *)Bt.ell_col->p, (const double *)Bt.dinv->p, b, x, iters,   \
+                           rel, status, order, (unsigned *)Bt.queue->p, red, mif, 10, chk,          \
+                           ell_budget, scr, stride, use_x0);                                        \
+        break;
+        switch (t.wg_size) {
+            MXL_BATCH_ELL_CASE(64) MXL_BATCH_ELL_CASE(128) MXL_BATCH_ELL_CASE(256) MXL_BATCH_ELL_CASE(512)
+            MXL_BATCH_ELL_CASE(1024)
+        default: return hipErrorInvalidValue;
+        }
+#undef MXL_BATCH_ELL_CASE
+        return hipGetLastError();
+    }
+    const size_t shm = lds_bytes_for(lds_cap);
     const int64_t stride = Bt.scratch ? (int64_t)4 * Bt.max_n : 0;
 #define MXL_BATCH_CASE(BB)                                                                          \
     case BB:                                                                                        \
@@ -571,20 +777,6 @@ hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_crit
     }
 #undef MXL_BATCH_CASE
     return hipGetLastError();
-}
-
-// LDS capacity (vector length that fits) for a schedule: all resident
-// workgroups of a CU share its LDS.
-int lds_cap_for(const mxl_ctx *ctx, const BatchImpl &Bt, int wpc) {
-    hipDeviceProp_t prop;
-    size_t per_cu = 160 * 1024, per_wg = 64 * 1024;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
-        if (prop.maxSharedMemoryPerMultiProcessor > 0) per_cu = prop.maxSharedMemoryPerMultiProcessor;
-        if (prop.sharedMemPerBlock > 0) per_wg = prop.sharedMemPerBlock;
-    }
-    size_t budget = std::min(per_wg, per_cu / (size_t)std::max(1, wpc)) - 2048;  // static LDS headroom
-    int cap = (int)(budget / (4 * sizeof(double)));
-    return std::min(cap, Bt.max_n);
 }
 
 }  // namespace
@@ -670,6 +862,55 @@ extern "C" mxl_status mxl_batch_csr_create(mxl_ctx *ctx, int64_t nsys, const int
         return set_error(MXL_ERR_DEVICE, "batch jacobi");
     if (badh != INT_MAX)
         return set_error(MXL_ERR_ZERO_DIAG, "row " + std::to_string(badh) + " has a missing or zero diagonal");
+    // Row lengths on the host: canonical row_ptr, and the per-system ELL
+    // layout when it stays compact (<= 1.5 x the stored entries) and local
+    // columns fit int16.
+    std::vector<int32_t> rp_h((size_t)Bt->rows + 1);
+    if (hipMemcpyAsync(rp_h.data(), row_ptr, ((size_t)Bt->rows + 1) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "read row_ptr");
+    if (rp_h[0] != 0) return set_error(MXL_ERR_INVALID_MATRIX, "row_ptr[0] != 0");
+    for (int64_t r = 0; r < Bt->rows; ++r)
+        if (rp_h[r + 1] < rp_h[r]) return set_error(MXL_ERR_INVALID_MATRIX, "row_ptr decreases at row " + std::to_string(r));
+    std::vector<int32_t> w_h(nsys);
+    std::vector<int64_t> off_h(nsys);
+    int64_t slots = 0;
+    int w_max = 0;
+    for (int64_t sy = 0; sy < nsys; ++sy) {
+        int w = 0;
+        for (int32_t r = Bt->sys_ptr_h[sy]; r < Bt->sys_ptr_h[sy + 1]; ++r) w = std::max(w, rp_h[r + 1] - rp_h[r]);
+        w_h[sy] = w;
+        w_max = std::max(w_max, w);
+        off_h[sy] = slots;
+        slots += ((int64_t)w * (Bt->sys_ptr_h[sy + 1] - Bt->sys_ptr_h[sy]) + 1) / 2 * 2;
+    }
+    const bool ell = max_n <= 32767 && (double)slots <= 1.5 * (double)Bt->nnz + 64.0 * (double)nsys;
+    if (ell) {
+        Bt->ell_val = alloc((size_t)slots * 8);
+        Bt->ell_col = alloc((size_t)slots * 2);
+        Bt->ell_off = alloc((size_t)nsys * 8);
+        Bt->ell_w = alloc((size_t)nsys * 4);
+        if (!Bt->ell_val || !Bt->ell_col || !Bt->ell_off || !Bt->ell_w)
+            return set_error(MXL_ERR_OUT_OF_MEMORY, "batch ELL copy");
+        if (hipMemcpyAsync(Bt->ell_off->p, off_h.data(), (size_t)nsys * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(Bt->ell_w->p, w_h.data(), (size_t)nsys * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            return set_error(MXL_ERR_DEVICE, "upload ELL tables");
+        Bt->ell = true;
+        Bt->w_max = w_max;
+        Bt->ell_slots = slots;
+    }
+    badh = INT_MAX;
+    if (hipMemcpyAsync(bad->p, &badh, 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "upload flag");
+    hipLaunchKernelGGL(k_batch_to_ell, dim3((unsigned)nsys), dim3(256), 0, s, sys_ptr, row_ptr, col, val,
+                       ell ? (const int64_t *)Bt->ell_off->p : nullptr, ell ? (const int *)Bt->ell_w->p : nullptr,
+                       ell ? (double *)Bt->ell_val->p : nullptr, ell ? (short *)Bt->ell_col->p : nullptr,
+                       (int *)bad->p);
+    if (hipMemcpyAsync(&badh, bad->p, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(MXL_ERR_DEVICE, "batch column check");
+    if (badh != INT_MAX)
+        return set_error(MXL_ERR_INVALID_MATRIX, "row " + std::to_string(badh) + " has a column outside its system");
     auto *op = new mxl_op;
     op->kind = MXL_OP_BATCH;
     op->bat = Bt;
@@ -694,6 +935,20 @@ static mxl_status batch_args(const BatchImpl &Bt, const double *b, double *x, co
     return MXL_OK;
 }
 
+// Dynamic LDS above 64 KB needs the kernel's attribute raised first.
+#define MXL_ALLOW_LDS(KERN, WG, SHM)                                                                    \
+    [&]() -> hipError_t {                                                                               \
+        if ((SHM) <= 64 * 1024) return hipSuccess;                                                      \
+        const int v_ = (int)(SHM);                                                                      \
+        switch (WG) {                                                                                   \
+        case 64: return hipFuncSetAttribute((const void *)KERN<64>, hipFuncAttributeMaxDynamicSharedMemorySize, v_);   \
+        case 128: return hipFuncSetAttribute((const void *)KERN<128>, hipFuncAttributeMaxDynamicSharedMemorySize, v_); \
+        case 256: return hipFuncSetAttribute((const void *)KERN<256>, hipFuncAttributeMaxDynamicSharedMemorySize, v_); \
+        case 512: return hipFuncSetAttribute((const void *)KERN<512>, hipFuncAttributeMaxDynamicSharedMemorySize, v_); \
+        default: return hipFuncSetAttribute((const void *)KERN<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, v_); \
+        }                                                                                               \
+    }()
+
 static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
                                const double *b, double *x, int32_t *iters, double *rel,
                                uint8_t *status) {
@@ -701,10 +956,18 @@ static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_cri
         return set_error(MXL_ERR_INVALID_ARG, "wg_size must be 64, 128, 256, 512 or 1024");
     if (t.wgs_per_cu < 1 || t.wgs_per_cu > 32 || (t.order != 0 && t.order != 1))
         return set_error(MXL_ERR_INVALID_ARG, "wgs_per_cu in 1..32, order 0 or 1");
+    if (t.format < 0 || t.format > 2) return set_error(MXL_ERR_INVALID_ARG, "format must be 0, 1 or 2");
+    if (t.format == 2 && !Bt.ell)
+        return set_error(MXL_ERR_NOT_IMPLEMENTED, "this batch has no compact ELL copy (format 2)");
+    const bool ell = use_ell(Bt, t);
     const int cap = lds_cap_for(Bt.ctx, Bt, t.wgs_per_cu);
-    if (cap < 1) return set_error(MXL_ERR_INVALID_ARG, "schedule leaves no LDS per workgroup");
-    if (cap < Bt.max_n) {  // systems above cap run from a global scratch slice per workgroup
-        const int64_t need = (int64_t)t.wgs_per_cu * Bt.ctx->num_cu * 4 * Bt.max_n;
+    // the ELL kernel's LDS: at most what the largest system can use
+    const int64_t ell_budget = std::min(lds_budget_for(Bt.ctx, t.wgs_per_cu),
+                                        (int64_t)Bt.max_n * (40 + 10 * (int64_t)Bt.w_max));
+    if (cap < 1 || ell_budget < 40) return set_error(MXL_ERR_INVALID_ARG, "schedule leaves no LDS per workgroup");
+    const bool spill = ell ? (int64_t)40 * Bt.max_n > ell_budget : cap < Bt.max_n;
+    if (spill) {  // systems above the LDS capacity run from a global scratch slice per workgroup
+        const int64_t need = (int64_t)t.wgs_per_cu * Bt.ctx->num_cu * 5 * Bt.max_n;
         if (Bt.scratch_elems < need) {
             auto d = std::make_shared<DevBuf>();
             if (hipMalloc(&d->p, need * 8) != hipSuccess) return set_error(MXL_ERR_OUT_OF_MEMORY, "batch scratch");
@@ -714,19 +977,10 @@ static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_cri
             Bt.scratch_elems = need;
         }
     }
-    const size_t shm = lds_bytes_for(cap);
-    hipError_t e = hipSuccess;
-    if (shm > 64 * 1024) {
-        switch (t.wg_size) {
-        case 64: e = hipFuncSetAttribute((const void *)k_batch_pcg<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
-        case 128: e = hipFuncSetAttribute((const void *)k_batch_pcg<128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
-        case 256: e = hipFuncSetAttribute((const void *)k_batch_pcg<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
-        case 512: e = hipFuncSetAttribute((const void *)k_batch_pcg<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
-        default: e = hipFuncSetAttribute((const void *)k_batch_pcg<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); break;
-        }
-        if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
-    }
-    e = launch_batch(Bt, t, c, b, x, iters, rel, status, cap, Bt.ctx->stream);
+    hipError_t e = ell ? MXL_ALLOW_LDS(k_batch_pcg_ell, t.wg_size, (size_t)ell_budget)
+                       : MXL_ALLOW_LDS(k_batch_pcg, t.wg_size, lds_bytes_for(cap));
+    if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
+    e = launch_batch(Bt, t, c, b, x, iters, rel, status, cap, ell_budget, Bt.ctx->stream);
     if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
     return MXL_OK;
 }
@@ -736,6 +990,7 @@ static mxl_tuning default_tuning() {
     t.wg_size = 256;
     t.wgs_per_cu = 2;
     t.order = 0;
+    t.format = 0;
     return t;
 }
 
@@ -775,11 +1030,15 @@ extern "C" mxl_status mxl_batch_autotune(const mxl_op *Bop, const mxl_criteria *
     double best = 1e300;
     mxl_tuning bt = default_tuning();
     st = MXL_OK;
+    std::vector<int> fmts{1};
+    if (Bt->ell) fmts.push_back(2);
+    for (int fmt : fmts) {
+    if (st != MXL_OK) break;
     for (int B : {64, 128, 256, 512}) {
         for (int wpc : {1, 2, 4, 8}) {
             if (B * wpc > 2048) continue;  // at most 32 waves per CU
             for (int ord : {0, 1}) {
-                mxl_tuning t{B, wpc, ord};
+                mxl_tuning t{B, wpc, ord, fmt};
                 std::vector<float> ts;
                 for (int r = 0; r < reps + 1 && st == MXL_OK; ++r) {
                     (void)hipEventRecord(e0, s);
@@ -798,6 +1057,7 @@ extern "C" mxl_status mxl_batch_autotune(const mxl_op *Bop, const mxl_criteria *
             if (st != MXL_OK) break;
         }
         if (st != MXL_OK) break;
+    }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -972,7 +1232,7 @@ mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double
         *stop = (uint8_t)h[16];
         return MXL_OK;
     }
-    mxl_tuning t{1024, 1, 0};
+    mxl_tuning t{1024, 1, 0, 1};
     const int cap = lds_cap_for(Bt.ctx, Bt, 1);
     if (cap < Bt.max_n && !Bt.scratch) {
         auto d = std::make_shared<DevBuf>();
@@ -990,7 +1250,7 @@ mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double
     int32_t *dit = (int32_t *)out3;
     double *drel = (double *)((char *)out3 + 8);
     uint8_t *dst = (uint8_t *)((char *)out3 + 16);
-    hipError_t e = launch_batch(Bt, t, c, b, x, dit, drel, dst, cap, Bt.ctx->stream, 1);
+    hipError_t e = launch_batch(Bt, t, c, b, x, dit, drel, dst, cap, 0, Bt.ctx->stream, 1);
     if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("single-launch CG: ") + hipGetErrorString(e));
     char h[24];
     if (hipMemcpyAsync(h, out3, 24, hipMemcpyDeviceToHost, Bt.ctx->stream) != hipSuccess ||

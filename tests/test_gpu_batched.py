@@ -3,7 +3,8 @@
 Bar: every system converges; iteration counts within 2 of the oracle's for
 at least 99% of systems (summation order differs); the residual recomputed
 in FP64 on the CPU meets 1e-10; schedules that share the workgroup size give
-bitwise-identical results."""
+bitwise-identical results, and so do the CSR and the per-system ELL kernels
+(the ELL product keeps each row's stored order)."""
 import numpy as np
 import pytest
 import torch
@@ -65,7 +66,8 @@ def test_batch_schedules_same_wg_size_bitwise(mxl, ctx):
     assert np.array_equal(it1, it2) and np.array_equal(x1, x2)
 
 
-def test_batch_large_system_scratch_path(mxl, ctx):
+@pytest.mark.parametrize("fmt", [1, 2], ids=["csr", "ell"])
+def test_batch_large_system_scratch_path(mxl, ctx, fmt):
     """A system larger than the LDS capacity runs from global scratch: the
     64x64 Poisson system as a batch of one, plus small systems around it."""
     A = W.stencil_2d5(64)
@@ -76,10 +78,63 @@ def test_batch_large_system_scratch_path(mxl, ctx):
     Bb = W.Batch(6, sp, rp, np.concatenate([A.col, S.col]), np.concatenate([A.val, S.val]),
                  np.concatenate([b1, S.b]))
     ref = O.batch_pcg(Bb, reduction=1e-10)
-    _, x, it, rel, st = _run(mxl, ctx, Bb, (1024, 1, 1))
+    _, x, it, rel, st = _run(mxl, ctx, Bb, (1024, 1, 1, fmt))
     assert np.all(st == 1)
     assert abs(int(it[0]) - int(ref["iterations"][0])) <= 2
     _check_residuals(Bb, x)
+
+
+@pytest.mark.parametrize("wg,wpc", [(64, 4), (128, 2), (256, 1), (512, 1), (1024, 1)])
+def test_batch_ell_equals_csr_bitwise(mxl, ctx, wg, wpc):
+    B = W.batch_systems(nsys=150, seed=21)
+    _, x1, it1, r1, s1 = _run(mxl, ctx, B, (wg, wpc, 0, 1))
+    _, x2, it2, r2, s2 = _run(mxl, ctx, B, (wg, wpc, 1, 2))
+    assert np.all(s1 == 1)
+    assert np.array_equal(it1, it2) and np.array_equal(x1, x2) and np.array_equal(r1, r2) and np.array_equal(s1, s2)
+
+
+def _batch_from(systems, rhs_seed=3):
+    rps, cols, vals, sp = [], [], [], [0]
+    off = 0
+    for A in systems:
+        rps.append(A.row_ptr[:-1] + off)
+        cols.append(A.col)
+        vals.append(A.val)
+        off += A.nnz
+        sp.append(sp[-1] + A.nrows)
+    rp = np.concatenate(rps + [[off]]).astype(np.int32)
+    b = W.uniform_vec(sp[-1], rhs_seed)
+    return W.Batch(len(systems), np.array(sp, np.int32), rp, np.concatenate(cols).astype(np.int32),
+                   np.concatenate(vals), b)
+
+
+def test_batch_skewed_rows_keep_csr(mxl, ctx):
+    """One dense row in a system makes the padded copy too large: the batch
+    has no ELL copy, format 2 is refused and format 0 runs the CSR kernel."""
+    n = 200
+    D = np.eye(n) * (n + 1.0)
+    D[0, :] += 1.0
+    D[:, 0] += 1.0
+    D[0, 0] = 4.0 * n
+    r, c = np.nonzero(D)
+    A = W.Csr(n, n, np.concatenate([[0], np.cumsum(np.bincount(r, minlength=n))]).astype(np.int32),
+              c.astype(np.int32), D[r, c], "arrow")
+    Bb = _batch_from([A, W.stencil_2d5(6)])
+    with pytest.raises(mxl.MxlError) as e:
+        _run(mxl, ctx, Bb, (128, 2, 0, 2))
+    assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
+    ref = O.batch_pcg(Bb, reduction=1e-10)
+    _, x, it, rel, st = _run(mxl, ctx, Bb, (128, 2, 0, 0))
+    assert np.all(st == 1) and np.all(np.abs(it - ref["iterations"]) <= 2)
+    _check_residuals(Bb, x)
+
+
+def test_batch_column_outside_system_rejected(mxl, ctx):
+    Bb = _batch_from([W.stencil_2d5(4), W.stencil_2d5(3)])
+    Bb.col[Bb.row_ptr[17]] = 9  # a row of the second (9-row) system points at local column 9
+    with pytest.raises(mxl.MxlError) as e:
+        mxl.batch(ctx, Bb.sys_ptr, dev(Bb.sys_ptr), dev(Bb.row_ptr), dev(Bb.col), dev(Bb.val))
+    assert e.value.status == mxl.ERR_INVALID_MATRIX
 
 
 def test_batch_max_iters_and_zero_rhs(mxl, ctx):
@@ -97,7 +152,7 @@ def test_batch_autotune(mxl, ctx):
     b = dev(B.b)
     xs = torch.zeros_like(b)
     best, ms = op.autotune(b, xs, reps=1, reduction=1e-10)
-    assert best[0] in (64, 128, 256, 512) and ms > 0
+    assert best[0] in (64, 128, 256, 512) and best[3] in (1, 2) and ms > 0
     x = torch.zeros_like(b)
     it = torch.zeros(B.nsys, dtype=torch.int32, device=DEV)
     rel = torch.zeros(B.nsys, dtype=torch.float64, device=DEV)
