@@ -99,7 +99,11 @@ def aniso_ir(args):
     # block-Jacobi CG (32-row blocks): binary64 storage and adaptive storage
     for red in (1e-10, 1e-12):
         for adaptive in (False, True):
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
             Pb = mxl.bjacobi(M, 32, adaptive, 0.1)
+            torch.cuda.synchronize()
+            gen_ms = (time.perf_counter() - tg) * 1e3
             Sb = mxl.solver("cg", M, Pb, max_iters=5000, reduction=red, check_every=16)
 
             def fb():
@@ -111,7 +115,7 @@ def aniso_ir(args):
             res[f"bjacobi32_{'adaptive' if adaptive else 'fp64'}_{red:g}"] = dict(
                 ms=round(dt * 1e3, 3), iterations=info["iterations"],
                 true_rel=float(torch.linalg.norm(r) / torch.linalg.norm(b)),
-                storage_MB=round(bi["storage_bytes"] / 1e6, 2),
+                storage_MB=round(bi["storage_bytes"] / 1e6, 2), generate_ms=round(gen_ms, 3),
                 blocks_by_precision=[int((bi["precision"] == k).sum()) for k in (0, 1, 2)])
     # refinement whose FP32 inner CG uses the 32-row adaptive block Jacobi
     for red in (1e-10, 1e-12):

@@ -33,7 +33,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4) -> str:
+def build(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
@@ -47,4 +47,4 @@ def build(jobs: int = 4) -> str:
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else 4))
+    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else 8))

@@ -38,12 +38,23 @@ __device__ __forceinline__ double round_f16(double x) {
     return copysign(rint(a / quantum) * quantum, x);
 }
 
-// One wave inverts one diagonal block.  Lane j owns column j of D and of
-// its inverse I (both in LDS); every element sees the same operations in the
-// same order as a sequential Gauss-Jordan elimination with partial
-// pivoting (first row of largest magnitude), with no multiply-add
-// contraction, so the inverse, its condition number and the precision
-// decision are reproducible.
+// Lane l's value of v, as a wave-uniform scalar (l uniform).
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One wave inverts one diagonal block.  Lane j holds column j of D and of
+// its inverse I in registers (the block is staged through LDS once, row by
+// row, to turn rows into columns); the pivot column's entries reach every
+// lane as uniform scalars, so an elimination step is register arithmetic
+// with no barrier.  Every element sees the same operations in the same
+// order as a sequential Gauss-Jordan elimination with partial pivoting
+// (first row of largest magnitude), with no multiply-add contraction, so
+// the inverse, its condition number and the precision decision are
+// reproducible.
 template <int BS>
 __global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__restrict__ rp,
                                                      const int *__restrict__ col,
@@ -52,81 +63,105 @@ __global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__res
                                                      double *__restrict__ cond, int *__restrict__ prec,
                                                      int *__restrict__ bad) {
 #pragma clang fp contract(off)
-    __shared__ double D[BS][BS], I[BS][BS];
+    __shared__ double L[BS][BS + 1];
     const int64_t b = blockIdx.x;
     const int64_t r0 = b * BS;
     const int m = (int)(n - r0 < BS ? n - r0 : BS);
     const int j = threadIdx.x;
-    if (j < BS)
-        for (int i = 0; i < BS; ++i) {
-            D[i][j] = 0.0;
-            I[i][j] = (i == j && j < m) ? 1.0 : 0.0;
-        }
+    for (int e = j; e < BS * BS; e += kWave) L[e / BS][e % BS] = 0.0;
     __syncthreads();
     if (j < m)  // lane j loads row j of the block
         for (int k = rp[r0 + j]; k < rp[r0 + j + 1]; ++k) {
             const int64_t c = (int64_t)col[k] - r0;
-            if (c >= 0 && c < m) D[j][c] = val[k];
+            if (c >= 0 && c < m) L[j][c] = val[k];
         }
     __syncthreads();
-    auto norm1 = [&](double (*M)[BS]) {
+    double D[BS], I[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        D[i] = j < BS ? L[i][j] : 0.0;
+        I[i] = (i == j && j < m) ? 1.0 : 0.0;
+    }
+    auto norm1 = [&](const double (&M)[BS]) {
         double s = 0.0;
-        if (j < m)
-            for (int i = 0; i < m; ++i) s += fabs(M[i][j]);
+        if (j < m) {
+#pragma unroll
+            for (int i = 0; i < BS; ++i)
+                if (i < m) s += fabs(M[i]);
+        }
         return wave_max(s);
     };
     const double nD = norm1(D);
-    for (int c = 0; c < m; ++c) {
-        const double v = (j >= c && j < m) ? fabs(D[j][c]) : -1.0;
-        const double mx = wave_max(v);
+    bool singular = false;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < BS; ++c) {
+        if (singular || c >= m) continue;
+        // pivot: the first row i >= c of largest |D[i][c]|, found by lane c
+        double best = -1.0;
+        int pv = c;
+#pragma clang loop unroll(full)
+        for (int i = c; i < BS; ++i)
+            if (i < m) {
+                const double a = fabs(D[i]);
+                if (a > best) {
+                    best = a;
+                    pv = i;
+                }
+            }
+        const double mx = lane_value(best, c);
+        const int piv = __builtin_amdgcn_readlane(pv, c);
         if (!(mx > 0.0)) {  // singular block (zero column below the diagonal)
-            if (j == 0) atomicMin(bad, (int)(b < INT_MAX ? b : INT_MAX));
-            return;
+            singular = true;
+            continue;
         }
-        const unsigned long long hit = __ballot(v == mx);
-        const int piv = __ffsll((long long)hit) - 1;
         if (piv != c && j < m) {
-            double t = D[c][j];
-            D[c][j] = D[piv][j];
-            D[piv][j] = t;
-            t = I[c][j];
-            I[c][j] = I[piv][j];
-            I[piv][j] = t;
+            const double dc = D[c], ic = I[c];
+#pragma clang loop unroll(full)
+            for (int i = c + 1; i < BS; ++i)
+                if (i == piv) {
+                    D[c] = D[i];
+                    I[c] = I[i];
+                    D[i] = dc;
+                    I[i] = ic;
+                }
         }
-        __syncthreads();
-        const double d = D[c][c];
-        __syncthreads();
-        if (j < m) {
-            D[c][j] = D[c][j] / d;
-            I[c][j] = I[c][j] / d;
+        const double d = lane_value(D[c], c);
+        if (j < m) {  // columns beyond a short last block stay zero
+            D[c] = D[c] / d;
+            I[c] = I[c] / d;
         }
-        __syncthreads();
-        for (int r = 0; r < m; ++r) {
-            if (r == c) continue;
-            const double f = D[r][c];
-            __syncthreads();
+#pragma clang loop unroll(full)
+        for (int r = 0; r < BS; ++r) {
+            if (r == c || r >= m) continue;
+            const double f = lane_value(D[r], c);
             if (f == 0.0) continue;
             if (j < m) {
-                const double pd = f * D[c][j];
-                const double pi = f * I[c][j];
-                D[r][j] = D[r][j] - pd;
-                I[r][j] = I[r][j] - pi;
+                const double pd = f * D[c];
+                const double pi = f * I[c];
+                D[r] = D[r] - pd;
+                I[r] = I[r] - pi;
             }
-            __syncthreads();
         }
+    }
+    if (singular) {
+        if (j == 0) atomicMin(bad, (int)(b < INT_MAX ? b : INT_MAX));
+        return;
     }
     const double nI = norm1(I);
     const double kappa = nD * nI;
     int p = BJ_P64;
     if (adaptive) {
         double lo = __builtin_inf(), hi = 0.0;
-        if (j < m)
-            for (int i = 0; i < m; ++i) {
-                const double a = fabs(I[i][j]);
+        if (j < m) {
+#pragma unroll
+            for (int i = 0; i < BS; ++i) {
+                if (i >= m) continue;
+                const double a = fabs(I[i]);
                 if (a == 0.0) continue;
                 lo = a < lo ? a : lo;
                 hi = a > hi ? a : hi;
             }
+        }
         lo = -wave_max(-lo);
         hi = wave_max(hi);
         if (hi == 0.0) lo = hi = 1.0;
@@ -134,13 +169,15 @@ __global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__res
         else if (kappa * ldexp(1.0, -24) <= accuracy && lo >= ldexp(1.0, -126) && hi <= 3.4028234663852886e38)
             p = BJ_P32;
     }
-    if (j < BS)
+    if (j < BS) {
+#pragma unroll
         for (int i = 0; i < BS; ++i) {
-            double x = I[i][j];
+            double x = I[i];
             if (p == BJ_P32) x = (double)(float)x;
             else if (p == BJ_P16) x = round_f16(x);
             inv[(b * BS + i) * BS + j] = x;
         }
+    }
     if (j == 0) {
         cond[b] = kappa;
         prec[b] = p;
