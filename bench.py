@@ -85,6 +85,11 @@ def cpu_baseline(A, x, b, sel_fmt):
                       f"(CSR) on the 128^3 27-point system, {dt:.2f} s on the host"}
 
 
+def mxl_catalog(name):
+    from paper_2006_16852_amd.selector import CATALOG
+    return CATALOG[name]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +208,45 @@ def main():
     base.apply(x, r, -1.0, 1.0)
     true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(bd))
 
+    # Outside the timed step: the metric's comparisons on the same system.
+    # Mixed precision: FP32-inner / FP64-outer refinement on the same operator.
+    # Learned: the trained selector's choice against the exhaustive timing.
+    log("[bench] comparisons: mixed-precision refinement and the learned selector")
+    comp = {"fp64_cg_ms": None}
+    ir_runs = {}
+    for tin in (1e-2, 1e-3):
+        I = mxl.ir(M, outer=dict(max_iters=60, reduction=1e-10),
+                   inner=dict(reduction=tin, max_iters=10_000, check_every=16))
+        ts = []
+        for _ in range(3):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            iinfo = I.solve(bd, x)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        rr = bd.clone()
+        base.apply(x, rr, -1.0, 1.0)
+        ir_runs[f"inner{tin:g}"] = {"ms": round(float(np.median(ts)) * 1e3, 3), "corrections": iinfo["iterations"],
+                                    "inner_iterations": iinfo["inner_iterations"],
+                                    "true_rel_residual": float(torch.linalg.norm(rr) / torch.linalg.norm(bd))}
+        del I
+    comp["mixed_ir"] = ir_runs
+    from paper_2006_16852_amd.selector import Selector
+    learned = Selector.load()
+    k_model, _ = learned.choose(ctx, base, xd, yd, fallback=False)
+    k_fb, _ = learned.choose(ctx, base, xd, yd, fallback=True)
+    pick = {"model": learned.classes[k_model], "model_with_fallback": learned.classes[k_fb]}
+    t_pick = {}
+    for name in set(pick.values()):
+        fmt, kw = mxl_catalog(name)
+        op = base.convert(fmt, **kw)
+        t_pick[name] = op.time_apply(xd, yd, reps=20)
+        del op
+    best_t = min(t_sel.values())
+    comp["learned_selector"] = {"choice": pick, "exhaustive_choice": sel,
+                                "regret": {k: round(t_pick[v] / best_t - 1.0, 4) for k, v in pick.items()}}
+
     spmv_detail = {}
     step_bytes = 0
     for k in spmv_set:
@@ -219,6 +263,9 @@ def main():
     cg_bytes = float(np.mean(its)) * cg_iter_bytes + cg_setup_bytes
     step_bytes += cg_bytes
     cg_ms = float(np.median([i["seconds"] for i in infos])) * 1e3
+    comp["fp64_cg_ms"] = round(cg_ms, 3)
+    best_ir = min(v["ms"] for v in comp["mixed_ir"].values())
+    comp["ir_speedup_vs_fp64"] = round(cg_ms / best_ir, 3)
     launch_ms = sum(i["spmv_ms"] for i in infos) / max(1, sum(i["spmv_timed"] for i in infos))
     achieved = cg_spmv / (launch_ms * 1e-3) / 1e9
 
@@ -257,6 +304,7 @@ def main():
         "spmv": spmv_detail,
         "selection_ms": {k: round(v, 4) for k, v in t_sel.items()},
         "setup_ms": t_setup,
+        "comparisons": comp,
     }
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline (bounded sample)")
