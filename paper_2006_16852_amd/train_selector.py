@@ -10,9 +10,13 @@ the selector with its timing fallback, the best single fixed class and a
 hand rule, plus their performance profiles.
 
     python -m paper_2006_16852_amd.train_selector --out DIR [--count 200] [--scale 1.0]
+        [--timings FILE] [--structured | --structured-timings FILE]
 
 Writes DIR/selector_timings.json (features + times), DIR/selector_eval.json
-and DIR/selector_weights.json.
+and DIR/selector_weights.json.  With --structured the regular stencil suite
+(2D 5-point, 3D 27-point, anisotropic 7-point, convection-diffusion at
+several sizes) joins the training set except its held-out matrices, which
+are reported separately.
 """
 from __future__ import annotations
 
@@ -74,6 +78,31 @@ def collect(ctx, idx, scale, reps, log, classes=S.CLASSES):
     return np.array(feats), np.array(times), meta
 
 
+def collect_structured(ctx, reps, log, classes=S.CLASSES):
+    """Features and class times of the regular stencil suite
+    (workloads.structured_suite); returns F, T, names, held_out flags."""
+    feats, times, names, held = [], [], [], []
+    dev = f"cuda:{ctx.device}"
+    for name, build, ho in W.structured_suite():
+        t0 = time.time()
+        A = build()
+        base = mxl.csr(ctx, torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                       torch.from_numpy(A.val).to(dev))
+        x = torch.from_numpy(W.uniform_vec(A.ncols, 2)).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        f = base.features()
+        ws = A.nnz * 12 + A.nrows * 20
+        t = S.time_classes(base, x, y, reps=reps, flush=ws < (512 << 20), classes=classes)
+        feats.append(f)
+        times.append(t)
+        names.append(name)
+        held.append(bool(ho))
+        log(f"[collect] {name} n={A.nrows} nnz={A.nnz} best={classes[int(np.argmin(t))]} {time.time() - t0:.1f}s")
+        del base, x, y, A
+        torch.cuda.empty_cache()
+    return np.array(feats), np.array(times), names, np.array(held)
+
+
 def evaluate(ctx, sel, F, T, fallback_times=None):
     pred = np.array([int(np.argmin(np.where(sel.feasible(f), s, np.inf)))
                      for f, s in zip(F, sel.scores(ctx, F))])
@@ -111,6 +140,9 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--lam", type=float, default=1e-3)
     ap.add_argument("--timings", default=None, help="reuse a timings file instead of measuring")
+    ap.add_argument("--structured", action="store_true",
+                    help="add the regular stencil suite (its non-held-out part) to the training set")
+    ap.add_argument("--structured-timings", default=None, help="reuse a structured-suite timings file")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
 
@@ -134,8 +166,25 @@ def main():
     perm = np.random.default_rng(7).permutation(n)
     ntest = max(1, n // 4)
     test, train_idx = np.sort(perm[:ntest]), np.sort(perm[ntest:])
+    Fs = Ts = None
+    if args.structured or args.structured_timings:
+        if args.structured_timings:
+            d = json.load(open(args.structured_timings))
+            assert list(d["classes"]) == classes
+            Fs, Ts = np.array(d["features"]), np.array(d["times_ms"], dtype=float)
+            Ts = np.where(Ts < 0, np.inf, Ts)
+            snames, sheld = d["names"], np.array(d["held_out"], bool)
+        else:
+            Fs, Ts, snames, sheld = collect_structured(ctx, args.reps, log, classes)
+            json.dump(dict(classes=classes, features=Fs.tolist(), times_ms=np.where(np.isfinite(Ts), Ts, -1.0).tolist(),
+                           names=snames, held_out=sheld.tolist(), reps=args.reps),
+                      open(os.path.join(args.out, "selector_structured_timings.json"), "w"))
+    Ftrain, Ttrain = F[train_idx], T[train_idx]
+    if Fs is not None:
+        Ftrain = np.concatenate([Ftrain, Fs[~sheld]])
+        Ttrain = np.concatenate([Ttrain, Ts[~sheld]])
     t0 = time.time()
-    sel = S.train(ctx, F[train_idx], T[train_idx], classes, epochs=args.epochs, lr=args.lr, lam=args.lam)
+    sel = S.train(ctx, Ftrain, Ttrain, classes, epochs=args.epochs, lr=args.lr, lam=args.lam)
     train_s = time.time() - t0
     sel.save(os.path.join(args.out, "selector_weights.json"))
     Ft, Tt = F[test], T[test]
@@ -185,6 +234,22 @@ def main():
               classes=classes,
               class_wins={c: int(np.sum(np.argmin(T, axis=1) == k)) for k, c in enumerate(classes)})
     ev["suite_bandwidth"] = suite_bandwidth(T, meta, test, choice_net, classes)
+    if Fs is not None:
+        sc = sel.scores(ctx, Fs)
+        rows = {}
+        for k, (f, s_, t) in enumerate(zip(Fs, sc, Ts)):
+            s_ = np.where(sel.feasible(f), s_, np.inf)
+            order = np.argsort(s_)
+            z = np.abs(sel.standardise(f))
+            unsure = (s_[order[1]] - s_[order[0]] < sel.delta) or bool(np.any(z > sel.zmax))
+            top = [j for j in order[:3] if np.isfinite(s_[j])]
+            fbk = int(top[int(np.argmin(t[top]))]) if unsure else int(order[0])
+            rows[snames[k]] = dict(held_out=bool(sheld[k]), best=classes[int(np.argmin(t))],
+                                   network=classes[int(order[0])], network_regret=float(t[order[0]] / t.min() - 1.0),
+                                   fallback_used=bool(unsure), with_fallback=classes[fbk],
+                                   with_fallback_regret=float(t[fbk] / t.min() - 1.0))
+        ev["structured"] = dict(n_train=int((~sheld).sum()), n_held_out=int(sheld.sum()), matrices=rows)
+        ev["n_train"] = int(len(Ftrain))
     json.dump(ev, open(os.path.join(args.out, "selector_eval.json"), "w"), indent=1)
     log(json.dumps(ev["regret"]))
 

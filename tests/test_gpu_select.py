@@ -136,6 +136,28 @@ def test_trained_selector_gain(mxl, ctx):
     assert S.regret(Tt, np.array(fb)).mean() <= S.regret(Tt, np.full(len(test), fixed)).mean()
 
 
+def test_structured_held_out_choices(ctx):
+    """The regular stencil systems kept out of training (including the
+    128^3 27-point and 160^3 anisotropic benchmark systems): from the stored
+    timings of that suite, the shipped network's choice (forward pass on the
+    GPU) is within 5 % of the fastest class on every one."""
+    import json
+    import os
+    from paper_2006_16852_amd import selector as S
+    d = json.load(open(os.path.join(os.path.dirname(S.__file__), "data", "selector_timings_structured.json")))
+    sel = S.Selector.load()
+    assert list(d["classes"]) == sel.classes
+    F = np.array(d["features"])
+    T = np.array(d["times_ms"], dtype=float)
+    T[T < 0] = np.inf
+    held = np.array(d["held_out"], bool)
+    assert held.sum() >= 4 and "stencil3d27_128" in [n for n, h in zip(d["names"], held) if h]
+    P = np.where([sel.feasible(f) for f in F[held]], sel.scores(ctx, F[held]), np.inf)
+    r = S.regret(T[held], P.argmin(axis=1))
+    print(f"[selector structured held-out] regret {r}", flush=True)
+    assert np.all(r <= 0.05)
+
+
 # --------------------------------------------------------------- mxl_select
 SEL_MATS = ([W.zipf_suite_matrix(m, scale_n=0.02) for m in (1, 8, 40, 77, 150)]
             + [W.stencil_3d27(16), W.aniso_3d7(12), W.edge_matrices()[3], W.edge_matrices()[0]])

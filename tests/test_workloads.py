@@ -26,3 +26,12 @@ def test_stencil_grid_ragged_counts():
     A = W.stencil_grid(nx, ny, nz, pts, cf)
     want = sum((nx - abs(di)) * (ny - abs(dj)) * (nz - abs(dk)) for di, dj, dk in pts)
     assert A.nnz == want and A.nrows == nx * ny * nz
+
+
+def test_structured_suite_holds_out_the_benchmark_systems():
+    suite = W.structured_suite()
+    names = [s[0] for s in suite]
+    assert len(names) == len(set(names))
+    held = {s[0] for s in suite if s[2]}
+    assert {"stencil3d27_128", "aniso3d7_160"} <= held
+    assert all(not s[2] for s in suite if s[0] not in held)

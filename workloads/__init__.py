@@ -307,6 +307,29 @@ def zipf_suite_matrix(m: int, scale_n: float = 1.0) -> Csr:
     return Csr(n, n, row_ptr.astype(np.int32), cc, val, f"zipf_{m}")
 
 
+# ------------------------------------------------------- structured suite
+def structured_suite() -> list:
+    """Regular stencil matrices for the selector's training set, as
+    (name, builder, held_out): 2D 5-point, 3D 27-point, anisotropic 3D
+    7-point and 3D convection-diffusion at several sizes.  The held-out ones
+    (including the 128^3 27-point and 160^3 anisotropic benchmark systems)
+    are never trained on."""
+    out = []
+    for N in (256, 724, 1448):
+        out.append((f"stencil2d5_{N}", lambda N=N: stencil_2d5(N), False))
+    out.append(("stencil2d5_1024", lambda: stencil_2d5(1024), True))
+    for N in (48, 80, 112, 144):
+        out.append((f"stencil3d27_{N}", lambda N=N: stencil_3d27(N), False))
+    out.append(("stencil3d27_128", lambda: stencil_3d27(128), True))
+    for N in (64, 100, 140):
+        out.append((f"aniso3d7_{N}", lambda N=N: aniso_3d7(N), False))
+    out.append(("aniso3d7_160", lambda: aniso_3d7(160), True))
+    for N in (64, 100, 150):
+        out.append((f"convdiff3d7_{N}", lambda N=N: convdiff_3d7(N), False))
+    out.append(("convdiff3d7_128", lambda: convdiff_3d7(128), True))
+    return out
+
+
 # ------------------------------------------------------------ batched systems
 @dataclass
 class Batch:
