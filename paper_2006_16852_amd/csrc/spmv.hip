@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                                              const V *__restrict__ evals,
                                              const int2 *__restrict__ win, SpmvK<V> p) {
     if (p.stop && *p.stop) return;
-    constexpr int U = 8 / R;
+    constexpr int U = (sizeof(V) == 4 ? 16 : 8) / R;  // slots of loads in flight per batch
     typedef typename std::conditional<D16, short, int>::type IT;
     typedef typename IdxVec<IT, R>::T IV;
     const IT *__restrict__ ecol = (const IT *)ecol_;
