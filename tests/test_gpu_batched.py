@@ -108,6 +108,27 @@ def _batch_from(systems, rhs_seed=3):
                    np.concatenate(vals), b)
 
 
+def test_batch_tiny_systems_ell_equals_csr(mxl, ctx):
+    """Systems of one and two rows, a diagonal system and a dense 5x5 one:
+    the ELL kernel (padding slots included) equals the CSR kernel bit for
+    bit and the oracle's counts."""
+    one = W.Csr(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0]), "one")
+    two = W.Csr(2, 2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32),
+                np.array([4.0, 1.0, 1.0, 3.0]), "two")
+    diag = W.Csr(7, 7, np.arange(8, dtype=np.int32), np.arange(7, dtype=np.int32), np.linspace(1, 2, 7), "diag")
+    D = np.full((5, 5), 0.5) + np.eye(5) * 4.0
+    r, c = np.nonzero(D)
+    dense = W.Csr(5, 5, np.arange(0, 26, 5, dtype=np.int32), c.astype(np.int32), D[r, c], "dense5")
+    Bb = _batch_from([one, two, W.stencil_2d5(5), diag, dense, one])
+    ref = O.batch_pcg(Bb, reduction=1e-10)
+    for wg in (64, 256):
+        _, x1, it1, _, s1 = _run(mxl, ctx, Bb, (wg, 2, 0, 1))
+        _, x2, it2, _, s2 = _run(mxl, ctx, Bb, (wg, 2, 0, 2))
+        assert np.all(s1 == 1) and np.array_equal(it1, it2) and np.array_equal(x1, x2)
+        assert np.all(np.abs(it1 - ref["iterations"]) <= 2)
+    _check_residuals(Bb, x1)
+
+
 def test_batch_skewed_rows_keep_csr(mxl, ctx):
     """One dense row in a system makes the padded copy too large: the batch
     has no ELL copy, format 2 is refused and format 0 runs the CSR kernel."""

@@ -171,6 +171,24 @@ def test_ir_block_inner_matches_oracle(mxl, ctx, bs, acc):
     assert res <= 1e-12
 
 
+@pytest.mark.parametrize("N,bs", [(9, 32), (7, 8), (11, 16)])
+def test_ir_block_short_last_block(mxl, ctx, N, bs):
+    """n not a multiple of the block size: the last diagonal block is short."""
+    A = W.aniso_3d7(N)
+    assert A.nrows % bs != 0
+    b = W.uniform_vec(A.nrows, 9)
+    ref = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4, block_size=bs, block_accuracy=0.1)
+    M = matrix(mxl, ctx, A)
+    S = mxl.ir(M, outer=dict(max_iters=50, reduction=1e-12), inner=dict(reduction=1e-4, max_iters=10_000),
+               block_size=bs, block_accuracy=0.1)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    assert ref["stop_reason"] == O.CONVERGED and info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["outer"]) <= 1
+    assert abs(info["inner_iterations"] - ref["inner_iterations"]) <= max(4, 0.05 * ref["inner_iterations"])
+    assert np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) <= 1e-12 * np.linalg.norm(b)
+
+
 def test_ir_block_full_size(mxl, ctx):
     """160^3 anisotropic system: refinement to 1e-10 with 32-row adaptive
     block Jacobi in the FP32 inner CG; the FP64 residual recomputed."""
