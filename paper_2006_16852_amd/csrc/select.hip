@@ -44,12 +44,25 @@ __device__ __forceinline__ int wave_min_i(int v) {
     return v;
 }
 
-// Row statistics: thread per row (grid-stride); wave partials combined with
-// 64-bit integer atomics (exact, so the order does not matter).
+// Row statistics: thread per row (grid-stride).  Row lengths below
+// kHistBins are counted in a per-workgroup LDS histogram that is added to
+// the global one bin by bin at the end (rows of equal length would
+// otherwise serialise on one global counter); the sums, minima and maxima
+// are reduced over the workgroup and combined with one integer atomic each
+// (exact, so the order does not matter).
+constexpr int kHistBins = 4096;
+
 __global__ __launch_bounds__(kWG) void k_features(int64_t n, int64_t nnz, const int *__restrict__ rp,
                                                   const int *__restrict__ col,
                                                   FeatAcc *__restrict__ acc,
-                                                  unsigned *__restrict__ hist) {
+                                                  unsigned *__restrict__ hist, int maxlen_all) {
+    constexpr int NW = kWG / kWave;
+    __shared__ unsigned sh[kHistBins];
+    __shared__ unsigned long long s_u[5][NW];
+    __shared__ int s_i[3][NW];
+    const int nbins = maxlen_all + 1 < kHistBins ? maxlen_all + 1 : kHistBins;
+    for (int j = threadIdx.x; j < nbins; j += kWG) sh[j] = 0u;
+    __syncthreads();
     unsigned long long s2 = 0, s3 = 0, above = 0, sumbw = 0, near = 0;
     int maxlen = 0, minlen = INT_MAX, maxbw = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -61,7 +74,8 @@ __global__ __launch_bounds__(kWG) void k_features(int64_t n, int64_t nnz, const 
         if ((int64_t)len * n > 2 * nnz) ++above;
         maxlen = max(maxlen, (int)len);
         minlen = min(minlen, (int)len);
-        atomicAdd(hist + len, 1u);
+        if (len < (unsigned long long)kHistBins) atomicAdd(&sh[len], 1u);
+        else atomicAdd(hist + len, 1u);
         for (int e = a; e < b; ++e) {
             long long d = (long long)col[e] - i;
             d = d < 0 ? -d : d;
@@ -78,7 +92,29 @@ __global__ __launch_bounds__(kWG) void k_features(int64_t n, int64_t nnz, const 
     maxlen = wave_max_i(maxlen);
     minlen = wave_min_i(minlen);
     maxbw = wave_max_i(maxbw);
+    const int w = threadIdx.x / kWave;
     if (threadIdx.x % kWave == 0) {
+        s_u[0][w] = s2;
+        s_u[1][w] = s3;
+        s_u[2][w] = above;
+        s_u[3][w] = sumbw;
+        s_u[4][w] = near;
+        s_i[0][w] = maxlen;
+        s_i[1][w] = minlen;
+        s_i[2][w] = maxbw;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < NW; ++v) {
+            s2 += s_u[0][v];
+            s3 += s_u[1][v];
+            above += s_u[2][v];
+            sumbw += s_u[3][v];
+            near += s_u[4][v];
+            maxlen = max(maxlen, s_i[0][v]);
+            minlen = min(minlen, s_i[1][v]);
+            maxbw = max(maxbw, s_i[2][v]);
+        }
         atomicAdd(&acc->s2, s2);
         atomicAdd(&acc->s3, s3);
         atomicAdd(&acc->above, above);
@@ -88,6 +124,8 @@ __global__ __launch_bounds__(kWG) void k_features(int64_t n, int64_t nnz, const 
         atomicMin(&acc->minlen, minlen);
         atomicMax(&acc->maxbw, maxbw);
     }
+    for (int j = threadIdx.x; j < nbins; j += kWG)
+        if (sh[j]) atomicAdd(hist + j, sh[j]);
 }
 
 __global__ void k_row_maxlen(int64_t n, const int *__restrict__ rp, int *__restrict__ out) {
@@ -251,8 +289,9 @@ mxl_status features_compute(const MatrixImpl &A, double out[16], std::vector<uns
         cleanup();
         return set_error(MXL_ERR_OUT_OF_MEMORY, "features histogram");
     }
-    hipLaunchKernelGGL(k_features, dim3(G), dim3(256), 0, s, n, nnz, (const int *)A.row_ptr->p,
-                       (const int *)A.col->p, (FeatAcc *)dacc, (unsigned *)dhist);
+    const unsigned Gf = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_features, dim3(Gf), dim3(kWG), 0, s, n, nnz, (const int *)A.row_ptr->p,
+                       (const int *)A.col->p, (FeatAcc *)dacc, (unsigned *)dhist, maxlen);
     FeatAcc h;
     std::vector<unsigned> hist((size_t)maxlen + 1);
     if (hipMemcpyAsync(&h, dacc, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
