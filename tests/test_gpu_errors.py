@@ -134,3 +134,52 @@ def test_handles_freed_in_any_order(mxl):
     y = torch.empty(64, dtype=torch.float64, device=DEV)
     B.apply(torch.ones(64, dtype=torch.float64, device=DEV), y)
     assert float(y.sum()) == float(W.stencil_2d5(8).val.sum())
+
+
+def test_repeated_create_solve_destroy_releases_memory(mxl, ctx):
+    """Every kind of operator created, used and dropped many times (GMRES
+    with its captured graphs, CG, BiCGSTAB, refinement with point and block
+    Jacobi, block Jacobi, ParILU, a batch with its ELL copy, a selector's
+    features): the device's free memory comes back."""
+    import gc
+    A = W.convdiff_2d5(48)
+    S2 = W.stencil_2d5(48)
+    Bt = W.batch_systems(nsys=40, seed=3)
+    b = dev(W.uniform_vec(A.nrows, 1))
+
+    def cycle():
+        M = matrix(mxl, ctx, A).convert("ell", variant=mxl.ELL_DELTA16)
+        Ms = matrix(mxl, ctx, S2)
+        x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+        for kind, P in (("gmres", mxl.jacobi(M)), ("bicgstab", mxl.jacobi(M)),
+                        ("gmres", mxl.ilu(matrix(mxl, ctx, A), sweeps=2, trisolve="jacobi", trs_sweeps=2))):
+            S = mxl.solver(kind, M, P, max_iters=200, reduction=1e-8, check_every=8)
+            x.zero_()
+            S.solve(b, x)
+        for P in (mxl.jacobi(Ms), mxl.bjacobi(Ms, 8, True)):
+            x.zero_()
+            mxl.solver("cg", Ms, P, max_iters=200, reduction=1e-8).solve(b, x)
+        for bs in (0, 8):
+            x.zero_()
+            mxl.ir(Ms, block_size=bs).solve(b, x)
+        Ms.features()
+        op = mxl.batch(ctx, Bt.sys_ptr, dev(Bt.sys_ptr), dev(Bt.row_ptr), dev(Bt.col), dev(Bt.val))
+        bb = dev(Bt.b)
+        xb = torch.zeros_like(bb)
+        it = torch.zeros(Bt.nsys, dtype=torch.int32, device=DEV)
+        rel = torch.zeros(Bt.nsys, dtype=torch.float64, device=DEV)
+        st = torch.zeros(Bt.nsys, dtype=torch.uint8, device=DEV)
+        op.solve(bb, xb, it, rel, st, reduction=1e-10)
+        torch.cuda.synchronize()
+
+    cycle()
+    gc.collect()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(25):
+        cycle()
+    gc.collect()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    print(f"[leak] free before {free0 / 2**20:.1f} MiB after {free1 / 2**20:.1f} MiB", flush=True)
+    assert free0 - free1 < 32 * 2**20
