@@ -188,7 +188,7 @@ def main():
             if record:
                 evs[k].append((e0, e1))
         x.zero_()
-        info = S.solve(bd, x, time_spmv=True)
+        info = S.solve(bd, x, time_spmv=16)  # events on every 16th product
         if record:
             infos.append(info)
 

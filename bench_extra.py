@@ -537,7 +537,7 @@ def stencil_mf(args):
 
         def f():
             x.zero_()
-            return S.solve(b, x, time_spmv=True)
+            return S.solve(b, x, time_spmv=16)
         dt, info = _timed(f, args.steps, args.warmup)
         r = b.clone()
         op.apply(x, r, -1.0, 1.0)

@@ -131,8 +131,9 @@ typedef struct {
     double *history;        /* in: host buffer or NULL */
     int64_t history_cap;    /* in */
     int64_t inner_iterations; /* iterative refinement: total inner iterations */
-    int32_t time_spmv;      /* in: nonzero = time every SpMV launch of the
-                               Krylov loop with HIP events (first 4096) */
+    int32_t time_spmv;      /* in: k > 0 = time every k-th SpMV launch of
+                               the CG loop with HIP events (first 4096
+                               samples); 0 = no events */
     double  spmv_ms;        /* out: summed SpMV time of the timed launches */
     int64_t spmv_timed;     /* out: number of timed launches */
     int64_t restarts;       /* out, GMRES: restarted cycles */

@@ -421,8 +421,9 @@ def criteria(max_iters=10_000, reduction=1e-10, time_limit=0.0, check_every=1,
 
 class Solver(Op):
     def solve(self, b: torch.Tensor, x: torch.Tensor, history: int = 0,
-              time_spmv: bool = False) -> dict:
-        """Solve A x = b in place (x = initial guess on entry)."""
+              time_spmv: int = 0) -> dict:
+        """Solve A x = b in place (x = initial guess on entry).  time_spmv = k > 0
+        times every k-th SpMV launch of the CG loop with HIP events (True = 1)."""
         _need_cuda(b, x)
         info = SolveInfo()
         info.time_spmv = int(time_spmv)
