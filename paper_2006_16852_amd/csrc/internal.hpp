@@ -171,6 +171,16 @@ struct SolverImpl {
     // GMRES step chunks captured as graphs, keyed by (first step, count);
     // their kernels take only solver-owned pointers and the step index
     std::map<int64_t, std::shared_ptr<GraphHold>> graphs;
+    // HIP events of the sampled SpMV timing, kept across solves so that a
+    // timed solve creates none
+    std::vector<hipEvent_t> spmv_events;
+    SolverImpl() = default;
+    SolverImpl(const SolverImpl &) = delete;
+    SolverImpl &operator=(const SolverImpl &) = delete;
+    ~SolverImpl() {
+        for (hipEvent_t e : spmv_events)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 struct IrImpl {

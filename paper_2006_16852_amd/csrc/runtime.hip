@@ -803,23 +803,23 @@ namespace {
 // loop (events recorded on the solver's stream around each launch).
 // HIP events around every `every`-th SpMV launch of a Krylov loop (the
 // first kCap samples): each recorded event is a packet in the stream, so
-// timing every launch would itself slow the loop it measures.
+// timing every launch would itself slow the loop it measures.  The events
+// belong to the solver and are reused by later solves.
 struct EventTimer {
     static constexpr int64_t kCap = 4096;
     bool on;
     int64_t every;
     hipStream_t s;
-    std::vector<hipEvent_t> ev;
-    EventTimer(int32_t period, hipStream_t st) : on(period > 0), every(period > 0 ? period : 1), s(st) {}
+    std::vector<hipEvent_t> &ev;
+    EventTimer(int32_t period, hipStream_t st, std::vector<hipEvent_t> &events)
+        : on(period > 0), every(period > 0 ? period : 1), s(st), ev(events) {}
     bool sampled(int64_t k) const { return on && k % every == 0 && k / every <= kCap; }
     void begin(int64_t k) {
         if (!sampled(k)) return;
         const int64_t j = k / every;
-        if ((int64_t)ev.size() < 2 * j) {
-            ev.resize(2 * j, nullptr);
-            (void)hipEventCreate(&ev[2 * j - 2]);
-            (void)hipEventCreate(&ev[2 * j - 1]);
-        }
+        if ((int64_t)ev.size() < 2 * j) ev.resize(2 * j, nullptr);
+        if (!ev[2 * j - 2]) (void)hipEventCreate(&ev[2 * j - 2]);
+        if (!ev[2 * j - 1]) (void)hipEventCreate(&ev[2 * j - 1]);
         (void)hipEventRecord(ev[2 * j - 2], s);
     }
     void end(int64_t k) {
@@ -830,17 +830,13 @@ struct EventTimer {
         *ms = 0.0;
         *count = 0;
         (void)hipStreamSynchronize(s);
-        for (int64_t j = 1; j * every <= iters && 2 * j <= (int64_t)ev.size(); ++j) {
+        for (int64_t j = 1; j * every <= iters && j <= kCap && 2 * j <= (int64_t)ev.size(); ++j) {
             float t = 0.f;
-            if (ev[2 * j - 2] && hipEventElapsedTime(&t, ev[2 * j - 2], ev[2 * j - 1]) == hipSuccess) {
+            if (ev[2 * j - 2] && ev[2 * j - 1] && hipEventElapsedTime(&t, ev[2 * j - 2], ev[2 * j - 1]) == hipSuccess) {
                 *ms += t;
                 ++*count;
             }
         }
-    }
-    ~EventTimer() {
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -969,7 +965,7 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     int64_t k = 0;
     int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
     int64_t iters = 0;
-    EventTimer timer(info ? info->time_spmv : 0, s);
+    EventTimer timer(info ? info->time_spmv : 0, s, const_cast<SolverImpl &>(S).spmv_events);
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         ++k;
         timer.begin(k);
