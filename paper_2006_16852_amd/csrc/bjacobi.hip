@@ -46,7 +46,8 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One wave inverts one diagonal block.  Lane j holds column j of D and of
+// One wave inverts one diagonal block (the 32-row shape, whose two
+// register columns per lane leave no room for a second block).  Lane j holds column j of D and of
 // its inverse I in registers (the block is staged through LDS once, row by
 // row, to turn rows into columns); the pivot column's entries reach every
 // lane as uniform scalars, so an elimination step is register arithmetic
@@ -56,7 +57,7 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // the inverse, its condition number and the precision decision are
 // reproducible.
 template <int BS>
-__global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__restrict__ rp,
+__global__ __launch_bounds__(kWave) void k_bj_invert1(int64_t n, const int *__restrict__ rp,
                                                      const int *__restrict__ col,
                                                      const double *__restrict__ val, int adaptive,
                                                      double accuracy, double *__restrict__ inv,
@@ -181,6 +182,161 @@ __global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__res
     if (j == 0) {
         cond[b] = kappa;
         prec[b] = p;
+    }
+}
+
+// Maximum over the BS lanes of a lane group (BS a power of two dividing
+// the wave), with wave_max's comparison.
+template <int BS, typename T>
+__device__ __forceinline__ T group_max(T v) {
+#pragma unroll
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// One wave inverts 64/BS diagonal blocks, one per group of BS lanes: lane
+// j of a group holds column j of its block D and of the inverse I in
+// registers (the blocks are staged through LDS once, row by row, to turn
+// rows into columns; the loops over pivots and rows are unrolled).  Lane c
+// of a group finds the pivot of column c and every entry of that column
+// reaches the group's lanes by a lane shuffle, so an elimination step is
+// register arithmetic with no barrier; a step that is zero in every block
+// of the wave is skipped as a whole.  Every element sees the same
+// operations in the same order as a sequential Gauss-Jordan elimination
+// with partial pivoting (first row of largest magnitude), with no
+// multiply-add contraction, so the inverse, its condition number and the
+// precision decision are reproducible.
+template <int BS>
+__global__ __launch_bounds__(kWave) void k_bj_invert(int64_t n, const int *__restrict__ rp,
+                                                     const int *__restrict__ col,
+                                                     const double *__restrict__ val, int adaptive,
+                                                     double accuracy, double *__restrict__ inv,
+                                                     double *__restrict__ cond, int *__restrict__ prec,
+                                                     int *__restrict__ bad) {
+#pragma clang fp contract(off)
+    constexpr int P = kWave / BS;
+    __shared__ double L[P][BS][BS + 1];
+    const int lane = threadIdx.x, q = lane / BS, j = lane % BS;
+    const int src0 = q * BS;  // first lane of this lane's group
+    const int64_t nb = (n + BS - 1) / BS;
+    const int64_t b = (int64_t)blockIdx.x * P + q;
+    const bool live = b < nb;
+    const int64_t r0 = b * BS;
+    const int m = live ? (int)(n - r0 < BS ? n - r0 : BS) : 0;
+    for (int e = lane; e < P * BS * BS; e += kWave) L[e / (BS * BS)][(e / BS) % BS][e % BS] = 0.0;
+    __syncthreads();
+    if (j < m)  // lane j loads row j of its block
+        for (int k = rp[r0 + j]; k < rp[r0 + j + 1]; ++k) {
+            const int64_t c = (int64_t)col[k] - r0;
+            if (c >= 0 && c < m) L[q][j][c] = val[k];
+        }
+    __syncthreads();
+    double D[BS], I[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        D[i] = L[q][i][j];
+        I[i] = (i == j && j < m) ? 1.0 : 0.0;
+    }
+    auto norm1 = [&](const double (&M)[BS]) {
+        double s = 0.0;
+        if (j < m) {
+#pragma unroll
+            for (int i = 0; i < BS; ++i)
+                if (i < m) s += fabs(M[i]);
+        }
+        return group_max<BS>(s);
+    };
+    const double nD = norm1(D);
+    bool singular = false;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < BS; ++c) {
+        // pivot: the first row i >= c of largest |D[i][c]|, found by lane c of the group
+        double best = -1.0;
+        int pv = c;
+#pragma clang loop unroll(full)
+        for (int i = c; i < BS; ++i)
+            if (i < m) {
+                const double a = fabs(D[i]);
+                if (a > best) {
+                    best = a;
+                    pv = i;
+                }
+            }
+        const double mx = __shfl(best, src0 + c, kWave);
+        const int piv = __shfl(pv, src0 + c, kWave);
+        bool act = !singular && c < m;
+        if (act && !(mx > 0.0)) {  // singular block (zero column below the diagonal)
+            singular = true;
+            act = false;
+        }
+        if (act && piv != c && j < m) {
+            const double dc = D[c], ic = I[c];
+#pragma clang loop unroll(full)
+            for (int i = c + 1; i < BS; ++i)
+                if (i == piv) {
+                    D[c] = D[i];
+                    I[c] = I[i];
+                    D[i] = dc;
+                    I[i] = ic;
+                }
+        }
+        const double d = __shfl(D[c], src0 + c, kWave);
+        if (act && j < m) {  // columns beyond a short last block stay zero
+            D[c] = D[c] / d;
+            I[c] = I[c] / d;
+        }
+#pragma clang loop unroll(full)
+        for (int r = 0; r < BS; ++r) {
+            if (r == c) continue;
+            const double f = __shfl(D[r], src0 + c, kWave);
+            const bool upd = act && r < m && f != 0.0;
+            if (!__any(upd)) continue;
+            if (upd && j < m) {
+                const double pd = f * D[c];
+                const double pi = f * I[c];
+                D[r] = D[r] - pd;
+                I[r] = I[r] - pi;
+            }
+        }
+    }
+    if (singular && j == 0) atomicMin(bad, (int)(b < INT_MAX ? b : INT_MAX));
+    const double nI = norm1(I);
+    const double kappa = nD * nI;
+    int p = BJ_P64;
+    if (adaptive) {
+        double lo = __builtin_inf(), hi = 0.0;
+        if (j < m) {
+#pragma unroll
+            for (int i = 0; i < BS; ++i) {
+                if (i >= m) continue;
+                const double a = fabs(I[i]);
+                if (a == 0.0) continue;
+                lo = a < lo ? a : lo;
+                hi = a > hi ? a : hi;
+            }
+        }
+        lo = -group_max<BS>(-lo);
+        hi = group_max<BS>(hi);
+        if (hi == 0.0) lo = hi = 1.0;
+        if (kappa * ldexp(1.0, -11) <= accuracy && lo >= ldexp(1.0, -14) && hi <= 65504.0) p = BJ_P16;
+        else if (kappa * ldexp(1.0, -24) <= accuracy && lo >= ldexp(1.0, -126) && hi <= 3.4028234663852886e38)
+            p = BJ_P32;
+    }
+    if (live && !singular) {
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            double x = I[i];
+            if (p == BJ_P32) x = (double)(float)x;
+            else if (p == BJ_P16) x = round_f16(x);
+            inv[(b * BS + i) * BS + j] = x;
+        }
+        if (j == 0) {
+            cond[b] = kappa;
+            prec[b] = p;
+        }
     }
 }
 
@@ -429,9 +585,23 @@ hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double a
 static hipError_t bj_invert(const MatrixImpl &A, int bs, int adaptive, double accuracy, double *inv,
                             double *cond, int *prec, int *bad, hipStream_t s) {
     const int64_t nb = (A.nrows + bs - 1) / bs;
-    MXL_BS_SWITCH(bs, hipLaunchKernelGGL(k_bj_invert<BS>, dim3((unsigned)nb), dim3(kWave), 0, s, A.nrows,
-                                         (const int *)A.row_ptr->p, (const int *)A.col->p,
-                                         (const double *)A.val->p, adaptive, accuracy, inv, cond, prec, bad));
+    if (bs == 32)
+        hipLaunchKernelGGL(k_bj_invert1<32>, dim3((unsigned)nb), dim3(kWave), 0, s, A.nrows,
+                           (const int *)A.row_ptr->p, (const int *)A.col->p, (const double *)A.val->p, adaptive,
+                           accuracy, inv, cond, prec, bad);
+    else {
+#define MXL_BJ_INV(BSV)                                                                                   \
+    case BSV:                                                                                             \
+        hipLaunchKernelGGL(k_bj_invert<BSV>, dim3((unsigned)((nb + kWave / BSV - 1) / (kWave / BSV))),    \
+                           dim3(kWave), 0, s, A.nrows, (const int *)A.row_ptr->p, (const int *)A.col->p,   \
+                           (const double *)A.val->p, adaptive, accuracy, inv, cond, prec, bad);           \
+        break;
+        switch (bs) {
+            MXL_BJ_INV(1) MXL_BJ_INV(2) MXL_BJ_INV(4) MXL_BJ_INV(8) MXL_BJ_INV(16)
+        default: return hipErrorInvalidValue;
+        }
+#undef MXL_BJ_INV
+    }
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ MATS = [W.aniso_3d7(10), W.stencil_3d27(7), _dd(100, 0.1, 3), _dd(37, 0.3, 4)]
 
 
 @pytest.mark.parametrize("adaptive", [False, True], ids=["fp64", "adaptive"])
-@pytest.mark.parametrize("bs", [1, 4, 8, 32])
+@pytest.mark.parametrize("bs", [1, 2, 4, 8, 16, 32])
 @pytest.mark.parametrize("A", MATS, ids=[a.name for a in MATS])
 def test_generation_parity(mxl, ctx, A, bs, adaptive):
     bp = O.uniform_blocks(A.nrows, bs)
