@@ -107,6 +107,8 @@ def _declare(L):
     L.orc_bj_generate.restype = i64
     L.orc_bj_generate.argtypes = [i64, vp, vp, vp, i64, vp, C.c_int, f64, vp, vp, vp]
     L.orc_bj_apply.argtypes = [i64, vp, vp, vp, vp]
+    L.orc_bicgstab_block.restype = C.c_int
+    L.orc_bicgstab_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, _Crit, C.POINTER(_Info), vp]
     L.orc_pcg_block.restype = C.c_int
     L.orc_pcg_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, _Crit, C.POINTER(_Info), vp]
     L.orc_gmres.restype = C.c_int
@@ -391,6 +393,25 @@ def bj_apply(bptr, inv, r):
     z = np.zeros_like(r)
     lib().orc_bj_apply(bptr.size - 1, _p(bptr), _p(_c(inv, np.float64)), _p(r), _p(z))
     return z
+
+
+def bicgstab_block(A, b, bptr, inv, x0=None, max_iters=10_000, reduction=1e-10, nonfinite_check=1,
+                   history=False):
+    """BiCGSTAB with the block-Jacobi preconditioner (right preconditioning)."""
+    rp, col, val = _csr(A)
+    b = _c(b, np.float64)
+    bptr = _c(bptr, np.int32)
+    inv = _c(inv, np.float64)
+    x = np.zeros(A.nrows) if x0 is None else _c(x0, np.float64).copy()
+    info = _Info()
+    hist = np.full(max_iters + 1, np.nan) if history else None
+    lib().orc_bicgstab_block(A.nrows, _p(rp), _p(col), _p(val), bptr.size - 1, _p(bptr), _p(inv), _p(b),
+                             _p(x), _Crit(max_iters, reduction, nonfinite_check), C.byref(info), _p(hist))
+    out = dict(x=x, iterations=info.iterations, spmv_count=info.spmv_count,
+               rel_residual=info.rel_residual, stop_reason=info.stop_reason)
+    if history:
+        out["history"] = hist[:info.iterations + 1]
+    return out
 
 
 def pcg_block(A, b, bptr, inv, x0=None, max_iters=10_000, reduction=1e-10, nonfinite_check=1,

@@ -379,9 +379,31 @@ done:
  *           [||r|| small: stop] ; rho_old = rho
  *
  * rho == 0, r_hat.v == 0, t.t == 0 or omega == 0 stops with BREAKDOWN. */
+static int bicgstab_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                         const orc_prec *M, const double *b, double *x, orc_criteria crit, orc_info *info,
+                         double *history);
+
 int orc_bicgstab(int64_t n, const int32_t *row_ptr, const int32_t *col,
                  const double *val, const double *dinv, const double *b,
                  double *x, orc_criteria crit, orc_info *info, double *history)
+{
+    orc_prec M = {dinv, 0, NULL, NULL, NULL, NULL, NULL, 0, 0};
+    return bicgstab_core(n, row_ptr, col, val, &M, b, x, crit, info, history);
+}
+
+/* BiCGSTAB with the block-Jacobi preconditioner: p_hat = blockdiag(inv) p
+ * and s_hat = blockdiag(inv) s (right preconditioning, Sec. 3.1 / 3.2). */
+int orc_bicgstab_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                       int64_t nblocks, const int32_t *bptr, const double *inv, const double *b, double *x,
+                       orc_criteria crit, orc_info *info, double *history)
+{
+    orc_prec M = {NULL, nblocks, bptr, inv, NULL, NULL, NULL, 0, 0};
+    return bicgstab_core(n, row_ptr, col, val, &M, b, x, crit, info, history);
+}
+
+static int bicgstab_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                         const orc_prec *M, const double *b, double *x, orc_criteria crit, orc_info *info,
+                         double *history)
 {
     size_t bytes = (size_t)(n + 1) * sizeof(double);
     double *r = malloc(bytes), *rh = malloc(bytes), *p = calloc(n + 1, sizeof(double));
@@ -413,7 +435,7 @@ int orc_bicgstab(int64_t n, const int32_t *row_ptr, const int32_t *col,
         if (rho == 0.0) { stop = ORC_BREAKDOWN; break; }
         double beta = (rho / rho_old) * (alpha / omega);
         for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-        prec(n, dinv, p, ph);
+        apply_prec(n, M, p, ph);
         orc_csr_spmv(n, row_ptr, col, val, 1.0, ph, 0.0, v);
         info->spmv_count++;
         double rv = dot(n, rh, v);
@@ -430,7 +452,7 @@ int orc_bicgstab(int64_t n, const int32_t *row_ptr, const int32_t *col,
             stop = ORC_CONVERGED;
             break;
         }
-        prec(n, dinv, s, sh);
+        apply_prec(n, M, s, sh);
         orc_csr_spmv(n, row_ptr, col, val, 1.0, sh, 0.0, t);
         info->spmv_count++;
         double tt = dot(n, t, t);

@@ -87,6 +87,9 @@ int orc_pcg(int64_t n, const int32_t *row_ptr, const int32_t *col,
             const double *val, const double *dinv, const double *b, double *x,
             orc_criteria crit, orc_info *info, double *history);
 
+int orc_bicgstab_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                       int64_t nblocks, const int32_t *bptr, const double *inv, const double *b, double *x,
+                       orc_criteria crit, orc_info *info, double *history);
 int orc_bicgstab(int64_t n, const int32_t *row_ptr, const int32_t *col,
                  const double *val, const double *dinv, const double *b,
                  double *x, orc_criteria crit, orc_info *info, double *history);

@@ -203,3 +203,40 @@ def test_ir_block_true_residual_and_fewer_inner_steps():
         assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
         # the strong coupling runs along consecutive rows, which the blocks absorb
         assert blk["inner_iterations"] < 0.6 * pt["inner_iterations"]
+
+
+# ------------------------------------------------- BiCGSTAB with blocks
+def test_bicgstab_block_size_one_is_point_jacobi():
+    A = W.convdiff_2d5(30)
+    b = W.uniform_vec(A.nrows, 3)
+    d, _ = O.jacobi_dinv(A)
+    inv, _, _ = O.bj_generate(A, O.uniform_blocks(A.nrows, 1), adaptive=False)
+    r0 = O.bicgstab(A, b, dinv=d, reduction=1e-10)
+    r1 = O.bicgstab_block(A, b, O.uniform_blocks(A.nrows, 1), inv, reduction=1e-10)
+    assert r0["iterations"] == r1["iterations"] and np.array_equal(r0["x"], r1["x"])
+
+
+def test_bicgstab_single_block_is_exact():
+    """One block holding the whole nonsymmetric matrix: p_hat = A^{-1} r, so
+    v = r, alpha = 1, s = 0 up to rounding and the half step converges in
+    the first iteration."""
+    A = W.convdiff_2d5(6)
+    b = W.uniform_vec(A.nrows, 4)
+    bp = np.array([0, A.nrows], np.int32)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=False)
+    r = O.bicgstab_block(A, b, bp, inv, reduction=1e-10)
+    assert r["stop_reason"] == O.CONVERGED and r["iterations"] == 1 and r["spmv_count"] == 2
+
+
+@pytest.mark.parametrize("bs", [4, 8, 32])
+def test_bicgstab_block_true_residual(bs):
+    A = W.convdiff_3d7(10)
+    b = W.uniform_vec(A.nrows, 5)
+    bp = O.uniform_blocks(A.nrows, bs)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=True)
+    r = O.bicgstab_block(A, b, bp, inv, reduction=1e-10)
+    assert r["stop_reason"] == O.CONVERGED
+    res = b - O.spmv(A, r["x"])
+    assert np.linalg.norm(res) <= 2e-10 * np.linalg.norm(b)
+    d, _ = O.jacobi_dinv(A)
+    assert r["iterations"] <= O.bicgstab(A, b, dinv=d, reduction=1e-10)["iterations"]
