@@ -253,7 +253,8 @@ mxl_status mxl_jacobi_generate(const mxl_op *A, mxl_op **P);
  * every nonzero entry lies in that format's normal range (memory precision
  * decoupled from the FP64 arithmetic); otherwise binary64.  accuracy 0
  * means 0.1.  mxl_apply computes z = M r in FP64 from the stored entries.
- * It preconditions CG (per-kernel path) and GMRES.  block_size in
+ * It preconditions CG (per-kernel path, FP64 or FP32 vectors), BiCGSTAB
+ * (FP64) and GMRES.  block_size in
  * {1, 2, 4, 8, 16, 32}.  Errors: INVALID_ARG, NOT_IMPLEMENTED (non-square,
  * FP32 or matrix-free operator), ZERO_DIAG (a singular diagonal block),
  * OUT_OF_MEMORY, DEVICE. */

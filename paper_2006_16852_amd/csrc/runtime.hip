@@ -776,8 +776,8 @@ mxl_status mxl_gmres_generate(const mxl_op *Aop, const mxl_op *Pop, const mxl_cr
     const bool ilu = Pop && Pop->kind == MXL_OP_ILU;
     if (Pop && Pop->kind != MXL_OP_JACOBI && !ilu)
         return fail(MXL_ERR_NOT_IMPLEMENTED, "only Jacobi or ILU preconditioning");
-    if (Pop && !ilu && Pop->jac->block && kind == MXL_SOLVER_BICGSTAB)
-        return fail(MXL_ERR_NOT_IMPLEMENTED, "block Jacobi preconditions CG and GMRES");
+    if (Pop && !ilu && Pop->jac->block && kind == MXL_SOLVER_BICGSTAB && Aop->mat->dtype != MXL_F64)
+        return fail(MXL_ERR_NOT_IMPLEMENTED, "block-Jacobi BiCGSTAB needs an FP64 operator");
     if (ilu && kind != MXL_SOLVER_GMRES) return fail(MXL_ERR_NOT_IMPLEMENTED, "ILU preconditions GMRES");
     if (ilu && Pop->ilu->A->nrows != Aop->mat->nrows)
         return fail(MXL_ERR_DIM_MISMATCH, "preconditioner does not conform to the matrix");
@@ -1081,9 +1081,13 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
     }
     int64_t k = 0;
     int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
+    // block Jacobi: the fused kernels copy p and s (no scaling), and the
+    // block products p_hat = M p, s_hat = M s follow as kernels of their own
+    const bool blockp = S.P && S.P->block;
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         ++k;
         HIP_TRY(bi_pupdate(ctx, dt, n, S.r->p, S.p->p, S.v->p, phat, dinv, st, pC, gv, (int)k, hist, s));
+        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.p->p, 0.0, phat, s));
         SpmvArgs a;
         a.x = phat;
         a.y = S.v->p;
@@ -1092,6 +1096,7 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
         a.partials = pA;
         HIP_TRY(spmv_launch(A, a, s));
         HIP_TRY(bi_supdate(ctx, dt, n, S.r->p, S.v->p, S.s->p, shat, dinv, st, pA, gs, pB, (int)k, s));
+        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.s->p, 0.0, shat, s));
         SpmvArgs t;
         t.x = shat;
         t.y = S.t->p;

@@ -124,8 +124,9 @@ def test_bjacobi_errors(mxl, ctx):
         mxl.bjacobi(matrix(mxl, ctx, W.stencil_2d5(8), torch.float32), 4)
     assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
     P = mxl.bjacobi(A, 4)
-    with pytest.raises(mxl.MxlError) as e:
-        mxl.solver("bicgstab", A, P)
+    mxl.solver("bicgstab", A, P)  # FP64 block-Jacobi BiCGSTAB is provided
+    with pytest.raises(mxl.MxlError) as e:  # FP32 BiCGSTAB with block Jacobi is not
+        mxl.solver("bicgstab", matrix(mxl, ctx, W.stencil_2d5(8), torch.float32), P)
     assert e.value.status == mxl.ERR_NOT_IMPLEMENTED
 
 
@@ -218,3 +219,40 @@ def test_ir_block_errors(mxl, ctx):
     with pytest.raises(mxl.MxlError) as e:
         mxl.ir(matrix(mxl, ctx, S2), block_size=1)
     assert e.value.status == mxl.ERR_ZERO_DIAG
+
+
+@pytest.mark.parametrize("bs", [1, 4, 8, 32])
+@pytest.mark.parametrize("A", [W.convdiff_3d7(12), W.convdiff_2d5(40), _dd(300, 0.05, 6)],
+                         ids=["convdiff3d7_12", "convdiff2d5_40", "dd300"])
+def test_bicgstab_block_matches_oracle(mxl, ctx, A, bs):
+    """Right-preconditioned BiCGSTAB with the adaptive block Jacobi (block
+    products as kernels of their own) against the oracle's: iteration
+    counts within 2, the FP64 residual recomputed."""
+    b = W.uniform_vec(A.nrows, 7)
+    bp = O.uniform_blocks(A.nrows, bs)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=True)
+    ref = O.bicgstab_block(A, b, bp, inv, reduction=1e-10)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("bicgstab", M, mxl.bjacobi(M, bs, True), max_iters=5000, reduction=1e-10, launch_mode=1)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    assert ref["stop_reason"] == O.CONVERGED and info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["iterations"]) <= 2, (info["iterations"], ref["iterations"])
+    res = np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) / np.linalg.norm(b)
+    assert res <= 2e-10
+
+
+def test_bicgstab_block_iterate_before_convergence(mxl, ctx):
+    """Five steps without a tolerance: the iterate equals the oracle's to
+    rounding (the block products apply the same stored inverses)."""
+    A = W.convdiff_3d7(9)
+    b = W.uniform_vec(A.nrows, 8)
+    bp = O.uniform_blocks(A.nrows, 8)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=False)
+    ref = O.bicgstab_block(A, b, bp, inv, max_iters=5, reduction=0.0)
+    M = matrix(mxl, ctx, A)
+    S = mxl.solver("bicgstab", M, mxl.bjacobi(M, 8, False), max_iters=5, reduction=0.0, launch_mode=1)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    assert info["iterations"] == 5 == ref["iterations"]
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-11 * np.linalg.norm(ref["x"])
