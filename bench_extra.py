@@ -498,6 +498,27 @@ def bicgstab(args):
            "true_rel_residual": float(torch.linalg.norm(r) / torch.linalg.norm(b)),
            "alg_GBs": round(byts / dt / 1e9, 1), "us_per_iteration": round(dt * 1e6 / max(its, 1), 2),
            "steps": args.steps, "warmup": args.warmup}
+    # a nonsymmetric system: 128^3 convection-diffusion, point vs block Jacobi
+    C3 = W.convdiff_3d7(128)
+    cb = mxl.csr(ctx, torch.from_numpy(C3.row_ptr).to(dev), torch.from_numpy(C3.col).to(dev),
+                 torch.from_numpy(C3.val).to(dev))
+    Mc = cb.convert("ell", variant=mxl.ELL_DELTA16)
+    bc = torch.from_numpy(W.uniform_vec(C3.nrows, 5)).to(dev)
+    xc = torch.zeros_like(bc)
+    conv = {}
+    for pname, Pc in (("jacobi", mxl.jacobi(Mc)), ("bjacobi8", mxl.bjacobi(cb, 8, True)),
+                      ("bjacobi32", mxl.bjacobi(cb, 32, True))):
+        Sc = mxl.solver("bicgstab", Mc, Pc, max_iters=5000, reduction=1e-10, check_every=16)
+
+        def fc():
+            xc.zero_()
+            return Sc.solve(bc, xc)
+        dtc, infc = _timed(fc, args.steps, args.warmup)
+        rc = bc.clone()
+        cb.apply(xc, rc, -1.0, 1.0)
+        conv[pname] = {"ms": round(dtc * 1e3, 3), "iterations": infc["iterations"], "stop": infc["stop"],
+                       "true_rel_residual": float(torch.linalg.norm(rc) / torch.linalg.norm(bc))}
+    out["convdiff3d7_128"] = conv
     if not args.no_cpu_baseline:
         O = _oracle()
         dh, _ = O.jacobi_dinv(A)
