@@ -164,8 +164,11 @@ enum { MXL_BORROW = 0, MXL_COPY = 1, MXL_VALIDATE = 2 };
  * views of the caller's arrays, which must stay alive and unchanged until
  * the handle and everything derived from it are destroyed (the Array views
  * of Sec. 2.4); MXL_COPY makes library-owned copies.  MXL_VALIDATE (or-ed
- * in) checks canonical form on the device and fails with INVALID_MATRIX.
- * Errors: INVALID_ARG (null, negative sizes, nnz >= 2^31), DTYPE,
+ * in) checks canonical form on the device and fails with INVALID_MATRIX;
+ * mxl_last_error() then gives the mask of violated rules (1 row_ptr[0] != 0,
+ * 2 row_ptr decreases, 4 row_ptr[nrows] != nnz, 8 a column outside
+ * [0, ncols), 16 columns of a row not strictly increasing) and names the
+ * first of them in that order.  Errors: INVALID_ARG (null, negative sizes, nnz >= 2^31), DTYPE,
  * INVALID_MATRIX, OUT_OF_MEMORY. */
 mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows,
                           int64_t ncols, int64_t nnz, const int32_t *row_ptr,

@@ -296,8 +296,16 @@ mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows, int64_t 
         HIP_TRY(hipMemcpyAsync(&h, fl->p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         if (h) {
-            char msg[128];
-            snprintf(msg, sizeof msg, "CSR arrays are not canonical (violation mask 0x%x)", h);
+            // mask bits in the order the rules are checked: the lowest set bit
+            // names the first violated rule
+            static const char *const rule[5] = {"row_ptr[0] != 0", "row_ptr decreases",
+                                                "row_ptr[n] != nnz", "column out of range",
+                                                "columns not strictly increasing"};
+            int first = 0;
+            while (first < 4 && !(h & (1 << first))) ++first;
+            char msg[160];
+            snprintf(msg, sizeof msg, "CSR arrays are not canonical (violation mask 0x%x; first: %s)", h,
+                     rule[first]);
             return fail(MXL_ERR_INVALID_MATRIX, msg);
         }
     }

@@ -7,6 +7,7 @@ oracle needs minutes at these sizes.  Run from the repository root:
     python tests/golden/make_golden.py bjacobi    # only the block-Jacobi entry
     python tests/golden/make_golden.py gmres      # only the GMRES entry
     python tests/golden/make_golden.py ilu        # only the ILU-GMRES entry
+    python tests/golden/make_golden.py bicgstab   # only the BiCGSTAB entries
 """
 import json
 import os
@@ -65,7 +66,46 @@ def ilu(out):
     print("ilu", r["iterations"], time.time() - t, flush=True)
 
 
-ONLY = {"bjacobi": bjacobi, "gmres": gmres, "ilu": ilu}
+def bicgstab(out):
+    """Jacobi-BiCGSTAB to 1e-10 on the 128^3 27-point system (b = A x*), and
+    on the 128^3 convection-diffusion system with point Jacobi and with
+    block Jacobi of 8- and 32-row blocks (adaptive storage)."""
+    A = W.stencil_3d27(128)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 2))
+    t = time.time()
+    d, _ = O.jacobi_dinv(A)
+    r = O.bicgstab(A, b, dinv=d, reduction=1e-10, max_iters=5000)
+    out["stencil27_128_bicgstab_1e-10"] = dict(
+        recipe="x* = U[-1,1) seed 2, b = A x*, x0 = 0; point Jacobi",
+        iterations=r["iterations"], spmv_count=r["spmv_count"], stop=r["stop_reason"],
+        rel_residual=r["rel_residual"])
+    print("bicgstab 27pt", r["iterations"], time.time() - t, flush=True)
+    del A, b, d
+    A = W.convdiff_3d7(128)
+    b = W.uniform_vec(A.nrows, 5)
+    t = time.time()
+    d, _ = O.jacobi_dinv(A)
+    r = O.bicgstab(A, b, dinv=d, reduction=1e-10, max_iters=5000)
+    out["convdiff3d7_128_bicgstab_jacobi_1e-10"] = dict(
+        recipe="peclet (0.5, 0.25, 0.125); b = U[-1,1) seed 5, x0 = 0; point Jacobi",
+        iterations=r["iterations"], spmv_count=r["spmv_count"], stop=r["stop_reason"],
+        rel_residual=r["rel_residual"])
+    print("bicgstab convdiff jacobi", r["iterations"], time.time() - t, flush=True)
+    for bs in (8, 32):
+        t = time.time()
+        bp = O.uniform_blocks(A.nrows, bs)
+        inv, cond, prec = O.bj_generate(A, bp, adaptive=True, accuracy=0.1)
+        r = O.bicgstab_block(A, b, bp, inv, reduction=1e-10, max_iters=5000)
+        out[f"convdiff3d7_128_bicgstab_bjacobi{bs}_1e-10"] = dict(
+            recipe=f"peclet (0.5, 0.25, 0.125); b = U[-1,1) seed 5, x0 = 0; blocks of {bs} rows, "
+                   "adaptive storage, accuracy 0.1",
+            iterations=r["iterations"], spmv_count=r["spmv_count"], stop=r["stop_reason"],
+            rel_residual=r["rel_residual"],
+            precision_counts=[int((prec == k).sum()) for k in (0, 1, 2)])
+        print("bicgstab convdiff bjacobi", bs, r["iterations"], time.time() - t, flush=True)
+
+
+ONLY = {"bjacobi": bjacobi, "gmres": gmres, "ilu": ilu, "bicgstab": bicgstab}
 
 
 def main():
@@ -107,6 +147,7 @@ def main():
     bjacobi(out)
     gmres(out)
     ilu(out)
+    bicgstab(out)
     json.dump(out, open(path, "w"), indent=1)
     print("wrote", path)
 

@@ -256,3 +256,28 @@ def test_bicgstab_block_iterate_before_convergence(mxl, ctx):
     info = S.solve(dev(b), x)
     assert info["iterations"] == 5 == ref["iterations"]
     assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-11 * np.linalg.norm(ref["x"])
+
+
+@pytest.mark.parametrize("prec", ["jacobi", "bjacobi8", "bjacobi32"])
+def test_full_size_bicgstab_convdiff128(mxl, ctx, prec):
+    """BiCGSTAB to 1e-10 on the 128^3 convection-diffusion system with point
+    Jacobi and with block Jacobi of 8- and 32-row blocks (adaptive storage),
+    on ELL16 with check_every 16 as benchmarked: the many-workgroup
+    reductions and the block products after a device-side stop are covered.
+    Counts within 2 of the oracle's stored counts; FP64 residual."""
+    g = json.load(open(os.path.join(GOLD, "solver_counts.json")))[f"convdiff3d7_128_bicgstab_{prec}_1e-10"]
+    A = W.convdiff_3d7(128)
+    b = W.uniform_vec(A.nrows, 5)
+    base = matrix(mxl, ctx, A)
+    M = base.convert("ell", variant=2)
+    P = mxl.jacobi(M) if prec == "jacobi" else mxl.bjacobi(base, int(prec[7:]), True)
+    if prec != "jacobi":
+        assert [int((P.info()["precision"] == k).sum()) for k in (0, 1, 2)] == g["precision_counts"]
+    S = mxl.solver("bicgstab", M, P, max_iters=5000, reduction=1e-10, check_every=16)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[bicgstab convdiff128 {prec}] gpu {info['iterations']} oracle {g['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - g["iterations"]) <= 2
+    rel = np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) / np.linalg.norm(b)
+    assert rel <= 2e-10

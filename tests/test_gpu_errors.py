@@ -183,3 +183,65 @@ def test_repeated_create_solve_destroy_releases_memory(mxl, ctx):
     free1 = torch.cuda.mem_get_info()[0]
     print(f"[leak] free before {free0 / 2**20:.1f} MiB after {free1 / 2**20:.1f} MiB", flush=True)
     assert free0 - free1 < 32 * 2**20
+
+
+CSR_RULES = {1: "row_ptr[0] != 0", 2: "row_ptr decreases", 3: "row_ptr[n] != nnz",
+             4: "column out of range", 5: "columns not strictly increasing"}
+
+
+def _violations(seed=3):
+    """One matrix per canonical-form rule, each breaking only that rule; the
+    expected oracle verdict (orc_csr_check's code) with it."""
+    A = W.random_sparse(300, 300, 0.05, seed)
+    n, nnz = A.nrows, A.nnz
+    out = []
+    rp = A.row_ptr.copy(); rp[0] = 1                        # bad start (row 0 loses an entry)
+    out.append((1, rp, A.col.copy()))
+    rp = A.row_ptr.copy()
+    i = next(i for i in range(1, n) if rp[i + 1] - rp[i] >= 2)
+    rp[i] = rp[i + 1] + 1 if rp[i + 1] + 1 <= nnz else rp[i + 1]
+    assert rp[i] > rp[i + 1]                                 # row i ends before it starts
+    out.append((2, rp, A.col.copy()))
+    rp = A.row_ptr.copy(); rp[n] = nnz - 1                   # last row ends early
+    out.append((3, rp, A.col.copy()))
+    col = A.col.copy(); col[nnz // 2] = -1                   # negative column
+    out.append((4, A.row_ptr.copy(), col))
+    col = A.col.copy(); k = A.row_ptr[n - 1]; col[k] = 300   # column == ncols
+    out.append((4, A.row_ptr.copy(), col))
+    col = A.col.copy()
+    r = next(r for r in range(n) if A.row_ptr[r + 1] - A.row_ptr[r] >= 2)
+    col[A.row_ptr[r] + 1] = col[A.row_ptr[r]]                # duplicate column
+    out.append((5, A.row_ptr.copy(), col))
+    col = A.col.copy()
+    r = next(r for r in range(n - 1, 0, -1) if A.row_ptr[r + 1] - A.row_ptr[r] >= 2)
+    k = A.row_ptr[r]
+    col[k], col[k + 1] = col[k + 1], col[k]                  # unsorted row
+    out.append((5, A.row_ptr.copy(), col))
+    return A, out
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_csr_validation_matches_oracle(mxl, ctx, case):
+    """Each canonical-form rule broken alone: the oracle's verdict is that
+    rule, and the device validation fails with INVALID_MATRIX naming the
+    same rule first (and setting its bit in the mask)."""
+    import oracle as O
+    A, cases = _violations()
+    kind, rp, col = cases[case]
+    bad = W.Csr(A.nrows, A.ncols, rp, col, A.val)
+    assert O.csr_check(bad) == kind
+    st = _status(mxl, mxl.csr, ctx, dev(rp), dev(col), dev(A.val), None, False, True)
+    assert st == mxl.ERR_INVALID_MATRIX
+    msg = mxl.lib.mxl_last_error().decode()
+    print(f"[validate case {case} kind {kind}] {msg}", flush=True)
+    assert f"first: {CSR_RULES[kind]}" in msg
+    mask = int(msg.split("mask 0x")[1].split(";")[0], 16)
+    assert mask & (1 << (kind - 1))
+
+
+def test_csr_validation_accepts_canonical(mxl, ctx):
+    import oracle as O
+    for A in [W.random_sparse(300, 300, 0.05, 3), W.stencil_2d5(16)] + W.edge_matrices():
+        assert O.csr_check(A) == 0
+        M = mxl.csr(ctx, dev(A.row_ptr), dev(A.col), dev(A.val), ncols=A.ncols, validate=True)
+        assert M.describe()["nnz"] == A.nnz

@@ -323,3 +323,91 @@ def test_full_size_pcg_stencil27(mxl, ctx):
     assert info["stop_reason"] == mxl.STOP_CONVERGED
     assert _close_iters(info["iterations"], g["iterations"])
     assert _true_rel(A, b, x.cpu().numpy()) <= 1.01e-10
+
+
+def _golden(key):
+    return json.load(open(os.path.join(GOLD, "solver_counts.json")))[key]
+
+
+@pytest.fixture(scope="module")
+def aniso160(mxl, ctx):
+    """The 160^3 anisotropic system on the ELL operator with 16-bit column
+    offsets (the operator the benchmark picks for it), b = U[-1,1) seed 4."""
+    A = W.aniso_3d7(160)
+    b = W.uniform_vec(A.nrows, 4)
+    M = matrix(mxl, ctx, A).convert("ell", variant=2)
+    return A, b, M
+
+
+@pytest.mark.parametrize("red,key", [(1e-10, "aniso7_160_pcg_1e-10"), (1e-12, "aniso7_160_pcg_1e-12")])
+def test_full_size_pcg_aniso160(mxl, ctx, aniso160, red, key):
+    """FP64 Jacobi-PCG on the 160^3 anisotropic system at full size, in the
+    benchmark's launch configuration (ELL16, check_every 16): iteration count
+    within 2 of the oracle's stored count, residual recomputed in FP64."""
+    A, b, M = aniso160
+    g = _golden(key)
+    S = mxl.solver("cg", M, mxl.jacobi(M), max_iters=5000, reduction=red, check_every=16)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[pcg aniso160 {red:g}] gpu {info['iterations']} oracle {g['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - g["iterations"]) <= 2
+    assert _true_rel(A, b, x.cpu().numpy()) <= 1.01 * red
+
+
+def test_full_size_ir_aniso160(mxl, ctx, aniso160):
+    """Refinement with the FP32 point-Jacobi inner CG (inner reduction 1e-4)
+    to 1e-12 on the 160^3 anisotropic system: corrections within 1 and
+    inner iterations within 5 % of the oracle's stored counts; the FP64
+    residual recomputed on the CPU."""
+    A, b, M = aniso160
+    g = _golden("aniso7_160_ir_1e-12_inner_1e-4")
+    S = mxl.ir(M, outer=dict(max_iters=60, reduction=1e-12),
+               inner=dict(reduction=1e-4, max_iters=10_000, check_every=16))
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[ir aniso160] gpu {info['iterations']}/{info['inner_iterations']} oracle "
+          f"{g['outer']}/{g['inner_iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - g["outer"]) <= 1
+    assert abs(info["inner_iterations"] - g["inner_iterations"]) <= 0.05 * g["inner_iterations"]
+    assert _true_rel(A, b, x.cpu().numpy()) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def stencil128(mxl, ctx):
+    A = W.stencil_3d27(128)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 2))
+    return A, b
+
+
+def test_full_size_pcg_bench_path(mxl, ctx, stencil128):
+    """The benchmark's CG exactly as it is timed: ELL with 16-bit offsets
+    (SpMV with the fused p.q), point Jacobi, check_every 16, on the 128^3
+    27-point system; count within 2 of the oracle's, FP64 residual."""
+    A, b = stencil128
+    g = _golden("stencil27_128_pcg_1e-10")
+    M = matrix(mxl, ctx, A).convert("ell", variant=2)
+    S = mxl.solver("cg", M, mxl.jacobi(M), max_iters=5000, reduction=1e-10, check_every=16)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[pcg bench path] gpu {info['iterations']} oracle {g['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - g["iterations"]) <= 2
+    assert _true_rel(A, b, x.cpu().numpy()) <= 1.01e-10
+
+
+def test_full_size_bicgstab_stencil27(mxl, ctx, stencil128):
+    """Jacobi-BiCGSTAB to 1e-10 on the 128^3 27-point system, ELL16 and
+    check_every 16 as benchmarked (the many-workgroup reductions): count
+    within 2 of the oracle's stored count, FP64 residual."""
+    A, b = stencil128
+    g = _golden("stencil27_128_bicgstab_1e-10")
+    M = matrix(mxl, ctx, A).convert("ell", variant=2)
+    S = mxl.solver("bicgstab", M, mxl.jacobi(M), max_iters=5000, reduction=1e-10, check_every=16)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[bicgstab full27] gpu {info['iterations']} oracle {g['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - g["iterations"]) <= 2
+    assert _true_rel(A, b, x.cpu().numpy()) <= 2e-10

@@ -241,3 +241,48 @@ def test_full_size_stencil27_sampled(mxl, ctx):
         assert np.array_equal(y.cpu().numpy(), rowsum), name
         del op
     torch.cuda.empty_cache()
+
+
+def _cast_values(n, seed):
+    """FP64 values that exercise FP32 rounding: random magnitudes from the
+    FP32 subnormal range to beyond its largest finite value, exact halfway
+    cases (ties to even), signed zeros, infinities and NaN."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n) * 10.0 ** rng.uniform(-47, 40, n)
+    k = np.arange(n)
+    ties = (1.0 + np.ldexp(1.0, -24) * (2 * (k % 7) + 1)) * np.ldexp(1.0, (k % 40) - 20)
+    v[::5] = ties[::5]                       # halfway between two FP32 neighbours
+    v[1::97] = -0.0
+    v[2::101] = np.inf
+    v[3::103] = -np.inf
+    v[4::107] = np.nan
+    v[6::109] = np.ldexp(1.0, -149) * 1.5    # halfway above the smallest subnormal
+    v[7::113] = np.finfo(np.float32).max * (1 + 2.0 ** -25)   # rounds down to FLT_MAX
+    return v
+
+
+@pytest.mark.parametrize("fmt,kw", [("csr", {}), ("coo", {}), ("ell", {}), ("ell", dict(variant=2)),
+                                    ("hyb", dict(hyb_quantile=0.66))],
+                         ids=["csr", "coo", "ell", "ell16", "hyb"])
+def test_cast_bitwise(mxl, ctx, fmt, kw):
+    """mxl_cast to FP32 rounds every stored value to nearest even exactly as
+    numpy's float64 -> float32 conversion does (bit patterns compared; NaN
+    stays NaN), keeps the index arrays, and the cast back to FP64 is exact."""
+    A = W.random_sparse(700, 700, 0.02, 8)
+    A = W.Csr(A.nrows, A.ncols, A.row_ptr, A.col, _cast_values(A.nnz, 9))
+    M = matrix(mxl, ctx, A).convert(fmt, **kw)
+    M32 = M.cast(torch.float32)
+    keys = {"csr": ["val"], "coo": ["val"], "ell": ["ell_val"], "hyb": ["ell_val", "tail_val"]}[fmt]
+    with np.errstate(over="ignore"):
+        for key in keys:
+            v64 = M.export(key).cpu().numpy()
+            v32 = M32.export(key).cpu().numpy()
+            want = v64.astype(np.float32)
+            nan = np.isnan(want)
+            assert np.array_equal(np.isnan(v32), nan), key
+            assert np.array_equal(v32[~nan].view(np.uint32), want[~nan].view(np.uint32)), key
+            back = M32.cast(torch.float64).export(key).cpu().numpy()
+            assert np.array_equal(back[~nan], want[~nan].astype(np.float64)), key
+    idx = {"csr": ["row_ptr", "col"], "coo": ["coo_row"], "ell": ["ell_col"], "hyb": ["ell_col", "tail_col"]}[fmt]
+    for key in idx:
+        assert torch.equal(M.export(key), M32.export(key)), key

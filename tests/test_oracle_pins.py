@@ -530,3 +530,43 @@ def test_adam_first_step_closed_form():
     O.adam_step(th, g, m, v, 1, lr=1e-2)
     # with zero moments the bias-corrected step is lr * g / (|g| + eps)
     assert np.allclose(th, t0 - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_constant_gradient_every_step():
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step t, so each of the T steps moves theta by
+    lr g / (|g| + eps): a dropped beta carry-over of m or v, or a bias
+    correction with the wrong power of beta, fails from t = 2 on."""
+    rng = np.random.default_rng(5)
+    th = rng.standard_normal(40); g = rng.standard_normal(40) * np.logspace(-3, 2, 40)
+    m = np.zeros(40); v = np.zeros(40)
+    t0 = th.copy()
+    lr, eps = 3e-3, 1e-8
+    for t in range(1, 26):
+        O.adam_step(th, g, m, v, t, lr=lr, eps=eps)
+        assert np.allclose(th, t0 - t * lr * g / (np.abs(g) + eps), rtol=1e-11, atol=1e-14), t
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12), t
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12), t
+
+
+def test_adam_moments_are_discounted_sums():
+    """Varying gradients g_1..g_T: the moments equal the discounted sums
+    m_t = (1-b1) sum_k b1^(t-k) g_k and v_t = (1-b2) sum_k b2^(t-k) g_k^2,
+    and theta moves by lr (m_t/(1-b1^t)) / (sqrt(v_t/(1-b2^t)) + eps) at
+    step t."""
+    rng = np.random.default_rng(6)
+    T, P = 12, 30
+    G = rng.standard_normal((T, P))
+    b1, b2, lr, eps = 0.8, 0.95, 1e-2, 1e-8
+    th = rng.standard_normal(P); m = np.zeros(P); v = np.zeros(P)
+    want = th.copy()
+    for t in range(1, T + 1):
+        O.adam_step(th, G[t - 1], m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        w1 = (1 - b1) * b1 ** (t - np.arange(1, t + 1))
+        w2 = (1 - b2) * b2 ** (t - np.arange(1, t + 1))
+        ms = w1 @ G[:t]
+        vs = w2 @ G[:t] ** 2
+        assert np.allclose(m, ms, rtol=1e-12, atol=1e-15), t
+        assert np.allclose(v, vs, rtol=1e-12, atol=1e-15), t
+        want -= lr * (ms / (1 - b1 ** t)) / (np.sqrt(vs / (1 - b2 ** t)) + eps)
+        assert np.allclose(th, want, rtol=1e-11, atol=1e-14), t
