@@ -10,9 +10,11 @@
  *
  * Conventions for every entry point
  *  - Every call returns mxl_status; MXL_OK is 0.  No C++ exception crosses
- *    this boundary.  On a non-OK status, mxl_last_error() returns a
- *    thread-local, NUL-terminated description valid until the next call on
- *    the same thread.
+ *    this boundary: a host allocation failure inside the library returns
+ *    MXL_ERR_OUT_OF_MEMORY, any other unexpected failure MXL_ERR_INTERNAL.
+ *    On a non-OK status, mxl_last_error() returns a thread-local,
+ *    NUL-terminated description (at most 511 characters) valid until the
+ *    next failing call on the same thread.
  *  - Vector and matrix-array arguments are DEVICE pointers on the context's
  *    device unless a parameter says "host".  The library never frees memory
  *    it did not allocate.
@@ -44,7 +46,8 @@ typedef enum {
     MXL_ERR_ZERO_DIAG = 6,         /* missing or zero diagonal entry */
     MXL_ERR_OUT_OF_MEMORY = 7,
     MXL_ERR_INFEASIBLE_FORMAT = 8, /* padded format exceeds its memory budget */
-    MXL_ERR_DEVICE = 9             /* HIP runtime error */
+    MXL_ERR_DEVICE = 9,            /* HIP runtime error */
+    MXL_ERR_INTERNAL = 10          /* unexpected failure inside the library */
 } mxl_status;
 
 typedef enum { MXL_F64 = 0, MXL_F32 = 1 } mxl_dtype;

@@ -27,9 +27,10 @@ OP_MATRIX, OP_JACOBI, OP_SOLVER, OP_BATCH, OP_ILU = 0, 1, 2, 3, 4
 SOLVER_CG, SOLVER_BICGSTAB, SOLVER_IR, SOLVER_GMRES = 0, 1, 2, 3
 STOP_NONE, STOP_CONVERGED, STOP_MAX_ITERS, STOP_TIME, STOP_BREAKDOWN, STOP_NONFINITE = range(6)
 OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_DTYPE, ERR_NOT_IMPLEMENTED, ERR_INVALID_MATRIX, \
-    ERR_ZERO_DIAG, ERR_OUT_OF_MEMORY, ERR_INFEASIBLE_FORMAT, ERR_DEVICE = range(10)
+    ERR_ZERO_DIAG, ERR_OUT_OF_MEMORY, ERR_INFEASIBLE_FORMAT, ERR_DEVICE, ERR_INTERNAL = range(11)
 STATUS_NAMES = ["OK", "INVALID_ARG", "DIM_MISMATCH", "DTYPE", "NOT_IMPLEMENTED",
-                "INVALID_MATRIX", "ZERO_DIAG", "OUT_OF_MEMORY", "INFEASIBLE_FORMAT", "DEVICE"]
+                "INVALID_MATRIX", "ZERO_DIAG", "OUT_OF_MEMORY", "INFEASIBLE_FORMAT", "DEVICE",
+                "INTERNAL"]
 STOP_NAMES = ["none", "converged", "max_iters", "time", "breakdown", "nonfinite"]
 FORMATS = {"csr": CSR, "coo": COO, "ell": ELL, "hyb": HYB}
 EXPORT_IDS = {"row_ptr": 0, "col": 1, "val": 2, "coo_row": 3, "ell_col": 4, "ell_val": 5,

@@ -784,7 +784,7 @@ hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_crit
 extern "C" mxl_status mxl_batch_csr_create(mxl_ctx *ctx, int64_t nsys, const int32_t *sys_ptr_host,
                                            const int32_t *sys_ptr, const int32_t *row_ptr,
                                            const int32_t *col, const double *val, int flags,
-                                           mxl_op **out) {
+                                           mxl_op **out) try {
     (void)flags;
     if (!ctx || !out || !sys_ptr_host || nsys <= 0 || !sys_ptr || !row_ptr || !col || !val)
         return set_error(MXL_ERR_INVALID_ARG, "batch: NULL argument or nsys <= 0");
@@ -916,6 +916,8 @@ extern "C" mxl_status mxl_batch_csr_create(mxl_ctx *ctx, int64_t nsys, const int
     op->bat = Bt;
     *out = op;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 static const BatchImpl *batch_of(const mxl_op *op) {
@@ -996,7 +998,7 @@ static mxl_tuning default_tuning() {
 
 extern "C" mxl_status mxl_batch_solve(const mxl_op *Bop, const mxl_criteria *crit, const mxl_tuning *tuning,
                                       const double *b, double *x, int32_t *iters, double *rel_res,
-                                      uint8_t *status) {
+                                      uint8_t *status) try {
     BatchImpl *Bt = const_cast<BatchImpl *>(batch_of(Bop));
     if (!Bt || !crit) return set_error(MXL_ERR_INVALID_ARG, "batch operator and criteria required");
     if (!(crit->reduction >= 0.0)) return set_error(MXL_ERR_INVALID_ARG, "reduction must be >= 0");
@@ -1007,11 +1009,13 @@ extern "C" mxl_status mxl_batch_solve(const mxl_op *Bop, const mxl_criteria *cri
     if (hipStreamSynchronize(Bt->ctx->stream) != hipSuccess)
         return set_error(MXL_ERR_DEVICE, "batched solve");
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_batch_autotune(const mxl_op *Bop, const mxl_criteria *crit, const double *b,
                                          double *x_scratch, int reps, mxl_tuning *best_out,
-                                         double *best_ms) {
+                                         double *best_ms) try {
     BatchImpl *Bt = const_cast<BatchImpl *>(batch_of(Bop));
     if (!Bt || !crit || reps < 1) return set_error(MXL_ERR_INVALID_ARG, "batch operator, criteria, reps >= 1");
     mxl_status st;
@@ -1068,6 +1072,8 @@ extern "C" mxl_status mxl_batch_autotune(const mxl_op *Bop, const mxl_criteria *
     if (best_out) *best_out = bt;
     if (best_ms) *best_ms = best;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 namespace mxl {

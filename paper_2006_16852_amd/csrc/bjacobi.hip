@@ -618,7 +618,7 @@ static hipError_t bj_pack(int bs, int64_t nb, const double *inv, const int *prec
 using namespace mxl;
 
 extern "C" mxl_status mxl_bjacobi_generate(const mxl_op *Aop, int32_t block_size, int32_t adaptive,
-                                           double accuracy, mxl_op **Pout) {
+                                           double accuracy, mxl_op **Pout) try {
     if (!Aop || !Pout || Aop->kind != MXL_OP_MATRIX)
         return set_error(MXL_ERR_INVALID_ARG, "matrix operator and output required");
     *Pout = nullptr;
@@ -695,10 +695,12 @@ extern "C" mxl_status mxl_bjacobi_generate(const mxl_op *Aop, int32_t block_size
     op->jac = J;
     *Pout = op;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_bjacobi_info(const mxl_op *Pop, int64_t *nblocks, double *cond_host,
-                                       int32_t *precision_host, double *inv_host, int64_t *storage_bytes) {
+                                       int32_t *precision_host, double *inv_host, int64_t *storage_bytes) try {
     if (!Pop || Pop->kind != MXL_OP_JACOBI || !Pop->jac->block)
         return set_error(MXL_ERR_INVALID_ARG, "not a block-Jacobi operator");
     const JacobiImpl &J = *Pop->jac;
@@ -749,4 +751,6 @@ extern "C" mxl_status mxl_bjacobi_info(const mxl_op *Pop, int64_t *nblocks, doub
         }
     }
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mxl.h"
+#include "abi_guard.hpp"
 
 namespace mxl {
 

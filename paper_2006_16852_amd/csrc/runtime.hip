@@ -3,10 +3,11 @@
 // conversion, and the host side of the Krylov solvers (kernel sequencing,
 // criterion checks, convergence records).
 //
-// The solver loops keep every scalar on the device: reductions finish in the
-// last workgroup of the kernel that produced them, and the host only reads
-// the solver state every check_every iterations to evaluate the Time
-// criterion and to stop launching.  Kernels enqueued after a device-side stop
+// The solver loops keep every scalar on the device: a kernel publishes one
+// partial per workgroup and the kernel that needs the scalar reduces all of
+// them in its prologue; the host only reads the solver state every
+// check_every iterations to evaluate the Time criterion and to stop
+// launching.  Kernels enqueued after a device-side stop
 // return immediately, so the result does not depend on check_every.
 #include <algorithm>
 #include <chrono>
@@ -24,12 +25,7 @@ using namespace mxl;
 
 namespace {
 
-thread_local std::string g_err;
-
-mxl_status fail(mxl_status st, const std::string &msg) {
-    g_err = msg;
-    return st;
-}
+mxl_status fail(mxl_status st, const std::string &msg) { return mxl::record_error(st, msg.c_str()); }
 
 mxl_status hip_fail(hipError_t e, const char *where) {
     return fail(e == hipErrorOutOfMemory ? MXL_ERR_OUT_OF_MEMORY : MXL_ERR_DEVICE,
@@ -203,11 +199,11 @@ mxl_status check_device_ptr(const mxl_ctx *ctx, const void *p, size_t bytes, con
 
 extern "C" {
 
-const char *mxl_last_error(void) { return g_err.c_str(); }
+const char *mxl_last_error(void) { return mxl::last_error(); }
 
 const char *mxl_version(void) { return "mxl 0.1 gfx950"; }
 
-mxl_status mxl_ctx_create(int device, void *hip_stream, mxl_ctx **out) {
+mxl_status mxl_ctx_create(int device, void *hip_stream, mxl_ctx **out) try {
     if (!out) return fail(MXL_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int ndev = 0;
@@ -231,15 +227,19 @@ mxl_status mxl_ctx_create(int device, void *hip_stream, mxl_ctx **out) {
     }
     *out = c;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_ctx_set_stream(mxl_ctx *ctx, void *hip_stream) {
+mxl_status mxl_ctx_set_stream(mxl_ctx *ctx, void *hip_stream) try {
     if (!ctx) return fail(MXL_ERR_INVALID_ARG, "ctx is NULL");
     ctx->stream = (hipStream_t)hip_stream;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_ctx_destroy(mxl_ctx *ctx) {
+mxl_status mxl_ctx_destroy(mxl_ctx *ctx) try {
     if (!ctx) return MXL_OK;
     {
         DeviceScope ds(ctx->device);
@@ -247,11 +247,13 @@ mxl_status mxl_ctx_destroy(mxl_ctx *ctx) {
     }
     ctx_release(ctx);  // objects still using the context keep it alive
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows, int64_t ncols, int64_t nnz,
                           const int32_t *row_ptr, const int32_t *col, const void *val, int flags,
-                          mxl_op **Aout) {
+                          mxl_op **Aout) try {
     if (!ctx || !Aout) return fail(MXL_ERR_INVALID_ARG, "ctx/out is NULL");
     *Aout = nullptr;
     if (dtype != MXL_F64 && dtype != MXL_F32) return fail(MXL_ERR_DTYPE, "unknown dtype");
@@ -316,10 +318,12 @@ mxl_status mxl_csr_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nrows, int64_t 
     finish_matrix(*A);
     *Aout = wrap_matrix(A);
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 mxl_status mxl_stencil_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nx, int64_t ny, int64_t nz,
-                              int32_t npts, const int32_t *offsets, const double *coef, mxl_op **Aout) {
+                              int32_t npts, const int32_t *offsets, const double *coef, mxl_op **Aout) try {
     if (!ctx || !offsets || !coef || !Aout) return fail(MXL_ERR_INVALID_ARG, "NULL argument");
     *Aout = nullptr;
     if (dtype != MXL_F64 && dtype != MXL_F32) return fail(MXL_ERR_DTYPE, "dtype must be F64 or F32");
@@ -358,10 +362,12 @@ mxl_status mxl_stencil_create(mxl_ctx *ctx, mxl_dtype dtype, int64_t nx, int64_t
     finish_matrix(*A);
     *Aout = wrap_matrix(A);
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_params *params,
-                       mxl_op **out) {
+                       mxl_op **out) try {
     if (!Aop || !out || Aop->kind != MXL_OP_MATRIX) return fail(MXL_ERR_INVALID_ARG, "not a matrix operator");
     *out = nullptr;
     const MatrixImpl &S = *Aop->mat;
@@ -494,9 +500,11 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
     finish_matrix(*A);
     *out = wrap_matrix(A);
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_cast(const mxl_op *Aop, mxl_dtype dtype, mxl_op **out) {
+mxl_status mxl_cast(const mxl_op *Aop, mxl_dtype dtype, mxl_op **out) try {
     if (!Aop || !out || Aop->kind != MXL_OP_MATRIX) return fail(MXL_ERR_INVALID_ARG, "not a matrix operator");
     if (dtype != MXL_F64 && dtype != MXL_F32) return fail(MXL_ERR_DTYPE, "unknown dtype");
     *out = nullptr;
@@ -534,6 +542,8 @@ mxl_status mxl_cast(const mxl_op *Aop, mxl_dtype dtype, mxl_op **out) {
     finish_matrix(*A);
     *out = wrap_matrix(A);
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 static mxl_status apply_matrix(const MatrixImpl &A, double alpha, const void *b, double beta,
@@ -551,7 +561,7 @@ static mxl_status apply_matrix(const MatrixImpl &A, double alpha, const void *b,
     return MXL_OK;
 }
 
-mxl_status mxl_apply_adv(const mxl_op *L, double alpha, const void *b, double beta, void *x) {
+mxl_status mxl_apply_adv(const mxl_op *L, double alpha, const void *b, double beta, void *x) try {
     if (!L) return fail(MXL_ERR_INVALID_ARG, "operator is NULL");
     if (!b || !x) return fail(MXL_ERR_INVALID_ARG, "vector is NULL");
     if (b == x) return fail(MXL_ERR_INVALID_ARG, "input and output alias");
@@ -586,11 +596,15 @@ mxl_status mxl_apply_adv(const mxl_op *L, double alpha, const void *b, double be
     default:
         return fail(MXL_ERR_NOT_IMPLEMENTED, "apply of this operator kind");
     }
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_apply(const mxl_op *L, const void *b, void *x) { return mxl_apply_adv(L, 1.0, b, 0.0, x); }
+mxl_status mxl_apply(const mxl_op *L, const void *b, void *x) try { return mxl_apply_adv(L, 1.0, b, 0.0, x); } catch (...) {
+    return mxl::abi_exception(__func__);
+}
 
-mxl_status mxl_op_describe(const mxl_op *op, mxl_op_desc *out) {
+mxl_status mxl_op_describe(const mxl_op *op, mxl_op_desc *out) try {
     if (!op || !out) return fail(MXL_ERR_INVALID_ARG, "NULL argument");
     memset(out, 0, sizeof(*out));
     out->kind = op->kind;
@@ -612,9 +626,11 @@ mxl_status mxl_op_describe(const mxl_op *op, mxl_op_desc *out) {
     out->tail_nnz = A->tail_nnz;
     out->stored_bytes = A->stored_bytes;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_op_export(const mxl_op *op, int32_t which, void *dst, int64_t dst_bytes) {
+mxl_status mxl_op_export(const mxl_op *op, int32_t which, void *dst, int64_t dst_bytes) try {
     if (!op || !dst) return fail(MXL_ERR_INVALID_ARG, "NULL argument");
     const MatrixImpl *A = op->kind == MXL_OP_MATRIX ? op->mat.get()
                           : op->kind == MXL_OP_JACOBI ? op->jac->A.get() : nullptr;
@@ -648,9 +664,11 @@ mxl_status mxl_op_export(const mxl_op *op, int32_t which, void *dst, int64_t dst
     if ((st = check_dev(A->ctx, dst, bytes, "dst")) != MXL_OK) return st;
     if (bytes) HIP_TRY(hipMemcpyAsync(dst, b->p, bytes, hipMemcpyDeviceToDevice, A->ctx->stream));
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_op_destroy(mxl_op *op) {
+mxl_status mxl_op_destroy(mxl_op *op) try {
     if (!op) return MXL_OK;
     const MatrixImpl *A = op->kind == MXL_OP_MATRIX ? op->mat.get()
                           : op->kind == MXL_OP_JACOBI ? op->jac->A.get()
@@ -663,9 +681,11 @@ mxl_status mxl_op_destroy(mxl_op *op) {
     }
     delete op;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-mxl_status mxl_jacobi_generate(const mxl_op *Aop, mxl_op **P) {
+mxl_status mxl_jacobi_generate(const mxl_op *Aop, mxl_op **P) try {
     if (!Aop || !P || Aop->kind != MXL_OP_MATRIX) return fail(MXL_ERR_INVALID_ARG, "not a matrix operator");
     *P = nullptr;
     const auto &A = Aop->mat;
@@ -707,6 +727,8 @@ mxl_status mxl_jacobi_generate(const mxl_op *Aop, mxl_op **P) {
     op->jac = J;
     *P = op;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
@@ -763,17 +785,19 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
 }
 
 mxl_status mxl_solver_generate(mxl_solver_kind kind, const mxl_op *Aop, const mxl_op *Pop,
-                               const mxl_criteria *crit, mxl_op **Sout) {
+                               const mxl_criteria *crit, mxl_op **Sout) try {
     if (!Aop || !Sout || !crit || Aop->kind != MXL_OP_MATRIX)
         return fail(MXL_ERR_INVALID_ARG, "matrix operator and criteria required");
     if (kind != MXL_SOLVER_CG && kind != MXL_SOLVER_BICGSTAB && kind != MXL_SOLVER_GMRES)
         return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown solver kind");
     return mxl_gmres_generate(Aop, Pop, crit, kind == MXL_SOLVER_GMRES ? 100 : -(int)kind - 1, Sout);
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 // kdim >= 1: GMRES(kdim); kdim = -kind-1 routes the other Krylov kinds here.
 mxl_status mxl_gmres_generate(const mxl_op *Aop, const mxl_op *Pop, const mxl_criteria *crit, int32_t kdim,
-                              mxl_op **Sout) {
+                              mxl_op **Sout) try {
     if (!Aop || !Sout || !crit || Aop->kind != MXL_OP_MATRIX)
         return fail(MXL_ERR_INVALID_ARG, "matrix operator and criteria required");
     const int kind = kdim < 0 ? -kdim - 1 : MXL_SOLVER_GMRES;
@@ -800,6 +824,8 @@ mxl_status mxl_gmres_generate(const mxl_op *Aop, const mxl_op *Pop, const mxl_cr
     op->sol = S;
     *Sout = op;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 }  // extern "C"
@@ -1387,7 +1413,7 @@ mxl_status solve_ir(const SolverImpl &S, const void *bv, void *xv, mxl_solve_inf
 
 }  // namespace
 
-extern "C" mxl_status mxl_ir_generate(const mxl_op *Aop, const mxl_ir_params *prm, mxl_op **out) {
+extern "C" mxl_status mxl_ir_generate(const mxl_op *Aop, const mxl_ir_params *prm, mxl_op **out) try {
     if (!Aop || !prm || !out || Aop->kind != MXL_OP_MATRIX)
         return fail(MXL_ERR_INVALID_ARG, "matrix operator and parameters required");
     *out = nullptr;
@@ -1442,9 +1468,11 @@ extern "C" mxl_status mxl_ir_generate(const mxl_op *Aop, const mxl_ir_params *pr
     op->sol = S;
     *out = op;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-extern "C" mxl_status mxl_solve(const mxl_op *Sop, const void *b, void *x, mxl_solve_info *info) {
+extern "C" mxl_status mxl_solve(const mxl_op *Sop, const void *b, void *x, mxl_solve_info *info) try {
     if (!Sop || Sop->kind != MXL_OP_SOLVER) return fail(MXL_ERR_INVALID_ARG, "not a solver operator");
     if (!b || !x) return fail(MXL_ERR_INVALID_ARG, "vector is NULL");
     if (b == x) return fail(MXL_ERR_INVALID_ARG, "right-hand side and solution alias");
@@ -1460,10 +1488,12 @@ extern "C" mxl_status mxl_solve(const mxl_op *Sop, const void *b, void *x, mxl_s
     if (S.kind == MXL_SOLVER_IR) return solve_ir(S, b, x, info);
     if (S.kind == MXL_SOLVER_GMRES) return solve_gmres(S, b, x, info);
     return fail(MXL_ERR_NOT_IMPLEMENTED, "unknown solver kind");
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_time_apply(const mxl_op *Aop, const void *x, void *y, int reps, int flush,
-                                     double *median_ms) {
+                                     double *median_ms) try {
     if (!Aop || Aop->kind != MXL_OP_MATRIX || !median_ms || reps < 1)
         return fail(MXL_ERR_INVALID_ARG, "matrix operator, reps >= 1 and output required");
     const MatrixImpl &A = *Aop->mat;
@@ -1505,10 +1535,12 @@ extern "C" mxl_status mxl_time_apply(const mxl_op *Aop, const void *x, void *y, 
     size_t m = ts.size();
     *median_ms = m % 2 ? ts[m / 2] : 0.5 * (ts[m / 2 - 1] + ts[m / 2]);
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_stream_bench(mxl_ctx *ctx, int op, int64_t n, const double *a,
-                                       const double *b, double *c, int reps, double *median_ms) {
+                                       const double *b, double *c, int reps, double *median_ms) try {
     if (!ctx || !median_ms || reps < 1 || n < 2 || (n & 1) || op < 0 || op > 2)
         return fail(MXL_ERR_INVALID_ARG, "stream: op in 0..2, even n >= 2, reps >= 1");
     DeviceScope ds(ctx->device);
@@ -1540,4 +1572,6 @@ extern "C" mxl_status mxl_stream_bench(mxl_ctx *ctx, int op, int64_t n, const do
     size_t m = ts.size();
     *median_ms = m % 2 ? ts[m / 2] : 0.5 * (ts[m / 2 - 1] + ts[m / 2]);
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }

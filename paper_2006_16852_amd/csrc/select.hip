@@ -350,7 +350,7 @@ struct mxl_mlp {
     float loss = 0.f;
 };
 
-extern "C" mxl_status mxl_features(const mxl_op *Aop, double out_host[16]) {
+extern "C" mxl_status mxl_features(const mxl_op *Aop, double out_host[16]) try {
     if (!Aop || Aop->kind != MXL_OP_MATRIX || !out_host)
         return set_error(MXL_ERR_INVALID_ARG, "matrix operator and output required");
     if (Aop->mat->format == MXL_FMT_STENCIL)
@@ -361,10 +361,12 @@ extern "C" mxl_status mxl_features(const mxl_op *Aop, double out_host[16]) {
     mxl_status st = features_compute(*Aop->mat, out_host);
     if (prev >= 0) (void)hipSetDevice(prev);
     return st;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_mlp_create(mxl_ctx *ctx, int32_t nlayers, const int32_t *dims,
-                                     const float *theta_host, mxl_mlp **out) {
+                                     const float *theta_host, mxl_mlp **out) try {
     if (!ctx || !dims || !out || nlayers < 1 || nlayers > kMlpMaxL)
         return set_error(MXL_ERR_INVALID_ARG, "mlp: 1..6 layers, dims and out required");
     *out = nullptr;
@@ -401,6 +403,8 @@ extern "C" mxl_status mxl_mlp_create(mxl_ctx *ctx, int32_t nlayers, const int32_
     }
     *out = mm;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 static mxl_status mlp_copy(const mxl_mlp *mm, void *dst, const void *src, int64_t n, hipMemcpyKind k) {
@@ -412,14 +416,20 @@ static mxl_status mlp_copy(const mxl_mlp *mm, void *dst, const void *src, int64_
     return MXL_OK;
 }
 
-extern "C" mxl_status mxl_mlp_get_params(const mxl_mlp *mm, float *theta_host, int64_t n) {
+extern "C" mxl_status mxl_mlp_get_params(const mxl_mlp *mm, float *theta_host, int64_t n) try {
     return mlp_copy(mm, theta_host, mm ? mm->theta : nullptr, n, hipMemcpyDeviceToHost);
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
-extern "C" mxl_status mxl_mlp_set_params(mxl_mlp *mm, const float *theta_host, int64_t n) {
+extern "C" mxl_status mxl_mlp_set_params(mxl_mlp *mm, const float *theta_host, int64_t n) try {
     return mlp_copy(mm, mm ? mm->theta : nullptr, theta_host, n, hipMemcpyHostToDevice);
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
-extern "C" mxl_status mxl_mlp_get_grad(const mxl_mlp *mm, float *grad_host, int64_t n) {
+extern "C" mxl_status mxl_mlp_get_grad(const mxl_mlp *mm, float *grad_host, int64_t n) try {
     return mlp_copy(mm, grad_host, mm ? mm->grad : nullptr, n, hipMemcpyDeviceToHost);
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 static mxl_status mlp_run(mxl_mlp *mm, int64_t ns, const float *X, const float *T, const float *M,
@@ -485,19 +495,23 @@ static mxl_status mlp_run(mxl_mlp *mm, int64_t ns, const float *X, const float *
     return MXL_OK;
 }
 
-extern "C" mxl_status mxl_mlp_forward(const mxl_mlp *mm, int64_t ns, const float *X, float *Y) {
+extern "C" mxl_status mxl_mlp_forward(const mxl_mlp *mm, int64_t ns, const float *X, float *Y) try {
     if (!Y) return set_error(MXL_ERR_INVALID_ARG, "Y required");
     return mlp_run(const_cast<mxl_mlp *>(mm), ns, X, nullptr, nullptr, 0.f, Y, nullptr, false);
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_mlp_loss_grad(mxl_mlp *mm, int64_t ns, const float *X, const float *T,
-                                        const float *M, float lambda, float *loss_host) {
+                                        const float *M, float lambda, float *loss_host) try {
     if (!T || !M) return set_error(MXL_ERR_INVALID_ARG, "targets and mask required");
     return mlp_run(mm, ns, X, T, M, lambda, nullptr, loss_host, true);
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 extern "C" mxl_status mxl_mlp_adam_step(mxl_mlp *mm, int64_t t, float lr, float beta1, float beta2,
-                                        float eps) {
+                                        float eps) try {
     if (!mm || t < 1) return set_error(MXL_ERR_INVALID_ARG, "network and step t >= 1");
     const float c1 = 1.f - (float)std::pow((double)beta1, (double)t);
     const float c2 = 1.f - (float)std::pow((double)beta2, (double)t);
@@ -506,9 +520,11 @@ extern "C" mxl_status mxl_mlp_adam_step(mxl_mlp *mm, int64_t t, float lr, float 
                        (float *)mm->v, lr, beta1, beta2, eps, c1, c2);
     if (hipGetLastError() != hipSuccess) return set_error(MXL_ERR_DEVICE, "adam launch");
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-extern "C" mxl_status mxl_mlp_destroy(mxl_mlp *mm) {
+extern "C" mxl_status mxl_mlp_destroy(mxl_mlp *mm) try {
     if (!mm) return MXL_OK;
     if (mm->ctx) (void)hipStreamSynchronize(mm->ctx->stream);
     (void)hipFree(mm->theta);
@@ -518,6 +534,8 @@ extern "C" mxl_status mxl_mlp_destroy(mxl_mlp *mm) {
     (void)hipFree(mm->gs);
     delete mm;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 // ================================================================ selector
@@ -534,7 +552,7 @@ struct mxl_selector {
 extern "C" mxl_status mxl_selector_create(mxl_ctx *ctx, int32_t nclasses, const mxl_kernel_class *classes,
                                           int32_t nlayers, const int32_t *dims, const float *theta_host,
                                           const double *mean16, const double *std16, uint32_t log_mask,
-                                          double delta, double zmax, mxl_selector **out) {
+                                          double delta, double zmax, mxl_selector **out) try {
     if (!ctx || !classes || !dims || !theta_host || !mean16 || !std16 || !out || nclasses < 1 ||
         nclasses > kMlpMaxW || nlayers < 1 || nlayers > kMlpMaxL)
         return set_error(MXL_ERR_INVALID_ARG, "selector: context, 1..64 classes, network and statistics required");
@@ -570,9 +588,11 @@ extern "C" mxl_status mxl_selector_create(mxl_ctx *ctx, int32_t nclasses, const 
     }
     *out = S;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
-extern "C" mxl_status mxl_selector_destroy(mxl_selector *S) {
+extern "C" mxl_status mxl_selector_destroy(mxl_selector *S) try {
     if (!S) return MXL_OK;
     {
         DeviceScope dsc(S->ctx->device);
@@ -582,6 +602,8 @@ extern "C" mxl_status mxl_selector_destroy(mxl_selector *S) {
     }
     delete S;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
 
 namespace {
@@ -605,7 +627,7 @@ int64_t class_width(const mxl_kernel_class &k, const std::vector<unsigned> &hist
 
 extern "C" mxl_status mxl_select(const mxl_selector *S, const mxl_op *Aop, int32_t mode, const void *x,
                                  void *y, int32_t reps, int32_t *class_out, double *scores,
-                                 double *times_ms, mxl_select_info *info) {
+                                 double *times_ms, mxl_select_info *info) try {
     if (!S || !Aop || Aop->kind != MXL_OP_MATRIX || !class_out)
         return set_error(MXL_ERR_INVALID_ARG, "selector, matrix operator and class output required");
     if (mode != MXL_SELECT_MODEL && mode != MXL_SELECT_EXHAUSTIVE && mode != MXL_SELECT_MODEL_FALLBACK)
@@ -709,4 +731,6 @@ extern "C" mxl_status mxl_select(const mxl_selector *S, const mxl_op *Aop, int32
         for (int c = 0; c < C; ++c) times_ms[c] = tm[c];
     if (info) *info = inf_out;
     return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
 }
