@@ -104,6 +104,8 @@ def _declare(L):
     L.orc_round_f16.argtypes = [f64]
     L.orc_bj_choose_precision.restype = C.c_int
     L.orc_bj_choose_precision.argtypes = [C.c_int, vp, f64, f64]
+    L.orc_bj_supervariable_blocks.restype = i64
+    L.orc_bj_supervariable_blocks.argtypes = [i64, vp, vp, C.c_int, vp]
     L.orc_bj_generate.restype = i64
     L.orc_bj_generate.argtypes = [i64, vp, vp, vp, i64, vp, C.c_int, f64, vp, vp, vp]
     L.orc_bj_apply.argtypes = [i64, vp, vp, vp, vp]
@@ -361,6 +363,16 @@ def round_f16(x: float) -> float:
 def uniform_blocks(n: int, bs: int) -> np.ndarray:
     """Block row pointers of consecutive blocks of bs rows (last one ragged)."""
     return np.minimum(np.arange(0, n + bs, bs), n).astype(np.int32)[:(n + bs - 1) // bs + 1]
+
+
+def supervariable_blocks(A, max_bs: int) -> np.ndarray:
+    """Block row pointers by supervariable agglomeration: runs of rows with
+    identical column sets, cut into pieces of at most max_bs rows, packed
+    greedily into blocks of at most max_bs rows."""
+    rp, col, _ = _csr(A)
+    bptr = np.zeros(A.nrows + 1, np.int32)
+    nb = lib().orc_bj_supervariable_blocks(A.nrows, _p(rp), _p(col), int(max_bs), _p(bptr))
+    return bptr[:nb + 1].copy()
 
 
 def bj_choose_precision(inv: np.ndarray, cond: float, accuracy: float = 0.1) -> int:

@@ -1187,6 +1187,51 @@ int orc_bj_choose_precision(int m, const double *inv, double cond, double accura
     return ORC_P64;
 }
 
+/* Variable block boundaries for block-Jacobi (Sec. 3.2 names batched
+ * variable-size Gauss-Jordan generation but no rule for the sizes).
+ * Reading: supervariable agglomeration.  A supervariable is a maximal run of
+ * consecutive rows whose column index sets are identical; one longer than
+ * max_bs is cut into pieces of max_bs rows from its first row on (the last
+ * piece may be shorter), and every piece counts as a unit.  Walking the
+ * units in row order, a unit joins the current block when the block then
+ * has at most max_bs rows, and starts a new block otherwise.  bptr (room
+ * for n + 1 entries) receives the block boundaries; returns the number of
+ * blocks. */
+static int same_pattern(const int32_t *row_ptr, const int32_t *col, int64_t a, int64_t b)
+{
+    const int32_t la = row_ptr[a + 1] - row_ptr[a], lb = row_ptr[b + 1] - row_ptr[b];
+    if (la != lb) return 0;
+    for (int32_t k = 0; k < la; ++k)
+        if (col[row_ptr[a] + k] != col[row_ptr[b] + k]) return 0;
+    return 1;
+}
+
+int64_t orc_bj_supervariable_blocks(int64_t n, const int32_t *row_ptr, const int32_t *col, int max_bs,
+                                    int32_t *bptr)
+{
+    int64_t nb = 0;
+    bptr[0] = 0;
+    int64_t block_rows = 0;
+    int64_t i = 0;
+    while (i < n) {
+        /* the supervariable starting at row i */
+        int64_t e = i + 1;
+        while (e < n && same_pattern(row_ptr, col, e, i)) ++e;
+        /* its pieces of at most max_bs rows */
+        for (int64_t p = i; p < e; p += max_bs) {
+            const int64_t len = (e - p < max_bs) ? e - p : max_bs;
+            if (block_rows > 0 && block_rows + len > max_bs) {
+                bptr[++nb] = (int32_t)p;
+                block_rows = 0;
+            }
+            block_rows += len;
+        }
+        i = e;
+    }
+    if (n > 0) bptr[++nb] = (int32_t)n;
+    return nb;
+}
+
 int64_t orc_bj_generate(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                         int64_t nblocks, const int32_t *bptr, int adaptive, double accuracy,
                         double *inv, double *cond, int32_t *prec_out)

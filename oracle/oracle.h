@@ -142,6 +142,8 @@ void orc_adam_step(int64_t nparams, double *theta, const double *grad,
 enum { ORC_P64 = 0, ORC_P32 = 1, ORC_P16 = 2 };
 double  orc_round_f16(double x);
 int     orc_bj_choose_precision(int m, const double *inv, double cond, double accuracy);
+int64_t orc_bj_supervariable_blocks(int64_t n, const int32_t *row_ptr, const int32_t *col, int max_bs,
+                                    int32_t *bptr);
 int64_t orc_bj_generate(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                         int64_t nblocks, const int32_t *bptr, int adaptive, double accuracy,
                         double *inv, double *cond, int32_t *prec);

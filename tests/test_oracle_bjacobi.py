@@ -240,3 +240,155 @@ def test_bicgstab_block_true_residual(bs):
     assert np.linalg.norm(res) <= 2e-10 * np.linalg.norm(b)
     d, _ = O.jacobi_dinv(A)
     assert r["iterations"] <= O.bicgstab(A, b, dinv=d, reduction=1e-10)["iterations"]
+
+
+# ----------------------------------------------- variable-size blocks
+def _grouped(sizes, seed, extra=0.15):
+    """A symmetric sparse matrix whose rows come in consecutive groups of the
+    given sizes, all rows of a group sharing one column set (a group couples
+    densely to itself and to a few random other groups), plus a dominant
+    diagonal."""
+    rng = np.random.default_rng(seed)
+    g = len(sizes)
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(start[-1])
+    G = rng.random((g, g)) < extra
+    G = G | G.T | np.eye(g, dtype=bool)
+    D = np.zeros((n, n))
+    for a in range(g):
+        for b in np.nonzero(G[a])[0]:
+            D[start[a]:start[a + 1], start[b]:start[b + 1]] = 1.0
+    V = rng.uniform(0.1, 1.0, (n, n))
+    D = -(D * (V + V.T) / 2)
+    np.fill_diagonal(D, 0.0)
+    np.fill_diagonal(D, np.abs(D).sum(1) + 1.0)
+    r, c = np.nonzero(np.abs(D) + np.eye(n))
+    rp = np.concatenate([[0], np.cumsum(np.bincount(r, minlength=n))]).astype(np.int32)
+    return W.Csr(n, n, rp, c.astype(np.int32), D[r, c], f"grouped{n}"), start
+
+
+def _units(A, max_bs):
+    """Supervariables found from whole-row pattern tuples (a different route
+    than a scan of neighbouring rows), cut into pieces of max_bs rows."""
+    pats = [tuple(A.col[A.row_ptr[i]:A.row_ptr[i + 1]]) for i in range(A.nrows)]
+    bounds = [0] + [i for i in range(1, A.nrows) if pats[i] != pats[i - 1]] + [A.nrows]
+    units = []
+    for s, e in zip(bounds[:-1], bounds[1:]):
+        units += [(p, min(e, p + max_bs)) for p in range(s, e, max_bs)]
+    return units
+
+
+def _check_greedy(A, bptr, max_bs):
+    """The three properties that single out the greedy agglomeration: no
+    block exceeds max_bs rows, no unit is split, and every block is maximal
+    (the unit after it would not fit)."""
+    sizes = np.diff(bptr)
+    assert bptr[0] == 0 and bptr[-1] == A.nrows and np.all(sizes >= 1) and np.all(sizes <= max_bs)
+    units = _units(A, max_bs)
+    ustarts = {s: e - s for s, e in units}
+    for t in range(1, bptr.size - 1):
+        assert bptr[t] in ustarts, f"block boundary {bptr[t]} splits a unit"
+        assert sizes[t - 1] + ustarts[bptr[t]] > max_bs, f"block {t - 1} is not maximal"
+
+
+@pytest.mark.parametrize("max_bs", [1, 4, 13, 32])
+def test_supervariable_blocks_on_a_stencil_are_uniform(max_bs):
+    """Every row of a stencil matrix has its own column set, so the rule
+    reduces to consecutive blocks of max_bs rows (the last one shorter)."""
+    A = W.stencil_3d27(6)
+    assert np.array_equal(O.supervariable_blocks(A, max_bs), O.uniform_blocks(A.nrows, max_bs))
+
+
+def test_supervariable_blocks_follow_the_node_structure():
+    """Groups of 1..6 rows with shared column sets: with max_bs = 6 every
+    group is a block of its own unless the next group still fits; with
+    max_bs = 1 the rule gives point Jacobi."""
+    sizes = np.random.default_rng(3).integers(1, 7, 60)
+    A, start = _grouped(list(sizes), 4)
+    for mb in (6, 8, 32):
+        bp = O.supervariable_blocks(A, mb)
+        _check_greedy(A, bp, mb)
+        assert set(bp.tolist()) <= set(start.tolist())     # node boundaries only
+    assert np.array_equal(O.supervariable_blocks(A, 1), np.arange(A.nrows + 1))
+
+
+@pytest.mark.parametrize("seed", [5, 6, 7])
+def test_supervariable_blocks_long_groups_are_cut(seed):
+    """Groups up to 70 rows with max_bs = 16 and 32: long groups are cut into
+    max_bs pieces, and the greedy properties hold."""
+    sizes = np.random.default_rng(seed).integers(1, 71, 12)
+    A, _ = _grouped(list(sizes), seed)
+    for mb in (16, 32):
+        bp = O.supervariable_blocks(A, mb)
+        _check_greedy(A, bp, mb)
+
+
+def test_supervariable_blocks_node_block_workload():
+    A = W.node_block_3d7(6, kmax=6, seed=7)
+    for mb in (8, 32):
+        _check_greedy(A, O.supervariable_blocks(A, mb), mb)
+
+
+def test_supervariable_blocks_empty_and_one_row():
+    E = W.Csr(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert list(O.supervariable_blocks(E, 8)) == [0]
+    one = W.Csr(1, 1, np.array([0, 1], np.int32), np.zeros(1, np.int32), np.ones(1))
+    assert list(O.supervariable_blocks(one, 8)) == [0, 1]
+
+
+def test_variable_blocks_inverses_and_product():
+    """Mixed block sizes: every inverse against numpy.linalg.inv of its
+    diagonal block, cond_1 against numpy, and the product against the dense
+    block-diagonal matrix."""
+    A, _ = _grouped([3, 1, 5, 2, 6, 4, 1, 1, 6], 8)
+    Dn = _dense(A)
+    bp = O.supervariable_blocks(A, 8)
+    assert len(set(np.diff(bp))) > 2
+    inv, cond, prec = O.bj_generate(A, bp, adaptive=False)
+    M = np.zeros_like(Dn)
+    off = 0
+    for b in range(bp.size - 1):
+        r0, m = bp[b], bp[b + 1] - bp[b]
+        D = Dn[r0:r0 + m, r0:r0 + m]
+        Inv = inv[off:off + m * m].reshape(m, m)
+        assert np.allclose(Inv, np.linalg.inv(D), rtol=1e-12, atol=1e-14)
+        assert np.isclose(cond[b], np.linalg.cond(D, 1), rtol=1e-10)
+        M[r0:r0 + m, r0:r0 + m] = Inv
+        off += m * m
+    r = W.uniform_vec(A.nrows, 9)
+    assert np.allclose(O.bj_apply(bp, inv, r), M @ r, rtol=1e-14, atol=1e-15)
+
+
+def test_variable_blocks_reduce_to_uniform_and_exact_cases():
+    """Variable boundaries that happen to be uniform give the uniform
+    preconditioner's solve bit for bit; one block over the whole matrix is
+    exact (one CG step)."""
+    A = W.node_block_3d7(4, kmax=3, seed=2)
+    b = W.uniform_vec(A.nrows, 3)
+    bp = O.supervariable_blocks(W.stencil_3d27(6), 5)[: (A.nrows + 4) // 5 + 1].copy()
+    bp[-1] = A.nrows
+    ub = O.uniform_blocks(A.nrows, 5)
+    assert np.array_equal(bp, ub)
+    i1, _, _ = O.bj_generate(A, bp)
+    i2, _, _ = O.bj_generate(A, ub)
+    r1 = O.pcg_block(A, b, bp, i1, reduction=1e-10)
+    r2 = O.pcg_block(A, b, ub, i2, reduction=1e-10)
+    assert r1["iterations"] == r2["iterations"] and np.array_equal(r1["x"], r2["x"])
+    whole = np.array([0, A.nrows], np.int32)
+    iw, _, _ = O.bj_generate(A, whole, adaptive=False)
+    assert O.pcg_block(A, b, whole, iw, reduction=1e-10)["iterations"] == 1
+
+
+def test_node_respecting_blocks_beat_uniform_blocks():
+    """On the node-block workload, blocks that keep every node whole need
+    fewer CG iterations than uniform blocks of the same maximum size."""
+    A = W.node_block_3d7(8, kmax=6, seed=7)
+    b = W.uniform_vec(A.nrows, 3)
+    its = {}
+    for name, bp in (("uniform", O.uniform_blocks(A.nrows, 32)), ("super", O.supervariable_blocks(A, 32))):
+        inv, _, _ = O.bj_generate(A, bp)
+        r = O.pcg_block(A, b, bp, inv, reduction=1e-10)
+        assert r["stop_reason"] == O.CONVERGED
+        assert np.linalg.norm(b - O.spmv(A, r["x"])) <= 1.01e-10 * np.linalg.norm(b)
+        its[name] = r["iterations"]
+    assert its["super"] < its["uniform"]

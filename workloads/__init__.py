@@ -25,6 +25,9 @@ Workload recipes (all seeds are explicit arguments):
                               banded-random columns, N(0,1) values).
 * ``batch_systems(...)``   -- thousands of small banded, diagonally dominant
                               SPD systems packed in one CSR.
+* ``node_block_3d7(N)``    -- 3D 7-point grid of nodes with 1..6 unknowns
+                              each, dense coupling within and between
+                              neighbouring nodes (variable-size blocks).
 * ``random_sparse(...)``, ``edge_matrices()``, ``convdiff_2d5(N)`` -- small
                               cases for parity and edge tests.
 """
@@ -38,7 +41,7 @@ import numpy as np
 __all__ = [
     "Csr", "stencil_2d5", "stencil_3d27", "aniso_3d7", "convdiff_2d5",
     "uniform_vec", "zipf_suite_params", "zipf_suite_matrix", "batch_systems",
-    "random_sparse", "edge_matrices", "spd_integer_small",
+    "random_sparse", "edge_matrices", "spd_integer_small", "node_block_3d7",
 ]
 
 
@@ -384,6 +387,60 @@ def batch_systems(nsys: int = 10_000, seed: int = 5000, nmin: int = 32,
     b = rng.uniform(-1.0, 1.0, int(sys_ptr[-1]))
     return Batch(nsys, sys_ptr.astype(np.int32), row_ptr.astype(np.int32),
                  np.concatenate(cols), np.concatenate(vals), b)
+
+
+# ------------------------------------------------------ variable node blocks
+def node_block_3d7(N: int, kmax: int = 6, seed: int = 7) -> Csr:
+    """A 3D 7-point grid of N^3 nodes carrying k_v ~ U{1..kmax} unknowns each
+    (seeded), numbered node after node in lexicographic node order.  Every
+    unknown couples to all unknowns of its own node and of the (up to six)
+    neighbouring nodes, so the rows of one node share one column set (a
+    supervariable of k_v rows).  Symmetric values: within a node -U[1, 10),
+    between nodes -U[0.1, 1), drawn once per unordered pair; diagonal = the
+    row's off-diagonal absolute sum + 1e-2 (symmetric, strictly diagonally
+    dominant with a positive diagonal, hence SPD)."""
+    rng = np.random.default_rng(seed)
+    nn = N ** 3
+    k = rng.integers(1, kmax + 1, nn).astype(np.int64)
+    start = np.zeros(nn + 1, np.int64)
+    np.cumsum(k, out=start[1:])
+    n = int(start[-1])
+    node = np.repeat(np.arange(nn), k)                      # node of each unknown
+    ii, jj, kk = node % N, (node // N) % N, node // (N * N)
+    # neighbour nodes in ascending node order: -N^2, -N, -1, 0, +1, +N, +N^2
+    offs = [(-N * N, kk > 0), (-N, jj > 0), (-1, ii > 0), (0, np.ones(n, bool)),
+            (1, ii < N - 1), (N, jj < N - 1), (N * N, kk < N - 1)]
+    cnt = np.zeros(n, np.int64)
+    for o, m in offs:
+        cnt += np.where(m, k[np.clip(node + o, 0, nn - 1)], 0)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(cnt, out=rp[1:])
+    nnz = int(rp[-1])
+    assert nnz < 2**31
+    col = np.empty(nnz, np.int64)
+    pos = rp[:-1].copy()
+    for o, m in offs:
+        rows = np.nonzero(m)[0]
+        nb = node[rows] + o
+        kn = k[nb]
+        tot = int(kn.sum())
+        r_rep = np.repeat(rows, kn)
+        local = np.arange(tot) - np.repeat(np.cumsum(kn) - kn, kn)
+        col[np.repeat(pos[rows], kn) + local] = np.repeat(start[nb], kn) + local
+        pos[rows] += kn
+        del r_rep
+    row = np.repeat(np.arange(n), cnt)
+    lo, hi = np.minimum(row, col), np.maximum(row, col)
+    key = lo * n + hi
+    uniq, inv = np.unique(key, return_inverse=True)
+    same = node[uniq // n] == node[uniq % n]
+    w = np.where(same, rng.uniform(1.0, 10.0, uniq.size), rng.uniform(0.1, 1.0, uniq.size))
+    val = -w[inv]
+    diag = row == col
+    val[diag] = 0.0
+    absum = np.bincount(row, weights=np.abs(val), minlength=n)
+    val[diag] = absum + 1e-2
+    return Csr(n, n, rp.astype(np.int32), col.astype(np.int32), val, f"nodeblock3d7_{N}_k{kmax}")
 
 
 # ------------------------------------------------------------- small / edge
