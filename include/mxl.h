@@ -267,6 +267,29 @@ mxl_status mxl_jacobi_generate(const mxl_op *A, mxl_op **P);
 mxl_status mxl_bjacobi_generate(const mxl_op *A, int32_t block_size, int32_t adaptive,
                                 double accuracy, mxl_op **P);
 
+/* Block-Jacobi with blocks of varying size (Sec. 3.2: the diagonal blocks
+ * are inverted by a batched variable-size Gauss-Jordan elimination).
+ * Boundaries: with bptr_host (HOST int32[nblocks + 1], 0 = bptr[0] <
+ * bptr[1] < ... < bptr[nblocks] = nrows, every block 1 to 32 rows) block b
+ * is rows bptr[b] .. bptr[b+1]-1; with bptr_host == NULL (nblocks ignored)
+ * the library finds them by supervariable agglomeration: runs of
+ * consecutive rows with identical column index sets, each cut into pieces
+ * of at most max_block_size (1..32) rows, are packed in row order into
+ * blocks of at most max_block_size rows, a piece that does not fit
+ * starting the next block (on a matrix whose rows all differ in pattern
+ * this gives uniform blocks of max_block_size rows).  Elimination,
+ * condition numbers, the adaptive storage rule, the product and the solvers
+ * it preconditions are those of mxl_bjacobi_generate.  Errors: INVALID_ARG
+ * (boundaries or max_block_size out of range), NOT_IMPLEMENTED, ZERO_DIAG,
+ * OUT_OF_MEMORY, DEVICE. */
+mxl_status mxl_bjacobi_generate_var(const mxl_op *A, int64_t nblocks, const int32_t *bptr_host,
+                                    int32_t max_block_size, int32_t adaptive, double accuracy,
+                                    mxl_op **P);
+
+/* Block boundaries of a block-Jacobi operator: HOST int32[nblocks + 1]
+ * (nblocks from mxl_bjacobi_info).  Errors: INVALID_ARG. */
+mxl_status mxl_bjacobi_blocks(const mxl_op *P, int32_t *bptr_host);
+
 /* Per-block data of a block-Jacobi operator (HOST outputs, each may be
  * NULL): the number of blocks, cond_1 of every diagonal block, its storage
  * precision (0 binary64, 1 binary32, 2 binary16), the stored inverses as
@@ -348,14 +371,18 @@ mxl_status mxl_solve(const mxl_op *S, const void *b, void *x,
  * rounded to FP32, so the inner solve decouples three precisions
  * (binary16/32/64 inverses, FP32 vectors, FP64 arithmetic).  0 keeps point
  * Jacobi; a zero-initialised tail of this struct is therefore the point
- * Jacobi solver.  Errors: DTYPE (A not FP64), INVALID_ARG (block size not
- * supported), ZERO_DIAG (a singular diagonal block, or a zero diagonal
- * entry for point Jacobi), OUT_OF_MEMORY. */
+ * Jacobi solver.  inner_block_mode 1 takes variable-size blocks found by
+ * supervariable agglomeration with at most inner_block_size rows (as
+ * mxl_bjacobi_generate_var with bptr_host == NULL; any size 1..32); 0 the
+ * uniform blocks.  Errors: DTYPE (A not FP64), INVALID_ARG (block size or
+ * mode not supported), ZERO_DIAG (a singular diagonal block, or a zero
+ * diagonal entry for point Jacobi), OUT_OF_MEMORY. */
 typedef struct {
     mxl_criteria outer;
     mxl_criteria inner;
     int32_t inner_block_size;
     double inner_block_accuracy;
+    int32_t inner_block_mode;
 } mxl_ir_params;
 mxl_status mxl_ir_generate(const mxl_op *A, const mxl_ir_params *params, mxl_op **S);
 

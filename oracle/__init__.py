@@ -93,6 +93,9 @@ def _declare(L):
     L.orc_ir.argtypes = [i64, vp, vp, vp, vp, vp, i64, f64, i64, f64, C.POINTER(_Info), vp]
     L.orc_pcg_f32_block.restype = C.c_int
     L.orc_pcg_f32_block.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, _Crit, C.POINTER(_Info)]
+    L.orc_ir_block_var.restype = C.c_int
+    L.orc_ir_block_var.argtypes = [i64, vp, vp, vp, vp, vp, i64, f64, i64, f64, i64, vp, f64,
+                                   C.POINTER(_Info), vp]
     L.orc_ir_block.restype = C.c_int
     L.orc_ir_block.argtypes = [i64, vp, vp, vp, vp, vp, i64, f64, i64, f64, i32, f64, C.POINTER(_Info), vp]
     L.orc_batch_pcg.argtypes = [i64, vp, vp, vp, vp, vp, vp, f64, i64, vp, vp, vp]
@@ -287,16 +290,22 @@ def pcg_f32_block(A, b32, bptr, inv, max_iters=10_000, reduction=1e-4):
 
 
 def ir(A, b, x0=None, max_outer=50, outer_reduction=1e-12, inner_max_iters=10_000,
-       inner_reduction=1e-4, block_size=0, block_accuracy=0.1):
+       inner_reduction=1e-4, block_size=0, block_accuracy=0.1, bptr=None):
     """Mixed-precision iterative refinement (Sec. 3.2): FP64 residual and
     update, FP32 Jacobi-CG inner solve; block_size > 0 switches the inner
-    preconditioner to adaptive block Jacobi over uniform blocks of that size."""
+    preconditioner to adaptive block Jacobi over uniform blocks of that size,
+    bptr (block boundaries) to adaptive block Jacobi over those blocks."""
     rp, col, val = _csr(A)
     b = _c(b, np.float64)
     x = np.zeros(A.nrows) if x0 is None else _c(x0, np.float64).copy()
     info = _Info()
     hist = np.full(max_outer + 1, np.nan)
-    if block_size > 0:
+    if bptr is not None:
+        bp = _c(bptr, np.int32)
+        lib().orc_ir_block_var(A.nrows, _p(rp), _p(col), _p(val), _p(b), _p(x), max_outer, outer_reduction,
+                               inner_max_iters, inner_reduction, bp.size - 1, _p(bp), block_accuracy,
+                               C.byref(info), _p(hist))
+    elif block_size > 0:
         lib().orc_ir_block(A.nrows, _p(rp), _p(col), _p(val), _p(b), _p(x), max_outer, outer_reduction,
                            inner_max_iters, inner_reduction, block_size, block_accuracy, C.byref(info),
                            _p(hist))

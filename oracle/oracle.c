@@ -781,6 +781,7 @@ done:
 static int ir_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                    const double *b, double *x, int64_t max_outer, double outer_reduction,
                    int64_t inner_max_iters, double inner_reduction, int32_t block_size, double accuracy,
+                   int64_t nb_given, const int32_t *bptr_given,
                    orc_info *info, double *outer_history);
 
 int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
@@ -790,7 +791,7 @@ int orc_ir(int64_t n, const int32_t *row_ptr, const int32_t *col,
            orc_info *info, double *outer_history)
 {
     return ir_core(n, row_ptr, col, val, b, x, max_outer, outer_reduction, inner_max_iters, inner_reduction, 0,
-                   0.0, info, outer_history);
+                   0.0, 0, NULL, info, outer_history);
 }
 
 /* IR whose FP32 inner CG uses block Jacobi: blocks of block_size rows of the
@@ -804,13 +805,24 @@ int orc_ir_block(int64_t n, const int32_t *row_ptr, const int32_t *col,
                  orc_info *info, double *outer_history)
 {
     return ir_core(n, row_ptr, col, val, b, x, max_outer, outer_reduction, inner_max_iters, inner_reduction,
-                   block_size, accuracy, info, outer_history);
+                   block_size, accuracy, 0, NULL, info, outer_history);
+}
+
+/* The same with blocks of varying size: the nblocks blocks of bptr. */
+int orc_ir_block_var(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                     const double *val, const double *b, double *x,
+                     int64_t max_outer, double outer_reduction,
+                     int64_t inner_max_iters, double inner_reduction, int64_t nblocks, const int32_t *bptr,
+                     double accuracy, orc_info *info, double *outer_history)
+{
+    return ir_core(n, row_ptr, col, val, b, x, max_outer, outer_reduction, inner_max_iters, inner_reduction,
+                   1, accuracy, nblocks, bptr, info, outer_history);
 }
 
 static int ir_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                    const double *b, double *x, int64_t max_outer, double outer_reduction,
                    int64_t inner_max_iters, double inner_reduction, int32_t block_size, double accuracy,
-                   orc_info *info, double *outer_history)
+                   int64_t nb_given, const int32_t *bptr_given, orc_info *info, double *outer_history)
 {
     int64_t nnz = row_ptr[n];
     float *v32 = malloc((size_t)(nnz + 1) * sizeof(float));
@@ -828,9 +840,10 @@ static int ir_core(int64_t n, const int32_t *row_ptr, const int32_t *col, const 
     if (orc_jacobi_dinv(n, row_ptr, col, val, dinv) >= 0) { stop = ORC_BREAKDOWN; goto done; }
     for (int64_t i = 0; i < n; ++i) dinv32[i] = (float)dinv[i];
     if (block_size > 0) {
-        nblocks = (n + block_size - 1) / block_size;
+        nblocks = bptr_given ? nb_given : (n + block_size - 1) / block_size;
         bptr = malloc((size_t)(nblocks + 1) * sizeof(int32_t));
-        for (int64_t k = 0; k <= nblocks; ++k) bptr[k] = (int32_t)(k * block_size < n ? k * block_size : n);
+        for (int64_t k = 0; k <= nblocks; ++k)
+            bptr[k] = bptr_given ? bptr_given[k] : (int32_t)(k * block_size < n ? k * block_size : n);
         int64_t tot = 0;
         for (int64_t k = 0; k < nblocks; ++k) tot += (int64_t)(bptr[k + 1] - bptr[k]) * (bptr[k + 1] - bptr[k]);
         inv = malloc((size_t)(tot + 1) * sizeof(double));

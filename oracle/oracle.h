@@ -111,6 +111,11 @@ int orc_pcg_f32(int64_t n, const int32_t *row_ptr, const int32_t *col,
 int orc_pcg_f32_block(int64_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
                       int64_t nblocks, const int32_t *bptr, const double *inv, const float *b, float *x,
                       orc_criteria crit, orc_info *info);
+int orc_ir_block_var(int64_t n, const int32_t *row_ptr, const int32_t *col,
+                     const double *val, const double *b, double *x,
+                     int64_t max_outer, double outer_reduction,
+                     int64_t inner_max_iters, double inner_reduction, int64_t nblocks, const int32_t *bptr,
+                     double accuracy, orc_info *info, double *outer_history);
 int orc_ir_block(int64_t n, const int32_t *row_ptr, const int32_t *col,
                  const double *val, const double *b, double *x,
                  int64_t max_outer, double outer_reduction,

@@ -73,7 +73,7 @@ class OpDesc(C.Structure):
 
 class IrParams(C.Structure):
     _fields_ = [("outer", Criteria), ("inner", Criteria), ("inner_block_size", C.c_int32),
-                ("inner_block_accuracy", C.c_double)]
+                ("inner_block_accuracy", C.c_double), ("inner_block_mode", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -136,6 +136,8 @@ def _load():
         "mxl_stencil_create": [vp, C.c_int, i64, i64, i64, i32, vp, vp, pp],
         "mxl_bjacobi_generate": [vp, i32, i32, f64, pp],
         "mxl_bjacobi_info": [vp, C.POINTER(C.c_int64), vp, vp, vp, C.POINTER(C.c_int64)],
+        "mxl_bjacobi_generate_var": [vp, i64, vp, i32, i32, f64, pp],
+        "mxl_bjacobi_blocks": [vp, vp],
         "mxl_ilu_generate": [vp, i32, i32, i32, pp],
         "mxl_ilu_info": [vp, vp, vp],
         "mxl_selector_destroy": [vp],
@@ -365,9 +367,7 @@ class BlockJacobi(Op):
         inv = None
         ptr_inv = None
         if inverses:
-            d = self.describe()
-            n, bs = d["nrows"], self._bs
-            sizes = np.minimum(bs, n - np.arange(nb.value) * bs)
+            sizes = np.diff(self.blocks()).astype(np.int64)
             inv = np.zeros(max(int((sizes ** 2).sum()), 1))
             ptr_inv = inv.ctypes.data_as(C.c_void_p)
         _check(lib.mxl_bjacobi_info(self.h, C.byref(nb), cond.ctypes.data_as(C.c_void_p),
@@ -377,6 +377,15 @@ class BlockJacobi(Op):
         if inverses:
             out["inv"] = inv
         return out
+
+    def blocks(self):
+        """Block boundaries (int32, nblocks + 1 entries)."""
+        import numpy as np
+        nb = C.c_int64()
+        _check(lib.mxl_bjacobi_info(self.h, C.byref(nb), None, None, None, None))
+        bp = np.zeros(nb.value + 1, np.int32)
+        _check(lib.mxl_bjacobi_blocks(self.h, bp.ctypes.data_as(C.c_void_p)))
+        return bp
 
 
 class Ilu(Op):
@@ -409,9 +418,24 @@ def bjacobi(A: Op, block_size: int = 8, adaptive: bool = True, accuracy: float =
     h = C.c_void_p()
     A.ctx.use_current_stream()
     _check(lib.mxl_bjacobi_generate(A.h, block_size, int(adaptive), accuracy, C.byref(h)))
-    P = BlockJacobi(h, A.ctx, parents=(A,))
-    P._bs = block_size
-    return P
+    return BlockJacobi(h, A.ctx, parents=(A,))
+
+
+def bjacobi_var(A: Op, bptr=None, max_block_size: int = 32, adaptive: bool = True,
+                accuracy: float = 0.1) -> BlockJacobi:
+    """Block Jacobi with blocks of varying size: the given boundaries (int32
+    host array, nblocks + 1 entries) or, with bptr None, supervariable
+    agglomeration with at most max_block_size rows per block."""
+    import numpy as np
+    h = C.c_void_p()
+    A.ctx.use_current_stream()
+    if bptr is None:
+        _check(lib.mxl_bjacobi_generate_var(A.h, 0, None, max_block_size, int(adaptive), accuracy, C.byref(h)))
+    else:
+        bp = np.ascontiguousarray(bptr, np.int32)
+        _check(lib.mxl_bjacobi_generate_var(A.h, bp.size - 1, bp.ctypes.data_as(C.c_void_p), max_block_size,
+                                            int(adaptive), accuracy, C.byref(h)))
+    return BlockJacobi(h, A.ctx, parents=(A,))
 
 
 def criteria(max_iters=10_000, reduction=1e-10, time_limit=0.0, check_every=1,
@@ -615,12 +639,13 @@ class SelectorHandle:
 
 
 def ir(A: Op, outer: dict = None, inner: dict = None, block_size: int = 0,
-       block_accuracy: float = 0.1) -> Solver:
+       block_accuracy: float = 0.1, block_mode: int = 0) -> Solver:
     """FP64-outer / FP32-inner-CG iterative refinement operator; block_size > 0
-    preconditions the inner CG with adaptive block Jacobi."""
+    preconditions the inner CG with adaptive block Jacobi (block_mode 0:
+    uniform blocks, 1: supervariable blocks of at most block_size rows)."""
     o = criteria(**({"max_iters": 50, "reduction": 1e-12} | (outer or {})))
     i = criteria(**({"max_iters": 10_000, "reduction": 1e-4} | (inner or {})))
-    prm = IrParams(o, i, block_size, block_accuracy)
+    prm = IrParams(o, i, block_size, block_accuracy, block_mode)
     h = C.c_void_p()
     A.ctx.use_current_stream()
     _check(lib.mxl_ir_generate(A.h, C.byref(prm), C.byref(h)))

@@ -117,6 +117,12 @@ struct JacobiImpl {
     int64_t nblocks = 0;
     BufPtr bstore, boff, bprec, bcond;
     int64_t bstore_bytes = 0;
+    // variable-size blocks (var): block b holds rows bptr[b] .. bptr[b+1)
+    // (at most 32); its m x m inverse is stored row by row, each row padded
+    // to a whole number of 16-byte chunks; rblk[i] = block of row i
+    bool var = false;
+    BufPtr bptr_d, rblk;
+    std::vector<int32_t> bptr_h;
 };
 
 // ILU-type preconditioner: factors on A's pattern (strict lower = L with
@@ -157,6 +163,7 @@ struct SolverImpl {
     mxl_criteria crit{};
     // work vectors (A's value type)
     BufPtr r, p, q, z, rhat, v, s, t, ones;
+    BufPtr r2;        // CG with variable-size block Jacobi: r alternates between r and r2
     BufPtr state;     // SolverState
     BufPtr partials;  // 3 doubles per slot
     BufPtr hist;      // max_iters + 1 doubles
@@ -280,9 +287,12 @@ hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a,
 // ------------------------------------------------------------- bjacobi.hip
 hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, const void *b,
                       const void *r, void *p, double *parts, hipStream_t s);
-hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, void *r, const void *q,
-                        void *z, SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
-                        hipStream_t s);
+// r_out = r_in - alpha q (r_out == r_in: in place; variable-size blocks
+// need distinct buffers, since a workgroup also reads the rows of blocks
+// that reach into its neighbours' tiles)
+hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, const void *r_in,
+                        void *r_out, const void *q, void *z, SolverState *st, const double *pq_parts, int pq_slots,
+                        double *parts, int k, hipStream_t s);
 hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
                     double beta, void *z, hipStream_t s);
 

@@ -763,6 +763,7 @@ static mxl_status make_solver(int kind, const std::shared_ptr<MatrixImpl> &A,
     if (ok && kind == MXL_SOLVER_BICGSTAB)
         ok = need(S->rhat, vb) && need(S->v, vb) && need(S->s, vb) && need(S->t, vb) && need(S->z, vb);
     if (ok && P && P->block) ok = need(S->z, vb);  // z = M r is kept in memory
+    if (ok && P && P->var && kind == MXL_SOLVER_CG) ok = need(S->r2, vb);
     if (ok && kind == MXL_SOLVER_GMRES) {
         // basis of krylov+1 vectors (ld rounded to 64 rows), z = M^{-1} v,
         // multi-dot partials, norm partials, Hessenberg/rotation workspace
@@ -1012,7 +1013,10 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
         HIP_TRY(spmv_launch(A, a, s));
         timer.end(k);
         if (blockp) {  // r update fused with z = M r; then p = z + beta p (z passed as "r", no scaling)
-            HIP_TRY(bj_cg_update(ctx, *S.P, dt, n, S.r->p, S.q->p, S.z->p, st, pA, gs, pB, (int)k, s));
+            // variable-size blocks: iteration k reads r from rb[(k-1)&1] and writes rb[k&1]
+            void *rin = S.P->var && !(k & 1) ? S.r2->p : S.r->p;
+            void *rout = S.P->var && (k & 1) ? S.r2->p : S.r->p;
+            HIP_TRY(bj_cg_update(ctx, *S.P, dt, n, rin, rout, S.q->p, S.z->p, st, pA, gs, pB, (int)k, s));
             HIP_TRY(cg_pupdate(ctx, dt, n, x, S.z->p, S.p->p, nullptr, st, pB, gv, (int)k, hist, s));
         } else {
             HIP_TRY(cg_update(ctx, dt, n, S.r->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
@@ -1430,11 +1434,15 @@ extern "C" mxl_status mxl_ir_generate(const mxl_op *Aop, const mxl_ir_params *pr
     delete a32;
     hipError_t e;
     std::shared_ptr<JacobiImpl> J32;
+    if (prm->inner_block_mode != 0 && prm->inner_block_mode != 1)
+        return fail(MXL_ERR_INVALID_ARG, "inner_block_mode must be 0 or 1");
     if (prm->inner_block_size > 0) {
         // block Jacobi from the FP64 matrix; usable with the FP32 vectors as is
         mxl_op *bj = nullptr;
-        if ((st = mxl_bjacobi_generate(Aop, prm->inner_block_size, 1, prm->inner_block_accuracy, &bj)) != MXL_OK)
-            return st;
+        st = prm->inner_block_mode == 1
+                 ? mxl_bjacobi_generate_var(Aop, 0, nullptr, prm->inner_block_size, 1, prm->inner_block_accuracy, &bj)
+                 : mxl_bjacobi_generate(Aop, prm->inner_block_size, 1, prm->inner_block_accuracy, &bj);
+        if (st != MXL_OK) return st;
         J32 = bj->jac;
         delete bj;
     } else {

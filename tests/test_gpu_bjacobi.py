@@ -281,3 +281,166 @@ def test_full_size_bicgstab_convdiff128(mxl, ctx, prec):
     assert abs(info["iterations"] - g["iterations"]) <= 2
     rel = np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) / np.linalg.norm(b)
     assert rel <= 2e-10
+
+
+# ----------------------------------------------------- variable-size blocks
+def _mixed_bptr(n, seed):
+    """Boundaries with sizes drawn from 1..32 (every size class present)."""
+    rng = np.random.default_rng(seed)
+    sizes = []
+    while sum(sizes) < n:
+        sizes.append(int(rng.choice([1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32])))
+    sizes[-1] -= sum(sizes) - n
+    if sizes[-1] == 0:
+        sizes.pop()
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+
+
+VAR_MATS = [W.node_block_3d7(5, 6, 7), W.node_block_3d7(12, 6, 7), W.node_block_3d7(4, 12, 3), _dd(300, 0.05, 5), W.aniso_3d7(9)]
+
+
+@pytest.mark.parametrize("adaptive", [False, True], ids=["fp64", "adaptive"])
+@pytest.mark.parametrize("rule", ["super8", "super32", "given"])
+@pytest.mark.parametrize("A", VAR_MATS, ids=[a.name for a in VAR_MATS])
+def test_var_generation_parity(mxl, ctx, A, rule, adaptive):
+    """Variable-size blocks: the boundaries (supervariable agglomeration or
+    given), inverses, cond_1 and storage precisions equal the oracle's bit
+    for bit; the product z = M r agrees to FP64 rounding."""
+    if rule == "given":
+        bp = _mixed_bptr(A.nrows, 11)
+        P = mxl.bjacobi_var(matrix(mxl, ctx, A), bp, adaptive=adaptive)
+    else:
+        mb = int(rule[5:])
+        bp = O.supervariable_blocks(A, mb)
+        P = mxl.bjacobi_var(matrix(mxl, ctx, A), None, mb, adaptive=adaptive)
+    assert np.array_equal(P.blocks(), bp)
+    inv, cond, prec = O.bj_generate(A, bp, adaptive=adaptive, accuracy=0.1)
+    info = P.info(inverses=True)
+    assert info["nblocks"] == bp.size - 1
+    assert np.array_equal(info["cond"], cond)
+    assert np.array_equal(info["precision"], prec)
+    assert np.array_equal(info["inv"], inv)
+    sizes = np.diff(bp).astype(np.int64)
+    per = np.where(prec == O.P16, 2, np.where(prec == O.P32, 4, 8))
+    chunks = (sizes * per + 15) // 16
+    assert info["storage_bytes"] == int((sizes * chunks * 16).sum())
+    r = W.uniform_vec(A.nrows, 9)
+    want = O.bj_apply(bp, inv, r)
+    absz = O.bj_apply(bp, np.abs(inv), np.abs(r))
+    z = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
+    P.apply(dev(r), z)
+    assert np.all(np.abs(z.cpu().numpy() - want) <= 1e-14 * absz + 1e-300)
+
+
+def test_var_apply_nan_stays_in_its_block(mxl, ctx):
+    """A NaN in r reaches exactly the rows of its own block (the padding of a
+    stored row never multiplies a neighbouring block's entry)."""
+    A = _dd(200, 0.05, 6)
+    bp = _mixed_bptr(A.nrows, 12)
+    P = mxl.bjacobi_var(matrix(mxl, ctx, A), bp, adaptive=True)
+    r = W.uniform_vec(A.nrows, 3)
+    k = int(bp[len(bp) // 2]) + 1
+    r[k] = np.nan
+    z = torch.empty(A.nrows, dtype=torch.float64, device=DEV)
+    P.apply(dev(r), z)
+    blk = np.searchsorted(bp, k, side="right") - 1
+    nan_rows = np.nonzero(np.isnan(z.cpu().numpy()))[0]
+    assert np.array_equal(nan_rows, np.arange(bp[blk], bp[blk + 1]))
+
+
+def test_var_errors(mxl, ctx):
+    A = matrix(mxl, ctx, W.stencil_2d5(8))
+    for bad in ([0, 10, 64], [0, 33, 64], [1, 32, 64], [0, 32, 63], [0, 32, 32, 64]):
+        with pytest.raises(mxl.MxlError) as e:
+            mxl.bjacobi_var(A, np.array(bad, np.int32))
+        assert e.value.status == mxl.ERR_INVALID_ARG, bad
+    for mb in (0, 33):
+        with pytest.raises(mxl.MxlError) as e:
+            mxl.bjacobi_var(A, None, mb)
+        assert e.value.status == mxl.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("rule", ["super32", "given"])
+def test_var_block_cg_matches_oracle(mxl, ctx, rule):
+    """CG with variable-size blocks (the fused r update and block product
+    reading 31 rows beyond each tile, r double-buffered) against the
+    oracle's block CG: counts within 2, FP64 residual; also bitwise
+    independent of check_every."""
+    A = W.node_block_3d7(10, 6, 7)
+    b = W.uniform_vec(A.nrows, 4)
+    bp = O.supervariable_blocks(A, 32) if rule == "super32" else _mixed_bptr(A.nrows, 13)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=True)
+    ref = O.pcg_block(A, b, bp, inv, reduction=1e-10)
+    M = matrix(mxl, ctx, A)
+    P = mxl.bjacobi_var(M, None if rule == "super32" else bp, 32, True)
+    xs = []
+    for ce in (1, 16):
+        S = mxl.solver("cg", M, P, max_iters=3000, reduction=1e-10, check_every=ce)
+        x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+        info = S.solve(dev(b), x)
+        print(f"[var cg {rule} ce {ce}] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
+        assert info["stop_reason"] == mxl.STOP_CONVERGED
+        assert abs(info["iterations"] - ref["iterations"]) <= 2
+        assert np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) <= 1.01e-10 * np.linalg.norm(b)
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1])
+
+
+def test_var_blocks_beat_uniform_on_node_blocks(mxl, ctx):
+    """On the node-block workload, supervariable blocks need fewer CG
+    iterations than uniform blocks of 32 rows (as in the oracle)."""
+    A = W.node_block_3d7(10, 6, 7)
+    b = dev(W.uniform_vec(A.nrows, 4))
+    M = matrix(mxl, ctx, A).convert("ell")
+    its = {}
+    for name, P in (("uniform", mxl.bjacobi(M, 32, True)), ("super", mxl.bjacobi_var(M, None, 32, True))):
+        x = torch.zeros_like(b)
+        its[name] = mxl.solver("cg", M, P, max_iters=3000, reduction=1e-10, check_every=8).solve(b, x)["iterations"]
+    assert its["super"] < its["uniform"], its
+
+
+def test_var_block_bicgstab_and_gmres_match_oracle(mxl, ctx):
+    """BiCGSTAB and GMRES(30) with variable-size blocks against the oracle:
+    counts within 2, FP64 residual."""
+    A = W.node_block_3d7(8, 6, 7)
+    b = W.uniform_vec(A.nrows, 5)
+    bp = O.supervariable_blocks(A, 32)
+    inv, _, _ = O.bj_generate(A, bp, adaptive=True)
+    M = matrix(mxl, ctx, A)
+    P = mxl.bjacobi_var(M, None, 32, True)
+    ref = O.bicgstab_block(A, b, bp, inv, reduction=1e-10)
+    S = mxl.solver("bicgstab", M, P, max_iters=3000, reduction=1e-10, launch_mode=1)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[var bicgstab] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["iterations"]) <= 2
+    assert np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) <= 2e-10 * np.linalg.norm(b)
+    refg = O.gmres(A, b, krylov_dim=30, reduction=1e-10, bptr=bp, inv=inv)
+    G = mxl.solver("gmres", M, P, krylov_dim=30, max_iters=3000, reduction=1e-10)
+    x.zero_()
+    info = G.solve(dev(b), x)
+    print(f"[var gmres] gpu {info['iterations']} oracle {refg['iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - refg["iterations"]) <= 2
+    assert np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) <= 1.01e-10 * np.linalg.norm(b)
+
+
+def test_var_block_ir_matches_oracle(mxl, ctx):
+    """Refinement whose FP32 inner CG uses supervariable blocks (mode 1):
+    corrections within 1 and inner iterations within 5 % of the oracle's,
+    FP64 residual <= 1e-12."""
+    A = W.node_block_3d7(8, 6, 7)
+    b = W.uniform_vec(A.nrows, 5)
+    ref = O.ir(A, b, outer_reduction=1e-12, inner_reduction=1e-4, bptr=O.supervariable_blocks(A, 32))
+    M = matrix(mxl, ctx, A)
+    S = mxl.ir(M, outer=dict(max_iters=50, reduction=1e-12), inner=dict(reduction=1e-4, max_iters=10_000),
+               block_size=32, block_mode=1)
+    x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    print(f"[var ir] gpu {info['iterations']}/{info['inner_iterations']} oracle "
+          f"{ref['outer']}/{ref['inner_iterations']}", flush=True)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["outer"]) <= 1
+    assert abs(info["inner_iterations"] - ref["inner_iterations"]) <= max(4, 0.05 * ref["inner_iterations"])
+    assert np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) <= 1e-12 * np.linalg.norm(b)

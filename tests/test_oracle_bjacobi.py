@@ -392,3 +392,20 @@ def test_node_respecting_blocks_beat_uniform_blocks():
         assert np.linalg.norm(b - O.spmv(A, r["x"])) <= 1.01e-10 * np.linalg.norm(b)
         its[name] = r["iterations"]
     assert its["super"] < its["uniform"]
+
+
+def test_ir_with_given_blocks_reduces_to_uniform():
+    """Refinement with given block boundaries equal to uniform blocks is the
+    uniform-block refinement bit for bit; with supervariable blocks on the
+    node-block workload it reaches 1e-12 in the recomputed FP64 residual."""
+    A = W.aniso_3d7(10)
+    b = W.uniform_vec(A.nrows, 4)
+    r1 = O.ir(A, b, outer_reduction=1e-12, block_size=8)
+    r2 = O.ir(A, b, outer_reduction=1e-12, bptr=O.uniform_blocks(A.nrows, 8))
+    assert r1["outer"] == r2["outer"] and r1["inner_iterations"] == r2["inner_iterations"]
+    assert np.array_equal(r1["x"], r2["x"])
+    B = W.node_block_3d7(6, kmax=6, seed=7)
+    bb = W.uniform_vec(B.nrows, 5)
+    r = O.ir(B, bb, outer_reduction=1e-12, bptr=O.supervariable_blocks(B, 32))
+    assert r["stop_reason"] == O.CONVERGED
+    assert np.linalg.norm(bb - O.spmv(B, r["x"])) <= 1e-12 * np.linalg.norm(bb)
