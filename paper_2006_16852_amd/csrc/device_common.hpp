@@ -136,17 +136,36 @@ __device__ __forceinline__ void publish(double (&v)[NV], double *partials, int s
 // slots [0, nslots) (fixed striding, fixed tree), so a consumer kernel can
 // take the same scalar decisions in all of its workgroups without any
 // inter-workgroup communication.
+// A thread's slots are t, t + 256, t + 512, ...; they are loaded kGatherU at
+// a time before any is added, so one round trip to L2 serves kGatherU slots
+// (a loop that adds each value as it arrives waits once per slot), and then
+// added in slot order, so the sum does not depend on kGatherU.
+constexpr int kGatherU = 16;
+
 template <int NV>
 __device__ __forceinline__ void gather_all(const double *__restrict__ partials, int nslots,
                                            double (&tot)[NV], unsigned max_mask = 0) {
     __shared__ double bc[NV > 0 ? NV : 1];
 #pragma unroll
     for (int j = 0; j < NV; ++j) tot[j] = 0.0;
-    for (int s = threadIdx.x; s < nslots; s += kWG) {
+    for (int s0 = threadIdx.x; s0 < nslots; s0 += kGatherU * kWG) {
+        double buf[kGatherU][NV > 0 ? NV : 1];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            double v = partials[(int64_t)s * NV + j];
-            tot[j] = (max_mask >> j & 1) ? (v > tot[j] ? v : tot[j]) : tot[j] + v;
+        for (int u = 0; u < kGatherU; ++u) {
+            const int s = s0 + u * kWG;
+            const int sc = s < nslots ? s : nslots - 1;  // in bounds, so the loads need no branch
+#pragma unroll
+            for (int j = 0; j < NV; ++j) buf[u][j] = partials[(int64_t)sc * NV + j];
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherU; ++u) {
+            const bool in = s0 + u * kWG < nslots;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const double v = buf[u][j];
+                const double t = (max_mask >> j & 1) ? (v > tot[j] ? v : tot[j]) : tot[j] + v;
+                tot[j] = in ? t : tot[j];
+            }
         }
     }
     block_reduce<NV>(tot, max_mask);

@@ -8,6 +8,8 @@
 // the scalar reduces the partials in its prologue, identically in every
 // workgroup (device_common.hpp).  Dot products of FP32 vectors multiply
 // exactly in FP64 and accumulate in FP64.
+#include <initializer_list>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -74,15 +76,72 @@ __global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict_
 // reduction instead of every workgroup paying the two in sequence.
 constexpr int kPf = 4;
 
-#define MXL_PF_INDEX(u)                                        \
+#define MXL_PF_INDEX(u, cnt)                                   \
     const int64_t t_##u = tb_ + (int64_t)(u) * ts_;             \
     const int64_t i_##u = t_##u * kWG + threadIdx.x;            \
-    const bool in_##u = t_##u < te_ && i_##u < n;
+    const bool in_##u = t_##u < te_ && i_##u < (cnt);
+
+// A thread of the CG update kernels owns chunks of E consecutive elements:
+// E = 2 for FP32 vectors (one 8-byte load per array, as wide as an FP64
+// element), E = 1 for FP64.  Chunk c holds elements cE .. cE + E - 1; the
+// last chunk may run past n and is then loaded and stored element-wise.
+template <typename V, int E>
+struct Chunk {
+    V v[E];
+};
+
+template <typename V, int E>
+__device__ __forceinline__ Chunk<V, E> fill_chunk(V a) {
+    Chunk<V, E> o;
+#pragma unroll
+    for (int e = 0; e < E; ++e) o.v[e] = a;
+    return o;
+}
+
+template <typename V, int E>
+__device__ __forceinline__ Chunk<V, E> ld_chunk(const V *__restrict__ p, int64_t c, int64_t n) {
+    Chunk<V, E> o;
+    const int64_t i0 = c * E;
+    if constexpr (E == 1) {
+        o.v[0] = p[i0];
+    } else {
+        typedef V VE __attribute__((ext_vector_type(E)));
+        if (i0 + E <= n) {
+            const VE t = *(const VE *)(p + i0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) o.v[e] = t[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) o.v[e] = i0 + e < n ? p[i0 + e] : (V)0;
+        }
+    }
+    return o;
+}
+
+template <typename V, int E>
+__device__ __forceinline__ void st_chunk(V *__restrict__ p, int64_t c, int64_t n, const Chunk<V, E> &o) {
+    const int64_t i0 = c * E;
+    if constexpr (E == 1) {
+        p[i0] = o.v[0];
+    } else {
+        typedef V VE __attribute__((ext_vector_type(E)));
+        if (i0 + E <= n) {
+            VE t;
+#pragma unroll
+            for (int e = 0; e < E; ++e) t[e] = o.v[e];
+            *(VE *)(p + i0) = t;
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (i0 + e < n) p[i0 + e] = o.v[e];
+        }
+    }
+}
 
 // Consumes p.q (fused into the SpMV): alpha = rho_{k-1} / p.q, then
 // r -= alpha q and the reductions r.z, r.r.  The matching x += alpha p is
 // applied by k_cg_pupdate, which reads p anyway, so p is read once less.
-template <typename V>
+template <typename V, int E>
 __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r, const V *__restrict__ q,
                                                    const V *__restrict__ dinv, SolverState *st,
                                                    const double *__restrict__ pq_parts, int pq_slots,
@@ -91,14 +150,16 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r,
         if (MXL_LEAD) st->ustop = 1;
         return;
     }
-    MXL_RANGE(n)
-    V rv[kPf], qv[kPf], dv[kPf];
+    typedef Chunk<V, E> CV;
+    const int64_t nc = (n + E - 1) / E;
+    MXL_RANGE(nc)
+    CV rv[kPf], qv[kPf], dv[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
-        rv[u] = in_u ? r[i_u] : (V)0;
-        qv[u] = in_u ? q[i_u] : (V)0;
-        dv[u] = in_u && dinv ? dinv[i_u] : (V)1;
+        MXL_PF_INDEX(u, nc)
+        rv[u] = in_u ? ld_chunk<V, E>(r, i_u, n) : fill_chunk<V, E>(0);
+        qv[u] = in_u ? ld_chunk<V, E>(q, i_u, n) : fill_chunk<V, E>(0);
+        dv[u] = in_u && dinv ? ld_chunk<V, E>(dinv, i_u, n) : fill_chunk<V, E>(1);
     }
     double eta[1];
     gather_all<1>(pq_parts, pq_slots, eta);
@@ -120,29 +181,38 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r,
         st->ustop = 0;
     }
     double rz = 0.0, rr = 0.0;
-    auto step = [&](int64_t i, V r0, V q0, V d0) {
-        V ri;
-        if constexpr (sizeof(V) == 8) ri = r0 - alpha * q0;
-        else ri = (V)((double)r0 - alpha * (double)q0);
-        r[i] = ri;
-        const double z = dinv ? (double)d0 * (double)ri : (double)ri;
-        rz += (double)ri * z;
-        rr += (double)ri * (double)ri;
+    auto step = [&](int64_t c, const CV &r0, const CV &q0, const CV &d0) {
+        CV ro;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            V ri;
+            if constexpr (sizeof(V) == 8) ri = r0.v[e] - alpha * q0.v[e];
+            else ri = (V)((double)r0.v[e] - alpha * (double)q0.v[e]);
+            ro.v[e] = ri;
+            if (E == 1 || c * E + e < n) {
+                const double z = dinv ? (double)d0.v[e] * (double)ri : (double)ri;
+                rz += (double)ri * z;
+                rr += (double)ri * (double)ri;
+            }
+        }
+        st_chunk<V, E>(r, c, n, ro);
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, nc)
         if (in_u) step(i_u, rv[u], qv[u], dv[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
-        if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(i, r[i], q[i], dinv ? dinv[i] : (V)1);
+        if (const int64_t c = t_ * kWG + threadIdx.x; c < nc)
+            step(c, ld_chunk<V, E>(r, c, n), ld_chunk<V, E>(q, c, n),
+                 dinv ? ld_chunk<V, E>(dinv, c, n) : fill_chunk<V, E>(1));
     double v[2] = {rz, rr};
     publish<2>(v, parts, L);
 }
 
 // Consumes r.z and r.r: x += alpha p (alpha from k_cg_update), the
 // criterion of iteration k, then p = z + beta p unless the solve stops.
-template <typename V>
+template <typename V, int E>
 __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x, const V *__restrict__ r,
                                                     V *__restrict__ p, const V *__restrict__ dinv,
                                                     SolverState *st, const double *__restrict__ parts,
@@ -150,15 +220,17 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     // k_cg_update saw an earlier stop or broke down: x is not advanced.  The
     // stop this kernel decides goes to st->stop, which it never reads.
     if (st->ustop) return;
-    MXL_RANGE(n)
-    V xv[kPf], rv[kPf], pv[kPf], dv[kPf];
+    typedef Chunk<V, E> CV;
+    const int64_t nc = (n + E - 1) / E;
+    MXL_RANGE(nc)
+    CV xv[kPf], rv[kPf], pv[kPf], dv[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
-        xv[u] = in_u ? x[i_u] : (V)0;
-        rv[u] = in_u ? r[i_u] : (V)0;
-        pv[u] = in_u ? p[i_u] : (V)0;
-        dv[u] = in_u && dinv ? dinv[i_u] : (V)1;
+        MXL_PF_INDEX(u, nc)
+        xv[u] = in_u ? ld_chunk<V, E>(x, i_u, n) : fill_chunk<V, E>(0);
+        rv[u] = in_u ? ld_chunk<V, E>(r, i_u, n) : fill_chunk<V, E>(0);
+        pv[u] = in_u ? ld_chunk<V, E>(p, i_u, n) : fill_chunk<V, E>(0);
+        dv[u] = in_u && dinv ? ld_chunk<V, E>(dinv, i_u, n) : fill_chunk<V, E>(1);
     }
     double t[2];
     gather_all<2>(parts, slots, t);
@@ -173,19 +245,27 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     else if (rz == 0.0) stop = ST_BREAKDOWN;
     const double beta = rz / st->rho2[(k - 1) & 1];
     const bool run = stop == ST_RUN;
-    auto step = [&](int64_t i, V x0, V r0, V p0, V d0) {
-        if constexpr (sizeof(V) == 8) x[i] = x0 + alpha * p0;
-        else x[i] = (V)((double)x0 + alpha * (double)p0);
-        if (run) p[i] = (V)((dinv ? (double)d0 * (double)r0 : (double)r0) + beta * (double)p0);
+    auto step = [&](int64_t c, const CV &x0, const CV &r0, const CV &p0, const CV &d0) {
+        CV xo, po;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if constexpr (sizeof(V) == 8) xo.v[e] = x0.v[e] + alpha * p0.v[e];
+            else xo.v[e] = (V)((double)x0.v[e] + alpha * (double)p0.v[e]);
+            po.v[e] = (V)((dinv ? (double)d0.v[e] * (double)r0.v[e] : (double)r0.v[e]) + beta * (double)p0.v[e]);
+        }
+        st_chunk<V, E>(x, c, n, xo);
+        if (run) st_chunk<V, E>(p, c, n, po);
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, nc)
         if (in_u) step(i_u, xv[u], rv[u], pv[u], dv[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
-        if (const int64_t i = t_ * kWG + threadIdx.x; i < n)
-            step(i, x[i], run ? r[i] : (V)0, p[i], run && dinv ? dinv[i] : (V)1);
+        if (const int64_t c = t_ * kWG + threadIdx.x; c < nc)
+            step(c, ld_chunk<V, E>(x, c, n), run ? ld_chunk<V, E>(r, c, n) : fill_chunk<V, E>(0),
+                 ld_chunk<V, E>(p, c, n),
+                 run && dinv ? ld_chunk<V, E>(dinv, c, n) : fill_chunk<V, E>(1));
     if (MXL_LEAD) {
         st->rr = rr;
         st->iters = k;
@@ -198,7 +278,7 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     }
 }
 
-// ------------------------------------------------------------ BiCGSTAB
+// ---------------------------------------------------------------- BiCGSTAB
 template <typename V>
 __global__ __launch_bounds__(kWG) void k_bi_init(int64_t n, const V *__restrict__ b,
                                                  const V *__restrict__ r, V *__restrict__ rhat,
@@ -232,7 +312,7 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
     V rv[kPf], pv[kPf], vv[kPf], dv[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         rv[u] = in_u ? r[i_u] : (V)0;
         pv[u] = in_u ? p[i_u] : (V)0;
         vv[u] = in_u ? v[i_u] : (V)0;
@@ -276,7 +356,7 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         if (in_u) step(i_u, rv[u], pv[u], vv[u], dv[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
@@ -296,7 +376,7 @@ __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restri
     V r_[kPf], v_[kPf], d_[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         r_[u] = in_u ? r[i_u] : (V)0;
         v_[u] = in_u ? v[i_u] : (V)0;
         d_[u] = in_u && dinv ? dinv[i_u] : (V)1;
@@ -323,7 +403,7 @@ __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restri
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         if (in_u) step(i_u, r_[u], v_[u], d_[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
@@ -343,7 +423,7 @@ __global__ __launch_bounds__(kWG) void k_bi_tdots(int64_t n, const V *__restrict
     V t_v[kPf], s_v[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         t_v[u] = in_u ? t[i_u] : (V)0;
         s_v[u] = in_u ? s[i_u] : (V)0;
     }
@@ -368,7 +448,7 @@ __global__ __launch_bounds__(kWG) void k_bi_tdots(int64_t n, const V *__restrict
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         if (in_u) step(t_v[u], s_v[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
@@ -402,7 +482,7 @@ __global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x
     V xv[kPf], ph[kPf], sh[kPf], sv[kPf], tv[kPf], rh[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         xv[u] = in_u ? x[i_u] : (V)0;
         ph[u] = in_u ? phat[i_u] : (V)0;
         sh[u] = in_u ? shat[i_u] : (V)0;
@@ -434,7 +514,7 @@ __global__ __launch_bounds__(kWG) void k_bi_xupdate(int64_t n, V *__restrict__ x
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u)
+        MXL_PF_INDEX(u, n)
         if (in_u) step(i_u, xv[u], ph[u], sh[u], sv[u], tv[u], rh[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
@@ -651,19 +731,43 @@ hipError_t cg_init(const mxl_ctx *ctx, int dtype, int64_t n, const void *b, cons
     return hipGetLastError();
 }
 
+// FP32 vectors move two elements per thread when every vector the kernel
+// touches is 8-byte aligned (a caller's x may be an odd offset view).
+static bool aligned8(std::initializer_list<const void *> ps) {
+    for (const void *p : ps)
+        if (p && ((uintptr_t)p & 7u)) return false;
+    return true;
+}
+
 hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *r, const void *q, const void *dinv,
                      SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
                      hipStream_t s) {
-    MXL_LAUNCH_V(dtype, k_cg_update, vec_grid(ctx, n), n, (V *)r, (const V *)q, (const V *)dinv, st,
-                 pq_parts, pq_slots, parts, k);
+    const dim3 g(vec_grid(ctx, n)), b(kWG);
+    if (dtype == MXL_F64)
+        hipLaunchKernelGGL((k_cg_update<double, 1>), g, b, 0, s, n, (double *)r, (const double *)q,
+                           (const double *)dinv, st, pq_parts, pq_slots, parts, k);
+    else if (aligned8({r, q, dinv}))
+        hipLaunchKernelGGL((k_cg_update<float, 2>), g, b, 0, s, n, (float *)r, (const float *)q,
+                           (const float *)dinv, st, pq_parts, pq_slots, parts, k);
+    else
+        hipLaunchKernelGGL((k_cg_update<float, 1>), g, b, 0, s, n, (float *)r, (const float *)q,
+                           (const float *)dinv, st, pq_parts, pq_slots, parts, k);
     return hipGetLastError();
 }
 
 hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, void *x, const void *r, void *p,
                       const void *dinv, SolverState *st, const double *parts, int slots, int k,
                       double *hist, hipStream_t s) {
-    MXL_LAUNCH_V(dtype, k_cg_pupdate, vec_grid(ctx, n), n, (V *)x, (const V *)r, (V *)p, (const V *)dinv,
-                 st, parts, slots, k, hist);
+    const dim3 g(vec_grid(ctx, n)), b(kWG);
+    if (dtype == MXL_F64)
+        hipLaunchKernelGGL((k_cg_pupdate<double, 1>), g, b, 0, s, n, (double *)x, (const double *)r,
+                           (double *)p, (const double *)dinv, st, parts, slots, k, hist);
+    else if (aligned8({x, r, p, dinv}))
+        hipLaunchKernelGGL((k_cg_pupdate<float, 2>), g, b, 0, s, n, (float *)x, (const float *)r,
+                           (float *)p, (const float *)dinv, st, parts, slots, k, hist);
+    else
+        hipLaunchKernelGGL((k_cg_pupdate<float, 1>), g, b, 0, s, n, (float *)x, (const float *)r,
+                           (float *)p, (const float *)dinv, st, parts, slots, k, hist);
     return hipGetLastError();
 }
 
