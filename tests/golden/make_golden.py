@@ -8,6 +8,7 @@ oracle needs minutes at these sizes.  Run from the repository root:
     python tests/golden/make_golden.py gmres      # only the GMRES entry
     python tests/golden/make_golden.py ilu        # only the ILU-GMRES entry
     python tests/golden/make_golden.py bicgstab   # only the BiCGSTAB entries
+    python tests/golden/make_golden.py bicgstab_spread  # their rounding spread
 """
 import json
 import os
@@ -105,7 +106,45 @@ def bicgstab(out):
         print("bicgstab convdiff bjacobi", bs, r["iterations"], time.time() - t, flush=True)
 
 
-ONLY = {"bjacobi": bjacobi, "gmres": gmres, "ilu": ilu, "bicgstab": bicgstab}
+def bicgstab_spread(out, nperturb=6):
+    """How far rounding alone moves BiCGSTAB's iteration count on the four
+    128^3 systems above: the oracle's counts when b is perturbed at rounding
+    level, b_i (1 + 4e-16 g_i) with g ~ N(0,1) (seeds 1..nperturb), and the
+    first 31 entries of the unperturbed residual history (relative
+    recurrence-residual norms), which rounding has not yet amplified."""
+    import numpy as np
+
+    def runs(key, solve, b):
+        t = time.time()
+        r = solve(b, True)
+        counts = []
+        for seed in range(1, nperturb + 1):
+            g = np.random.default_rng(seed).standard_normal(b.size)
+            counts.append(int(solve(b * (1.0 + 4e-16 * g), False)["iterations"]))
+        out[key]["history_head"] = [float(v) for v in r["history"][:31]]
+        out[key]["perturbed_counts"] = counts
+        out[key]["perturbation"] = "b_i (1 + 4e-16 g_i), g ~ N(0,1) seeds 1..%d" % nperturb
+        print(key, r["iterations"], counts, time.time() - t, flush=True)
+
+    A = W.stencil_3d27(128)
+    b = O.spmv(A, W.uniform_vec(A.nrows, 2))
+    d, _ = O.jacobi_dinv(A)
+    runs("stencil27_128_bicgstab_1e-10",
+         lambda bb, h: O.bicgstab(A, bb, dinv=d, reduction=1e-10, max_iters=5000, history=h), b)
+    del A, b, d
+    A = W.convdiff_3d7(128)
+    b = W.uniform_vec(A.nrows, 5)
+    d, _ = O.jacobi_dinv(A)
+    runs("convdiff3d7_128_bicgstab_jacobi_1e-10",
+         lambda bb, h: O.bicgstab(A, bb, dinv=d, reduction=1e-10, max_iters=5000, history=h), b)
+    for bs in (8, 32):
+        bp = O.uniform_blocks(A.nrows, bs)
+        inv, _, _ = O.bj_generate(A, bp, adaptive=True, accuracy=0.1)
+        runs(f"convdiff3d7_128_bicgstab_bjacobi{bs}_1e-10",
+             lambda bb, h: O.bicgstab_block(A, bb, bp, inv, reduction=1e-10, max_iters=5000, history=h), b)
+
+
+ONLY = {"bjacobi": bjacobi, "gmres": gmres, "ilu": ilu, "bicgstab": bicgstab, "bicgstab_spread": bicgstab_spread}
 
 
 def main():
@@ -148,6 +187,7 @@ def main():
     gmres(out)
     ilu(out)
     bicgstab(out)
+    bicgstab_spread(out)
     json.dump(out, open(path, "w"), indent=1)
     print("wrote", path)
 

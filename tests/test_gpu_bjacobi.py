@@ -16,7 +16,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests._gpu import DEV, dev, matrix
+from tests._gpu import assert_bicgstab_tracks_oracle, DEV, dev, matrix
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -264,7 +264,9 @@ def test_full_size_bicgstab_convdiff128(mxl, ctx, prec):
     Jacobi and with block Jacobi of 8- and 32-row blocks (adaptive storage),
     on ELL16 with check_every 16 as benchmarked: the many-workgroup
     reductions and the block products after a device-side stop are covered.
-    Counts within 2 of the oracle's stored counts; FP64 residual."""
+    The first ten residuals match the oracle's; the count lies within the
+    oracle's own spread under rounding-level changes of b (widened by 2);
+    FP64 residual."""
     g = json.load(open(os.path.join(GOLD, "solver_counts.json")))[f"convdiff3d7_128_bicgstab_{prec}_1e-10"]
     A = W.convdiff_3d7(128)
     b = W.uniform_vec(A.nrows, 5)
@@ -275,10 +277,11 @@ def test_full_size_bicgstab_convdiff128(mxl, ctx, prec):
         assert [int((P.info()["precision"] == k).sum()) for k in (0, 1, 2)] == g["precision_counts"]
     S = mxl.solver("bicgstab", M, P, max_iters=5000, reduction=1e-10, check_every=16)
     x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
-    info = S.solve(dev(b), x)
-    print(f"[bicgstab convdiff128 {prec}] gpu {info['iterations']} oracle {g['iterations']}", flush=True)
+    info = S.solve(dev(b), x, history=5001)
+    print(f"[bicgstab convdiff128 {prec}] gpu {info['iterations']} oracle {g['iterations']} "
+          f"perturbed oracle {g['perturbed_counts']}", flush=True)
     assert info["stop_reason"] == mxl.STOP_CONVERGED
-    assert abs(info["iterations"] - g["iterations"]) <= 2
+    assert_bicgstab_tracks_oracle(info, g)
     rel = np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) / np.linalg.norm(b)
     assert rel <= 2e-10
 
@@ -400,21 +403,29 @@ def test_var_blocks_beat_uniform_on_node_blocks(mxl, ctx):
 
 
 def test_var_block_bicgstab_and_gmres_match_oracle(mxl, ctx):
-    """BiCGSTAB and GMRES(30) with variable-size blocks against the oracle:
-    counts within 2, FP64 residual."""
+    """BiCGSTAB and GMRES(30) with variable-size blocks against the oracle.
+    BiCGSTAB: the first ten residuals match the oracle's and the count lies
+    within the oracle's own spread when b changes at rounding level (53..62
+    around 55 on this system: the method fixes the count only up to
+    rounding); GMRES: count within 2.  FP64 residuals."""
     A = W.node_block_3d7(8, 6, 7)
     b = W.uniform_vec(A.nrows, 5)
     bp = O.supervariable_blocks(A, 32)
     inv, _, _ = O.bj_generate(A, bp, adaptive=True)
     M = matrix(mxl, ctx, A)
     P = mxl.bjacobi_var(M, None, 32, True)
-    ref = O.bicgstab_block(A, b, bp, inv, reduction=1e-10)
+    ref = O.bicgstab_block(A, b, bp, inv, reduction=1e-10, history=True)
+    spread = [O.bicgstab_block(A, b * (1.0 + 4e-16 * np.random.default_rng(s).standard_normal(b.size)),
+                               bp, inv, reduction=1e-10)["iterations"] for s in range(1, 21)]
+    g = {"iterations": ref["iterations"], "perturbed_counts": spread,
+         "history_head": list(ref["history"][:31])}
     S = mxl.solver("bicgstab", M, P, max_iters=3000, reduction=1e-10, launch_mode=1)
     x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
-    info = S.solve(dev(b), x)
-    print(f"[var bicgstab] gpu {info['iterations']} oracle {ref['iterations']}", flush=True)
+    info = S.solve(dev(b), x, history=3001)
+    print(f"[var bicgstab] gpu {info['iterations']} oracle {ref['iterations']} perturbed {sorted(spread)}",
+          flush=True)
     assert info["stop_reason"] == mxl.STOP_CONVERGED
-    assert abs(info["iterations"] - ref["iterations"]) <= 2
+    assert_bicgstab_tracks_oracle(info, g)
     assert np.linalg.norm(b - O.spmv(A, x.cpu().numpy())) <= 2e-10 * np.linalg.norm(b)
     refg = O.gmres(A, b, krylov_dim=30, reduction=1e-10, bptr=bp, inv=inv)
     G = mxl.solver("gmres", M, P, krylov_dim=30, max_iters=3000, reduction=1e-10)

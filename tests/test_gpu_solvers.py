@@ -15,7 +15,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests._gpu import DEV, dev, matrix
+from tests._gpu import assert_bicgstab_tracks_oracle, DEV, dev, matrix
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -399,15 +399,17 @@ def test_full_size_pcg_bench_path(mxl, ctx, stencil128):
 
 def test_full_size_bicgstab_stencil27(mxl, ctx, stencil128):
     """Jacobi-BiCGSTAB to 1e-10 on the 128^3 27-point system, ELL16 and
-    check_every 16 as benchmarked (the many-workgroup reductions): count
-    within 2 of the oracle's stored count, FP64 residual."""
+    check_every 16 as benchmarked (the many-workgroup reductions): the first
+    ten residuals match the oracle's, the count lies within the oracle's own
+    rounding spread widened by 2, FP64 residual."""
     A, b = stencil128
     g = _golden("stencil27_128_bicgstab_1e-10")
     M = matrix(mxl, ctx, A).convert("ell", variant=2)
     S = mxl.solver("bicgstab", M, mxl.jacobi(M), max_iters=5000, reduction=1e-10, check_every=16)
     x = torch.zeros(A.nrows, dtype=torch.float64, device=DEV)
-    info = S.solve(dev(b), x)
-    print(f"[bicgstab full27] gpu {info['iterations']} oracle {g['iterations']}", flush=True)
+    info = S.solve(dev(b), x, history=5001)
+    print(f"[bicgstab full27] gpu {info['iterations']} oracle {g['iterations']} "
+          f"perturbed oracle {g['perturbed_counts']}", flush=True)
     assert info["stop_reason"] == mxl.STOP_CONVERGED
-    assert abs(info["iterations"] - g["iterations"]) <= 2
+    assert_bicgstab_tracks_oracle(info, g)
     assert _true_rel(A, b, x.cpu().numpy()) <= 2e-10
