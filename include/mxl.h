@@ -21,7 +21,8 @@
  *  - Work is enqueued on the context's HIP stream (borrowed from the caller)
  *    and is stream-ordered: mxl_apply* returns before the result is ready,
  *    exactly like a kernel launch.  mxl_solve and
- *    mxl_batch_solve block until the solve has stopped.
+ *    mxl_batch_solve block until the solve has stopped;
+ *    mxl_batch_solve_noalloc does not.
  *  - Index arrays are int32 and must describe canonical CSR: row_ptr[0] = 0,
  *    non-decreasing, row_ptr[nrows] = nnz, column indices in [0, ncols) and
  *    strictly increasing within a row.
@@ -424,6 +425,26 @@ mxl_status mxl_batch_solve(const mxl_op *B, const mxl_criteria *crit,
 mxl_status mxl_batch_autotune(const mxl_op *B, const mxl_criteria *crit,
                               const double *b, double *x_scratch, int reps,
                               mxl_tuning *best, double *best_ms);
+
+/* mxl_batch_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, schedule rules and results, but the work counter and the
+ * spill region of systems too large for LDS live in a fixed 96 MiB device
+ * array that the library holds on each GPU until the process ends, and the
+ * call neither allocates nor synchronises: the solve is enqueued on the
+ * context's stream and its outputs are ready when that stream reaches it.
+ * Arguments, layout and ownership as for mxl_batch_solve; tuning NULL takes
+ * the handle's autotuned schedule if mxl_batch_autotune has run, else the
+ * default one (no tuning happens here).  INVALID_ARG when the schedule's
+ * spill region (wgs_per_cu * CUs * 5 * the largest system's rows doubles,
+ * 0 when every system fits in LDS) plus 256 bytes exceeds 96 MiB; DEVICE
+ * when the array's address could not be looked up at mxl_ctx_create.  All
+ * calls on one GPU share the array: calls whose solves overlap on the device
+ * (other streams, other contexts or threads) race and give wrong results. */
+mxl_status mxl_batch_solve_noalloc(const mxl_op *B, const mxl_criteria *crit,
+                                   const mxl_tuning *tuning, const double *b,
+                                   double *x, int32_t *iters, double *rel_res,
+                                   uint8_t *status);
 
 /* ---------------------------------------------------------------- selector */
 

@@ -119,6 +119,7 @@ def _load():
         "mxl_ir_generate": [vp, C.POINTER(IrParams), pp],
         "mxl_batch_csr_create": [vp, i64, vp, vp, vp, vp, vp, C.c_int, pp],
         "mxl_batch_solve": [vp, C.POINTER(Criteria), C.POINTER(Tuning), vp, vp, vp, vp, vp],
+        "mxl_batch_solve_noalloc": [vp, C.POINTER(Criteria), C.POINTER(Tuning), vp, vp, vp, vp, vp],
         "mxl_batch_autotune": [vp, C.POINTER(Criteria), vp, vp, C.c_int, C.POINTER(Tuning),
                                C.POINTER(C.c_double)],
         "mxl_features": [vp, vp],
@@ -494,6 +495,15 @@ class Batch(Op):
         self.ctx.use_current_stream()
         _check(lib.mxl_batch_solve(self.h, C.byref(c), C.byref(t) if t is not None else None,
                                    _ptr(b), _ptr(x), _ptr(iters), _ptr(rel_res), _ptr(status)))
+
+    def solve_noalloc(self, b, x, iters, rel_res, status, tuning=None, **crit) -> None:
+        """mxl_batch_solve_noalloc: enqueued on the stream, no allocation, no host wait."""
+        _need_cuda(b, x, iters, rel_res, status)
+        c = criteria(**({"max_iters": 0} | crit))
+        t = Tuning(*tuning) if tuning is not None else None
+        self.ctx.use_current_stream()
+        _check(lib.mxl_batch_solve_noalloc(self.h, C.byref(c), C.byref(t) if t is not None else None,
+                                           _ptr(b), _ptr(x), _ptr(iters), _ptr(rel_res), _ptr(status)))
 
     def autotune(self, b, x_scratch, reps: int = 2, **crit):
         """Time every schedule on this batch; returns ((wg_size, wgs_per_cu, order, format), ms)."""

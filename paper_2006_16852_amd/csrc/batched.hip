@@ -17,6 +17,8 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -699,6 +701,37 @@ __global__ void k_batch_jacobi(int64_t rows, const int *__restrict__ rows_sys_lo
 
 __global__ void k_zero_u32(unsigned *p) { *p = 0u; }
 
+// Fixed device scratch of mxl_batch_solve_noalloc: the work counter in the
+// first 256 bytes, the spill region after it.  Each GPU that loads the
+// library holds its own copy until the process ends.  Host code must not
+// pass `noalloc_scratch` itself to a kernel (on the host it names a stand-in,
+// not the device copy); it uses the address noalloc_scratch_init looked up.
+constexpr size_t kNoAllocQueueBytes = 256;
+__device__ __align__(256) unsigned char noalloc_scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, void *> g_noalloc_ptr;  // device -> address of that device's copy
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(device);
+    if (it != g_noalloc_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !ptr) {
+        *out = nullptr;
+        return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    g_noalloc_ptr[device] = ptr;
+    *out = ptr;
+    return hipSuccess;
+}
+
 mxl_ctx *batch_ctx(const BatchImpl &B) { return B.ctx; }
 
 }  // namespace mxl
@@ -731,26 +764,29 @@ int lds_cap_for(const mxl_ctx *ctx, const BatchImpl &Bt, int wpc) {
 // The kernel a schedule runs: its format field, 0 choosing ELL when built.
 bool use_ell(const BatchImpl &Bt, const mxl_tuning &t) { return t.format == 2 || (t.format == 0 && Bt.ell); }
 
-hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
-                        const double *b, double *x, int32_t *iters, double *rel, uint8_t *status,
-                        int lds_cap, int64_t ell_budget, hipStream_t s, int use_x0 = 0) {
+// queue: the work counter (zeroed here by a kernel, not a memset, so the
+// launch sequence can be captured); scr: the spill region, at least
+// wgs_per_cu * num_cu * 5 * max_n doubles when any system spills, else NULL.
+hipError_t launch_batch_on(const BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
+                           const double *b, double *x, int32_t *iters, double *rel, uint8_t *status,
+                           int lds_cap, int64_t ell_budget, hipStream_t s, unsigned *queue, double *scr,
+                           int use_x0 = 0) {
     const int G = t.wgs_per_cu * Bt.ctx->num_cu;
     const int *order = (const int *)(t.order ? Bt.order_big->p : Bt.order_input->p);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, (unsigned *)Bt.queue->p);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, queue);
     const int chk = c.nonfinite_check;
     const double red = c.reduction;
     const int64_t mif = c.max_iters;
-    double *scr = Bt.scratch ? (double *)Bt.scratch->p : nullptr;
     if (use_ell(Bt, t)) {
         const size_t shm = (size_t)ell_budget;
-        const int64_t stride = Bt.scratch ? (int64_t)5 * Bt.max_n : 0;
+        const int64_t stride = scr ? (int64_t)5 * Bt.max_n : 0;
 #define MXL_BATCH_ELL_CASE(BB)                                                                       \
     case BB:                                                                                         \
         hipLaunchKernelGGL(k_batch_pcg_ell<BB>, dim3(G), dim3(BB), shm, s, Bt.nsys,                  \
                            (const int *)Bt.sys_ptr->p, (const int64_t *)Bt.ell_off->p,              \
                            (const int *)Bt.ell_w->p, (const double *)Bt.ell_val->p,                 \
                            (const short *)Bt.ell_col->p, (const double *)Bt.dinv->p, b, x, iters,   \
-                           rel, status, order, (unsigned *)Bt.queue->p, red, mif, 10, chk,          \
+                           rel, status, order, queue, red, mif, 10, chk,                            \
                            ell_budget, scr, stride, use_x0);                                        \
         break;
         switch (t.wg_size) {
@@ -762,14 +798,14 @@ hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_crit
         return hipGetLastError();
     }
     const size_t shm = lds_bytes_for(lds_cap);
-    const int64_t stride = Bt.scratch ? (int64_t)4 * Bt.max_n : 0;
+    const int64_t stride = scr ? (int64_t)4 * Bt.max_n : 0;
 #define MXL_BATCH_CASE(BB)                                                                          \
     case BB:                                                                                        \
         hipLaunchKernelGGL(k_batch_pcg<BB>, dim3(G), dim3(BB), shm, s, Bt.nsys,                     \
                            (const int *)Bt.sys_ptr->p, (const int *)Bt.row_ptr->p,                 \
                            (const int *)Bt.col->p, (const double *)Bt.val->p,                      \
                            (const double *)Bt.dinv->p, b, x, iters, rel, status, order,            \
-                           (unsigned *)Bt.queue->p, red, mif, 10, chk, lds_cap, scr, stride, use_x0); \
+                           queue, red, mif, 10, chk, lds_cap, scr, stride, use_x0);                \
         break;
     switch (t.wg_size) {
         MXL_BATCH_CASE(64) MXL_BATCH_CASE(128) MXL_BATCH_CASE(256) MXL_BATCH_CASE(512) MXL_BATCH_CASE(1024)
@@ -777,6 +813,15 @@ hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_crit
     }
 #undef MXL_BATCH_CASE
     return hipGetLastError();
+}
+
+// The handle's own queue counter and (lazily allocated) spill region.
+hipError_t launch_batch(const BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
+                        const double *b, double *x, int32_t *iters, double *rel, uint8_t *status,
+                        int lds_cap, int64_t ell_budget, hipStream_t s, int use_x0 = 0) {
+    return launch_batch_on(Bt, t, c, b, x, iters, rel, status, lds_cap, ell_budget, s,
+                           (unsigned *)Bt.queue->p, Bt.scratch ? (double *)Bt.scratch->p : nullptr,
+                           use_x0);
 }
 
 }  // namespace
@@ -951,9 +996,16 @@ static mxl_status batch_args(const BatchImpl &Bt, const double *b, double *x, co
         }                                                                                               \
     }()
 
-static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
-                               const double *b, double *x, int32_t *iters, double *rel,
-                               uint8_t *status) {
+// What a schedule needs: its kernel, that kernel's LDS, and the spill region
+// (doubles) when the largest system does not fit in LDS.
+struct SchedPlan {
+    bool ell = false;
+    int cap = 0;
+    int64_t ell_budget = 0;
+    int64_t spill_elems = 0;
+};
+
+static mxl_status plan_schedule(const BatchImpl &Bt, const mxl_tuning &t, SchedPlan &p) {
     if (t.wg_size != 64 && t.wg_size != 128 && t.wg_size != 256 && t.wg_size != 512 && t.wg_size != 1024)
         return set_error(MXL_ERR_INVALID_ARG, "wg_size must be 64, 128, 256, 512 or 1024");
     if (t.wgs_per_cu < 1 || t.wgs_per_cu > 32 || (t.order != 0 && t.order != 1))
@@ -961,28 +1013,42 @@ static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_cri
     if (t.format < 0 || t.format > 2) return set_error(MXL_ERR_INVALID_ARG, "format must be 0, 1 or 2");
     if (t.format == 2 && !Bt.ell)
         return set_error(MXL_ERR_NOT_IMPLEMENTED, "this batch has no compact ELL copy (format 2)");
-    const bool ell = use_ell(Bt, t);
-    const int cap = lds_cap_for(Bt.ctx, Bt, t.wgs_per_cu);
+    p.ell = use_ell(Bt, t);
+    p.cap = lds_cap_for(Bt.ctx, Bt, t.wgs_per_cu);
     // the ELL kernel's LDS: at most what the largest system can use
-    const int64_t ell_budget = std::min(lds_budget_for(Bt.ctx, t.wgs_per_cu),
-                                        (int64_t)Bt.max_n * (40 + 10 * (int64_t)Bt.w_max));
-    if (cap < 1 || ell_budget < 40) return set_error(MXL_ERR_INVALID_ARG, "schedule leaves no LDS per workgroup");
-    const bool spill = ell ? (int64_t)40 * Bt.max_n > ell_budget : cap < Bt.max_n;
-    if (spill) {  // systems above the LDS capacity run from a global scratch slice per workgroup
-        const int64_t need = (int64_t)t.wgs_per_cu * Bt.ctx->num_cu * 5 * Bt.max_n;
-        if (Bt.scratch_elems < need) {
-            auto d = std::make_shared<DevBuf>();
-            if (hipMalloc(&d->p, need * 8) != hipSuccess) return set_error(MXL_ERR_OUT_OF_MEMORY, "batch scratch");
-            d->bytes = need * 8;
-            d->owned = true;
-            Bt.scratch = d;
-            Bt.scratch_elems = need;
-        }
-    }
-    hipError_t e = ell ? MXL_ALLOW_LDS(k_batch_pcg_ell, t.wg_size, (size_t)ell_budget)
-                       : MXL_ALLOW_LDS(k_batch_pcg, t.wg_size, lds_bytes_for(cap));
+    p.ell_budget = std::min(lds_budget_for(Bt.ctx, t.wgs_per_cu),
+                            (int64_t)Bt.max_n * (40 + 10 * (int64_t)Bt.w_max));
+    if (p.cap < 1 || p.ell_budget < 40) return set_error(MXL_ERR_INVALID_ARG, "schedule leaves no LDS per workgroup");
+    const bool spill = p.ell ? (int64_t)40 * Bt.max_n > p.ell_budget : p.cap < Bt.max_n;
+    // systems above the LDS capacity run from a global scratch slice per workgroup
+    p.spill_elems = spill ? (int64_t)t.wgs_per_cu * Bt.ctx->num_cu * 5 * Bt.max_n : 0;
+    return MXL_OK;
+}
+
+static mxl_status allow_lds(const SchedPlan &p, const mxl_tuning &t) {
+    hipError_t e = p.ell ? MXL_ALLOW_LDS(k_batch_pcg_ell, t.wg_size, (size_t)p.ell_budget)
+                         : MXL_ALLOW_LDS(k_batch_pcg, t.wg_size, lds_bytes_for(p.cap));
     if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("LDS attribute: ") + hipGetErrorString(e));
-    e = launch_batch(Bt, t, c, b, x, iters, rel, status, cap, ell_budget, Bt.ctx->stream);
+    return MXL_OK;
+}
+
+static mxl_status run_schedule(BatchImpl &Bt, const mxl_tuning &t, const mxl_criteria &c,
+                               const double *b, double *x, int32_t *iters, double *rel,
+                               uint8_t *status) {
+    SchedPlan p;
+    mxl_status st;
+    if ((st = plan_schedule(Bt, t, p)) != MXL_OK) return st;
+    if (p.spill_elems > 0 && Bt.scratch_elems < p.spill_elems) {
+        auto d = std::make_shared<DevBuf>();
+        if (hipMalloc(&d->p, p.spill_elems * 8) != hipSuccess)
+            return set_error(MXL_ERR_OUT_OF_MEMORY, "batch scratch");
+        d->bytes = p.spill_elems * 8;
+        d->owned = true;
+        Bt.scratch = d;
+        Bt.scratch_elems = p.spill_elems;
+    }
+    if ((st = allow_lds(p, t)) != MXL_OK) return st;
+    hipError_t e = launch_batch(Bt, t, c, b, x, iters, rel, status, p.cap, p.ell_budget, Bt.ctx->stream);
     if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
     return MXL_OK;
 }
@@ -1008,6 +1074,34 @@ extern "C" mxl_status mxl_batch_solve(const mxl_op *Bop, const mxl_criteria *cri
     if ((st = run_schedule(*Bt, t, *crit, b, x, iters, rel_res, status)) != MXL_OK) return st;
     if (hipStreamSynchronize(Bt->ctx->stream) != hipSuccess)
         return set_error(MXL_ERR_DEVICE, "batched solve");
+    return MXL_OK;
+} catch (...) {
+    return mxl::abi_exception(__func__);
+}
+
+extern "C" mxl_status mxl_batch_solve_noalloc(const mxl_op *Bop, const mxl_criteria *crit,
+                                              const mxl_tuning *tuning, const double *b, double *x,
+                                              int32_t *iters, double *rel_res, uint8_t *status) try {
+    BatchImpl *Bt = const_cast<BatchImpl *>(batch_of(Bop));
+    if (!Bt || !crit) return set_error(MXL_ERR_INVALID_ARG, "batch operator and criteria required");
+    if (!(crit->reduction >= 0.0)) return set_error(MXL_ERR_INVALID_ARG, "reduction must be >= 0");
+    mxl_status st;
+    if ((st = batch_args(*Bt, b, x, iters, rel_res, status)) != MXL_OK) return st;
+    const mxl_tuning t = tuning ? *tuning : (Bt->tuned ? Bt->best : default_tuning());
+    SchedPlan p;
+    if ((st = plan_schedule(*Bt, t, p)) != MXL_OK) return st;
+    const size_t need = kNoAllocQueueBytes + (size_t)p.spill_elems * 8;
+    if (need > kNoAllocScratchBytes)
+        return set_error(MXL_ERR_INVALID_ARG,
+                         "schedule needs " + std::to_string(need) + " bytes of scratch; the static limit is " +
+                             std::to_string(kNoAllocScratchBytes) + " (fewer workgroups per CU spill less)");
+    char *base = (char *)Bt->ctx->noalloc_scratch;
+    if (!base) return set_error(MXL_ERR_DEVICE, "static scratch address not available on this device");
+    if ((st = allow_lds(p, t)) != MXL_OK) return st;
+    double *spill = p.spill_elems > 0 ? (double *)(base + kNoAllocQueueBytes) : nullptr;
+    hipError_t e = launch_batch_on(*Bt, t, *crit, b, x, iters, rel_res, status, p.cap, p.ell_budget,
+                                   Bt->ctx->stream, (unsigned *)base, spill);
+    if (e != hipSuccess) return set_error(MXL_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
     return MXL_OK;
 } catch (...) {
     return mxl::abi_exception(__func__);

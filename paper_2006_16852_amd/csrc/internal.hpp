@@ -43,6 +43,8 @@ struct mxl_ctx {
     mxl::BufPtr flush_buf;      // lazily allocated 1 GiB buffer for cache flushes
     hipStream_t cap_stream = nullptr;  // lazily created stream that graphs are captured on
                                        // (the caller's stream may be the null stream)
+    void *noalloc_scratch = nullptr;   // this device's copy of the static batch scratch
+                                       // (NULL if its address could not be looked up)
     // The caller's handle plus one count per library object that uses the
     // context: mxl_ctx_destroy drops the caller's count, and the context is
     // freed with the last object, whatever order handles are destroyed in.
@@ -201,6 +203,13 @@ struct IrImpl {
 
 struct BatchImpl;  // batched.hip
 mxl_ctx *batch_ctx(const BatchImpl &B);
+// Size of the fixed device scratch behind mxl_batch_solve_noalloc (96 MiB):
+// the queue counter plus the spill region of 8 workgroups per CU on 256 CUs
+// at 1,024-row systems (80 MiB).
+constexpr size_t kNoAllocScratchBytes = (size_t)96 << 20;
+// Looks up (once per device, with that device current) the address of the
+// device's copy of that scratch.
+hipError_t noalloc_scratch_init(int device, void **out);
 std::shared_ptr<BatchImpl> batch_from_matrix(const MatrixImpl &A, const void *dinv);
 mxl_status batch_single_solve(BatchImpl &Bt, const mxl_criteria &c, const double *b, double *x,
                               void *out3, int64_t *iters, double *rel, int *stop);

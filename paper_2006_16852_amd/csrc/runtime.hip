@@ -225,6 +225,9 @@ mxl_status mxl_ctx_create(int device, void *hip_stream, mxl_ctx **out) try {
         delete c;
         return fail(MXL_ERR_OUT_OF_MEMORY, "pinned host staging");
     }
+    // the static scratch of mxl_batch_solve_noalloc: a failed lookup leaves
+    // NULL, and only that entry point reports it
+    if (mxl::noalloc_scratch_init(device, &c->noalloc_scratch) != hipSuccess) c->noalloc_scratch = nullptr;
     *out = c;
     return MXL_OK;
 } catch (...) {
