@@ -50,10 +50,53 @@ def spmv_bytes(fmt, n, nnz, desc, vt=8, it=4, beta_nonzero=False):
     raise ValueError(fmt)
 
 
+def cg_table2_bytes(n, nnz, iters, VT=8, IT=4):
+    """Read + write volume of an unpreconditioned CG run with a COO product
+    by the paper's memory model (Table 2): x charged once per nonzero, every
+    vector operation a separate pass."""
+    rd = (4 * n + 2 * nnz) * VT + 2 * nnz * IT + iters * ((15 * n + 2 * nnz) * VT + 2 * nnz * IT)
+    wr = (5 * n + 2) * VT + iters * (5 * n + 2) * VT
+    return rd + wr
+
+
+def bicgstab_table2_bytes(n, nnz, iters, VT=8, IT=4):
+    """The same model for BiCGSTAB (Table 2).  Its iteration count counts
+    half iterations, one product each, so a run of k full iterations is
+    iter = 2 k: ceil(iter/2) first halves and floor(iter/2) second halves."""
+    h1, h0 = (iters + 1) // 2, iters // 2
+    rd = ((5 * n + 2 * nnz) * VT + 2 * nnz * IT + h1 * ((16 * n + 2 * nnz) * VT + 2 * nnz * IT)
+          + h0 * ((13 * n + 2 * nnz) * VT + 2 * nnz * IT))
+    wr = (10 * n + 6) * VT + h1 * (4 * n + 2) * VT + h0 * (4 * n + 3) * VT
+    return rd + wr
+
+
+def host_identity():
+    """CPU model name and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
 def source_digest():
+    """Digest of the CG-loop SpMV's source: the ELL kernel's text, the launch
+    plan constant of its fused-dot grid, and the shared device helpers.  The
+    stored traffic counters apply while it is unchanged."""
+    csrc = os.path.join(ROOT, "paper_2006_16852_amd", "csrc")
+    spmv = open(os.path.join(csrc, "spmv.hip")).read()
+    i = spmv.index("template <typename V, bool DOT, bool LDS, int R, bool D16 = false>")
+    j = spmv.index("// y = beta*y (alpha*A*x with no stored entries)", i)
+    k = spmv.index("constexpr int kDotSlotCap")
     h = hashlib.sha256()
-    for f in ("spmv.hip", "device_common.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2006_16852_amd", "csrc", f), "rb").read())
+    h.update(spmv[i:j].encode())
+    h.update(spmv[k:spmv.index("\n", k)].encode())
+    h.update(open(os.path.join(csrc, "device_common.hpp"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -82,7 +125,107 @@ def cpu_baseline(A, x, b, sel_fmt):
             + r["iterations"] * (spmv_bytes("csr", n, nnz, {}) + 10 * n * 8))
     return {"value": round(byts / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"4 SpMVs (csr, coo, ell, hyb) + {r['iterations']} Jacobi-PCG iterations "
-                      f"(CSR) on the 128^3 27-point system, {dt:.2f} s on the host"}
+                      f"(CSR) on the 128^3 27-point system, {dt:.2f} s on the host",
+            "host": host_identity()}
+
+
+def timed_solve(solve, x, reps=3):
+    """Median GPU time (ms) of `reps` solves from x = 0, events on the solver's
+    stream; returns (ms, info of the last solve)."""
+    import numpy as np
+    import torch
+    ts, info = [], None
+    for _ in range(reps):
+        x.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        info = solve()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), info
+
+
+def true_rel(base, x, b):
+    import torch
+    r = b.clone()
+    base.apply(x, r, -1.0, 1.0)
+    return float(torch.linalg.norm(r) / torch.linalg.norm(b))
+
+
+def solver_bandwidth(mxl, M, base, b, x, n, nnz, triad_gbs, iters=150):
+    """The paper's solver-bandwidth protocol (Sec. 7.4): the COO product, no
+    preconditioner, a fixed number of iterations, bytes by its Table 2 model
+    (which charges x once per nonzero), set against the measured triad."""
+    from bench_extra import gmres_table2_bytes
+    out = {"iterations": iters, "operator": "coo", "preconditioner": None}
+    for kind in ("cg", "bicgstab", "gmres"):
+        S = mxl.solver(kind, M, None, max_iters=iters, reduction=0.0, check_every=16,
+                       **({"krylov_dim": 100} if kind == "gmres" else {}))
+        ms, info = timed_solve(lambda: S.solve(b, x), x)
+        k = info["iterations"]
+        if kind == "cg":
+            byts = cg_table2_bytes(n, nnz, k)
+        elif kind == "bicgstab":
+            byts = bicgstab_table2_bytes(n, nnz, 2 * k)
+        else:
+            byts = gmres_table2_bytes(n, nnz, k, 100)
+        gbs = byts / (ms * 1e-3) / 1e9
+        out[kind] = {"iterations": k, "stop": mxl.STOP_NAMES[info["stop_reason"]], "ms": round(ms, 3),
+                     "table2_MB": round(byts / 1e6, 1), "table2_GBs": round(gbs, 1),
+                     "frac_of_triad": round(gbs / triad_gbs, 3), "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
+        del S
+    return out
+
+
+def aniso_comparison(mxl, ctx, reps=3):
+    """FP64 Jacobi-CG against FP32-inner iterative refinement on the 160^3
+    anisotropic 7-point system (b ~ U[-1,1), seed 4), to 1e-10 and 1e-12,
+    on the faster of the ELL operators; the refinement with point Jacobi
+    and with 32-row adaptive block Jacobi in its inner solve."""
+    import torch
+    import workloads as W
+    dev = "cuda:0"
+    A = W.aniso_3d7(160)
+    n = A.nrows
+    base = mxl.csr(ctx, torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                   torch.from_numpy(A.val).to(dev))
+    b = torch.from_numpy(W.uniform_vec(n, 4)).to(dev)
+    x = torch.zeros_like(b)
+    y = torch.empty_like(b)
+    cands = {"ell": base.convert("ell"), "ell16": base.convert("ell", variant=mxl.ELL_DELTA16)}
+    t_sel = {k: v.time_apply(b, y, reps=20) for k, v in cands.items()}
+    opname = min(t_sel, key=t_sel.get)
+    M = cands[opname]
+    P = mxl.jacobi(M)
+    out = {"workload": "aniso7_160^3 (n = 4,096,000), coefficients 1 / 1e-2 / 1e-4, shift 1e-3",
+           "operator": opname}
+    for red in (1e-10, 1e-12):
+        S = mxl.solver("cg", M, P, max_iters=5000, reduction=red, check_every=16)
+        ms, info = timed_solve(lambda: S.solve(b, x), x, reps)
+        f64 = {"ms": round(ms, 3), "iterations": info["iterations"], "true_rel_residual": true_rel(base, x, b)}
+        irs = {}
+        for tin in (1e-2, 1e-3, 1e-4):
+            I = mxl.ir(M, outer=dict(max_iters=60, reduction=red),
+                       inner=dict(reduction=tin, max_iters=10_000, check_every=16))
+            ms, info = timed_solve(lambda: I.solve(b, x), x, reps)
+            irs[f"inner{tin:g}"] = {"ms": round(ms, 3), "corrections": info["iterations"],
+                                    "inner_iterations": info["inner_iterations"],
+                                    "true_rel_residual": true_rel(base, x, b)}
+            del I
+        Ib = mxl.ir(M, outer=dict(max_iters=60, reduction=red),
+                    inner=dict(reduction=1e-3, max_iters=10_000, check_every=16), block_size=32,
+                    block_accuracy=0.1)
+        ms, info = timed_solve(lambda: Ib.solve(b, x), x, reps)
+        irb = {"ms": round(ms, 3), "corrections": info["iterations"], "inner_iterations": info["inner_iterations"],
+               "true_rel_residual": true_rel(base, x, b)}
+        del Ib
+        best = min(irs, key=lambda k: irs[k]["ms"])
+        out[f"to_{red:g}"] = {"fp64_cg": f64, "ir_point_jacobi": irs,
+                              "ir_speedup_vs_fp64": round(f64["ms"] / irs[best]["ms"], 3),
+                              "ir_adaptive_bjacobi32_inner1e-3": irb,
+                              "ir_bjacobi_speedup_vs_fp64_point": round(f64["ms"] / irb["ms"], 3)}
+    return out
 
 
 def mxl_catalog(name):
@@ -99,7 +242,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="stencil27",
                     choices=["stencil27", "aniso_ir", "poisson2d", "batch", "overhead", "stream", "bicgstab", "stencil_mf",
-                             "gmres"])
+                             "gmres", "suite"])
+    ap.add_argument("--matrices", default="74,79,60", help="suite members for --workload suite")
+    ap.add_argument("--with-stencil", action="store_true", help="--workload suite: add the 128^3 27-point system")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path (a sharded solve "
@@ -177,7 +322,7 @@ def main():
     x = torch.zeros(n, dtype=torch.float64, device=dev)
 
     evs = {k: [] for k in spmv_set}
-    infos = []
+    infos, cg_evs = [], []
 
     def step(record):
         for k in spmv_set:
@@ -188,9 +333,15 @@ def main():
             if record:
                 evs[k].append((e0, e1))
         x.zero_()
+        # the solve's own time: events on the solver's stream, after the
+        # products above (the solver's host clock would start while they run)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
         info = S.solve(bd, x, time_spmv=16)  # events on every 16th product
+        c1.record()
         if record:
             infos.append(info)
+            cg_evs.append((c0, c1))
 
     for _ in range(args.warmup):
         step(False)
@@ -204,9 +355,7 @@ def main():
     step_s = (t1 - t0) / args.steps
 
     # correctness guard of the timed result (recomputed in FP64 on the GPU)
-    r = bd.clone()
-    base.apply(x, r, -1.0, 1.0)
-    true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(bd))
+    cg_true_rel = true_rel(base, x, bd)
 
     # Outside the timed step: the metric's comparisons on the same system.
     # Mixed precision: FP32-inner / FP64-outer refinement on the same operator.
@@ -217,21 +366,16 @@ def main():
     for tin in (1e-2, 1e-3):
         I = mxl.ir(M, outer=dict(max_iters=60, reduction=1e-10),
                    inner=dict(reduction=tin, max_iters=10_000, check_every=16))
-        ts = []
-        for _ in range(3):
-            x.zero_()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            iinfo = I.solve(bd, x)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t)
-        rr = bd.clone()
-        base.apply(x, rr, -1.0, 1.0)
-        ir_runs[f"inner{tin:g}"] = {"ms": round(float(np.median(ts)) * 1e3, 3), "corrections": iinfo["iterations"],
+        ms, iinfo = timed_solve(lambda: I.solve(bd, x), x)
+        ir_runs[f"inner{tin:g}"] = {"ms": round(ms, 3), "corrections": iinfo["iterations"],
                                     "inner_iterations": iinfo["inner_iterations"],
-                                    "true_rel_residual": float(torch.linalg.norm(rr) / torch.linalg.norm(bd))}
+                                    "true_rel_residual": true_rel(base, x, bd)}
         del I
     comp["mixed_ir"] = ir_runs
+    log("[bench] comparisons: the paper's solver-bandwidth protocol (COO, no preconditioner)")
+    comp["solver_bandwidth_table2"] = solver_bandwidth(mxl, ops["coo"], base, bd, x, n, nnz, ref_gbs["triad"])
+    log("[bench] comparisons: 160^3 anisotropic system, FP64 CG vs mixed-precision refinement")
+    comp["aniso160"] = aniso_comparison(mxl, ctx)
     from paper_2006_16852_amd.selector import Selector
     learned = Selector.load()
     k_model, _ = learned.choose(ctx, base, xd, yd, fallback=False)
@@ -262,7 +406,7 @@ def main():
     cg_setup_bytes = spmv_bytes(fmt_of[sel], n, nnz, descs[sel], beta_nonzero=True) + 5 * n * 8
     cg_bytes = float(np.mean(its)) * cg_iter_bytes + cg_setup_bytes
     step_bytes += cg_bytes
-    cg_ms = float(np.median([i["seconds"] for i in infos])) * 1e3
+    cg_ms = float(np.median([a.elapsed_time(b) for a, b in cg_evs]))
     comp["fp64_cg_ms"] = round(cg_ms, 3)
     best_ir = min(v["ms"] for v in comp["mixed_ir"].values())
     comp["ir_speedup_vs_fp64"] = round(cg_ms / best_ir, 3)
@@ -298,9 +442,14 @@ def main():
                      # CSR-minimal bytes of y = A x over this kernel's time
                      "csr_equiv_GBs": round(spmv_bytes("csr", n, nnz, None) / (launch_ms * 1e-3) / 1e9, 1),
                      "alg_bytes_per_launch": cg_spmv, "avg_launch_us": round(launch_ms * 1e3, 2)},
-        "cg": {"iterations": its[0], "time_to_1e-10_ms": round(cg_ms, 3), "true_rel_residual": true_rel,
+        "cg": {"iterations": its[0], "time_to_1e-10_ms": round(cg_ms, 3), "true_rel_residual": cg_true_rel,
                "alg_GBs": round(cg_bytes / (cg_ms * 1e-3) / 1e9, 1),
-               "us_per_iteration": round(cg_ms * 1e3 / its[0], 2)},
+               "us_per_iteration": round(cg_ms * 1e3 / its[0], 2),
+               "alg_MB_per_iteration": round(cg_iter_bytes / 1e6, 2),
+               # the paper's unfused accounting of the same iterations (Table 2:
+               # COO product, x once per nonzero, one pass per vector operation)
+               "table2_MB_per_iteration": round((cg_table2_bytes(n, nnz, 1) - cg_table2_bytes(n, nnz, 0)) / 1e6, 2),
+               "table2_GBs": round(cg_table2_bytes(n, nnz, its[0]) / (cg_ms * 1e-3) / 1e9, 1)},
         "spmv": spmv_detail,
         "selection_ms": {k: round(v, 4) for k, v in t_sel.items()},
         "setup_ms": t_setup,

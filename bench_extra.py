@@ -14,6 +14,9 @@ stencil_mf: the same operator matrix-free: SpMV and Jacobi-PCG to 1e-10.
 gmres     : 128^3 3D convection-diffusion (nonsymmetric), Jacobi-GMRES(100) to
             1e-10, with the solve's algorithmic GB/s and the GB/s the paper's
             memory model (Table 2) assigns to the same run.
+suite     : SpMV per stored-format class on members of the skewed suite
+            (--matrices, e.g. 74,79,60) and the 128^3 27-point system
+            (--with-stencil); the workload the SpMV counter passes profile.
 
 Each line carries a cpu_baseline: the oracle on a bounded sample of the same
 work (one host core), unless --no-cpu-baseline.
@@ -237,6 +240,18 @@ def batch(args):
     res["autotuned"] = round(dt * 1e3, 3)
     ok = int((st.cpu().numpy() == 1).sum())
     bytes_once = B.row_ptr[-1] * 12 + B.sys_ptr[-1] * (4 + 8 * 3)
+    # no-reuse model: every iteration of system s moves its matrix and 11 n_s values
+    ns = np.diff(B.sys_ptr).astype(np.int64)
+    nz = np.diff(B.row_ptr[B.sys_ptr]).astype(np.int64)
+    iters = it.cpu().numpy().astype(np.int64)
+    bytes_noreuse = int((iters * (nz * 12 + (ns + 1) * 4 + 11 * ns * 8)).sum())
+    # denominators: HBM peak and the measured read bandwidth of the caches
+    # the systems' working sets live in between iterations
+    sa = torch.rand(1 << 24, dtype=torch.float64, device=dev)
+    sc = torch.empty(1 << 12, dtype=torch.float64, device=dev)
+    cached = cached_read_bandwidth(mxl, ctx, sa, sc)
+    del sa, sc
+    noreuse_gbs = bytes_noreuse / dt / 1e9
     print(json.dumps({"metric": "batched Jacobi-CG systems/s (10,000 systems to 1e-10)", "unit": "systems/s",
                       "value": round(B.nsys / (dt), 1), "higher_is_better": True, "n_gpus": 1,
                       "dtype": "f64", "data": "synthetic",
@@ -246,6 +261,10 @@ def batch(args):
                       "autotune_seconds": round(tune_s, 3),
                       "converged": ok, "total_iterations": int(it.sum()),
                       "read_once_GBs": round(bytes_once / dt / 1e9, 1),
+                      "noreuse_GBs": round(noreuse_gbs, 1),
+                      "noreuse_frac_hbm": round(noreuse_gbs / 8000.0, 3),
+                      "cached_read_GBs": cached,
+                      "noreuse_frac_llc": round(noreuse_gbs / cached["llc_128MiB"], 3),
                       **({} if args.no_cpu_baseline else {"cpu_baseline": _batch_cpu(B)})}), flush=True)
 
 
@@ -444,13 +463,29 @@ def stream(args):
     c = torch.empty(n, dtype=torch.float64, device=dev)
     reps = max(5, args.steps)
     res = {}
-    for op, nbytes in (("copy", 16 * n), ("triad", 24 * n), ("dot", 16 * n)):
+    for op, nbytes in (("copy", 16 * n), ("triad", 24 * n), ("dot", 16 * n), ("read", 8 * n)):
         ms = mxl.stream_bench(ctx, op, a, b, c, reps=reps)
         res[op] = {"ms": round(ms, 4), "GBs": round(nbytes / ms / 1e6, 1), "bytes": nbytes}
     print(json.dumps({"metric": "STREAM triad bandwidth", "unit": "GB/s", "value": res["triad"]["GBs"],
                       "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "stream 2^28 doubles", "n": n}, "runs": res,
+                      "cached_read_GBs": cached_read_bandwidth(mxl, ctx, a, c, reps),
                       "peak_GBs": 8000.0}), flush=True)
+
+
+def cached_read_bandwidth(mxl, ctx, a, c, reps=10):
+    """Read bandwidth (GB/s) of the cached read-only kernel over arrays that
+    fit the caches; one launch sweeps the array until 2^28 values are read
+    (the first sweep fills the cache): 2^24 doubles (128 MiB: in the 256 MB
+    last-level cache, but 16 MiB per XCD, beyond its 4 MB L2) and 2^21
+    doubles (16 MiB: each XCD sweeps a 2 MiB band inside its L2)."""
+    out = {}
+    for tag, m in (("llc_128MiB", 1 << 24), ("l2_16MiB", 1 << 21)):
+        v = a[:m]
+        sweeps = -(-(1 << 28) // m)
+        ms = mxl.stream_bench(ctx, "read", v, None, c, reps=reps)
+        out[tag] = round(8 * m * sweeps / ms / 1e6, 1)
+    return out
 
 
 def bicgstab(args):
@@ -583,6 +618,62 @@ def stencil_mf(args):
     print(json.dumps(out), flush=True)
 
 
+def suite(args):
+    """SpMV of every stored-format class on members of the skewed suite (row
+    lengths Zipf-distributed, banded-random columns) and on the 128^3
+    27-point system: the per-class GB/s (CSR-minimal bytes and the class's
+    own bytes) that the counter passes are read against."""
+    import numpy as np
+    import torch
+    import paper_2006_16852_amd as mxl
+    import workloads as W
+    from paper_2006_16852_amd.selector import convert
+    dev = "cuda:0"
+    ctx = mxl.Context(0)
+    classes = ["csr_stream", "csr_merge", "csr_vec64", "coo", "hyb66", "ell16"]
+    mats = [int(m) for m in args.matrices.split(",")] if args.matrices else []
+    out = {"metric": "SpMV GB/s per class, skewed suite members and the 128^3 27-point system",
+           "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "reps": args.steps, "matrices": {}}
+    todo = [(f"zipf{m}", lambda m=m: W.zipf_suite_matrix(m)) for m in mats]
+    if args.with_stencil:
+        todo.append(("stencil27_128", lambda: W.stencil_3d27(128)))
+    for name, gen in todo:
+        A = gen()
+        n, nnz = A.nrows, A.nnz
+        base = mxl.csr(ctx, torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
+                       torch.from_numpy(A.val).to(dev))
+        x = torch.from_numpy(W.uniform_vec(A.ncols, 2)).to(dev)
+        y = torch.empty(n, dtype=torch.float64, device=dev)
+        csr_b = nnz * 12 + (n + 1) * 4 + 2 * n * 8
+        rec = {"n": n, "nnz": nnz, "max_row": int(np.diff(A.row_ptr).max()), "csr_MB": round(csr_b / 1e6, 1)}
+        if name.startswith("zipf"):
+            p = W.zipf_suite_params(int(name[4:]))
+            rec.update(zipf_a=round(p.a, 3), bandwidth=p.bw)
+        for c in classes:
+            try:
+                op = convert(base, c)
+            except mxl.MxlError as e:
+                if e.status == mxl.ERR_INFEASIBLE_FORMAT:
+                    rec[c] = None
+                    continue
+                raise
+            ms = op.time_apply(x, y, reps=args.steps, flush=True)
+            d = op.describe()
+            rec[c] = {"us": round(ms * 1e3, 2), "csr_GBs": round(csr_b / ms / 1e6, 1),
+                      "stored_MB": round(d["stored_bytes"] / 1e6, 1)}
+            log(f"[suite] {name} {c}: {ms * 1e3:.1f} us, {csr_b / ms / 1e6:.0f} GB/s (CSR bytes)")
+            del op
+        out["matrices"][name] = rec
+        del base, A
+    print(json.dumps(out), flush=True)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def run(args):
     {"aniso_ir": aniso_ir, "poisson2d": poisson2d, "batch": batch, "overhead": overhead,
-     "stream": stream, "bicgstab": bicgstab, "stencil_mf": stencil_mf, "gmres": gmres}[args.workload](args)
+     "stream": stream, "bicgstab": bicgstab, "stencil_mf": stencil_mf, "gmres": gmres,
+     "suite": suite}[args.workload](args)

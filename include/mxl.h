@@ -464,8 +464,14 @@ mxl_status mxl_time_apply(const mxl_op *A, const void *x, void *y, int reps,
 /* Bandwidth reference kernels, the STREAM-style operations the paper uses
  * to calibrate solver bandwidth (Sec. 7.4, Table 3): op 0 copy c = a,
  * op 1 triad c = a + 0.5*b, op 2 dot a.b (partials written to c, which
- * then needs 8*256*num_CU bytes).  FP64, n even.  median_ms: median of reps
- * launches timed with HIP events on the context stream. */
+ * then needs 8*8*num_CU bytes), all with nontemporal loads; op 3 the sum
+ * of a with ordinary loads (b unused, partials in c as for op 2), sweeping
+ * the array ceil(2^28 / n) times in one launch (once when n >= 2^28; it
+ * reads 8 n bytes per sweep): ordinary loads are cached, so over an array
+ * that fits L2 or the last-level cache the launch measures that cache's
+ * read bandwidth.  FP64, n even.
+ * median_ms: median of reps launches timed with HIP events on the context
+ * stream. */
 mxl_status mxl_stream_bench(mxl_ctx *ctx, int op, int64_t n, const double *a,
                             const double *b, double *c, int reps,
                             double *median_ms);

@@ -338,8 +338,9 @@ def stencil(ctx: Context, shape, points, coefs, dtype=torch.float64) -> Op:
 
 def stream_bench(ctx: Context, op: str, a, b=None, c=None, reps: int = 10) -> float:
     """Median ms of a STREAM-style kernel: 'copy' c = a, 'triad' c = a + 0.5 b,
-    'dot' a.b (c receives per-workgroup partials)."""
-    code = {"copy": 0, "triad": 1, "dot": 2}[op]
+    'dot' a.b (c receives per-workgroup partials), 'read' sum of a with
+    ordinary (caching) loads (c receives partials)."""
+    code = {"copy": 0, "triad": 1, "dot": 2, "read": 3}[op]
     ms = C.c_double()
     ctx.use_current_stream()
     _check(lib.mxl_stream_bench(ctx.h, code, a.numel(), _ptr(a), _ptr(b), _ptr(c), reps,

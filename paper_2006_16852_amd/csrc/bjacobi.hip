@@ -442,7 +442,8 @@ __global__ __launch_bounds__(kWG) void k_bj_apply(int64_t n, const unsigned char
                                                   const int64_t *__restrict__ off,
                                                   const int *__restrict__ prec, double alpha,
                                                   const double *__restrict__ r, double beta,
-                                                  double *__restrict__ z) {
+                                                  double *__restrict__ z, const int *stop) {
+    if (stop && *stop) return;  // inside a solve: nothing after a device-side stop uses z
     __shared__ double xs[kWG];
     MXL_BJ_TILE(n)
     (void)L;
@@ -668,7 +669,8 @@ __global__ __launch_bounds__(kWG) void k_bj_apply_var(int64_t n, const int *__re
                                                       const int64_t *__restrict__ off,
                                                       const int *__restrict__ prec, double alpha,
                                                       const double *__restrict__ r, double beta,
-                                                      double *__restrict__ z) {
+                                                      double *__restrict__ z, const int *stop) {
+    if (stop && *stop) return;
     __shared__ double xw[kBjWin];
     MXL_BJ_TILE(n)
     (void)L;
@@ -869,18 +871,18 @@ hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int6
 }
 
 hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
-                    double beta, void *z, hipStream_t s) {
+                    double beta, void *z, hipStream_t s, const int *stop) {
     const int g = vec_grid(ctx, n);
     if (P.var) {
         hipLaunchKernelGGL(k_bj_apply_var, dim3(g), dim3(kWG), 0, s, n, (const int *)P.rblk->p,
                            (const int *)P.bptr_d->p, (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
-                           (const int *)P.bprec->p, alpha, (const double *)r, beta, (double *)z);
+                           (const int *)P.bprec->p, alpha, (const double *)r, beta, (double *)z, stop);
         return hipGetLastError();
     }
     MXL_BS_SWITCH(P.bs, hipLaunchKernelGGL(k_bj_apply<BS>, dim3(g), dim3(kWG), 0, s, n,
                                            (const unsigned char *)P.bstore->p, (const int64_t *)P.boff->p,
                                            (const int *)P.bprec->p, alpha, (const double *)r, beta,
-                                           (double *)z));
+                                           (double *)z, stop));
     return hipGetLastError();
 }
 

@@ -136,35 +136,43 @@ __device__ __forceinline__ void publish(double (&v)[NV], double *partials, int s
 // slots [0, nslots) (fixed striding, fixed tree), so a consumer kernel can
 // take the same scalar decisions in all of its workgroups without any
 // inter-workgroup communication.
-// A thread's slots are t, t + 256, t + 512, ...; they are loaded kGatherU at
-// a time before any is added, so one round trip to L2 serves kGatherU slots
-// (a loop that adds each value as it arrives waits once per slot), and then
-// added in slot order, so the sum does not depend on kGatherU.
-constexpr int kGatherU = 16;
-
+// A thread's slots are t, t + 256, t + 512, ...; a batch of U rounds of
+// them is loaded before any is added, so one round trip to L2 serves U slots
+// (a loop that adds each value as it arrives waits once per slot), and the
+// values are added in slot order, so the sum does not depend on U.  Whether
+// a batch is complete depends only on nslots, so the branch is uniform and
+// complete batches load without per-slot predicates.  U shrinks as NV grows
+// to keep the batch at 8 doubles per thread: the update kernels hold their
+// prefetched operands in registers at the same time.
 template <int NV>
 __device__ __forceinline__ void gather_all(const double *__restrict__ partials, int nslots,
                                            double (&tot)[NV], unsigned max_mask = 0) {
+    constexpr int U = NV <= 1 ? 8 : (NV == 2 ? 4 : 2);
     __shared__ double bc[NV > 0 ? NV : 1];
 #pragma unroll
     for (int j = 0; j < NV; ++j) tot[j] = 0.0;
-    for (int s0 = threadIdx.x; s0 < nslots; s0 += kGatherU * kWG) {
-        double buf[kGatherU][NV > 0 ? NV : 1];
+    auto add = [&](int j, double v) {
+        tot[j] = (max_mask >> j & 1) ? (v > tot[j] ? v : tot[j]) : tot[j] + v;
+    };
+    const int full = nslots / kWG;  // rounds in which every thread has a slot
+    for (int r0 = 0; r0 * kWG < nslots; r0 += U) {
+        if (r0 + U <= full) {
+            double buf[U][NV > 0 ? NV : 1];
 #pragma unroll
-        for (int u = 0; u < kGatherU; ++u) {
-            const int s = s0 + u * kWG;
-            const int sc = s < nslots ? s : nslots - 1;  // in bounds, so the loads need no branch
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < NV; ++j) buf[u][j] = partials[(int64_t)sc * NV + j];
-        }
+                for (int j = 0; j < NV; ++j) buf[u][j] = partials[(int64_t)((r0 + u) * kWG + threadIdx.x) * NV + j];
 #pragma unroll
-        for (int u = 0; u < kGatherU; ++u) {
-            const bool in = s0 + u * kWG < nslots;
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                const double v = buf[u][j];
-                const double t = (max_mask >> j & 1) ? (v > tot[j] ? v : tot[j]) : tot[j] + v;
-                tot[j] = in ? t : tot[j];
+                for (int j = 0; j < NV; ++j) add(j, buf[u][j]);
+        } else {
+            for (int u = 0; u < U; ++u) {
+                const int s = (r0 + u) * kWG + threadIdx.x;
+                if (s < nslots) {
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) add(j, partials[(int64_t)s * NV + j]);
+                }
             }
         }
     }

@@ -251,7 +251,7 @@ hipError_t launch_jacobi(const MatrixImpl &A, void *dinv, int *bad, hipStream_t 
 hipError_t launch_convert_vals(int64_t n, int from, const void *in, void *out, hipStream_t s);
 
 // ------------------------------------------------------------- krylov.hip
-constexpr int kSolverSlots = 4096;  // partial slots per reduction region
+constexpr int kSolverSlots = 8192;  // partial slots per reduction region
 constexpr int kRegions = 4;         // partial regions A..D, 3 doubles per slot
 int vec_grid(const mxl_ctx *ctx, int64_t n);
 hipError_t launch_finalize(int nv, const double *parts, int slots, SolverState *st, int op, int k,
@@ -302,8 +302,10 @@ hipError_t bj_cg_init(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_
 hipError_t bj_cg_update(const mxl_ctx *ctx, const JacobiImpl &P, int dtype, int64_t n, const void *r_in,
                         void *r_out, const void *q, void *z, SolverState *st, const double *pq_parts, int pq_slots,
                         double *parts, int k, hipStream_t s);
+// z = alpha M r + beta z; stop (nullable, device) skips the product once a
+// solve has stopped.
 hipError_t bj_apply(const mxl_ctx *ctx, const JacobiImpl &P, int64_t n, double alpha, const void *r,
-                    double beta, void *z, hipStream_t s);
+                    double beta, void *z, hipStream_t s, const int *stop = nullptr);
 
 // ------------------------------------------------------------- gmres.hip
 constexpr int kGmMaxKrylov = 1024;

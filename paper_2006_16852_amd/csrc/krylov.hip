@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict_
 // kPf tiles, then reduce the partials of the previous kernel (gather_all):
 // the loads do not depend on that scalar, so their latency overlaps the
 // reduction instead of every workgroup paying the two in sequence.
-constexpr int kPf = 4;
+constexpr int kPf = 2;
 
 #define MXL_PF_INDEX(u, cnt)                                   \
     const int64_t t_##u = tb_ + (int64_t)(u) * ts_;             \
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kWG) void k_bi_init(int64_t n, const V *__restrict_
 
 // Consumes [r.r, rhat.r] of iteration k-1: its criterion (k >= 2), then the
 // loop head of iteration k: rho_k, beta, p = r + beta (p - omega v),
-// p_hat = D^{-1} p.
+// p_hat = D^{-1} p (not stored when phat is NULL: block Jacobi forms it).
 template <typename V>
 __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restrict__ r,
                                                     V *__restrict__ p, const V *__restrict__ v,
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
     auto step = [&](int64_t i, V r0, V p0, V v0, V d0) {
         const V pi = (V)((double)r0 + beta * ((double)p0 - omega_prev * (double)v0));
         p[i] = pi;
-        phat[i] = (V)(dinv ? (double)d0 * (double)pi : (double)pi);
+        if (phat) phat[i] = (V)(dinv ? (double)d0 * (double)pi : (double)pi);
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
@@ -363,7 +363,8 @@ __global__ __launch_bounds__(kWG) void k_bi_pupdate(int64_t n, const V *__restri
         if (const int64_t i = t_ * kWG + threadIdx.x; i < n) step(i, r[i], p[i], v[i], dinv ? dinv[i] : (V)1);
 }
 
-// Consumes rhat.v (fused into the SpMV): alpha = rho_k / rhat.v; s = r - alpha v.
+// Consumes rhat.v (fused into the SpMV): alpha = rho_k / rhat.v; s = r - alpha v
+// and s_hat = D^{-1} s (not stored when shat is NULL).
 template <typename V>
 __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restrict__ r,
                                                     const V *__restrict__ v, V *__restrict__ s,
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(kWG) void k_bi_supdate(int64_t n, const V *__restri
     auto step = [&](int64_t i, V r0, V v0, V d0) {
         const V si = (V)((double)r0 - alpha * (double)v0);
         s[i] = si;
-        shat[i] = (V)(dinv ? (double)d0 * (double)si : (double)si);
+        if (shat) shat[i] = (V)(dinv ? (double)d0 * (double)si : (double)si);
         ss += (double)si * (double)si;
     };
 #pragma unroll
@@ -625,6 +626,33 @@ __global__ __launch_bounds__(kWG) void k_stream_dot(int64_t n2, const dvec2 *__r
     publish<1>(v, parts, L);
 }
 
+// Read-only sum of a with ordinary (temporal) loads, `sweeps` times over the
+// array in one launch.  Ordinary loads allocate in L2 and the last-level
+// cache, and each workgroup re-reads its own band, so over an array whose
+// per-XCD band fits L2 (or whose whole fits the last-level cache) every
+// sweep after the first measures that cache's read bandwidth; one sweep over
+// a large array calibrates the fetch counters for ordinary loads (the other
+// stream kernels stream with nontemporal loads).
+__global__ __launch_bounds__(kWG) void k_stream_read(int64_t n2, const dvec2 *__restrict__ a, int sweeps,
+                                                     double *__restrict__ parts) {
+    MXL_RANGE(n2)
+    double acc = 0.0;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        MXL_FOR(i, n2) {
+            const dvec2 x = a[i];
+            acc += x.x + x.y;
+        }
+    }
+    double v[1] = {acc};
+    publish<1>(v, parts, L);
+}
+
+// Sweeps of the cached read: enough to read 2^28 values in one launch.
+int stream_read_sweeps(int64_t n) {
+    const int64_t target = (int64_t)1 << 28;
+    return n >= target ? 1 : (int)((target + n - 1) / n);
+}
+
 hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a, const double *b,
                          double *c, hipStream_t s) {
     const int64_t n2 = n / 2;
@@ -633,6 +661,9 @@ hipError_t launch_stream(const mxl_ctx *ctx, int op, int64_t n, const double *a,
     case 0: hipLaunchKernelGGL(k_stream_copy, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a, (dvec2 *)c); break;
     case 1: hipLaunchKernelGGL(k_stream_triad, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a, (const dvec2 *)b, 0.5, (dvec2 *)c); break;
     case 2: hipLaunchKernelGGL(k_stream_dot, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a, (const dvec2 *)b, c); break;
+    case 3: hipLaunchKernelGGL(k_stream_read, dim3(G), dim3(kWG), 0, s, n2, (const dvec2 *)a,
+                               stream_read_sweeps(n), c);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1122,13 +1122,16 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
     }
     int64_t k = 0;
     int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
-    // block Jacobi: the fused kernels copy p and s (no scaling), and the
-    // block products p_hat = M p, s_hat = M s follow as kernels of their own
+    // block Jacobi: the block products p_hat = M p, s_hat = M s follow the
+    // fused kernels as kernels of their own
     const bool blockp = S.P && S.P->block;
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         ++k;
-        HIP_TRY(bi_pupdate(ctx, dt, n, S.r->p, S.p->p, S.v->p, phat, dinv, st, pC, gv, (int)k, hist, s));
-        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.p->p, 0.0, phat, s));
+        // with block Jacobi the fused kernels store no p_hat / s_hat (NULL):
+        // the block products write them
+        HIP_TRY(bi_pupdate(ctx, dt, n, S.r->p, S.p->p, S.v->p, blockp ? nullptr : phat, dinv, st, pC, gv, (int)k,
+                           hist, s));
+        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.p->p, 0.0, phat, s, &st->stop));
         SpmvArgs a;
         a.x = phat;
         a.y = S.v->p;
@@ -1136,8 +1139,9 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
         a.w = S.rhat->p;
         a.partials = pA;
         HIP_TRY(spmv_launch(A, a, s));
-        HIP_TRY(bi_supdate(ctx, dt, n, S.r->p, S.v->p, S.s->p, shat, dinv, st, pA, gs, pB, (int)k, s));
-        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.s->p, 0.0, shat, s));
+        HIP_TRY(bi_supdate(ctx, dt, n, S.r->p, S.v->p, S.s->p, blockp ? nullptr : shat, dinv, st, pA, gs, pB,
+                           (int)k, s));
+        if (blockp) HIP_TRY(bj_apply(ctx, *S.P, n, 1.0, S.s->p, 0.0, shat, s, &st->stop));
         SpmvArgs t;
         t.x = shat;
         t.y = S.t->p;
@@ -1552,14 +1556,14 @@ extern "C" mxl_status mxl_time_apply(const mxl_op *Aop, const void *x, void *y, 
 
 extern "C" mxl_status mxl_stream_bench(mxl_ctx *ctx, int op, int64_t n, const double *a,
                                        const double *b, double *c, int reps, double *median_ms) try {
-    if (!ctx || !median_ms || reps < 1 || n < 2 || (n & 1) || op < 0 || op > 2)
-        return fail(MXL_ERR_INVALID_ARG, "stream: op in 0..2, even n >= 2, reps >= 1");
+    if (!ctx || !median_ms || reps < 1 || n < 2 || (n & 1) || op < 0 || op > 3)
+        return fail(MXL_ERR_INVALID_ARG, "stream: op in 0..3, even n >= 2, reps >= 1");
     DeviceScope ds(ctx->device);
     mxl_status st;
     const size_t bytes = (size_t)n * 8;
     if ((st = check_dev(ctx, a, bytes, "a")) != MXL_OK) return st;
-    if (op != 0 && (st = check_dev(ctx, b, bytes, "b")) != MXL_OK) return st;
-    const size_t cbytes = op == 2 ? (size_t)ctx->num_cu * 8 * 8 : bytes;
+    if ((op == 1 || op == 2) && (st = check_dev(ctx, b, bytes, "b")) != MXL_OK) return st;
+    const size_t cbytes = op >= 2 ? (size_t)ctx->num_cu * 8 * 8 : bytes;
     if ((st = check_dev(ctx, c, cbytes, "c")) != MXL_OK) return st;
     hipStream_t s = ctx->stream;
     hipEvent_t e0, e1;

@@ -192,9 +192,23 @@ __global__ __launch_bounds__(kWG) void k_csr_stream(int64_t nblk, const int2 *__
             e1 = blk[bn + 1];
         }
         const int r0 = d0.x, k0 = d0.y, nr = d1.x - d0.x, k1 = d1.y;
-        if (k1 - k0 > kStreamK * kWave) {  // one long row
+        if (k1 - k0 > kStreamK * kWave) {  // one long row, kStreamK loads per lane in flight
             V acc = 0;
-            for (int k = k0 + lane; k < k1; k += kWave) acc += ld_stream(val + k) * p.x[ld_stream(col + k)];
+            for (int kb = k0; kb < k1; kb += kStreamK * kWave) {
+                int c[kStreamK];
+                V v[kStreamK];
+#pragma unroll
+                for (int j = 0; j < kStreamK; ++j) {
+                    const int k = kb + lane + kWave * j;
+                    const bool in = k < k1;
+                    c[j] = in ? ld_stream(col + k) : -1;
+                    v[j] = in ? ld_stream(val + k) : (V)0;
+                }
+                // same order as one entry at a time: k = lane, lane + 64, ...
+#pragma unroll
+                for (int j = 0; j < kStreamK; ++j)
+                    if (c[j] >= 0) acc += v[j] * p.x[c[j]];
+            }
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
             if (lane == 0) {
@@ -564,6 +578,7 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
     int ts;
     band_walk(ntiles, blockIdx.x, gridDim.x, t0, t1, ts);
     double dacc = 0.0;
+    const bool yvec = ((uintptr_t)p.y & (sizeof(V) * R - 1)) == 0;  // y aligned for R-row vectors
     for (int64_t tile = t0; tile < t1; tile += ts) {
         const int64_t row0 = tile * kWG * R + (int64_t)threadIdx.x * R;
         bool staged = false;
@@ -621,13 +636,30 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                     for (int r = 0; r < R; ++r)
                         if (ci[u][r] >= 0) acc[r] += lane_of<R>(v[u], r) * xv[u][r];
             }
+            if (R > 1 && yvec && row0 + R <= n) {
+                // the thread's R outputs as one vector store (two half-line
+                // stores per line cost twice the write traffic)
+                VV yo, yi;
+                if (!p.beta_zero) yi = *(const VV *)(p.y + row0);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t row = row0 + r;
-                if (row < n) {
-                    V out = combine(p, acc[r], row);
-                    p.y[row] = out;
-                    if (DOT) dacc += (double)p.w[row] * (double)out;
+                for (int r = 0; r < R; ++r) {
+                    V out;
+                    if constexpr (R == 1) out = p.beta_zero ? p.alpha * acc[r] : p.alpha * acc[r] + p.beta * yi;
+                    else out = p.beta_zero ? p.alpha * acc[r] : p.alpha * acc[r] + p.beta * yi[r];
+                    if constexpr (R == 1) yo = out;
+                    else yo[r] = out;
+                    if (DOT) dacc += (double)p.w[row0 + r] * (double)out;
+                }
+                *(VV *)(p.y + row0) = yo;
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t row = row0 + r;
+                    if (row < n) {
+                        V out = combine(p, acc[r], row);
+                        p.y[row] = out;
+                        if (DOT) dacc += (double)p.w[row] * (double)out;
+                    }
                 }
             }
         }
@@ -873,7 +905,7 @@ static int plain_grid(const MatrixImpl &A, int64_t tiles) {
     return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
 }
 
-constexpr int kDotSlotCap = 4096;  // partial slots a fused-dot launch may publish
+constexpr int kDotSlotCap = 8192;  // partial slots a fused-dot launch may publish
 
 // Grids of the wave-walker kernels (4 walking waves per workgroup): a
 // multiple of 8 workgroups keeps each walker on its XCD's band.
