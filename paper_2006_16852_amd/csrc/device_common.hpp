@@ -88,12 +88,12 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
-// Reduce NV doubles over the 256-thread workgroup (fixed tree: shuffle within
-// each wave, then the four wave results in order).  Result valid in thread 0.
+// Reduce NV doubles over the B-thread workgroup (fixed tree: shuffle within
+// each wave, then the wave results in order).  Result valid in thread 0.
 // mask selects which values are max-reductions instead of sums.
-template <int NV>
+template <int NV, int B = kWG>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned max_mask = 0) {
-    __shared__ double red_smem[kWG / kWave][NV > 0 ? NV : 1];
+    __shared__ double red_smem[B / kWave][NV > 0 ? NV : 1];
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = (max_mask >> j & 1) ? wave_max(v[j]) : wave_sum(v[j]);
@@ -107,7 +107,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned max_mask 
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
             double a = red_smem[0][j];
-            for (int w = 1; w < kWG / kWave; ++w) {
+            for (int w = 1; w < B / kWave; ++w) {
                 double b = red_smem[w][j];
                 a = (max_mask >> j & 1) ? (b > a ? b : a) : a + b;
             }
@@ -122,10 +122,10 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], unsigned max_mask 
 // stores: the consumer is a later kernel, and the kernel boundary makes them
 // visible on every XCD.  (A per-workgroup device-scope fence would write
 // back the whole L2 of the XCD for every workgroup.)
-template <int NV>
+template <int NV, int B = kWG>
 __device__ __forceinline__ void publish(double (&v)[NV], double *partials, int slot,
                                         unsigned max_mask = 0) {
-    block_reduce<NV>(v, max_mask);
+    block_reduce<NV, B>(v, max_mask);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) partials[(int64_t)slot * NV + j] = v[j];
@@ -136,7 +136,7 @@ __device__ __forceinline__ void publish(double (&v)[NV], double *partials, int s
 // slots [0, nslots) (fixed striding, fixed tree), so a consumer kernel can
 // take the same scalar decisions in all of its workgroups without any
 // inter-workgroup communication.
-// A thread's slots are t, t + 256, t + 512, ...; a batch of U rounds of
+// A thread's slots are t, t + B, t + 2B, ...; a batch of U rounds of
 // them is loaded before any is added, so one round trip to L2 serves U slots
 // (a loop that adds each value as it arrives waits once per slot), and the
 // values are added in slot order, so the sum does not depend on U.  Whether
@@ -144,7 +144,7 @@ __device__ __forceinline__ void publish(double (&v)[NV], double *partials, int s
 // complete batches load without per-slot predicates.  U shrinks as NV grows
 // to keep the batch at 8 doubles per thread: the update kernels hold their
 // prefetched operands in registers at the same time.
-template <int NV>
+template <int NV, int B = kWG>
 __device__ __forceinline__ void gather_all(const double *__restrict__ partials, int nslots,
                                            double (&tot)[NV], unsigned max_mask = 0) {
     constexpr int U = NV <= 1 ? 8 : (NV == 2 ? 4 : 2);
@@ -154,21 +154,21 @@ __device__ __forceinline__ void gather_all(const double *__restrict__ partials, 
     auto add = [&](int j, double v) {
         tot[j] = (max_mask >> j & 1) ? (v > tot[j] ? v : tot[j]) : tot[j] + v;
     };
-    const int full = nslots / kWG;  // rounds in which every thread has a slot
-    for (int r0 = 0; r0 * kWG < nslots; r0 += U) {
+    const int full = nslots / B;  // rounds in which every thread has a slot
+    for (int r0 = 0; r0 * B < nslots; r0 += U) {
         if (r0 + U <= full) {
             double buf[U][NV > 0 ? NV : 1];
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int j = 0; j < NV; ++j) buf[u][j] = partials[(int64_t)((r0 + u) * kWG + threadIdx.x) * NV + j];
+                for (int j = 0; j < NV; ++j) buf[u][j] = partials[(int64_t)((r0 + u) * B + threadIdx.x) * NV + j];
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int j = 0; j < NV; ++j) add(j, buf[u][j]);
         } else {
             for (int u = 0; u < U; ++u) {
-                const int s = (r0 + u) * kWG + threadIdx.x;
+                const int s = (r0 + u) * B + threadIdx.x;
                 if (s < nslots) {
 #pragma unroll
                     for (int j = 0; j < NV; ++j) add(j, partials[(int64_t)s * NV + j]);
@@ -176,7 +176,7 @@ __device__ __forceinline__ void gather_all(const double *__restrict__ partials, 
             }
         }
     }
-    block_reduce<NV>(tot, max_mask);
+    block_reduce<NV, B>(tot, max_mask);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) bc[j] = tot[j];

@@ -254,6 +254,7 @@ hipError_t launch_convert_vals(int64_t n, int from, const void *in, void *out, h
 constexpr int kSolverSlots = 8192;  // partial slots per reduction region
 constexpr int kRegions = 4;         // partial regions A..D, 3 doubles per slot
 int vec_grid(const mxl_ctx *ctx, int64_t n);
+int cg_update_grid(const mxl_ctx *ctx, int64_t n);  // grid (and partial count) of cg_update / cg_pupdate
 hipError_t launch_finalize(int nv, const double *parts, int slots, SolverState *st, int op, int k,
                            int max_iters, double *hist, hipStream_t s);
 hipError_t launch_jacobi_apply(int dtype, int64_t n, double alpha, const void *dinv, const void *b,

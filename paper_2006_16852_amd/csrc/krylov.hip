@@ -30,6 +30,13 @@ namespace mxl {
 
 #define MXL_LEAD (blockIdx.x == 0 && threadIdx.x == 0)
 
+// The same walk for B-thread workgroups (tiles of B elements or chunks).
+#define MXL_RANGE_B(n, B)                                            \
+    const int L = blockIdx.x;                                        \
+    int64_t tb_, te_;                                                \
+    int ts_;                                                         \
+    band_walk(((n) + (B) - 1) / (B), blockIdx.x, gridDim.x, tb_, te_, ts_);
+
 template <typename V>
 __device__ __forceinline__ double prec_z(const V *dinv, int64_t i, V r) {
     return dinv ? (double)dinv[i] * (double)r : (double)r;
@@ -76,10 +83,18 @@ __global__ __launch_bounds__(kWG) void k_cg_init(int64_t n, const V *__restrict_
 // reduction instead of every workgroup paying the two in sequence.
 constexpr int kPf = 2;
 
-#define MXL_PF_INDEX(u, cnt)                                   \
+#define MXL_PF_INDEX_B(u, cnt, B)                               \
     const int64_t t_##u = tb_ + (int64_t)(u) * ts_;             \
-    const int64_t i_##u = t_##u * kWG + threadIdx.x;            \
+    const int64_t i_##u = t_##u * (B) + threadIdx.x;            \
     const bool in_##u = t_##u < te_ && i_##u < (cnt);
+#define MXL_PF_INDEX(u, cnt) MXL_PF_INDEX_B(u, cnt, kWG)
+
+// The CG update kernels run B = kCgWG threads per workgroup: every workgroup
+// of a consumer reduces all partials of the kernel before it, so fewer,
+// larger workgroups read fewer partials in all (half of the 256-thread
+// workgroups' traffic, and the gather of 4,096 partials costs each launch
+// about 4 us less on the 128^3 system).
+constexpr int kCgWG = 512;
 
 // A thread of the CG update kernels owns chunks of E consecutive elements:
 // E = 2 for FP32 vectors (one 8-byte load per array, as wide as an FP64
@@ -142,7 +157,7 @@ __device__ __forceinline__ void st_chunk(V *__restrict__ p, int64_t c, int64_t n
 // r -= alpha q and the reductions r.z, r.r.  The matching x += alpha p is
 // applied by k_cg_pupdate, which reads p anyway, so p is read once less.
 template <typename V, int E>
-__global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r, const V *__restrict__ q,
+__global__ __launch_bounds__(kCgWG) void k_cg_update(int64_t n, V *__restrict__ r, const V *__restrict__ q,
                                                    const V *__restrict__ dinv, SolverState *st,
                                                    const double *__restrict__ pq_parts, int pq_slots,
                                                    double *__restrict__ parts, int k) {
@@ -152,17 +167,17 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r,
     }
     typedef Chunk<V, E> CV;
     const int64_t nc = (n + E - 1) / E;
-    MXL_RANGE(nc)
+    MXL_RANGE_B(nc, kCgWG)
     CV rv[kPf], qv[kPf], dv[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u, nc)
+        MXL_PF_INDEX_B(u, nc, kCgWG)
         rv[u] = in_u ? ld_chunk<V, E>(r, i_u, n) : fill_chunk<V, E>(0);
         qv[u] = in_u ? ld_chunk<V, E>(q, i_u, n) : fill_chunk<V, E>(0);
         dv[u] = in_u && dinv ? ld_chunk<V, E>(dinv, i_u, n) : fill_chunk<V, E>(1);
     }
     double eta[1];
-    gather_all<1>(pq_parts, pq_slots, eta);
+    gather_all<1, kCgWG>(pq_parts, pq_slots, eta);
     const bool chk = st->nonfinite_check != 0;
     const bool nonfin = chk && !finite_d(eta[0]);
     if (nonfin || eta[0] <= 0.0) {  // not positive definite along p
@@ -199,21 +214,21 @@ __global__ __launch_bounds__(kWG) void k_cg_update(int64_t n, V *__restrict__ r,
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u, nc)
+        MXL_PF_INDEX_B(u, nc, kCgWG)
         if (in_u) step(i_u, rv[u], qv[u], dv[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
-        if (const int64_t c = t_ * kWG + threadIdx.x; c < nc)
+        if (const int64_t c = t_ * kCgWG + threadIdx.x; c < nc)
             step(c, ld_chunk<V, E>(r, c, n), ld_chunk<V, E>(q, c, n),
                  dinv ? ld_chunk<V, E>(dinv, c, n) : fill_chunk<V, E>(1));
     double v[2] = {rz, rr};
-    publish<2>(v, parts, L);
+    publish<2, kCgWG>(v, parts, L);
 }
 
 // Consumes r.z and r.r: x += alpha p (alpha from k_cg_update), the
 // criterion of iteration k, then p = z + beta p unless the solve stops.
 template <typename V, int E>
-__global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x, const V *__restrict__ r,
+__global__ __launch_bounds__(kCgWG) void k_cg_pupdate(int64_t n, V *__restrict__ x, const V *__restrict__ r,
                                                     V *__restrict__ p, const V *__restrict__ dinv,
                                                     SolverState *st, const double *__restrict__ parts,
                                                     int slots, int k, double *hist) {
@@ -222,18 +237,19 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     if (st->ustop) return;
     typedef Chunk<V, E> CV;
     const int64_t nc = (n + E - 1) / E;
-    MXL_RANGE(nc)
+    MXL_RANGE_B(nc, kCgWG)
+    (void)L;
     CV xv[kPf], rv[kPf], pv[kPf], dv[kPf];
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u, nc)
+        MXL_PF_INDEX_B(u, nc, kCgWG)
         xv[u] = in_u ? ld_chunk<V, E>(x, i_u, n) : fill_chunk<V, E>(0);
         rv[u] = in_u ? ld_chunk<V, E>(r, i_u, n) : fill_chunk<V, E>(0);
         pv[u] = in_u ? ld_chunk<V, E>(p, i_u, n) : fill_chunk<V, E>(0);
         dv[u] = in_u && dinv ? ld_chunk<V, E>(dinv, i_u, n) : fill_chunk<V, E>(1);
     }
     double t[2];
-    gather_all<2>(parts, slots, t);
+    gather_all<2, kCgWG>(parts, slots, t);
     const double rz = t[0], rr = t[1];
     const double alpha = st->alpha;
     const bool chk = st->nonfinite_check != 0;
@@ -258,11 +274,11 @@ __global__ __launch_bounds__(kWG) void k_cg_pupdate(int64_t n, V *__restrict__ x
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-        MXL_PF_INDEX(u, nc)
+        MXL_PF_INDEX_B(u, nc, kCgWG)
         if (in_u) step(i_u, xv[u], rv[u], pv[u], dv[u]);
     }
     for (int64_t t_ = tb_ + (int64_t)kPf * ts_; t_ < te_; t_ += ts_)
-        if (const int64_t c = t_ * kWG + threadIdx.x; c < nc)
+        if (const int64_t c = t_ * kCgWG + threadIdx.x; c < nc)
             step(c, ld_chunk<V, E>(x, c, n), run ? ld_chunk<V, E>(r, c, n) : fill_chunk<V, E>(0),
                  ld_chunk<V, E>(p, c, n),
                  run && dinv ? ld_chunk<V, E>(dinv, c, n) : fill_chunk<V, E>(1));
@@ -770,10 +786,19 @@ static bool aligned8(std::initializer_list<const void *> ps) {
     return true;
 }
 
+// Grid of the CG update kernels (kCgWG threads): four tiles per workgroup,
+// at most four workgroups per CU.  k_cg_update publishes this many partials.
+int cg_update_grid(const mxl_ctx *ctx, int64_t n) {
+    int64_t want = (n + (int64_t)kCgWG * 4 - 1) / ((int64_t)kCgWG * 4);
+    const int cap = ctx->num_cu * 4;
+    if (want < 1) want = 1;
+    return (int)(want < cap ? want : cap);
+}
+
 hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *r, const void *q, const void *dinv,
                      SolverState *st, const double *pq_parts, int pq_slots, double *parts, int k,
                      hipStream_t s) {
-    const dim3 g(vec_grid(ctx, n)), b(kWG);
+    const dim3 g(cg_update_grid(ctx, n)), b(kCgWG);
     if (dtype == MXL_F64)
         hipLaunchKernelGGL((k_cg_update<double, 1>), g, b, 0, s, n, (double *)r, (const double *)q,
                            (const double *)dinv, st, pq_parts, pq_slots, parts, k);
@@ -789,7 +814,7 @@ hipError_t cg_update(const mxl_ctx *ctx, int dtype, int64_t n, void *r, const vo
 hipError_t cg_pupdate(const mxl_ctx *ctx, int dtype, int64_t n, void *x, const void *r, void *p,
                       const void *dinv, SolverState *st, const double *parts, int slots, int k,
                       double *hist, hipStream_t s) {
-    const dim3 g(vec_grid(ctx, n)), b(kWG);
+    const dim3 g(cg_update_grid(ctx, n)), b(kCgWG);
     if (dtype == MXL_F64)
         hipLaunchKernelGGL((k_cg_pupdate<double, 1>), g, b, 0, s, n, (double *)x, (const double *)r,
                            (double *)p, (const double *)dinv, st, parts, slots, k, hist);

@@ -1023,7 +1023,8 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
             HIP_TRY(cg_pupdate(ctx, dt, n, x, S.z->p, S.p->p, nullptr, st, pB, gv, (int)k, hist, s));
         } else {
             HIP_TRY(cg_update(ctx, dt, n, S.r->p, S.q->p, dinv, st, pA, gs, pB, (int)k, s));
-            HIP_TRY(cg_pupdate(ctx, dt, n, x, S.r->p, S.p->p, dinv, st, pB, gv, (int)k, hist, s));
+            HIP_TRY(cg_pupdate(ctx, dt, n, x, S.r->p, S.p->p, dinv, st, pB, cg_update_grid(ctx, n), (int)k, hist,
+                               s));
         }
         if (k % c.check_every == 0 || k == c.max_iters) {
             if ((rs = read_state(S, h)) != MXL_OK) return rs;
