@@ -229,15 +229,23 @@ __global__ __launch_bounds__(kWG) void k_csr_stream(int64_t nblk, const int2 *__
             }
 #pragma unroll
             for (int j = 0; j < kStreamK; ++j) sp[lane + kWave * j] = c[j] >= 0 ? v[j] * p.x[c[j]] : (V)0;
-            const int re = __shfl(rs, lane + 1 < kWave ? lane + 1 : kWave - 1, kWave);
+            // each row of the block gets g = 2^lg lanes (as many as 64 / nr
+            // allows, at most 8): lane l sums every g-th product of row l >> lg
+            // from offset l & (g - 1), and the g partial sums meet by shuffles
+            const int lg = nr <= 8 ? 3 : (nr <= 16 ? 2 : (nr <= 32 ? 1 : 0));
+            const int myrow = lane >> lg, part = lane & ((1 << lg) - 1);
+            const int rs_m = __shfl(rs, myrow < kWave ? myrow : kWave - 1, kWave);
+            const int re_m = __shfl(rs, myrow + 1 < kWave ? myrow + 1 : kWave - 1, kWave);
             // products visible to the other lanes of this wave (LDS is in order per wave)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < nr) {
-                V acc = 0;
-                for (int k = rs - k0; k < re - k0; ++k) acc += sp[k];
-                const int64_t row = (int64_t)r0 + lane;
+            V acc = 0;
+            if (myrow < nr)
+                for (int k = rs_m - k0 + part; k < re_m - k0; k += 1 << lg) acc += sp[k];
+            for (int off = 1; off < (1 << lg); off <<= 1) acc += __shfl_xor(acc, off, kWave);
+            if (myrow < nr && part == 0) {
+                const int64_t row = (int64_t)r0 + myrow;
                 const V out = combine(p, acc, row);
                 p.y[row] = out;
                 if (DOT) dacc += (double)p.w[row] * (double)out;
