@@ -135,6 +135,16 @@ struct IluImpl {
     int sweeps = 0, trisolve = 0, trs_sweeps = 0;
     BufPtr lu, dpos, lperm, uperm, y, t, z;
     std::vector<int64_t> lptr, uptr;
+    // exact solves: the level offsets on the device (runs of small levels are
+    // solved by one workgroup in one launch) and the schedule of launches
+    BufPtr lptr_d, uptr_d;
+    std::vector<int2> lruns, uruns;  // (first level, end level): a run of small levels, or one level
+    // each triangle's strict entries in level order, slot-major [w][n_pad]
+    // (position t of the level schedule at slot*n_pad + t; column -1 pads),
+    // and diag(U) in upper level order; NULL when the padding would exceed
+    // 4x the factor storage (the solves then walk the CSR rows)
+    int lw_lv = 0, uw_lv = 0;
+    BufPtr lcol_lv, lval_lv, ucol_lv, uval_lv, udiag_lv;
     // slot-major strict triangles and diag(U) for the Jacobi sweeps (optional)
     int wl = 0, wu = 0;
     int64_t n_pad = 0;
