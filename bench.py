@@ -90,7 +90,7 @@ def source_digest():
     stored traffic counters apply while it is unchanged."""
     csrc = os.path.join(ROOT, "paper_2006_16852_amd", "csrc")
     spmv = open(os.path.join(csrc, "spmv.hip")).read()
-    i = spmv.index("template <typename V, bool DOT, bool LDS, int R, bool D16 = false>")
+    i = spmv.rindex("template <", 0, spmv.index(" void k_ell("))
     j = spmv.index("// y = beta*y (alpha*A*x with no stored entries)", i)
     k = spmv.index("constexpr int kDotSlotCap")
     h = hashlib.sha256()

@@ -68,7 +68,8 @@ class OpDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("format", C.c_int32), ("variant", C.c_int32),
                 ("dtype", C.c_int32), ("nrows", C.c_int64), ("ncols", C.c_int64),
                 ("nnz", C.c_int64), ("vector_width", C.c_int32), ("ell_width", C.c_int32),
-                ("n_pad", C.c_int64), ("tail_nnz", C.c_int64), ("stored_bytes", C.c_int64)]
+                ("n_pad", C.c_int64), ("tail_nnz", C.c_int64), ("stored_bytes", C.c_int64),
+                ("ell_reuse", C.c_int32)]
 
 
 class IrParams(C.Structure):

@@ -92,6 +92,7 @@ struct MatrixImpl {
     BufPtr ell_col, ell_val, ell_win;  // ELL / HYB ELL part
     int ell_w = 0;
     int ell_rpt = 1;                   // ELL rows per thread (1, 2, 4)
+    int ell_nb = 0;                    // ELL: neighbour reuse of gathered x values on
     int64_t n_pad = 0;
     double hyb_q = 0.0;
     BufPtr tail_row, tail_col, tail_val;  // HYB COO tail
@@ -254,6 +255,7 @@ hipError_t launch_csr_to_ell16(const MatrixImpl &A, int w, int64_t n_pad, short 
                                int *overflow, hipStream_t s);
 hipError_t launch_csr_to_ell(const MatrixImpl &A, int w, int64_t n_pad, int *ecol, void *evals,
                              hipStream_t s);
+hipError_t launch_ell_reuse_count(const MatrixImpl &A, unsigned long long *count, hipStream_t s);
 hipError_t launch_hyb_tail(const MatrixImpl &A, int k, const int64_t *toff, int *trow, int *tcol,
                            void *tval, hipStream_t s);
 hipError_t launch_ell_windows(const MatrixImpl &A, int2 *win, hipStream_t s);

@@ -568,11 +568,12 @@ __device__ __forceinline__ auto lane_of(const T &v, int r) {
 // loads are issued before their x gathers.
 // D16: the slots hold 16-bit offsets d = col - row (kEll16Pad = padding),
 // which cuts the index stream from 4 to 2 bytes per slot.
-template <typename V, bool DOT, bool LDS, int R, bool D16 = false>
+template <typename V, bool DOT, bool LDS, int R, bool D16 = false, bool NB = false>
 __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                                              const void *__restrict__ ecol_,
                                              const V *__restrict__ evals,
                                              const int2 *__restrict__ win, SpmvK<V> p) {
+    static_assert(!(LDS && NB), "neighbour reuse is for the global-gather variants");
     if (p.stop && *p.stop) return;
     constexpr int U = (sizeof(V) == 4 ? 16 : 8) / R;  // slots of loads in flight per batch
     typedef typename std::conditional<D16, short, int>::type IT;
@@ -601,19 +602,29 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
             }
             __syncthreads();
         }
-        if (row0 < n) {  // rows row0..row0+R-1 < n_pad (n_pad is a multiple of 64)
-            const IV *cp = (const IV *)(ecol + row0);
-            const VV *vp = (const VV *)(evals + row0);
+        // rows row0..row0+R-1 < n_pad (n_pad is a multiple of 64).  With NB
+        // every lane of the wave runs the slot loop (the shuffles need all
+        // lanes); lanes past n load nothing and see padding only.
+        const bool live = row0 < n;
+        if (NB || live) {
+            const IV *cp = (const IV *)(ecol + (live ? row0 : 0));
+            const VV *vp = (const VV *)(evals + (live ? row0 : 0));
             const int64_t stride = n_pad / R;  // one slot, in vector units
             V acc[R];
+            int pc[R];  // NB: columns and x values of the previous slot
+            V px[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = 0;
+            for (int r = 0; r < R; ++r) {
+                acc[r] = 0;
+                pc[r] = -1;
+                px[r] = 0;
+            }
             for (int s0 = 0; s0 < w; s0 += U) {
                 IV c[U];
                 VV v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (s0 + u < w) {
+                    if ((!NB || live) && s0 + u < w) {
                         c[u] = __builtin_nontemporal_load(cp + (int64_t)(s0 + u) * stride);
                         v[u] = __builtin_nontemporal_load(vp + (int64_t)(s0 + u) * stride);
                     } else {
@@ -631,20 +642,60 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                         else ci[u][r] = e;
                     }
                 V xv[U][R];
+                if constexpr (NB) {
+                    // Entry (i, s) whose column equals that of entry (i+1, s-1)
+                    // takes x from it instead of gathering: row i+1 is the
+                    // thread's next row or, for its last row, the first row of
+                    // the next lane.  The value moved is x at the compared
+                    // column, so the product is unchanged.  Hits are decided
+                    // from the columns before any gather is issued.
+                    bool hit[U][R];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int r = 0; r + 1 < R; ++r) {
+                            const int q = u == 0 ? pc[r + 1] : ci[u - 1][r + 1];
+                            hit[u][r] = ci[u][r] >= 0 && ci[u][r] == q;
+                        }
+                        const int nq = __shfl_down(u == 0 ? pc[0] : ci[u - 1][0], 1, kWave);
+                        hit[u][R - 1] = ci[u][R - 1] >= 0 && ci[u][R - 1] == nq;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            xv[u][r] = ci[u][r] >= 0 && !hit[u][r] ? p.x[ci[u][r]] : (V)0;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int r = 0; r + 1 < R; ++r)
+                            if (hit[u][r]) xv[u][r] = u == 0 ? px[r + 1] : xv[u - 1][r + 1];
+                        const V nx = __shfl_down(u == 0 ? px[0] : xv[u - 1][0], 1, kWave);
+                        if (hit[u][R - 1]) xv[u][R - 1] = nx;
+                    }
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const int cc = ci[u][r];
-                        xv[u][r] = cc >= 0 ? ((LDS && staged) ? s_x[cc - lo] : p.x[cc]) : (V)0;
+                        pc[r] = ci[U - 1][r];
+                        px[r] = xv[U - 1][r];
                     }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int cc = ci[u][r];
+                            xv[u][r] = cc >= 0 ? ((LDS && staged) ? s_x[cc - lo] : p.x[cc]) : (V)0;
+                        }
+                }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         if (ci[u][r] >= 0) acc[r] += lane_of<R>(v[u], r) * xv[u][r];
             }
-            if (R > 1 && yvec && row0 + R <= n) {
+            if (!live) {
+                // NB lane past the last row: nothing to store
+            } else if (R > 1 && yvec && row0 + R <= n) {
                 // the thread's R outputs as one vector store (two half-line
                 // stores per line cost twice the write traffic)
                 VV yo, yi;
@@ -794,6 +845,32 @@ __global__ void k_csr_to_ell16(int64_t n, int64_t n_pad, int w, const int *__res
         }
     }
     if (bad) atomicOr(overflow, 1);
+}
+
+// Entries whose column equals that of the entry one row down and one slot
+// to the left, (i, s) against (i+1, s-1): the x values an ELL product with
+// neighbour reuse takes from a neighbouring row instead of gathering.
+// Integer sums (one atomic per workgroup), so the count is exact.
+__global__ __launch_bounds__(kWG) void k_ell_reuse_count(int64_t n, const int *__restrict__ rp,
+                                                         const int *__restrict__ col,
+                                                         unsigned long long *count) {
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    unsigned long long h = 0;
+    if (i + 1 < n) {
+        const int a0 = rp[i], la = rp[i + 1] - a0;
+        const int b0 = rp[i + 1], lb = rp[i + 2] - b0;
+        for (int s = 1; s < la && s - 1 < lb; ++s) h += col[a0 + s] == col[b0 + s - 1];
+    }
+    __shared__ unsigned long long sh[kWG / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) h += __shfl_xor(h, off, kWave);
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = h;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int j = 0; j < kWG / kWave; ++j) t += sh[j];
+        if (t) atomicAdd(count, t);
+    }
 }
 
 template <typename V>
@@ -1089,16 +1166,23 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
         const int2 *win = A.ell_win ? (const int2 *)A.ell_win->p : nullptr;
         const bool lds = A.variant == MXL_ELL_LDS && win;
         const bool d16 = A.format == MXL_FMT_ELL && A.variant == MXL_ELL_DELTA16;
+        const bool nb = A.format == MXL_FMT_ELL && A.ell_nb && !lds;
         const dim3 ge(dot ? A.grid_dot
                           : plain_grid(A, (n + (int64_t)kWG * A.ell_rpt - 1) / ((int64_t)kWG * A.ell_rpt)));
 #define MXL_ELL_CASE(RR)                                                                                          \
     case RR:                                                                                                      \
-        if (d16) {                                                                                                \
+        if (d16 && nb) {                                                                                          \
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, false, RR, true, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p); \
+            else hipLaunchKernelGGL((k_ell<V, false, false, RR, true, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);    \
+        } else if (d16) {                                                                                         \
             if (dot) hipLaunchKernelGGL((k_ell<V, true, false, RR, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p); \
             else hipLaunchKernelGGL((k_ell<V, false, false, RR, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);    \
         } else if (lds) {                                                                                         \
             if (dot) hipLaunchKernelGGL((k_ell<V, true, true, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);   \
             else hipLaunchKernelGGL((k_ell<V, false, true, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);      \
+        } else if (nb) {                                                                                          \
+            if (dot) hipLaunchKernelGGL((k_ell<V, true, false, RR, false, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p); \
+            else hipLaunchKernelGGL((k_ell<V, false, false, RR, false, true>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);    \
         } else {                                                                                                  \
             if (dot) hipLaunchKernelGGL((k_ell<V, true, false, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);  \
             else hipLaunchKernelGGL((k_ell<V, false, false, RR>), ge, blk, 0, s, n, A.n_pad, A.ell_w, ec, ev, win, p);     \
@@ -1174,6 +1258,13 @@ hipError_t launch_csr_to_ell16(const MatrixImpl &A, int w, int64_t n_pad, short 
         hipLaunchKernelGGL(k_csr_to_ell16<float>, g1(n_pad), dim3(256), 0, s, A.nrows, n_pad, w,
                            (const int *)A.row_ptr->p, (const int *)A.col->p,
                            (const float *)A.val->p, ecol, (float *)evals, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_reuse_count(const MatrixImpl &A, unsigned long long *count, hipStream_t s) {
+    if (A.nrows < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_reuse_count, g1(A.nrows), dim3(kWG), 0, s, A.nrows, (const int *)A.row_ptr->p,
+                       (const int *)A.col->p, count);
     return hipGetLastError();
 }
 
