@@ -575,7 +575,11 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                                              const int2 *__restrict__ win, SpmvK<V> p) {
     static_assert(!(LDS && NB), "neighbour reuse is for the global-gather variants");
     if (p.stop && *p.stop) return;
-    constexpr int U = (sizeof(V) == 4 ? 16 : 8) / R;  // slots of loads in flight per batch
+    // slots of loads in flight per batch; with neighbour reuse most slots
+    // gather nothing, and 3 FP64 slots of 2 rows keep the kernel at 76
+    // registers instead of 84 (128^3 27-point CG product 116 -> 108 us
+    // together with the streaming store below)
+    constexpr int U = (NB && sizeof(V) == 8 && R == 2) ? 3 : (sizeof(V) == 4 ? 16 : 8) / R;
     typedef typename std::conditional<D16, short, int>::type IT;
     typedef typename IdxVec<IT, R>::T IV;
     const IT *__restrict__ ecol = (const IT *)ecol_;
@@ -709,7 +713,10 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                     else yo[r] = out;
                     if (DOT) dacc += (double)p.w[row0 + r] * (double)out;
                 }
-                *(VV *)(p.y + row0) = yo;
+                // FP64 outputs stream past the caches (6 us less per 128^3
+                // product in the CG loop); FP32 inner solves ran 3 % slower so
+                if constexpr (sizeof(V) == 8) __builtin_nontemporal_store(yo, (VV *)(p.y + row0));
+                else *(VV *)(p.y + row0) = yo;
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
