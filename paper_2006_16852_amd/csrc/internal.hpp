@@ -233,7 +233,7 @@ struct SpmvArgs {
     const void *x = nullptr;
     void *y = nullptr;
     const int *stop = nullptr;  // skip all work when *stop != 0 (device flag)
-    const void *w = nullptr;    // fused dot w.y (nullable) ...
+    const void *w = nullptr;    // fused dot w.y (nullable; never the output y) ...
     double *partials = nullptr; // ... one partial per workgroup, spmv_slots(A) slots
 };
 

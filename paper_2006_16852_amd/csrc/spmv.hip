@@ -645,6 +645,13 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
         if (NB || live) {
             const IV *cp = (const IV *)(ecol + (live ? row0 : 0));
             const VV *vp = (const VV *)(evals + (live ? row0 : 0));
+            // the fused dot's w rows are loaded with the first slots, not
+            // after the sums (the dependent load at the tile's end cost
+            // 5 us per 128^3 product in the CG loop); w never aliases y
+            VV wpre;
+            const bool wvec = DOT && R > 1 && live && row0 + R <= n &&
+                              ((uintptr_t)p.w & (sizeof(V) * R - 1)) == 0;
+            if (wvec) wpre = *(const VV *)(p.w + row0);
             const int64_t stride = n_pad / R;  // one slot, in vector units
             V acc[R];
             int pc[R];  // NB: columns and x values of the previous slot
@@ -743,7 +750,7 @@ __global__ __launch_bounds__(kWG) void k_ell(int64_t n, int64_t n_pad, int w,
                     else out = p.beta_zero ? p.alpha * acc[r] : p.alpha * acc[r] + p.beta * yi[r];
                     if constexpr (R == 1) yo = out;
                     else yo[r] = out;
-                    if (DOT) dacc += (double)p.w[row0 + r] * (double)out;
+                    if (DOT) dacc += (double)(wvec ? lane_of<R>(wpre, r) : p.w[row0 + r]) * (double)out;
                 }
                 // FP64 outputs stream past the caches (6 us less per 128^3
                 // product in the CG loop); FP32 inner solves ran 3 % slower so
