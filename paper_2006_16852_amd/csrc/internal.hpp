@@ -195,11 +195,15 @@ struct SolverImpl {
     // HIP events of the sampled SpMV timing, kept across solves so that a
     // timed solve creates none
     std::vector<hipEvent_t> spmv_events;
+    // events of the two state snapshots of the trailing host check
+    mutable hipEvent_t chk_ev[2] = {nullptr, nullptr};
     SolverImpl() = default;
     SolverImpl(const SolverImpl &) = delete;
     SolverImpl &operator=(const SolverImpl &) = delete;
     ~SolverImpl() {
         for (hipEvent_t e : spmv_events)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : chk_ev)
             if (e) (void)hipEventDestroy(e);
     }
 };

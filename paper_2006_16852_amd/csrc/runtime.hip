@@ -900,6 +900,42 @@ mxl_status read_state(const SolverImpl &S, SolverState &out) {
     return MXL_OK;
 }
 
+// Host checks that trail the device by one chunk of iterations.  After each
+// chunk the state is copied to one of two pinned slots; the host then waits
+// for the copy made after the chunk before, so the next chunk is already
+// queued while it reads (the GPU does not idle for the host's round trip).
+// A chunk queued after a device-side stop returns at once in every kernel.
+struct TrailingCheck {
+    const SolverImpl &S;
+    int next = 0;
+    bool pending = false;
+    static constexpr size_t kSlot0 = 1024, kSlotBytes = 512;  // offsets in ctx->pinned
+    static_assert(sizeof(SolverState) <= kSlotBytes, "state snapshot slot");
+    explicit TrailingCheck(const SolverImpl &s) : S(s) {}
+    // Snapshot the state after the work queued so far; if an earlier
+    // snapshot is in flight, wait for it and return it in out (have = true).
+    mxl_status step(SolverState &out, bool &have) {
+        mxl_ctx *ctx = S.A->ctx;
+        hipStream_t s = ctx->stream;
+        have = false;
+        if (ctx->pinned_bytes < kSlot0 + 2 * kSlotBytes) return fail(MXL_ERR_INTERNAL, "pinned staging too small");
+        for (int i = 0; i < 2; ++i)
+            if (!S.chk_ev[i]) HIP_TRY(hipEventCreateWithFlags(&S.chk_ev[i], hipEventDisableTiming));
+        char *base = (char *)ctx->pinned + kSlot0;
+        const int slot = next, prev = next ^ 1;
+        HIP_TRY(hipMemcpyAsync(base + slot * kSlotBytes, S.state->p, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(S.chk_ev[slot], s));
+        if (pending) {
+            HIP_TRY(hipEventSynchronize(S.chk_ev[prev]));
+            memcpy(&out, base + prev * kSlotBytes, sizeof(SolverState));
+            have = true;
+        }
+        pending = true;
+        next = prev;
+        return MXL_OK;
+    }
+};
+
 // r = b - A x into S.r
 mxl_status residual(const SolverImpl &S, const void *b, const void *x) {
     const MatrixImpl &A = *S.A;
@@ -1018,6 +1054,7 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
     int64_t iters = 0;
     EventTimer timer(info ? info->time_spmv : 0, s, const_cast<SolverImpl &>(S).spmv_events);
+    TrailingCheck chk(S);
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         ++k;
         timer.begin(k);
@@ -1041,8 +1078,9 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
                                s));
         }
         if (k % c.check_every == 0 || k == c.max_iters) {
-            if ((rs = read_state(S, h)) != MXL_OK) return rs;
-            if (h.stop) {
+            bool have = false;
+            if ((rs = chk.step(h, have)) != MXL_OK) return rs;
+            if (have && h.stop) {
                 stop = map_stop(h.stop);
                 break;
             }
@@ -1053,7 +1091,8 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
         }
     }
     if ((rs = read_state(S, h)) != MXL_OK) return rs;
-    if (stop == MXL_STOP_NONE && h.stop) stop = map_stop(h.stop);
+    // a stop the trailing check had not seen yet decides over max_iters and time
+    if ((stop == MXL_STOP_NONE || stop == MXL_STOP_TIME) && h.stop) stop = map_stop(h.stop);
     if (stop == MXL_STOP_NONE) {
         stop = MXL_STOP_MAX_ITERS;
         iters = k;
@@ -1140,6 +1179,7 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
     // block Jacobi: the block products p_hat = M p, s_hat = M s follow the
     // fused kernels as kernels of their own
     const bool blockp = S.P && S.P->block;
+    TrailingCheck chk(S);
     while (stop == MXL_STOP_NONE && k < c.max_iters) {
         ++k;
         // with block Jacobi the fused kernels store no p_hat / s_hat (NULL):
@@ -1166,8 +1206,9 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
         HIP_TRY(bi_xupdate(ctx, dt, n, x, S.r->p, phat, shat, S.s->p, S.t->p, S.rhat->p, st, pD, gv, pC,
                            (int)k, s));
         if (k % c.check_every == 0 || k == c.max_iters) {
-            if ((rs = read_state(S, h)) != MXL_OK) return rs;
-            if (h.stop) {
+            bool have = false;
+            if ((rs = chk.step(h, have)) != MXL_OK) return rs;
+            if (have && h.stop) {
                 stop = map_stop(h.stop);
                 break;
             }
@@ -1180,7 +1221,8 @@ mxl_status solve_bicgstab(const SolverImpl &S, const void *b, void *x, mxl_solve
     if (stop == MXL_STOP_NONE && k > 0)  // criterion of the last iteration
         HIP_TRY(launch_finalize(3, pC, gv, st, FIN_BI_LAST, (int)k, mi, hist, s));
     if ((rs = read_state(S, h)) != MXL_OK) return rs;
-    if (stop == MXL_STOP_NONE && h.stop) stop = map_stop(h.stop);
+    // a stop the trailing check had not seen yet decides over max_iters and time
+    if ((stop == MXL_STOP_NONE || stop == MXL_STOP_TIME) && h.stop) stop = map_stop(h.stop);
     int64_t iters;
     if (stop == MXL_STOP_NONE) {
         stop = MXL_STOP_MAX_ITERS;
