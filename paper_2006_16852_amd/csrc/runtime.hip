@@ -1021,7 +1021,11 @@ mxl_status solve_cg_single(SolverImpl &S, const void *b, void *x, mxl_solve_info
     return MXL_OK;
 }
 
-mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info *info) {
+// x_zero: x is known to be zero (the inner solve of iterative refinement),
+// so r = b needs no product and the host does not wait for the initial
+// state: a zero b or an initial residual below the criterion stops on the
+// device, and the trailing check sees it.
+mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info *info, bool x_zero = false) {
     if (single_launch_ok(S, info)) return solve_cg_single(const_cast<SolverImpl &>(S), b, x, info);
     auto t0 = std::chrono::steady_clock::now();
     const MatrixImpl &A = *S.A;
@@ -1037,18 +1041,21 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     const mxl_criteria &c = S.crit;
     mxl_status rs;
     HIP_TRY(launch_state_init(st, c.reduction, c.nonfinite_check, s));
-    if ((rs = residual(S, b, x)) != MXL_OK) return rs;
+    if (x_zero) HIP_TRY(launch_copy(dt, n, b, S.r->p, s));
+    else if ((rs = residual(S, b, x)) != MXL_OK) return rs;
     const bool blockp = S.P && S.P->block;
     if (blockp) HIP_TRY(bj_cg_init(ctx, *S.P, dt, n, b, S.r->p, S.p->p, pC, s));
     else HIP_TRY(cg_init(ctx, dt, n, b, S.r->p, S.p->p, dinv, pC, s));
     HIP_TRY(launch_finalize(3, pC, gv, st, FIN_CG_INIT, 0, 0, hist, s));
-    SolverState h;
-    if ((rs = read_state(S, h)) != MXL_OK) return rs;
-    if (h.nb2 == 0.0) {
-        HIP_TRY(launch_fill(dt, n, 0.0, x, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        fill_info(info, S, h, 0, MXL_STOP_CONVERGED, 1, elapsed_s(t0));
-        return MXL_OK;
+    SolverState h{};
+    if (!x_zero) {
+        if ((rs = read_state(S, h)) != MXL_OK) return rs;
+        if (h.nb2 == 0.0) {
+            HIP_TRY(launch_fill(dt, n, 0.0, x, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            fill_info(info, S, h, 0, MXL_STOP_CONVERGED, 1, elapsed_s(t0));
+            return MXL_OK;
+        }
     }
     int64_t k = 0;
     int stop = h.stop ? map_stop(h.stop) : MXL_STOP_NONE;
@@ -1101,7 +1108,7 @@ mxl_status solve_cg(const SolverImpl &S, const void *b, void *x, mxl_solve_info 
     } else {
         iters = h.iters;
     }
-    int64_t spmvs = 1 + iters + (stop == MXL_STOP_BREAKDOWN || stop == MXL_STOP_NONFINITE ? 1 : 0);
+    int64_t spmvs = (x_zero ? 0 : 1) + iters + (stop == MXL_STOP_BREAKDOWN || stop == MXL_STOP_NONFINITE ? 1 : 0);
     fill_info(info, S, h, iters, stop, spmvs, elapsed_s(t0));
     if (info && info->time_spmv) timer.collect(iters, &info->spmv_ms, &info->spmv_timed);
     return MXL_OK;
@@ -1457,7 +1464,7 @@ mxl_status solve_ir(const SolverImpl &S, const void *bv, void *xv, mxl_solve_inf
         HIP_TRY(ir_scale_to_f32(n, (const double *)O.r->p, st, (float *)ir.r32->p, s));
         HIP_TRY(launch_fill(MXL_F32, n, 0.0, ir.d32->p, s));
         mxl_solve_info ii{};
-        if ((rs = solve_cg(*ir.inner, ir.r32->p, ir.d32->p, &ii)) != MXL_OK) return rs;
+        if ((rs = solve_cg(*ir.inner, ir.r32->p, ir.d32->p, &ii, true)) != MXL_OK) return rs;
         inner_total += ii.iterations;
         spmvs += ii.spmv_count;
         HIP_TRY(ir_correct(n, x, (const float *)ir.d32->p, st, s));
