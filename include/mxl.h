@@ -229,10 +229,11 @@ typedef struct {
     int32_t vector_width, ell_width;
     int64_t n_pad, tail_nnz;
     int64_t stored_bytes;  /* bytes of the format's own arrays */
-    int32_t ell_reuse;     /* ELL (not LDS-staged): 1 when the product takes x values
-                              from the neighbouring row instead of gathering them,
-                              set at conversion when at least a quarter of the
-                              entries (i, s) share their column with (i+1, s-1) */
+    int32_t ell_reuse;     /* ELL and HYB (not LDS-staged): 1 when the product takes x
+                              values from the neighbouring row instead of gathering
+                              them, set at conversion when at least a quarter of the
+                              entries (i, s) of the ELL slots share their column
+                              with (i+1, s-1) */
 } mxl_op_desc;
 mxl_status mxl_op_describe(const mxl_op *A, mxl_op_desc *out);
 

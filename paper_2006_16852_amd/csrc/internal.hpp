@@ -259,7 +259,7 @@ hipError_t launch_csr_to_ell16(const MatrixImpl &A, int w, int64_t n_pad, short 
                                int *overflow, hipStream_t s);
 hipError_t launch_csr_to_ell(const MatrixImpl &A, int w, int64_t n_pad, int *ecol, void *evals,
                              hipStream_t s);
-hipError_t launch_ell_reuse_count(const MatrixImpl &A, unsigned long long *count, hipStream_t s);
+hipError_t launch_ell_reuse_count(const MatrixImpl &A, int w, unsigned long long *count, hipStream_t s);
 hipError_t launch_hyb_tail(const MatrixImpl &A, int k, const int64_t *toff, int *trow, int *tcol,
                            void *tval, hipStream_t s);
 hipError_t launch_ell_windows(const MatrixImpl &A, int2 *win, hipStream_t s);

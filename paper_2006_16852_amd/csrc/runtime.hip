@@ -476,18 +476,20 @@ mxl_status mxl_convert(const mxl_op *Aop, mxl_format fmt, const mxl_format_param
         }
         if (prm.variant == MXL_ELL_LDS)
             if ((st = build_ell_windows(*A)) != MXL_OK) return st;
-        if (fmt == MXL_FMT_ELL && prm.variant != MXL_ELL_LDS && S.nnz > 0) {
-            // neighbour reuse pays where at least a quarter of the entries
-            // can take x from the row below (stencils: runs of consecutive
-            // columns); elsewhere its shuffles are overhead
+        if (prm.variant != MXL_ELL_LDS && S.nnz > 0) {
+            // neighbour reuse pays where at least a quarter of the ELL
+            // entries can take x from the row below (stencils: runs of
+            // consecutive columns); elsewhere its shuffles are overhead
+            unsigned long long stored = 0;  // entries in the ELL slots
+            for (int64_t i = 0; i < S.nrows; ++i) stored += (unsigned long long)std::min(len[i], w);
             auto cnt = alloc(8, &e);
             if (!cnt) return hip_fail(e, "alloc reuse count");
             unsigned long long hits = 0;
             HIP_TRY(hipMemcpyAsync(cnt->p, &hits, 8, hipMemcpyHostToDevice, ctx->stream));
-            HIP_TRY(launch_ell_reuse_count(*A, (unsigned long long *)cnt->p, ctx->stream));
+            HIP_TRY(launch_ell_reuse_count(*A, w, (unsigned long long *)cnt->p, ctx->stream));
             HIP_TRY(hipMemcpyAsync(&hits, cnt->p, 8, hipMemcpyDeviceToHost, ctx->stream));
             HIP_TRY(hipStreamSynchronize(ctx->stream));
-            A->ell_nb = 4 * hits >= (unsigned long long)S.nnz ? 1 : 0;
+            A->ell_nb = stored > 0 && 4 * hits >= stored ? 1 : 0;
         }
         if (fmt == MXL_FMT_HYB) {
             std::vector<int64_t> toff((size_t)S.nrows + 1, 0);

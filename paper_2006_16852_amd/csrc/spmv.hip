@@ -894,17 +894,18 @@ __global__ void k_csr_to_ell16(int64_t n, int64_t n_pad, int w, const int *__res
 }
 
 // Entries whose column equals that of the entry one row down and one slot
-// to the left, (i, s) against (i+1, s-1): the x values an ELL product with
-// neighbour reuse takes from a neighbouring row instead of gathering.
-// Integer sums (one atomic per workgroup), so the count is exact.
+// to the left, (i, s) against (i+1, s-1), among the first w slots of each
+// row (the ELL part of HYB; w >= the longest row for ELL): the x values an
+// ELL product with neighbour reuse takes from a neighbouring row instead of
+// gathering.  Integer sums (one atomic per workgroup), so the count is exact.
 __global__ __launch_bounds__(kWG) void k_ell_reuse_count(int64_t n, const int *__restrict__ rp,
-                                                         const int *__restrict__ col,
+                                                         const int *__restrict__ col, int w,
                                                          unsigned long long *count) {
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
     unsigned long long h = 0;
     if (i + 1 < n) {
-        const int a0 = rp[i], la = rp[i + 1] - a0;
-        const int b0 = rp[i + 1], lb = rp[i + 2] - b0;
+        const int a0 = rp[i], la = min(rp[i + 1] - a0, w);
+        const int b0 = rp[i + 1], lb = min(rp[i + 2] - b0, w);
         for (int s = 1; s < la && s - 1 < lb; ++s) h += col[a0 + s] == col[b0 + s - 1];
     }
     __shared__ unsigned long long sh[kWG / kWave];
@@ -1212,7 +1213,7 @@ static hipError_t spmv_typed(const MatrixImpl &A, const SpmvArgs &a, hipStream_t
         const int2 *win = A.ell_win ? (const int2 *)A.ell_win->p : nullptr;
         const bool lds = A.variant == MXL_ELL_LDS && win;
         const bool d16 = A.format == MXL_FMT_ELL && A.variant == MXL_ELL_DELTA16;
-        const bool nb = A.format == MXL_FMT_ELL && A.ell_nb && !lds;
+        const bool nb = A.ell_nb && !lds;  // ELL or the ELL part of HYB
         const dim3 ge(dot ? A.grid_dot
                           : plain_grid(A, (n + (int64_t)kWG * A.ell_rpt - 1) / ((int64_t)kWG * A.ell_rpt)));
 #define MXL_ELL_CASE(RR)                                                                                          \
@@ -1307,10 +1308,10 @@ hipError_t launch_csr_to_ell16(const MatrixImpl &A, int w, int64_t n_pad, short 
     return hipGetLastError();
 }
 
-hipError_t launch_ell_reuse_count(const MatrixImpl &A, unsigned long long *count, hipStream_t s) {
+hipError_t launch_ell_reuse_count(const MatrixImpl &A, int w, unsigned long long *count, hipStream_t s) {
     if (A.nrows < 2) return hipSuccess;
     hipLaunchKernelGGL(k_ell_reuse_count, g1(A.nrows), dim3(kWG), 0, s, A.nrows, (const int *)A.row_ptr->p,
-                       (const int *)A.col->p, count);
+                       (const int *)A.col->p, w, count);
     return hipGetLastError();
 }
 

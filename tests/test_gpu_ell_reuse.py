@@ -4,8 +4,8 @@ Entry (i, s) whose column equals that of entry (i+1, s-1) takes x from that
 entry instead of gathering it.  The value moved is x at the same column, so
 the product must equal, bit for bit, the one that gathers every entry (the
 LDS-staged variant never reuses), and stay within the oracle's per-row bound.
-The conversion enables reuse when at least a quarter of the entries hit; the
-rule is recomputed here from the CSR arrays.
+The conversion enables reuse when at least a quarter of the entries (of HYB's
+ELL part) hit; the rule is recomputed here from the CSR arrays.
 """
 import numpy as np
 import pytest
@@ -17,17 +17,23 @@ from tests._gpu import assert_rows_close, dev, matrix, spmv_reference
 pytestmark = pytest.mark.gpu
 
 
-def _hits(A):
-    """Entries (i, s), s >= 1, whose column equals that of (i+1, s-1)."""
+def _hits(A, w=None):
+    """Entries (i, s), 1 <= s < w, whose column equals that of (i+1, s-1),
+    counting the first w entries of each row only (the ELL part of HYB)."""
     rp = A.row_ptr.astype(np.int64)
+    w = int(np.diff(rp).max(initial=0)) if w is None else w
     h = 0
     for i in range(A.nrows - 1):
-        a0, la = rp[i], rp[i + 1] - rp[i]
-        b0, lb = rp[i + 1], rp[i + 2] - rp[i + 1]
+        a0, la = rp[i], min(rp[i + 1] - rp[i], w)
+        b0, lb = rp[i + 1], min(rp[i + 2] - rp[i + 1], w)
         m = int(min(la - 1, lb))
         if m > 0:
             h += int(np.count_nonzero(A.col[a0 + 1:a0 + 1 + m] == A.col[b0:b0 + m]))
     return h
+
+
+def _stored(A, w):
+    return int(np.minimum(np.diff(A.row_ptr.astype(np.int64)), w).sum())
 
 
 def _band_dropout(n, half, keep, seed):
@@ -73,6 +79,29 @@ def test_reuse_flag_follows_rule(mxl, ctx, A):
     for var in (0, mxl.ELL_DELTA16):
         assert base.convert("ell", variant=var).describe()["ell_reuse"] == want
     assert base.convert("ell", variant=mxl.ELL_LDS).describe()["ell_reuse"] == 0
+
+
+@pytest.mark.parametrize("q", [0.66, 0.9])
+@pytest.mark.parametrize("A", MATS, ids=[a.name for a in MATS])
+def test_reuse_hyb_flag_and_bitwise(mxl, ctx, A, q):
+    """HYB reuses within its ELL part; the tail is unchanged.  Against the
+    LDS-staged HYB (which never reuses), bit for bit."""
+    print(f"[hyb-reuse] {A.name} q={q}", flush=True)
+    base = matrix(mxl, ctx, A)
+    op = base.convert("hyb", hyb_quantile=q)
+    d = op.describe()
+    w = d["ell_width"]
+    want = 1 if _stored(A, w) > 0 and 4 * _hits(A, w) >= _stored(A, w) else 0
+    assert d["ell_reuse"] == want
+    ref = base.convert("hyb", variant=mxl.ELL_LDS, hyb_quantile=q)
+    assert ref.describe()["ell_reuse"] == 0
+    rng = np.random.default_rng(5)
+    x = dev(rng.uniform(-1, 1, A.ncols))
+    y0 = rng.uniform(-1, 1, A.nrows)
+    ya, yb = dev(y0), dev(y0)
+    op.apply(x, ya, alpha=1.1, beta=0.3)
+    ref.apply(x, yb, alpha=1.1, beta=0.3)
+    assert np.array_equal(ya.cpu().numpy(), yb.cpu().numpy())
 
 
 def test_reuse_off_on_scattered_columns(mxl, ctx):
