@@ -29,7 +29,11 @@ CASES = [("3d27_9", (9, 9, 9), W.points_3d27()),
          ("aniso7_11", (11, 11, 11), W.points_aniso7()),
          ("2d5_37", (37, 37, 1), W.points_2d5()),
          ("convdiff_17", (17, 17, 1), W.points_convdiff()),
+         ("3d27_even", (12, 7, 5), W.points_3d27()),     # even nx: two points per thread
+         ("aniso7_even", (10, 9, 8), W.points_aniso7()),
+         ("2d5_even", (36, 37, 1), W.points_2d5()),
          ("line_3", (70, 1, 1), ([(-1, 0, 0), (0, 0, 0), (1, 0, 0)], [-1.0, 2.5, -1.0])),
+         ("line_2", (2, 3, 1), ([(-1, 0, 0), (0, 0, 0), (1, 0, 0)], [-1.0, 2.5, -1.0])),
          ("single", (1, 1, 1), W.points_3d27())]
 
 
