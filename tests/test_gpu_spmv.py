@@ -286,3 +286,66 @@ def test_cast_bitwise(mxl, ctx, fmt, kw):
     idx = {"csr": ["row_ptr", "col"], "coo": ["coo_row"], "ell": ["ell_col"], "hyb": ["ell_col", "tail_col"]}[fmt]
     for key in idx:
         assert torch.equal(M.export(key), M32.export(key)), key
+
+
+def _long_rows(seed):
+    """Rows of every length class of the row-block CSR kernel: long rows
+    (> 512 entries, several 512-entry sweeps), exactly 512 and 513, runs of
+    long rows, long first and last rows, and short rows."""
+    rng = np.random.default_rng(seed)
+    n = 6000
+    lens = rng.integers(0, 40, n)
+    for i, L in [(0, 5000), (1, 4097), (2, 4096), (7, 2048), (8, 2049), (9, 513), (10, 512),
+                 (3000, 6000), (3001, 6000), (3002, 100), (4500, 1500), (n - 1, 3333)]:
+        lens[i] = L
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, size=L, replace=False)) for L in lens]).astype(np.int32)
+    val = rng.standard_normal(int(rp[-1]))
+    return W.Csr(n, n, rp.astype(np.int32), col, val, f"long_rows_{seed}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_csr_stream_long_rows(mxl, ctx, dtype):
+    """Rows in every length class of the row-block CSR kernel (long rows are
+    swept by a whole wave): every row within the oracle's bound, for beta = 0
+    and beta != 0."""
+    A = _long_rows(1)
+    op = matrix(mxl, ctx, A, dtype).convert("csr", variant=mxl.CSR_STREAM)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, A.ncols)
+    y0 = rng.uniform(-1, 1, A.nrows)
+    fp32 = dtype == torch.float32
+    for alpha, beta in [(1.0, 0.0), (-0.7, 1.3)]:
+        yd = dev(y0, dtype)
+        op.apply(dev(x, dtype), yd, alpha, beta)
+        want, bound = spmv_reference(A, x, alpha, beta, y0, fp32)
+        assert_rows_close(yd.cpu().numpy(), want, bound, 1e-5 if fp32 else 1e-12, f"a={alpha} b={beta}")
+
+
+def test_csr_stream_long_rows_cg(mxl, ctx):
+    """The fused dot with a long row: an arrow matrix (row and column 0 dense,
+    5,000 entries) made SPD by its diagonal (spread over
+    [1, 100], so plain CG needs many iterations) on the row-block CSR
+    operator, against the oracle's count and residual."""
+    n = 5000
+    rng = np.random.default_rng(4)
+    u = rng.uniform(0.1, 1.0, n - 1) / np.sqrt(n)
+    d = 1.0 + 99.0 * rng.random(n - 1)
+    rows = [np.arange(n)] + [np.array([0, i]) for i in range(1, n)]
+    vals = [np.concatenate([[2.0 + u @ (u / d)], u])] + [np.array([u[i - 1], d[i - 1]]) for i in range(1, n)]
+    lens = np.array([len(r) for r in rows])
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    A = W.Csr(n, n, rp.astype(np.int32), np.concatenate(rows).astype(np.int32), np.concatenate(vals), "arrow5000")
+    b = rng.uniform(-1, 1, n)
+    ref = O.pcg(A, b, reduction=1e-10)
+    assert ref["iterations"] > 20
+    op = matrix(mxl, ctx, A).convert("csr", variant=mxl.CSR_STREAM)
+    S = mxl.solver("cg", op, None, max_iters=1000, reduction=1e-10, check_every=4, launch_mode=1)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = S.solve(dev(b), x)
+    assert info["stop_reason"] == mxl.STOP_CONVERGED
+    assert abs(info["iterations"] - ref["iterations"]) <= 2
+    r = b - O.spmv(A, x.cpu().numpy())
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(b)
