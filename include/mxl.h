@@ -460,7 +460,8 @@ mxl_status mxl_batch_solve_noalloc(const mxl_op *B, const mxl_criteria *crit,
 mxl_status mxl_features(const mxl_op *A, double out_host[16]);
 
 /* Median time in milliseconds of reps applications y = A x (HIP events on
- * the context stream).  flush != 0 reads a 1 GiB buffer (allocated on first
+ * the context stream), after one untimed application (the first launch of a
+ * kernel also loads its code).  flush != 0 reads a 1 GiB buffer (allocated on first
  * use and kept by the context) before every rep to evict the 256 MB
  * last-level cache without leaving dirty lines; its time is excluded. */
 mxl_status mxl_time_apply(const mxl_op *A, const void *x, void *y, int reps,
