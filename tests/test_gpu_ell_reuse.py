@@ -135,3 +135,33 @@ def test_reuse_bitwise_and_bound(mxl, ctx, A, rpt, dtype):
             got = yd.cpu().numpy()
             assert np.array_equal(got, yr), f"{name}: differs from the gathering product"
             assert_rows_close(got, want, bound, 1e-12 if dtype == torch.float64 else 1e-5, name)
+
+
+@pytest.mark.parametrize("fmt,q", [("ell", 0.0), ("hyb", 0.9)], ids=["ell", "hyb"])
+@pytest.mark.parametrize("A", [MATS[0], MATS[2], MATS[4]], ids=lambda a: a.name)
+def test_reuse_cg_bitwise(mxl, ctx, A, fmt, q):
+    """Jacobi-CG through the fused product with reuse (and the dot's w rows
+    loaded with the first slots) equals, bit for bit, the same solve through
+    the LDS-staged variant, which neither reuses nor prefetches: every
+    product and every partial of the fused dot is the same (on the
+    nonsymmetric band matrix down to the same breakdown)."""
+    print(f"[ell-reuse cg] {A.name} {fmt}", flush=True)
+    base = matrix(mxl, ctx, A)
+    kw = {"hyb_quantile": q} if fmt == "hyb" else {}
+    ops = [base.convert(fmt, **kw), base.convert(fmt, variant=mxl.ELL_LDS, **kw)]
+    if fmt == "ell":
+        ops.append(base.convert("ell", variant=mxl.ELL_DELTA16))
+    assert ops[0].describe()["ell_reuse"] == 1 and ops[1].describe()["ell_reuse"] == 0
+    rng = np.random.default_rng(9)
+    b = dev(rng.uniform(-1, 1, A.nrows))
+    outs = []
+    for op in ops:
+        S = mxl.solver("cg", op, mxl.jacobi(op), max_iters=2000, reduction=1e-10, check_every=8,
+                       launch_mode=1)
+        x = torch.zeros(A.nrows, dtype=torch.float64, device="cuda:0")
+        info = S.solve(b, x)
+        outs.append((info["stop_reason"], info["iterations"], x.cpu().numpy()))
+    if A.name.startswith(("stencil", "aniso")):  # SPD: CG converges
+        assert outs[0][0] == mxl.STOP_CONVERGED
+    for stop, it, x in outs[1:]:  # the nonsymmetric band matrix breaks down, identically
+        assert stop == outs[0][0] and it == outs[0][1] and np.array_equal(x, outs[0][2])
