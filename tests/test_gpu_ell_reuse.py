@@ -165,3 +165,24 @@ def test_reuse_cg_bitwise(mxl, ctx, A, fmt, q):
         assert outs[0][0] == mxl.STOP_CONVERGED
     for stop, it, x in outs[1:]:  # the nonsymmetric band matrix breaks down, identically
         assert stop == outs[0][0] and it == outs[0][1] and np.array_equal(x, outs[0][2])
+
+
+@pytest.mark.parametrize("A", [W.aniso_3d7(24), W.stencil_3d27(22)], ids=lambda a: a.name)
+def test_reuse_refinement_bitwise(mxl, ctx, A):
+    """FP32-inner refinement: the FP32 copy keeps the reuse of the FP64
+    operator, and the refined solution equals, bit for bit, the one through
+    the LDS-staged operator (no reuse in either precision)."""
+    print(f"[ell-reuse ir] {A.name}", flush=True)
+    base = matrix(mxl, ctx, A)
+    ops = [base.convert("ell", variant=mxl.ELL_DELTA16), base.convert("ell", variant=mxl.ELL_LDS)]
+    assert ops[0].describe()["ell_reuse"] == 1 and ops[1].describe()["ell_reuse"] == 0
+    b = dev(np.random.default_rng(12).uniform(-1, 1, A.nrows))
+    outs = []
+    for op in ops:
+        I = mxl.ir(op, outer=dict(max_iters=30, reduction=1e-12),
+                   inner=dict(reduction=1e-3, max_iters=5000, check_every=8, launch_mode=1))
+        x = torch.zeros(A.nrows, dtype=torch.float64, device="cuda:0")
+        info = I.solve(b, x)
+        assert info["stop_reason"] == mxl.STOP_CONVERGED
+        outs.append((info["iterations"], info["inner_iterations"], x.cpu().numpy()))
+    assert outs[0][:2] == outs[1][:2] and np.array_equal(outs[0][2], outs[1][2])
